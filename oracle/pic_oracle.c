@@ -1,0 +1,451 @@
+/*
+ * FP64 CPU oracle for one FDTD-Esirkepov PIC timestep with the small-k_z
+ * correction stencils of Godfrey & Vay (arXiv:1401.0838).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * GPU path is checked against.  It shares no code with the GPU library and is
+ * never part of the product path.  Build: gcc -O2 -ffp-contract=off -shared.
+ *
+ * Conventions (c = eps0 = mu0 = 1).  Fields live on the Yee staggered mesh
+ * (Sec. 2 names "the usual Yee staggered mesh"); the staggering of each
+ * component, as offsets of half a cell along (x, y, z), is
+ *     Ex (1,0,0)  Ey (0,1,0)  Ez (0,0,1)  Bx (0,1,1)  By (1,0,1)  Bz (1,1,0)
+ * and J shares E's staggering.  A half-integer location i+1/2 is stored at
+ * array index i.  Arrays are [nz][ny][nx], x fastest, periodic on every axis.
+ * 2D runs use ny == 1 with y-invariance (2D3V: y is not tracked for particles).
+ * Particles carry absolute positions and u = gamma*v per unit mass.
+ *
+ * One step (the order used throughout this project):
+ *   1. Yee: B -= dt/2 curl E;  E += dt (curl B - J - Jbg);  B -= dt/2 curl E
+ *   2. fields as seen by the particles: Psi series along z (Sec. 2), then the
+ *      3-point digital filter passes along z, then x, then y (Sec. 3, Eq. 6)
+ *   3. J = 0; per particle, in order: Galerkin gather (Eq. 3 scheme; Sec. 3
+ *      on E_z's lowered spline order), Boris push, move, Esirkepov deposit
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int dims;                 /* 2 or 3 */
+    int nx, ny, nz;           /* ny == 1 when dims == 2 */
+    double dx, dy, dz, dt;
+    int order;                /* charge shape order l (1 or 3) */
+    int interp;               /* 0 Galerkin, 1 Uniform */
+    double q, m, w;           /* charge, mass, macro-particle weight */
+    int correction;           /* 1: apply Psi_E / Psi_B */
+    int psi_deg;              /* polynomial degree of Psi (<= 8) */
+    double psi_e[9], psi_b[9];/* power-series coefficients in s = sin^2(kz dz/2) */
+    int nfilt;                /* number of 3-point passes per axis (<= 16) */
+    double filt[16];          /* pass weights w of (w, 1-2w, w) */
+    double jbg[3];            /* uniform background current (ion current) */
+    double *E[3], *B[3], *J[3];
+    double *Et[3], *Bt[3];    /* fields as seen by the particles */
+    double *tmp, *tmp2;       /* scratch planes, ncell each */
+    long np;
+    double *x[3];             /* absolute positions (x[1] unused in 2D) */
+    double *u[3];
+    int status;               /* 1 if some particle moved a full cell or more */
+} OSim;
+
+static const int STAG_E[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+static const int STAG_B[3][3] = {{0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+
+static long ncell(const OSim *s) { return (long)s->nx * s->ny * s->nz; }
+
+static long wrap(long i, long n)
+{
+    long r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+static long at(const OSim *s, long i, long j, long k)
+{
+    return (wrap(k, s->nz) * s->ny + wrap(j, s->ny)) * s->nx + wrap(i, s->nx);
+}
+
+/* ---------------------------------------------------------------- Yee ---- */
+
+static void yee_b_half(OSim *s)
+{
+    const double h = 0.5 * s->dt;
+    double *Ex = s->E[0], *Ey = s->E[1], *Ez = s->E[2];
+    for (long k = 0; k < s->nz; k++)
+        for (long j = 0; j < s->ny; j++)
+            for (long i = 0; i < s->nx; i++) {
+                long p = at(s, i, j, k);
+                double dyEz = (Ez[at(s, i, j + 1, k)] - Ez[p]) / s->dy;
+                double dzEy = (Ey[at(s, i, j, k + 1)] - Ey[p]) / s->dz;
+                double dzEx = (Ex[at(s, i, j, k + 1)] - Ex[p]) / s->dz;
+                double dxEz = (Ez[at(s, i + 1, j, k)] - Ez[p]) / s->dx;
+                double dxEy = (Ey[at(s, i + 1, j, k)] - Ey[p]) / s->dx;
+                double dyEx = (Ex[at(s, i, j + 1, k)] - Ex[p]) / s->dy;
+                s->B[0][p] -= h * (dyEz - dzEy);
+                s->B[1][p] -= h * (dzEx - dxEz);
+                s->B[2][p] -= h * (dxEy - dyEx);
+            }
+}
+
+static void yee_e(OSim *s)
+{
+    const double dt = s->dt;
+    double *Bx = s->B[0], *By = s->B[1], *Bz = s->B[2];
+    for (long k = 0; k < s->nz; k++)
+        for (long j = 0; j < s->ny; j++)
+            for (long i = 0; i < s->nx; i++) {
+                long p = at(s, i, j, k);
+                double dyBz = (Bz[p] - Bz[at(s, i, j - 1, k)]) / s->dy;
+                double dzBy = (By[p] - By[at(s, i, j, k - 1)]) / s->dz;
+                double dzBx = (Bx[p] - Bx[at(s, i, j, k - 1)]) / s->dz;
+                double dxBz = (Bz[p] - Bz[at(s, i - 1, j, k)]) / s->dx;
+                double dxBy = (By[p] - By[at(s, i - 1, j, k)]) / s->dx;
+                double dyBx = (Bx[p] - Bx[at(s, i, j - 1, k)]) / s->dy;
+                s->E[0][p] += dt * (dyBz - dzBy - (s->J[0][p] + s->jbg[0]));
+                s->E[1][p] += dt * (dzBx - dxBz - (s->J[1][p] + s->jbg[1]));
+                s->E[2][p] += dt * (dxBy - dyBx - (s->J[2][p] + s->jbg[2]));
+            }
+}
+
+void o_yee(OSim *s)
+{
+    yee_b_half(s);
+    yee_e(s);
+    yee_b_half(s);
+}
+
+/* ------------------------------------------- fields as seen (Sec. 2, 3) -- */
+
+/* out = S_z in, S_z = -(1/4)(1,-2,1) along z, whose symbol is sin^2(kz dz/2) */
+static void apply_sz(const OSim *s, const double *in, double *out)
+{
+    for (long k = 0; k < s->nz; k++)
+        for (long j = 0; j < s->ny; j++)
+            for (long i = 0; i < s->nx; i++) {
+                long p = at(s, i, j, k);
+                out[p] = -0.25 * (in[at(s, i, j, k - 1)] - 2.0 * in[p] + in[at(s, i, j, k + 1)]);
+            }
+}
+
+/* one (w, 1-2w, w) pass along an axis (0 x, 1 y, 2 z) */
+static void filter_pass(const OSim *s, int axis, double wt, const double *in, double *out)
+{
+    int ex = axis == 0, ey = axis == 1, ez = axis == 2;
+    for (long k = 0; k < s->nz; k++)
+        for (long j = 0; j < s->ny; j++)
+            for (long i = 0; i < s->nx; i++) {
+                long p = at(s, i, j, k);
+                double lo = in[at(s, i - ex, j - ey, k - ez)];
+                double hi = in[at(s, i + ex, j + ey, k + ez)];
+                out[p] = wt * lo + (1.0 - 2.0 * wt) * in[p] + wt * hi;
+            }
+}
+
+/* Psi(S_z) F = sum_j a_j S_z^j F, written as the power series (Sec. 2);
+ * coef == NULL means the identity.  Then the filter passes along z, x, y. */
+static void seen_one(OSim *s, const double *coef, const double *F, double *out)
+{
+    long nc = ncell(s);
+    if (coef) {
+        double *t = s->tmp, *t2 = s->tmp2;
+        memcpy(t, F, nc * sizeof(double));
+        for (long p = 0; p < nc; p++) out[p] = coef[0] * F[p];
+        for (int j = 1; j <= s->psi_deg; j++) {
+            apply_sz(s, t, t2);
+            memcpy(t, t2, nc * sizeof(double));
+            for (long p = 0; p < nc; p++) out[p] += coef[j] * t[p];
+        }
+    } else {
+        memcpy(out, F, nc * sizeof(double));
+    }
+    static const int axes[3] = {2, 0, 1};
+    for (int a = 0; a < 3; a++) {
+        int axis = axes[a];
+        if (axis == 1 && s->dims == 2) continue;
+        for (int f = 0; f < s->nfilt; f++) {
+            filter_pass(s, axis, s->filt[f], out, s->tmp);
+            memcpy(out, s->tmp, nc * sizeof(double));
+        }
+    }
+}
+
+/* Psi_E on both transverse E components; Psi_B on E_z and every B (Sec. 2) */
+void o_seen(OSim *s)
+{
+    const double *pe = s->correction ? s->psi_e : NULL;
+    const double *pb = s->correction ? s->psi_b : NULL;
+    seen_one(s, pe, s->E[0], s->Et[0]);
+    seen_one(s, pe, s->E[1], s->Et[1]);
+    seen_one(s, pb, s->E[2], s->Et[2]);
+    for (int c = 0; c < 3; c++) seen_one(s, pb, s->B[c], s->Bt[c]);
+}
+
+/* apply the seen-field operator with polynomial `which` (0 Psi_E, 1 Psi_B,
+ * 2 identity) to one plane; used by the stencil-response tests */
+void o_seen_plane(OSim *s, int which, const double *in, double *out)
+{
+    const double *coef = which == 0 ? s->psi_e : which == 1 ? s->psi_b : NULL;
+    seen_one(s, coef, in, out);
+}
+
+/* -------------------------------------------------- B-spline shapes ------ */
+
+/* centred B-spline of order o evaluated at t (cell units) */
+double o_spline(int o, double t)
+{
+    double a = fabs(t);
+    switch (o) {
+    case 0:
+        return (t >= -0.5 && t < 0.5) ? 1.0 : 0.0;
+    case 1:
+        return a < 1.0 ? 1.0 - a : 0.0;
+    case 2:
+        if (a < 0.5) return 0.75 - a * a;
+        if (a < 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
+        return 0.0;
+    case 3:
+        if (a < 1.0) return 2.0 / 3.0 - a * a + 0.5 * a * a * a;
+        if (a < 2.0) return (2.0 - a) * (2.0 - a) * (2.0 - a) / 6.0;
+        return 0.0;
+    }
+    return 0.0;
+}
+
+/* ------------------------------------------------------------ gather ----- */
+
+/* interpolate plane F with per-axis orders ord[] and staggering stag[] at the
+ * point whose cell-unit coordinates are c[] (c[1] ignored in 2D) */
+static double interp(const OSim *s, const double *F, const int *stag, const int *ord, const double *c)
+{
+    long lo[3], hi[3];
+    for (int a = 0; a < 3; a++) {
+        if (a == 1 && s->dims == 2) { lo[a] = hi[a] = 0; continue; }
+        double shift = 0.5 * stag[a];
+        double half = 0.5 * (ord[a] + 1);
+        lo[a] = (long)floor(c[a] - shift - half);
+        hi[a] = (long)floor(c[a] - shift + half);
+    }
+    double sum = 0.0;
+    for (long k = lo[2]; k <= hi[2]; k++) {
+        double wz = o_spline(ord[2], c[2] - k - 0.5 * stag[2]);
+        if (wz == 0.0) continue;
+        for (long j = lo[1]; j <= hi[1]; j++) {
+            double wy = s->dims == 2 ? 1.0 : o_spline(ord[1], c[1] - j - 0.5 * stag[1]);
+            if (wy == 0.0) continue;
+            for (long i = lo[0]; i <= hi[0]; i++) {
+                double wx = o_spline(ord[0], c[0] - i - 0.5 * stag[0]);
+                if (wx == 0.0) continue;
+                sum += wx * wy * wz * F[at(s, i, j, k)];
+            }
+        }
+    }
+    return sum;
+}
+
+/* Galerkin: order l on axes where the component sits on integer nodes and
+ * l-1 where it sits half a cell off (Eq. 3 scheme; Sec. 3 for E_z).
+ * Uniform: order l on every axis from each component's own location. */
+static void comp_orders(const OSim *s, const int *stag, int *ord)
+{
+    for (int a = 0; a < 3; a++) ord[a] = s->interp == 0 ? s->order - stag[a] : s->order;
+}
+
+void o_gather(const OSim *s, const double *pos, double *Eo, double *Bo)
+{
+    double c[3] = {pos[0] / s->dx, s->dims == 3 ? pos[1] / s->dy : 0.0, pos[2] / s->dz};
+    int ord[3];
+    for (int comp = 0; comp < 3; comp++) {
+        comp_orders(s, STAG_E[comp], ord);
+        Eo[comp] = interp(s, s->Et[comp], STAG_E[comp], ord, c);
+        comp_orders(s, STAG_B[comp], ord);
+        Bo[comp] = interp(s, s->Bt[comp], STAG_B[comp], ord, c);
+    }
+}
+
+/* ------------------------------------------------------------- Boris ----- */
+
+void o_boris(double *u, const double *E, const double *B, double q, double m, double dt)
+{
+    double eps = q * dt / (2.0 * m);
+    double um[3], t[3], sv[3], up[3], uq[3];
+    for (int a = 0; a < 3; a++) um[a] = u[a] + eps * E[a];
+    double gm = sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+    for (int a = 0; a < 3; a++) t[a] = eps * B[a] / gm;
+    double t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    for (int a = 0; a < 3; a++) sv[a] = 2.0 * t[a] / (1.0 + t2);
+    up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
+    up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
+    up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
+    uq[0] = um[0] + (up[1] * sv[2] - up[2] * sv[1]);
+    uq[1] = um[1] + (up[2] * sv[0] - up[0] * sv[2]);
+    uq[2] = um[2] + (up[0] * sv[1] - up[1] * sv[0]);
+    for (int a = 0; a < 3; a++) u[a] = uq[a] + eps * E[a];
+}
+
+/* ----------------------------------------------------- Esirkepov ------- */
+
+#define MAXN 12
+
+/* Add one particle's Esirkepov current for a move from p0 to p1 (absolute,
+ * unwrapped: p1 = p0 + displacement).  vy is the y velocity used for J_y in
+ * 2D3V.  Shapes are order-l B-splines on integer nodes. */
+void o_deposit(OSim *s, const double *p0, const double *p1, double vy)
+{
+    const int l = s->order;
+    const double d[3] = {s->dx, s->dy, s->dz};
+    const double half = 0.5 * (l + 1);
+    long lo[3] = {0, 0, 0};
+    int cnt[3] = {1, 1, 1};
+    double S0[3][MAXN], S1[3][MAXN], DS[3][MAXN];
+    for (int a = 0; a < 3; a++) {
+        if (a == 1 && s->dims == 2) { S0[a][0] = S1[a][0] = 1.0; DS[a][0] = 0.0; continue; }
+        double c0 = p0[a] / d[a], c1 = p1[a] / d[a];
+        double mn = c0 < c1 ? c0 : c1, mx = c0 < c1 ? c1 : c0;
+        lo[a] = (long)floor(mn - half);
+        long hi = (long)floor(mx + half);
+        cnt[a] = (int)(hi - lo[a] + 1);
+        for (int i = 0; i < cnt[a]; i++) {
+            S0[a][i] = o_spline(l, c0 - (double)(lo[a] + i));
+            S1[a][i] = o_spline(l, c1 - (double)(lo[a] + i));
+            DS[a][i] = S1[a][i] - S0[a][i];
+        }
+    }
+    const double qw = s->q * s->w;
+    if (s->dims == 2) {
+        const double dV = s->dx * s->dz;
+        const double cx = -qw * s->dx / (s->dt * dV);
+        const double cz = -qw * s->dz / (s->dt * dV);
+        const double cy = qw * vy / dV;
+        for (int k = 0; k < cnt[2]; k++) {          /* J_x: running sum along x */
+            double acc = 0.0;
+            for (int i = 0; i < cnt[0]; i++) {
+                acc += DS[0][i] * (S0[2][k] + 0.5 * DS[2][k]);
+                s->J[0][at(s, lo[0] + i, 0, lo[2] + k)] += cx * acc;
+            }
+        }
+        for (int i = 0; i < cnt[0]; i++) {          /* J_z: running sum along z */
+            double acc = 0.0;
+            for (int k = 0; k < cnt[2]; k++) {
+                acc += DS[2][k] * (S0[0][i] + 0.5 * DS[0][i]);
+                s->J[2][at(s, lo[0] + i, 0, lo[2] + k)] += cz * acc;
+            }
+        }
+        for (int k = 0; k < cnt[2]; k++)            /* J_y: out-of-plane */
+            for (int i = 0; i < cnt[0]; i++) {
+                double wy = S0[0][i] * S0[2][k] + 0.5 * DS[0][i] * S0[2][k]
+                          + 0.5 * S0[0][i] * DS[2][k] + DS[0][i] * DS[2][k] / 3.0;
+                s->J[1][at(s, lo[0] + i, 0, lo[2] + k)] += cy * wy;
+            }
+        return;
+    }
+    const double dV = s->dx * s->dy * s->dz;
+    const double cf[3] = {-qw * s->dx / (s->dt * dV), -qw * s->dy / (s->dt * dV),
+                          -qw * s->dz / (s->dt * dV)};
+    /* W_a = DS_a * (S0_b S0_c + DS_b S0_c / 2 + S0_b DS_c / 2 + DS_b DS_c / 3) */
+    for (int a = 0; a < 3; a++) {
+        int b = (a + 1) % 3, c = (a + 2) % 3;
+        int idx[3];
+        for (idx[b] = 0; idx[b] < cnt[b]; idx[b]++)
+            for (idx[c] = 0; idx[c] < cnt[c]; idx[c]++) {
+                double sb0 = S0[b][idx[b]], dsb = DS[b][idx[b]];
+                double sc0 = S0[c][idx[c]], dsc = DS[c][idx[c]];
+                double tr = sb0 * sc0 + 0.5 * dsb * sc0 + 0.5 * sb0 * dsc + dsb * dsc / 3.0;
+                double acc = 0.0;
+                for (idx[a] = 0; idx[a] < cnt[a]; idx[a]++) {
+                    acc += DS[a][idx[a]] * tr;
+                    s->J[a][at(s, lo[0] + idx[0], lo[1] + idx[1], lo[2] + idx[2])] += cf[a] * acc;
+                }
+            }
+    }
+}
+
+/* ------------------------------------------------------------ step ------ */
+
+static double wrap_pos(double x, double L)
+{
+    if (x >= L) x -= L;
+    if (x < 0.0) {
+        x += L;
+        if (x >= L) x -= L;
+    }
+    return x;
+}
+
+void o_push_deposit(OSim *s)
+{
+    long nc = ncell(s);
+    for (int c = 0; c < 3; c++) memset(s->J[c], 0, nc * sizeof(double));
+    const double L[3] = {s->nx * s->dx, s->ny * s->dy, s->nz * s->dz};
+    const double d[3] = {s->dx, s->dy, s->dz};
+    for (long p = 0; p < s->np; p++) {
+        double p0[3] = {s->x[0][p], s->dims == 3 ? s->x[1][p] : 0.0, s->x[2][p]};
+        double E[3], B[3];
+        o_gather(s, p0, E, B);
+        double u[3] = {s->u[0][p], s->u[1][p], s->u[2][p]};
+        o_boris(u, E, B, s->q, s->m, s->dt);
+        double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        double p1[3];
+        for (int a = 0; a < 3; a++) {
+            if (a == 1 && s->dims == 2) { p1[a] = 0.0; continue; }
+            p1[a] = p0[a] + s->dt * u[a] / g;
+            if (fabs(p1[a] - p0[a]) >= d[a]) s->status = 1;
+        }
+        o_deposit(s, p0, p1, u[1] / g);
+        for (int a = 0; a < 3; a++) {
+            s->u[a][p] = u[a];
+            if (a == 1 && s->dims == 2) continue;
+            s->x[a][p] = wrap_pos(p1[a], L[a]);
+        }
+    }
+}
+
+void o_step(OSim *s, int nsteps)
+{
+    for (int n = 0; n < nsteps; n++) {
+        o_yee(s);
+        o_seen(s);
+        o_push_deposit(s);
+    }
+}
+
+/* ------------------------------------------------------- diagnostics ---- */
+
+/* charge density on integer nodes with the order-l shape */
+void o_rho(const OSim *s, double *rho)
+{
+    long nc = ncell(s);
+    memset(rho, 0, nc * sizeof(double));
+    const double dV = s->dims == 2 ? s->dx * s->dz : s->dx * s->dy * s->dz;
+    static const int zero[3] = {0, 0, 0};
+    int ord[3] = {s->order, s->order, s->order};
+    for (long p = 0; p < s->np; p++) {
+        double c[3] = {s->x[0][p] / s->dx, s->dims == 3 ? s->x[1][p] / s->dy : 0.0, s->x[2][p] / s->dz};
+        long lo[3], hi[3];
+        for (int a = 0; a < 3; a++) {
+            if (a == 1 && s->dims == 2) { lo[a] = hi[a] = 0; continue; }
+            lo[a] = (long)floor(c[a] - 0.5 * (ord[a] + 1));
+            hi[a] = (long)floor(c[a] + 0.5 * (ord[a] + 1));
+        }
+        for (long k = lo[2]; k <= hi[2]; k++)
+            for (long j = lo[1]; j <= hi[1]; j++)
+                for (long i = lo[0]; i <= hi[0]; i++) {
+                    double wgt = o_spline(ord[0], c[0] - i - 0.5 * zero[0]) *
+                                 (s->dims == 2 ? 1.0 : o_spline(ord[1], c[1] - j)) *
+                                 o_spline(ord[2], c[2] - k);
+                    rho[at(s, i, j, k)] += s->q * s->w * wgt / dV;
+                }
+    }
+}
+
+/* discrete divergence of a field with E's staggering, at integer nodes */
+void o_div(const OSim *s, double *const F[3], double *out)
+{
+    for (long k = 0; k < s->nz; k++)
+        for (long j = 0; j < s->ny; j++)
+            for (long i = 0; i < s->nx; i++) {
+                long p = at(s, i, j, k);
+                double v = (F[0][p] - F[0][at(s, i - 1, j, k)]) / s->dx
+                         + (F[2][p] - F[2][at(s, i, j, k - 1)]) / s->dz;
+                if (s->dims == 3) v += (F[1][p] - F[1][at(s, i, j - 1, k)]) / s->dy;
+                out[p] = v;
+            }
+}
