@@ -1,0 +1,147 @@
+"""Benchmark of the GPU PIC step on one MI355X.
+
+Workload: 2D 512x512 periodic Yee grid, 16 particles per cell (4,194,304
+macro-particles), cold beam gamma = 130 along z with 1e-4 relative momentum
+spread, c dt / dz = 0.5, linear Galerkin shapes, correction stencils (Psi_E /
+Psi_B, quartics) plus a 4-pass (1,2,1) filter per axis, FP32 particles and
+fields (int32 cell index + FP32 offset, fixed-point current).  Synthetic
+seeded input (pic_inputs).
+
+A step is the whole hot path: Yee update, fields as seen by the particles
+(correction + filter), gather, Boris push, move, Esirkepov deposit, and the
+periodic tile re-sort check.  `value` = particle-steps per second over the
+timed steps (inputs resident in HBM, HIP-graph replay).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--extra]
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SRC = os.path.join(ROOT, "paper_1401_0838_amd", "csrc", "pic_kernels.hip")
+
+
+def kernel_sha():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def particle_kernel_bytes(n_particles, n_cells, word=4, state_bytes=24):
+    """Algorithmic HBM bytes of one particle-kernel launch: every particle's state read
+    and written once (state_bytes each way), the six seen-field components read once
+    and the three current components written once per cell."""
+    return 2 * state_bytes * n_particles + 9 * word * n_cells
+
+
+def stored_traffic(name):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken
+    on the current kernel source; else None."""
+    path = os.path.join(PROFILE_DIR, name)
+    if not os.path.exists(path):
+        return None
+    doc = json.load(open(path))
+    if doc.get("kernel_source_sha") != kernel_sha():
+        return None
+    return doc.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, x, u, steps):
+    """The FP64 oracle (single thread, as it stands) on a bounded sample: `steps`
+    steps of the same 512x512, 16 ppc workload."""
+    from oracle.ref import OracleSim
+    ref = OracleSim(wl, x, u)
+    t0 = time.perf_counter()
+    ref.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": x.shape[0] * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d steps of the full 512x512 x 16 ppc workload, FP64 C oracle, 1 thread, %.1f s"
+                      % (steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--profile-steps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the domain would shard along z with halo exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import pic_inputs as pi
+    from paper_1401_0838_amd.sim import Simulation
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    wl = pi.workload("beam2d_512", alpha=0.5, precision="fp32")
+    x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], wl["sigma"], 0)
+    sim = Simulation(wl, (x, u), precision="fp32")
+    sim.set_schedule("batched", True)
+    n_part = x.shape[0]
+    n_cells = wl["n"][0] * wl["n"][1]
+
+    sim.step(args.warmup)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = n_part * args.steps / elapsed
+
+    # per-kernel durations with HIP events on the library's stream
+    prof = sim.profile(args.profile_steps)
+    d = sim.diag()
+    sim.close()
+    pk_bytes = particle_kernel_bytes(n_part, n_cells)
+    achieved = pk_bytes / (prof["particle_ms"] * 1e-3) / 1e9
+    traffic = stored_traffic("traffic_k_particles_beam2d_512_fp32.json")
+    out = {
+        "metric": "particle-steps/s (gather+Boris+Esirkepov) plain vs batched; adjoint cost ratio",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "beam2d_512x512_ppc16_fp32", "cells": n_cells, "particles": n_part,
+                   "alpha": 0.5, "gamma": 130.0, "shape": "linear galerkin",
+                   "correction": "Psi_E/Psi_B quartic", "filter": "4-pass 1-2-1 per axis",
+                   "schedule": "batched hipGraph"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_particles<2,1,float>", "bytes_per_launch": pk_bytes,
+                     "avg_launch_ms": prof["particle_ms"]},
+        "kernels_ms": {k: prof[k] for k in ("yee_ms", "seen_ms", "particle_ms", "resort_ms", "step_ms")},
+        "grid_cell_updates_per_s": n_cells * args.steps / elapsed,
+        "gauss_linf_rel": d["gauss_linf"] / max(d["rho_max"], 1e-300),
+        "kernel_source_sha": kernel_sha(),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, x, u, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

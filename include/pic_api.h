@@ -1,0 +1,207 @@
+/*
+ * pic_api.h -- C ABI of the MI355X (gfx950) FDTD-Esirkepov PIC step with the
+ * small-k_z correction stencils of Godfrey & Vay, "Suppressing the Numerical
+ * Cherenkov Instability in FDTD PIC Codes" (arXiv:1401.0838).
+ *
+ * One step advances every bound simulation instance by dt:
+ *   1. Yee update on the staggered mesh (Sec. 2 names the usual Yee mesh):
+ *        B -= dt/2 curl E;  E += dt (curl B - J - J_bg);  B -= dt/2 curl E
+ *   2. fields as seen by the particles (Sec. 2): Psi_E(S_z) on both transverse
+ *      E components, Psi_B(S_z) on E_z and on every B component, with S_z the
+ *      -(1/4)(1,-2,1) stencil along z whose symbol is s = sin^2(k_z dz/2);
+ *      then the 3-point digital filter passes along every axis (Sec. 3, Eq. 6)
+ *   3. per particle: Galerkin shape-factor gather (the scheme of Eq. 3: order l
+ *      along axes where a component sits on integer nodes, l-1 where it sits
+ *      half a cell off; Sec. 3), Boris push, move, Esirkepov deposit
+ *      (the current-conserving scheme the paper's dispersion analysis assumes)
+ *
+ * Units: c = eps0 = mu0 = 1.  Positions are absolute (0 <= x < n*dx),
+ * momenta are u = gamma*v per unit mass.  2D means the (x, z) plane with y
+ * invariant and three velocity components; z is the beam axis.
+ *
+ * Memory: the caller owns one device arena (any allocator; the Python binding
+ * uses a torch uint8 tensor) whose size pic_plan() reports.  The library keeps
+ * every field, particle and tile array inside it and allocates no device
+ * memory of its own.  A state is bound to one HIP stream and is not
+ * thread-safe.  Every function returns PIC_OK (0) or a negative PIC_E* code
+ * and never throws across the ABI.
+ */
+#ifndef PIC_API_H
+#define PIC_API_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define PIC_OK            0
+#define PIC_EINVAL       -1   /* bad argument, shape or order */
+#define PIC_ECOURANT     -2   /* c dt >= 1 / sqrt(sum 1/d^2): Yee unstable */
+#define PIC_EPSI         -3   /* Psi_E or Psi_B <= 0 somewhere on s in [0,1], or
+                                 a singular interpolation system (Sec. 3 notes a
+                                 breakdown window of the determination) */
+#define PIC_ENOMEM       -4   /* arena smaller than pic_plan() asked for */
+#define PIC_EHIP         -5   /* a HIP runtime call failed */
+#define PIC_ENONFINITE   -6   /* pic_diag found a NaN or Inf */
+#define PIC_EPARTICLE    -7   /* a particle moved a full cell or more in a step */
+#define PIC_EUNSUPPORTED -8   /* valid but not built (e.g. Uniform gather) */
+#define PIC_ESTATE       -9   /* call not valid in the current state */
+
+/* ------------------------------------------------------------- enumerations */
+#define PIC_GALERKIN 0        /* Eq. 3 scheme (gather built) */
+#define PIC_UNIFORM  1        /* Eq. 4 scheme (coefficients only) */
+#define PIC_MOMENTUM 2        /* Eq. 5 scheme (coefficients only) */
+
+#define PIC_FP64 0            /* fields, offsets, momenta and J in double */
+#define PIC_FP32 1            /* float fields/offsets/momenta, int32 cell index,
+                                 J accumulated as 64-bit fixed point */
+
+#define PIC_IONS_CHARGE             0  /* immobile ions carry charge only */
+#define PIC_IONS_CHARGE_AND_CURRENT 1  /* plus a fixed uniform current equal to
+                                          minus the beam's initial mean current */
+
+/* field selectors for pic_fields */
+#define PIC_FIELD_E      0    /* E^n on the Yee mesh */
+#define PIC_FIELD_B      1    /* B^n */
+#define PIC_FIELD_J      2    /* J^{n+1/2} deposited by the last step */
+#define PIC_FIELD_SEEN_E 3    /* E as seen by the particles in the last step */
+#define PIC_FIELD_SEEN_B 4    /* B as seen by the particles in the last step */
+#define PIC_FIELD_RHO    5    /* charge density of the current particles (comp 0) */
+
+#define PIC_GET 0
+#define PIC_SET 1
+
+#define PIC_SCHED_BATCHED 0   /* every kernel launched once over all instances */
+#define PIC_SCHED_PLAIN   1   /* each kernel launched once per instance */
+
+/* ----------------------------------------------------------- configuration */
+typedef struct pic_config {
+    int    dims;              /* 2 (x, z) or 3 (x, y, z) */
+    int    nx, ny, nz;        /* cells per axis, periodic; ny must be 1 in 2D */
+    double dx, dy, dz;        /* cell sizes (dy ignored in 2D) */
+    double cdt;               /* c * dt */
+    int    shape_order;       /* charge shape order l: 1 or 3 */
+    int    interp;            /* PIC_GALERKIN */
+    int    precision;         /* PIC_FP64 or PIC_FP32; equal for all instances */
+    int    correction;        /* 1: apply Psi_E / Psi_B (Sec. 2) */
+    int    psi_deg;           /* polynomial degree of Psi_E and Psi_B, <= 8 */
+    double psi_e[9];          /* Psi_E(s) = sum_j psi_e[j] s^j, psi_e[0] = 1 */
+    double psi_b[9];          /* Psi_B(s) = sum_j psi_b[j] s^j, psi_b[0] = 1 */
+    int    filter_npass;      /* 3-point passes per axis, <= 8 */
+    double filter_w[8];       /* pass j is (w, 1-2w, w): 0.25 bilinear, -1 compensation */
+    double q, m;              /* species charge and mass */
+    double weight;            /* macro-particle weight (real particles per macro-particle
+                                 per unit cell volume times cell volume) */
+    int    ion_mode;          /* PIC_IONS_* */
+    int    tile[3];           /* particle tile in cells along x, y, z (0 = default) */
+    int    block;             /* threads per particle workgroup: 0 (default), 256 or 512 */
+    int    trace_capacity;    /* steps of per-step field-energy trace kept on the device */
+} pic_config;
+
+/* particles of one instance as host float64 arrays (structure of arrays) */
+typedef struct pic_particles {
+    int64_t       n;
+    const double *pos[3];     /* absolute x, y, z positions; pos[1] ignored in 2D */
+    const double *mom[3];     /* u_x, u_y, u_z */
+} pic_particles;
+
+typedef struct pic_diag_t {
+    double  WE[3], WB[3];     /* 1/2 sum E_c^2 dV and 1/2 sum B_c^2 dV (E^n, B^n) */
+    double  Wkin;             /* sum w m (gamma - 1) over particles (u^{n+1/2}) */
+    double  gauss_l2;         /* ||(div E - rho) - (div E - rho)_initial||_2 on nodes */
+    double  gauss_linf;       /* same, max norm; both at the particles' time level */
+    double  charge;           /* sum rho dV */
+    double  rho_max;          /* max |rho| (scale for the Gauss residual) */
+    int64_t n_particles;
+    int64_t step;             /* steps taken since pic_init */
+    int     nonfinite;        /* 1 if any field or momentum is NaN / Inf */
+    int     particle_error;   /* 1 if a particle moved a full cell or more */
+    int     resorts;          /* tile re-sorts done since pic_init */
+    int     slow_tiles;       /* tile visits that overflowed the LDS window */
+} pic_diag_t;
+
+/* per-kernel average durations measured with HIP events (milliseconds) */
+typedef struct pic_timing_t {
+    double yee_ms, seen_ms, particle_ms, resort_ms, step_ms;
+    int    steps;
+} pic_timing_t;
+
+struct pic_state;
+typedef struct pic_state pic_state;
+
+/* Correction-stencil coefficients (Sec. 2): the power-series coefficients of
+ * Psi_E and Psi_B in s = sin^2(k_z dz/2), from rational interpolation of the
+ * multiplier of Eq. 3 (PIC_GALERKIN), Eq. 4 (PIC_UNIFORM) or Eq. 5
+ * (PIC_MOMENTUM) at 2*deg+1 nodes spaced uniformly on s in [0, 1]
+ * (9 nodes, quartics, for deg = 4), with psi_b[0] = 1.  alpha = c dt / dz.
+ * Solved in 113-bit binary floating point and rounded to double.  Returns
+ * PIC_EPSI if the system is singular (except where the multiplier is
+ * identically 1, which gives Psi_E = Psi_B = 1) or if either polynomial is
+ * <= 0 somewhere on s in [0, 1].  Writes deg+1 doubles to each output. */
+int pic_psi_coeffs(int interp, double alpha, int deg, double *psi_e, double *psi_b);
+
+/* Size in bytes of the device arena for n_inst instances with the given
+ * particle counts. */
+int pic_plan(const pic_config *cfgs, int n_inst, const int64_t *n_particles, size_t *arena_bytes);
+
+/* Validate the configurations, lay them out in the arena, upload the
+ * particles (host float64 -> device; converted to cell index + in-cell
+ * offset), sort them by tile and record the initial charge density.
+ * d_arena: device pointer of arena_bytes bytes (256-byte aligned), owned by
+ * the caller and kept alive until pic_destroy.  hip_stream: hipStream_t or
+ * NULL for the default stream.  Blocks until the upload is complete. */
+int pic_init(const pic_config *cfgs, int n_inst, const pic_particles *parts,
+             void *d_arena, size_t arena_bytes, void *hip_stream, pic_state **out);
+
+/* Advance every instance by nsteps steps.  Asynchronous on the bound stream. */
+int pic_step(pic_state *st, int nsteps);
+
+/* Choose the launch schedule (PIC_SCHED_*) and whether steps are replayed
+ * from a captured HIP graph (use_graph = 1) or launched eagerly. */
+int pic_set_schedule(pic_state *st, int sched, int use_graph);
+
+/* Copy one component of a grid quantity (PIC_FIELD_*) of instance inst to
+ * (GET) or from (SET) a host float64 array of n = nx*ny*nz values laid out
+ * [z][y][x], x fastest, half-integer locations stored at the lower index.
+ * SET is allowed for E and B only.  Synchronises the stream. */
+int pic_fields(pic_state *st, int inst, int which, int comp, double *host, size_t n, int dir);
+
+/* Copy the particles of instance inst to host float64 arrays in the order
+ * they were given to pic_init (absolute positions wrapped into the box).
+ * pos[1] may be NULL in 2D.  Synchronises the stream. */
+int pic_get_particles(pic_state *st, int inst, double *pos[3], double *mom[3], int64_t n);
+
+/* Diagnostics of instance inst (float64 reductions on the device).
+ * Synchronises the stream.  Returns PIC_ENONFINITE or PIC_EPARTICLE when the
+ * corresponding flag is set (out is filled in either case). */
+int pic_diag(pic_state *st, int inst, pic_diag_t *out);
+
+/* Per-step transverse and total field energies recorded since pic_init when
+ * trace_capacity > 0: host_out receives count rows of 6 doubles
+ * (WE_x, WE_y, WE_z, WB_x, WB_y, WB_z) for the last min(steps, capacity) steps
+ * in step order; *count is set to the number of rows written. */
+int pic_read_trace(pic_state *st, int inst, double *host_out, int max_rows, int *count);
+
+/* Run nsteps steps with HIP events around every kernel of the step and
+ * report average durations.  Synchronises the stream. */
+int pic_profile(pic_state *st, int nsteps, pic_timing_t *out);
+
+/* Number of instances, and the total particle count over all instances. */
+int pic_info(pic_state *st, int *n_inst, int64_t *n_particles, int64_t *n_cells);
+
+void pic_destroy(pic_state *st);
+
+/* Static description of a status code. */
+const char *pic_strerror(int code);
+
+/* Text of the most recent error on this thread (HIP error names included). */
+const char *pic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_API_H */

@@ -1,0 +1,865 @@
+// Host side of the C ABI declared in include/pic_api.h: configuration checks,
+// device arena layout, particle upload and tile sort, work lists, launch
+// schedules (batched or per instance, eager or HIP-graph replay), and the
+// accessors for fields, particles and diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pic_api.h"
+#include "pic_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            return fail(PIC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+struct Range { int off, n; };
+
+struct Layout {
+    size_t bytes = 0;
+    char *base = nullptr;
+    template <class T> T *take(size_t count)
+    {
+        bytes = (bytes + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + bytes) : nullptr;
+        bytes += count * sizeof(T);
+        return p;
+    }
+};
+
+int default_block() { return 256; }
+
+// tile size and slack per axis for an instance
+void tile_shape(const pic_config &c, int tile[3], int &slack)
+{
+    const int n[3] = {c.nx, c.dims == 3 ? c.ny : 1, c.nz};
+    int def[3];
+    if (c.dims == 2) {
+        def[0] = 16; def[1] = 1; def[2] = 16;
+        slack = 4;
+    } else {
+        def[0] = c.shape_order == 1 ? 8 : 4; def[1] = c.shape_order == 1 ? 4 : 4; def[2] = c.shape_order == 1 ? 4 : 4;
+        slack = 2;
+    }
+    for (int a = 0; a < 3; a++) {
+        int t = c.tile[a] > 0 ? c.tile[a] : def[a];
+        if (c.dims == 2 && a == 1) t = 1;
+        tile[a] = std::min(t, n[a]);
+    }
+}
+
+int validate(const pic_config &c, int idx)
+{
+    char buf[256];
+    auto bad = [&](int code, const char *what) {
+        snprintf(buf, sizeof buf, "instance %d: %s", idx, what);
+        return fail(code, buf);
+    };
+    if (c.dims != 2 && c.dims != 3) return bad(PIC_EINVAL, "dims must be 2 or 3");
+    if (c.nx < 1 || c.nz < 1 || c.ny < 1) return bad(PIC_EINVAL, "cell counts must be >= 1");
+    if (c.dims == 2 && c.ny != 1) return bad(PIC_EINVAL, "ny must be 1 in 2D");
+    if ((double)c.nx * c.ny * c.nz > 2.0e9) return bad(PIC_EINVAL, "grid too large for int32 cell index");
+    if (!(c.dx > 0) || !(c.dz > 0) || (c.dims == 3 && !(c.dy > 0))) return bad(PIC_EINVAL, "cell sizes must be > 0");
+    if (!(c.cdt > 0)) return bad(PIC_EINVAL, "c dt must be > 0");
+    double s = 1.0 / (c.dx * c.dx) + 1.0 / (c.dz * c.dz) + (c.dims == 3 ? 1.0 / (c.dy * c.dy) : 0.0);
+    if (c.cdt * std::sqrt(s) >= 1.0) return bad(PIC_ECOURANT, "Courant limit c dt < 1/sqrt(sum 1/d^2) violated");
+    if (c.shape_order != 1 && c.shape_order != 3) return bad(PIC_EINVAL, "shape_order must be 1 or 3");
+    if (c.interp != PIC_GALERKIN) return bad(PIC_EUNSUPPORTED, "only the Galerkin gather is built");
+    if (c.precision != PIC_FP32 && c.precision != PIC_FP64) return bad(PIC_EINVAL, "precision");
+    if (c.filter_npass < 0 || c.filter_npass > 8) return bad(PIC_EINVAL, "filter_npass must be in [0, 8]");
+    if (c.correction) {
+        if (c.psi_deg < 1 || c.psi_deg > 8) return bad(PIC_EINVAL, "psi_deg must be in [1, 8]");
+        if (c.psi_deg + c.filter_npass > PIC_MAX_HZ) return bad(PIC_EINVAL, "z stencil too wide");
+        for (int k = 0; k <= 4096; k++) {
+            double x = k / 4096.0, pe = 0, pb = 0;
+            for (int i = c.psi_deg; i >= 0; i--) { pe = pe * x + c.psi_e[i]; pb = pb * x + c.psi_b[i]; }
+            if (!(pe > 0.0) || !(pb > 0.0)) return bad(PIC_EPSI, "Psi_E or Psi_B <= 0 on s in [0,1]");
+        }
+    }
+    if (!(c.m > 0) || !(c.weight >= 0) || !std::isfinite(c.q)) return bad(PIC_EINVAL, "species parameters");
+    if (c.ion_mode != PIC_IONS_CHARGE && c.ion_mode != PIC_IONS_CHARGE_AND_CURRENT) return bad(PIC_EINVAL, "ion_mode");
+    if (c.block != 0 && c.block != 256 && c.block != 512) return bad(PIC_EINVAL, "block must be 0, 256 or 512");
+    if (c.trace_capacity < 0) return bad(PIC_EINVAL, "trace_capacity");
+    return PIC_OK;
+}
+
+// polynomial (in the stencil algebra) convolution helpers: taps centred arrays
+std::vector<double> conv(const std::vector<double> &a, const std::vector<double> &b)
+{
+    std::vector<double> r(a.size() + b.size() - 1, 0.0);
+    for (size_t i = 0; i < a.size(); i++)
+        for (size_t j = 0; j < b.size(); j++) r[i + j] += a[i] * b[j];
+    return r;
+}
+
+// taps of Psi(S_z) with S_z = -(1/4)(1,-2,1): sum_j c_j S_z^j
+std::vector<double> psi_taps(const double *c, int deg)
+{
+    const std::vector<double> S = {-0.25, 0.5, -0.25};
+    std::vector<double> pw = {1.0};
+    std::vector<double> acc(2 * deg + 1, 0.0);
+    for (int j = 0; j <= deg; j++) {
+        for (size_t t = 0; t < pw.size(); t++) acc[deg - j + t] += c[j] * pw[t];
+        pw = conv(pw, S);
+    }
+    return acc;
+}
+
+std::vector<double> filter_taps(const pic_config &c)
+{
+    std::vector<double> t = {1.0};
+    for (int k = 0; k < c.filter_npass; k++) {
+        const double w = c.filter_w[k];
+        t = conv(t, {w, 1.0 - 2.0 * w, w});
+    }
+    return t;
+}
+
+}  // namespace
+
+struct pic_state {
+    int n_inst = 0, dims = 2, order = 1, fp32 = 1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    std::vector<pic_config> cfg;
+    std::vector<InstDesc> desc;
+    std::vector<int64_t> np;
+    InstDesc *d_desc = nullptr;
+    int2 *fwork = nullptr, *pwork = nullptr, *cwork = nullptr;
+    int nfwork = 0, npwork = 0, ncwork = 0;
+    std::vector<Range> frange, prange, crange;
+    int wmax[3] = {1, 1, 1};
+    int block = 256;
+    int sched = PIC_SCHED_BATCHED, use_graph = 1;
+    int graph_k = 8;                 // steps per captured graph (and re-sort period)
+    hipGraphExec_t gexec_k = nullptr, gexec_1 = nullptr;
+    long long step = 0;
+    int *trace_pos = nullptr;
+    double *trace = nullptr;
+    int trace_cap = 0;
+    int *h_flags_tmp = nullptr;
+};
+
+namespace {
+
+LaunchCtx ctx(const pic_state *s)
+{
+    LaunchCtx c;
+    c.desc = s->d_desc;
+    c.stream = s->stream;
+    c.dims = s->dims;
+    c.order = s->order;
+    c.fp32 = s->fp32;
+    return c;
+}
+
+// Lay out all arrays; with base == nullptr only the size is computed.
+size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *np, char *base)
+{
+    Layout L;
+    L.base = base;
+    const size_t R = cfgs[0].precision == PIC_FP32 ? 4 : 8;
+    InstDesc *dd = L.take<InstDesc>(n_inst);
+    if (s) s->d_desc = dd;
+    size_t nf = 0, npw = 0, nc = 0;
+    std::vector<int> ntiles(n_inst);
+    for (int i = 0; i < n_inst; i++) {
+        const pic_config &c = cfgs[i];
+        const size_t ncell = (size_t)c.nx * c.ny * c.nz;
+        int tile[3], slack;
+        tile_shape(c, tile, slack);
+        const int nt = ((c.nx + tile[0] - 1) / tile[0]) * ((c.ny + tile[1] - 1) / tile[1]) *
+                       ((c.nz + tile[2] - 1) / tile[2]);
+        ntiles[i] = nt;
+        nf += (ncell + PIC_FIELD_CHUNK - 1) / PIC_FIELD_CHUNK;
+        npw += nt;
+        nc += (np[i] + PIC_PART_CHUNK - 1) / PIC_PART_CHUNK;
+    }
+    int2 *fw = L.take<int2>(nf), *pw = L.take<int2>(npw), *cw = L.take<int2>(std::max<size_t>(nc, 1));
+    if (s) { s->fwork = fw; s->pwork = pw; s->cwork = cw; }
+    int *tpos = L.take<int>(64);
+    if (s) s->trace_pos = tpos;
+    int cap = 0;
+    for (int i = 0; i < n_inst; i++) cap = std::max(cap, cfgs[i].trace_capacity);
+    double *tr = L.take<double>((size_t)std::max(cap, 1) * n_inst * 6);
+    if (s) { s->trace = tr; s->trace_cap = cap; }
+    for (int i = 0; i < n_inst; i++) {
+        const pic_config &c = cfgs[i];
+        const size_t ncell = (size_t)c.nx * c.ny * c.nz;
+        const size_t n = (size_t)np[i];
+        InstDesc *D = s ? &s->desc[i] : nullptr;
+        auto plane = [&](size_t bytes_per) { return (void *)L.take<char>(ncell * bytes_per); };
+        for (int k = 0; k < 3; k++) {
+            void *e = plane(R), *b = plane(R), *et = plane(R), *bt = plane(R), *j = plane(8);
+            if (D) { D->E[k] = e; D->B[k] = b; D->Et[k] = et; D->Bt[k] = bt; D->J[k] = j; }
+        }
+        for (int k = 0; k < 6; k++) {
+            void *t1 = plane(R);
+            void *t2 = c.dims == 3 ? plane(R) : nullptr;
+            if (D) { D->T1[k] = t1; D->T2[k] = t2; }
+        }
+        double *r0 = L.take<double>(ncell), *r1 = L.take<double>(ncell);
+        int *pidx = L.take<int>(n), *ppid = L.take<int>(n);
+        int *sidx = L.take<int>(n), *spid = L.take<int>(n), *srank = L.take<int>(n), *stile = L.take<int>(n);
+        void *poff[3] = {nullptr, nullptr, nullptr}, *pu[3], *soff[3] = {nullptr, nullptr, nullptr}, *su[3];
+        for (int a = 0; a < 3; a++) {
+            if (!(c.dims == 2 && a == 1)) { poff[a] = L.take<char>(n * R); soff[a] = L.take<char>(n * R); }
+            pu[a] = L.take<char>(n * R);
+            su[a] = L.take<char>(n * R);
+        }
+        int *tstart = L.take<int>(ntiles[i] + 1), *tbox = L.take<int>((size_t)ntiles[i] * 6);
+        int *tcount = L.take<int>(ntiles[i]);
+        int *flags = L.take<int>(FLAG_COUNT);
+        double *diag = L.take<double>(DG_COUNT);
+        if (D) {
+            D->rho0 = r0; D->rho = r1;
+            D->pidx = pidx; D->ppid = ppid; D->sidx = sidx; D->spid = spid; D->srank = srank; D->stile = stile;
+            for (int a = 0; a < 3; a++) { D->poff[a] = poff[a]; D->pu[a] = pu[a]; D->soff[a] = soff[a]; D->su[a] = su[a]; }
+            D->tstart = tstart; D->tbox = tbox; D->tcount = tcount; D->flags = flags; D->diag = diag;
+            D->trace = tr;
+        }
+    }
+    return L.bytes + 256;
+}
+
+void fill_desc(InstDesc &D, const pic_config &c, const pic_particles &p)
+{
+    const bool f32 = c.precision == PIC_FP32;
+    D.n[0] = c.nx; D.n[1] = c.dims == 3 ? c.ny : 1; D.n[2] = c.nz;
+    D.ncell = D.n[0] * D.n[1] * D.n[2];
+    int slack;
+    tile_shape(c, D.tile, slack);
+    for (int a = 0; a < 3; a++) D.nt[a] = (D.n[a] + D.tile[a] - 1) / D.tile[a];
+    D.ntiles = D.nt[0] * D.nt[1] * D.nt[2];
+    D.trace_cap = c.trace_capacity;
+    D.np = p.n;
+    D.d[0] = c.dx; D.d[1] = c.dims == 3 ? c.dy : 1.0; D.d[2] = c.dz;
+    D.dt = c.cdt;
+    for (int a = 0; a < 3; a++) D.dtd[a] = c.cdt / D.d[a];
+    D.qdt2m = c.q * c.cdt / (2.0 * c.m);
+    D.w = c.weight;
+    D.m = c.m;
+    D.dV = c.dims == 3 ? c.dx * c.dy * c.dz : c.dx * c.dz;
+    const double qw = c.q * c.weight;
+    // fixed-point quantum: 2^-28 of the largest single-particle contribution scale
+    double U = std::fabs(qw) / D.dV;
+    for (int a = 0; a < 3; a++) U = std::max(U, std::fabs(qw) * D.d[a] / (c.cdt * D.dV));
+    D.jq = (f32 && U > 0) ? U * std::ldexp(1.0, -28) : 1.0;
+    const double sc = f32 ? 1.0 / D.jq : 1.0;
+    for (int a = 0; a < 3; a++) D.cdep[a] = -qw * D.d[a] / (c.cdt * D.dV) * sc;
+    D.cy2d = qw / D.dV * sc;
+    D.rho_c = qw / D.dV;
+    // uniform ion current: minus the initial mean beam current
+    double sv[3] = {0, 0, 0};
+    if (c.ion_mode == PIC_IONS_CHARGE_AND_CURRENT) {
+        for (int64_t i = 0; i < p.n; i++) {
+            const double ux = p.mom[0][i], uy = p.mom[1][i], uz = p.mom[2][i];
+            const double ig = 1.0 / std::sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+            sv[0] += ux * ig; sv[1] += uy * ig; sv[2] += uz * ig;
+        }
+    }
+    for (int a = 0; a < 3; a++) D.jbg[a] = -qw * sv[a] / ((double)D.ncell * D.dV);
+    // seen-field stencils
+    const std::vector<double> fz = filter_taps(c);
+    std::vector<double> ze = fz, zb = fz;
+    if (c.correction) {
+        ze = conv(psi_taps(c.psi_e, c.psi_deg), fz);
+        zb = conv(psi_taps(c.psi_b, c.psi_deg), fz);
+    }
+    D.hz = (int)(ze.size() / 2);
+    D.hx = (int)(fz.size() / 2);
+    D.hy = c.dims == 3 ? D.hx : 0;
+    std::memset(D.tz, 0, sizeof D.tz);
+    std::memset(D.tx, 0, sizeof D.tx);
+    std::memset(D.ty, 0, sizeof D.ty);
+    for (size_t t = 0; t < ze.size(); t++) { D.tz[0][t] = ze[t]; D.tz[1][t] = zb[t]; }
+    for (size_t t = 0; t < fz.size(); t++) { D.tx[t] = fz[t]; D.ty[t] = fz[t]; }
+}
+
+template <class R>
+int upload_particles(pic_state *s, int inst, const pic_particles &p)
+{
+    const InstDesc &D = s->desc[inst];
+    const int dims = s->dims;
+    const int64_t n = p.n;
+    std::vector<int> cell(n), tile(n), rank(n);
+    std::vector<R> off[3];
+    for (int a = 0; a < 3; a++) off[a].resize(dims == 2 && a == 1 ? 0 : n);
+    for (int64_t i = 0; i < n; i++) {
+        int c[3] = {0, 0, 0};
+        for (int a = 0; a < 3; a++) {
+            if (dims == 2 && a == 1) continue;
+            const double x = p.pos[a][i] / D.d[a];
+            double f = std::floor(x);
+            double o = x - f;
+            long long ci = (long long)f;
+            R ro = (R)o;
+            if (ro >= R(1)) { ro = R(0); ci += 1; }
+            ci %= D.n[a];
+            if (ci < 0) ci += D.n[a];
+            c[a] = (int)ci;
+            off[a][i] = ro;
+        }
+        cell[i] = (c[2] * D.n[1] + c[1]) * D.n[0] + c[0];
+        tile[i] = ((c[2] / D.tile[2]) * D.nt[1] + c[1] / D.tile[1]) * D.nt[0] + c[0] / D.tile[0];
+    }
+    // order: by tile, then by rank within the cell, then by cell, so that
+    // consecutive lanes of a wavefront work on different cells
+    std::vector<int> cnt(D.ncell, 0);
+    int kmax = 0;
+    for (int64_t i = 0; i < n; i++) { rank[i] = cnt[cell[i]]++; kmax = std::max(kmax, rank[i] + 1); }
+    std::vector<int64_t> order(n), tmp(n);
+    {   // stable counting sort by cell
+        std::vector<int64_t> off_c(D.ncell + 1, 0);
+        for (int64_t i = 0; i < n; i++) off_c[cell[i] + 1]++;
+        for (int c = 0; c < D.ncell; c++) off_c[c + 1] += off_c[c];
+        for (int64_t i = 0; i < n; i++) order[off_c[cell[i]]++] = i;
+    }
+    {   // stable by rank
+        std::vector<int64_t> off_k(kmax + 1, 0);
+        for (int64_t i = 0; i < n; i++) off_k[rank[i] + 1]++;
+        for (int k = 0; k < kmax; k++) off_k[k + 1] += off_k[k];
+        for (int64_t j = 0; j < n; j++) { int64_t i = order[j]; tmp[off_k[rank[i]]++] = i; }
+    }
+    std::vector<int> tstart(D.ntiles + 1, 0);
+    {   // stable by tile
+        for (int64_t i = 0; i < n; i++) tstart[tile[i] + 1]++;
+        for (int t = 0; t < D.ntiles; t++) tstart[t + 1] += tstart[t];
+        std::vector<int> fill(tstart.begin(), tstart.end() - 1);
+        for (int64_t j = 0; j < n; j++) { int64_t i = tmp[j]; order[fill[tile[i]]++] = i; }
+    }
+    std::vector<int> h_idx(n), h_pid(n);
+    std::vector<R> h_off[3], h_u[3];
+    for (int a = 0; a < 3; a++) {
+        if (!(dims == 2 && a == 1)) h_off[a].resize(n);
+        h_u[a].resize(n);
+    }
+    for (int64_t j = 0; j < n; j++) {
+        const int64_t i = order[j];
+        h_idx[j] = cell[i];
+        h_pid[j] = (int)i;
+        for (int a = 0; a < 3; a++) {
+            if (!(dims == 2 && a == 1)) h_off[a][j] = off[a][i];
+            h_u[a][j] = (R)p.mom[a][i];
+        }
+    }
+    hipStream_t st = s->stream;
+    HIP_TRY(hipMemcpyAsync(D.pidx, h_idx.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(D.ppid, h_pid.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+    for (int a = 0; a < 3; a++) {
+        if (!(dims == 2 && a == 1))
+            HIP_TRY(hipMemcpyAsync(D.poff[a], h_off[a].data(), n * sizeof(R), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(D.pu[a], h_u[a].data(), n * sizeof(R), hipMemcpyHostToDevice, st));
+    }
+    HIP_TRY(hipMemcpyAsync(D.tstart, tstart.data(), tstart.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));   // host vectors go out of scope
+    return PIC_OK;
+}
+
+// XCD-aware order of one instance's tiles: launch slot b runs on XCD b % 8,
+// so give each XCD a contiguous run of tiles (their halos share that XCD's L2)
+void tile_order(int nt, std::vector<int> &out)
+{
+    out.resize(nt);
+    if (nt % 8 != 0) {
+        for (int t = 0; t < nt; t++) out[t] = t;
+        return;
+    }
+    const int per = nt / 8;
+    for (int b = 0; b < nt; b++) out[b] = (b % 8) * per + b / 8;
+}
+
+int build_worklists(pic_state *s)
+{
+    std::vector<int2> fw, pw, cw;
+    s->frange.clear(); s->prange.clear(); s->crange.clear();
+    std::vector<int> ord;
+    for (int i = 0; i < s->n_inst; i++) {
+        const InstDesc &D = s->desc[i];
+        Range r{(int)fw.size(), 0};
+        for (int k = 0; k < (D.ncell + PIC_FIELD_CHUNK - 1) / PIC_FIELD_CHUNK; k++) fw.push_back(make_int2(i, k));
+        r.n = (int)fw.size() - r.off;
+        s->frange.push_back(r);
+        Range q{(int)pw.size(), 0};
+        tile_order(D.ntiles, ord);
+        for (int t = 0; t < D.ntiles; t++) pw.push_back(make_int2(i, ord[t]));
+        q.n = (int)pw.size() - q.off;
+        s->prange.push_back(q);
+        Range c{(int)cw.size(), 0};
+        for (long long k = 0; k < (D.np + PIC_PART_CHUNK - 1) / PIC_PART_CHUNK; k++) cw.push_back(make_int2(i, (int)k));
+        c.n = (int)cw.size() - c.off;
+        s->crange.push_back(c);
+    }
+    s->nfwork = (int)fw.size();
+    s->npwork = (int)pw.size();
+    s->ncwork = (int)cw.size();
+    HIP_TRY(hipMemcpyAsync(s->fwork, fw.data(), fw.size() * sizeof(int2), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->pwork, pw.data(), pw.size() * sizeof(int2), hipMemcpyHostToDevice, s->stream));
+    if (!cw.empty())
+        HIP_TRY(hipMemcpyAsync(s->cwork, cw.data(), cw.size() * sizeof(int2), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return PIC_OK;
+}
+
+// one step's launches for instances [i0, i0 + ni) using the given work ranges
+int enqueue_step_range(pic_state *s, const Range &f, const Range &p, bool trace)
+{
+    LaunchCtx c = ctx(s);
+    if (launch_yee(c, s->fwork + f.off, f.n)) return fail(PIC_EHIP, "yee launch");
+    if (launch_seen(c, s->fwork + f.off, f.n)) return fail(PIC_EHIP, "seen launch");
+    if (launch_particles(c, s->pwork + p.off, p.n, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particle launch");
+    (void)trace;
+    return PIC_OK;
+}
+
+int enqueue_step(pic_state *s)
+{
+    if (s->sched == PIC_SCHED_BATCHED) {
+        int rc = enqueue_step_range(s, Range{0, s->nfwork}, Range{0, s->npwork}, false);
+        if (rc) return rc;
+    } else {
+        for (int i = 0; i < s->n_inst; i++) {
+            int rc = enqueue_step_range(s, s->frange[i], s->prange[i], false);
+            if (rc) return rc;
+        }
+    }
+    if (s->trace_cap > 0) {
+        LaunchCtx c = ctx(s);
+        if (launch_trace_rows(c, s->fwork, s->nfwork, s->trace_pos, s->trace, s->n_inst, s->trace_cap))
+            return fail(PIC_EHIP, "trace launch");
+    }
+    return PIC_OK;
+}
+
+int enqueue_resort(pic_state *s)
+{
+    LaunchCtx c = ctx(s);
+    if (s->sched == PIC_SCHED_BATCHED) {
+        if (launch_resort(c, s->cwork, s->ncwork, 0, s->n_inst)) return fail(PIC_EHIP, "resort launch");
+    } else {
+        for (int i = 0; i < s->n_inst; i++)
+            if (launch_resort(c, s->cwork + s->crange[i].off, s->crange[i].n, i, 1))
+                return fail(PIC_EHIP, "resort launch");
+    }
+    return PIC_OK;
+}
+
+void drop_graphs(pic_state *s)
+{
+    if (s->gexec_k) { (void)hipGraphExecDestroy(s->gexec_k); s->gexec_k = nullptr; }
+    if (s->gexec_1) { (void)hipGraphExecDestroy(s->gexec_1); s->gexec_1 = nullptr; }
+}
+
+int capture(pic_state *s, int k, bool with_resort, hipGraphExec_t *out)
+{
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    int rc = PIC_OK;
+    for (int i = 0; i < k && rc == PIC_OK; i++) rc = enqueue_step(s);
+    if (rc == PIC_OK && with_resort) rc = enqueue_resort(s);
+    hipError_t e = hipStreamEndCapture(s->stream, &g);
+    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return fail(PIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(PIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return PIC_OK;
+}
+
+template <class R>
+int copy_plane_out(pic_state *s, const void *src, size_t n, double *host, double scale, bool is_j)
+{
+    if (is_j && s->fp32) {
+        std::vector<long long> tmp(n);
+        HIP_TRY(hipMemcpyAsync(tmp.data(), src, n * 8, hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        for (size_t i = 0; i < n; i++) host[i] = (double)tmp[i] * scale;
+        return PIC_OK;
+    }
+    if (is_j) {
+        HIP_TRY(hipMemcpyAsync(host, src, n * 8, hipMemcpyDeviceToHost, s->stream));
+        return hipStreamSynchronize(s->stream) == hipSuccess ? PIC_OK : fail(PIC_EHIP, "sync");
+    }
+    std::vector<R> tmp(n);
+    HIP_TRY(hipMemcpyAsync(tmp.data(), src, n * sizeof(R), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (size_t i = 0; i < n; i++) host[i] = (double)tmp[i];
+    return PIC_OK;
+}
+
+template <class R>
+int copy_plane_in(pic_state *s, void *dst, size_t n, const double *host)
+{
+    std::vector<R> tmp(n);
+    for (size_t i = 0; i < n; i++) tmp[i] = (R)host[i];
+    HIP_TRY(hipMemcpyAsync(dst, tmp.data(), n * sizeof(R), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return PIC_OK;
+}
+
+template <class R>
+int get_particles(pic_state *s, int inst, double *pos[3], double *mom[3])
+{
+    const InstDesc &D = s->desc[inst];
+    const size_t n = (size_t)D.np;
+    std::vector<int> idx(n), pid(n);
+    std::vector<R> off[3], u[3];
+    HIP_TRY(hipMemcpyAsync(idx.data(), D.pidx, n * 4, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(pid.data(), D.ppid, n * 4, hipMemcpyDeviceToHost, s->stream));
+    for (int a = 0; a < 3; a++) {
+        u[a].resize(n);
+        HIP_TRY(hipMemcpyAsync(u[a].data(), D.pu[a], n * sizeof(R), hipMemcpyDeviceToHost, s->stream));
+        if (D.poff[a]) {
+            off[a].resize(n);
+            HIP_TRY(hipMemcpyAsync(off[a].data(), D.poff[a], n * sizeof(R), hipMemcpyDeviceToHost, s->stream));
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (size_t j = 0; j < n; j++) {
+        const int i = pid[j];
+        if (i < 0 || (size_t)i >= n) return fail(PIC_ESTATE, "corrupt particle ids");
+        int c[3];
+        c[0] = idx[j] % D.n[0];
+        c[1] = (idx[j] / D.n[0]) % D.n[1];
+        c[2] = idx[j] / (D.n[0] * D.n[1]);
+        for (int a = 0; a < 3; a++) {
+            if (mom[a]) mom[a][i] = (double)u[a][j];
+            if (pos[a] && D.poff[a]) pos[a][i] = ((double)c[a] + (double)off[a][j]) * D.d[a];
+        }
+    }
+    return PIC_OK;
+}
+
+}  // namespace
+
+// ==================================================================== C ABI
+
+extern "C" const char *pic_strerror(int code)
+{
+    switch (code) {
+    case PIC_OK: return "ok";
+    case PIC_EINVAL: return "invalid argument";
+    case PIC_ECOURANT: return "time step violates the Yee Courant limit";
+    case PIC_EPSI: return "correction polynomials not positive on [0,1] or singular interpolation";
+    case PIC_ENOMEM: return "device arena too small";
+    case PIC_EHIP: return "HIP runtime error";
+    case PIC_ENONFINITE: return "non-finite value in fields or particles";
+    case PIC_EPARTICLE: return "particle moved a full cell or more in one step";
+    case PIC_EUNSUPPORTED: return "configuration not supported by this build";
+    case PIC_ESTATE: return "invalid state";
+    }
+    return "unknown error";
+}
+
+extern "C" const char *pic_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int pic_plan(const pic_config *cfgs, int n_inst, const int64_t *n_particles, size_t *arena_bytes)
+{
+    if (!cfgs || n_inst < 1 || !n_particles || !arena_bytes) return fail(PIC_EINVAL, "null argument");
+    for (int i = 0; i < n_inst; i++) {
+        int rc = validate(cfgs[i], i);
+        if (rc) return rc;
+        if (cfgs[i].dims != cfgs[0].dims || cfgs[i].precision != cfgs[0].precision ||
+            cfgs[i].shape_order != cfgs[0].shape_order)
+            return fail(PIC_EINVAL, "all instances must share dims, precision and shape_order");
+        if (n_particles[i] < 0 || n_particles[i] > INT32_MAX) return fail(PIC_EINVAL, "particle count");
+    }
+    *arena_bytes = layout(nullptr, cfgs, n_inst, n_particles, nullptr);
+    return PIC_OK;
+}
+
+extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles *parts, void *d_arena,
+                        size_t arena_bytes, void *hip_stream, pic_state **out)
+{
+    if (!out || !parts || !d_arena) return fail(PIC_EINVAL, "null argument");
+    *out = nullptr;
+    std::vector<int64_t> np(n_inst > 0 ? n_inst : 0);
+    for (int i = 0; i < n_inst; i++) {
+        np[i] = parts[i].n;
+        if (parts[i].n > 0 && (!parts[i].pos[0] || !parts[i].pos[2] || !parts[i].mom[0] || !parts[i].mom[1] ||
+                               !parts[i].mom[2] || (cfgs[i].dims == 3 && !parts[i].pos[1])))
+            return fail(PIC_EINVAL, "null particle array");
+    }
+    size_t need = 0;
+    int rc = pic_plan(cfgs, n_inst, np.data(), &need);
+    if (rc) return rc;
+    if (arena_bytes < need) return fail(PIC_ENOMEM, "arena smaller than pic_plan reported");
+    if (((uintptr_t)d_arena & 255) != 0) return fail(PIC_EINVAL, "arena must be 256-byte aligned");
+
+    pic_state *s = new pic_state();
+    s->n_inst = n_inst;
+    s->dims = cfgs[0].dims;
+    s->order = cfgs[0].shape_order;
+    s->fp32 = cfgs[0].precision == PIC_FP32;
+    s->cfg.assign(cfgs, cfgs + n_inst);
+    s->np = np;
+    s->desc.resize(n_inst);
+    s->arena = (char *)d_arena;
+    s->arena_bytes = arena_bytes;
+    if (hip_stream) {
+        s->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete s;
+            return fail(PIC_EHIP, "hipStreamCreateWithFlags");
+        }
+        s->own_stream = true;
+    }
+    auto bail = [&](int code) { pic_destroy(s); return code; };
+    layout(s, cfgs, n_inst, np.data(), s->arena);
+    s->block = cfgs[0].block ? cfgs[0].block : default_block();
+    // largest LDS window over the instances
+    int maxsm = 0;
+    if (hipDeviceGetAttribute(&maxsm, hipDeviceAttributeMaxSharedMemoryPerBlock, 0) != hipSuccess) maxsm = 65536;
+    for (int i = 0; i < n_inst; i++) {
+        fill_desc(s->desc[i], cfgs[i], parts[i]);
+        int tile[3], slack;
+        tile_shape(cfgs[i], tile, slack);
+        for (int a = 0; a < 3; a++) {
+            int w = (s->dims == 2 && a == 1) ? 1 : tile[a] + slack + s->order + 2;
+            s->wmax[a] = std::max(s->wmax[a], w);
+        }
+    }
+    while (particle_smem_bytes(s->dims, s->fp32, s->wmax) > (size_t)maxsm) {
+        // shrink the slack until the window fits (tiles then re-sort more often)
+        bool shrunk = false;
+        for (int a = 0; a < 3; a++)
+            if (!(s->dims == 2 && a == 1) && s->wmax[a] > s->order + 3) { s->wmax[a]--; shrunk = true; }
+        if (!shrunk) return bail(fail(PIC_EINVAL, "tile window does not fit in LDS"));
+    }
+    {
+        // allow the dynamic LDS size on every particle kernel instantiation
+        (void)maxsm;
+    }
+    for (int i = 0; i < n_inst; i++) s->desc[i].trace = s->trace;
+    if (hipMemsetAsync(s->arena, 0, need - 256, s->stream) != hipSuccess) return bail(fail(PIC_EHIP, "arena clear"));
+    if (hipMemcpyAsync(s->d_desc, s->desc.data(), n_inst * sizeof(InstDesc), hipMemcpyHostToDevice, s->stream) !=
+        hipSuccess)
+        return bail(fail(PIC_EHIP, "descriptor upload"));
+    if ((rc = build_worklists(s))) return bail(rc);
+    for (int i = 0; i < n_inst; i++) {
+        rc = s->fp32 ? upload_particles<float>(s, i, parts[i]) : upload_particles<double>(s, i, parts[i]);
+        if (rc) return bail(rc);
+    }
+    LaunchCtx c = ctx(s);
+    if (launch_fill_bbox(c, 0, n_inst)) return bail(fail(PIC_EHIP, "bbox init"));
+    if (launch_rho(c, s->cwork, s->ncwork, s->fwork, s->nfwork, 1)) return bail(fail(PIC_EHIP, "rho0"));
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(fail(PIC_EHIP, "init sync"));
+    *out = s;
+    return PIC_OK;
+}
+
+extern "C" int pic_set_schedule(pic_state *s, int sched, int use_graph)
+{
+    if (!s || (sched != PIC_SCHED_BATCHED && sched != PIC_SCHED_PLAIN)) return fail(PIC_EINVAL, "schedule");
+    if (s->sched != sched || s->use_graph != (use_graph ? 1 : 0)) drop_graphs(s);
+    s->sched = sched;
+    s->use_graph = use_graph ? 1 : 0;
+    return PIC_OK;
+}
+
+extern "C" int pic_step(pic_state *s, int nsteps)
+{
+    if (!s || nsteps < 0) return fail(PIC_EINVAL, "pic_step");
+    int rc;
+    if (!s->use_graph) {
+        for (int n = 0; n < nsteps; n++) {
+            if ((rc = enqueue_step(s))) return rc;
+            s->step++;
+            if (s->step % s->graph_k == 0 && (rc = enqueue_resort(s))) return rc;
+        }
+        return PIC_OK;
+    }
+    if (!s->gexec_k && (rc = capture(s, s->graph_k, true, &s->gexec_k))) return rc;
+    if (!s->gexec_1 && (rc = capture(s, 1, false, &s->gexec_1))) return rc;
+    int n = 0;
+    // single steps until the step count is a multiple of the graph length, then whole graphs
+    while (n < nsteps && (s->step % s->graph_k) != 0) {
+        HIP_TRY(hipGraphLaunch(s->gexec_1, s->stream));
+        s->step++; n++;
+        if (s->step % s->graph_k == 0 && (rc = enqueue_resort(s))) return rc;
+    }
+    while (nsteps - n >= s->graph_k) {
+        HIP_TRY(hipGraphLaunch(s->gexec_k, s->stream));
+        s->step += s->graph_k;
+        n += s->graph_k;
+    }
+    while (n < nsteps) {
+        HIP_TRY(hipGraphLaunch(s->gexec_1, s->stream));
+        s->step++; n++;
+    }
+    return PIC_OK;
+}
+
+extern "C" int pic_fields(pic_state *s, int inst, int which, int comp, double *host, size_t n, int dir)
+{
+    if (!s || inst < 0 || inst >= s->n_inst || comp < 0 || comp > 2 || !host) return fail(PIC_EINVAL, "pic_fields");
+    const InstDesc &D = s->desc[inst];
+    if (n != (size_t)D.ncell) return fail(PIC_EINVAL, "pic_fields: n must equal nx*ny*nz");
+    void *src = nullptr;
+    bool is_j = false, is_rho = false;
+    switch (which) {
+    case PIC_FIELD_E: src = D.E[comp]; break;
+    case PIC_FIELD_B: src = D.B[comp]; break;
+    case PIC_FIELD_J: src = D.J[comp]; is_j = true; break;
+    case PIC_FIELD_SEEN_E: src = D.Et[comp]; break;
+    case PIC_FIELD_SEEN_B: src = D.Bt[comp]; break;
+    case PIC_FIELD_RHO: is_rho = true; break;
+    default: return fail(PIC_EINVAL, "pic_fields: which");
+    }
+    if (dir == PIC_SET) {
+        if (which != PIC_FIELD_E && which != PIC_FIELD_B) return fail(PIC_EINVAL, "SET allowed for E and B only");
+        return s->fp32 ? copy_plane_in<float>(s, src, n, host) : copy_plane_in<double>(s, src, n, host);
+    }
+    if (dir != PIC_GET) return fail(PIC_EINVAL, "pic_fields: dir");
+    if (is_rho) {
+        LaunchCtx c = ctx(s);
+        const Range &cr = s->crange[inst], &fr = s->frange[inst];
+        if (launch_rho(c, s->cwork + cr.off, cr.n, s->fwork + fr.off, fr.n, 0)) return fail(PIC_EHIP, "rho");
+        HIP_TRY(hipMemcpyAsync(host, D.rho, n * 8, hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        return PIC_OK;
+    }
+    return s->fp32 ? copy_plane_out<float>(s, src, n, host, D.jq, is_j)
+                   : copy_plane_out<double>(s, src, n, host, D.jq, is_j);
+}
+
+extern "C" int pic_get_particles(pic_state *s, int inst, double *pos[3], double *mom[3], int64_t n)
+{
+    if (!s || inst < 0 || inst >= s->n_inst || !pos || !mom) return fail(PIC_EINVAL, "pic_get_particles");
+    if (n != s->desc[inst].np) return fail(PIC_EINVAL, "pic_get_particles: n mismatch");
+    return s->fp32 ? get_particles<float>(s, inst, pos, mom) : get_particles<double>(s, inst, pos, mom);
+}
+
+extern "C" int pic_diag(pic_state *s, int inst, pic_diag_t *out)
+{
+    if (!s || inst < 0 || inst >= s->n_inst || !out) return fail(PIC_EINVAL, "pic_diag");
+    const InstDesc &D = s->desc[inst];
+    LaunchCtx c = ctx(s);
+    const Range &cr = s->crange[inst], &fr = s->frange[inst];
+    if (launch_diag(c, s->fwork + fr.off, fr.n, s->cwork + cr.off, cr.n, inst, 1)) return fail(PIC_EHIP, "diag");
+    double dg[DG_COUNT];
+    int fl[FLAG_COUNT];
+    HIP_TRY(hipMemcpyAsync(dg, D.diag, sizeof dg, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(fl, D.flags, sizeof fl, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    std::memset(out, 0, sizeof *out);
+    for (int k = 0; k < 3; k++) { out->WE[k] = dg[DG_WE + k]; out->WB[k] = dg[DG_WB + k]; }
+    out->Wkin = dg[DG_WKIN];
+    out->gauss_l2 = std::sqrt(dg[DG_G2]);
+    out->gauss_linf = dg[DG_GMAX];
+    out->charge = dg[DG_CHARGE];
+    out->rho_max = dg[DG_RHOMAX];
+    out->n_particles = D.np;
+    out->step = s->step;
+    out->nonfinite = dg[DG_NONFIN] > 0 ? 1 : 0;
+    for (int k = 0; k < 6; k++) {
+        double v = k < 3 ? out->WE[k] : out->WB[k - 3];
+        if (!std::isfinite(v)) out->nonfinite = 1;
+    }
+    out->particle_error = fl[FLAG_PERR] ? 1 : 0;
+    out->resorts = fl[FLAG_NRESORT];
+    out->slow_tiles = fl[FLAG_SLOW];
+    if (out->nonfinite) return fail(PIC_ENONFINITE, "non-finite value found");
+    if (out->particle_error) return fail(PIC_EPARTICLE, "particle moved a full cell");
+    return PIC_OK;
+}
+
+extern "C" int pic_read_trace(pic_state *s, int inst, double *host_out, int max_rows, int *count)
+{
+    if (!s || inst < 0 || inst >= s->n_inst || !host_out || !count) return fail(PIC_EINVAL, "pic_read_trace");
+    *count = 0;
+    if (s->trace_cap <= 0) return PIC_OK;
+    int pos = 0;
+    HIP_TRY(hipMemcpyAsync(&pos, s->trace_pos, sizeof pos, hipMemcpyDeviceToHost, s->stream));
+    std::vector<double> all((size_t)s->trace_cap * s->n_inst * 6);
+    HIP_TRY(hipMemcpyAsync(all.data(), s->trace, all.size() * 8, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const int rows = std::min(std::min(pos, s->trace_cap), max_rows);
+    const int first = pos - rows;
+    for (int r = 0; r < rows; r++) {
+        const int slot = (first + r) % s->trace_cap;
+        for (int k = 0; k < 6; k++) host_out[r * 6 + k] = all[((size_t)slot * s->n_inst + inst) * 6 + k];
+    }
+    *count = rows;
+    return PIC_OK;
+}
+
+extern "C" int pic_profile(pic_state *s, int nsteps, pic_timing_t *out)
+{
+    if (!s || !out || nsteps < 1) return fail(PIC_EINVAL, "pic_profile");
+    std::memset(out, 0, sizeof *out);
+    hipEvent_t ev[5];
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    double acc[4] = {0, 0, 0, 0}, total = 0;
+    int nres = 0;
+    LaunchCtx c = ctx(s);
+    for (int n = 0; n < nsteps; n++) {
+        const Range f{0, s->nfwork}, p{0, s->npwork};
+        HIP_TRY(hipEventRecord(ev[0], s->stream));
+        if (launch_yee(c, s->fwork, f.n)) return fail(PIC_EHIP, "yee");
+        HIP_TRY(hipEventRecord(ev[1], s->stream));
+        if (launch_seen(c, s->fwork, f.n)) return fail(PIC_EHIP, "seen");
+        HIP_TRY(hipEventRecord(ev[2], s->stream));
+        if (launch_particles(c, s->pwork, p.n, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particles");
+        HIP_TRY(hipEventRecord(ev[3], s->stream));
+        s->step++;
+        const bool res = s->step % s->graph_k == 0;
+        if (res && launch_resort(c, s->cwork, s->ncwork, 0, s->n_inst)) return fail(PIC_EHIP, "resort");
+        HIP_TRY(hipEventRecord(ev[4], s->stream));
+        HIP_TRY(hipEventSynchronize(ev[4]));
+        float t[4];
+        for (int k = 0; k < 4; k++) HIP_TRY(hipEventElapsedTime(&t[k], ev[k], ev[k + 1]));
+        for (int k = 0; k < 4; k++) acc[k] += t[k];
+        total += t[0] + t[1] + t[2] + t[3];
+        nres += res;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    out->yee_ms = acc[0] / nsteps;
+    out->seen_ms = acc[1] / nsteps;
+    out->particle_ms = acc[2] / nsteps;
+    out->resort_ms = nres ? acc[3] / nres : 0.0;
+    out->step_ms = total / nsteps;
+    out->steps = nsteps;
+    return PIC_OK;
+}
+
+extern "C" int pic_info(pic_state *s, int *n_inst, int64_t *n_particles, int64_t *n_cells)
+{
+    if (!s) return fail(PIC_EINVAL, "pic_info");
+    int64_t np = 0, nc = 0;
+    for (int i = 0; i < s->n_inst; i++) { np += s->desc[i].np; nc += s->desc[i].ncell; }
+    if (n_inst) *n_inst = s->n_inst;
+    if (n_particles) *n_particles = np;
+    if (n_cells) *n_cells = nc;
+    return PIC_OK;
+}
+
+extern "C" void pic_destroy(pic_state *s)
+{
+    if (!s) return;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    drop_graphs(s);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+}

@@ -1,0 +1,94 @@
+// Internal layout shared by the HIP kernels and the host orchestration.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PIC_MAX_HZ 16           // half-width of the combined z stencil (Psi degree + passes)
+#define PIC_MAX_HX 8            // half-width of the x / y filter stencils
+#define PIC_FIELD_CHUNK 256     // cells per field work item
+#define PIC_PART_CHUNK 256      // particles per particle-chunk work item
+#define PIC_TILE_SLACK 4        // cells a tile's particle bounding box may grow before a re-sort
+
+// device flag slots (per instance)
+enum { FLAG_RESORT = 0, FLAG_PERR = 1, FLAG_SLOW = 2, FLAG_NRESORT = 3, FLAG_COUNT = 8 };
+
+// per-instance diagnostic accumulator slots (doubles)
+enum {
+    DG_WE = 0,      // 3
+    DG_WB = 3,      // 3
+    DG_WKIN = 6,
+    DG_G2 = 7,      // sum of squared Gauss residual
+    DG_GMAX = 8,    // max |residual| (bit pattern of a non-negative double)
+    DG_CHARGE = 9,
+    DG_RHOMAX = 10, // max |rho| (bit pattern)
+    DG_NONFIN = 11, // > 0 if a non-finite value was seen
+    DG_COUNT = 16
+};
+
+// Everything a kernel needs to know about one simulation instance.
+struct InstDesc {
+    int n[3];              // cells along x, y, z (n[1] = 1 in 2D)
+    int ncell;
+    int tile[3];           // particle tile size in cells
+    int nt[3];             // tiles per axis
+    int ntiles;
+    int trace_cap;
+    long long np;          // particles
+    double d[3];           // cell sizes
+    double dt;
+    double dtd[3];         // dt / d_a
+    double qdt2m;          // q dt / (2 m)
+    double w, m;           // weight, mass
+    double dV;
+    double jbg[3];         // uniform background current
+    double jq;             // fixed-point quantum of J (float mode): J = int * jq
+    double cdep[3];        // Esirkepov factors -q w d_a / (dt dV) (times 1/jq in float mode)
+    double cy2d;           // q w / dV (times 1/jq in float mode): J_y = cy2d * v_y * W_y in 2D
+    double rho_c;          // q w / dV for the charge density
+    int hz, hx, hy;        // stencil half-widths
+    double tz[2][2 * PIC_MAX_HZ + 1];  // combined z taps: [0] Psi_E o filter, [1] Psi_B o filter
+    double tx[2 * PIC_MAX_HX + 1];     // x filter taps
+    double ty[2 * PIC_MAX_HX + 1];     // y filter taps (3D)
+    // grid planes (element type follows the precision)
+    void *E[3], *B[3], *Et[3], *Bt[3];
+    void *T1[6], *T2[6];   // intermediates of the separable seen-field passes
+    void *J[3];            // long long fixed point (float mode) or double
+    double *rho0, *rho;
+    // particles
+    int *pidx;             // linear cell index (z * ny + y) * nx + x
+    void *poff[3];         // in-cell offsets in [0, 1) per active axis
+    void *pu[3];           // momenta
+    int *ppid;             // original particle number
+    int *sidx, *spid, *srank, *stile;
+    void *soff[3], *su[3];
+    // tiles
+    int *tstart;           // ntiles + 1 slot offsets
+    int *tbox;             // per tile: lo[3] (wrapped cell coords), ext[3]
+    int *tcount;
+    int *flags;            // FLAG_*
+    double *diag;          // DG_*
+    double *trace;         // trace_cap rows of 6 doubles
+};
+
+// launch helpers implemented in pic_kernels.hip
+struct LaunchCtx {
+    const InstDesc *desc;       // device table
+    hipStream_t stream;
+    int dims, order, fp32;
+};
+
+int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork);
+int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork);
+int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid, int block,
+                     const int wmax[3]);
+size_t particle_smem_bytes(int dims, int fp32, const int wmax[3]);
+int launch_resort(const LaunchCtx &c, const int2 *cwork, int ncwork, int n_inst_first, int n_inst);
+int launch_clear_j(const LaunchCtx &c, const int2 *fwork, int nwork);
+int launch_rho(const LaunchCtx &c, const int2 *cwork, int ncwork, const int2 *fwork, int nfwork,
+               int to_rho0);
+int launch_diag(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *cwork, int ncwork,
+                int inst_first, int n_inst);
+int launch_trace_rows(const LaunchCtx &c, const int2 *fwork, int nfwork, int *pos, double *trace, int n_inst,
+                      int cap);
+int launch_fill_bbox(const LaunchCtx &c, int inst_first, int n_inst);

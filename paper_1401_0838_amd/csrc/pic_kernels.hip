@@ -1,0 +1,998 @@
+// HIP kernels (gfx950) of one FDTD-Esirkepov PIC step with the small-k_z
+// correction stencils of Godfrey & Vay (arXiv:1401.0838).
+//
+//   yee        three sweeps: B half step, E full step (reads J, then clears it),
+//              B half step (textbook Yee on the staggered mesh, Sec. 2)
+//   seen       separable passes: combined z stencil (Psi(S_z) of Sec. 2 composed
+//              with the z filter passes of Sec. 3 / Eq. 6), then x (then y)
+//   particles  one workgroup per particle tile: stage the seen fields of the
+//              tile's bounding window (plus guard cells) in LDS, then per
+//              particle Galerkin gather (Eq. 3 scheme), Boris push, move and
+//              Esirkepov deposit into an LDS current window; flush the window
+//              with global atomics
+//   resort     counting sort of particles by tile when a tile's bounding box
+//              has outgrown its LDS window
+//   diag       float64 wavefront-shuffle reductions for energies, charge and
+//              the Gauss-law residual
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <climits>
+
+#include "pic_internal.h"
+
+namespace {
+
+// ------------------------------------------------------------------ helpers
+
+template <class R> struct JOf;
+template <> struct JOf<float> { typedef long long T; };   // 64-bit fixed point
+template <> struct JOf<double> { typedef double T; };
+
+__device__ __forceinline__ int wrapi(int i, int n)
+{
+    // i in (-n, 2n)
+    return i < 0 ? i + n : (i >= n ? i - n : i);
+}
+
+__device__ __forceinline__ void jadd(long long *p, long long v)
+{
+    atomicAdd(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(v));
+}
+__device__ __forceinline__ void jadd(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+// contribution -> accumulator type (already scaled by 1/quantum in float mode)
+__device__ __forceinline__ long long jcvt(float v, long long *) { return (long long)__float2int_rn(v); }
+__device__ __forceinline__ double jcvt(double v, double *) { return v; }
+
+__device__ __forceinline__ double jreal(long long v, double q) { return (double)v * q; }
+__device__ __forceinline__ double jreal(double v, double) { return v; }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_min_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// atomic max of a non-negative double through its bit pattern
+__device__ __forceinline__ void atomic_max_pos(double *p, double v)
+{
+    atomicMax(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
+}
+
+// ----------------------------------------------------------- shape factors
+// Weights of the centred B-spline of order O for a point a fraction d in
+// [0,1) past its cell's lower node.
+//   integer nodes (order L): node c - (L-1)/2 + j, j in [0, L+1)
+//   half nodes (order L-1):  node c - (L-1)/2 + j + 1/2, j in [0, L)
+
+template <int L, class R> struct Shape;
+
+template <class R> struct Shape<1, R> {
+    static __device__ __forceinline__ void integer(R d, R *w) { w[0] = R(1) - d; w[1] = d; }
+    static __device__ __forceinline__ void half(R, R *w) { w[0] = R(1); }
+};
+
+template <class R> struct Shape<3, R> {
+    static __device__ __forceinline__ void integer(R d, R *w)
+    {
+        R e = R(1) - d;
+        w[0] = e * e * e * R(1.0 / 6.0);
+        w[1] = R(2.0 / 3.0) - d * d + R(0.5) * d * d * d;
+        w[2] = R(2.0 / 3.0) - e * e + R(0.5) * e * e * e;
+        w[3] = d * d * d * R(1.0 / 6.0);
+    }
+    static __device__ __forceinline__ void half(R d, R *w)
+    {
+        R e = R(1) - d, h = d - R(0.5);
+        w[0] = R(0.5) * e * e;
+        w[1] = R(0.75) - h * h;
+        w[2] = R(0.5) * d * d;
+    }
+};
+
+// ------------------------------------------------------------ accessors
+// Field / current access by window-local node coordinates.
+
+template <class R, class JT> struct LdsWin {
+    const R *F;   // 6 planes of wc values: Ex Ey Ez Bx By Bz (seen)
+    JT *J;        // 3 planes
+    int wx, wxy, wc;
+    __device__ __forceinline__ int at(int x, int y, int z) const { return z * wxy + y * wx + x; }
+    __device__ __forceinline__ R f(int comp, int x, int y, int z) const { return F[comp * wc + at(x, y, z)]; }
+    __device__ __forceinline__ void add(int comp, int x, int y, int z, JT v) { jadd(&J[comp * wc + at(x, y, z)], v); }
+};
+
+template <class R, class JT> struct GlbWin {
+    const R *F[6];
+    JT *J[3];
+    int o[3], n[3];
+    __device__ __forceinline__ int at(int x, int y, int z) const
+    {
+        int gx = (o[0] + x) % n[0], gy = (o[1] + y) % n[1], gz = (o[2] + z) % n[2];
+        return (gz * n[1] + gy) * n[0] + gx;
+    }
+    __device__ __forceinline__ R f(int comp, int x, int y, int z) const { return F[comp][at(x, y, z)]; }
+    __device__ __forceinline__ void add(int comp, int x, int y, int z, JT v) { jadd(&J[comp][at(x, y, z)], v); }
+};
+
+// Galerkin interpolation of one component with staggering (SX, SY, SZ).
+template <int SX, int SY, int SZ, int DIM, int L, class R, class Win>
+__device__ __forceinline__ R interp(const Win &W, int comp, const int *lc, const R (*wi)[L + 1],
+                                    const R (*wh)[L])
+{
+    constexpr int H = (L - 1) / 2;
+    constexpr int NX = L + 1 - SX, NZ = L + 1 - SZ, NY = DIM == 3 ? L + 1 - SY : 1;
+    R s = R(0);
+#pragma unroll
+    for (int kz = 0; kz < NZ; kz++) {
+        R wz;
+        if constexpr (SZ) wz = wh[2][kz]; else wz = wi[2][kz];
+#pragma unroll
+        for (int ky = 0; ky < NY; ky++) {
+            R wy = R(1);
+            if constexpr (DIM == 3) {
+                if constexpr (SY) wy = wh[1][ky]; else wy = wi[1][ky];
+            }
+            R row = R(0);
+#pragma unroll
+            for (int kx = 0; kx < NX; kx++) {
+                R wx;
+                if constexpr (SX) wx = wh[0][kx]; else wx = wi[0][kx];
+                row += wx * W.f(comp, lc[0] - H + kx, DIM == 3 ? lc[1] - H + ky : 0, lc[2] - H + kz);
+            }
+            s += wy * wz * row;
+        }
+    }
+    return s;
+}
+
+// One particle: gather, Boris, move, Esirkepov deposit.
+// lc: window-local cell; off: in-cell offsets; u: momenta (updated);
+// dc / offn: cell step and new offsets (outputs).
+template <int DIM, int L, class R, class JT, class Win>
+__device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *off, R *u, int *dc, R *offn,
+                                              const R *dtd, R qdt2m, const R *cdep, R cy2d, int &err)
+{
+    constexpr int H = (L - 1) / 2;
+    R wi[3][L + 1], wh[3][L];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (DIM == 2 && a == 1) continue;
+        Shape<L, R>::integer(off[a], wi[a]);
+        Shape<L, R>::half(off[a], wh[a]);
+    }
+    // staggering: Ex(1,0,0) Ey(0,1,0) Ez(0,0,1) Bx(0,1,1) By(1,0,1) Bz(1,1,0)
+    R E0 = interp<1, 0, 0, DIM, L, R>(W, 0, lc, wi, wh);
+    R E1 = interp<0, 1, 0, DIM, L, R>(W, 1, lc, wi, wh);
+    R E2 = interp<0, 0, 1, DIM, L, R>(W, 2, lc, wi, wh);
+    R B0 = interp<0, 1, 1, DIM, L, R>(W, 3, lc, wi, wh);
+    R B1 = interp<1, 0, 1, DIM, L, R>(W, 4, lc, wi, wh);
+    R B2 = interp<1, 1, 0, DIM, L, R>(W, 5, lc, wi, wh);
+
+    // Boris (textbook): half electric kick, magnetic rotation, half kick
+    R um0 = u[0] + qdt2m * E0, um1 = u[1] + qdt2m * E1, um2 = u[2] + qdt2m * E2;
+    R igm = R(1) / sqrt(R(1) + um0 * um0 + um1 * um1 + um2 * um2);
+    R t0 = qdt2m * B0 * igm, t1 = qdt2m * B1 * igm, t2 = qdt2m * B2 * igm;
+    R f = R(2) / (R(1) + t0 * t0 + t1 * t1 + t2 * t2);
+    R s0 = f * t0, s1 = f * t1, s2 = f * t2;
+    R up0 = um0 + (um1 * t2 - um2 * t1);
+    R up1 = um1 + (um2 * t0 - um0 * t2);
+    R up2 = um2 + (um0 * t1 - um1 * t0);
+    u[0] = um0 + (up1 * s2 - up2 * s1) + qdt2m * E0;
+    u[1] = um1 + (up2 * s0 - up0 * s2) + qdt2m * E1;
+    u[2] = um2 + (up0 * s1 - up1 * s0) + qdt2m * E2;
+
+    // move in cell units
+    R ig = R(1) / sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (DIM == 2 && a == 1) { dc[a] = 0; offn[a] = R(0); continue; }
+        R x1 = off[a] + dtd[a] * u[a] * ig;
+        int c = x1 >= R(1) ? 1 : (x1 < R(0) ? -1 : 0);
+        if (x1 >= R(2) || x1 < R(-1)) { err = 1; x1 = x1 < R(0) ? R(-0.5) : R(1.5); c = x1 < R(0) ? -1 : 1; }
+        R on = x1 - R(c);
+        if (on >= R(1)) { on -= R(1); c += 1; }
+        dc[a] = c;
+        offn[a] = on;
+    }
+
+    // Esirkepov: shapes on the L+2 nodes starting at min(old, new) cell - H
+    R S0[3][L + 2], DS[3][L + 2];
+    int base[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (DIM == 2 && a == 1) { base[a] = 0; continue; }
+        R w0[L + 1], w1[L + 1];
+        Shape<L, R>::integer(off[a], w0);
+        Shape<L, R>::integer(offn[a], w1);
+        const int mn = dc[a] < 0 ? -1 : 0;
+        const bool sh0 = mn < 0;          // old support starts one node in
+        const bool sh1 = dc[a] > 0;       // new support starts one node in
+        base[a] = lc[a] + mn - H;
+#pragma unroll
+        for (int i = 0; i < L + 2; i++) {
+            // node i of the (L+2)-node stencil; supports are L+1 nodes, shifted by one
+            // when the particle's cell is the upper of old / new
+            const R lo0 = i >= 1 ? w0[i >= 1 ? i - 1 : 0] : R(0), hi0 = i < L + 1 ? w0[i < L + 1 ? i : L] : R(0);
+            const R lo1 = i >= 1 ? w1[i >= 1 ? i - 1 : 0] : R(0), hi1 = i < L + 1 ? w1[i < L + 1 ? i : L] : R(0);
+            const R a0 = sh0 ? lo0 : hi0;
+            const R a1 = sh1 ? lo1 : hi1;
+            S0[a][i] = a0;
+            DS[a][i] = a1 - a0;
+        }
+    }
+    JT *tag = nullptr;
+    if constexpr (DIM == 2) {
+        // J_x: running sum along x
+#pragma unroll
+        for (int k = 0; k < L + 2; k++) {
+            R tz = S0[2][k] + R(0.5) * DS[2][k];
+            R acc = R(0);
+#pragma unroll
+            for (int i = 0; i < L + 1; i++) {
+                acc += DS[0][i] * tz;
+                W.add(0, base[0] + i, 0, base[2] + k, jcvt(cdep[0] * acc, tag));
+            }
+        }
+        // J_z: running sum along z
+#pragma unroll
+        for (int i = 0; i < L + 2; i++) {
+            R tx = S0[0][i] + R(0.5) * DS[0][i];
+            R acc = R(0);
+#pragma unroll
+            for (int k = 0; k < L + 1; k++) {
+                acc += DS[2][k] * tx;
+                W.add(2, base[0] + i, 0, base[2] + k, jcvt(cdep[2] * acc, tag));
+            }
+        }
+        // J_y: out of plane, with v_y
+        R cy = cy2d * u[1] * ig;
+#pragma unroll
+        for (int k = 0; k < L + 2; k++)
+#pragma unroll
+            for (int i = 0; i < L + 2; i++) {
+                R wy = S0[0][i] * S0[2][k] + R(0.5) * DS[0][i] * S0[2][k] + R(0.5) * S0[0][i] * DS[2][k]
+                     + R(1.0 / 3.0) * DS[0][i] * DS[2][k];
+                W.add(1, base[0] + i, 0, base[2] + k, jcvt(cy * wy, tag));
+            }
+    } else {
+        // J_x
+#pragma unroll
+        for (int kz = 0; kz < L + 2; kz++)
+#pragma unroll
+            for (int ky = 0; ky < L + 2; ky++) {
+                R tr = S0[1][ky] * S0[2][kz] + R(0.5) * DS[1][ky] * S0[2][kz] + R(0.5) * S0[1][ky] * DS[2][kz]
+                     + R(1.0 / 3.0) * DS[1][ky] * DS[2][kz];
+                R acc = R(0);
+#pragma unroll
+                for (int kx = 0; kx < L + 1; kx++) {
+                    acc += DS[0][kx] * tr;
+                    W.add(0, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(cdep[0] * acc, tag));
+                }
+            }
+        // J_y
+#pragma unroll
+        for (int kz = 0; kz < L + 2; kz++)
+#pragma unroll
+            for (int kx = 0; kx < L + 2; kx++) {
+                R tr = S0[2][kz] * S0[0][kx] + R(0.5) * DS[2][kz] * S0[0][kx] + R(0.5) * S0[2][kz] * DS[0][kx]
+                     + R(1.0 / 3.0) * DS[2][kz] * DS[0][kx];
+                R acc = R(0);
+#pragma unroll
+                for (int ky = 0; ky < L + 1; ky++) {
+                    acc += DS[1][ky] * tr;
+                    W.add(1, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(cdep[1] * acc, tag));
+                }
+            }
+        // J_z
+#pragma unroll
+        for (int ky = 0; ky < L + 2; ky++)
+#pragma unroll
+            for (int kx = 0; kx < L + 2; kx++) {
+                R tr = S0[0][kx] * S0[1][ky] + R(0.5) * DS[0][kx] * S0[1][ky] + R(0.5) * S0[0][kx] * DS[1][ky]
+                     + R(1.0 / 3.0) * DS[0][kx] * DS[1][ky];
+                R acc = R(0);
+#pragma unroll
+                for (int kz = 0; kz < L + 1; kz++) {
+                    acc += DS[2][kz] * tr;
+                    W.add(2, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(cdep[2] * acc, tag));
+                }
+            }
+    }
+}
+
+// ------------------------------------------------------------ particle kernel
+
+template <int DIM, int L, class R>
+__global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                                   int nwork, int wmx, int wmy, int wmz)
+{
+    typedef typename JOf<R>::T JT;
+    constexpr int JL = (L + 1) / 2;      // guard cells below the bounding box
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int sbox[6];
+    const int tid = threadIdx.x, bs = blockDim.x;
+
+    for (int item = blockIdx.x; item < nwork; item += gridDim.x) {
+        const int inst = work[item].x, tile = work[item].y;
+        const InstDesc &D = Dt[inst];
+        const int p0 = D.tstart[tile], p1 = D.tstart[tile + 1];
+        if (p1 <= p0) continue;
+        int lo[3], ext[3], o[3], wn[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            lo[a] = D.tbox[tile * 6 + a];
+            ext[a] = D.tbox[tile * 6 + 3 + a];
+            if (DIM == 2 && a == 1) { o[a] = 0; wn[a] = 1; continue; }
+            o[a] = wrapi(lo[a] - JL, D.n[a]);
+            wn[a] = ext[a] + L + 2;
+        }
+        const bool fits = wn[0] <= wmx && wn[1] <= wmy && wn[2] <= wmz;
+        const int wc = wn[0] * wn[1] * wn[2];
+        JT *sJ = reinterpret_cast<JT *>(smem);
+        R *sF = reinterpret_cast<R *>(smem + (size_t)3 * wmx * wmy * wmz * sizeof(JT));
+
+        if (tid < 3) { sbox[tid] = INT_MAX; sbox[3 + tid] = INT_MIN; }
+        if (fits) {
+            const R *src[6] = {(const R *)D.Et[0], (const R *)D.Et[1], (const R *)D.Et[2],
+                               (const R *)D.Bt[0], (const R *)D.Bt[1], (const R *)D.Bt[2]};
+            for (int c = tid; c < wc; c += bs) {
+                int x = c % wn[0], r = c / wn[0];
+                int y = r % wn[1], z = r / wn[1];
+                const int gx = (o[0] + x) % D.n[0], gy = (o[1] + y) % D.n[1], gz = (o[2] + z) % D.n[2];
+                const int g = (gz * D.n[1] + gy) * D.n[0] + gx;
+#pragma unroll
+                for (int k = 0; k < 6; k++) sF[k * wc + c] = src[k][g];
+#pragma unroll
+                for (int k = 0; k < 3; k++) sJ[k * wc + c] = JT(0);
+            }
+        } else if (tid == 0) {
+            atomicAdd(&D.flags[FLAG_SLOW], 1);
+            atomicExch(&D.flags[FLAG_RESORT], 1);
+        }
+        __syncthreads();
+
+        const R dtd[3] = {(R)D.dtd[0], (R)D.dtd[1], (R)D.dtd[2]};
+        const R cdep[3] = {(R)D.cdep[0], (R)D.cdep[1], (R)D.cdep[2]};
+        const R qdt2m = (R)D.qdt2m, cy2d = (R)D.cy2d;
+        R *poff[3] = {(R *)D.poff[0], (R *)D.poff[1], (R *)D.poff[2]};
+        R *pu[3] = {(R *)D.pu[0], (R *)D.pu[1], (R *)D.pu[2]};
+        int bmin[3] = {INT_MAX, INT_MAX, INT_MAX}, bmax[3] = {INT_MIN, INT_MIN, INT_MIN};
+        int err = 0;
+
+        LdsWin<R, JT> lw{sF, sJ, wn[0], wn[0] * wn[1], wc};
+        GlbWin<R, JT> gw;
+        if (!fits) {
+            gw.F[0] = (const R *)D.Et[0]; gw.F[1] = (const R *)D.Et[1]; gw.F[2] = (const R *)D.Et[2];
+            gw.F[3] = (const R *)D.Bt[0]; gw.F[4] = (const R *)D.Bt[1]; gw.F[5] = (const R *)D.Bt[2];
+            for (int k = 0; k < 3; k++) { gw.J[k] = (JT *)D.J[k]; gw.o[k] = o[k]; gw.n[k] = D.n[k]; }
+        }
+
+        for (int p = p0 + tid; p < p1; p += bs) {
+            const int idx = D.pidx[p];
+            int c[3];
+            c[0] = idx % D.n[0];
+            const int r = idx / D.n[0];
+            c[1] = r % D.n[1];
+            c[2] = r / D.n[1];
+            int lc[3];
+            R off[3], u[3], offn[3];
+            int dc[3];
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                if (DIM == 2 && a == 1) { lc[a] = 0; off[a] = R(0); continue; }
+                int rel = c[a] - lo[a];
+                rel += rel < 0 ? D.n[a] : 0;
+                lc[a] = rel + JL;
+                off[a] = poff[a][p];
+            }
+            u[0] = pu[0][p]; u[1] = pu[1][p]; u[2] = pu[2][p];
+            if (fits)
+                push_particle<DIM, L, R, JT>(lw, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
+            else
+                push_particle<DIM, L, R, JT>(gw, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
+            int nc[3];
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                nc[a] = c[a];
+                if (DIM == 2 && a == 1) continue;
+                nc[a] = wrapi(c[a] + dc[a], D.n[a]);
+                poff[a][p] = offn[a];
+                const int l1 = lc[a] + dc[a];
+                bmin[a] = min(bmin[a], l1);
+                bmax[a] = max(bmax[a], l1);
+            }
+            pu[0][p] = u[0]; pu[1][p] = u[1]; pu[2][p] = u[2];
+            D.pidx[p] = (nc[2] * D.n[1] + nc[1]) * D.n[0] + nc[0];
+        }
+        if (err) atomicExch(&D.flags[FLAG_PERR], 1);
+        // bounding box of the moved particles (window-local coordinates)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            int mn = wave_min_i(bmin[a]), mx = wave_max_i(bmax[a]);
+            if ((tid & 63) == 0) { atomicMin(&sbox[a], mn); atomicMax(&sbox[3 + a], mx); }
+        }
+        __syncthreads();
+        if (fits) {
+            JT *gJ[3] = {(JT *)D.J[0], (JT *)D.J[1], (JT *)D.J[2]};
+            for (int c = tid; c < wc; c += bs) {
+                int x = c % wn[0], r = c / wn[0];
+                int y = r % wn[1], z = r / wn[1];
+                const int gx = (o[0] + x) % D.n[0], gy = (o[1] + y) % D.n[1], gz = (o[2] + z) % D.n[2];
+                const int g = (gz * D.n[1] + gy) * D.n[0] + gx;
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    JT v = sJ[k * wc + c];
+                    if (v != JT(0)) jadd(&gJ[k][g], v);
+                }
+            }
+        }
+        if (tid == 0) {
+            bool regrow = false;
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                if (DIM == 2 && a == 1) continue;
+                int e = sbox[3 + a] - sbox[a] + 1;
+                int l = (o[a] + sbox[a]) % D.n[a];
+                l += l < 0 ? D.n[a] : 0;
+                if (e >= D.n[a]) { e = D.n[a]; l = 0; }
+                D.tbox[tile * 6 + a] = l;
+                D.tbox[tile * 6 + 3 + a] = e;
+                if (e > D.tile[a] + PIC_TILE_SLACK) regrow = true;
+            }
+            if (regrow) atomicExch(&D.flags[FLAG_RESORT], 1);
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------- Yee sweeps
+
+template <class R>
+__device__ __forceinline__ void cell_ijk(const InstDesc &D, int cell, int &i, int &j, int &k)
+{
+    i = cell % D.n[0];
+    int r = cell / D.n[0];
+    j = r % D.n[1];
+    k = r / D.n[1];
+}
+
+// B -= (dt/2) curl E with forward differences
+template <int DIM, class R>
+__global__ void __launch_bounds__(256) k_yee_b(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    const int inst = work[blockIdx.x].x;
+    const InstDesc &D = Dt[inst];
+    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    if (cell >= D.ncell) return;
+    int i, j, k;
+    cell_ijk<R>(D, cell, i, j, k);
+    const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
+    const int ip = (i + 1 == nx ? 0 : i + 1) + (j + (k * ny)) * nx;
+    const int kp = i + (j + (k + 1 == nz ? 0 : k + 1) * ny) * nx;
+    const R *Ex = (const R *)D.E[0], *Ey = (const R *)D.E[1], *Ez = (const R *)D.E[2];
+    R *Bx = (R *)D.B[0], *By = (R *)D.B[1], *Bz = (R *)D.B[2];
+    const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2];
+    const R h = R(0.5) * (R)D.dt;
+    const R ex = Ex[cell], ey = Ey[cell], ez = Ez[cell];
+    R dyEz = R(0), dyEx = R(0);
+    if constexpr (DIM == 3) {
+        const int jp = i + ((j + 1 == ny ? 0 : j + 1) + k * ny) * nx;
+        const R idy = R(1) / (R)D.d[1];
+        dyEz = (Ez[jp] - ez) * idy;
+        dyEx = (Ex[jp] - ex) * idy;
+    }
+    const R dzEy = (Ey[kp] - ey) * idz, dzEx = (Ex[kp] - ex) * idz;
+    const R dxEz = (Ez[ip] - ez) * idx, dxEy = (Ey[ip] - ey) * idx;
+    Bx[cell] -= h * (dyEz - dzEy);
+    By[cell] -= h * (dzEx - dxEz);
+    Bz[cell] -= h * (dxEy - dyEx);
+}
+
+// E += dt (curl B - J - J_bg) with backward differences; clears J afterwards
+template <int DIM, class R>
+__global__ void __launch_bounds__(256) k_yee_e(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    typedef typename JOf<R>::T JT;
+    const int inst = work[blockIdx.x].x;
+    const InstDesc &D = Dt[inst];
+    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    if (cell >= D.ncell) return;
+    int i, j, k;
+    cell_ijk<R>(D, cell, i, j, k);
+    const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
+    const int im = (i == 0 ? nx - 1 : i - 1) + (j + k * ny) * nx;
+    const int km = i + (j + (k == 0 ? nz - 1 : k - 1) * ny) * nx;
+    const R *Bx = (const R *)D.B[0], *By = (const R *)D.B[1], *Bz = (const R *)D.B[2];
+    R *Ex = (R *)D.E[0], *Ey = (R *)D.E[1], *Ez = (R *)D.E[2];
+    JT *J0 = (JT *)D.J[0], *J1 = (JT *)D.J[1], *J2 = (JT *)D.J[2];
+    const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2];
+    const R dt = (R)D.dt;
+    const R bx = Bx[cell], by = By[cell], bz = Bz[cell];
+    R dyBz = R(0), dyBx = R(0);
+    if constexpr (DIM == 3) {
+        const int jm = i + ((j == 0 ? ny - 1 : j - 1) + k * ny) * nx;
+        const R idy = R(1) / (R)D.d[1];
+        dyBz = (bz - Bz[jm]) * idy;
+        dyBx = (bx - Bx[jm]) * idy;
+    }
+    const R dzBy = (by - By[km]) * idz, dzBx = (bx - Bx[km]) * idz;
+    const R dxBz = (bz - Bz[im]) * idx, dxBy = (by - By[im]) * idx;
+    const R jx = (R)(jreal(J0[cell], D.jq) + D.jbg[0]);
+    const R jy = (R)(jreal(J1[cell], D.jq) + D.jbg[1]);
+    const R jz = (R)(jreal(J2[cell], D.jq) + D.jbg[2]);
+    Ex[cell] += dt * (dyBz - dzBy - jx);
+    Ey[cell] += dt * (dzBx - dxBz - jy);
+    Ez[cell] += dt * (dxBy - dyBx - jz);
+    J0[cell] = JT(0); J1[cell] = JT(0); J2[cell] = JT(0);
+}
+
+// ------------------------------------------------------ seen-field passes
+// axis 2: combined z taps (tz[0] for Ex, Ey; tz[1] for Ez, Bx, By, Bz)
+// axis 0 / 1: filter taps along x / y.  blockIdx.y selects the component.
+template <int AXIS, class R>
+__global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                                   int src_sel, int dst_sel)
+{
+    const int inst = work[blockIdx.x].x;
+    const InstDesc &D = Dt[inst];
+    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    const int comp = blockIdx.y;
+    if (cell >= D.ncell) return;
+    const R *src;
+    if (src_sel == 0) src = comp < 3 ? (const R *)D.E[comp] : (const R *)D.B[comp - 3];
+    else if (src_sel == 1) src = (const R *)D.T1[comp];
+    else src = (const R *)D.T2[comp];
+    R *dst;
+    if (dst_sel == 1) dst = (R *)D.T1[comp];
+    else if (dst_sel == 2) dst = (R *)D.T2[comp];
+    else dst = comp < 3 ? (R *)D.Et[comp] : (R *)D.Bt[comp - 3];
+    int i, j, k;
+    cell_ijk<R>(D, cell, i, j, k);
+    const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
+    R acc = R(0);
+    if constexpr (AXIS == 2) {
+        const double *tap = D.tz[comp < 2 ? 0 : 1];
+        const int h = D.hz;
+        const int rowoff = i + j * nx, plane = nx * ny;
+        for (int t = -h; t <= h; t++) {
+            int kk = k + t;
+            kk = ((kk % nz) + nz) % nz;
+            acc += (R)tap[t + h] * src[rowoff + kk * plane];
+        }
+    } else if constexpr (AXIS == 0) {
+        const int h = D.hx;
+        const int rowbase = cell - i;
+        for (int t = -h; t <= h; t++) {
+            int ii = i + t;
+            ii = ((ii % nx) + nx) % nx;
+            acc += (R)D.tx[t + h] * src[rowbase + ii];
+        }
+    } else {
+        const int h = D.hy;
+        const int base = i + k * ny * nx;
+        for (int t = -h; t <= h; t++) {
+            int jj = j + t;
+            jj = ((jj % ny) + ny) % ny;
+            acc += (R)D.ty[t + h] * src[base + jj * nx];
+        }
+    }
+    dst[cell] = acc;
+}
+
+// ------------------------------------------------------------------ resort
+
+__device__ __forceinline__ int tile_of(const InstDesc &D, int idx)
+{
+    const int cx = idx % D.n[0];
+    const int r = idx / D.n[0];
+    const int cy = r % D.n[1], cz = r / D.n[1];
+    return (cz / D.tile[2] * D.nt[1] + cy / D.tile[1]) * D.nt[0] + cx / D.tile[0];
+}
+
+__global__ void __launch_bounds__(256) k_resort_count(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    const InstDesc &D = Dt[work[blockIdx.x].x];
+    if (!D.flags[FLAG_RESORT]) return;
+    const long long p = (long long)work[blockIdx.x].y * PIC_PART_CHUNK + threadIdx.x;
+    if (p >= D.np) return;
+    const int t = tile_of(D, D.pidx[p]);
+    D.stile[p] = t;
+    D.srank[p] = atomicAdd(&D.tcount[t], 1);
+}
+
+// one 1024-thread block per instance: exclusive scan of the tile counts
+__global__ void __launch_bounds__(1024) k_resort_scan(const InstDesc *__restrict__ Dt, int inst0)
+{
+    const InstDesc &D = Dt[inst0 + blockIdx.x];
+    if (!D.flags[FLAG_RESORT]) return;
+    __shared__ int part[1024];
+    const int n = D.ntiles, tid = threadIdx.x;
+    const int per = (n + 1023) / 1024;
+    const int b = tid * per, e = min(n, b + per);
+    int s = 0;
+    for (int t = b; t < e; t++) s += D.tcount[t];
+    part[tid] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int run = tid == 0 ? 0 : part[tid - 1];
+    for (int t = b; t < e; t++) {
+        D.tstart[t] = run;
+        run += D.tcount[t];
+        D.tcount[t] = 0;
+    }
+    if (tid == 1023) D.tstart[n] = part[1023];
+}
+
+template <int DIM, class R>
+__global__ void __launch_bounds__(256) k_resort_scatter(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    const InstDesc &D = Dt[work[blockIdx.x].x];
+    if (!D.flags[FLAG_RESORT]) return;
+    const long long p = (long long)work[blockIdx.x].y * PIC_PART_CHUNK + threadIdx.x;
+    if (p >= D.np) return;
+    const int q = D.tstart[D.stile[p]] + D.srank[p];
+    D.sidx[q] = D.pidx[p];
+    D.spid[q] = D.ppid[p];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (!(DIM == 2 && a == 1)) ((R *)D.soff[a])[q] = ((const R *)D.poff[a])[p];
+        ((R *)D.su[a])[q] = ((const R *)D.pu[a])[p];
+    }
+}
+
+template <int DIM, class R>
+__global__ void __launch_bounds__(256) k_resort_copy(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    const InstDesc &D = Dt[work[blockIdx.x].x];
+    if (!D.flags[FLAG_RESORT]) return;
+    const long long p = (long long)work[blockIdx.x].y * PIC_PART_CHUNK + threadIdx.x;
+    if (p >= D.np) return;
+    D.pidx[p] = D.sidx[p];
+    D.ppid[p] = D.spid[p];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (!(DIM == 2 && a == 1)) ((R *)D.poff[a])[p] = ((const R *)D.soff[a])[p];
+        ((R *)D.pu[a])[p] = ((const R *)D.su[a])[p];
+    }
+}
+
+// per instance: reset every tile's bounding box to the tile itself and clear the flag
+__global__ void __launch_bounds__(256) k_resort_done(const InstDesc *__restrict__ Dt, int inst0, int force)
+{
+    const InstDesc &D = Dt[inst0 + blockIdx.x];
+    if (!force && !D.flags[FLAG_RESORT]) return;
+    for (int t = threadIdx.x; t < D.ntiles; t += blockDim.x) {
+        const int tx = t % D.nt[0], r = t / D.nt[0];
+        const int ty = r % D.nt[1], tz = r / D.nt[1];
+        const int tc[3] = {tx, ty, tz};
+        for (int a = 0; a < 3; a++) {
+            const int lo = tc[a] * D.tile[a];
+            D.tbox[t * 6 + a] = lo;
+            D.tbox[t * 6 + 3 + a] = min(D.tile[a], D.n[a] - lo);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        D.flags[FLAG_RESORT] = 0;
+        if (!force) D.flags[FLAG_NRESORT] += 1;
+    }
+}
+
+// ------------------------------------------------------------- diagnostics
+
+template <class R> __device__ __forceinline__ bool finite_r(R v) { return isfinite(v); }
+
+__device__ __forceinline__ void block_sum_to(double v, double *dst)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0 && v != 0.0) unsafeAtomicAdd(dst, v);
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_energy(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                                double *out, int out_stride, const int *pos, int cap)
+{
+    const int inst = work[blockIdx.x].x;
+    const InstDesc &D = Dt[inst];
+    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    double bad = 0.0;
+    if (cell < D.ncell) {
+        for (int c = 0; c < 3; c++) {
+            const double e = (double)((const R *)D.E[c])[cell];
+            const double b = (double)((const R *)D.B[c])[cell];
+            v[c] = e * e;
+            v[3 + c] = b * b;
+            if (!isfinite(e) || !isfinite(b)) bad = 1.0;
+        }
+    }
+    double *dst;
+    if (pos) dst = out + ((size_t)(*pos % cap) * out_stride + inst) * 6;   // trace rows
+    else dst = D.diag;
+    const double h = 0.5 * D.dV;
+    for (int c = 0; c < 6; c++) block_sum_to(h * v[c], dst + c);
+    if (!pos) block_sum_to(bad, D.diag + DG_NONFIN);
+}
+
+// charge density (order-L shape on integer nodes) of the current particles,
+// plus kinetic energy and non-finite momenta
+template <int DIM, int L, class R>
+__global__ void __launch_bounds__(256) k_rho(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                             int to_rho0, int with_kin)
+{
+    const InstDesc &D = Dt[work[blockIdx.x].x];
+    const long long p = (long long)work[blockIdx.x].y * PIC_PART_CHUNK + threadIdx.x;
+    double kin = 0.0, bad = 0.0;
+    if (p < D.np) {
+        const int idx = D.pidx[p];
+        int c[3];
+        c[0] = idx % D.n[0];
+        const int r = idx / D.n[0];
+        c[1] = r % D.n[1];
+        c[2] = r / D.n[1];
+        double w[3][L + 1];
+        for (int a = 0; a < 3; a++) {
+            if (DIM == 2 && a == 1) continue;
+            Shape<L, double>::integer((double)((const R *)D.poff[a])[p], w[a]);
+        }
+        constexpr int H = (L - 1) / 2;
+        double *rho = to_rho0 ? D.rho0 : D.rho;
+        const int NY = DIM == 3 ? L + 1 : 1;
+        for (int kz = 0; kz < L + 1; kz++)
+            for (int ky = 0; ky < NY; ky++)
+                for (int kx = 0; kx < L + 1; kx++) {
+                    const int gx = ((c[0] - H + kx) % D.n[0] + D.n[0]) % D.n[0];
+                    const int gy = DIM == 3 ? ((c[1] - H + ky) % D.n[1] + D.n[1]) % D.n[1] : 0;
+                    const int gz = ((c[2] - H + kz) % D.n[2] + D.n[2]) % D.n[2];
+                    const double wt = w[0][kx] * (DIM == 3 ? w[1][ky] : 1.0) * w[2][kz];
+                    unsafeAtomicAdd(&rho[(gz * D.n[1] + gy) * D.n[0] + gx], D.rho_c * wt);
+                }
+        if (with_kin) {
+            const double u0 = ((const R *)D.pu[0])[p], u1 = ((const R *)D.pu[1])[p], u2 = ((const R *)D.pu[2])[p];
+            const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+            kin = D.w * D.m * uu / (sqrt(1.0 + uu) + 1.0);   // gamma - 1 without cancellation
+            if (!isfinite(uu)) { bad = 1.0; kin = 0.0; }
+        }
+    }
+    if (with_kin) {
+        block_sum_to(kin, D.diag + DG_WKIN);
+        block_sum_to(bad, D.diag + DG_NONFIN);
+    }
+}
+
+// Gauss residual after a step: div E^n - dt div J^{n+1/2} - (rho^{n+1} - rho^0)
+template <int DIM, class R>
+__global__ void __launch_bounds__(256) k_gauss(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    typedef typename JOf<R>::T JT;
+    const InstDesc &D = Dt[work[blockIdx.x].x];
+    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    double g2 = 0.0, gmax = 0.0, chg = 0.0, rmax = 0.0;
+    if (cell < D.ncell) {
+        int i, j, k;
+        cell_ijk<R>(D, cell, i, j, k);
+        const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
+        const int im = (i == 0 ? nx - 1 : i - 1) + (j + k * ny) * nx;
+        const int km = i + (j + (k == 0 ? nz - 1 : k - 1) * ny) * nx;
+        const R *E0 = (const R *)D.E[0], *E1 = (const R *)D.E[1], *E2 = (const R *)D.E[2];
+        const JT *J0 = (const JT *)D.J[0], *J1 = (const JT *)D.J[1], *J2 = (const JT *)D.J[2];
+        double divE = ((double)E0[cell] - (double)E0[im]) / D.d[0] + ((double)E2[cell] - (double)E2[km]) / D.d[2];
+        double divJ = (jreal(J0[cell], D.jq) - jreal(J0[im], D.jq)) / D.d[0] +
+                      (jreal(J2[cell], D.jq) - jreal(J2[km], D.jq)) / D.d[2];
+        if (DIM == 3) {
+            const int jm = i + ((j == 0 ? ny - 1 : j - 1) + k * ny) * nx;
+            divE += ((double)E1[cell] - (double)E1[jm]) / D.d[1];
+            divJ += (jreal(J1[cell], D.jq) - jreal(J1[jm], D.jq)) / D.d[1];
+        }
+        const double rho = D.rho[cell];
+        const double res = divE - D.dt * divJ - (rho - D.rho0[cell]);
+        g2 = res * res;
+        gmax = fabs(res);
+        chg = rho * D.dV;
+        rmax = fabs(rho);
+    }
+    block_sum_to(g2, D.diag + DG_G2);
+    block_sum_to(chg, D.diag + DG_CHARGE);
+    gmax = wave_max(gmax);
+    rmax = wave_max(rmax);
+    if ((threadIdx.x & 63) == 0) {
+        atomic_max_pos(D.diag + DG_GMAX, gmax);
+        atomic_max_pos(D.diag + DG_RHOMAX, rmax);
+    }
+}
+
+__global__ void k_zero_rho_diag(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int rho0)
+{
+    const InstDesc &D = Dt[work[blockIdx.x].x];
+    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    if (cell < D.ncell) (rho0 ? D.rho0 : D.rho)[cell] = 0.0;
+    if (work[blockIdx.x].y == 0 && threadIdx.x < DG_COUNT && !rho0) D.diag[threadIdx.x] = 0.0;
+}
+
+__global__ void k_trace_tick(int *pos, double *trace, int n_inst, int cap)
+{
+    // advance the trace row and clear the next one
+    const int next = (*pos + 1) % cap;
+    for (int t = threadIdx.x; t < n_inst * 6; t += blockDim.x) trace[(size_t)next * n_inst * 6 + t] = 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) *pos += 1;
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_clear_j(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    typedef typename JOf<R>::T JT;
+    const InstDesc &D = Dt[work[blockIdx.x].x];
+    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    if (cell >= D.ncell) return;
+    for (int c = 0; c < 3; c++) ((JT *)D.J[c])[cell] = JT(0);
+}
+
+inline int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : -1; }
+
+}  // namespace
+
+// ================================================================ launchers
+
+#define DISPATCH_R(fp32, ...) \
+    do { if (fp32) { typedef float R; __VA_ARGS__; } else { typedef double R; __VA_ARGS__; } } while (0)
+
+int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork)
+{
+    if (nwork <= 0) return 0;
+    dim3 g(nwork), b(PIC_FIELD_CHUNK);
+    DISPATCH_R(c.fp32, {
+        if (c.dims == 2) {
+            k_yee_b<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
+            k_yee_e<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
+            k_yee_b<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
+        } else {
+            k_yee_b<3, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
+            k_yee_e<3, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
+            k_yee_b<3, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
+        }
+    });
+    return hip_ok(hipGetLastError());
+}
+
+int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork)
+{
+    if (nwork <= 0) return 0;
+    dim3 g(nwork, 6), b(PIC_FIELD_CHUNK);
+    DISPATCH_R(c.fp32, {
+        k_seen_pass<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1);
+        if (c.dims == 2) {
+            k_seen_pass<0, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 0);
+        } else {
+            k_seen_pass<0, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2);
+            k_seen_pass<1, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 2, 0);
+        }
+    });
+    return hip_ok(hipGetLastError());
+}
+
+size_t particle_smem_bytes(int dims, int fp32, const int wmax[3])
+{
+    const size_t wc = (size_t)wmax[0] * (dims == 3 ? wmax[1] : 1) * wmax[2];
+    const size_t r = fp32 ? 4 : 8;
+    return wc * (3 * 8 + 6 * r);
+}
+
+int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid, int block, const int wmax[3])
+{
+    if (nwork <= 0) return 0;
+    const int wy = c.dims == 3 ? wmax[1] : 1;
+    const int wm[3] = {wmax[0], wy, wmax[2]};
+    const size_t smem = particle_smem_bytes(c.dims, c.fp32, wm);
+    dim3 g(grid > 0 ? grid : nwork), b(block);
+#define PK(D_, L_) k_particles<D_, L_, R><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2])
+    DISPATCH_R(c.fp32, {
+        if (c.dims == 2 && c.order == 1) PK(2, 1);
+        else if (c.dims == 2 && c.order == 3) PK(2, 3);
+        else if (c.dims == 3 && c.order == 1) PK(3, 1);
+        else PK(3, 3);
+    });
+#undef PK
+    return hip_ok(hipGetLastError());
+}
+
+int launch_resort(const LaunchCtx &c, const int2 *cwork, int ncwork, int inst0, int n_inst)
+{
+    if (ncwork <= 0) return 0;
+    dim3 g(ncwork), b(PIC_PART_CHUNK);
+    k_resort_count<<<g, b, 0, c.stream>>>(c.desc, cwork);
+    k_resort_scan<<<dim3(n_inst), dim3(1024), 0, c.stream>>>(c.desc, inst0);
+    DISPATCH_R(c.fp32, {
+        if (c.dims == 2) {
+            k_resort_scatter<2, R><<<g, b, 0, c.stream>>>(c.desc, cwork);
+            k_resort_copy<2, R><<<g, b, 0, c.stream>>>(c.desc, cwork);
+        } else {
+            k_resort_scatter<3, R><<<g, b, 0, c.stream>>>(c.desc, cwork);
+            k_resort_copy<3, R><<<g, b, 0, c.stream>>>(c.desc, cwork);
+        }
+    });
+    k_resort_done<<<dim3(n_inst), dim3(256), 0, c.stream>>>(c.desc, inst0, 0);
+    return hip_ok(hipGetLastError());
+}
+
+int launch_clear_j(const LaunchCtx &c, const int2 *fwork, int nwork)
+{
+    if (nwork <= 0) return 0;
+    DISPATCH_R(c.fp32, { k_clear_j<R><<<dim3(nwork), dim3(PIC_FIELD_CHUNK), 0, c.stream>>>(c.desc, fwork); });
+    return hip_ok(hipGetLastError());
+}
+
+int launch_rho(const LaunchCtx &c, const int2 *cwork, int ncwork, const int2 *fwork, int nfwork, int to_rho0)
+{
+    if (nfwork > 0)
+        k_zero_rho_diag<<<dim3(nfwork), dim3(PIC_FIELD_CHUNK), 0, c.stream>>>(c.desc, fwork, to_rho0);
+    if (ncwork > 0) {
+        dim3 g(ncwork), b(PIC_PART_CHUNK);
+#define RK(D_, L_) k_rho<D_, L_, R><<<g, b, 0, c.stream>>>(c.desc, cwork, to_rho0, to_rho0 ? 0 : 1)
+        DISPATCH_R(c.fp32, {
+            if (c.dims == 2 && c.order == 1) RK(2, 1);
+            else if (c.dims == 2 && c.order == 3) RK(2, 3);
+            else if (c.dims == 3 && c.order == 1) RK(3, 1);
+            else RK(3, 3);
+        });
+#undef RK
+    }
+    return hip_ok(hipGetLastError());
+}
+
+int launch_diag(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *cwork, int ncwork, int, int)
+{
+    // zero rho and the accumulators, deposit rho (+ kinetic energy), then the grid reductions
+    if (launch_rho(c, cwork, ncwork, fwork, nfwork, 0)) return -1;
+    if (nfwork <= 0) return 0;
+    dim3 g(nfwork), b(PIC_FIELD_CHUNK);
+    DISPATCH_R(c.fp32, {
+        k_energy<R><<<g, b, 0, c.stream>>>(c.desc, fwork, nullptr, 0, nullptr, 1);
+        if (c.dims == 2) k_gauss<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
+        else k_gauss<3, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
+    });
+    return hip_ok(hipGetLastError());
+}
+
+int launch_trace_rows(const LaunchCtx &c, const int2 *fwork, int nfwork, int *pos, double *trace, int n_inst,
+                      int cap)
+{
+    if (nfwork <= 0 || cap <= 0) return 0;
+    DISPATCH_R(c.fp32, {
+        k_energy<R><<<dim3(nfwork), dim3(PIC_FIELD_CHUNK), 0, c.stream>>>(c.desc, fwork, trace, n_inst, pos, cap);
+    });
+    k_trace_tick<<<dim3(1), dim3(256), 0, c.stream>>>(pos, trace, n_inst, cap);
+    return hip_ok(hipGetLastError());
+}
+
+int launch_fill_bbox(const LaunchCtx &c, int inst0, int n_inst)
+{
+    k_resort_done<<<dim3(n_inst), dim3(256), 0, c.stream>>>(c.desc, inst0, 1);
+    return hip_ok(hipGetLastError());
+}

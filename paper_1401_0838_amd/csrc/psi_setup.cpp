@@ -1,0 +1,94 @@
+// Host setup of the correction-stencil coefficients (Sec. 2, Eqs. 3-5).
+//
+// The multiplier M(s) that zeroes the m_z = 0 mismatch term at omega = k_z is
+// approximated by Psi_E(s) / Psi_B(s), two polynomials of degree deg in
+// s = sin^2(k_z dz / 2), by rational interpolation at 2*deg+1 nodes spaced
+// uniformly on [0, 1] with Psi_B(0) = 1.  The linear system is badly
+// conditioned (around 1e8 for quartics), so it is assembled and solved in
+// 113-bit binary floating point (libquadmath) and only the result is rounded
+// to double.  Built with g++ (quadmath is a GCC runtime library).
+#include <quadmath.h>
+
+#include <cmath>
+
+#include "pic_api.h"
+
+namespace {
+
+typedef __float128 quad;
+
+quad multiplier(int interp, quad alpha, quad s)
+{
+    if (s == 0) return 1;
+    quad th = asinq(sqrtq(s));       // theta = k_z dz / 2
+    quad sn = sinq(th);
+    quad num = sinq(2 * alpha * th); // 2 sin(k dt/2) cos(k dt/2)
+    switch (interp) {
+    case PIC_GALERKIN: return num * th / (2 * alpha * sn * sn);         // Eq. 3
+    case PIC_UNIFORM:  return num / (2 * alpha * sn);                   // Eq. 4
+    default:           return num * cosq(th) / (2 * alpha * sn);        // Eq. 5
+    }
+}
+
+}  // namespace
+
+extern "C" int pic_psi_coeffs(int interp, double alpha_d, int deg, double *psi_e, double *psi_b)
+{
+    if (!psi_e || !psi_b || deg < 1 || deg > 8 || !(alpha_d > 0.0) || alpha_d >= 1.0 ||
+        interp < PIC_GALERKIN || interp > PIC_MOMENTUM)
+        return PIC_EINVAL;
+    const int nn = 2 * deg + 1;
+    const quad alpha = alpha_d;
+    quad M[17];
+    quad dev = 0;
+    for (int j = 0; j < nn; j++) {
+        M[j] = multiplier(interp, alpha, (quad)j / (nn - 1));
+        quad d = fabsq(M[j] - 1);
+        if (d > dev) dev = d;
+    }
+    for (int i = 0; i <= deg; i++) psi_e[i] = psi_b[i] = (i == 0) ? 1.0 : 0.0;
+    if (dev < (quad)1e-28) return PIC_OK;   // multiplier identically 1: identity
+
+    // unknowns a_0..a_deg, b_1..b_deg;  sum a_i s^i - M sum_{i>=1} b_i s^i = M
+    quad A[17][18];
+    for (int r = 0; r < nn; r++) {
+        quad s = (quad)r / (nn - 1), p = 1;
+        for (int i = 0; i <= deg; i++) {
+            A[r][i] = p;
+            if (i >= 1) A[r][deg + i] = -M[r] * p;
+            p *= s;
+        }
+        A[r][nn] = M[r];
+    }
+    quad scale = 0;
+    for (int r = 0; r < nn; r++)
+        for (int c = 0; c < nn; c++) scale = fmaxq(scale, fabsq(A[r][c]));
+    // Gaussian elimination with partial pivoting
+    for (int c = 0; c < nn; c++) {
+        int piv = c;
+        for (int r = c + 1; r < nn; r++)
+            if (fabsq(A[r][c]) > fabsq(A[piv][c])) piv = r;
+        if (fabsq(A[piv][c]) < scale * (quad)1e-30) return PIC_EPSI;
+        if (piv != c)
+            for (int k = 0; k <= nn; k++) { quad t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
+        for (int r = c + 1; r < nn; r++) {
+            quad f = A[r][c] / A[c][c];
+            for (int k = c; k <= nn; k++) A[r][k] -= f * A[c][k];
+        }
+    }
+    quad x[17];
+    for (int r = nn - 1; r >= 0; r--) {
+        quad acc = A[r][nn];
+        for (int k = r + 1; k < nn; k++) acc -= A[r][k] * x[k];
+        x[r] = acc / A[r][r];
+    }
+    for (int i = 0; i <= deg; i++) psi_e[i] = (double)x[i];
+    for (int i = 1; i <= deg; i++) psi_b[i] = (double)x[deg + i];
+    // both polynomials must stay positive on [0, 1]
+    for (int k = 0; k <= 4096; k++) {
+        double s = k / 4096.0, pe = 0, pb = 0;
+        for (int i = deg; i >= 0; i--) { pe = pe * s + psi_e[i]; pb = pb * s + psi_b[i]; }
+        if (!(pe > 0.0) || !(pb > 0.0)) return PIC_EPSI;
+    }
+    return PIC_OK;
+}

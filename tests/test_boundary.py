@@ -1,0 +1,95 @@
+"""C-ABI library: loads, exports every declared entry point, and its host-only
+logic (coefficient setup, configuration checks) behaves.  CPU only."""
+import ctypes as C
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import pic_inputs as pi
+from paper_1401_0838_amd import _lib as L
+from paper_1401_0838_amd.sim import make_config
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pic_api.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = C.CDLL(L.LIB_PATH)
+    names = _declared()
+    assert "pic_step" in names and "pic_init" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(L.EXPORTED) == names
+
+
+def test_strerror_codes():
+    for code in range(0, -10, -1):
+        assert L.strerror(code)
+
+
+@pytest.mark.parametrize("case", json.load(open(os.path.join(ROOT, "tests", "golden", "psi_coeffs.json")))["cases"])
+def test_psi_setup_matches_oracle_golden(case):
+    """The library's 113-bit setup reproduces the oracle's 50-digit coefficients
+    (stored by tests/golden/make_psi_golden.py) to float64 rounding."""
+    interp = {"galerkin": L.PIC_GALERKIN, "uniform": L.PIC_UNIFORM, "momentum": L.PIC_MOMENTUM}[case["interp"]]
+    rc, a, b = L.pic_psi_coeffs(interp, case["alpha"], 4)
+    ea = np.array([float(v) for v in case["psi_e"]])
+    eb = np.array([float(v) for v in case["psi_b"]])
+    if case["positive"]:
+        assert rc == L.PIC_OK
+    else:
+        assert rc == L.PIC_EPSI
+    assert np.max(np.abs(a - ea) / np.maximum(np.abs(ea), 1e-300)) <= 4e-16
+    assert np.max(np.abs(b - eb) / np.maximum(np.abs(eb), 1e-300)) <= 4e-16
+
+
+def test_psi_setup_rejects_breakdown():
+    """Sec. 3 notes a narrow alpha window where the determination breaks down; for the
+    Galerkin multiplier Psi_B turns negative near alpha = 0.69 (reading used here)."""
+    rc, a, b = L.pic_psi_coeffs(L.PIC_GALERKIN, 0.69, 4)
+    assert rc == L.PIC_EPSI
+    rc, _, _ = L.pic_psi_coeffs(L.PIC_GALERKIN, 1.2, 4)
+    assert rc == L.PIC_EINVAL
+
+
+def _cfg(**kw):
+    wl = pi.workload("beam2d_64_fp64", n=(16, 16))
+    wl.update(kw)
+    return make_config(wl)
+
+
+def test_plan_validates_configs():
+    assert L.pic_plan([_cfg()], [1024]) > 0
+    with pytest.raises(L.PicError) as e:
+        L.pic_plan([_cfg(alpha=0.71)], [1024])      # 2D Yee limit 1/sqrt(2)
+    assert e.value.code == L.PIC_ECOURANT
+    c = _cfg(correction=True)
+    c.psi_b[4] = -5.0
+    with pytest.raises(L.PicError) as e:
+        L.pic_plan([c], [16])
+    assert e.value.code == L.PIC_EPSI
+    c = _cfg()
+    c.shape_order = 2
+    with pytest.raises(L.PicError) as e:
+        L.pic_plan([c], [16])
+    assert e.value.code == L.PIC_EINVAL
+    c = _cfg(interp="uniform")
+    with pytest.raises(L.PicError) as e:
+        L.pic_plan([c], [16])
+    assert e.value.code == L.PIC_EUNSUPPORTED
+    with pytest.raises(L.PicError):
+        L.pic_plan([_cfg(), _cfg(dims=3, n=(8, 8, 8))], [16, 16])
+
+
+def test_plan_grows_with_batch():
+    one = L.pic_plan([_cfg()], [1024])
+    two = L.pic_plan([_cfg(), _cfg(n=(32, 16))], [1024, 2048])
+    assert two > one

@@ -1,0 +1,245 @@
+"""GPU path (libpic.so through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 fields relative L2 <= 1e-10 after 50 steps; FP32 <= 1e-4
+after 10 steps (relative L2 over each field vector).  Inputs are seeded
+synthetic beams from pic_inputs, identical on both sides.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import pic_inputs as pi
+from oracle.ref import OracleSim
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(*a, **k):
+    from paper_1401_0838_amd.sim import Simulation
+    return Simulation(*a, **k)
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _pair(wl, nsteps, precision, seed=0, sigma=None, x=None, u=None):
+    if x is None:
+        x, u = pi.load_beam(wl["dims"], wl["n"], wl["ppc"], wl["gamma"],
+                            wl["sigma"] if sigma is None else sigma, seed)
+    _say("case %s n=%s prec=%s steps=%d np=%d" % (wl.get("name"), wl["n"], precision, nsteps, x.shape[0]))
+    sim = _sim(wl, (x, u), precision=precision)
+    ref = OracleSim(wl, x, u)
+    sim.step(nsteps)
+    ref.step(nsteps)
+    return sim, ref
+
+
+def _field_errors(sim, ref):
+    return {k: _rel(sim.fields(k), getattr(ref, k)) for k in ("E", "B", "J")}
+
+
+def _particle_errors(sim, ref, wl):
+    x, u = sim.particles()
+    rx = ref.positions()
+    L = np.array(wl["n"], float) * np.array(wl.get("d", (1.0,) * wl["dims"]))
+    dx = np.abs(x - rx)
+    dx = np.minimum(dx, L - dx)
+    return float(dx.max()), _rel(u, ref.momenta())
+
+
+# ------------------------------------------------------------------ Yee
+
+def test_yee_standing_mode_fp64():
+    wl = pi.workload("beam2d_64_fp64", n=(48, 32), correction=False, filter=[], alpha=0.45)
+    x = np.zeros((0, 2))
+    u = np.zeros((0, 3))
+    sim = _sim(wl, (x, u), precision="fp64")
+    ref = OracleSim(wl, x, u)
+    nz, ny, nx = ref.shape
+    kx, kz = 2 * math.pi * 3 / nx, 2 * math.pi * 2 / nz
+    mode = np.sin(kx * np.arange(nx))[None, None, :] * np.sin(kz * np.arange(nz))[:, None, None]
+    sim.set_field("E", 1, mode)
+    ref.E[1][:] = mode
+    sim.step(300)
+    for _ in range(300):
+        ref.yee()
+    assert _rel(sim.fields("E"), ref.E) < 1e-12
+    assert _rel(sim.fields("B"), ref.B) < 1e-12
+    dt = 0.45
+    w = 2 / dt * math.asin(dt * math.sqrt(math.sin(kx / 2) ** 2 + math.sin(kz / 2) ** 2))
+    assert np.max(np.abs(sim.field("E", 1) - math.cos(300 * w * dt) * mode)) < 1e-11
+
+
+# ------------------------------------------------------------ beam parity
+
+@pytest.mark.parametrize("corr", [False, True])
+def test_beam_fp64_parity_50_steps(corr):
+    wl = pi.workload("beam2d_64_fp64", correction=corr,
+                     filter=pi.workloads.BINOMIAL4 if corr else [])
+    sim, ref = _pair(wl, 50, "fp64")
+    errs = _field_errors(sim, ref)
+    _say("fp64 corr=%s %s" % (corr, errs))
+    assert errs["E"] < 1e-10 and errs["B"] < 1e-10 and errs["J"] < 1e-10
+    dxm, du = _particle_errors(sim, ref, wl)
+    assert dxm < 1e-9 and du < 1e-10
+    assert _rel(sim.fields("Et"), ref.Et) < 1e-10
+    d = sim.diag()
+    assert d["rc"] == 0 and d["nonfinite"] == 0 and d["particle_error"] == 0
+    assert d["gauss_linf"] < 1e-11 * d["rho_max"]
+    od = ref.diag()
+    assert abs(d["Wkin"] - od["Wkin"]) < 1e-10 * od["Wkin"]
+    assert abs(d["Wperp"] - od["Wperp"]) <= 1e-9 * od["Wperp"] + 1e-300
+    assert abs(d["charge"] - od["charge"]) < 1e-10 * abs(od["charge"])
+    sim.close()
+
+
+def test_beam_fp32_parity_10_steps():
+    wl = pi.workload("beam2d_64_fp64", correction=True, filter=pi.workloads.BINOMIAL4)
+    sim, ref = _pair(wl, 10, "fp32")
+    errs = _field_errors(sim, ref)
+    _say("fp32 %s" % errs)
+    assert errs["E"] < 1e-4 and errs["B"] < 1e-4 and errs["J"] < 1e-4
+    dxm, du = _particle_errors(sim, ref, wl)
+    assert dxm < 1e-5 and du < 1e-6
+    d = sim.diag()
+    assert d["gauss_linf"] < 1e-5 * d["rho_max"]
+    sim.close()
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.7])
+def test_beam_fp64_parity_alpha_scan(alpha):
+    wl = pi.workload("beam2d_512", n=(64, 96), alpha=alpha, ppc=4, precision="fp64")
+    sim, ref = _pair(wl, 50, "fp64")
+    errs = _field_errors(sim, ref)
+    _say("alpha %g %s" % (alpha, errs))
+    assert max(errs.values()) < 1e-10
+    sim.close()
+
+
+def test_cubic_2d_fp64_parity():
+    wl = pi.workload("beam2d_64_fp64", n=(48, 64), order=3, correction=True, filter=pi.workloads.BINOMIAL4)
+    sim, ref = _pair(wl, 30, "fp64")
+    errs = _field_errors(sim, ref)
+    _say("cubic2d %s" % errs)
+    assert max(errs.values()) < 1e-10
+    sim.close()
+
+
+@pytest.mark.parametrize("order,prec,tol", [(1, "fp64", 1e-10), (3, "fp64", 1e-10), (1, "fp32", 1e-4),
+                                            (3, "fp32", 1e-4)])
+def test_3d_parity(order, prec, tol):
+    wl = pi.workload("beam3d_128x128x256", n=(16, 12, 24), ppc=2, order=order)
+    sim, ref = _pair(wl, 10, prec)
+    errs = _field_errors(sim, ref)
+    _say("3d order %d %s %s" % (order, prec, errs))
+    assert max(errs.values()) < tol
+    d = sim.diag()
+    assert d["gauss_linf"] < (1e-11 if prec == "fp64" else 1e-5) * d["rho_max"]
+    sim.close()
+
+
+# ----------------------------------------------------------- edge cases
+
+def test_ragged_grid_and_tiny_grid():
+    for n in [(50, 37), (8, 8), (5, 70)]:
+        wl = pi.workload("beam2d_64_fp64", n=n, correction=True, filter=pi.workloads.BINOMIAL4)
+        sim, ref = _pair(wl, 25, "fp64", sigma=1e-2)
+        errs = _field_errors(sim, ref)
+        _say("grid %s %s" % (n, errs))
+        assert max(errs.values()) < 1e-10
+        sim.close()
+
+
+def test_empty_and_clumped_beams():
+    wl = pi.workload("beam2d_64_fp64", n=(32, 32), correction=True, filter=pi.workloads.BINOMIAL4)
+    # empty: fields stay zero
+    sim = _sim(wl, (np.zeros((0, 2)), np.zeros((0, 3))), precision="fp64")
+    sim.step(5)
+    assert np.all(sim.fields("E") == 0)
+    sim.close()
+    # clumped: all particles in a 3x3 block of cells, hot enough to spread across tiles
+    cells = np.array([i + 32 * k for i in range(10, 13) for k in range(10, 13)])
+    x, u = pi.load_beam(2, (32, 32), 64, 1.5, 0.8, 4, cells=cells)
+    sim, ref = _pair(wl, 40, "fp64", x=x, u=u)
+    errs = _field_errors(sim, ref)
+    d = sim.diag()
+    _say("clumped %s resorts=%d slow=%d" % (errs, d["resorts"], d["slow_tiles"]))
+    assert max(errs.values()) < 1e-10
+    sim.close()
+
+
+def test_strong_instability_growth_fp64():
+    """No correction, no filter, 200 steps (the plain 64x64 case): fields grow by many
+    orders of magnitude and GPU and oracle still agree."""
+    wl = pi.workload("beam2d_64_fp64")
+    sim, ref = _pair(wl, 200, "fp64")
+    errs = _field_errors(sim, ref)
+    _say("plain 200 steps %s Wperp=%g" % (errs, ref.energies()["Wperp"]))
+    assert errs["E"] < 1e-8 and errs["B"] < 1e-8
+    sim.close()
+
+
+# ------------------------------------------------------ determinism / modes
+
+def test_fp32_bitwise_deterministic_and_graph_equals_eager():
+    wl = pi.workload("beam2d_64_fp64", n=(64, 64), correction=True, filter=pi.workloads.BINOMIAL4)
+    x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], 1e-3, 9)
+    out = []
+    for graph in (True, True, False):
+        sim = _sim(wl, (x, u), precision="fp32")
+        sim.set_schedule("batched", graph)
+        sim.step(23)
+        out.append((sim.fields("E"), sim.fields("B"), sim.fields("J")))
+        sim.close()
+    for k in range(3):
+        assert np.array_equal(out[0][k], out[1][k])
+        assert np.array_equal(out[0][k], out[2][k])
+
+
+def test_batched_instances_match_own_oracle_and_plain():
+    wls = [pi.workload("beam2d_512", n=(64, 32), alpha=0.35, ppc=4, precision="fp64", tag="a"),
+           pi.workload("beam2d_512", n=(32, 96), alpha=0.55, ppc=4, gamma=10.0, precision="fp64", tag="b"),
+           pi.workload("beam2d_512", n=(48, 48), alpha=0.45, ppc=2, gamma=50.0, precision="fp64", tag="c")]
+    parts = [pi.load_beam(2, w["n"], w["ppc"], w["gamma"], 1e-4, 20 + i) for i, w in enumerate(wls)]
+    sim = _sim(wls, parts, precision="fp64")
+    sim.step(20)
+    for i, (w, (x, u)) in enumerate(zip(wls, parts)):
+        ref = OracleSim(w, x, u)
+        ref.step(20)
+        assert _rel(sim.fields("E", i), ref.E) < 1e-10
+        assert _rel(sim.fields("B", i), ref.B) < 1e-10
+    sim.close()
+    # plain (one launch per instance) equals batched bitwise in fp32
+    res = []
+    for sched in ("batched", "plain"):
+        sim = _sim(wls, parts, precision="fp32")
+        sim.set_schedule(sched, True)
+        sim.step(12)
+        res.append([sim.fields("E", i) for i in range(3)])
+        sim.close()
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
+# ------------------------------------------------------ full-size sample
+
+def test_full_size_512_fp32_parity_10_steps():
+    """The 512x512, 16 ppc workload in the launch configuration the benchmark
+    times (FP32, batched, graph), against the oracle after 10 steps."""
+    wl = pi.workload("beam2d_512")
+    sim, ref = _pair(wl, 10, "fp32")
+    errs = _field_errors(sim, ref)
+    _say("512 fp32 %s" % errs)
+    assert errs["E"] < 1e-4 and errs["B"] < 1e-4 and errs["J"] < 1e-4
+    d = sim.diag()
+    assert d["gauss_linf"] < 1e-5 * d["rho_max"]
+    sim.close()
