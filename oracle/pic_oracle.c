@@ -449,3 +449,368 @@ void o_div(const OSim *s, double *const F[3], double *out)
                 out[p] = v;
             }
 }
+
+/* ================================================================ adjoint
+ *
+ * Reverse mode of one oracle step, with exact transposes.  The step maps
+ * (E, B, J, x, u) to (E1, B2, J', x', u') through
+ *   B1 = B - h Cf E,  E1 = E + dt (Cb B1 - J - Jbg),  B2 = B1 - h Cf E1   (h = dt/2)
+ *   Et = M_E E1, Bt = M_B B2           (Psi series then filter passes; symmetric)
+ *   per particle: gather at x, Boris, x' = x + dt u'/gamma', Esirkepov J'
+ * with Cb = Cf^T on the periodic mesh.  Given the adjoints of the outputs,
+ * o_adj_step overwrites them with the adjoints of the inputs and adds
+ * dL/da_j = sum_{c in x,y} <lambda_Et_c, F S_z^j E1_c> to grad[j].
+ * The tape of the step is E1, B2 (after its Yee update) and the particle
+ * state x, u before its push.
+ */
+
+double o_dspline(int o, double t)
+{
+    double a = fabs(t), sg = t < 0.0 ? -1.0 : 1.0;
+    switch (o) {
+    case 0:
+        return 0.0;
+    case 1:
+        return a < 1.0 ? -sg : 0.0;
+    case 2:
+        if (a < 0.5) return -2.0 * t;
+        if (a < 1.5) return -sg * (1.5 - a);
+        return 0.0;
+    case 3:
+        if (a < 1.0) return -2.0 * t + 1.5 * t * a;
+        if (a < 2.0) return -0.5 * sg * (2.0 - a) * (2.0 - a);
+        return 0.0;
+    }
+    return 0.0;
+}
+
+/* out = Cf F (forward-difference curl, E locations -> B locations) */
+static void curl_f(const OSim *s, double *const F[3], double *out[3])
+{
+    for (long k = 0; k < s->nz; k++)
+        for (long j = 0; j < s->ny; j++)
+            for (long i = 0; i < s->nx; i++) {
+                long p = at(s, i, j, k);
+                double dyFz = (F[2][at(s, i, j + 1, k)] - F[2][p]) / s->dy;
+                double dzFy = (F[1][at(s, i, j, k + 1)] - F[1][p]) / s->dz;
+                double dzFx = (F[0][at(s, i, j, k + 1)] - F[0][p]) / s->dz;
+                double dxFz = (F[2][at(s, i + 1, j, k)] - F[2][p]) / s->dx;
+                double dxFy = (F[1][at(s, i + 1, j, k)] - F[1][p]) / s->dx;
+                double dyFx = (F[0][at(s, i, j + 1, k)] - F[0][p]) / s->dy;
+                out[0][p] = dyFz - dzFy;
+                out[1][p] = dzFx - dxFz;
+                out[2][p] = dxFy - dyFx;
+            }
+}
+
+/* out = Cb F (backward-difference curl, B locations -> E locations) */
+static void curl_b(const OSim *s, double *const F[3], double *out[3])
+{
+    for (long k = 0; k < s->nz; k++)
+        for (long j = 0; j < s->ny; j++)
+            for (long i = 0; i < s->nx; i++) {
+                long p = at(s, i, j, k);
+                double dyFz = (F[2][p] - F[2][at(s, i, j - 1, k)]) / s->dy;
+                double dzFy = (F[1][p] - F[1][at(s, i, j, k - 1)]) / s->dz;
+                double dzFx = (F[0][p] - F[0][at(s, i, j, k - 1)]) / s->dz;
+                double dxFz = (F[2][p] - F[2][at(s, i - 1, j, k)]) / s->dx;
+                double dxFy = (F[1][p] - F[1][at(s, i - 1, j, k)]) / s->dx;
+                double dyFx = (F[0][p] - F[0][at(s, i, j - 1, k)]) / s->dy;
+                out[0][p] = dyFz - dzFy;
+                out[1][p] = dzFx - dxFz;
+                out[2][p] = dxFy - dyFx;
+            }
+}
+
+/* adjoint of the gather of one component: scatter w * lv into lF and add
+ * d(value)/d(position) * lv to lpos (physical units) */
+static void interp_adj(const OSim *s, const double *F, double *lF, const int *stag, const int *ord,
+                       const double *c, double lv, double *lpos)
+{
+    long lo[3], hi[3];
+    const double d[3] = {s->dx, s->dy, s->dz};
+    for (int a = 0; a < 3; a++) {
+        if (a == 1 && s->dims == 2) { lo[a] = hi[a] = 0; continue; }
+        double shift = 0.5 * stag[a];
+        double half = 0.5 * (ord[a] + 1);
+        lo[a] = (long)floor(c[a] - shift - half);
+        hi[a] = (long)floor(c[a] - shift + half);
+    }
+    for (long k = lo[2]; k <= hi[2]; k++) {
+        double tz = c[2] - k - 0.5 * stag[2];
+        double wz = o_spline(ord[2], tz), dwz = o_dspline(ord[2], tz);
+        for (long j = lo[1]; j <= hi[1]; j++) {
+            double ty = c[1] - j - 0.5 * stag[1];
+            double wy = s->dims == 2 ? 1.0 : o_spline(ord[1], ty);
+            double dwy = s->dims == 2 ? 0.0 : o_dspline(ord[1], ty);
+            for (long i = lo[0]; i <= hi[0]; i++) {
+                double tx = c[0] - i - 0.5 * stag[0];
+                double wx = o_spline(ord[0], tx), dwx = o_dspline(ord[0], tx);
+                long p = at(s, i, j, k);
+                lF[p] += wx * wy * wz * lv;
+                double fv = F[p] * lv;
+                lpos[0] += dwx * wy * wz * fv / d[0];
+                if (s->dims == 3) lpos[1] += wx * dwy * wz * fv / d[1];
+                lpos[2] += wx * wy * dwz * fv / d[2];
+            }
+        }
+    }
+}
+
+/* reverse of the Boris push: given lun = dL/du_new, return lu (= dL/du_old),
+ * and add to lE, lB */
+void o_boris_adj(const double *u, const double *E, const double *B, double q, double m, double dt,
+                 const double *lun, double *lu, double *lE, double *lB)
+{
+    double eps = q * dt / (2.0 * m);
+    double um[3], t[3], sv[3], up[3];
+    for (int a = 0; a < 3; a++) um[a] = u[a] + eps * E[a];
+    double g = sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+    for (int a = 0; a < 3; a++) t[a] = eps * B[a] / g;
+    double t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    double f = 2.0 / (1.0 + t2);
+    for (int a = 0; a < 3; a++) sv[a] = f * t[a];
+    up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
+    up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
+    up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
+    /* un = uq + eps E;  uq = um + up x s */
+    double luq[3], lum[3], lup[3], ls[3], lt[3];
+    for (int a = 0; a < 3; a++) { luq[a] = lun[a]; lE[a] += eps * lun[a]; lum[a] = luq[a]; }
+    /* d(up x s): lup = s x luq ; ls = luq x up */
+    lup[0] = sv[1] * luq[2] - sv[2] * luq[1];
+    lup[1] = sv[2] * luq[0] - sv[0] * luq[2];
+    lup[2] = sv[0] * luq[1] - sv[1] * luq[0];
+    ls[0] = luq[1] * up[2] - luq[2] * up[1];
+    ls[1] = luq[2] * up[0] - luq[0] * up[2];
+    ls[2] = luq[0] * up[1] - luq[1] * up[0];
+    /* up = um + um x t: lum += lup + t x lup ; lt = lup x um */
+    lum[0] += lup[0] + (t[1] * lup[2] - t[2] * lup[1]);
+    lum[1] += lup[1] + (t[2] * lup[0] - t[0] * lup[2]);
+    lum[2] += lup[2] + (t[0] * lup[1] - t[1] * lup[0]);
+    lt[0] = lup[1] * um[2] - lup[2] * um[1];
+    lt[1] = lup[2] * um[0] - lup[0] * um[2];
+    lt[2] = lup[0] * um[1] - lup[1] * um[0];
+    /* s = f t, f = 2 / (1 + t.t) */
+    double lf = ls[0] * t[0] + ls[1] * t[1] + ls[2] * t[2];
+    double lt2 = -lf * f * f / 2.0;
+    for (int a = 0; a < 3; a++) lt[a] += f * ls[a] + 2.0 * t[a] * lt2;
+    /* t = eps B / g */
+    double lg = -(t[0] * lt[0] + t[1] * lt[1] + t[2] * lt[2]) / g;
+    for (int a = 0; a < 3; a++) lB[a] += eps * lt[a] / g;
+    /* g = sqrt(1 + um.um) */
+    for (int a = 0; a < 3; a++) lum[a] += lg * um[a] / g;
+    /* um = u + eps E */
+    for (int a = 0; a < 3; a++) { lu[a] = lum[a]; lE[a] += eps * lum[a]; }
+}
+
+/* reverse of o_deposit: given lJ on the grid, add dL/dp0, dL/dp1 (physical
+ * units) and return dL/dvy (2D J_y) */
+double o_deposit_adj(const OSim *s, const double *p0, const double *p1, double vy, double *const lJ[3],
+                     double *lp0, double *lp1)
+{
+    const int l = s->order;
+    const double d[3] = {s->dx, s->dy, s->dz};
+    const double half = 0.5 * (l + 1);
+    long lo[3] = {0, 0, 0};
+    int cnt[3] = {1, 1, 1};
+    double S0[3][MAXN], S1[3][MAXN], DS[3][MAXN], D0[3][MAXN], D1[3][MAXN];
+    double L0[3][MAXN], L1[3][MAXN];  /* dL/dS0, dL/dS1 */
+    double c0[3], c1[3];
+    for (int a = 0; a < 3; a++) {
+        for (int i = 0; i < MAXN; i++) L0[a][i] = L1[a][i] = 0.0;
+        if (a == 1 && s->dims == 2) { S0[a][0] = S1[a][0] = 1.0; DS[a][0] = 0.0; continue; }
+        c0[a] = p0[a] / d[a];
+        c1[a] = p1[a] / d[a];
+        double mn = c0[a] < c1[a] ? c0[a] : c1[a], mx = c0[a] < c1[a] ? c1[a] : c0[a];
+        lo[a] = (long)floor(mn - half);
+        long hi = (long)floor(mx + half);
+        cnt[a] = (int)(hi - lo[a] + 1);
+        for (int i = 0; i < cnt[a]; i++) {
+            double t0 = c0[a] - (double)(lo[a] + i), t1 = c1[a] - (double)(lo[a] + i);
+            S0[a][i] = o_spline(l, t0);
+            S1[a][i] = o_spline(l, t1);
+            D0[a][i] = o_dspline(l, t0);
+            D1[a][i] = o_dspline(l, t1);
+            DS[a][i] = S1[a][i] - S0[a][i];
+        }
+    }
+    const double qw = s->q * s->w;
+    double lvy = 0.0;
+    if (s->dims == 2) {
+        const double dV = s->dx * s->dz;
+        const double cx = -qw * s->dx / (s->dt * dV);
+        const double cz = -qw * s->dz / (s->dt * dV);
+        const double cy = qw * vy / dV;
+        /* J_x(i) = cx sum_{i'<=i} Wx(i'), Wx(i,k) = DSx(i) (S0z(k) + DSz(k)/2) */
+        for (int k = 0; k < cnt[2]; k++) {
+            double acc = 0.0;
+            for (int i = cnt[0] - 1; i >= 0; i--) {
+                acc += cx * lJ[0][at(s, lo[0] + i, 0, lo[2] + k)];   /* lWx(i,k) */
+                double az = 0.5 * (S0[2][k] + S1[2][k]);
+                L1[0][i] += acc * az;
+                L0[0][i] -= acc * az;
+                L0[2][k] += acc * 0.5 * DS[0][i];
+                L1[2][k] += acc * 0.5 * DS[0][i];
+            }
+        }
+        for (int i = 0; i < cnt[0]; i++) {
+            double acc = 0.0;
+            for (int k = cnt[2] - 1; k >= 0; k--) {
+                acc += cz * lJ[2][at(s, lo[0] + i, 0, lo[2] + k)];   /* lWz(i,k) */
+                double ax = 0.5 * (S0[0][i] + S1[0][i]);
+                L1[2][k] += acc * ax;
+                L0[2][k] -= acc * ax;
+                L0[0][i] += acc * 0.5 * DS[2][k];
+                L1[0][i] += acc * 0.5 * DS[2][k];
+            }
+        }
+        for (int k = 0; k < cnt[2]; k++)
+            for (int i = 0; i < cnt[0]; i++) {
+                double lj = lJ[1][at(s, lo[0] + i, 0, lo[2] + k)];
+                double wy = S0[0][i] * S0[2][k] / 3.0 + S1[0][i] * S0[2][k] / 6.0 + S0[0][i] * S1[2][k] / 6.0
+                          + S1[0][i] * S1[2][k] / 3.0;
+                lvy += qw / dV * wy * lj;
+                double lw = cy * lj;
+                L0[0][i] += lw * (S0[2][k] / 3.0 + S1[2][k] / 6.0);
+                L1[0][i] += lw * (S0[2][k] / 6.0 + S1[2][k] / 3.0);
+                L0[2][k] += lw * (S0[0][i] / 3.0 + S1[0][i] / 6.0);
+                L1[2][k] += lw * (S0[0][i] / 6.0 + S1[0][i] / 3.0);
+            }
+    } else {
+        const double dV = s->dx * s->dy * s->dz;
+        for (int a = 0; a < 3; a++) {
+            const double cf = -qw * d[a] / (s->dt * dV);
+            int b = (a + 1) % 3, c = (a + 2) % 3;
+            int idx[3];
+            for (idx[b] = 0; idx[b] < cnt[b]; idx[b]++)
+                for (idx[c] = 0; idx[c] < cnt[c]; idx[c]++) {
+                    const int ib = idx[b], ic = idx[c];
+                    /* tr = S0b S0c/3 + S1b S0c/6 + S0b S1c/6 + S1b S1c/3 */
+                    double tr = S0[b][ib] * S0[c][ic] / 3.0 + S1[b][ib] * S0[c][ic] / 6.0
+                              + S0[b][ib] * S1[c][ic] / 6.0 + S1[b][ib] * S1[c][ic] / 3.0;
+                    double acc = 0.0, ltr = 0.0;
+                    for (idx[a] = cnt[a] - 1; idx[a] >= 0; idx[a]--) {
+                        acc += cf * lJ[a][at(s, lo[0] + idx[0], lo[1] + idx[1], lo[2] + idx[2])];
+                        L1[a][idx[a]] += acc * tr;
+                        L0[a][idx[a]] -= acc * tr;
+                        ltr += acc * DS[a][idx[a]];
+                    }
+                    L0[b][ib] += ltr * (S0[c][ic] / 3.0 + S1[c][ic] / 6.0);
+                    L1[b][ib] += ltr * (S0[c][ic] / 6.0 + S1[c][ic] / 3.0);
+                    L0[c][ic] += ltr * (S0[b][ib] / 3.0 + S1[b][ib] / 6.0);
+                    L1[c][ic] += ltr * (S0[b][ib] / 6.0 + S1[b][ib] / 3.0);
+                }
+        }
+    }
+    for (int a = 0; a < 3; a++) {
+        if (a == 1 && s->dims == 2) continue;
+        for (int i = 0; i < cnt[a]; i++) {
+            lp0[a] += L0[a][i] * D0[a][i] / d[a];
+            lp1[a] += L1[a][i] * D1[a][i] / d[a];
+        }
+    }
+    return lvy;
+}
+
+void o_adj_step(OSim *s, double *const E1[3], double *const B2[3], double *const x0[3], double *const u0[3],
+                double *lE[3], double *lB[3], double *lJ[3], double *lx[3], double *lu[3],
+                double *lEt[3], double *lBt[3], double *grad)
+{
+    const long nc = ncell(s);
+    const double h = 0.5 * s->dt;
+    /* recompute the seen fields of this step */
+    for (int c = 0; c < 3; c++) {
+        memcpy(s->E[c], E1[c], nc * sizeof(double));
+        memcpy(s->B[c], B2[c], nc * sizeof(double));
+        memset(lEt[c], 0, nc * sizeof(double));
+        memset(lBt[c], 0, nc * sizeof(double));
+    }
+    o_seen(s);
+    /* particles */
+    int ord[3];
+    const double d[3] = {s->dx, s->dy, s->dz};
+    for (long p = 0; p < s->np; p++) {
+        double p0[3] = {x0[0][p], s->dims == 3 ? x0[1][p] : 0.0, x0[2][p]};
+        double E[3], B[3];
+        o_gather(s, p0, E, B);
+        double u[3] = {u0[0][p], u0[1][p], u0[2][p]};
+        double un[3] = {u[0], u[1], u[2]};
+        o_boris(un, E, B, s->q, s->m, s->dt);
+        double g = sqrt(1.0 + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+        double p1[3];
+        for (int a = 0; a < 3; a++) p1[a] = (a == 1 && s->dims == 2) ? 0.0 : p0[a] + s->dt * un[a] / g;
+        double lp0[3] = {0, 0, 0}, lp1[3] = {lx[0][p], s->dims == 3 ? lx[1][p] : 0.0, lx[2][p]};
+        double lvy = o_deposit_adj(s, p0, p1, un[1] / g, lJ, lp0, lp1);
+        /* move: p1 = p0 + dt v(un);  J_y used vy = un_y / g */
+        double lv[3] = {0, 0, 0};
+        for (int a = 0; a < 3; a++) {
+            if (a == 1 && s->dims == 2) continue;
+            lp0[a] += lp1[a];
+            lv[a] += s->dt * lp1[a];
+        }
+        if (s->dims == 2) lv[1] += lvy;
+        double un_dot_lv = un[0] * lv[0] + un[1] * lv[1] + un[2] * lv[2];
+        double lun[3];
+        for (int a = 0; a < 3; a++) lun[a] = lu[a][p] + lv[a] / g - un[a] * un_dot_lv / (g * g * g);
+        double luo[3], lEp[3] = {0, 0, 0}, lBp[3] = {0, 0, 0};
+        o_boris_adj(u, E, B, s->q, s->m, s->dt, lun, luo, lEp, lBp);
+        /* gather */
+        double c[3] = {p0[0] / d[0], s->dims == 3 ? p0[1] / d[1] : 0.0, p0[2] / d[2]};
+        for (int comp = 0; comp < 3; comp++) {
+            comp_orders(s, STAG_E[comp], ord);
+            interp_adj(s, s->Et[comp], lEt[comp], STAG_E[comp], ord, c, lEp[comp], lp0);
+            comp_orders(s, STAG_B[comp], ord);
+            interp_adj(s, s->Bt[comp], lBt[comp], STAG_B[comp], ord, c, lBp[comp], lp0);
+        }
+        for (int a = 0; a < 3; a++) {
+            lu[a][p] = luo[a];
+            if (a == 1 && s->dims == 2) continue;
+            lx[a][p] = lp0[a];
+        }
+    }
+    /* seen fields: lE1 += M_E lEt, lB2 += M_B lBt; gradient of the Psi_E coefficients */
+    const double *pe = s->correction ? s->psi_e : NULL;
+    const double *pb = s->correction ? s->psi_b : NULL;
+    double *t = s->tmp, *t2 = s->tmp2;
+    double *buf = s->Et[0];   /* the recomputed seen fields are no longer needed */
+    for (int c = 0; c < 3; c++) {
+        seen_one(s, c < 2 ? pe : pb, lEt[c], buf);
+        for (long q = 0; q < nc; q++) lE[c][q] += buf[q];
+        seen_one(s, pb, lBt[c], buf);
+        for (long q = 0; q < nc; q++) lB[c][q] += buf[q];
+    }
+    if (s->correction && grad) {
+        for (int c = 0; c < 2; c++) {
+            /* F lEt (filter only), then S_z^j, dotted with E1 */
+            seen_one(s, NULL, lEt[c], buf);
+            memcpy(t, buf, nc * sizeof(double));
+            for (int j = 0; j <= s->psi_deg; j++) {
+                if (j > 0) {
+                    apply_sz(s, t, t2);
+                    memcpy(t, t2, nc * sizeof(double));
+                }
+                double acc = 0.0;
+                for (long q = 0; q < nc; q++) acc += t[q] * E1[c][q];
+                grad[j] += acc;
+            }
+        }
+    }
+    /* Yee reverse */
+    double *w0 = s->Et[0], *w1 = s->Et[1], *w2 = s->Et[2];
+    double *cw[3] = {w0, w1, w2};
+    /* B2 = B1 - h Cf E1  ->  lB1 = lB2 ;  lE1 -= h Cb lB2 */
+    curl_b(s, lB, cw);
+    for (int c = 0; c < 3; c++)
+        for (long q = 0; q < nc; q++) lE[c][q] -= h * cw[c][q];
+    /* E1 = E + dt (Cb B1 - J) -> lB1 += dt Cf lE1 ; lJ = -dt lE1 ; lE = lE1 */
+    curl_f(s, lE, cw);
+    for (int c = 0; c < 3; c++)
+        for (long q = 0; q < nc; q++) {
+            lB[c][q] += s->dt * cw[c][q];
+            lJ[c][q] = -s->dt * lE[c][q];
+        }
+    /* B1 = B - h Cf E -> lB = lB1 ; lE -= h Cb lB1 */
+    curl_b(s, lB, cw);
+    for (int c = 0; c < 3; c++)
+        for (long q = 0; q < nc; q++) lE[c][q] -= h * cw[c][q];
+}
