@@ -66,6 +66,75 @@ def cpu_baseline(wl, x, u, steps):
                       % (steps, dt)}
 
 
+def batched_block(steps, warmup):
+    """64 uneven 2D instances (nx, nz in {64..512}, alpha in [0.3, 0.7], gamma in
+    {10, 50, 130}, 8 ppc, FP32): batched graph-replayed step vs one launch per
+    instance per kernel, same kernels, same GPU."""
+    import pic_inputs as pi
+    from paper_1401_0838_amd import _lib as L
+    from paper_1401_0838_amd.sim import Simulation
+    wls, parts = [], []
+    for cand in pi.batched_candidates(0):
+        rc, _, _ = L.pic_psi_coeffs(L.PIC_GALERKIN, cand["alpha"], 4)
+        if rc != L.PIC_OK:
+            continue
+        wls.append(cand)
+        parts.append(pi.load_beam(2, cand["n"], cand["ppc"], cand["gamma"], cand["sigma"], cand["seeds"][0]))
+        if len(wls) == 64:
+            break
+    n_part = sum(p[0].shape[0] for p in parts)
+    out = {"instances": len(wls), "particles": n_part,
+           "cells": sum(w["n"][0] * w["n"][1] for w in wls)}
+    for sched, graph in (("batched", True), ("plain", False)):
+        sim = Simulation(wls, parts, precision="fp32")
+        sim.set_schedule(sched, graph)
+        sim.step(warmup)
+        sim.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.synchronize()
+        dt = time.perf_counter() - t0
+        if sched == "batched":
+            prof = sim.profile(10)
+            out["batched_particle_ms"] = prof["particle_ms"]
+            out["batched_bytes_per_particle_launch"] = particle_kernel_bytes(n_part, out["cells"])
+        sim.close()
+        out[sched + "_particle_steps_per_s"] = n_part * steps / dt
+        out[sched + "_ms_per_step"] = 1e3 * dt / steps
+    out["speedup_batched_vs_plain"] = out["batched_particle_steps_per_s"] / out["plain_particle_steps_per_s"]
+    out["batched_hbm_frac"] = (out["batched_bytes_per_particle_launch"] / (out["batched_particle_ms"] * 1e-3)
+                               / 1e9 / HBM_PEAK_GBS)
+    return out
+
+
+def adjoint_block():
+    """256x256, 8 ppc, 200 steps, checkpoints every 20 (FP32): backward (recompute +
+    reverse sweep) time over forward time."""
+    import pic_inputs as pi
+    from paper_1401_0838_amd.sim import Simulation
+    wl = pi.workload("beam2d_256_adjoint")
+    x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], wl["sigma"], 0)
+    n = wl["steps"]
+    fwd = Simulation(wl, (x, u), precision="fp32")
+    fwd.step(5)
+    fwd.synchronize()
+    t0 = time.perf_counter()
+    fwd.step(n)
+    fwd.synchronize()
+    t_step = time.perf_counter() - t0
+    fwd.close()
+    sim = Simulation(wl, (x, u), precision="fp32", adjoint_steps=n, adjoint_ckpt=wl["checkpoint"])
+    t0 = time.perf_counter()
+    sim.adjoint_forward(n)
+    t_f = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sim.adjoint_backward()
+    t_b = time.perf_counter() - t0
+    sim.close()
+    return {"steps": n, "checkpoint_every": wl["checkpoint"], "forward_s": t_step,
+            "forward_with_checkpoints_s": t_f, "backward_s": t_b, "ratio": t_b / t_step}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +143,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched comparison")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost ratio")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -138,6 +209,10 @@ def main():
         "gauss_linf_rel": d["gauss_linf"] / max(d["rho_max"], 1e-300),
         "kernel_source_sha": kernel_sha(),
     }
+    if not args.no_batched:
+        out["batched"] = batched_block(max(20, args.steps // 4), 5)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_block()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, x, u, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -99,6 +99,8 @@ typedef struct pic_config {
     int    tile[3];           /* particle tile in cells along x, y, z (0 = default) */
     int    block;             /* threads per particle workgroup: 0 (default), 256 or 512 */
     int    trace_capacity;    /* steps of per-step field-energy trace kept on the device */
+    int    adjoint_steps;     /* longest gradient run pic_wperp_gradient may do (0: none) */
+    int    adjoint_ckpt;      /* checkpoint interval of gradient runs (steps, >= 1) */
 } pic_config;
 
 /* particles of one instance as host float64 arrays (structure of arrays) */
@@ -188,6 +190,26 @@ int pic_read_trace(pic_state *st, int inst, double *host_out, int max_rows, int 
 /* Run nsteps steps with HIP events around every kernel of the step and
  * report average durations.  Synchronises the stream. */
 int pic_profile(pic_state *st, int nsteps, pic_timing_t *out);
+
+/* Reverse mode: gradient of the late-time transverse field energy
+ *   W = 1/2 sum (E_x^2 + E_y^2 + B_x^2 + B_y^2) dV   after nsteps steps
+ * with respect to the Psi_E coefficients psi_e[0..psi_deg] of every instance
+ * (Sec. 2 defines Psi_E; tuning its coefficients is the use).
+ *
+ * pic_adjoint_forward runs nsteps steps from the current state, saving a
+ * checkpoint every adjoint_ckpt steps, and writes W of instance i to loss[i].
+ * Tile re-sorting is suspended until the matching backward call.  Requires
+ * correction = 1 and nsteps <= adjoint_steps for every instance.
+ *
+ * pic_adjoint_backward then runs the reverse sweep: every segment is
+ * recomputed from its checkpoint while its per-step tape is recorded, and its
+ * steps are reversed with hand-written adjoint kernels (exact transposes of
+ * the Yee update, the correction and filter stencils, the gather, the Boris
+ * push, the move and the Esirkepov deposit).  grad[i*9 + j] receives
+ * dW/dpsi_e[j] of instance i (zero for j > psi_deg).  On return the state is
+ * again the forward state after the nsteps steps.  Both calls synchronise. */
+int pic_adjoint_forward(pic_state *st, int nsteps, double *loss);
+int pic_adjoint_backward(pic_state *st, double *grad);
 
 /* Number of instances, and the total particle count over all instances. */
 int pic_info(pic_state *st, int *n_inst, int64_t *n_particles, int64_t *n_cells);

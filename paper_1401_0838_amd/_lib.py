@@ -40,7 +40,7 @@ class pic_config(C.Structure):
                 ("filter_npass", C.c_int), ("filter_w", C.c_double * 8),
                 ("q", C.c_double), ("m", C.c_double), ("weight", C.c_double),
                 ("ion_mode", C.c_int), ("tile", C.c_int * 3), ("block", C.c_int),
-                ("trace_capacity", C.c_int)]
+                ("trace_capacity", C.c_int), ("adjoint_steps", C.c_int), ("adjoint_ckpt", C.c_int)]
 
 
 class pic_particles(C.Structure):
@@ -82,6 +82,8 @@ _SIGS = {
     "pic_read_trace": (C.c_int, [C.c_void_p, C.c_int, _D, C.c_int, C.POINTER(C.c_int)]),
     "pic_profile": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(pic_timing_t)]),
     "pic_info": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "pic_adjoint_forward": (C.c_int, [C.c_void_p, C.c_int, _D]),
+    "pic_adjoint_backward": (C.c_int, [C.c_void_p, _D]),
     "pic_destroy": (None, [C.c_void_p]),
     "pic_strerror": (C.c_char_p, [C.c_int]),
     "pic_last_error": (C.c_char_p, []),
@@ -196,6 +198,20 @@ def pic_info(st):
     ni, npart, nc = C.c_int(0), C.c_int64(0), C.c_int64(0)
     check(load().pic_info(st, C.byref(ni), C.byref(npart), C.byref(nc)), "pic_info")
     return ni.value, npart.value, nc.value
+
+
+def pic_adjoint_forward(st, nsteps, n_inst):
+    import numpy as np
+    loss = np.zeros(n_inst)
+    check(load().pic_adjoint_forward(st, int(nsteps), dptr(loss)), "pic_adjoint_forward")
+    return loss
+
+
+def pic_adjoint_backward(st, n_inst):
+    import numpy as np
+    grad = np.zeros(n_inst * 9)
+    check(load().pic_adjoint_backward(st, dptr(grad)), "pic_adjoint_backward")
+    return grad.reshape(n_inst, 9)
 
 
 def pic_destroy(st):

@@ -20,7 +20,7 @@ ARCH = "gfx950"
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", INCLUDE, "-I", CSRC]
-HIP_SOURCES = ["pic_kernels.hip", "pic_host.hip"]
+HIP_SOURCES = ["pic_kernels.hip", "pic_adjoint.hip", "pic_host.hip"]
 
 
 def _run(cmd):

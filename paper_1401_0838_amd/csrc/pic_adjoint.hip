@@ -1,0 +1,713 @@
+// Reverse-mode (adjoint) kernels of the PIC step, for gradients of the
+// late-time transverse field energy with respect to the Psi_E coefficients
+// (Sec. 2 defines Psi_E; its coefficients are what gets tuned).
+//
+// The forward step maps (E, B, J, particles) through
+//   Yee:  B1 = B - h Cf E,  E1 = E + dt (Cb B1 - J - J_bg),  B2 = B1 - h Cf E1
+//   seen: Et = M_E E1, Bt = M_B B2   (Psi(S_z) composed with the filter; symmetric)
+//   particles: gather at x, Boris, move, Esirkepov deposit of J'
+// and, on the periodic Yee mesh, Cb = Cf^T.  Each kernel below is the exact
+// transpose of its forward counterpart:
+//   k_adj_particles  per tile: recompute the particle's forward step, then the
+//                    reverse of deposit, move, Boris and gather; the adjoint
+//                    of the seen fields is scattered into an LDS window
+//   k_pass           separable stencil passes applied to adjoint planes
+//   k_adj_grad       dW/da_j += <S_z^j F lambda_Et_c, E1_c>, c in {x, y}
+//   k_adj_yee_e/_b   the transposed Yee sweeps
+// Positions and their adjoints are in cell units (offsets).
+#include <hip/hip_runtime.h>
+
+#include "pic_device.h"
+#include "pic_internal.h"
+
+namespace {
+
+using namespace pic;
+
+// derivatives of the Shape weights with respect to the in-cell offset
+template <int L, class R> struct DShape;
+
+template <class R> struct DShape<1, R> {
+    static __device__ __forceinline__ void integer(R, R *w) { w[0] = R(-1); w[1] = R(1); }
+    static __device__ __forceinline__ void half(R, R *w) { w[0] = R(0); }
+};
+
+template <class R> struct DShape<3, R> {
+    static __device__ __forceinline__ void integer(R d, R *w)
+    {
+        R e = R(1) - d;
+        w[0] = R(-0.5) * e * e;
+        w[1] = R(-2) * d + R(1.5) * d * d;
+        w[2] = R(2) * e - R(1.5) * e * e;
+        w[3] = R(0.5) * d * d;
+    }
+    static __device__ __forceinline__ void half(R d, R *w)
+    {
+        w[0] = -(R(1) - d);
+        w[1] = R(-2) * (d - R(0.5));
+        w[2] = d;
+    }
+};
+
+__device__ __forceinline__ void fadd(float *p, float v) { atomicAdd(p, v); }
+__device__ __forceinline__ void fadd(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void gadd(float *p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void gadd(double *p, double v) { unsafeAtomicAdd(p, v); }
+
+// window of seen fields (read), adjoint current (read) and adjoint seen fields (accumulate)
+template <class R> struct AdjLds {
+    const R *F;    // 6 planes
+    const R *LJ;   // 3 planes
+    R *LF;         // 6 planes
+    int wx, wxy, wc;
+    __device__ __forceinline__ int at(int x, int y, int z) const { return z * wxy + y * wx + x; }
+    __device__ __forceinline__ R f(int c, int x, int y, int z) const { return F[c * wc + at(x, y, z)]; }
+    __device__ __forceinline__ R lj(int c, int x, int y, int z) const { return LJ[c * wc + at(x, y, z)]; }
+    __device__ __forceinline__ void addf(int c, int x, int y, int z, R v) { fadd(&LF[c * wc + at(x, y, z)], v); }
+};
+
+template <class R> struct AdjGlb {
+    const R *F[6];
+    const R *LJ[3];
+    R *LF[6];
+    int o[3], n[3];
+    __device__ __forceinline__ int at(int x, int y, int z) const
+    {
+        int gx = (o[0] + x) % n[0], gy = (o[1] + y) % n[1], gz = (o[2] + z) % n[2];
+        return (gz * n[1] + gy) * n[0] + gx;
+    }
+    __device__ __forceinline__ R f(int c, int x, int y, int z) const { return F[c][at(x, y, z)]; }
+    __device__ __forceinline__ R lj(int c, int x, int y, int z) const { return LJ[c][at(x, y, z)]; }
+    __device__ __forceinline__ void addf(int c, int x, int y, int z, R v) { gadd(&LF[c][at(x, y, z)], v); }
+};
+
+template <int SX, int SY, int SZ, int DIM, int L, class R, class Win>
+__device__ __forceinline__ R interp_f(const Win &W, int comp, const int *lc, const R (*wi)[L + 1], const R (*wh)[L])
+{
+    constexpr int H = (L - 1) / 2;
+    constexpr int NX = L + 1 - SX, NZ = L + 1 - SZ, NY = DIM == 3 ? L + 1 - SY : 1;
+    R s = R(0);
+#pragma unroll
+    for (int kz = 0; kz < NZ; kz++) {
+        R wz;
+        if constexpr (SZ) wz = wh[2][kz]; else wz = wi[2][kz];
+#pragma unroll
+        for (int ky = 0; ky < NY; ky++) {
+            R wy = R(1);
+            if constexpr (DIM == 3) { if constexpr (SY) wy = wh[1][ky]; else wy = wi[1][ky]; }
+            R row = R(0);
+#pragma unroll
+            for (int kx = 0; kx < NX; kx++) {
+                R wx;
+                if constexpr (SX) wx = wh[0][kx]; else wx = wi[0][kx];
+                row += wx * W.f(comp, lc[0] - H + kx, DIM == 3 ? lc[1] - H + ky : 0, lc[2] - H + kz);
+            }
+            s += wy * wz * row;
+        }
+    }
+    return s;
+}
+
+// adjoint of one gathered component: scatter w * lv, accumulate d/doffset
+template <int SX, int SY, int SZ, int DIM, int L, class R, class Win>
+__device__ __forceinline__ void interp_adj(Win &W, int comp, const int *lc, const R (*wi)[L + 1], const R (*wh)[L],
+                                           const R (*dwi)[L + 1], const R (*dwh)[L], R lv, R *lo)
+{
+    constexpr int H = (L - 1) / 2;
+    constexpr int NX = L + 1 - SX, NZ = L + 1 - SZ, NY = DIM == 3 ? L + 1 - SY : 1;
+#pragma unroll
+    for (int kz = 0; kz < NZ; kz++) {
+        R wz, dwz;
+        if constexpr (SZ) { wz = wh[2][kz]; dwz = dwh[2][kz]; } else { wz = wi[2][kz]; dwz = dwi[2][kz]; }
+#pragma unroll
+        for (int ky = 0; ky < NY; ky++) {
+            R wy = R(1), dwy = R(0);
+            if constexpr (DIM == 3) {
+                if constexpr (SY) { wy = wh[1][ky]; dwy = dwh[1][ky]; } else { wy = wi[1][ky]; dwy = dwi[1][ky]; }
+            }
+#pragma unroll
+            for (int kx = 0; kx < NX; kx++) {
+                R wx, dwx;
+                if constexpr (SX) { wx = wh[0][kx]; dwx = dwh[0][kx]; } else { wx = wi[0][kx]; dwx = dwi[0][kx]; }
+                const int x = lc[0] - H + kx, y = DIM == 3 ? lc[1] - H + ky : 0, z = lc[2] - H + kz;
+                W.addf(comp, x, y, z, wx * wy * wz * lv);
+                const R fv = W.f(comp, x, y, z) * lv;
+                lo[0] += dwx * wy * wz * fv;
+                if constexpr (DIM == 3) lo[1] += wx * dwy * wz * fv;
+                lo[2] += wx * wy * dwz * fv;
+            }
+        }
+    }
+}
+
+// Reverse of one particle's step.  loff / lu hold the adjoints of the new
+// offset / momentum on entry and of the old ones on exit.
+template <int DIM, int L, class R, class Win>
+__device__ __forceinline__ void adjoint_particle(Win &W, const int *lc, const R *off, const R *u, R *loff, R *lu,
+                                                 const R *dtd, R qdt2m, const R *cdr, R cyr)
+{
+    constexpr int H = (L - 1) / 2;
+    R wi[3][L + 1], wh[3][L], dwi[3][L + 1], dwh[3][L];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (DIM == 2 && a == 1) continue;
+        Shape<L, R>::integer(off[a], wi[a]);
+        Shape<L, R>::half(off[a], wh[a]);
+        DShape<L, R>::integer(off[a], dwi[a]);
+        DShape<L, R>::half(off[a], dwh[a]);
+    }
+    R E[3], B[3];
+    E[0] = interp_f<1, 0, 0, DIM, L, R>(W, 0, lc, wi, wh);
+    E[1] = interp_f<0, 1, 0, DIM, L, R>(W, 1, lc, wi, wh);
+    E[2] = interp_f<0, 0, 1, DIM, L, R>(W, 2, lc, wi, wh);
+    B[0] = interp_f<0, 1, 1, DIM, L, R>(W, 3, lc, wi, wh);
+    B[1] = interp_f<1, 0, 1, DIM, L, R>(W, 4, lc, wi, wh);
+    B[2] = interp_f<1, 1, 0, DIM, L, R>(W, 5, lc, wi, wh);
+    // Boris forward, keeping the intermediates
+    R um[3], t[3], sv[3], up[3], un[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) um[a] = u[a] + qdt2m * E[a];
+    const R gm = sqrt(R(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+#pragma unroll
+    for (int a = 0; a < 3; a++) t[a] = qdt2m * B[a] / gm;
+    const R f = R(2) / (R(1) + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+#pragma unroll
+    for (int a = 0; a < 3; a++) sv[a] = f * t[a];
+    up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
+    up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
+    up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
+    un[0] = um[0] + (up[1] * sv[2] - up[2] * sv[1]) + qdt2m * E[0];
+    un[1] = um[1] + (up[2] * sv[0] - up[0] * sv[2]) + qdt2m * E[1];
+    un[2] = um[2] + (up[0] * sv[1] - up[1] * sv[0]) + qdt2m * E[2];
+    const R ig = R(1) / sqrt(R(1) + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+    // move (as the forward kernel)
+    int dc[3];
+    R offn[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (DIM == 2 && a == 1) { dc[a] = 0; offn[a] = R(0); continue; }
+        R x1 = off[a] + dtd[a] * un[a] * ig;
+        int c = x1 >= R(1) ? 1 : (x1 < R(0) ? -1 : 0);
+        if (x1 >= R(2) || x1 < R(-1)) { x1 = x1 < R(0) ? R(-0.5) : R(1.5); c = x1 < R(0) ? -1 : 1; }
+        R on = x1 - R(c);
+        if (on >= R(1)) { on -= R(1); c += 1; }
+        dc[a] = c;
+        offn[a] = on;
+    }
+    // Esirkepov reverse
+    R S0[3][L + 2], S1[3][L + 2], D0[3][L + 2], D1[3][L + 2], lS0[3][L + 2], lS1[3][L + 2];
+    int base[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+#pragma unroll
+        for (int i = 0; i < L + 2; i++) { lS0[a][i] = R(0); lS1[a][i] = R(0); }
+        if (DIM == 2 && a == 1) { base[a] = 0; continue; }
+        R w0[L + 1], w1[L + 1], d0[L + 1], d1[L + 1];
+        Shape<L, R>::integer(off[a], w0);
+        Shape<L, R>::integer(offn[a], w1);
+        DShape<L, R>::integer(off[a], d0);
+        DShape<L, R>::integer(offn[a], d1);
+        const int mn = dc[a] < 0 ? -1 : 0;
+        const bool sh0 = mn < 0, sh1 = dc[a] > 0;
+        base[a] = lc[a] + mn - H;
+#pragma unroll
+        for (int i = 0; i < L + 2; i++) {
+            const int jl = i >= 1 ? i - 1 : 0, jh = i < L + 1 ? i : L;
+            const bool okl = i >= 1, okh = i < L + 1;
+            S0[a][i] = sh0 ? (okl ? w0[jl] : R(0)) : (okh ? w0[jh] : R(0));
+            D0[a][i] = sh0 ? (okl ? d0[jl] : R(0)) : (okh ? d0[jh] : R(0));
+            S1[a][i] = sh1 ? (okl ? w1[jl] : R(0)) : (okh ? w1[jh] : R(0));
+            D1[a][i] = sh1 ? (okl ? d1[jl] : R(0)) : (okh ? d1[jh] : R(0));
+        }
+    }
+    R lvy = R(0);
+    if constexpr (DIM == 2) {
+#pragma unroll
+        for (int k = 0; k < L + 2; k++) {
+            const R az = R(0.5) * (S0[2][k] + S1[2][k]);
+            R acc = R(0);
+#pragma unroll
+            for (int i = L; i >= 0; i--) {
+                acc += cdr[0] * W.lj(0, base[0] + i, 0, base[2] + k);
+                lS1[0][i] += acc * az;
+                lS0[0][i] -= acc * az;
+                const R tt = R(0.5) * acc * (S1[0][i] - S0[0][i]);
+                lS0[2][k] += tt;
+                lS1[2][k] += tt;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < L + 2; i++) {
+            const R ax = R(0.5) * (S0[0][i] + S1[0][i]);
+            R acc = R(0);
+#pragma unroll
+            for (int k = L; k >= 0; k--) {
+                acc += cdr[2] * W.lj(2, base[0] + i, 0, base[2] + k);
+                lS1[2][k] += acc * ax;
+                lS0[2][k] -= acc * ax;
+                const R tt = R(0.5) * acc * (S1[2][k] - S0[2][k]);
+                lS0[0][i] += tt;
+                lS1[0][i] += tt;
+            }
+        }
+        const R vy = un[1] * ig;
+#pragma unroll
+        for (int k = 0; k < L + 2; k++)
+#pragma unroll
+            for (int i = 0; i < L + 2; i++) {
+                const R lj = W.lj(1, base[0] + i, 0, base[2] + k);
+                const R wy = R(1.0 / 3.0) * S0[0][i] * S0[2][k] + R(1.0 / 6.0) * S1[0][i] * S0[2][k]
+                           + R(1.0 / 6.0) * S0[0][i] * S1[2][k] + R(1.0 / 3.0) * S1[0][i] * S1[2][k];
+                lvy += cyr * wy * lj;
+                const R lw = cyr * vy * lj;
+                lS0[0][i] += lw * (R(1.0 / 3.0) * S0[2][k] + R(1.0 / 6.0) * S1[2][k]);
+                lS1[0][i] += lw * (R(1.0 / 6.0) * S0[2][k] + R(1.0 / 3.0) * S1[2][k]);
+                lS0[2][k] += lw * (R(1.0 / 3.0) * S0[0][i] + R(1.0 / 6.0) * S1[0][i]);
+                lS1[2][k] += lw * (R(1.0 / 6.0) * S0[0][i] + R(1.0 / 3.0) * S1[0][i]);
+            }
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const int b = (a + 1) % 3, c = (a + 2) % 3;
+#pragma unroll
+            for (int ib = 0; ib < L + 2; ib++)
+#pragma unroll
+                for (int ic = 0; ic < L + 2; ic++) {
+                    const R tr = R(1.0 / 3.0) * S0[b][ib] * S0[c][ic] + R(1.0 / 6.0) * S1[b][ib] * S0[c][ic]
+                               + R(1.0 / 6.0) * S0[b][ib] * S1[c][ic] + R(1.0 / 3.0) * S1[b][ib] * S1[c][ic];
+                    R acc = R(0), ltr = R(0);
+#pragma unroll
+                    for (int ia = L; ia >= 0; ia--) {
+                        int nd[3];
+                        nd[a] = base[a] + ia;
+                        nd[b] = base[b] + ib;
+                        nd[c] = base[c] + ic;
+                        acc += cdr[a] * W.lj(a, nd[0], nd[1], nd[2]);
+                        lS1[a][ia] += acc * tr;
+                        lS0[a][ia] -= acc * tr;
+                        ltr += acc * (S1[a][ia] - S0[a][ia]);
+                    }
+                    lS0[b][ib] += ltr * (R(1.0 / 3.0) * S0[c][ic] + R(1.0 / 6.0) * S1[c][ic]);
+                    lS1[b][ib] += ltr * (R(1.0 / 6.0) * S0[c][ic] + R(1.0 / 3.0) * S1[c][ic]);
+                    lS0[c][ic] += ltr * (R(1.0 / 3.0) * S0[b][ib] + R(1.0 / 6.0) * S1[b][ib]);
+                    lS1[c][ic] += ltr * (R(1.0 / 6.0) * S0[b][ib] + R(1.0 / 3.0) * S1[b][ib]);
+                }
+        }
+    }
+    // shapes -> offsets; move reverse
+    R lo[3] = {R(0), R(0), R(0)}, lv[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (DIM == 2 && a == 1) continue;
+        R l0 = R(0), l1 = R(0);
+#pragma unroll
+        for (int i = 0; i < L + 2; i++) { l0 += lS0[a][i] * D0[a][i]; l1 += lS1[a][i] * D1[a][i]; }
+        const R lx1 = loff[a] + l1;
+        lo[a] = l0 + lx1;
+        lv[a] = dtd[a] * lx1;
+    }
+    if constexpr (DIM == 2) lv[1] += lvy;
+    const R udl = un[0] * lv[0] + un[1] * lv[1] + un[2] * lv[2];
+    R lun[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) lun[a] = lu[a] + lv[a] * ig - un[a] * udl * ig * ig * ig;
+    // Boris reverse
+    R lE[3], lB[3], lum[3], lup[3], ls[3], lt[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) { lE[a] = qdt2m * lun[a]; lum[a] = lun[a]; }
+    lup[0] = sv[1] * lun[2] - sv[2] * lun[1];
+    lup[1] = sv[2] * lun[0] - sv[0] * lun[2];
+    lup[2] = sv[0] * lun[1] - sv[1] * lun[0];
+    ls[0] = lun[1] * up[2] - lun[2] * up[1];
+    ls[1] = lun[2] * up[0] - lun[0] * up[2];
+    ls[2] = lun[0] * up[1] - lun[1] * up[0];
+    lum[0] += lup[0] + (t[1] * lup[2] - t[2] * lup[1]);
+    lum[1] += lup[1] + (t[2] * lup[0] - t[0] * lup[2]);
+    lum[2] += lup[2] + (t[0] * lup[1] - t[1] * lup[0]);
+    lt[0] = lup[1] * um[2] - lup[2] * um[1];
+    lt[1] = lup[2] * um[0] - lup[0] * um[2];
+    lt[2] = lup[0] * um[1] - lup[1] * um[0];
+    const R lf = ls[0] * t[0] + ls[1] * t[1] + ls[2] * t[2];
+    const R lt2 = -lf * f * f * R(0.5);
+#pragma unroll
+    for (int a = 0; a < 3; a++) lt[a] += f * ls[a] + R(2) * t[a] * lt2;
+    const R lg = -(t[0] * lt[0] + t[1] * lt[1] + t[2] * lt[2]) / gm;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        lB[a] = qdt2m * lt[a] / gm;
+        lum[a] += lg * um[a] / gm;
+        lE[a] += qdt2m * lum[a];
+        lu[a] = lum[a];
+    }
+    // gather reverse
+    interp_adj<1, 0, 0, DIM, L, R>(W, 0, lc, wi, wh, dwi, dwh, lE[0], lo);
+    interp_adj<0, 1, 0, DIM, L, R>(W, 1, lc, wi, wh, dwi, dwh, lE[1], lo);
+    interp_adj<0, 0, 1, DIM, L, R>(W, 2, lc, wi, wh, dwi, dwh, lE[2], lo);
+    interp_adj<0, 1, 1, DIM, L, R>(W, 3, lc, wi, wh, dwi, dwh, lB[0], lo);
+    interp_adj<1, 0, 1, DIM, L, R>(W, 4, lc, wi, wh, dwi, dwh, lB[1], lo);
+    interp_adj<1, 1, 0, DIM, L, R>(W, 5, lc, wi, wh, dwi, dwh, lB[2], lo);
+#pragma unroll
+    for (int a = 0; a < 3; a++) loff[a] = lo[a];
+}
+
+template <int DIM, int L, class R>
+__global__ void __launch_bounds__(256) k_adj_particles(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                                       int nwork, int wmx, int wmy, int wmz)
+{
+    constexpr int JL = (L + 1) / 2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int tid = threadIdx.x, bs = blockDim.x;
+    const int wcmax = wmx * wmy * wmz;
+    for (int item = blockIdx.x; item < nwork; item += gridDim.x) {
+        const int inst = work[item].x, tile = work[item].y;
+        const InstDesc &D = Dt[inst];
+        const int p0 = D.tstart[tile], p1 = D.tstart[tile + 1];
+        if (p1 <= p0) continue;
+        int lo[3], o[3], wn[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            lo[a] = D.tbox[tile * 6 + a];
+            const int ext = D.tbox[tile * 6 + 3 + a];
+            if (DIM == 2 && a == 1) { o[a] = 0; wn[a] = 1; continue; }
+            o[a] = wrapi(lo[a] - JL, D.n[a]);
+            wn[a] = ext + L + 2;
+        }
+        const bool fits = wn[0] <= wmx && wn[1] <= wmy && wn[2] <= wmz;
+        const int wc = wn[0] * wn[1] * wn[2];
+        R *sF = reinterpret_cast<R *>(smem);
+        R *sLJ = sF + 6 * wcmax;
+        R *sLF = sLJ + 3 * wcmax;
+        if (fits) {
+            const R *src[6] = {(const R *)D.Et[0], (const R *)D.Et[1], (const R *)D.Et[2],
+                               (const R *)D.Bt[0], (const R *)D.Bt[1], (const R *)D.Bt[2]};
+            const R *lsrc[3] = {(const R *)D.lJ[0], (const R *)D.lJ[1], (const R *)D.lJ[2]};
+            for (int c = tid; c < wc; c += bs) {
+                const int x = c % wn[0], r = c / wn[0];
+                const int y = r % wn[1], z = r / wn[1];
+                const int g = (((o[2] + z) % D.n[2]) * D.n[1] + (o[1] + y) % D.n[1]) * D.n[0] + (o[0] + x) % D.n[0];
+#pragma unroll
+                for (int k = 0; k < 6; k++) { sF[k * wc + c] = src[k][g]; sLF[k * wc + c] = R(0); }
+#pragma unroll
+                for (int k = 0; k < 3; k++) sLJ[k * wc + c] = lsrc[k][g];
+            }
+        }
+        __syncthreads();
+        const R dtd[3] = {(R)D.dtd[0], (R)D.dtd[1], (R)D.dtd[2]};
+        const R cdr[3] = {(R)D.cdep_r[0], (R)D.cdep_r[1], (R)D.cdep_r[2]};
+        const R qdt2m = (R)D.qdt2m, cyr = (R)D.cy2d_r;
+        AdjLds<R> lw{sF, sLJ, sLF, wn[0], wn[0] * wn[1], wc};
+        AdjGlb<R> gw;
+        if (!fits) {
+            for (int k = 0; k < 3; k++) {
+                gw.F[k] = (const R *)D.Et[k]; gw.F[3 + k] = (const R *)D.Bt[k];
+                gw.LJ[k] = (const R *)D.lJ[k];
+                gw.LF[k] = (R *)D.lEt[k]; gw.LF[3 + k] = (R *)D.lBt[k];
+                gw.o[k] = o[k]; gw.n[k] = D.n[k];
+            }
+        }
+        for (int p = p0 + tid; p < p1; p += bs) {
+            const int idx = D.pidx[p];
+            int c[3];
+            c[0] = idx % D.n[0];
+            const int r = idx / D.n[0];
+            c[1] = r % D.n[1];
+            c[2] = r / D.n[1];
+            int lc[3];
+            R off[3], u[3], loff[3], lu[3];
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                u[a] = ((const R *)D.pu[a])[p];
+                lu[a] = ((const R *)D.lu[a])[p];
+                if (DIM == 2 && a == 1) { lc[a] = 0; off[a] = R(0); loff[a] = R(0); continue; }
+                int rel = c[a] - lo[a];
+                rel += rel < 0 ? D.n[a] : 0;
+                lc[a] = rel + JL;
+                off[a] = ((const R *)D.poff[a])[p];
+                loff[a] = ((const R *)D.loff[a])[p];
+            }
+            if (fits) adjoint_particle<DIM, L, R>(lw, lc, off, u, loff, lu, dtd, qdt2m, cdr, cyr);
+            else adjoint_particle<DIM, L, R>(gw, lc, off, u, loff, lu, dtd, qdt2m, cdr, cyr);
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                ((R *)D.lu[a])[p] = lu[a];
+                if (!(DIM == 2 && a == 1)) ((R *)D.loff[a])[p] = loff[a];
+            }
+        }
+        __syncthreads();
+        if (fits) {
+            R *dst[6] = {(R *)D.lEt[0], (R *)D.lEt[1], (R *)D.lEt[2], (R *)D.lBt[0], (R *)D.lBt[1], (R *)D.lBt[2]};
+            for (int c = tid; c < wc; c += bs) {
+                const int x = c % wn[0], r = c / wn[0];
+                const int y = r % wn[1], z = r / wn[1];
+                const int g = (((o[2] + z) % D.n[2]) * D.n[1] + (o[1] + y) % D.n[1]) * D.n[0] + (o[0] + x) % D.n[0];
+#pragma unroll
+                for (int k = 0; k < 6; k++) {
+                    const R v = sLF[k * wc + c];
+                    if (v != R(0)) gadd(&dst[k][g], v);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ stencil passes
+enum { PL_EB = 0, PL_T1 = 1, PL_T2 = 2, PL_SEEN = 3, PL_LSEEN = 4, PL_LEB = 5 };
+
+__device__ __forceinline__ void *plane(const InstDesc &D, int sel, int comp)
+{
+    switch (sel) {
+    case PL_EB: return comp < 3 ? D.E[comp] : D.B[comp - 3];
+    case PL_T1: return D.T1[comp];
+    case PL_T2: return D.T2[comp];
+    case PL_SEEN: return comp < 3 ? D.Et[comp] : D.Bt[comp - 3];
+    case PL_LSEEN: return comp < 3 ? D.lEt[comp] : D.lBt[comp - 3];
+    default: return comp < 3 ? D.lE[comp] : D.lB[comp - 3];
+    }
+}
+
+// AXIS 2 with filter_only = 0 uses the per-component correction taps;
+// filter_only = 1 uses the filter taps alone.  accumulate adds into dst.
+template <int AXIS, class R>
+__global__ void __launch_bounds__(256) k_pass(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                              int src_sel, int dst_sel, int filter_only, int accumulate)
+{
+    const InstDesc &D = Dt[work[blockIdx.x].x];
+    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    const int comp = blockIdx.y;
+    if (cell >= D.ncell) return;
+    const R *src = (const R *)plane(D, src_sel, comp);
+    R *dst = (R *)plane(D, dst_sel, comp);
+    const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
+    const int i = cell % nx, r = cell / nx, j = r % ny, k = r / ny;
+    R acc = R(0);
+    if constexpr (AXIS == 2) {
+        const double *tap = filter_only ? D.tzf : D.tz[comp < 2 ? 0 : 1];
+        const int h = filter_only ? D.hzf : D.hz;
+        const int rowoff = i + j * nx, pl = nx * ny;
+        for (int t = -h; t <= h; t++) {
+            int kk = k + t;
+            kk = ((kk % nz) + nz) % nz;
+            acc += (R)tap[t + h] * src[rowoff + kk * pl];
+        }
+    } else if constexpr (AXIS == 0) {
+        const int h = D.hx, rowbase = cell - i;
+        for (int t = -h; t <= h; t++) {
+            int ii = i + t;
+            ii = ((ii % nx) + nx) % nx;
+            acc += (R)D.tx[t + h] * src[rowbase + ii];
+        }
+    } else {
+        const int h = D.hy, base = i + k * ny * nx;
+        for (int t = -h; t <= h; t++) {
+            int jj = j + t;
+            jj = ((jj % ny) + ny) % ny;
+            acc += (R)D.ty[t + h] * src[base + jj * nx];
+        }
+    }
+    if (accumulate) dst[cell] += acc;
+    else dst[cell] = acc;
+}
+
+// dW/da_j += <S_z^j Lambda_c, E1_c> with Lambda_c = F lambda_Et_c (c = blockIdx.y in {0,1})
+template <class R>
+__global__ void __launch_bounds__(256) k_adj_grad(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                                  int lam_sel)
+{
+    const InstDesc &D = Dt[work[blockIdx.x].x];
+    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    const int comp = blockIdx.y;
+    double v[9];
+    for (int j = 0; j < 9; j++) v[j] = 0.0;
+    if (cell < D.ncell) {
+        const R *lam = (const R *)plane(D, lam_sel, comp);
+        const double e1 = (double)((const R *)D.E[comp])[cell];
+        const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
+        const int i = cell % nx, r = cell / nx, j0 = r % ny, k = r / ny;
+        const int rowoff = i + j0 * nx, pl = nx * ny;
+        for (int j = 0; j <= D.psi_deg; j++) {
+            double s = 0.0;
+            for (int t = -j; t <= j; t++) {
+                int kk = k + t;
+                kk = ((kk % nz) + nz) % nz;
+                s += D.sj[j][8 + t] * (double)lam[rowoff + kk * pl];
+            }
+            v[j] = s * e1;
+        }
+    }
+    for (int j = 0; j < 9; j++) {
+        if (j > D.psi_deg) break;
+        const double w = wave_sum(v[j]);
+        if ((threadIdx.x & 63) == 0 && w != 0.0) unsafeAtomicAdd(&D.grad[j], w);
+    }
+}
+
+// lambda_E -= h Cb lambda_B  (backward differences, B locations -> E locations)
+template <int DIM, class R>
+__global__ void __launch_bounds__(256) k_adj_yee_e(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    const InstDesc &D = Dt[work[blockIdx.x].x];
+    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    if (cell >= D.ncell) return;
+    const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
+    const int i = cell % nx, r = cell / nx, j = r % ny, k = r / ny;
+    const int im = (i == 0 ? nx - 1 : i - 1) + (j + k * ny) * nx;
+    const int km = i + (j + (k == 0 ? nz - 1 : k - 1) * ny) * nx;
+    const R *Bx = (const R *)D.lB[0], *By = (const R *)D.lB[1], *Bz = (const R *)D.lB[2];
+    const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], h = R(0.5) * (R)D.dt;
+    const R bx = Bx[cell], by = By[cell], bz = Bz[cell];
+    R dyBz = R(0), dyBx = R(0);
+    if constexpr (DIM == 3) {
+        const int jm = i + ((j == 0 ? ny - 1 : j - 1) + k * ny) * nx;
+        const R idy = R(1) / (R)D.d[1];
+        dyBz = (bz - Bz[jm]) * idy;
+        dyBx = (bx - Bx[jm]) * idy;
+    }
+    ((R *)D.lE[0])[cell] -= h * (dyBz - (by - By[km]) * idz);
+    ((R *)D.lE[1])[cell] -= h * ((bx - Bx[km]) * idz - (bz - Bz[im]) * idx);
+    ((R *)D.lE[2])[cell] -= h * ((by - By[im]) * idx - dyBx);
+}
+
+// lambda_B += dt Cf lambda_E (forward differences);  lambda_J = -dt lambda_E
+template <int DIM, class R>
+__global__ void __launch_bounds__(256) k_adj_yee_b(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    const InstDesc &D = Dt[work[blockIdx.x].x];
+    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    if (cell >= D.ncell) return;
+    const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
+    const int i = cell % nx, r = cell / nx, j = r % ny, k = r / ny;
+    const int ip = (i + 1 == nx ? 0 : i + 1) + (j + k * ny) * nx;
+    const int kp = i + (j + (k + 1 == nz ? 0 : k + 1) * ny) * nx;
+    const R *Ex = (const R *)D.lE[0], *Ey = (const R *)D.lE[1], *Ez = (const R *)D.lE[2];
+    const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt;
+    const R ex = Ex[cell], ey = Ey[cell], ez = Ez[cell];
+    R dyEz = R(0), dyEx = R(0);
+    if constexpr (DIM == 3) {
+        const int jp = i + ((j + 1 == ny ? 0 : j + 1) + k * ny) * nx;
+        const R idy = R(1) / (R)D.d[1];
+        dyEz = (Ez[jp] - ez) * idy;
+        dyEx = (Ex[jp] - ex) * idy;
+    }
+    ((R *)D.lB[0])[cell] += dt * (dyEz - (Ey[kp] - ey) * idz);
+    ((R *)D.lB[1])[cell] += dt * ((Ex[kp] - ex) * idz - (Ez[ip] - ez) * idx);
+    ((R *)D.lB[2])[cell] += dt * ((Ey[ip] - ey) * idx - dyEx);
+    ((R *)D.lJ[0])[cell] = -dt * ex;
+    ((R *)D.lJ[1])[cell] = -dt * ey;
+    ((R *)D.lJ[2])[cell] = -dt * ez;
+}
+
+// loss W and its gradient seed lambda_E = dV (Ex, Ey, 0), lambda_B = dV (Bx, By, 0)
+template <class R>
+__global__ void __launch_bounds__(256) k_adj_seed(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    const InstDesc &D = Dt[work[blockIdx.x].x];
+    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    double w = 0.0;
+    if (cell < D.ncell) {
+        const R dV = (R)D.dV;
+        for (int c = 0; c < 3; c++) {
+            const R e = ((const R *)D.E[c])[cell], b = ((const R *)D.B[c])[cell];
+            ((R *)D.lE[c])[cell] = c < 2 ? dV * e : R(0);
+            ((R *)D.lB[c])[cell] = c < 2 ? dV * b : R(0);
+            ((R *)D.lJ[c])[cell] = R(0);
+            if (c < 2) w += 0.5 * D.dV * ((double)e * e + (double)b * b);
+        }
+    }
+    w = wave_sum(w);
+    if ((threadIdx.x & 63) == 0 && w != 0.0) unsafeAtomicAdd(D.loss, w);
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_adj_seed_particles(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    const InstDesc &D = Dt[work[blockIdx.x].x];
+    const long long p = (long long)work[blockIdx.x].y * PIC_PART_CHUNK + threadIdx.x;
+    if (p >= D.np) return;
+    for (int a = 0; a < 3; a++) {
+        ((R *)D.lu[a])[p] = R(0);
+        if (D.loff[a]) ((R *)D.loff[a])[p] = R(0);
+    }
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_zero_lseen(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    const InstDesc &D = Dt[work[blockIdx.x].x];
+    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    if (cell >= D.ncell) return;
+    for (int c = 0; c < 3; c++) { ((R *)D.lEt[c])[cell] = R(0); ((R *)D.lBt[c])[cell] = R(0); }
+}
+
+inline int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : -1; }
+
+}  // namespace
+
+#define DISPATCH_R(fp32, ...) \
+    do { if (fp32) { typedef float R; __VA_ARGS__; } else { typedef double R; __VA_ARGS__; } } while (0)
+
+size_t adjoint_smem_bytes(int dims, int fp32, const int wmax[3])
+{
+    const size_t wc = (size_t)wmax[0] * (dims == 3 ? wmax[1] : 1) * wmax[2];
+    return wc * 15 * (fp32 ? 4 : 8);
+}
+
+int launch_adj_seed(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *cwork, int ncwork)
+{
+    DISPATCH_R(c.fp32, {
+        if (nfwork > 0) k_adj_seed<R><<<dim3(nfwork), dim3(PIC_FIELD_CHUNK), 0, c.stream>>>(c.desc, fwork);
+        if (ncwork > 0) k_adj_seed_particles<R><<<dim3(ncwork), dim3(PIC_PART_CHUNK), 0, c.stream>>>(c.desc, cwork);
+    });
+    return hip_ok(hipGetLastError());
+}
+
+// Reverse of one step.  `tape` addresses this step's E1, B2, particles and
+// tile boxes; `live` the shared planes (identical for everything else).
+int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fwork, int nfwork, const int2 *pwork,
+                    int npwork, int block, const int wmax[3])
+{
+    if (launch_seen(tape, fwork, nfwork)) return -1;      // Et, Bt of this step
+    const int wm[3] = {wmax[0], live.dims == 3 ? wmax[1] : 1, wmax[2]};
+    const size_t smem = adjoint_smem_bytes(live.dims, live.fp32, wm);
+    const dim3 gf(nfwork), g6(nfwork, 6), g2(nfwork, 2), bf(PIC_FIELD_CHUNK);
+    hipStream_t st = live.stream;
+#define AK(D_, L_) k_adj_particles<D_, L_, R><<<dim3(npwork), dim3(block), smem, st>>>(tape.desc, pwork, npwork, wm[0], wm[1], wm[2])
+    DISPATCH_R(live.fp32, {
+        k_zero_lseen<R><<<gf, bf, 0, st>>>(live.desc, fwork);
+        if (npwork > 0) {
+            if (live.dims == 2 && live.order == 1) AK(2, 1);
+            else if (live.dims == 2 && live.order == 3) AK(2, 3);
+            else if (live.dims == 3 && live.order == 1) AK(3, 1);
+            else AK(3, 3);
+        }
+        // lambda_E += M_E lambda_Et, lambda_B += M_B lambda_Bt
+        k_pass<2, R><<<g6, bf, 0, st>>>(live.desc, fwork, PL_LSEEN, PL_T1, 0, 0);
+        if (live.dims == 2) {
+            k_pass<0, R><<<g6, bf, 0, st>>>(live.desc, fwork, PL_T1, PL_LEB, 0, 1);
+        } else {
+            k_pass<0, R><<<g6, bf, 0, st>>>(live.desc, fwork, PL_T1, PL_T2, 0, 0);
+            k_pass<1, R><<<g6, bf, 0, st>>>(live.desc, fwork, PL_T2, PL_LEB, 0, 1);
+        }
+        // gradient: F lambda_Et_c (filter only), then <S^j ., E1_c>
+        k_pass<2, R><<<g2, bf, 0, st>>>(live.desc, fwork, PL_LSEEN, PL_T1, 1, 0);
+        k_pass<0, R><<<g2, bf, 0, st>>>(live.desc, fwork, PL_T1, PL_T2, 0, 0);
+        int lam = PL_T2;
+        if (live.dims == 3) {
+            k_pass<1, R><<<g2, bf, 0, st>>>(live.desc, fwork, PL_T2, PL_T1, 0, 0);
+            lam = PL_T1;
+        }
+        k_adj_grad<R><<<g2, bf, 0, st>>>(tape.desc, fwork, lam);
+        // transposed Yee
+        if (live.dims == 2) {
+            k_adj_yee_e<2, R><<<gf, bf, 0, st>>>(live.desc, fwork);
+            k_adj_yee_b<2, R><<<gf, bf, 0, st>>>(live.desc, fwork);
+            k_adj_yee_e<2, R><<<gf, bf, 0, st>>>(live.desc, fwork);
+        } else {
+            k_adj_yee_e<3, R><<<gf, bf, 0, st>>>(live.desc, fwork);
+            k_adj_yee_b<3, R><<<gf, bf, 0, st>>>(live.desc, fwork);
+            k_adj_yee_e<3, R><<<gf, bf, 0, st>>>(live.desc, fwork);
+        }
+    });
+#undef AK
+    return hip_ok(hipGetLastError());
+}

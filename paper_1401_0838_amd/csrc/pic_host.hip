@@ -33,6 +33,14 @@ int fail(int code, const std::string &msg)
 
 struct Range { int off, n; };
 
+// device copies of the state an adjoint run needs to restore or replay
+struct Snap {
+    void *E[3] = {nullptr, nullptr, nullptr}, *B[3] = {nullptr, nullptr, nullptr};
+    void *J[3] = {nullptr, nullptr, nullptr};
+    int *pidx = nullptr, *tbox = nullptr;
+    void *poff[3] = {nullptr, nullptr, nullptr}, *pu[3] = {nullptr, nullptr, nullptr};
+};
+
 struct Layout {
     size_t bytes = 0;
     char *base = nullptr;
@@ -98,6 +106,7 @@ int validate(const pic_config &c, int idx)
     if (c.ion_mode != PIC_IONS_CHARGE && c.ion_mode != PIC_IONS_CHARGE_AND_CURRENT) return bad(PIC_EINVAL, "ion_mode");
     if (c.block != 0 && c.block != 256 && c.block != 512) return bad(PIC_EINVAL, "block must be 0, 256 or 512");
     if (c.trace_capacity < 0) return bad(PIC_EINVAL, "trace_capacity");
+    if (c.adjoint_steps < 0 || (c.adjoint_steps > 0 && c.adjoint_ckpt < 1)) return bad(PIC_EINVAL, "adjoint sizes");
     return PIC_OK;
 }
 
@@ -157,7 +166,13 @@ struct pic_state {
     int *trace_pos = nullptr;
     double *trace = nullptr;
     int trace_cap = 0;
-    int *h_flags_tmp = nullptr;
+    // reverse mode
+    int adj_steps = 0, adj_k = 0;
+    bool no_resort = false;
+    int adj_pending = 0;                         // steps of the last pic_adjoint_forward
+    std::vector<std::vector<Snap>> ckpt, tape;   // [instance][slot]
+    InstDesc *d_tape_desc = nullptr;             // adj_k * n_inst descriptors
+    int adj_wmax[3] = {1, 1, 1};
 };
 
 namespace {
@@ -203,6 +218,10 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
     for (int i = 0; i < n_inst; i++) cap = std::max(cap, cfgs[i].trace_capacity);
     double *tr = L.take<double>((size_t)std::max(cap, 1) * n_inst * 6);
     if (s) { s->trace = tr; s->trace_cap = cap; }
+    if (cfgs[0].adjoint_steps > 0) {
+        InstDesc *td = L.take<InstDesc>((size_t)cfgs[0].adjoint_ckpt * n_inst);
+        if (s) s->d_tape_desc = td;
+    }
     for (int i = 0; i < n_inst; i++) {
         const pic_config &c = cfgs[i];
         const size_t ncell = (size_t)c.nx * c.ny * c.nz;
@@ -213,9 +232,10 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
             void *e = plane(R), *b = plane(R), *et = plane(R), *bt = plane(R), *j = plane(8);
             if (D) { D->E[k] = e; D->B[k] = b; D->Et[k] = et; D->Bt[k] = bt; D->J[k] = j; }
         }
+        const bool adj = c.adjoint_steps > 0;
         for (int k = 0; k < 6; k++) {
             void *t1 = plane(R);
-            void *t2 = c.dims == 3 ? plane(R) : nullptr;
+            void *t2 = (c.dims == 3 || adj) ? plane(R) : nullptr;
             if (D) { D->T1[k] = t1; D->T2[k] = t2; }
         }
         double *r0 = L.take<double>(ncell), *r1 = L.take<double>(ncell);
@@ -231,6 +251,40 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
         int *tcount = L.take<int>(ntiles[i]);
         int *flags = L.take<int>(FLAG_COUNT);
         double *diag = L.take<double>(DG_COUNT);
+        if (adj) {
+            const int K = c.adjoint_ckpt;
+            const int nck = (c.adjoint_steps + K - 1) / K + 1;
+            for (int k = 0; k < 3; k++) {
+                void *a = plane(R), *b = plane(R), *j = plane(R), *e = plane(R), *f = plane(R);
+                if (D) { D->lE[k] = a; D->lB[k] = b; D->lJ[k] = j; D->lEt[k] = e; D->lBt[k] = f; }
+            }
+            for (int a = 0; a < 3; a++) {
+                void *lo = (c.dims == 2 && a == 1) ? nullptr : (void *)L.take<char>(n * R);
+                void *lu = L.take<char>(n * R);
+                if (D) { D->loff[a] = lo; D->lu[a] = lu; }
+            }
+            double *g = L.take<double>(16);
+            if (D) { D->grad = g; D->loss = g + 9; }
+            auto snap = [&](bool with_j) {
+                Snap sn;
+                for (int k = 0; k < 3; k++) {
+                    sn.E[k] = plane(R);
+                    sn.B[k] = plane(R);
+                    if (with_j) sn.J[k] = plane(8);
+                }
+                sn.pidx = L.take<int>(n);
+                for (int a = 0; a < 3; a++) {
+                    if (!(c.dims == 2 && a == 1)) sn.poff[a] = L.take<char>(n * R);
+                    sn.pu[a] = L.take<char>(n * R);
+                }
+                sn.tbox = L.take<int>((size_t)ntiles[i] * 6);
+                return sn;
+            };
+            std::vector<Snap> ck, tp;
+            for (int k = 0; k < nck; k++) ck.push_back(snap(true));
+            for (int k = 0; k < K; k++) tp.push_back(snap(false));
+            if (s) { s->ckpt.push_back(ck); s->tape.push_back(tp); }
+        }
         if (D) {
             D->rho0 = r0; D->rho = r1;
             D->pidx = pidx; D->ppid = ppid; D->sidx = sidx; D->spid = spid; D->srank = srank; D->stile = stile;
@@ -294,6 +348,19 @@ void fill_desc(InstDesc &D, const pic_config &c, const pic_particles &p)
     std::memset(D.ty, 0, sizeof D.ty);
     for (size_t t = 0; t < ze.size(); t++) { D.tz[0][t] = ze[t]; D.tz[1][t] = zb[t]; }
     for (size_t t = 0; t < fz.size(); t++) { D.tx[t] = fz[t]; D.ty[t] = fz[t]; }
+    // reverse mode: filter-only z taps, taps of S_z^j, unscaled deposit factors
+    std::memset(D.tzf, 0, sizeof D.tzf);
+    D.hzf = (int)(fz.size() / 2);
+    for (size_t t = 0; t < fz.size(); t++) D.tzf[t] = fz[t];
+    D.psi_deg = c.correction ? c.psi_deg : 0;
+    std::memset(D.sj, 0, sizeof D.sj);
+    std::vector<double> pw = {1.0};
+    for (int j = 0; j <= 8; j++) {
+        for (size_t t = 0; t < pw.size(); t++) D.sj[j][8 - j + t] = pw[t];
+        pw = conv(pw, {-0.25, 0.5, -0.25});
+    }
+    for (int a = 0; a < 3; a++) D.cdep_r[a] = -qw * D.d[a] / (c.cdt * D.dV);
+    D.cy2d_r = qw / D.dV;
 }
 
 template <class R>
@@ -376,6 +443,37 @@ int upload_particles(pic_state *s, int inst, const pic_particles &p)
     return PIC_OK;
 }
 
+// particle arrays and tile boxes of one instance to (save) or from a snapshot
+int snap_copy_particles(pic_state *s, int inst, const Snap &sn, bool save)
+{
+    const InstDesc &D = s->desc[inst];
+    const size_t R = s->fp32 ? 4 : 8, n = (size_t)D.np;
+    const hipMemcpyKind kd = hipMemcpyDeviceToDevice;
+    auto cp = [&](void *live, void *snapp, size_t bytes) {
+        if (!bytes || !live || !snapp) return hipSuccess;
+        return save ? hipMemcpyAsync(snapp, live, bytes, kd, s->stream) : hipMemcpyAsync(live, snapp, bytes, kd, s->stream);
+    };
+    HIP_TRY(cp(D.pidx, sn.pidx, n * 4));
+    for (int a = 0; a < 3; a++) {
+        HIP_TRY(cp(D.poff[a], sn.poff[a], n * R));
+        HIP_TRY(cp(D.pu[a], sn.pu[a], n * R));
+    }
+    HIP_TRY(cp(D.tbox, sn.tbox, (size_t)D.ntiles * 6 * 4));
+    return PIC_OK;
+}
+
+// E and B of one instance into a snapshot
+int snap_copy_fields(pic_state *s, int inst, const Snap &sn)
+{
+    const InstDesc &D = s->desc[inst];
+    const size_t bytes = (size_t)D.ncell * (s->fp32 ? 4 : 8);
+    for (int c = 0; c < 3; c++) {
+        HIP_TRY(hipMemcpyAsync(sn.E[c], D.E[c], bytes, hipMemcpyDeviceToDevice, s->stream));
+        HIP_TRY(hipMemcpyAsync(sn.B[c], D.B[c], bytes, hipMemcpyDeviceToDevice, s->stream));
+    }
+    return PIC_OK;
+}
+
 // XCD-aware order of one instance's tiles: launch slot b runs on XCD b % 8,
 // so give each XCD a contiguous run of tiles (their halos share that XCD's L2)
 void tile_order(int nt, std::vector<int> &out)
@@ -453,6 +551,7 @@ int enqueue_step(pic_state *s)
 
 int enqueue_resort(pic_state *s)
 {
+    if (s->no_resort) return PIC_OK;
     LaunchCtx c = ctx(s);
     if (s->sched == PIC_SCHED_BATCHED) {
         if (launch_resort(c, s->cwork, s->ncwork, 0, s->n_inst)) return fail(PIC_EHIP, "resort launch");
@@ -580,8 +679,9 @@ extern "C" int pic_plan(const pic_config *cfgs, int n_inst, const int64_t *n_par
         int rc = validate(cfgs[i], i);
         if (rc) return rc;
         if (cfgs[i].dims != cfgs[0].dims || cfgs[i].precision != cfgs[0].precision ||
-            cfgs[i].shape_order != cfgs[0].shape_order)
-            return fail(PIC_EINVAL, "all instances must share dims, precision and shape_order");
+            cfgs[i].shape_order != cfgs[0].shape_order || cfgs[i].adjoint_steps != cfgs[0].adjoint_steps ||
+            (cfgs[0].adjoint_steps > 0 && cfgs[i].adjoint_ckpt != cfgs[0].adjoint_ckpt))
+            return fail(PIC_EINVAL, "all instances must share dims, precision, shape_order and adjoint sizes");
         if (n_particles[i] < 0 || n_particles[i] > INT32_MAX) return fail(PIC_EINVAL, "particle count");
     }
     *arena_bytes = layout(nullptr, cfgs, n_inst, n_particles, nullptr);
@@ -627,6 +727,7 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
     }
     auto bail = [&](int code) { pic_destroy(s); return code; };
     layout(s, cfgs, n_inst, np.data(), s->arena);
+    if (hipMemsetAsync(s->arena, 0, need - 256, s->stream) != hipSuccess) return bail(fail(PIC_EHIP, "arena clear"));
     s->block = cfgs[0].block ? cfgs[0].block : default_block();
     // largest LDS window over the instances
     int maxsm = 0;
@@ -652,7 +753,37 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
         (void)maxsm;
     }
     for (int i = 0; i < n_inst; i++) s->desc[i].trace = s->trace;
-    if (hipMemsetAsync(s->arena, 0, need - 256, s->stream) != hipSuccess) return bail(fail(PIC_EHIP, "arena clear"));
+    if (cfgs[0].adjoint_steps > 0) {
+        s->adj_steps = cfgs[0].adjoint_steps;
+        s->adj_k = cfgs[0].adjoint_ckpt;
+        for (int a = 0; a < 3; a++) s->adj_wmax[a] = s->wmax[a];
+        while (adjoint_smem_bytes(s->dims, s->fp32, s->adj_wmax) > (size_t)maxsm) {
+            bool shrunk = false;
+            for (int a = 0; a < 3; a++)
+                if (!(s->dims == 2 && a == 1) && s->adj_wmax[a] > s->order + 3) { s->adj_wmax[a]--; shrunk = true; }
+            if (!shrunk) return bail(fail(PIC_EINVAL, "adjoint tile window does not fit in LDS"));
+        }
+        // one descriptor table per tape slot: E/B, particles and tile boxes of that slot
+        std::vector<InstDesc> td((size_t)s->adj_k * n_inst);
+        for (int k = 0; k < s->adj_k; k++)
+            for (int i = 0; i < n_inst; i++) {
+                InstDesc d = s->desc[i];
+                const Snap &sn = s->tape[i][k];
+                for (int c = 0; c < 3; c++) {
+                    d.E[c] = sn.E[c];
+                    d.B[c] = sn.B[c];
+                    d.poff[c] = sn.poff[c];
+                    d.pu[c] = sn.pu[c];
+                }
+                d.pidx = sn.pidx;
+                d.tbox = sn.tbox;
+                td[(size_t)k * n_inst + i] = d;
+            }
+        if (hipMemcpyAsync(s->d_tape_desc, td.data(), td.size() * sizeof(InstDesc), hipMemcpyHostToDevice,
+                           s->stream) != hipSuccess ||
+            hipStreamSynchronize(s->stream) != hipSuccess)
+            return bail(fail(PIC_EHIP, "tape descriptor upload"));
+    }
     if (hipMemcpyAsync(s->d_desc, s->desc.data(), n_inst * sizeof(InstDesc), hipMemcpyHostToDevice, s->stream) !=
         hipSuccess)
         return bail(fail(PIC_EHIP, "descriptor upload"));
@@ -841,6 +972,124 @@ extern "C" int pic_profile(pic_state *s, int nsteps, pic_timing_t *out)
     out->resort_ms = nres ? acc[3] / nres : 0.0;
     out->step_ms = total / nsteps;
     out->steps = nsteps;
+    return PIC_OK;
+}
+
+namespace {
+
+int snap_copy(pic_state *s, int inst, const Snap &sn, bool save, bool with_j)
+{
+    const InstDesc &D = s->desc[inst];
+    const size_t R = s->fp32 ? 4 : 8, nc = (size_t)D.ncell, n = (size_t)D.np;
+    const hipMemcpyKind kd = hipMemcpyDeviceToDevice;
+    auto cp = [&](void *live, void *snapp, size_t bytes) {
+        if (!bytes || !live || !snapp) return hipSuccess;
+        return save ? hipMemcpyAsync(snapp, live, bytes, kd, s->stream) : hipMemcpyAsync(live, snapp, bytes, kd, s->stream);
+    };
+    for (int c = 0; c < 3; c++) {
+        HIP_TRY(cp(D.E[c], sn.E[c], nc * R));
+        HIP_TRY(cp(D.B[c], sn.B[c], nc * R));
+        if (with_j) HIP_TRY(cp(D.J[c], sn.J[c], nc * 8));
+    }
+    return snap_copy_particles(s, inst, sn, save);
+}
+
+}  // namespace
+
+namespace {
+
+int gradient_preconditions(pic_state *s)
+{
+    if (s->adj_steps <= 0) return fail(PIC_ESTATE, "gradient runs were not planned (adjoint_steps = 0)");
+    for (int i = 0; i < s->n_inst; i++)
+        if (!s->cfg[i].correction) return fail(PIC_EINVAL, "gradient needs the correction enabled");
+    return PIC_OK;
+}
+
+int forward_step_eager(pic_state *s)
+{
+    LaunchCtx live = ctx(s);
+    if (launch_yee(live, s->fwork, s->nfwork)) return fail(PIC_EHIP, "yee");
+    if (launch_seen(live, s->fwork, s->nfwork)) return fail(PIC_EHIP, "seen");
+    if (launch_particles(live, s->pwork, s->npwork, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particles");
+    return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" int pic_adjoint_forward(pic_state *s, int nsteps, double *loss)
+{
+    if (!s || !loss || nsteps < 1) return fail(PIC_EINVAL, "pic_adjoint_forward");
+    int rc = gradient_preconditions(s);
+    if (rc) return rc;
+    if (nsteps > s->adj_steps) return fail(PIC_EINVAL, "nsteps exceeds the planned adjoint_steps");
+    const int K = s->adj_k, nseg = (nsteps + K - 1) / K;
+    s->no_resort = true;      // particle order must stay fixed until the backward sweep
+    s->adj_pending = 0;
+    for (int n = 0; n < nsteps && rc == PIC_OK; n++) {
+        if (n % K == 0)
+            for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy(s, i, s->ckpt[i][n / K], true, true);
+        if (rc == PIC_OK) rc = forward_step_eager(s);
+    }
+    for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy(s, i, s->ckpt[i][nseg], true, true);
+    if (rc) { s->no_resort = false; return rc; }
+    s->step += nsteps;
+    // W of the final fields (the seed kernel also writes lambda_E, lambda_B, lambda_J)
+    for (int i = 0; i < s->n_inst; i++)
+        HIP_TRY(hipMemsetAsync(s->desc[i].grad, 0, 16 * sizeof(double), s->stream));
+    LaunchCtx live = ctx(s);
+    if (launch_adj_seed(live, s->fwork, s->nfwork, s->cwork, s->ncwork)) return fail(PIC_EHIP, "seed");
+    std::vector<double> g(16);
+    for (int i = 0; i < s->n_inst; i++) {
+        HIP_TRY(hipMemcpyAsync(g.data(), s->desc[i].grad, 16 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        loss[i] = g[9];
+    }
+    s->adj_pending = nsteps;
+    return PIC_OK;
+}
+
+extern "C" int pic_adjoint_backward(pic_state *s, double *grad)
+{
+    if (!s || !grad) return fail(PIC_EINVAL, "pic_adjoint_backward");
+    const int nsteps = s->adj_pending;
+    if (nsteps <= 0) return fail(PIC_ESTATE, "pic_adjoint_forward must run first");
+    const int K = s->adj_k, nseg = (nsteps + K - 1) / K;
+    LaunchCtx live = ctx(s);
+    int rc = PIC_OK;
+    for (int seg = nseg - 1; seg >= 0 && rc == PIC_OK; seg--) {
+        for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy(s, i, s->ckpt[i][seg], false, true);
+        const int n0 = seg * K, n1 = std::min(nsteps, n0 + K);
+        // recompute the segment, recording its tape
+        for (int n = n0; n < n1 && rc == PIC_OK; n++) {
+            const int slot = n - n0;
+            for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy_particles(s, i, s->tape[i][slot], true);
+            if (rc) break;
+            if (launch_yee(live, s->fwork, s->nfwork)) { rc = fail(PIC_EHIP, "yee"); break; }
+            for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy_fields(s, i, s->tape[i][slot]);
+            if (rc) break;
+            if (launch_seen(live, s->fwork, s->nfwork) ||
+                launch_particles(live, s->pwork, s->npwork, 0, s->block, s->wmax)) { rc = fail(PIC_EHIP, "recompute"); break; }
+        }
+        // reverse its steps
+        for (int n = n1 - 1; n >= n0 && rc == PIC_OK; n--) {
+            LaunchCtx tp = live;
+            tp.desc = s->d_tape_desc + (size_t)(n - n0) * s->n_inst;
+            if (launch_adj_step(live, tp, s->fwork, s->nfwork, s->pwork, s->npwork, 256, s->adj_wmax))
+                rc = fail(PIC_EHIP, "adjoint step");
+        }
+    }
+    // back to the forward end state
+    for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy(s, i, s->ckpt[i][nseg], false, true);
+    s->no_resort = false;
+    s->adj_pending = 0;
+    if (rc) return rc;
+    std::vector<double> g(16);
+    for (int i = 0; i < s->n_inst; i++) {
+        HIP_TRY(hipMemcpyAsync(g.data(), s->desc[i].grad, 16 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        for (int j = 0; j < 9; j++) grad[i * 9 + j] = j <= s->desc[i].psi_deg ? g[j] : 0.0;
+    }
     return PIC_OK;
 }
 

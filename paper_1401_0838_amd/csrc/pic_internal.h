@@ -69,6 +69,15 @@ struct InstDesc {
     int *flags;            // FLAG_*
     double *diag;          // DG_*
     double *trace;         // trace_cap rows of 6 doubles
+    // reverse mode (null unless gradient runs were planned)
+    void *lE[3], *lB[3], *lJ[3], *lEt[3], *lBt[3];   // adjoint grid planes
+    void *loff[3], *lu[3];                            // adjoint particle offsets / momenta
+    double *grad;          // dW/dpsi_e[j], 9 slots
+    double *loss;          // W
+    int psi_deg, hzf;
+    double tzf[2 * PIC_MAX_HZ + 1];  // z filter taps alone
+    double sj[9][17];      // taps of S_z^j (half-width j), j <= psi_deg
+    double cdep_r[3], cy2d_r;        // Esirkepov factors in real units (float mode unscaled)
 };
 
 // launch helpers implemented in pic_kernels.hip
@@ -92,3 +101,7 @@ int launch_diag(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *c
 int launch_trace_rows(const LaunchCtx &c, const int2 *fwork, int nfwork, int *pos, double *trace, int n_inst,
                       int cap);
 int launch_fill_bbox(const LaunchCtx &c, int inst_first, int n_inst);
+size_t adjoint_smem_bytes(int dims, int fp32, const int wmax[3]);
+int launch_adj_seed(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *cwork, int ncwork);
+int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fwork, int nfwork,
+                    const int2 *pwork, int npwork, int block, const int wmax[3]);

@@ -20,7 +20,8 @@ def _require_gpu():
     return torch
 
 
-def make_config(wl, precision=None, tile=None, block=0, trace_capacity=0, psi=None):
+def make_config(wl, precision=None, tile=None, block=0, trace_capacity=0, psi=None, adjoint_steps=0,
+                adjoint_ckpt=20):
     """pic_config for one workload dict.  The correction coefficients come from
     the library's own rational-interpolation setup unless `psi` is given."""
     c = L.pic_config()
@@ -67,6 +68,8 @@ def make_config(wl, precision=None, tile=None, block=0, trace_capacity=0, psi=No
         c.tile[i] = int(t[i])
     c.block = int(block)
     c.trace_capacity = int(trace_capacity)
+    c.adjoint_steps = int(adjoint_steps)
+    c.adjoint_ckpt = int(adjoint_ckpt) if adjoint_steps else 0
     return c
 
 
@@ -78,7 +81,7 @@ class Simulation:
     """
 
     def __init__(self, workloads, particles, precision=None, tile=None, block=0,
-                 trace_capacity=0, psi=None, stream=None):
+                 trace_capacity=0, psi=None, stream=None, adjoint_steps=0, adjoint_ckpt=20):
         torch = _require_gpu()
         L.load()
         if isinstance(workloads, dict):
@@ -86,7 +89,7 @@ class Simulation:
         self.workloads = list(workloads)
         self.dims = int(self.workloads[0]["dims"])
         self.cfgs = [make_config(wl, precision, tile, block, trace_capacity,
-                                 None if psi is None else psi[i])
+                                 None if psi is None else psi[i], adjoint_steps, adjoint_ckpt)
                      for i, wl in enumerate(self.workloads)]
         self.n_inst = len(self.cfgs)
         self.np = [int(p[0].shape[0]) for p in particles]
@@ -180,6 +183,21 @@ class Simulation:
         self.steps_taken += nsteps
         return dict(yee_ms=t.yee_ms, seen_ms=t.seen_ms, particle_ms=t.particle_ms,
                     resort_ms=t.resort_ms, step_ms=t.step_ms, steps=t.steps)
+
+    def adjoint_forward(self, nsteps):
+        """Run nsteps with checkpoints; returns W per instance."""
+        loss = L.pic_adjoint_forward(self.st, nsteps, self.n_inst)
+        self.steps_taken += nsteps
+        return loss
+
+    def adjoint_backward(self):
+        """dW/dpsi_e per instance, shape (n_inst, psi_deg + 1)."""
+        g = L.pic_adjoint_backward(self.st, self.n_inst)
+        return g[:, : self.cfgs[0].psi_deg + 1]
+
+    def psi(self, inst=0):
+        c = self.cfgs[inst]
+        return (np.array(c.psi_e[: c.psi_deg + 1]), np.array(c.psi_b[: c.psi_deg + 1]))
 
     def info(self):
         return L.pic_info(self.st)

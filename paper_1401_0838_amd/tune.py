@@ -1,0 +1,76 @@
+"""Autotuner for the particle-tile shape, workgroup size and launch schedule.
+
+For a workload it builds short-lived simulations with each candidate
+(tile shape, threads per workgroup), times a few steps with HIP events
+(pic_profile) and keeps the fastest; for batches it also compares the batched
+and the per-instance schedules.  Results are cached in a JSON file keyed by
+the workload's shape so later runs reuse them.
+"""
+import json
+import os
+import time
+
+from .sim import Simulation
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+CANDIDATES_2D = [((16, 1, 16), 256), ((16, 1, 16), 512), ((32, 1, 16), 256), ((16, 1, 32), 256),
+                 ((32, 1, 32), 512), ((8, 1, 16), 256)]
+CANDIDATES_3D = [((8, 4, 4), 256), ((4, 4, 8), 256), ((8, 8, 4), 256), ((4, 4, 4), 256)]
+
+
+def key(workloads, precision):
+    w = workloads[0]
+    sizes = sorted(tuple(x["n"]) for x in workloads)
+    return "%dd_o%d_ppc%d_%s_n%d_%s" % (w["dims"], w["order"], w["ppc"], precision, len(workloads),
+                                        "-".join("x".join(map(str, s)) for s in sizes[:4]))
+
+
+def _load_cache(path):
+    if os.path.exists(path):
+        try:
+            return json.load(open(path))
+        except (OSError, ValueError):
+            return {}
+    return {}
+
+
+def tune(workloads, particles, precision="fp32", steps=10, warmup=3, cache=CACHE, candidates=None):
+    """Return {"tile": [tx, ty, tz], "block": b, "schedule": "batched"|"plain", "step_ms": t}."""
+    if isinstance(workloads, dict):
+        workloads, particles = [workloads], [particles]
+    k = key(workloads, precision)
+    db = _load_cache(cache) if cache else {}
+    if k in db:
+        return db[k]
+    dims = workloads[0]["dims"]
+    cands = candidates or (CANDIDATES_2D if dims == 2 else CANDIDATES_3D)
+    best = None
+    for tile, block in cands:
+        sim = Simulation(workloads, particles, precision=precision, tile=tile, block=block)
+        sim.step(warmup)
+        prof = sim.profile(steps)
+        sim.close()
+        if best is None or prof["step_ms"] < best["step_ms"]:
+            best = {"tile": list(tile), "block": block, "step_ms": prof["step_ms"]}
+    best["schedule"] = "batched"
+    if len(workloads) > 1:
+        times = {}
+        for sched in ("batched", "plain"):
+            sim = Simulation(workloads, particles, precision=precision, tile=best["tile"], block=best["block"])
+            sim.set_schedule(sched, True)
+            sim.step(warmup)
+            sim.synchronize()
+            t0 = time.perf_counter()
+            sim.step(steps)
+            sim.synchronize()
+            times[sched] = (time.perf_counter() - t0) / steps * 1e3
+            sim.close()
+        best["schedule"] = min(times, key=times.get)
+        best["schedule_ms"] = times
+    if cache:
+        db[k] = best
+        with open(cache + ".tmp", "w") as f:
+            json.dump(db, f, indent=1)
+        os.replace(cache + ".tmp", cache)
+    return best

@@ -1,0 +1,98 @@
+"""Instability growth rates: GPU (FP32 and FP64) against the FP64 oracle.
+
+Growth rate of the transverse field energy (fit window and definition in
+paper_1401_0838_amd/fit.py; the oracle side uses its own oracle/fit.py).
+Bar: within 5 %, or |dGamma| dt <= 5e-5 when the growth is too weak for a
+relative comparison (Gamma dt < 1e-4 or less than ten-fold total growth).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import pic_inputs as pi
+from oracle import fit as ofit
+from oracle.ref import OracleSim
+from paper_1401_0838_amd import fit as gfit
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu_trace(wl, x, u, prec, nsteps):
+    from paper_1401_0838_amd.sim import Simulation
+    sim = Simulation(wl, (x, u), precision=prec, trace_capacity=nsteps)
+    wkin0 = sim.diag()["Wkin"]
+    sim.step(nsteps)
+    tr = sim.trace()
+    sim.close()
+    W = tr[:, 0] + tr[:, 1] + tr[:, 3] + tr[:, 4]
+    return W, wkin0
+
+
+def _oracle_trace(wl, x, u, nsteps):
+    ref = OracleSim(wl, x, u)
+    wkin0 = ref.energies()["Wkin"]
+    W = []
+    for _ in range(nsteps):
+        ref.step(1)
+        W.append(ref.energies()["Wperp"])
+    return np.array(W), wkin0
+
+
+def _close(g_a, g_b, W, dt):
+    weak = abs(g_b) * dt < 1e-4 or W.max() < 10 * max(W[W > 0].min(), 1e-300)
+    if weak:
+        return abs(g_a - g_b) * dt <= 5e-5
+    return abs(g_a - g_b) <= 0.05 * abs(g_b)
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.5, 0.7])
+def test_growth_rate_plain_method_vs_oracle(alpha):
+    """No correction, no filter: the instability grows fast; the GPU trace and the
+    fitted rate follow the oracle."""
+    wl = pi.workload("beam2d_64_fp64", alpha=alpha)
+    x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], wl["sigma"], 0)
+    n = 400
+    Wo, wk = _oracle_trace(wl, x, u, n)
+    go, _ = ofit.growth_rate(list(Wo), wl["alpha"], wk)
+    for prec in ("fp64", "fp32"):
+        Wg, wkg = _gpu_trace(wl, x, u, prec, n)
+        gg, win = gfit.growth_rate(Wg, wl["alpha"], wkg)
+        _say("alpha %.1f %s: Gamma gpu %.6e oracle %.6e window %s" % (alpha, prec, gg, go, win))
+        if prec == "fp64":
+            assert np.max(np.abs(Wg - Wo) / np.maximum(Wo, 1e-300)) < 1e-6
+        assert _close(gg, go, Wo, wl["alpha"])
+
+
+def test_growth_rate_corrected_vs_oracle():
+    """Correction + 4-pass filter (the 512x512 configuration's method at 64x64)."""
+    wl = pi.workload("beam2d_512", n=(64, 64), ppc=4, alpha=0.5)
+    x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], wl["sigma"], 0)
+    n = 400
+    Wo, wk = _oracle_trace(wl, x, u, n)
+    go, _ = ofit.growth_rate(list(Wo), wl["alpha"], wk)
+    Wg, wkg = _gpu_trace(wl, x, u, "fp32", n)
+    gg, _ = gfit.growth_rate(Wg, wl["alpha"], wkg)
+    _say("corrected: Gamma gpu %.6e oracle %.6e" % (gg, go))
+    assert _close(gg, go, Wo, wl["alpha"])
+
+
+def test_growth_rate_full_size_fp32_vs_fp64():
+    """512x512, 16 ppc, 2000 steps at alpha 0.3, 0.5, 0.7: the FP32 growth rate equals
+    the FP64 one (a property that holds at any size; the oracle is checked at 64x64)."""
+    wl0 = pi.workload("beam2d_512")
+    x, u = pi.load_beam(2, wl0["n"], wl0["ppc"], wl0["gamma"], wl0["sigma"], 0)
+    for alpha in wl0["alphas"]:
+        wl = dict(wl0, alpha=alpha)
+        W64, wk = _gpu_trace(wl, x, u, "fp64", wl["steps"])
+        W32, _ = _gpu_trace(wl, x, u, "fp32", wl["steps"])
+        g64, win = gfit.growth_rate(W64, alpha, wk)
+        g32, _ = gfit.growth_rate(W32, alpha, wk)
+        _say("512 alpha %.1f: Gamma fp32 %.6e fp64 %.6e (Gamma dt %.2e) window %s W %.3e..%.3e"
+             % (alpha, g32, g64, g64 * alpha, win, W64[10], W64[-1]))
+        assert _close(g32, g64, W64, alpha)
