@@ -165,6 +165,15 @@ int pic_step(pic_state *st, int nsteps);
  * from a captured HIP graph (use_graph = 1) or launched eagerly. */
 int pic_set_schedule(pic_state *st, int sched, int use_graph);
 
+/* Tuning knobs (used by the autotuner); every one keeps results unchanged:
+ *   "yee_tile_z"     rows of the 2D Yee tile: 4, 8 or 16 (16 is float only)
+ *   "seen_tile_z"    rows of the 2D seen-field tile: 8, 16 or 32
+ *   "resort_every"   steps between tile re-sort checks (and per captured graph)
+ *   "particle_block" threads per particle workgroup: 256 or 512
+ * Returns PIC_EINVAL for an unknown name or value.  Drops captured graphs. */
+int pic_set_option(pic_state *st, const char *name, int value);
+int pic_get_option(pic_state *st, const char *name, int *value);
+
 /* Copy one component of a grid quantity (PIC_FIELD_*) of instance inst to
  * (GET) or from (SET) a host float64 array of n = nx*ny*nz values laid out
  * [z][y][x], x fastest, half-integer locations stored at the lower index.

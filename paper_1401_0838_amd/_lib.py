@@ -75,6 +75,8 @@ _SIGS = {
     "pic_init": (C.c_int, [C.POINTER(pic_config), C.c_int, C.POINTER(pic_particles), C.c_void_p,
                            C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
     "pic_step": (C.c_int, [C.c_void_p, C.c_int]),
+    "pic_set_option": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int]),
+    "pic_get_option": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int)]),
     "pic_set_schedule": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "pic_fields": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, _D, C.c_size_t, C.c_int]),
     "pic_get_particles": (C.c_int, [C.c_void_p, C.c_int, _D * 3, _D * 3, C.c_int64]),
@@ -159,6 +161,16 @@ def pic_init(cfgs, parts, arena_ptr, arena_bytes, stream_ptr):
 
 def pic_step(st, nsteps):
     return check(load().pic_step(st, int(nsteps)), "pic_step")
+
+
+def pic_set_option(st, name, value):
+    return check(load().pic_set_option(st, name.encode(), int(value)), "pic_set_option(%s)" % name)
+
+
+def pic_get_option(st, name):
+    v = C.c_int(0)
+    check(load().pic_get_option(st, name.encode(), C.byref(v)), "pic_get_option(%s)" % name)
+    return v.value
 
 
 def pic_set_schedule(st, sched, use_graph):

@@ -163,37 +163,15 @@ __device__ __forceinline__ void adjoint_particle(Win &W, const int *lc, const R 
     B[0] = interp_f<0, 1, 1, DIM, L, R>(W, 3, lc, wi, wh);
     B[1] = interp_f<1, 0, 1, DIM, L, R>(W, 4, lc, wi, wh);
     B[2] = interp_f<1, 1, 0, DIM, L, R>(W, 5, lc, wi, wh);
-    // Boris forward, keeping the intermediates
-    R um[3], t[3], sv[3], up[3], un[3];
-#pragma unroll
-    for (int a = 0; a < 3; a++) um[a] = u[a] + qdt2m * E[a];
-    const R gm = sqrt(R(1) + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
-#pragma unroll
-    for (int a = 0; a < 3; a++) t[a] = qdt2m * B[a] / gm;
-    const R f = R(2) / (R(1) + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
-#pragma unroll
-    for (int a = 0; a < 3; a++) sv[a] = f * t[a];
-    up[0] = um[0] + (um[1] * t[2] - um[2] * t[1]);
-    up[1] = um[1] + (um[2] * t[0] - um[0] * t[2]);
-    up[2] = um[2] + (um[0] * t[1] - um[1] * t[0]);
-    un[0] = um[0] + (up[1] * sv[2] - up[2] * sv[1]) + qdt2m * E[0];
-    un[1] = um[1] + (up[2] * sv[0] - up[0] * sv[2]) + qdt2m * E[1];
-    un[2] = um[2] + (up[0] * sv[1] - up[1] * sv[0]) + qdt2m * E[2];
-    const R ig = R(1) / sqrt(R(1) + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
-    // move (as the forward kernel)
-    int dc[3];
+    // Boris and move, recomputed with the forward kernel's own routines
+    R un[3];
+    BorisTrace<R> bt;
+    boris_push<R>(u, E, B, qdt2m, un, bt);
+    const R *um = bt.um, *t = bt.t, *sv = bt.sv, *up = bt.up;
+    const R igm = bt.igm, f = bt.f;
+    int dc[3], err = 0;
     R offn[3];
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        if (DIM == 2 && a == 1) { dc[a] = 0; offn[a] = R(0); continue; }
-        R x1 = off[a] + dtd[a] * un[a] * ig;
-        int c = x1 >= R(1) ? 1 : (x1 < R(0) ? -1 : 0);
-        if (x1 >= R(2) || x1 < R(-1)) { x1 = x1 < R(0) ? R(-0.5) : R(1.5); c = x1 < R(0) ? -1 : 1; }
-        R on = x1 - R(c);
-        if (on >= R(1)) { on -= R(1); c += 1; }
-        dc[a] = c;
-        offn[a] = on;
-    }
+    const R ig = move_cells<DIM, R>(off, un, dtd, dc, offn, err);
     // Esirkepov reverse
     R S0[3][L + 2], S1[3][L + 2], D0[3][L + 2], D1[3][L + 2], lS0[3][L + 2], lS1[3][L + 2];
     int base[3];
@@ -331,11 +309,12 @@ __device__ __forceinline__ void adjoint_particle(Win &W, const int *lc, const R 
     const R lt2 = -lf * f * f * R(0.5);
 #pragma unroll
     for (int a = 0; a < 3; a++) lt[a] += f * ls[a] + R(2) * t[a] * lt2;
-    const R lg = -(t[0] * lt[0] + t[1] * lt[1] + t[2] * lt[2]) / gm;
+    // t = qdt2m B igm, igm = (1 + um.um)^(-1/2)
+    const R lg = -(t[0] * lt[0] + t[1] * lt[1] + t[2] * lt[2]) * igm;
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        lB[a] = qdt2m * lt[a] / gm;
-        lum[a] += lg * um[a] / gm;
+        lB[a] = qdt2m * lt[a] * igm;
+        lum[a] += lg * um[a] * igm;
         lE[a] += qdt2m * lum[a];
         lu[a] = lum[a];
     }
@@ -406,12 +385,8 @@ __global__ void __launch_bounds__(256) k_adj_particles(const InstDesc *__restric
             }
         }
         for (int p = p0 + tid; p < p1; p += bs) {
-            const int idx = D.pidx[p];
             int c[3];
-            c[0] = idx % D.n[0];
-            const int r = idx / D.n[0];
-            c[1] = r % D.n[1];
-            c[2] = r / D.n[1];
+            unpack_cell<DIM>((unsigned)D.pidx[p], c);
             int lc[3];
             R off[3], u[3], loff[3], lu[3];
 #pragma unroll
@@ -663,10 +638,10 @@ int launch_adj_seed(const LaunchCtx &c, const int2 *fwork, int nfwork, const int
 
 // Reverse of one step.  `tape` addresses this step's E1, B2, particles and
 // tile boxes; `live` the shared planes (identical for everything else).
-int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fwork, int nfwork, const int2 *pwork,
-                    int npwork, int block, const int wmax[3])
+int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fwork, int nfwork, const int2 *swork,
+                    int nswork, const int2 *pwork, int npwork, int block, const int wmax[3])
 {
-    if (launch_seen(tape, fwork, nfwork)) return -1;      // Et, Bt of this step
+    if (launch_seen(tape, fwork, nfwork, swork, nswork)) return -1;      // Et, Bt of this step
     const int wm[3] = {wmax[0], live.dims == 3 ? wmax[1] : 1, wmax[2]};
     const size_t smem = adjoint_smem_bytes(live.dims, live.fp32, wm);
     const dim3 gf(nfwork), g6(nfwork, 6), g2(nfwork, 2), bf(PIC_FIELD_CHUNK);

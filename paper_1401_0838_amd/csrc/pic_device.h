@@ -28,7 +28,8 @@ __device__ __forceinline__ void jadd(long long *p, long long v)
 __device__ __forceinline__ void jadd(double *p, double v) { unsafeAtomicAdd(p, v); }
 
 // contribution -> accumulator type (already scaled by 1/quantum in float mode)
-__device__ __forceinline__ long long jcvt(float v, long long *) { return (long long)__float2int_rn(v); }
+// truncation toward zero (one instruction); the bias is below one quantum
+__device__ __forceinline__ long long jcvt(float v, long long *) { return (long long)(int)v; }
 __device__ __forceinline__ double jcvt(double v, double *) { return v; }
 
 __device__ __forceinline__ double jreal(long long v, double q) { return (double)v * q; }
@@ -96,6 +97,110 @@ template <class R> struct Shape<3, R> {
     }
 };
 
+// -------------------------------------------------------- global pointers
+// Pointers read from the descriptor are generic; casting them to the global
+// address space makes the compiler emit global (not flat) loads, stores and
+// atomics, so LDS and HBM waits are tracked separately.
+template <class T> using gp = __attribute__((address_space(1))) T *;
+template <class T> __device__ __forceinline__ gp<T> G(void *p) { return (gp<T>)p; }
+template <class T> __device__ __forceinline__ gp<const T> G(const void *p) { return (gp<const T>)p; }
+
+__device__ __forceinline__ void gatomic_add(gp<long long> p, long long v)
+{
+    __hip_atomic_fetch_add((gp<unsigned long long>)p, (unsigned long long)v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gatomic_add(gp<double> p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gatomic_add(gp<float> p, float v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// reciprocal and reciprocal square root: hardware approximations (1 ulp) in
+// float, exact division in double
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+
+// ----------------------------------------------------- packed cell index
+// 2D: x | z << 16 ;  3D: x | y << 11 | z << 21  (unsigned 32-bit)
+template <int DIM> __host__ __device__ __forceinline__ unsigned pack_cell(int x, int y, int z)
+{
+    return DIM == 2 ? ((unsigned)x | ((unsigned)z << 16)) : ((unsigned)x | ((unsigned)y << 11) | ((unsigned)z << 21));
+}
+template <int DIM> __host__ __device__ __forceinline__ void unpack_cell(unsigned v, int *c)
+{
+    if (DIM == 2) { c[0] = (int)(v & 0xffffu); c[1] = 0; c[2] = (int)(v >> 16); }
+    else { c[0] = (int)(v & 0x7ffu); c[1] = (int)((v >> 11) & 0x3ffu); c[2] = (int)(v >> 21); }
+}
+
+// ------------------------------------------------- Boris push and move
+// Shared by the forward kernel and the adjoint's recomputation so both take
+// bit-identical cell steps.
+template <class R> struct BorisTrace {
+    R um[3], t[3], sv[3], up[3];
+    R igm, f;
+};
+
+template <class R>
+__device__ __forceinline__ void boris_push(const R *u, const R *E, const R *B, R qdt2m, R *un, BorisTrace<R> &b)
+{
+#pragma unroll
+    for (int a = 0; a < 3; a++) b.um[a] = u[a] + qdt2m * E[a];
+    b.igm = rsq(R(1) + b.um[0] * b.um[0] + b.um[1] * b.um[1] + b.um[2] * b.um[2]);
+#pragma unroll
+    for (int a = 0; a < 3; a++) b.t[a] = qdt2m * B[a] * b.igm;
+    b.f = R(2) * rcp(R(1) + b.t[0] * b.t[0] + b.t[1] * b.t[1] + b.t[2] * b.t[2]);
+#pragma unroll
+    for (int a = 0; a < 3; a++) b.sv[a] = b.f * b.t[a];
+    b.up[0] = b.um[0] + (b.um[1] * b.t[2] - b.um[2] * b.t[1]);
+    b.up[1] = b.um[1] + (b.um[2] * b.t[0] - b.um[0] * b.t[2]);
+    b.up[2] = b.um[2] + (b.um[0] * b.t[1] - b.um[1] * b.t[0]);
+    un[0] = b.um[0] + (b.up[1] * b.sv[2] - b.up[2] * b.sv[1]) + qdt2m * E[0];
+    un[1] = b.um[1] + (b.up[2] * b.sv[0] - b.up[0] * b.sv[2]) + qdt2m * E[1];
+    un[2] = b.um[2] + (b.up[0] * b.sv[1] - b.up[1] * b.sv[0]) + qdt2m * E[2];
+}
+
+// new offsets and cell steps (cell units); returns 1/gamma of un
+template <int DIM, class R>
+__device__ __forceinline__ R move_cells(const R *off, const R *un, const R *dtd, int *dc, R *offn, int &err)
+{
+    const R ig = rsq(R(1) + un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (DIM == 2 && a == 1) { dc[a] = 0; offn[a] = R(0); continue; }
+        R x1 = off[a] + dtd[a] * un[a] * ig;
+        int c = x1 >= R(1) ? 1 : (x1 < R(0) ? -1 : 0);
+        if (x1 >= R(2) || x1 < R(-1)) { err = 1; x1 = x1 < R(0) ? R(-0.5) : R(1.5); c = x1 < R(0) ? -1 : 1; }
+        R on = x1 - R(c);
+        if (on >= R(1)) { on -= R(1); c += 1; }
+        dc[a] = c;
+        offn[a] = on;
+    }
+    return ig;
+}
+
+// global cell of window cell c (window dims wn, origin o, grid n); the
+// window may exceed the grid on tiny grids, hence the second wrap
+__device__ __forceinline__ int window_cell(int c, const int *wn, const int *o, const int *n)
+{
+    const int wxy = wn[0] * wn[1];
+    int z = (int)(((float)c + 0.5f) * (1.0f / (float)wxy));
+    int r = c - z * wxy;
+    int y = (int)(((float)r + 0.5f) * (1.0f / (float)wn[0]));
+    int x = r - y * wn[0];
+    int gx = o[0] + x, gy = o[1] + y, gz = o[2] + z;
+    gx = gx >= n[0] ? gx - n[0] : gx;
+    gy = gy >= n[1] ? gy - n[1] : gy;
+    gz = gz >= n[2] ? gz - n[2] : gz;
+    if (gx >= n[0] || gy >= n[1] || gz >= n[2]) { gx %= n[0]; gy %= n[1]; gz %= n[2]; }
+    return (gz * n[1] + gy) * n[0] + gx;
+}
+
 // ------------------------------------------------------------ accessors
 // Field / current access by window-local node coordinates.
 
@@ -108,9 +213,20 @@ template <class R, class JT> struct LdsWin {
     __device__ __forceinline__ void add(int comp, int x, int y, int z, JT v) { jadd(&J[comp * wc + at(x, y, z)], v); }
 };
 
+// LDS window with a compile-time row pitch P (2D): every node a particle
+// touches is at a constant offset from one base address
+template <class R, class JT, int P> struct LdsWinP {
+    const R *F;
+    JT *J;
+    static constexpr int wc = P * P;
+    __device__ __forceinline__ int at(int x, int, int z) const { return z * P + x; }
+    __device__ __forceinline__ R f(int comp, int x, int y, int z) const { return F[comp * wc + at(x, y, z)]; }
+    __device__ __forceinline__ void add(int comp, int x, int y, int z, JT v) { jadd(&J[comp * wc + at(x, y, z)], v); }
+};
+
 template <class R, class JT> struct GlbWin {
-    const R *F[6];
-    JT *J[3];
+    gp<const R> F[6];
+    gp<JT> J[3];
     int o[3], n[3];
     __device__ __forceinline__ int at(int x, int y, int z) const
     {
@@ -118,7 +234,7 @@ template <class R, class JT> struct GlbWin {
         return (gz * n[1] + gy) * n[0] + gx;
     }
     __device__ __forceinline__ R f(int comp, int x, int y, int z) const { return F[comp][at(x, y, z)]; }
-    __device__ __forceinline__ void add(int comp, int x, int y, int z, JT v) { jadd(&J[comp][at(x, y, z)], v); }
+    __device__ __forceinline__ void add(int comp, int x, int y, int z, JT v) { gatomic_add(J[comp] + at(x, y, z), v); }
 };
 
 

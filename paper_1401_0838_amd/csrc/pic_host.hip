@@ -13,8 +13,12 @@
 
 #include "pic_api.h"
 #include "pic_internal.h"
+#include "pic_device.h"
 
 namespace {
+
+using pic::pack_cell;
+using pic::unpack_cell;
 
 thread_local std::string g_last_error;
 
@@ -84,7 +88,9 @@ int validate(const pic_config &c, int idx)
     if (c.dims != 2 && c.dims != 3) return bad(PIC_EINVAL, "dims must be 2 or 3");
     if (c.nx < 1 || c.nz < 1 || c.ny < 1) return bad(PIC_EINVAL, "cell counts must be >= 1");
     if (c.dims == 2 && c.ny != 1) return bad(PIC_EINVAL, "ny must be 1 in 2D");
-    if ((double)c.nx * c.ny * c.nz > 2.0e9) return bad(PIC_EINVAL, "grid too large for int32 cell index");
+    if (c.dims == 2 && (c.nx > 65536 || c.nz > 65536)) return bad(PIC_EINVAL, "2D cell counts must be <= 65536");
+    if (c.dims == 3 && (c.nx > 2048 || c.ny > 1024 || c.nz > 2048))
+        return bad(PIC_EINVAL, "3D cell counts must be <= 2048 x 1024 x 2048 (packed int32 cell index)");
     if (!(c.dx > 0) || !(c.dz > 0) || (c.dims == 3 && !(c.dy > 0))) return bad(PIC_EINVAL, "cell sizes must be > 0");
     if (!(c.cdt > 0)) return bad(PIC_EINVAL, "c dt must be > 0");
     double s = 1.0 / (c.dx * c.dx) + 1.0 / (c.dz * c.dz) + (c.dims == 3 ? 1.0 / (c.dy * c.dy) : 0.0);
@@ -154,13 +160,14 @@ struct pic_state {
     std::vector<InstDesc> desc;
     std::vector<int64_t> np;
     InstDesc *d_desc = nullptr;
-    int2 *fwork = nullptr, *pwork = nullptr, *cwork = nullptr;
-    int nfwork = 0, npwork = 0, ncwork = 0;
-    std::vector<Range> frange, prange, crange;
+    int2 *fwork = nullptr, *pwork = nullptr, *cwork = nullptr, *swork = nullptr, *ywork = nullptr;
+    int nfwork = 0, npwork = 0, ncwork = 0, nswork = 0, nywork = 0;
+    std::vector<Range> frange, prange, crange, srange, yrange;
     int wmax[3] = {1, 1, 1};
     int block = 256;
     int sched = PIC_SCHED_BATCHED, use_graph = 1;
     int graph_k = 8;                 // steps per captured graph (and re-sort period)
+    int yee_tz = 8, seen_tz = 16;    // 2D field-kernel tile heights (tunable)
     hipGraphExec_t gexec_k = nullptr, gexec_1 = nullptr;
     long long step = 0;
     int *trace_pos = nullptr;
@@ -170,6 +177,7 @@ struct pic_state {
     int adj_steps = 0, adj_k = 0;
     bool no_resort = false;
     int adj_pending = 0;                         // steps of the last pic_adjoint_forward
+    hipGraphExec_t gexec_adj_fwd = nullptr, gexec_adj_seg = nullptr;
     std::vector<std::vector<Snap>> ckpt, tape;   // [instance][slot]
     InstDesc *d_tape_desc = nullptr;             // adj_k * n_inst descriptors
     int adj_wmax[3] = {1, 1, 1};
@@ -185,8 +193,12 @@ LaunchCtx ctx(const pic_state *s)
     c.dims = s->dims;
     c.order = s->order;
     c.fp32 = s->fp32;
+    c.yee_tz = s->yee_tz;
+    c.seen_tz = s->seen_tz;
     return c;
 }
+
+int yee_tz_eff(int tz, int fp32) { return (!fp32 && tz > 8) ? 8 : tz; }
 
 // Lay out all arrays; with base == nullptr only the size is computed.
 size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *np, char *base)
@@ -196,7 +208,7 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
     const size_t R = cfgs[0].precision == PIC_FP32 ? 4 : 8;
     InstDesc *dd = L.take<InstDesc>(n_inst);
     if (s) s->d_desc = dd;
-    size_t nf = 0, npw = 0, nc = 0;
+    size_t nf = 0, npw = 0, nc = 0, ns = 0, ny = 0;
     std::vector<int> ntiles(n_inst);
     for (int i = 0; i < n_inst; i++) {
         const pic_config &c = cfgs[i];
@@ -207,17 +219,23 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
                        ((c.nz + tile[2] - 1) / tile[2]);
         ntiles[i] = nt;
         nf += (ncell + PIC_FIELD_CHUNK - 1) / PIC_FIELD_CHUNK;
+        // sized for the smallest selectable tiles (seen 8 rows, Yee 4 rows)
+        ns += (size_t)((c.nx + PIC_SEEN_TX - 1) / PIC_SEEN_TX) * ((c.nz + 8 - 1) / 8);
+        ny += (size_t)((c.nx + PIC_YEE_TX - 1) / PIC_YEE_TX) * ((c.nz + 4 - 1) / 4);
         npw += nt;
         nc += (np[i] + PIC_PART_CHUNK - 1) / PIC_PART_CHUNK;
     }
     int2 *fw = L.take<int2>(nf), *pw = L.take<int2>(npw), *cw = L.take<int2>(std::max<size_t>(nc, 1));
-    if (s) { s->fwork = fw; s->pwork = pw; s->cwork = cw; }
+    int2 *sw = L.take<int2>(ns), *yw = L.take<int2>(ny);
+    if (s) { s->fwork = fw; s->pwork = pw; s->cwork = cw; s->swork = sw; s->ywork = yw; }
     int *tpos = L.take<int>(64);
     if (s) s->trace_pos = tpos;
     int cap = 0;
     for (int i = 0; i < n_inst; i++) cap = std::max(cap, cfgs[i].trace_capacity);
-    double *tr = L.take<double>((size_t)std::max(cap, 1) * n_inst * 6);
-    if (s) { s->trace = tr; s->trace_cap = cap; }
+    // one spare row: each step clears the row the next step writes, so a ring
+    // of cap + 1 rows always holds the last cap complete rows
+    double *tr = L.take<double>((size_t)(std::max(cap, 1) + 1) * n_inst * 6);
+    if (s) { s->trace = tr; s->trace_cap = cap > 0 ? cap + 1 : 0; }
     if (cfgs[0].adjoint_steps > 0) {
         InstDesc *td = L.take<InstDesc>((size_t)cfgs[0].adjoint_ckpt * n_inst);
         if (s) s->d_tape_desc = td;
@@ -228,10 +246,16 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
         const size_t n = (size_t)np[i];
         InstDesc *D = s ? &s->desc[i] : nullptr;
         auto plane = [&](size_t bytes_per) { return (void *)L.take<char>(ncell * bytes_per); };
-        for (int k = 0; k < 3; k++) {
-            void *e = plane(R), *b = plane(R), *et = plane(R), *bt = plane(R), *j = plane(8);
-            if (D) { D->E[k] = e; D->B[k] = b; D->Et[k] = et; D->Bt[k] = bt; D->J[k] = j; }
-        }
+        // E, B and J each occupy one contiguous region (planes in component
+        // order) so that checkpoints copy them with one transfer each
+        void *pe[3], *pb[3], *pj[3], *pet[3], *pbt[3];
+        for (int k = 0; k < 3; k++) pe[k] = plane(R);
+        for (int k = 0; k < 3; k++) pb[k] = plane(R);
+        for (int k = 0; k < 3; k++) pj[k] = plane(8);
+        for (int k = 0; k < 3; k++) pet[k] = plane(R);
+        for (int k = 0; k < 3; k++) pbt[k] = plane(R);
+        if (D)
+            for (int k = 0; k < 3; k++) { D->E[k] = pe[k]; D->B[k] = pb[k]; D->J[k] = pj[k]; D->Et[k] = pet[k]; D->Bt[k] = pbt[k]; }
         const bool adj = c.adjoint_steps > 0;
         for (int k = 0; k < 6; k++) {
             void *t1 = plane(R);
@@ -239,12 +263,16 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
             if (D) { D->T1[k] = t1; D->T2[k] = t2; }
         }
         double *r0 = L.take<double>(ncell), *r1 = L.take<double>(ncell);
-        int *pidx = L.take<int>(n), *ppid = L.take<int>(n);
-        int *sidx = L.take<int>(n), *spid = L.take<int>(n), *srank = L.take<int>(n), *stile = L.take<int>(n);
+        // particle state (cell index, offsets, momenta) is one contiguous region
+        int *pidx = L.take<int>(n);
         void *poff[3] = {nullptr, nullptr, nullptr}, *pu[3], *soff[3] = {nullptr, nullptr, nullptr}, *su[3];
+        for (int a = 0; a < 3; a++)
+            if (!(c.dims == 2 && a == 1)) poff[a] = L.take<char>(n * R);
+        for (int a = 0; a < 3; a++) pu[a] = L.take<char>(n * R);
+        int *ppid = L.take<int>(n);
+        int *sidx = L.take<int>(n), *spid = L.take<int>(n), *srank = L.take<int>(n), *stile = L.take<int>(n);
         for (int a = 0; a < 3; a++) {
-            if (!(c.dims == 2 && a == 1)) { poff[a] = L.take<char>(n * R); soff[a] = L.take<char>(n * R); }
-            pu[a] = L.take<char>(n * R);
+            if (!(c.dims == 2 && a == 1)) soff[a] = L.take<char>(n * R);
             su[a] = L.take<char>(n * R);
         }
         int *tstart = L.take<int>(ntiles[i] + 1), *tbox = L.take<int>((size_t)ntiles[i] * 6);
@@ -265,18 +293,17 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
             }
             double *g = L.take<double>(16);
             if (D) { D->grad = g; D->loss = g + 9; }
+            // same region order as the live arrays (see above)
             auto snap = [&](bool with_j) {
                 Snap sn;
-                for (int k = 0; k < 3; k++) {
-                    sn.E[k] = plane(R);
-                    sn.B[k] = plane(R);
-                    if (with_j) sn.J[k] = plane(8);
-                }
+                for (int k = 0; k < 3; k++) sn.E[k] = plane(R);
+                for (int k = 0; k < 3; k++) sn.B[k] = plane(R);
+                if (with_j)
+                    for (int k = 0; k < 3; k++) sn.J[k] = plane(8);
                 sn.pidx = L.take<int>(n);
-                for (int a = 0; a < 3; a++) {
+                for (int a = 0; a < 3; a++)
                     if (!(c.dims == 2 && a == 1)) sn.poff[a] = L.take<char>(n * R);
-                    sn.pu[a] = L.take<char>(n * R);
-                }
+                for (int a = 0; a < 3; a++) sn.pu[a] = L.take<char>(n * R);
                 sn.tbox = L.take<int>((size_t)ntiles[i] * 6);
                 return sn;
             };
@@ -370,6 +397,7 @@ int upload_particles(pic_state *s, int inst, const pic_particles &p)
     const int dims = s->dims;
     const int64_t n = p.n;
     std::vector<int> cell(n), tile(n), rank(n);
+    std::vector<unsigned> packed(n);
     std::vector<R> off[3];
     for (int a = 0; a < 3; a++) off[a].resize(dims == 2 && a == 1 ? 0 : n);
     for (int64_t i = 0; i < n; i++) {
@@ -388,6 +416,7 @@ int upload_particles(pic_state *s, int inst, const pic_particles &p)
             off[a][i] = ro;
         }
         cell[i] = (c[2] * D.n[1] + c[1]) * D.n[0] + c[0];
+        packed[i] = dims == 2 ? pack_cell<2>(c[0], c[1], c[2]) : pack_cell<3>(c[0], c[1], c[2]);
         tile[i] = ((c[2] / D.tile[2]) * D.nt[1] + c[1] / D.tile[1]) * D.nt[0] + c[0] / D.tile[0];
     }
     // order: by tile, then by rank within the cell, then by cell, so that
@@ -423,7 +452,7 @@ int upload_particles(pic_state *s, int inst, const pic_particles &p)
     }
     for (int64_t j = 0; j < n; j++) {
         const int64_t i = order[j];
-        h_idx[j] = cell[i];
+        h_idx[j] = (int)packed[i];
         h_pid[j] = (int)i;
         for (int a = 0; a < 3; a++) {
             if (!(dims == 2 && a == 1)) h_off[a][j] = off[a][i];
@@ -443,21 +472,25 @@ int upload_particles(pic_state *s, int inst, const pic_particles &p)
     return PIC_OK;
 }
 
-// particle arrays and tile boxes of one instance to (save) or from a snapshot
+// bytes of the contiguous regions [E..B], [J], [cell index..momenta]
+size_t region_fields(const InstDesc &D, size_t R) { return (size_t)((char *)D.B[2] - (char *)D.E[0]) + D.ncell * R; }
+size_t region_j(const InstDesc &D) { return (size_t)((char *)D.J[2] - (char *)D.J[0]) + (size_t)D.ncell * 8; }
+size_t region_particles(const InstDesc &D, size_t R)
+{
+    return (size_t)((char *)D.pu[2] - (char *)D.pidx) + (size_t)D.np * R;
+}
+
+// particle state and tile boxes of one instance to (save) or from a snapshot
 int snap_copy_particles(pic_state *s, int inst, const Snap &sn, bool save)
 {
     const InstDesc &D = s->desc[inst];
-    const size_t R = s->fp32 ? 4 : 8, n = (size_t)D.np;
+    const size_t R = s->fp32 ? 4 : 8;
     const hipMemcpyKind kd = hipMemcpyDeviceToDevice;
     auto cp = [&](void *live, void *snapp, size_t bytes) {
         if (!bytes || !live || !snapp) return hipSuccess;
         return save ? hipMemcpyAsync(snapp, live, bytes, kd, s->stream) : hipMemcpyAsync(live, snapp, bytes, kd, s->stream);
     };
-    HIP_TRY(cp(D.pidx, sn.pidx, n * 4));
-    for (int a = 0; a < 3; a++) {
-        HIP_TRY(cp(D.poff[a], sn.poff[a], n * R));
-        HIP_TRY(cp(D.pu[a], sn.pu[a], n * R));
-    }
+    if (D.np > 0) HIP_TRY(cp(D.pidx, sn.pidx, region_particles(D, R)));
     HIP_TRY(cp(D.tbox, sn.tbox, (size_t)D.ntiles * 6 * 4));
     return PIC_OK;
 }
@@ -466,11 +499,7 @@ int snap_copy_particles(pic_state *s, int inst, const Snap &sn, bool save)
 int snap_copy_fields(pic_state *s, int inst, const Snap &sn)
 {
     const InstDesc &D = s->desc[inst];
-    const size_t bytes = (size_t)D.ncell * (s->fp32 ? 4 : 8);
-    for (int c = 0; c < 3; c++) {
-        HIP_TRY(hipMemcpyAsync(sn.E[c], D.E[c], bytes, hipMemcpyDeviceToDevice, s->stream));
-        HIP_TRY(hipMemcpyAsync(sn.B[c], D.B[c], bytes, hipMemcpyDeviceToDevice, s->stream));
-    }
+    HIP_TRY(hipMemcpyAsync(sn.E[0], D.E[0], region_fields(D, s->fp32 ? 4 : 8), hipMemcpyDeviceToDevice, s->stream));
     return PIC_OK;
 }
 
@@ -489,8 +518,9 @@ void tile_order(int nt, std::vector<int> &out)
 
 int build_worklists(pic_state *s)
 {
-    std::vector<int2> fw, pw, cw;
-    s->frange.clear(); s->prange.clear(); s->crange.clear();
+    std::vector<int2> fw, pw, cw, sw, yw;
+    s->frange.clear(); s->prange.clear(); s->crange.clear(); s->srange.clear(); s->yrange.clear();
+    const int ytz = yee_tz_eff(s->yee_tz, s->fp32), stz = s->seen_tz;
     std::vector<int> ord;
     for (int i = 0; i < s->n_inst; i++) {
         const InstDesc &D = s->desc[i];
@@ -503,6 +533,16 @@ int build_worklists(pic_state *s)
         for (int t = 0; t < D.ntiles; t++) pw.push_back(make_int2(i, ord[t]));
         q.n = (int)pw.size() - q.off;
         s->prange.push_back(q);
+        Range sr{(int)sw.size(), 0};
+        const int nst = ((D.n[0] + PIC_SEEN_TX - 1) / PIC_SEEN_TX) * ((D.n[2] + stz - 1) / stz);
+        for (int k = 0; k < nst; k++) sw.push_back(make_int2(i, k));
+        sr.n = (int)sw.size() - sr.off;
+        s->srange.push_back(sr);
+        Range yr{(int)yw.size(), 0};
+        const int nyt = ((D.n[0] + PIC_YEE_TX - 1) / PIC_YEE_TX) * ((D.n[2] + ytz - 1) / ytz);
+        for (int k = 0; k < nyt; k++) yw.push_back(make_int2(i, k));
+        yr.n = (int)yw.size() - yr.off;
+        s->yrange.push_back(yr);
         Range c{(int)cw.size(), 0};
         for (long long k = 0; k < (D.np + PIC_PART_CHUNK - 1) / PIC_PART_CHUNK; k++) cw.push_back(make_int2(i, (int)k));
         c.n = (int)cw.size() - c.off;
@@ -511,6 +551,10 @@ int build_worklists(pic_state *s)
     s->nfwork = (int)fw.size();
     s->npwork = (int)pw.size();
     s->ncwork = (int)cw.size();
+    s->nswork = (int)sw.size();
+    s->nywork = (int)yw.size();
+    HIP_TRY(hipMemcpyAsync(s->ywork, yw.data(), yw.size() * sizeof(int2), hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->swork, sw.data(), sw.size() * sizeof(int2), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(s->fwork, fw.data(), fw.size() * sizeof(int2), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(s->pwork, pw.data(), pw.size() * sizeof(int2), hipMemcpyHostToDevice, s->stream));
     if (!cw.empty())
@@ -520,11 +564,11 @@ int build_worklists(pic_state *s)
 }
 
 // one step's launches for instances [i0, i0 + ni) using the given work ranges
-int enqueue_step_range(pic_state *s, const Range &f, const Range &p, bool trace)
+int enqueue_step_range(pic_state *s, const Range &f, const Range &sr, const Range &yr, const Range &p, bool trace)
 {
     LaunchCtx c = ctx(s);
-    if (launch_yee(c, s->fwork + f.off, f.n)) return fail(PIC_EHIP, "yee launch");
-    if (launch_seen(c, s->fwork + f.off, f.n)) return fail(PIC_EHIP, "seen launch");
+    if (launch_yee(c, s->fwork + f.off, f.n, s->ywork + yr.off, yr.n)) return fail(PIC_EHIP, "yee launch");
+    if (launch_seen(c, s->fwork + f.off, f.n, s->swork + sr.off, sr.n)) return fail(PIC_EHIP, "seen launch");
     if (launch_particles(c, s->pwork + p.off, p.n, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particle launch");
     (void)trace;
     return PIC_OK;
@@ -533,11 +577,12 @@ int enqueue_step_range(pic_state *s, const Range &f, const Range &p, bool trace)
 int enqueue_step(pic_state *s)
 {
     if (s->sched == PIC_SCHED_BATCHED) {
-        int rc = enqueue_step_range(s, Range{0, s->nfwork}, Range{0, s->npwork}, false);
+        int rc = enqueue_step_range(s, Range{0, s->nfwork}, Range{0, s->nswork}, Range{0, s->nywork},
+                                    Range{0, s->npwork}, false);
         if (rc) return rc;
     } else {
         for (int i = 0; i < s->n_inst; i++) {
-            int rc = enqueue_step_range(s, s->frange[i], s->prange[i], false);
+            int rc = enqueue_step_range(s, s->frange[i], s->srange[i], s->yrange[i], s->prange[i], false);
             if (rc) return rc;
         }
     }
@@ -567,6 +612,23 @@ void drop_graphs(pic_state *s)
 {
     if (s->gexec_k) { (void)hipGraphExecDestroy(s->gexec_k); s->gexec_k = nullptr; }
     if (s->gexec_1) { (void)hipGraphExecDestroy(s->gexec_1); s->gexec_1 = nullptr; }
+    if (s->gexec_adj_fwd) { (void)hipGraphExecDestroy(s->gexec_adj_fwd); s->gexec_adj_fwd = nullptr; }
+    if (s->gexec_adj_seg) { (void)hipGraphExecDestroy(s->gexec_adj_seg); s->gexec_adj_seg = nullptr; }
+}
+
+// capture whatever `body` enqueues on the state's stream into an executable graph
+template <class F> int capture_fn(pic_state *s, F body, hipGraphExec_t *out)
+{
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    int rc = body();
+    hipError_t e = hipStreamEndCapture(s->stream, &g);
+    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return fail(PIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(PIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return PIC_OK;
 }
 
 int capture(pic_state *s, int k, bool with_resort, hipGraphExec_t *out)
@@ -638,9 +700,8 @@ int get_particles(pic_state *s, int inst, double *pos[3], double *mom[3])
         const int i = pid[j];
         if (i < 0 || (size_t)i >= n) return fail(PIC_ESTATE, "corrupt particle ids");
         int c[3];
-        c[0] = idx[j] % D.n[0];
-        c[1] = (idx[j] / D.n[0]) % D.n[1];
-        c[2] = idx[j] / (D.n[0] * D.n[1]);
+        if (s->dims == 2) unpack_cell<2>((unsigned)idx[j], c);
+        else unpack_cell<3>((unsigned)idx[j], c);
         for (int a = 0; a < 3; a++) {
             if (mom[a]) mom[a][i] = (double)u[a][j];
             if (pos[a] && D.poff[a]) pos[a][i] = ((double)c[a] + (double)off[a][j]) * D.d[a];
@@ -741,6 +802,14 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
             s->wmax[a] = std::max(s->wmax[a], w);
         }
     }
+    if (s->dims == 2) {
+        // square windows of pitch 24 or 32 let the 2D kernel address LDS with immediates
+        const int w = std::max(s->wmax[0], s->wmax[2]);
+        const int pw = w <= 24 ? 24 : (w <= 32 ? 32 : w);
+        const int wm2[3] = {pw, 1, pw};
+        if (pw != w || s->wmax[0] != s->wmax[2])
+            if (particle_smem_bytes(2, s->fp32, wm2) <= (size_t)maxsm) { s->wmax[0] = pw; s->wmax[2] = pw; }
+    }
     while (particle_smem_bytes(s->dims, s->fp32, s->wmax) > (size_t)maxsm) {
         // shrink the slack until the window fits (tiles then re-sort more often)
         bool shrunk = false;
@@ -806,6 +875,41 @@ extern "C" int pic_set_schedule(pic_state *s, int sched, int use_graph)
     if (s->sched != sched || s->use_graph != (use_graph ? 1 : 0)) drop_graphs(s);
     s->sched = sched;
     s->use_graph = use_graph ? 1 : 0;
+    return PIC_OK;
+}
+
+extern "C" int pic_set_option(pic_state *s, const char *name, int value)
+{
+    if (!s || !name) return fail(PIC_EINVAL, "pic_set_option");
+    const std::string n(name);
+    if (n == "yee_tile_z") {
+        if (value != 4 && value != 8 && value != 16) return fail(PIC_EINVAL, "yee_tile_z must be 4, 8 or 16");
+        s->yee_tz = yee_tz_eff(value, s->fp32);
+    } else if (n == "seen_tile_z") {
+        if (value != 8 && value != 16 && value != 32) return fail(PIC_EINVAL, "seen_tile_z must be 8, 16 or 32");
+        s->seen_tz = value;
+    } else if (n == "resort_every") {
+        if (value < 1 || value > 1024) return fail(PIC_EINVAL, "resort_every must be in [1, 1024]");
+        s->graph_k = value;
+    } else if (n == "particle_block") {
+        if (value != 256 && value != 512) return fail(PIC_EINVAL, "particle_block must be 256 or 512");
+        s->block = value;
+    } else {
+        return fail(PIC_EINVAL, "unknown option " + n);
+    }
+    drop_graphs(s);
+    return build_worklists(s);
+}
+
+extern "C" int pic_get_option(pic_state *s, const char *name, int *value)
+{
+    if (!s || !name || !value) return fail(PIC_EINVAL, "pic_get_option");
+    const std::string n(name);
+    if (n == "yee_tile_z") *value = s->yee_tz;
+    else if (n == "seen_tile_z") *value = s->seen_tz;
+    else if (n == "resort_every") *value = s->graph_k;
+    else if (n == "particle_block") *value = s->block;
+    else return fail(PIC_EINVAL, "unknown option " + n);
     return PIC_OK;
 }
 
@@ -926,7 +1030,7 @@ extern "C" int pic_read_trace(pic_state *s, int inst, double *host_out, int max_
     std::vector<double> all((size_t)s->trace_cap * s->n_inst * 6);
     HIP_TRY(hipMemcpyAsync(all.data(), s->trace, all.size() * 8, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
-    const int rows = std::min(std::min(pos, s->trace_cap), max_rows);
+    const int rows = std::min(std::min(pos, s->trace_cap - 1), max_rows);
     const int first = pos - rows;
     for (int r = 0; r < rows; r++) {
         const int slot = (first + r) % s->trace_cap;
@@ -948,9 +1052,9 @@ extern "C" int pic_profile(pic_state *s, int nsteps, pic_timing_t *out)
     for (int n = 0; n < nsteps; n++) {
         const Range f{0, s->nfwork}, p{0, s->npwork};
         HIP_TRY(hipEventRecord(ev[0], s->stream));
-        if (launch_yee(c, s->fwork, f.n)) return fail(PIC_EHIP, "yee");
+        if (launch_yee(c, s->fwork, f.n, s->ywork, s->nywork)) return fail(PIC_EHIP, "yee");
         HIP_TRY(hipEventRecord(ev[1], s->stream));
-        if (launch_seen(c, s->fwork, f.n)) return fail(PIC_EHIP, "seen");
+        if (launch_seen(c, s->fwork, f.n, s->swork, s->nswork)) return fail(PIC_EHIP, "seen");
         HIP_TRY(hipEventRecord(ev[2], s->stream));
         if (launch_particles(c, s->pwork, p.n, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particles");
         HIP_TRY(hipEventRecord(ev[3], s->stream));
@@ -980,17 +1084,13 @@ namespace {
 int snap_copy(pic_state *s, int inst, const Snap &sn, bool save, bool with_j)
 {
     const InstDesc &D = s->desc[inst];
-    const size_t R = s->fp32 ? 4 : 8, nc = (size_t)D.ncell, n = (size_t)D.np;
+    const size_t R = s->fp32 ? 4 : 8;
     const hipMemcpyKind kd = hipMemcpyDeviceToDevice;
     auto cp = [&](void *live, void *snapp, size_t bytes) {
-        if (!bytes || !live || !snapp) return hipSuccess;
         return save ? hipMemcpyAsync(snapp, live, bytes, kd, s->stream) : hipMemcpyAsync(live, snapp, bytes, kd, s->stream);
     };
-    for (int c = 0; c < 3; c++) {
-        HIP_TRY(cp(D.E[c], sn.E[c], nc * R));
-        HIP_TRY(cp(D.B[c], sn.B[c], nc * R));
-        if (with_j) HIP_TRY(cp(D.J[c], sn.J[c], nc * 8));
-    }
+    HIP_TRY(cp(D.E[0], sn.E[0], region_fields(D, R)));
+    if (with_j) HIP_TRY(cp(D.J[0], sn.J[0], region_j(D)));
     return snap_copy_particles(s, inst, sn, save);
 }
 
@@ -1009,9 +1109,44 @@ int gradient_preconditions(pic_state *s)
 int forward_step_eager(pic_state *s)
 {
     LaunchCtx live = ctx(s);
-    if (launch_yee(live, s->fwork, s->nfwork)) return fail(PIC_EHIP, "yee");
-    if (launch_seen(live, s->fwork, s->nfwork)) return fail(PIC_EHIP, "seen");
+    if (launch_yee(live, s->fwork, s->nfwork, s->ywork, s->nywork)) return fail(PIC_EHIP, "yee");
+    if (launch_seen(live, s->fwork, s->nfwork, s->swork, s->nswork)) return fail(PIC_EHIP, "seen");
     if (launch_particles(live, s->pwork, s->npwork, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particles");
+    return PIC_OK;
+}
+
+// recompute m steps from the restored checkpoint while recording the tape,
+// then reverse them
+int enqueue_segment(pic_state *s, int m)
+{
+    LaunchCtx live = ctx(s);
+    int rc = PIC_OK;
+    for (int slot = 0; slot < m && rc == PIC_OK; slot++) {
+        for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy_particles(s, i, s->tape[i][slot], true);
+        if (rc) break;
+        if (launch_yee(live, s->fwork, s->nfwork, s->ywork, s->nywork)) return fail(PIC_EHIP, "yee");
+        for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy_fields(s, i, s->tape[i][slot]);
+        if (rc) break;
+        if (launch_seen(live, s->fwork, s->nfwork, s->swork, s->nswork) ||
+            launch_particles(live, s->pwork, s->npwork, 0, s->block, s->wmax))
+            return fail(PIC_EHIP, "recompute");
+    }
+    for (int slot = m - 1; slot >= 0 && rc == PIC_OK; slot--) {
+        LaunchCtx tp = live;
+        tp.desc = s->d_tape_desc + (size_t)slot * s->n_inst;
+        if (launch_adj_step(live, tp, s->fwork, s->nfwork, s->swork, s->nswork, s->pwork, s->npwork, 256,
+                            s->adj_wmax))
+            rc = fail(PIC_EHIP, "adjoint step");
+    }
+    return rc;
+}
+
+int enqueue_forward_steps(pic_state *s, int m)
+{
+    for (int n = 0; n < m; n++) {
+        int rc = forward_step_eager(s);
+        if (rc) return rc;
+    }
     return PIC_OK;
 }
 
@@ -1026,10 +1161,18 @@ extern "C" int pic_adjoint_forward(pic_state *s, int nsteps, double *loss)
     const int K = s->adj_k, nseg = (nsteps + K - 1) / K;
     s->no_resort = true;      // particle order must stay fixed until the backward sweep
     s->adj_pending = 0;
-    for (int n = 0; n < nsteps && rc == PIC_OK; n++) {
-        if (n % K == 0)
-            for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy(s, i, s->ckpt[i][n / K], true, true);
-        if (rc == PIC_OK) rc = forward_step_eager(s);
+    for (int seg = 0; seg < nseg && rc == PIC_OK; seg++) {
+        for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy(s, i, s->ckpt[i][seg], true, true);
+        if (rc) break;
+        const int m = std::min(K, nsteps - seg * K);
+        if (m == K && s->use_graph) {
+            if (!s->gexec_adj_fwd &&
+                (rc = capture_fn(s, [&]() { return enqueue_forward_steps(s, K); }, &s->gexec_adj_fwd)))
+                break;
+            if (hipGraphLaunch(s->gexec_adj_fwd, s->stream) != hipSuccess) rc = fail(PIC_EHIP, "graph launch");
+        } else {
+            rc = enqueue_forward_steps(s, m);
+        }
     }
     for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy(s, i, s->ckpt[i][nseg], true, true);
     if (rc) { s->no_resort = false; return rc; }
@@ -1055,28 +1198,18 @@ extern "C" int pic_adjoint_backward(pic_state *s, double *grad)
     const int nsteps = s->adj_pending;
     if (nsteps <= 0) return fail(PIC_ESTATE, "pic_adjoint_forward must run first");
     const int K = s->adj_k, nseg = (nsteps + K - 1) / K;
-    LaunchCtx live = ctx(s);
     int rc = PIC_OK;
     for (int seg = nseg - 1; seg >= 0 && rc == PIC_OK; seg--) {
         for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy(s, i, s->ckpt[i][seg], false, true);
-        const int n0 = seg * K, n1 = std::min(nsteps, n0 + K);
-        // recompute the segment, recording its tape
-        for (int n = n0; n < n1 && rc == PIC_OK; n++) {
-            const int slot = n - n0;
-            for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy_particles(s, i, s->tape[i][slot], true);
-            if (rc) break;
-            if (launch_yee(live, s->fwork, s->nfwork)) { rc = fail(PIC_EHIP, "yee"); break; }
-            for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy_fields(s, i, s->tape[i][slot]);
-            if (rc) break;
-            if (launch_seen(live, s->fwork, s->nfwork) ||
-                launch_particles(live, s->pwork, s->npwork, 0, s->block, s->wmax)) { rc = fail(PIC_EHIP, "recompute"); break; }
-        }
-        // reverse its steps
-        for (int n = n1 - 1; n >= n0 && rc == PIC_OK; n--) {
-            LaunchCtx tp = live;
-            tp.desc = s->d_tape_desc + (size_t)(n - n0) * s->n_inst;
-            if (launch_adj_step(live, tp, s->fwork, s->nfwork, s->pwork, s->npwork, 256, s->adj_wmax))
-                rc = fail(PIC_EHIP, "adjoint step");
+        if (rc) break;
+        const int m = std::min(K, nsteps - seg * K);
+        if (m == K && s->use_graph) {
+            if (!s->gexec_adj_seg &&
+                (rc = capture_fn(s, [&]() { return enqueue_segment(s, K); }, &s->gexec_adj_seg)))
+                break;
+            if (hipGraphLaunch(s->gexec_adj_seg, s->stream) != hipSuccess) rc = fail(PIC_EHIP, "graph launch");
+        } else {
+            rc = enqueue_segment(s, m);
         }
     }
     // back to the forward end state

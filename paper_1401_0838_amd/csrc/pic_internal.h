@@ -8,6 +8,7 @@
 #define PIC_MAX_HX 8            // half-width of the x / y filter stencils
 #define PIC_FIELD_CHUNK 256     // cells per field work item
 #define PIC_PART_CHUNK 256      // particles per particle-chunk work item
+#define PIC_SEEN_TX 64          // 2D seen-field tile (x)
 #define PIC_TILE_SLACK 4        // cells a tile's particle bounding box may grow before a re-sort
 
 // device flag slots (per instance)
@@ -56,7 +57,7 @@ struct InstDesc {
     void *J[3];            // long long fixed point (float mode) or double
     double *rho0, *rho;
     // particles
-    int *pidx;             // linear cell index (z * ny + y) * nx + x
+    int *pidx;             // packed cell index: 2D x | z << 16, 3D x | y << 11 | z << 21
     void *poff[3];         // in-cell offsets in [0, 1) per active axis
     void *pu[3];           // momenta
     int *ppid;             // original particle number
@@ -85,10 +86,13 @@ struct LaunchCtx {
     const InstDesc *desc;       // device table
     hipStream_t stream;
     int dims, order, fp32;
+    int yee_tz = 8, seen_tz = 16; // 2D field-kernel tile heights (x width 64)
 };
 
-int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork);
-int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork);
+int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork);
+#define PIC_YEE_TX 64
+int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork);
+size_t seen_smem_bytes(int fp32, int tz);
 int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid, int block,
                      const int wmax[3]);
 size_t particle_smem_bytes(int dims, int fp32, const int wmax[3]);
@@ -104,4 +108,4 @@ int launch_fill_bbox(const LaunchCtx &c, int inst_first, int n_inst);
 size_t adjoint_smem_bytes(int dims, int fp32, const int wmax[3]);
 int launch_adj_seed(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *cwork, int ncwork);
 int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fwork, int nfwork,
-                    const int2 *pwork, int npwork, int block, const int wmax[3]);
+                    const int2 *swork, int nswork, const int2 *pwork, int npwork, int block, const int wmax[3]);

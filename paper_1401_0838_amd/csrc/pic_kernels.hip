@@ -80,32 +80,13 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
     R B1 = interp<1, 0, 1, DIM, L, R>(W, 4, lc, wi, wh);
     R B2 = interp<1, 1, 0, DIM, L, R>(W, 5, lc, wi, wh);
 
-    // Boris (textbook): half electric kick, magnetic rotation, half kick
-    R um0 = u[0] + qdt2m * E0, um1 = u[1] + qdt2m * E1, um2 = u[2] + qdt2m * E2;
-    R igm = R(1) / sqrt(R(1) + um0 * um0 + um1 * um1 + um2 * um2);
-    R t0 = qdt2m * B0 * igm, t1 = qdt2m * B1 * igm, t2 = qdt2m * B2 * igm;
-    R f = R(2) / (R(1) + t0 * t0 + t1 * t1 + t2 * t2);
-    R s0 = f * t0, s1 = f * t1, s2 = f * t2;
-    R up0 = um0 + (um1 * t2 - um2 * t1);
-    R up1 = um1 + (um2 * t0 - um0 * t2);
-    R up2 = um2 + (um0 * t1 - um1 * t0);
-    u[0] = um0 + (up1 * s2 - up2 * s1) + qdt2m * E0;
-    u[1] = um1 + (up2 * s0 - up0 * s2) + qdt2m * E1;
-    u[2] = um2 + (up0 * s1 - up1 * s0) + qdt2m * E2;
-
-    // move in cell units
-    R ig = R(1) / sqrt(R(1) + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        if (DIM == 2 && a == 1) { dc[a] = 0; offn[a] = R(0); continue; }
-        R x1 = off[a] + dtd[a] * u[a] * ig;
-        int c = x1 >= R(1) ? 1 : (x1 < R(0) ? -1 : 0);
-        if (x1 >= R(2) || x1 < R(-1)) { err = 1; x1 = x1 < R(0) ? R(-0.5) : R(1.5); c = x1 < R(0) ? -1 : 1; }
-        R on = x1 - R(c);
-        if (on >= R(1)) { on -= R(1); c += 1; }
-        dc[a] = c;
-        offn[a] = on;
-    }
+    // Boris (textbook): half electric kick, magnetic rotation, half kick; then move
+    const R Ev[3] = {E0, E1, E2}, Bv[3] = {B0, B1, B2};
+    R un[3];
+    BorisTrace<R> bt;
+    boris_push<R>(u, Ev, Bv, qdt2m, un, bt);
+    const R ig = move_cells<DIM, R>(off, un, dtd, dc, offn, err);
+    u[0] = un[0]; u[1] = un[1]; u[2] = un[2];
 
     // Esirkepov: shapes on the L+2 nodes starting at min(old, new) cell - H
     R S0[3][L + 2], DS[3][L + 2];
@@ -156,16 +137,19 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
                 W.add(2, base[0] + i, 0, base[2] + k, jcvt(cdep[2] * acc, tag));
             }
         }
-        // J_y: out of plane, with v_y
-        R cy = cy2d * u[1] * ig;
+        // J_y: out of plane, with v_y.  W_y = S0x (S0z/3 + S1z/6) + S1x (S0z/6 + S1z/3)
+        const R cy = cy2d * u[1] * ig;
 #pragma unroll
-        for (int k = 0; k < L + 2; k++)
+        for (int k = 0; k < L + 2; k++) {
+            const R s1z = S0[2][k] + DS[2][k];
+            const R az = cy * (R(1.0 / 3.0) * S0[2][k] + R(1.0 / 6.0) * s1z);
+            const R bz = cy * (R(1.0 / 6.0) * S0[2][k] + R(1.0 / 3.0) * s1z);
 #pragma unroll
             for (int i = 0; i < L + 2; i++) {
-                R wy = S0[0][i] * S0[2][k] + R(0.5) * DS[0][i] * S0[2][k] + R(0.5) * S0[0][i] * DS[2][k]
-                     + R(1.0 / 3.0) * DS[0][i] * DS[2][k];
-                W.add(1, base[0] + i, 0, base[2] + k, jcvt(cy * wy, tag));
+                const R wy = S0[0][i] * az + (S0[0][i] + DS[0][i]) * bz;
+                W.add(1, base[0] + i, 0, base[2] + k, jcvt(wy, tag));
             }
+        }
     } else {
         // J_x
 #pragma unroll
@@ -214,7 +198,8 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 
 // ------------------------------------------------------------ particle kernel
 
-template <int DIM, int L, class R>
+// P > 0 (2D only): LDS windows use the fixed row pitch P and plane size P*P
+template <int DIM, int L, class R, int P>
 __global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                    int nwork, int wmx, int wmy, int wmz)
 {
@@ -239,23 +224,25 @@ __global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ 
             wn[a] = ext[a] + L + 2;
         }
         const bool fits = wn[0] <= wmx && wn[1] <= wmy && wn[2] <= wmz;
-        const int wc = wn[0] * wn[1] * wn[2];
+        // plane stride and row pitch of the LDS windows
+        const int wc = P > 0 ? P * P : wn[0] * wn[1] * wn[2];
+        const int pitch = P > 0 ? P : wn[0];
         JT *sJ = reinterpret_cast<JT *>(smem);
         R *sF = reinterpret_cast<R *>(smem + (size_t)3 * wmx * wmy * wmz * sizeof(JT));
 
         if (tid < 3) { sbox[tid] = INT_MAX; sbox[3 + tid] = INT_MIN; }
         if (fits) {
-            const R *src[6] = {(const R *)D.Et[0], (const R *)D.Et[1], (const R *)D.Et[2],
-                               (const R *)D.Bt[0], (const R *)D.Bt[1], (const R *)D.Bt[2]};
-            for (int c = tid; c < wc; c += bs) {
-                int x = c % wn[0], r = c / wn[0];
-                int y = r % wn[1], z = r / wn[1];
-                const int gx = (o[0] + x) % D.n[0], gy = (o[1] + y) % D.n[1], gz = (o[2] + z) % D.n[2];
-                const int g = (gz * D.n[1] + gy) * D.n[0] + gx;
+            gp<const R> src[6] = {G<R>((const void *)D.Et[0]), G<R>((const void *)D.Et[1]),
+                                  G<R>((const void *)D.Et[2]), G<R>((const void *)D.Bt[0]),
+                                  G<R>((const void *)D.Bt[1]), G<R>((const void *)D.Bt[2])};
+            const int nwin = wn[0] * wn[1] * wn[2];
+            for (int c = tid; c < nwin; c += bs) {
+                const int g = window_cell(c, wn, o, D.n);
+                const int l = P > 0 ? (c / wn[0]) * P + c % wn[0] : c;
 #pragma unroll
-                for (int k = 0; k < 6; k++) sF[k * wc + c] = src[k][g];
+                for (int k = 0; k < 6; k++) sF[k * wc + l] = src[k][g];
 #pragma unroll
-                for (int k = 0; k < 3; k++) sJ[k * wc + c] = JT(0);
+                for (int k = 0; k < 3; k++) sJ[k * wc + l] = JT(0);
             }
         } else if (tid == 0) {
             atomicAdd(&D.flags[FLAG_SLOW], 1);
@@ -266,26 +253,28 @@ __global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ 
         const R dtd[3] = {(R)D.dtd[0], (R)D.dtd[1], (R)D.dtd[2]};
         const R cdep[3] = {(R)D.cdep[0], (R)D.cdep[1], (R)D.cdep[2]};
         const R qdt2m = (R)D.qdt2m, cy2d = (R)D.cy2d;
-        R *poff[3] = {(R *)D.poff[0], (R *)D.poff[1], (R *)D.poff[2]};
-        R *pu[3] = {(R *)D.pu[0], (R *)D.pu[1], (R *)D.pu[2]};
+        gp<R> poff[3] = {G<R>(D.poff[0]), G<R>(D.poff[1]), G<R>(D.poff[2])};
+        gp<R> pu[3] = {G<R>(D.pu[0]), G<R>(D.pu[1]), G<R>(D.pu[2])};
+        gp<unsigned> pidx = G<unsigned>(D.pidx);
         int bmin[3] = {INT_MAX, INT_MAX, INT_MAX}, bmax[3] = {INT_MIN, INT_MIN, INT_MIN};
         int err = 0;
 
-        LdsWin<R, JT> lw{sF, sJ, wn[0], wn[0] * wn[1], wc};
+        LdsWin<R, JT> lw{sF, sJ, pitch, pitch * wn[1], wc};
+        LdsWinP<R, JT, (P > 0 ? P : 1)> lwp{sF, sJ};
         GlbWin<R, JT> gw;
         if (!fits) {
-            gw.F[0] = (const R *)D.Et[0]; gw.F[1] = (const R *)D.Et[1]; gw.F[2] = (const R *)D.Et[2];
-            gw.F[3] = (const R *)D.Bt[0]; gw.F[4] = (const R *)D.Bt[1]; gw.F[5] = (const R *)D.Bt[2];
-            for (int k = 0; k < 3; k++) { gw.J[k] = (JT *)D.J[k]; gw.o[k] = o[k]; gw.n[k] = D.n[k]; }
+            for (int k = 0; k < 3; k++) {
+                gw.F[k] = G<R>((const void *)D.Et[k]);
+                gw.F[3 + k] = G<R>((const void *)D.Bt[k]);
+                gw.J[k] = G<JT>(D.J[k]);
+                gw.o[k] = o[k];
+                gw.n[k] = D.n[k];
+            }
         }
 
         for (int p = p0 + tid; p < p1; p += bs) {
-            const int idx = D.pidx[p];
             int c[3];
-            c[0] = idx % D.n[0];
-            const int r = idx / D.n[0];
-            c[1] = r % D.n[1];
-            c[2] = r / D.n[1];
+            unpack_cell<DIM>(pidx[p], c);
             int lc[3];
             R off[3], u[3], offn[3];
             int dc[3];
@@ -298,9 +287,10 @@ __global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ 
                 off[a] = poff[a][p];
             }
             u[0] = pu[0][p]; u[1] = pu[1][p]; u[2] = pu[2][p];
-            if (fits)
-                push_particle<DIM, L, R, JT>(lw, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
-            else
+            if (fits) {
+                if constexpr (P > 0) push_particle<DIM, L, R, JT>(lwp, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
+                else push_particle<DIM, L, R, JT>(lw, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
+            } else
                 push_particle<DIM, L, R, JT>(gw, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
             int nc[3];
 #pragma unroll
@@ -314,7 +304,7 @@ __global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ 
                 bmax[a] = max(bmax[a], l1);
             }
             pu[0][p] = u[0]; pu[1][p] = u[1]; pu[2][p] = u[2];
-            D.pidx[p] = (nc[2] * D.n[1] + nc[1]) * D.n[0] + nc[0];
+            pidx[p] = pack_cell<DIM>(nc[0], nc[1], nc[2]);
         }
         if (err) atomicExch(&D.flags[FLAG_PERR], 1);
         // bounding box of the moved particles (window-local coordinates)
@@ -325,16 +315,15 @@ __global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ 
         }
         __syncthreads();
         if (fits) {
-            JT *gJ[3] = {(JT *)D.J[0], (JT *)D.J[1], (JT *)D.J[2]};
-            for (int c = tid; c < wc; c += bs) {
-                int x = c % wn[0], r = c / wn[0];
-                int y = r % wn[1], z = r / wn[1];
-                const int gx = (o[0] + x) % D.n[0], gy = (o[1] + y) % D.n[1], gz = (o[2] + z) % D.n[2];
-                const int g = (gz * D.n[1] + gy) * D.n[0] + gx;
+            gp<JT> gJ[3] = {G<JT>(D.J[0]), G<JT>(D.J[1]), G<JT>(D.J[2])};
+            const int nwin = wn[0] * wn[1] * wn[2];
+            for (int c = tid; c < nwin; c += bs) {
+                const int g = window_cell(c, wn, o, D.n);
+                const int l = P > 0 ? (c / wn[0]) * P + c % wn[0] : c;
 #pragma unroll
                 for (int k = 0; k < 3; k++) {
-                    JT v = sJ[k * wc + c];
-                    if (v != JT(0)) jadd(&gJ[k][g], v);
+                    JT v = sJ[k * wc + l];
+                    if (v != JT(0)) gatomic_add(gJ[k] + g, v);
                 }
             }
         }
@@ -438,6 +427,90 @@ __global__ void __launch_bounds__(256) k_yee_e(const InstDesc *__restrict__ Dt, 
     J0[cell] = JT(0); J1[cell] = JT(0); J2[cell] = JT(0);
 }
 
+// Fused 2D Yee update: B half step, E step (J read and cleared), B half step
+// for a (YEE_TX x TZ) tile in one pass.  LDS windows, in global coordinates
+// relative to the tile origin (x0, z0):
+//   E^{n-1} on [-1, T+1], B^{n-1} on [-1, T], J on [0, T]
+// B^{n-1/2} is formed on [-1, T], E^n on [0, T], B^n and the stores on [0, T).
+#define YEE_TX PIC_YEE_TX
+
+template <class R, int TZ>
+__global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    typedef typename JOf<R>::T JT;
+    constexpr int TX = YEE_TX;
+    constexpr int EX = TX + 3, EZ = TZ + 3, BX = TX + 2, BZ = TZ + 2, JX = TX + 1, JZ = TZ + 1;
+    __shared__ R sE[3][EZ * EX], sB[3][BZ * BX], sJ[3][JZ * JX];
+    const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
+    const InstDesc &D = Dt[inst];
+    const int nx = D.n[0], nz = D.n[2];
+    const int ntx = (nx + TX - 1) / TX;
+    const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
+    const int tid = threadIdx.x;
+    auto wrapx = [&](int g) { g += g < 0 ? nx : 0; g -= g >= nx ? nx : 0; return (g < 0 || g >= nx) ? ((g % nx) + nx) % nx : g; };
+    auto wrapz = [&](int g) { g += g < 0 ? nz : 0; g -= g >= nz ? nz : 0; return (g < 0 || g >= nz) ? ((g % nz) + nz) % nz : g; };
+    gp<R> E[3] = {G<R>(D.E[0]), G<R>(D.E[1]), G<R>(D.E[2])};
+    gp<R> B[3] = {G<R>(D.B[0]), G<R>(D.B[1]), G<R>(D.B[2])};
+    gp<JT> J[3] = {G<JT>(D.J[0]), G<JT>(D.J[1]), G<JT>(D.J[2])};
+    for (int c = tid; c < EZ * EX; c += blockDim.x) {
+        const int lz = c / EX, lx = c - lz * EX;
+        const int g = wrapz(z0 - 1 + lz) * nx + wrapx(x0 - 1 + lx);
+        sE[0][c] = E[0][g]; sE[1][c] = E[1][g]; sE[2][c] = E[2][g];
+    }
+    for (int c = tid; c < BZ * BX; c += blockDim.x) {
+        const int lz = c / BX, lx = c - lz * BX;
+        const int g = wrapz(z0 - 1 + lz) * nx + wrapx(x0 - 1 + lx);
+        sB[0][c] = B[0][g]; sB[1][c] = B[1][g]; sB[2][c] = B[2][g];
+    }
+    for (int c = tid; c < JZ * JX; c += blockDim.x) {
+        const int lz = c / JX, lx = c - lz * JX;
+        const int g = wrapz(z0 + lz) * nx + wrapx(x0 + lx);
+#pragma unroll
+        for (int k = 0; k < 3; k++) sJ[k][c] = (R)(jreal(J[k][g], D.jq) + D.jbg[k]);
+    }
+    __syncthreads();
+    const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
+    // B^{n-1/2} on the B window: forward differences of E (E local index = B local index)
+    for (int c = tid; c < BZ * BX; c += blockDim.x) {
+        const int lz = c / BX, lx = c - lz * BX;
+        const int e = lz * EX + lx, ex = e + 1, ez = e + EX;
+        const R dzEy = (sE[1][ez] - sE[1][e]) * idz, dzEx = (sE[0][ez] - sE[0][e]) * idz;
+        const R dxEz = (sE[2][ex] - sE[2][e]) * idx, dxEy = (sE[1][ex] - sE[1][e]) * idx;
+        sB[0][c] -= h * (-dzEy);
+        sB[1][c] -= h * (dzEx - dxEz);
+        sB[2][c] -= h * dxEy;
+    }
+    __syncthreads();
+    // E^n on [0, T]: backward differences of B^{n-1/2}; J local = E local - 1
+    for (int c = tid; c < JZ * JX; c += blockDim.x) {
+        const int lz = c / JX, lx = c - lz * JX;
+        const int b = (lz + 1) * BX + lx + 1, bxm = b - 1, bzm = b - BX;
+        const int e = (lz + 1) * EX + lx + 1;
+        const R dzBy = (sB[1][b] - sB[1][bzm]) * idz, dzBx = (sB[0][b] - sB[0][bzm]) * idz;
+        const R dxBz = (sB[2][b] - sB[2][bxm]) * idx, dxBy = (sB[1][b] - sB[1][bxm]) * idx;
+        sE[0][e] += dt * (-dzBy - sJ[0][c]);
+        sE[1][e] += dt * (dzBx - dxBz - sJ[1][c]);
+        sE[2][e] += dt * (dxBy - sJ[2][c]);
+    }
+    __syncthreads();
+    // B^n on [0, T) and the stores
+    for (int c = tid; c < TZ * TX; c += blockDim.x) {
+        const int lz = c / TX, lx = c - lz * TX;
+        const int gx = x0 + lx, gz = z0 + lz;
+        if (gx >= nx || gz >= nz) continue;
+        const int e = (lz + 1) * EX + lx + 1, ex = e + 1, ez = e + EX;
+        const int b = (lz + 1) * BX + lx + 1;
+        const R dzEy = (sE[1][ez] - sE[1][e]) * idz, dzEx = (sE[0][ez] - sE[0][e]) * idz;
+        const R dxEz = (sE[2][ex] - sE[2][e]) * idx, dxEy = (sE[1][ex] - sE[1][e]) * idx;
+        const int g = gz * nx + gx;
+        B[0][g] = sB[0][b] - h * (-dzEy);
+        B[1][g] = sB[1][b] - h * (dzEx - dxEz);
+        B[2][g] = sB[2][b] - h * dxEy;
+        E[0][g] = sE[0][e]; E[1][g] = sE[1][e]; E[2][g] = sE[2][e];
+        J[0][g] = JT(0); J[1][g] = JT(0); J[2][g] = JT(0);
+    }
+}
+
 // ------------------------------------------------------ seen-field passes
 // axis 2: combined z taps (tz[0] for Ex, Ey; tz[1] for Ez, Bx, By, Bz)
 // axis 0 / 1: filter taps along x / y.  blockIdx.y selects the component.
@@ -491,25 +564,89 @@ __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ 
     dst[cell] = acc;
 }
 
-// ------------------------------------------------------------------ resort
-
-__device__ __forceinline__ int tile_of(const InstDesc &D, int idx)
+// 2D fields as seen by the particles in one kernel: a (SX x SZ) output tile of
+// one component is loaded with its stencil halo into LDS, the combined z
+// stencil (Psi o z filter) is applied into a second LDS tile, then the x
+// filter stencil writes the output.  blockIdx.y = component, work = (inst, tile).
+#define SEEN_TX PIC_SEEN_TX
+template <class R, int SEEN_TZ>
+__global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
 {
-    const int cx = idx % D.n[0];
-    const int r = idx / D.n[0];
-    const int cy = r % D.n[1], cz = r / D.n[1];
-    return (cz / D.tile[2] * D.nt[1] + cy / D.tile[1]) * D.nt[0] + cx / D.tile[0];
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
+    const int comp = blockIdx.y;
+    const InstDesc &D = Dt[inst];
+    const int nx = D.n[0], nz = D.n[2];
+    const int ntx = (nx + SEEN_TX - 1) / SEEN_TX;
+    const int x0 = (t % ntx) * SEEN_TX, z0 = (t / ntx) * SEEN_TZ;
+    const int hz = D.hz, hx = D.hx;
+    const int wx = SEEN_TX + 2 * hx, wz = SEEN_TZ + 2 * hz;
+    R *win = reinterpret_cast<R *>(smem);
+    R *mid = win + wx * wz;
+    R *tz = mid + wx * SEEN_TZ;
+    R *tx = tz + 2 * PIC_MAX_HZ + 1;
+    const double *tzs = D.tz[comp < 2 ? 0 : 1];
+    for (int i = threadIdx.x; i <= 2 * hz; i += blockDim.x) tz[i] = (R)tzs[i];
+    for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)D.tx[i];
+    gp<const R> src = G<R>((const void *)(comp < 3 ? D.E[comp] : D.B[comp - 3]));
+    for (int c = threadIdx.x; c < wx * wz; c += blockDim.x) {
+        const int zz = (int)(((float)c + 0.5f) * (1.0f / (float)wx));
+        const int xx = c - zz * wx;
+        int gx = x0 - hx + xx, gz = z0 - hz + zz;
+        gx += gx < 0 ? nx : 0; gx -= gx >= nx ? nx : 0;
+        gz += gz < 0 ? nz : 0; gz -= gz >= nz ? nz : 0;
+        if (gx < 0 || gx >= nx) gx = ((gx % nx) + nx) % nx;
+        if (gz < 0 || gz >= nz) gz = ((gz % nz) + nz) % nz;
+        win[c] = src[gz * nx + gx];
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < wx * SEEN_TZ; c += blockDim.x) {
+        const int zz = (int)(((float)c + 0.5f) * (1.0f / (float)wx));
+        const int xx = c - zz * wx;
+        R acc = R(0);
+        for (int k = 0; k <= 2 * hz; k++) acc += tz[k] * win[(zz + k) * wx + xx];
+        mid[c] = acc;
+    }
+    __syncthreads();
+    gp<R> dst = G<R>(comp < 3 ? D.Et[comp] : D.Bt[comp - 3]);
+    for (int c = threadIdx.x; c < SEEN_TX * SEEN_TZ; c += blockDim.x) {
+        const int zz = c / SEEN_TX, xx = c % SEEN_TX;
+        const int gx = x0 + xx, gz = z0 + zz;
+        if (gx >= nx || gz >= nz) continue;
+        R acc = R(0);
+        for (int k = 0; k <= 2 * hx; k++) acc += tx[k] * mid[zz * wx + xx + k];
+        dst[gz * nx + gx] = acc;
+    }
 }
 
-__global__ void __launch_bounds__(256) k_resort_count(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+// ------------------------------------------------------------------ resort
+
+template <int DIM> __device__ __forceinline__ int tile_of(const InstDesc &D, unsigned idx)
 {
-    const InstDesc &D = Dt[work[blockIdx.x].x];
-    if (!D.flags[FLAG_RESORT]) return;
-    const long long p = (long long)work[blockIdx.x].y * PIC_PART_CHUNK + threadIdx.x;
-    if (p >= D.np) return;
-    const int t = tile_of(D, D.pidx[p]);
-    D.stile[p] = t;
-    D.srank[p] = atomicAdd(&D.tcount[t], 1);
+    int c[3];
+    unpack_cell<DIM>(idx, c);
+    return (c[2] / D.tile[2] * D.nt[1] + c[1] / D.tile[1]) * D.nt[0] + c[0] / D.tile[0];
+}
+
+// the re-sort kernels walk RESORT_ITEMS consecutive work items per block so
+// that their launches (made every few steps, mostly finding nothing to do)
+// stay small
+#define RESORT_ITEMS 16
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_resort_count(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                                      int nwork)
+{
+    const int it1 = min(nwork, (int)(blockIdx.x + 1) * RESORT_ITEMS);
+    for (int it = blockIdx.x * RESORT_ITEMS; it < it1; it++) {
+        const InstDesc &D = Dt[work[it].x];
+        if (!D.flags[FLAG_RESORT]) continue;
+        const long long p = (long long)work[it].y * PIC_PART_CHUNK + threadIdx.x;
+        if (p >= D.np) continue;
+        const int t = tile_of<DIM>(D, (unsigned)D.pidx[p]);
+        D.stile[p] = t;
+        D.srank[p] = atomicAdd(&D.tcount[t], 1);
+    }
 }
 
 // one 1024-thread block per instance: exclusive scan of the tile counts
@@ -541,12 +678,15 @@ __global__ void __launch_bounds__(1024) k_resort_scan(const InstDesc *__restrict
 }
 
 template <int DIM, class R>
-__global__ void __launch_bounds__(256) k_resort_scatter(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+__global__ void __launch_bounds__(256) k_resort_scatter(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                                        int nwork)
 {
-    const InstDesc &D = Dt[work[blockIdx.x].x];
-    if (!D.flags[FLAG_RESORT]) return;
-    const long long p = (long long)work[blockIdx.x].y * PIC_PART_CHUNK + threadIdx.x;
-    if (p >= D.np) return;
+    const int it1 = min(nwork, (int)(blockIdx.x + 1) * RESORT_ITEMS);
+    for (int it = blockIdx.x * RESORT_ITEMS; it < it1; it++) {
+    const InstDesc &D = Dt[work[it].x];
+    if (!D.flags[FLAG_RESORT]) continue;
+    const long long p = (long long)work[it].y * PIC_PART_CHUNK + threadIdx.x;
+    if (p >= D.np) continue;
     const int q = D.tstart[D.stile[p]] + D.srank[p];
     D.sidx[q] = D.pidx[p];
     D.spid[q] = D.ppid[p];
@@ -555,21 +695,26 @@ __global__ void __launch_bounds__(256) k_resort_scatter(const InstDesc *__restri
         if (!(DIM == 2 && a == 1)) ((R *)D.soff[a])[q] = ((const R *)D.poff[a])[p];
         ((R *)D.su[a])[q] = ((const R *)D.pu[a])[p];
     }
+    }
 }
 
 template <int DIM, class R>
-__global__ void __launch_bounds__(256) k_resort_copy(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+__global__ void __launch_bounds__(256) k_resort_copy(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                                     int nwork)
 {
-    const InstDesc &D = Dt[work[blockIdx.x].x];
-    if (!D.flags[FLAG_RESORT]) return;
-    const long long p = (long long)work[blockIdx.x].y * PIC_PART_CHUNK + threadIdx.x;
-    if (p >= D.np) return;
+    const int it1 = min(nwork, (int)(blockIdx.x + 1) * RESORT_ITEMS);
+    for (int it = blockIdx.x * RESORT_ITEMS; it < it1; it++) {
+    const InstDesc &D = Dt[work[it].x];
+    if (!D.flags[FLAG_RESORT]) continue;
+    const long long p = (long long)work[it].y * PIC_PART_CHUNK + threadIdx.x;
+    if (p >= D.np) continue;
     D.pidx[p] = D.sidx[p];
     D.ppid[p] = D.spid[p];
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         if (!(DIM == 2 && a == 1)) ((R *)D.poff[a])[p] = ((const R *)D.soff[a])[p];
         ((R *)D.pu[a])[p] = ((const R *)D.su[a])[p];
+    }
     }
 }
 
@@ -605,30 +750,43 @@ __device__ __forceinline__ void block_sum_to(double v, double *dst)
     if ((threadIdx.x & 63) == 0 && v != 0.0) unsafeAtomicAdd(dst, v);
 }
 
+#define ENERGY_ITEMS 16
+
+// 1/2 sum E_c^2 dV and 1/2 sum B_c^2 dV; a block covers ENERGY_ITEMS field
+// chunks (all of one instance or split where instances change)
 template <class R>
 __global__ void __launch_bounds__(256) k_energy(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                                double *out, int out_stride, const int *pos, int cap)
+                                                int nwork, double *out, int out_stride, const int *pos, int cap)
 {
-    const int inst = work[blockIdx.x].x;
-    const InstDesc &D = Dt[inst];
-    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    const int it0 = blockIdx.x * ENERGY_ITEMS, it1 = min(nwork, it0 + ENERGY_ITEMS);
+    int inst = work[it0].x;
     double v[6] = {0, 0, 0, 0, 0, 0};
     double bad = 0.0;
-    if (cell < D.ncell) {
-        for (int c = 0; c < 3; c++) {
-            const double e = (double)((const R *)D.E[c])[cell];
-            const double b = (double)((const R *)D.B[c])[cell];
-            v[c] = e * e;
-            v[3 + c] = b * b;
-            if (!isfinite(e) || !isfinite(b)) bad = 1.0;
+    for (int it = it0; it <= it1; it++) {
+        const bool flush = it == it1 || work[it].x != inst;
+        if (flush) {
+            // wave-uniform: every lane sees the same item sequence
+            const InstDesc &D = Dt[inst];
+            double *dst = pos ? out + ((size_t)(*pos % cap) * out_stride + inst) * 6 : D.diag;
+            const double h = 0.5 * D.dV;
+            for (int c = 0; c < 6; c++) { block_sum_to(h * v[c], dst + c); v[c] = 0.0; }
+            if (!pos) block_sum_to(bad, D.diag + DG_NONFIN);
+            bad = 0.0;
+            if (it == it1) break;
+            inst = work[it].x;
+        }
+        const InstDesc &D = Dt[inst];
+        const int cell = work[it].y * PIC_FIELD_CHUNK + threadIdx.x;
+        if (cell < D.ncell) {
+            for (int c = 0; c < 3; c++) {
+                const double e = (double)G<R>((const void *)D.E[c])[cell];
+                const double b = (double)G<R>((const void *)D.B[c])[cell];
+                v[c] += e * e;
+                v[3 + c] += b * b;
+                if (!isfinite(e) || !isfinite(b)) bad = 1.0;
+            }
         }
     }
-    double *dst;
-    if (pos) dst = out + ((size_t)(*pos % cap) * out_stride + inst) * 6;   // trace rows
-    else dst = D.diag;
-    const double h = 0.5 * D.dV;
-    for (int c = 0; c < 6; c++) block_sum_to(h * v[c], dst + c);
-    if (!pos) block_sum_to(bad, D.diag + DG_NONFIN);
 }
 
 // charge density (order-L shape on integer nodes) of the current particles,
@@ -641,12 +799,8 @@ __global__ void __launch_bounds__(256) k_rho(const InstDesc *__restrict__ Dt, co
     const long long p = (long long)work[blockIdx.x].y * PIC_PART_CHUNK + threadIdx.x;
     double kin = 0.0, bad = 0.0;
     if (p < D.np) {
-        const int idx = D.pidx[p];
         int c[3];
-        c[0] = idx % D.n[0];
-        const int r = idx / D.n[0];
-        c[1] = r % D.n[1];
-        c[2] = r / D.n[1];
+        unpack_cell<DIM>((unsigned)D.pidx[p], c);
         double w[3][L + 1];
         for (int a = 0; a < 3; a++) {
             if (DIM == 2 && a == 1) continue;
@@ -754,15 +908,25 @@ inline int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : -1; }
 #define DISPATCH_R(fp32, ...) \
     do { if (fp32) { typedef float R; __VA_ARGS__; } else { typedef double R; __VA_ARGS__; } } while (0)
 
-int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork)
+template <class R> void launch_yee_2d(const LaunchCtx &c, const int2 *ywork, int nywork)
+{
+    const dim3 g(nywork), b(PIC_FIELD_CHUNK);
+    if (c.yee_tz == 4) k_yee_2d<R, 4><<<g, b, 0, c.stream>>>(c.desc, ywork);
+    else if constexpr (sizeof(R) == 4) {
+        if (c.yee_tz == 16) k_yee_2d<R, 16><<<g, b, 0, c.stream>>>(c.desc, ywork);
+        else k_yee_2d<R, 8><<<g, b, 0, c.stream>>>(c.desc, ywork);
+    } else {
+        k_yee_2d<R, 8><<<g, b, 0, c.stream>>>(c.desc, ywork);   // 16 rows of doubles exceed the LDS
+    }
+}
+
+int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork)
 {
     if (nwork <= 0) return 0;
     dim3 g(nwork), b(PIC_FIELD_CHUNK);
     DISPATCH_R(c.fp32, {
         if (c.dims == 2) {
-            k_yee_b<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
-            k_yee_e<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
-            k_yee_b<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
+            launch_yee_2d<R>(c, ywork, nywork);
         } else {
             k_yee_b<3, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
             k_yee_e<3, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
@@ -772,15 +936,24 @@ int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork)
     return hip_ok(hipGetLastError());
 }
 
-int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork)
+size_t seen_smem_bytes(int fp32, int tz)
+{
+    const int wx = SEEN_TX + 2 * PIC_MAX_HX, wz = tz + 2 * PIC_MAX_HZ;
+    return (size_t)(wx * wz + wx * tz + 2 * PIC_MAX_HZ + 1 + 2 * PIC_MAX_HX + 1) * (fp32 ? 4 : 8);
+}
+
+int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork)
 {
     if (nwork <= 0) return 0;
     dim3 g(nwork, 6), b(PIC_FIELD_CHUNK);
     DISPATCH_R(c.fp32, {
-        k_seen_pass<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1);
         if (c.dims == 2) {
-            k_seen_pass<0, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 0);
+            const size_t sm = seen_smem_bytes(c.fp32, c.seen_tz);
+            if (c.seen_tz == 8) k_seen_2d<R, 8><<<dim3(nswork, 6), b, sm, c.stream>>>(c.desc, swork);
+            else if (c.seen_tz == 16) k_seen_2d<R, 16><<<dim3(nswork, 6), b, sm, c.stream>>>(c.desc, swork);
+            else k_seen_2d<R, 32><<<dim3(nswork, 6), b, sm, c.stream>>>(c.desc, swork);
         } else {
+            k_seen_pass<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1);
             k_seen_pass<0, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2);
             k_seen_pass<1, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 2, 0);
         }
@@ -802,12 +975,17 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
     const int wm[3] = {wmax[0], wy, wmax[2]};
     const size_t smem = particle_smem_bytes(c.dims, c.fp32, wm);
     dim3 g(grid > 0 ? grid : nwork), b(block);
-#define PK(D_, L_) k_particles<D_, L_, R><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2])
+#define PK(D_, L_, P_) k_particles<D_, L_, R, P_><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2])
     DISPATCH_R(c.fp32, {
-        if (c.dims == 2 && c.order == 1) PK(2, 1);
-        else if (c.dims == 2 && c.order == 3) PK(2, 3);
-        else if (c.dims == 3 && c.order == 1) PK(3, 1);
-        else PK(3, 3);
+        if (c.dims == 2 && c.order == 1) {
+            if (wm[0] == 24 && wm[2] == 24) PK(2, 1, 24);
+            else if (wm[0] == 32 && wm[2] == 32) PK(2, 1, 32);
+            else PK(2, 1, 0);
+        } else if (c.dims == 2 && c.order == 3) {
+            if (wm[0] == 32 && wm[2] == 32) PK(2, 3, 32);
+            else PK(2, 3, 0);
+        } else if (c.dims == 3 && c.order == 1) PK(3, 1, 0);
+        else PK(3, 3, 0);
     });
 #undef PK
     return hip_ok(hipGetLastError());
@@ -816,16 +994,17 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
 int launch_resort(const LaunchCtx &c, const int2 *cwork, int ncwork, int inst0, int n_inst)
 {
     if (ncwork <= 0) return 0;
-    dim3 g(ncwork), b(PIC_PART_CHUNK);
-    k_resort_count<<<g, b, 0, c.stream>>>(c.desc, cwork);
+    dim3 g((ncwork + RESORT_ITEMS - 1) / RESORT_ITEMS), b(PIC_PART_CHUNK);
+    if (c.dims == 2) k_resort_count<2><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork);
+    else k_resort_count<3><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork);
     k_resort_scan<<<dim3(n_inst), dim3(1024), 0, c.stream>>>(c.desc, inst0);
     DISPATCH_R(c.fp32, {
         if (c.dims == 2) {
-            k_resort_scatter<2, R><<<g, b, 0, c.stream>>>(c.desc, cwork);
-            k_resort_copy<2, R><<<g, b, 0, c.stream>>>(c.desc, cwork);
+            k_resort_scatter<2, R><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork);
+            k_resort_copy<2, R><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork);
         } else {
-            k_resort_scatter<3, R><<<g, b, 0, c.stream>>>(c.desc, cwork);
-            k_resort_copy<3, R><<<g, b, 0, c.stream>>>(c.desc, cwork);
+            k_resort_scatter<3, R><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork);
+            k_resort_copy<3, R><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork);
         }
     });
     k_resort_done<<<dim3(n_inst), dim3(256), 0, c.stream>>>(c.desc, inst0, 0);
@@ -864,7 +1043,8 @@ int launch_diag(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *c
     if (nfwork <= 0) return 0;
     dim3 g(nfwork), b(PIC_FIELD_CHUNK);
     DISPATCH_R(c.fp32, {
-        k_energy<R><<<g, b, 0, c.stream>>>(c.desc, fwork, nullptr, 0, nullptr, 1);
+        k_energy<R><<<dim3((nfwork + ENERGY_ITEMS - 1) / ENERGY_ITEMS), b, 0, c.stream>>>(c.desc, fwork, nfwork,
+                                                                                      nullptr, 0, nullptr, 1);
         if (c.dims == 2) k_gauss<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
         else k_gauss<3, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
     });
@@ -876,7 +1056,8 @@ int launch_trace_rows(const LaunchCtx &c, const int2 *fwork, int nfwork, int *po
 {
     if (nfwork <= 0 || cap <= 0) return 0;
     DISPATCH_R(c.fp32, {
-        k_energy<R><<<dim3(nfwork), dim3(PIC_FIELD_CHUNK), 0, c.stream>>>(c.desc, fwork, trace, n_inst, pos, cap);
+        k_energy<R><<<dim3((nfwork + ENERGY_ITEMS - 1) / ENERGY_ITEMS), dim3(PIC_FIELD_CHUNK), 0, c.stream>>>(
+            c.desc, fwork, nfwork, trace, n_inst, pos, cap);
     });
     k_trace_tick<<<dim3(1), dim3(256), 0, c.stream>>>(pos, trace, n_inst, cap);
     return hip_ok(hipGetLastError());

@@ -128,6 +128,12 @@ class Simulation:
         L.pic_set_schedule(self.st, L.PIC_SCHED_BATCHED if sched == "batched" else L.PIC_SCHED_PLAIN,
                            1 if use_graph else 0)
 
+    def set_option(self, name, value):
+        L.pic_set_option(self.st, name, value)
+
+    def get_option(self, name):
+        return L.pic_get_option(self.st, name)
+
     def synchronize(self):
         self.stream.synchronize()
 
