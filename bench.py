@@ -107,6 +107,35 @@ def batched_block(steps, warmup):
     return out
 
 
+def beam3d_block(steps, warmup):
+    """3D 128x128x256, 8 ppc (33.5M particles), cubic shapes, correction + filter,
+    FP32: particle-steps/s and the particle kernel's HBM fraction (this case is
+    bound by VALU and LDS atomics, not HBM: ~250 gathered nodes and 300 current
+    updates per particle)."""
+    import pic_inputs as pi
+    from paper_1401_0838_amd.sim import Simulation
+    wl = pi.workload("beam3d_128x128x256")
+    x, u = pi.load_beam(3, wl["n"], wl["ppc"], wl["gamma"], wl["sigma"], 0)
+    sim = Simulation(wl, (x, u), precision="fp32")
+    n_part = x.shape[0]
+    n_cells = wl["n"][0] * wl["n"][1] * wl["n"][2]
+    del x, u
+    sim.step(warmup)
+    sim.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    dt = time.perf_counter() - t0
+    prof = sim.profile(5)
+    d = sim.diag()
+    sim.close()
+    pk = particle_kernel_bytes(n_part, n_cells, state_bytes=28)
+    return {"particles": n_part, "cells": n_cells, "particle_steps_per_s": n_part * steps / dt,
+            "ms_per_step": 1e3 * dt / steps, "kernels_ms": {k: prof[k] for k in ("yee_ms", "seen_ms", "particle_ms")},
+            "particle_kernel_hbm_frac": pk / (prof["particle_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "gauss_linf_rel": d["gauss_linf"] / max(d["rho_max"], 1e-300), "slow_tiles": d["slow_tiles"]}
+
+
 def adjoint_block():
     """256x256, 8 ppc, 200 steps, checkpoints every 20 (FP32): backward (recompute +
     reverse sweep) time over forward time."""
@@ -135,6 +164,23 @@ def adjoint_block():
             "forward_with_checkpoints_s": t_f, "backward_s": t_b, "ratio": t_b / t_step}
 
 
+def copy_calibration(gib=1.0, reps=5):
+    """A plain device-to-device copy of known size, for scaling the HBM counters
+    (FETCH_SIZE / WRITE_SIZE) of a profiler run into bytes."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_each_way": 4 * n, "reps": reps, "GBps_read_plus_write": 8 * n / dt / 1e9}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,7 +191,13 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost ratio")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D cubic case")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the domain would shard along z with halo exchange; see the design notes)", file=sys.stderr)
@@ -213,6 +265,8 @@ def main():
         out["batched"] = batched_block(max(20, args.steps // 4), 5)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_block()
+    if not args.no_3d:
+        out["beam3d"] = beam3d_block(20, 3)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, x, u, args.cpu_steps)
     print(json.dumps(out), flush=True)

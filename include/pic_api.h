@@ -170,6 +170,8 @@ int pic_set_schedule(pic_state *st, int sched, int use_graph);
  *   "seen_tile_z"    rows of the 2D seen-field tile: 8, 16 or 32
  *   "resort_every"   steps between tile re-sort checks (and per captured graph)
  *   "particle_block" threads per particle workgroup: 256 or 512
+ *   "particle_waves4" 1: 2D linear float particle kernel built for four waves
+ *                    per SIMD (register cap 128)
  * Returns PIC_EINVAL for an unknown name or value.  Drops captured graphs. */
 int pic_set_option(pic_state *st, const char *name, int value);
 int pic_get_option(pic_state *st, const char *name, int *value);

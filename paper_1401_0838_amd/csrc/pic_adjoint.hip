@@ -11,9 +11,10 @@
 //   k_adj_particles  per tile: recompute the particle's forward step, then the
 //                    reverse of deposit, move, Boris and gather; the adjoint
 //                    of the seen fields is scattered into an LDS window
-//   k_pass           separable stencil passes applied to adjoint planes
-//   k_adj_grad       dW/da_j += <S_z^j F lambda_Et_c, E1_c>, c in {x, y}
-//   k_adj_yee_e/_b   the transposed Yee sweeps
+//   k_adj_seen_2d    2D: the transposed seen-field stencils in LDS, fused with
+//                    dW/da_j += <S_z^j F lambda_Et_c, E1_c>, c in {x, y}
+//   k_adj_yee_2d     2D: the three transposed Yee sweeps in one LDS pass
+//   k_pass, k_adj_grad, k_adj_yee_e/_b   the same in 3D as per-cell passes
 // Positions and their adjoints are in cell units (offsets).
 #include <hip/hip_runtime.h>
 
@@ -614,6 +615,179 @@ __global__ void __launch_bounds__(256) k_zero_lseen(const InstDesc *__restrict__
     for (int c = 0; c < 3; c++) { ((R *)D.lEt[c])[cell] = R(0); ((R *)D.lBt[c])[cell] = R(0); }
 }
 
+// ------------------------------------------------------------ fused 2D kernels
+// Adjoint of the fields as seen by the particles, 2D, one (64 x TZ) tile of one
+// component per block.  GRAD (components x, y): Lambda = F lambda_Et is formed
+// in LDS (filter passes only), then lambda_E += sum_j a_j S_z^j Lambda
+// (= Psi_E(S_z) F lambda_Et) and dW/da_j += <S_z^j Lambda, E1>.  Otherwise
+// (E_z and all of B): lambda += Psi_B(S_z) F lambda_t with the combined taps.
+#define ADJ_TX 64
+template <class R, int TZ, bool GRAD>
+__global__ void __launch_bounds__(256) k_adj_seen_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                                     int comp0)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
+    const int comp = comp0 + blockIdx.y;
+    const InstDesc &D = Dt[inst];
+    const int nx = D.n[0], nz = D.n[2];
+    const int ntx = (nx + ADJ_TX - 1) / ADJ_TX;
+    const int x0 = (t % ntx) * ADJ_TX, z0 = (t / ntx) * TZ;
+    const int hx = D.hx;
+    const int deg = GRAD ? D.psi_deg : 0;
+    const int hz = GRAD ? D.hzf : D.hz;             // z half-width of the first pass
+    const int wx = ADJ_TX + 2 * hx;
+    const int rows_mid = TZ + 2 * deg;              // rows kept after the z pass
+    const int wz = rows_mid + 2 * hz;
+    R *win = reinterpret_cast<R *>(smem);
+    R *mid = win + wx * wz;
+    R *lam = mid + wx * rows_mid;
+    R *tz = lam + ADJ_TX * rows_mid;
+    R *tx = tz + 2 * PIC_MAX_HZ + 1;
+    __shared__ double red[9][4];
+    const double *tzs = GRAD ? D.tzf : D.tz[comp < 2 ? 0 : 1];
+    for (int i = threadIdx.x; i <= 2 * hz; i += blockDim.x) tz[i] = (R)tzs[i];
+    for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)D.tx[i];
+    gp<const R> src = G<R>((const void *)(comp < 3 ? D.lEt[comp] : D.lBt[comp - 3]));
+    auto wrapx = [&](int g) { g += g < 0 ? nx : 0; g -= g >= nx ? nx : 0; return (g < 0 || g >= nx) ? ((g % nx) + nx) % nx : g; };
+    auto wrapz = [&](int g) { g += g < 0 ? nz : 0; g -= g >= nz ? nz : 0; return (g < 0 || g >= nz) ? ((g % nz) + nz) % nz : g; };
+    for (int c = threadIdx.x; c < wx * wz; c += blockDim.x) {
+        const int zz = c / wx, xx = c - zz * wx;
+        win[c] = src[wrapz(z0 - deg - hz + zz) * nx + wrapx(x0 - hx + xx)];
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < wx * rows_mid; c += blockDim.x) {
+        const int zz = c / wx, xx = c - zz * wx;
+        R acc = R(0);
+        for (int k = 0; k <= 2 * hz; k++) acc += tz[k] * win[(zz + k) * wx + xx];
+        mid[c] = acc;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < ADJ_TX * rows_mid; c += blockDim.x) {
+        const int zz = c / ADJ_TX, xx = c - zz * ADJ_TX;
+        R acc = R(0);
+        for (int k = 0; k <= 2 * hx; k++) acc += tx[k] * mid[zz * wx + xx + k];
+        lam[c] = acc;
+    }
+    __syncthreads();
+    // lambda_E, lambda_B plus this contribution go to the scratch planes T1: the
+    // reverse Yee kernel reads them with halos and writes lambda_E, lambda_B
+    gp<const R> own = G<R>((const void *)(comp < 3 ? D.lE[comp] : D.lB[comp - 3]));
+    gp<R> dst = G<R>(D.T1[comp]);
+    double gpart[9];
+    for (int j = 0; j < 9; j++) gpart[j] = 0.0;
+    for (int c = threadIdx.x; c < ADJ_TX * TZ; c += blockDim.x) {
+        const int zz = c / ADJ_TX, xx = c - zz * ADJ_TX;
+        const int gx = x0 + xx, gz = z0 + zz;
+        if (gx >= nx || gz >= nz) continue;
+        const int g = gz * nx + gx;
+        if constexpr (GRAD) {
+            const double e1 = (double)G<R>((const void *)D.E[comp])[g];
+            R add = R(0);
+            for (int j = 0; j <= deg; j++) {
+                R tj = R(0);
+                for (int k = -j; k <= j; k++) tj += (R)D.sj[j][8 + k] * lam[(zz + deg + k) * ADJ_TX + xx];
+                add += (R)D.psi_e[j] * tj;
+                gpart[j] += (double)tj * e1;
+            }
+            dst[g] = own[g] + add;
+        } else {
+            dst[g] = own[g] + lam[zz * ADJ_TX + xx];
+        }
+    }
+    if constexpr (GRAD) {
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        for (int j = 0; j <= deg; j++) {
+            const double v = wave_sum(gpart[j]);
+            if (lane == 0) red[j][wave] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x <= deg) {
+            const int j = threadIdx.x;
+            const double v = red[j][0] + red[j][1] + red[j][2] + red[j][3];
+            if (v != 0.0) unsafeAtomicAdd(&D.grad[j], v);
+        }
+    }
+}
+
+// Fused transposed Yee update (2D): with h = dt/2 and Cb = Cf^T,
+//   lE' = lE - h Cb lB;   lB' = lB + dt Cf lE';  lJ = -dt lE';   lE'' = lE' - h Cb lB'
+// Windows relative to the tile origin: lB on [-2, T], lE on [-1, T].
+template <class R, int TZ>
+__global__ void __launch_bounds__(256) k_adj_yee_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    constexpr int TX = PIC_YEE_TX;
+    constexpr int EX = TX + 2, EZ = TZ + 2, BX = TX + 3, BZ = TZ + 3;
+    __shared__ R sE[3][EZ * EX], sB[3][BZ * BX];
+    const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
+    const InstDesc &D = Dt[inst];
+    const int nx = D.n[0], nz = D.n[2];
+    const int ntx = (nx + TX - 1) / TX;
+    const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
+    const int tid = threadIdx.x;
+    auto wrapx = [&](int g) { g += g < 0 ? nx : 0; g -= g >= nx ? nx : 0; return (g < 0 || g >= nx) ? ((g % nx) + nx) % nx : g; };
+    auto wrapz = [&](int g) { g += g < 0 ? nz : 0; g -= g >= nz ? nz : 0; return (g < 0 || g >= nz) ? ((g % nz) + nz) % nz : g; };
+    // inputs: lambda_E, lambda_B as left in T1 by the reverse seen kernels
+    gp<const R> iE[3] = {G<R>((const void *)D.T1[0]), G<R>((const void *)D.T1[1]), G<R>((const void *)D.T1[2])};
+    gp<const R> iB[3] = {G<R>((const void *)D.T1[3]), G<R>((const void *)D.T1[4]), G<R>((const void *)D.T1[5])};
+    gp<R> lE[3] = {G<R>(D.lE[0]), G<R>(D.lE[1]), G<R>(D.lE[2])};
+    gp<R> lB[3] = {G<R>(D.lB[0]), G<R>(D.lB[1]), G<R>(D.lB[2])};
+    gp<R> lJ[3] = {G<R>(D.lJ[0]), G<R>(D.lJ[1]), G<R>(D.lJ[2])};
+    for (int c = tid; c < EZ * EX; c += blockDim.x) {
+        const int lz = c / EX, lx = c - lz * EX;
+        const int g = wrapz(z0 - 1 + lz) * nx + wrapx(x0 - 1 + lx);
+        sE[0][c] = iE[0][g]; sE[1][c] = iE[1][g]; sE[2][c] = iE[2][g];
+    }
+    for (int c = tid; c < BZ * BX; c += blockDim.x) {
+        const int lz = c / BX, lx = c - lz * BX;
+        const int g = wrapz(z0 - 2 + lz) * nx + wrapx(x0 - 2 + lx);
+        sB[0][c] = iB[0][g]; sB[1][c] = iB[1][g]; sB[2][c] = iB[2][g];
+    }
+    __syncthreads();
+    const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
+    // lE' on the whole E window: backward differences of lB (B local = E local + 1)
+    for (int c = tid; c < EZ * EX; c += blockDim.x) {
+        const int lz = c / EX, lx = c - lz * EX;
+        const int b = (lz + 1) * BX + lx + 1, bxm = b - 1, bzm = b - BX;
+        const R cx = -(sB[1][b] - sB[1][bzm]) * idz;
+        const R cy = (sB[0][b] - sB[0][bzm]) * idz - (sB[2][b] - sB[2][bxm]) * idx;
+        const R cz = (sB[1][b] - sB[1][bxm]) * idx;
+        sE[0][c] -= h * cx;
+        sE[1][c] -= h * cy;
+        sE[2][c] -= h * cz;
+    }
+    __syncthreads();
+    // lB' on B locals [1, T+1] x [1, TZ+1]: forward differences of lE' (E local = B local - 1)
+    for (int c = tid; c < (TZ + 1) * (TX + 1); c += blockDim.x) {
+        const int lz = c / (TX + 1) + 1, lx = c % (TX + 1) + 1;
+        const int b = lz * BX + lx;
+        const int e = (lz - 1) * EX + lx - 1, exp = e + 1, ezp = e + EX;
+        const R fx = -(sE[1][ezp] - sE[1][e]) * idz;
+        const R fy = (sE[0][ezp] - sE[0][e]) * idz - (sE[2][exp] - sE[2][e]) * idx;
+        const R fz = (sE[1][exp] - sE[1][e]) * idx;
+        sB[0][b] += dt * fx;
+        sB[1][b] += dt * fy;
+        sB[2][b] += dt * fz;
+    }
+    __syncthreads();
+    for (int c = tid; c < TZ * TX; c += blockDim.x) {
+        const int lz = c / TX, lx = c - lz * TX;
+        const int gx = x0 + lx, gz = z0 + lz;
+        if (gx >= nx || gz >= nz) continue;
+        const int e = (lz + 1) * EX + lx + 1;
+        const int b = (lz + 2) * BX + lx + 2, bxm = b - 1, bzm = b - BX;
+        const R cx = -(sB[1][b] - sB[1][bzm]) * idz;
+        const R cy = (sB[0][b] - sB[0][bzm]) * idz - (sB[2][b] - sB[2][bxm]) * idx;
+        const R cz = (sB[1][b] - sB[1][bxm]) * idx;
+        const int g = gz * nx + gx;
+        lJ[0][g] = -dt * sE[0][e]; lJ[1][g] = -dt * sE[1][e]; lJ[2][g] = -dt * sE[2][e];
+        lE[0][g] = sE[0][e] - h * cx;
+        lE[1][g] = sE[1][e] - h * cy;
+        lE[2][g] = sE[2][e] - h * cz;
+        lB[0][g] = sB[0][b]; lB[1][g] = sB[1][b]; lB[2][g] = sB[2][b];
+    }
+}
+
 inline int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : -1; }
 
 }  // namespace
@@ -638,10 +812,21 @@ int launch_adj_seed(const LaunchCtx &c, const int2 *fwork, int nfwork, const int
 
 // Reverse of one step.  `tape` addresses this step's E1, B2, particles and
 // tile boxes; `live` the shared planes (identical for everything else).
-int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fwork, int nfwork, const int2 *swork,
-                    int nswork, const int2 *pwork, int npwork, int block, const int wmax[3])
+size_t adj_seen_smem_bytes(int fp32)
 {
-    if (launch_seen(tape, fwork, nfwork, swork, nswork)) return -1;      // Et, Bt of this step
+    // worst case halos: filter 8 passes, Psi degree 8 (GRAD) or combined z stencil 16
+    const int wx = ADJ_TX + 2 * PIC_MAX_HX, tz = PIC_ADJ_TZ;
+    const int rows_mid = tz + 2 * 8, wz = rows_mid + 2 * PIC_MAX_HX;
+    const int g = wx * wz + wx * rows_mid + ADJ_TX * rows_mid;
+    const int wz2 = tz + 2 * PIC_MAX_HZ, g2 = wx * wz2 + wx * tz + ADJ_TX * tz;
+    return (size_t)((g > g2 ? g : g2) + 2 * PIC_MAX_HZ + 1 + 2 * PIC_MAX_HX + 1) * (fp32 ? 4 : 8);
+}
+
+int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fwork, int nfwork, const int2 *swork,
+                    int nswork, const int2 *awork, int nawork, const int2 *pwork, int npwork, int block,
+                    const int wmax[3])
+{
+    if (launch_seen(tape, fwork, nfwork, swork, nswork, 0)) return -1;   // Et, Bt of this step
     const int wm[3] = {wmax[0], live.dims == 3 ? wmax[1] : 1, wmax[2]};
     const size_t smem = adjoint_smem_bytes(live.dims, live.fp32, wm);
     const dim3 gf(nfwork), g6(nfwork, 6), g2(nfwork, 2), bf(PIC_FIELD_CHUNK);
@@ -655,29 +840,23 @@ int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fw
             else if (live.dims == 3 && live.order == 1) AK(3, 1);
             else AK(3, 3);
         }
-        // lambda_E += M_E lambda_Et, lambda_B += M_B lambda_Bt
-        k_pass<2, R><<<g6, bf, 0, st>>>(live.desc, fwork, PL_LSEEN, PL_T1, 0, 0);
         if (live.dims == 2) {
-            k_pass<0, R><<<g6, bf, 0, st>>>(live.desc, fwork, PL_T1, PL_LEB, 0, 1);
+            // fused LDS kernels on 64 x 8 tiles (the awork list)
+            const size_t sm = adj_seen_smem_bytes(live.fp32);
+            k_adj_seen_2d<R, PIC_ADJ_TZ, true><<<dim3(nawork, 2), bf, sm, st>>>(tape.desc, awork, 0);
+            k_adj_seen_2d<R, PIC_ADJ_TZ, false><<<dim3(nawork, 4), bf, sm, st>>>(live.desc, awork, 2);
+            k_adj_yee_2d<R, PIC_ADJ_TZ><<<dim3(nawork), bf, 0, st>>>(live.desc, awork);
         } else {
+            // lambda_E += M_E lambda_Et, lambda_B += M_B lambda_Bt
+            k_pass<2, R><<<g6, bf, 0, st>>>(live.desc, fwork, PL_LSEEN, PL_T1, 0, 0);
             k_pass<0, R><<<g6, bf, 0, st>>>(live.desc, fwork, PL_T1, PL_T2, 0, 0);
             k_pass<1, R><<<g6, bf, 0, st>>>(live.desc, fwork, PL_T2, PL_LEB, 0, 1);
-        }
-        // gradient: F lambda_Et_c (filter only), then <S^j ., E1_c>
-        k_pass<2, R><<<g2, bf, 0, st>>>(live.desc, fwork, PL_LSEEN, PL_T1, 1, 0);
-        k_pass<0, R><<<g2, bf, 0, st>>>(live.desc, fwork, PL_T1, PL_T2, 0, 0);
-        int lam = PL_T2;
-        if (live.dims == 3) {
+            // gradient: F lambda_Et_c (filter only), then <S^j ., E1_c>
+            k_pass<2, R><<<g2, bf, 0, st>>>(live.desc, fwork, PL_LSEEN, PL_T1, 1, 0);
+            k_pass<0, R><<<g2, bf, 0, st>>>(live.desc, fwork, PL_T1, PL_T2, 0, 0);
             k_pass<1, R><<<g2, bf, 0, st>>>(live.desc, fwork, PL_T2, PL_T1, 0, 0);
-            lam = PL_T1;
-        }
-        k_adj_grad<R><<<g2, bf, 0, st>>>(tape.desc, fwork, lam);
-        // transposed Yee
-        if (live.dims == 2) {
-            k_adj_yee_e<2, R><<<gf, bf, 0, st>>>(live.desc, fwork);
-            k_adj_yee_b<2, R><<<gf, bf, 0, st>>>(live.desc, fwork);
-            k_adj_yee_e<2, R><<<gf, bf, 0, st>>>(live.desc, fwork);
-        } else {
+            k_adj_grad<R><<<g2, bf, 0, st>>>(tape.desc, fwork, PL_T1);
+            // transposed Yee
             k_adj_yee_e<3, R><<<gf, bf, 0, st>>>(live.desc, fwork);
             k_adj_yee_b<3, R><<<gf, bf, 0, st>>>(live.desc, fwork);
             k_adj_yee_e<3, R><<<gf, bf, 0, st>>>(live.desc, fwork);

@@ -160,14 +160,15 @@ struct pic_state {
     std::vector<InstDesc> desc;
     std::vector<int64_t> np;
     InstDesc *d_desc = nullptr;
-    int2 *fwork = nullptr, *pwork = nullptr, *cwork = nullptr, *swork = nullptr, *ywork = nullptr;
-    int nfwork = 0, npwork = 0, ncwork = 0, nswork = 0, nywork = 0;
+    int2 *fwork = nullptr, *pwork = nullptr, *cwork = nullptr, *swork = nullptr, *ywork = nullptr, *awork = nullptr;
+    int nfwork = 0, npwork = 0, ncwork = 0, nswork = 0, nywork = 0, nawork = 0;
     std::vector<Range> frange, prange, crange, srange, yrange;
     int wmax[3] = {1, 1, 1};
     int block = 256;
     int sched = PIC_SCHED_BATCHED, use_graph = 1;
     int graph_k = 8;                 // steps per captured graph (and re-sort period)
     int yee_tz = 8, seen_tz = 16;    // 2D field-kernel tile heights (tunable)
+    int waves4 = 0;                  // particle kernel capped at four waves per SIMD (tunable)
     hipGraphExec_t gexec_k = nullptr, gexec_1 = nullptr;
     long long step = 0;
     int *trace_pos = nullptr;
@@ -195,6 +196,7 @@ LaunchCtx ctx(const pic_state *s)
     c.fp32 = s->fp32;
     c.yee_tz = s->yee_tz;
     c.seen_tz = s->seen_tz;
+    c.waves4 = s->waves4;
     return c;
 }
 
@@ -226,8 +228,8 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
         nc += (np[i] + PIC_PART_CHUNK - 1) / PIC_PART_CHUNK;
     }
     int2 *fw = L.take<int2>(nf), *pw = L.take<int2>(npw), *cw = L.take<int2>(std::max<size_t>(nc, 1));
-    int2 *sw = L.take<int2>(ns), *yw = L.take<int2>(ny);
-    if (s) { s->fwork = fw; s->pwork = pw; s->cwork = cw; s->swork = sw; s->ywork = yw; }
+    int2 *sw = L.take<int2>(ns), *yw = L.take<int2>(ny), *aw = L.take<int2>(ns);
+    if (s) { s->fwork = fw; s->pwork = pw; s->cwork = cw; s->swork = sw; s->ywork = yw; s->awork = aw; }
     int *tpos = L.take<int>(64);
     if (s) s->trace_pos = tpos;
     int cap = 0;
@@ -259,7 +261,7 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
         const bool adj = c.adjoint_steps > 0;
         for (int k = 0; k < 6; k++) {
             void *t1 = plane(R);
-            void *t2 = (c.dims == 3 || adj) ? plane(R) : nullptr;
+            void *t2 = c.dims == 3 ? plane(R) : nullptr;
             if (D) { D->T1[k] = t1; D->T2[k] = t2; }
         }
         double *r0 = L.take<double>(ncell), *r1 = L.take<double>(ncell);
@@ -388,6 +390,7 @@ void fill_desc(InstDesc &D, const pic_config &c, const pic_particles &p)
     }
     for (int a = 0; a < 3; a++) D.cdep_r[a] = -qw * D.d[a] / (c.cdt * D.dV);
     D.cy2d_r = qw / D.dV;
+    for (int j = 0; j < 9; j++) D.psi_e[j] = c.correction ? (j <= c.psi_deg ? c.psi_e[j] : 0.0) : (j == 0 ? 1.0 : 0.0);
 }
 
 template <class R>
@@ -518,7 +521,7 @@ void tile_order(int nt, std::vector<int> &out)
 
 int build_worklists(pic_state *s)
 {
-    std::vector<int2> fw, pw, cw, sw, yw;
+    std::vector<int2> fw, pw, cw, sw, yw, aw;
     s->frange.clear(); s->prange.clear(); s->crange.clear(); s->srange.clear(); s->yrange.clear();
     const int ytz = yee_tz_eff(s->yee_tz, s->fp32), stz = s->seen_tz;
     std::vector<int> ord;
@@ -543,6 +546,8 @@ int build_worklists(pic_state *s)
         for (int k = 0; k < nyt; k++) yw.push_back(make_int2(i, k));
         yr.n = (int)yw.size() - yr.off;
         s->yrange.push_back(yr);
+        const int nat = ((D.n[0] + PIC_SEEN_TX - 1) / PIC_SEEN_TX) * ((D.n[2] + PIC_ADJ_TZ - 1) / PIC_ADJ_TZ);
+        for (int k = 0; k < nat; k++) aw.push_back(make_int2(i, k));
         Range c{(int)cw.size(), 0};
         for (long long k = 0; k < (D.np + PIC_PART_CHUNK - 1) / PIC_PART_CHUNK; k++) cw.push_back(make_int2(i, (int)k));
         c.n = (int)cw.size() - c.off;
@@ -553,6 +558,8 @@ int build_worklists(pic_state *s)
     s->ncwork = (int)cw.size();
     s->nswork = (int)sw.size();
     s->nywork = (int)yw.size();
+    s->nawork = (int)aw.size();
+    HIP_TRY(hipMemcpyAsync(s->awork, aw.data(), aw.size() * sizeof(int2), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(s->ywork, yw.data(), yw.size() * sizeof(int2), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(s->swork, sw.data(), sw.size() * sizeof(int2), hipMemcpyHostToDevice, s->stream));
     HIP_TRY(hipMemcpyAsync(s->fwork, fw.data(), fw.size() * sizeof(int2), hipMemcpyHostToDevice, s->stream));
@@ -568,7 +575,7 @@ int enqueue_step_range(pic_state *s, const Range &f, const Range &sr, const Rang
 {
     LaunchCtx c = ctx(s);
     if (launch_yee(c, s->fwork + f.off, f.n, s->ywork + yr.off, yr.n)) return fail(PIC_EHIP, "yee launch");
-    if (launch_seen(c, s->fwork + f.off, f.n, s->swork + sr.off, sr.n)) return fail(PIC_EHIP, "seen launch");
+    if (launch_seen(c, s->fwork + f.off, f.n, s->swork + sr.off, sr.n, 1)) return fail(PIC_EHIP, "seen launch");
     if (launch_particles(c, s->pwork + p.off, p.n, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particle launch");
     (void)trace;
     return PIC_OK;
@@ -894,6 +901,9 @@ extern "C" int pic_set_option(pic_state *s, const char *name, int value)
     } else if (n == "particle_block") {
         if (value != 256 && value != 512) return fail(PIC_EINVAL, "particle_block must be 256 or 512");
         s->block = value;
+    } else if (n == "particle_waves4") {
+        if (value != 0 && value != 1) return fail(PIC_EINVAL, "particle_waves4 must be 0 or 1");
+        s->waves4 = value;
     } else {
         return fail(PIC_EINVAL, "unknown option " + n);
     }
@@ -909,6 +919,7 @@ extern "C" int pic_get_option(pic_state *s, const char *name, int *value)
     else if (n == "seen_tile_z") *value = s->seen_tz;
     else if (n == "resort_every") *value = s->graph_k;
     else if (n == "particle_block") *value = s->block;
+    else if (n == "particle_waves4") *value = s->waves4;
     else return fail(PIC_EINVAL, "unknown option " + n);
     return PIC_OK;
 }
@@ -1054,7 +1065,7 @@ extern "C" int pic_profile(pic_state *s, int nsteps, pic_timing_t *out)
         HIP_TRY(hipEventRecord(ev[0], s->stream));
         if (launch_yee(c, s->fwork, f.n, s->ywork, s->nywork)) return fail(PIC_EHIP, "yee");
         HIP_TRY(hipEventRecord(ev[1], s->stream));
-        if (launch_seen(c, s->fwork, f.n, s->swork, s->nswork)) return fail(PIC_EHIP, "seen");
+        if (launch_seen(c, s->fwork, f.n, s->swork, s->nswork, 1)) return fail(PIC_EHIP, "seen");
         HIP_TRY(hipEventRecord(ev[2], s->stream));
         if (launch_particles(c, s->pwork, p.n, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particles");
         HIP_TRY(hipEventRecord(ev[3], s->stream));
@@ -1110,7 +1121,7 @@ int forward_step_eager(pic_state *s)
 {
     LaunchCtx live = ctx(s);
     if (launch_yee(live, s->fwork, s->nfwork, s->ywork, s->nywork)) return fail(PIC_EHIP, "yee");
-    if (launch_seen(live, s->fwork, s->nfwork, s->swork, s->nswork)) return fail(PIC_EHIP, "seen");
+    if (launch_seen(live, s->fwork, s->nfwork, s->swork, s->nswork, 1)) return fail(PIC_EHIP, "seen");
     if (launch_particles(live, s->pwork, s->npwork, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particles");
     return PIC_OK;
 }
@@ -1124,17 +1135,18 @@ int enqueue_segment(pic_state *s, int m)
     for (int slot = 0; slot < m && rc == PIC_OK; slot++) {
         for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy_particles(s, i, s->tape[i][slot], true);
         if (rc) break;
-        if (launch_yee(live, s->fwork, s->nfwork, s->ywork, s->nywork)) return fail(PIC_EHIP, "yee");
+        if (launch_yee(live, s->fwork, s->nfwork, s->ywork, s->nywork) ||
+            launch_seen(live, s->fwork, s->nfwork, s->swork, s->nswork, 1))
+            return fail(PIC_EHIP, "recompute");
         for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy_fields(s, i, s->tape[i][slot]);
         if (rc) break;
-        if (launch_seen(live, s->fwork, s->nfwork, s->swork, s->nswork) ||
-            launch_particles(live, s->pwork, s->npwork, 0, s->block, s->wmax))
-            return fail(PIC_EHIP, "recompute");
+        if (launch_particles(live, s->pwork, s->npwork, 0, s->block, s->wmax)) return fail(PIC_EHIP, "recompute");
     }
     for (int slot = m - 1; slot >= 0 && rc == PIC_OK; slot--) {
         LaunchCtx tp = live;
         tp.desc = s->d_tape_desc + (size_t)slot * s->n_inst;
-        if (launch_adj_step(live, tp, s->fwork, s->nfwork, s->swork, s->nswork, s->pwork, s->npwork, 256,
+        if (launch_adj_step(live, tp, s->fwork, s->nfwork, s->swork, s->nswork, s->awork, s->nawork, s->pwork,
+                            s->npwork, 256,
                             s->adj_wmax))
             rc = fail(PIC_EHIP, "adjoint step");
     }

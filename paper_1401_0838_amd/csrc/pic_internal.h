@@ -79,6 +79,7 @@ struct InstDesc {
     double tzf[2 * PIC_MAX_HZ + 1];  // z filter taps alone
     double sj[9][17];      // taps of S_z^j (half-width j), j <= psi_deg
     double cdep_r[3], cy2d_r;        // Esirkepov factors in real units (float mode unscaled)
+    double psi_e[9];                 // Psi_E coefficients (1, 0, ... without the correction)
 };
 
 // launch helpers implemented in pic_kernels.hip
@@ -87,11 +88,16 @@ struct LaunchCtx {
     hipStream_t stream;
     int dims, order, fp32;
     int yee_tz = 8, seen_tz = 16; // 2D field-kernel tile heights (x width 64)
+    int waves4 = 0;               // 2D linear float particle kernel capped at 128 VGPRs
 };
 
 int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork);
 #define PIC_YEE_TX 64
-int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork);
+// commit = 1: the step's own seen pass.  In 2D the fused Yee kernel leaves the
+// new E, B in T1 (it cannot update in place: neighbouring tiles read its halo),
+// and this pass copies them to E, B and clears J for the deposit.
+// commit = 0: recompute Et, Bt from E, B as they are (reverse sweep).
+int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork, int commit);
 size_t seen_smem_bytes(int fp32, int tz);
 int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid, int block,
                      const int wmax[3]);
@@ -107,5 +113,9 @@ int launch_trace_rows(const LaunchCtx &c, const int2 *fwork, int nfwork, int *po
 int launch_fill_bbox(const LaunchCtx &c, int inst_first, int n_inst);
 size_t adjoint_smem_bytes(int dims, int fp32, const int wmax[3]);
 int launch_adj_seed(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *cwork, int ncwork);
+size_t adj_seen_smem_bytes(int fp32);
+// awork: 2D field tiles of 64 x 8 cells (PIC_ADJ_TZ rows) for the fused reverse kernels
+#define PIC_ADJ_TZ 8
 int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fwork, int nfwork,
-                    const int2 *swork, int nswork, const int2 *pwork, int npwork, int block, const int wmax[3]);
+                    const int2 *swork, int nswork, const int2 *awork, int nawork, const int2 *pwork, int npwork,
+                    int block, const int wmax[3]);

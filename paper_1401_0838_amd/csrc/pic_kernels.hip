@@ -151,8 +151,9 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
             }
         }
     } else {
-        // J_x
-#pragma unroll
+        // J_x (outer loops stay rolled for cubic shapes to bound register use)
+        constexpr int UNROLL_OUTER = L == 1 ? L + 2 : 1;
+#pragma unroll UNROLL_OUTER
         for (int kz = 0; kz < L + 2; kz++)
 #pragma unroll
             for (int ky = 0; ky < L + 2; ky++) {
@@ -166,7 +167,7 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
                 }
             }
         // J_y
-#pragma unroll
+#pragma unroll UNROLL_OUTER
         for (int kz = 0; kz < L + 2; kz++)
 #pragma unroll
             for (int kx = 0; kx < L + 2; kx++) {
@@ -180,7 +181,7 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
                 }
             }
         // J_z
-#pragma unroll
+#pragma unroll UNROLL_OUTER
         for (int ky = 0; ky < L + 2; ky++)
 #pragma unroll
             for (int kx = 0; kx < L + 2; kx++) {
@@ -200,8 +201,8 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 
 // P > 0 (2D only): LDS windows use the fixed row pitch P and plane size P*P
 template <int DIM, int L, class R, int P>
-__global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                                   int nwork, int wmx, int wmy, int wmz)
+__device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                               int nwork, int wmx, int wmy, int wmz)
 {
     typedef typename JOf<R>::T JT;
     constexpr int JL = (L + 1) / 2;      // guard cells below the bounding box
@@ -272,21 +273,43 @@ __global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ 
             }
         }
 
+        // software pipelining: the next particle's state is loaded while the
+        // current one is processed (doubles the bytes in flight per wave)
+        unsigned nidx = 0;
+        R noff[3] = {R(0), R(0), R(0)}, nu[3] = {R(0), R(0), R(0)};
+        if (p0 + tid < p1) {
+            const int q = p0 + tid;
+            nidx = pidx[q];
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                if (!(DIM == 2 && a == 1)) noff[a] = poff[a][q];
+                nu[a] = pu[a][q];
+            }
+        }
         for (int p = p0 + tid; p < p1; p += bs) {
             int c[3];
-            unpack_cell<DIM>(pidx[p], c);
+            unpack_cell<DIM>(nidx, c);
             int lc[3];
             R off[3], u[3], offn[3];
             int dc[3];
 #pragma unroll
             for (int a = 0; a < 3; a++) {
+                u[a] = nu[a];
                 if (DIM == 2 && a == 1) { lc[a] = 0; off[a] = R(0); continue; }
                 int rel = c[a] - lo[a];
                 rel += rel < 0 ? D.n[a] : 0;
                 lc[a] = rel + JL;
-                off[a] = poff[a][p];
+                off[a] = noff[a];
             }
-            u[0] = pu[0][p]; u[1] = pu[1][p]; u[2] = pu[2][p];
+            if (p + bs < p1) {
+                const int q = p + bs;
+                nidx = pidx[q];
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    if (!(DIM == 2 && a == 1)) noff[a] = poff[a][q];
+                    nu[a] = pu[a][q];
+                }
+            }
             if (fits) {
                 if constexpr (P > 0) push_particle<DIM, L, R, JT>(lwp, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
                 else push_particle<DIM, L, R, JT>(lw, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
@@ -344,6 +367,21 @@ __global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ 
         }
         __syncthreads();
     }
+}
+
+template <int DIM, int L, class R, int P>
+__global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                                   int nwork, int wmx, int wmy, int wmz)
+{
+    particles_body<DIM, L, R, P>(Dt, work, nwork, wmx, wmy, wmz);
+}
+
+// same body compiled for four waves per SIMD (at most 128 VGPRs)
+template <int DIM, int L, class R, int P>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+k_particles_w4(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int nwork, int wmx, int wmy, int wmz)
+{
+    particles_body<DIM, L, R, P>(Dt, work, nwork, wmx, wmy, wmz);
 }
 
 // ------------------------------------------------------------- Yee sweeps
@@ -451,7 +489,10 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
     auto wrapz = [&](int g) { g += g < 0 ? nz : 0; g -= g >= nz ? nz : 0; return (g < 0 || g >= nz) ? ((g % nz) + nz) % nz : g; };
     gp<R> E[3] = {G<R>(D.E[0]), G<R>(D.E[1]), G<R>(D.E[2])};
     gp<R> B[3] = {G<R>(D.B[0]), G<R>(D.B[1]), G<R>(D.B[2])};
-    gp<JT> J[3] = {G<JT>(D.J[0]), G<JT>(D.J[1]), G<JT>(D.J[2])};
+    gp<const JT> J[3] = {G<JT>((const void *)D.J[0]), G<JT>((const void *)D.J[1]), G<JT>((const void *)D.J[2])};
+    // E, B and J are read with halos that neighbouring tiles own, so the new
+    // fields go to the scratch planes T1 (E then B); the seen pass commits them
+    gp<R> O[6] = {G<R>(D.T1[0]), G<R>(D.T1[1]), G<R>(D.T1[2]), G<R>(D.T1[3]), G<R>(D.T1[4]), G<R>(D.T1[5])};
     for (int c = tid; c < EZ * EX; c += blockDim.x) {
         const int lz = c / EX, lx = c - lz * EX;
         const int g = wrapz(z0 - 1 + lz) * nx + wrapx(x0 - 1 + lx);
@@ -503,11 +544,10 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
         const R dzEy = (sE[1][ez] - sE[1][e]) * idz, dzEx = (sE[0][ez] - sE[0][e]) * idz;
         const R dxEz = (sE[2][ex] - sE[2][e]) * idx, dxEy = (sE[1][ex] - sE[1][e]) * idx;
         const int g = gz * nx + gx;
-        B[0][g] = sB[0][b] - h * (-dzEy);
-        B[1][g] = sB[1][b] - h * (dzEx - dxEz);
-        B[2][g] = sB[2][b] - h * dxEy;
-        E[0][g] = sE[0][e]; E[1][g] = sE[1][e]; E[2][g] = sE[2][e];
-        J[0][g] = JT(0); J[1][g] = JT(0); J[2][g] = JT(0);
+        O[3][g] = sB[0][b] - h * (-dzEy);
+        O[4][g] = sB[1][b] - h * (dzEx - dxEz);
+        O[5][g] = sB[2][b] - h * dxEy;
+        O[0][g] = sE[0][e]; O[1][g] = sE[1][e]; O[2][g] = sE[2][e];
     }
 }
 
@@ -570,8 +610,10 @@ __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ 
 // filter stencil writes the output.  blockIdx.y = component, work = (inst, tile).
 #define SEEN_TX PIC_SEEN_TX
 template <class R, int SEEN_TZ>
-__global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+__global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                                 int commit)
 {
+    typedef typename JOf<R>::T JT;
     extern __shared__ __align__(16) unsigned char smem[];
     const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
     const int comp = blockIdx.y;
@@ -588,7 +630,8 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     const double *tzs = D.tz[comp < 2 ? 0 : 1];
     for (int i = threadIdx.x; i <= 2 * hz; i += blockDim.x) tz[i] = (R)tzs[i];
     for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)D.tx[i];
-    gp<const R> src = G<R>((const void *)(comp < 3 ? D.E[comp] : D.B[comp - 3]));
+    const void *sp = commit ? D.T1[comp] : (comp < 3 ? D.E[comp] : D.B[comp - 3]);
+    gp<const R> src = G<R>(sp);
     for (int c = threadIdx.x; c < wx * wz; c += blockDim.x) {
         const int zz = (int)(((float)c + 0.5f) * (1.0f / (float)wx));
         const int xx = c - zz * wx;
@@ -615,7 +658,12 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
         if (gx >= nx || gz >= nz) continue;
         R acc = R(0);
         for (int k = 0; k <= 2 * hx; k++) acc += tx[k] * mid[zz * wx + xx + k];
-        dst[gz * nx + gx] = acc;
+        const int g = gz * nx + gx;
+        dst[g] = acc;
+        if (commit) {
+            G<R>(comp < 3 ? D.E[comp] : D.B[comp - 3])[g] = win[(zz + hz) * wx + xx + hx];
+            if (comp < 3) G<JT>(D.J[comp])[g] = JT(0);
+        }
     }
 }
 
@@ -942,16 +990,16 @@ size_t seen_smem_bytes(int fp32, int tz)
     return (size_t)(wx * wz + wx * tz + 2 * PIC_MAX_HZ + 1 + 2 * PIC_MAX_HX + 1) * (fp32 ? 4 : 8);
 }
 
-int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork)
+int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork, int commit)
 {
     if (nwork <= 0) return 0;
     dim3 g(nwork, 6), b(PIC_FIELD_CHUNK);
     DISPATCH_R(c.fp32, {
         if (c.dims == 2) {
             const size_t sm = seen_smem_bytes(c.fp32, c.seen_tz);
-            if (c.seen_tz == 8) k_seen_2d<R, 8><<<dim3(nswork, 6), b, sm, c.stream>>>(c.desc, swork);
-            else if (c.seen_tz == 16) k_seen_2d<R, 16><<<dim3(nswork, 6), b, sm, c.stream>>>(c.desc, swork);
-            else k_seen_2d<R, 32><<<dim3(nswork, 6), b, sm, c.stream>>>(c.desc, swork);
+            if (c.seen_tz == 8) k_seen_2d<R, 8><<<dim3(nswork, 6), b, sm, c.stream>>>(c.desc, swork, commit);
+            else if (c.seen_tz == 16) k_seen_2d<R, 16><<<dim3(nswork, 6), b, sm, c.stream>>>(c.desc, swork, commit);
+            else k_seen_2d<R, 32><<<dim3(nswork, 6), b, sm, c.stream>>>(c.desc, swork, commit);
         } else {
             k_seen_pass<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1);
             k_seen_pass<0, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2);
@@ -978,8 +1026,11 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
 #define PK(D_, L_, P_) k_particles<D_, L_, R, P_><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2])
     DISPATCH_R(c.fp32, {
         if (c.dims == 2 && c.order == 1) {
-            if (wm[0] == 24 && wm[2] == 24) PK(2, 1, 24);
-            else if (wm[0] == 32 && wm[2] == 32) PK(2, 1, 32);
+            if (wm[0] == 24 && wm[2] == 24) {
+                if (c.fp32 && c.waves4)
+                    k_particles_w4<2, 1, float, 24><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2]);
+                else PK(2, 1, 24);
+            } else if (wm[0] == 32 && wm[2] == 32) PK(2, 1, 32);
             else PK(2, 1, 0);
         } else if (c.dims == 2 && c.order == 3) {
             if (wm[0] == 32 && wm[2] == 32) PK(2, 3, 32);

@@ -230,6 +230,37 @@ def test_batched_instances_match_own_oracle_and_plain():
         assert np.array_equal(a, b)
 
 
+def test_many_batched_instances_fp64_match_oracle():
+    """32 instances of 512x512 in one batched launch: far more field tiles than
+    the chip holds at once, so tiles run in waves.  Every instance must still
+    equal the oracle (a field kernel that read a neighbour's already-updated
+    halo would make the instances differ)."""
+    wl = pi.workload("beam2d_512", ppc=1, precision="fp64")
+    x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], 1e-3, 5)
+    rng = np.random.default_rng(5)
+    E0 = rng.normal(size=(3, 512, 1, 512)) * 1e-3
+    B0 = rng.normal(size=(3, 512, 1, 512)) * 1e-3
+    ninst = 32
+    _say("case 32 x 512x512 fp64 batched, 3 steps")
+    sim = _sim([wl] * ninst, [(x, u)] * ninst, precision="fp64")
+    for i in range(ninst):
+        for c in range(3):
+            sim.set_field("E", c, E0[c], i)
+            sim.set_field("B", c, B0[c], i)
+    ref = OracleSim(wl, x, u)
+    ref.E[:] = E0
+    ref.B[:] = B0
+    sim.step(3)
+    ref.step(3)
+    worst = 0.0
+    for i in range(ninst):
+        for k in ("E", "B", "J"):
+            worst = max(worst, _rel(sim.fields(k, i), getattr(ref, k)))
+    _say("  worst relative error over instances %.3e" % worst)
+    sim.close()
+    assert worst < 1e-10
+
+
 # ------------------------------------------------------ full-size sample
 
 def test_full_size_512_fp32_parity_10_steps():
