@@ -96,7 +96,9 @@ typedef struct pic_config {
     double weight;            /* macro-particle weight (real particles per macro-particle
                                  per unit cell volume times cell volume) */
     int    ion_mode;          /* PIC_IONS_* */
-    int    tile[3];           /* particle tile in cells along x, y, z (0 = default) */
+    int    tile[3];           /* particle tile in cells along x, y, z (0 = default: 2D 16 x 16, or
+                                 8 x 8 when the whole batch has fewer than 1024 default tiles;
+                                 3D 8x4x4 linear, 4x4x4 cubic) */
     int    block;             /* threads per particle workgroup: 0 (default), 256 or 512 */
     int    trace_capacity;    /* steps of per-step field-energy trace kept on the device */
     int    adjoint_steps;     /* longest gradient run pic_wperp_gradient may do (0: none) */
@@ -172,6 +174,8 @@ int pic_set_schedule(pic_state *st, int sched, int use_graph);
  *   "particle_block" threads per particle workgroup: 256 or 512
  *   "particle_waves4" 1: 2D linear float particle kernel built for four waves
  *                    per SIMD (register cap 128)
+ *   "particle_prefetch" 1: 2D linear float particle kernel loads the next
+ *                    particle's state while pushing the current one
  * Returns PIC_EINVAL for an unknown name or value.  Drops captured graphs. */
 int pic_set_option(pic_state *st, const char *name, int value);
 int pic_get_option(pic_state *st, const char *name, int *value);

@@ -357,19 +357,17 @@ __global__ void __launch_bounds__(256) k_adj_particles(const InstDesc *__restric
         R *sF = reinterpret_cast<R *>(smem);
         R *sLJ = sF + 6 * wcmax;
         R *sLF = sLJ + 3 * wcmax;
+        const int nn[3] = {D.n[0], D.n[1], D.n[2]};
         if (fits) {
-            const R *src[6] = {(const R *)D.Et[0], (const R *)D.Et[1], (const R *)D.Et[2],
-                               (const R *)D.Bt[0], (const R *)D.Bt[1], (const R *)D.Bt[2]};
-            const R *lsrc[3] = {(const R *)D.lJ[0], (const R *)D.lJ[1], (const R *)D.lJ[2]};
-            for (int c = tid; c < wc; c += bs) {
-                const int x = c % wn[0], r = c / wn[0];
-                const int y = r % wn[1], z = r / wn[1];
-                const int g = (((o[2] + z) % D.n[2]) * D.n[1] + (o[1] + y) % D.n[1]) * D.n[0] + (o[0] + x) % D.n[0];
-#pragma unroll
-                for (int k = 0; k < 6; k++) { sF[k * wc + c] = src[k][g]; sLF[k * wc + c] = R(0); }
-#pragma unroll
-                for (int k = 0; k < 3; k++) sLJ[k * wc + c] = lsrc[k][g];
-            }
+            const gp<const R> src[6] = {G<R>((const void *)D.Et[0]), G<R>((const void *)D.Et[1]),
+                                        G<R>((const void *)D.Et[2]), G<R>((const void *)D.Bt[0]),
+                                        G<R>((const void *)D.Bt[1]), G<R>((const void *)D.Bt[2])};
+            const gp<const R> lsrc[3] = {G<R>((const void *)D.lJ[0]), G<R>((const void *)D.lJ[1]),
+                                         G<R>((const void *)D.lJ[2])};
+            auto addr = [&](int c) { return window_cell(c, wn, o, nn); };
+            stage<2, 6, R, R>(sF, wc, src, wc, addr, IdentityIx{}, PlainCv{});
+            stage<2, 3, R, R>(sLJ, wc, lsrc, wc, addr, IdentityIx{}, PlainCv{});
+            for (int c = tid; c < 6 * wc; c += bs) sLF[c] = R(0);
         }
         __syncthreads();
         const R dtd[3] = {(R)D.dtd[0], (R)D.dtd[1], (R)D.dtd[2]};
@@ -385,41 +383,46 @@ __global__ void __launch_bounds__(256) k_adj_particles(const InstDesc *__restric
                 gw.o[k] = o[k]; gw.n[k] = D.n[k];
             }
         }
+        const gp<const unsigned> pidx = G<unsigned>((const void *)D.pidx);
+        const gp<const R> pu[3] = {G<R>((const void *)D.pu[0]), G<R>((const void *)D.pu[1]), G<R>((const void *)D.pu[2])};
+        const gp<const R> po[3] = {G<R>((const void *)D.poff[0]), G<R>((const void *)D.poff[1]),
+                                   G<R>((const void *)D.poff[2])};
+        const gp<R> plu[3] = {G<R>(D.lu[0]), G<R>(D.lu[1]), G<R>(D.lu[2])};
+        const gp<R> plo[3] = {G<R>(D.loff[0]), G<R>(D.loff[1]), G<R>(D.loff[2])};
         for (int p = p0 + tid; p < p1; p += bs) {
             int c[3];
-            unpack_cell<DIM>((unsigned)D.pidx[p], c);
+            unpack_cell<DIM>(pidx[p], c);
             int lc[3];
             R off[3], u[3], loff[3], lu[3];
 #pragma unroll
             for (int a = 0; a < 3; a++) {
-                u[a] = ((const R *)D.pu[a])[p];
-                lu[a] = ((const R *)D.lu[a])[p];
+                u[a] = pu[a][p];
+                lu[a] = plu[a][p];
                 if (DIM == 2 && a == 1) { lc[a] = 0; off[a] = R(0); loff[a] = R(0); continue; }
                 int rel = c[a] - lo[a];
-                rel += rel < 0 ? D.n[a] : 0;
+                rel += rel < 0 ? nn[a] : 0;
                 lc[a] = rel + JL;
-                off[a] = ((const R *)D.poff[a])[p];
-                loff[a] = ((const R *)D.loff[a])[p];
+                off[a] = po[a][p];
+                loff[a] = plo[a][p];
             }
             if (fits) adjoint_particle<DIM, L, R>(lw, lc, off, u, loff, lu, dtd, qdt2m, cdr, cyr);
             else adjoint_particle<DIM, L, R>(gw, lc, off, u, loff, lu, dtd, qdt2m, cdr, cyr);
 #pragma unroll
             for (int a = 0; a < 3; a++) {
-                ((R *)D.lu[a])[p] = lu[a];
-                if (!(DIM == 2 && a == 1)) ((R *)D.loff[a])[p] = loff[a];
+                plu[a][p] = lu[a];
+                if (!(DIM == 2 && a == 1)) plo[a][p] = loff[a];
             }
         }
         __syncthreads();
         if (fits) {
-            R *dst[6] = {(R *)D.lEt[0], (R *)D.lEt[1], (R *)D.lEt[2], (R *)D.lBt[0], (R *)D.lBt[1], (R *)D.lBt[2]};
+            const gp<R> dst[6] = {G<R>(D.lEt[0]), G<R>(D.lEt[1]), G<R>(D.lEt[2]),
+                                  G<R>(D.lBt[0]), G<R>(D.lBt[1]), G<R>(D.lBt[2])};
             for (int c = tid; c < wc; c += bs) {
-                const int x = c % wn[0], r = c / wn[0];
-                const int y = r % wn[1], z = r / wn[1];
-                const int g = (((o[2] + z) % D.n[2]) * D.n[1] + (o[1] + y) % D.n[1]) * D.n[0] + (o[0] + x) % D.n[0];
+                const int g = window_cell(c, wn, o, nn);
 #pragma unroll
                 for (int k = 0; k < 6; k++) {
                     const R v = sLF[k * wc + c];
-                    if (v != R(0)) gadd(&dst[k][g], v);
+                    if (v != R(0)) gatomic_add(dst[k] + g, v);
                 }
             }
         }
@@ -648,13 +651,13 @@ __global__ void __launch_bounds__(256) k_adj_seen_2d(const InstDesc *__restrict_
     const double *tzs = GRAD ? D.tzf : D.tz[comp < 2 ? 0 : 1];
     for (int i = threadIdx.x; i <= 2 * hz; i += blockDim.x) tz[i] = (R)tzs[i];
     for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)D.tx[i];
-    gp<const R> src = G<R>((const void *)(comp < 3 ? D.lEt[comp] : D.lBt[comp - 3]));
-    auto wrapx = [&](int g) { g += g < 0 ? nx : 0; g -= g >= nx ? nx : 0; return (g < 0 || g >= nx) ? ((g % nx) + nx) % nx : g; };
-    auto wrapz = [&](int g) { g += g < 0 ? nz : 0; g -= g >= nz ? nz : 0; return (g < 0 || g >= nz) ? ((g % nz) + nz) % nz : g; };
-    for (int c = threadIdx.x; c < wx * wz; c += blockDim.x) {
-        const int zz = c / wx, xx = c - zz * wx;
-        win[c] = src[wrapz(z0 - deg - hz + zz) * nx + wrapx(x0 - hx + xx)];
-    }
+    const gp<const R> src[1] = {G<R>((const void *)(comp < 3 ? D.lEt[comp] : D.lBt[comp - 3]))};
+    const float iwx = 1.0f / (float)wx;
+    stage<8, 1, R, R>(win, 0, src, wx * wz, [&](int c) {
+        const int zz = (int)(((float)c + 0.5f) * iwx);
+        const int xx = c - zz * wx;
+        return wrap_near(z0 - deg - hz + zz, nz) * nx + wrap_near(x0 - hx + xx, nx);
+    }, IdentityIx{}, PlainCv{});
     __syncthreads();
     for (int c = threadIdx.x; c < wx * rows_mid; c += blockDim.x) {
         const int zz = c / wx, xx = c - zz * wx;
@@ -725,24 +728,21 @@ __global__ void __launch_bounds__(256) k_adj_yee_2d(const InstDesc *__restrict__
     const int ntx = (nx + TX - 1) / TX;
     const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
     const int tid = threadIdx.x;
-    auto wrapx = [&](int g) { g += g < 0 ? nx : 0; g -= g >= nx ? nx : 0; return (g < 0 || g >= nx) ? ((g % nx) + nx) % nx : g; };
-    auto wrapz = [&](int g) { g += g < 0 ? nz : 0; g -= g >= nz ? nz : 0; return (g < 0 || g >= nz) ? ((g % nz) + nz) % nz : g; };
     // inputs: lambda_E, lambda_B as left in T1 by the reverse seen kernels
-    gp<const R> iE[3] = {G<R>((const void *)D.T1[0]), G<R>((const void *)D.T1[1]), G<R>((const void *)D.T1[2])};
-    gp<const R> iB[3] = {G<R>((const void *)D.T1[3]), G<R>((const void *)D.T1[4]), G<R>((const void *)D.T1[5])};
+    const gp<const R> iE[3] = {G<R>((const void *)D.T1[0]), G<R>((const void *)D.T1[1]), G<R>((const void *)D.T1[2])};
+    const gp<const R> iB[3] = {G<R>((const void *)D.T1[3]), G<R>((const void *)D.T1[4]), G<R>((const void *)D.T1[5])};
     gp<R> lE[3] = {G<R>(D.lE[0]), G<R>(D.lE[1]), G<R>(D.lE[2])};
     gp<R> lB[3] = {G<R>(D.lB[0]), G<R>(D.lB[1]), G<R>(D.lB[2])};
     gp<R> lJ[3] = {G<R>(D.lJ[0]), G<R>(D.lJ[1]), G<R>(D.lJ[2])};
-    for (int c = tid; c < EZ * EX; c += blockDim.x) {
+    constexpr int UE = (EZ * EX + 255) / 256, UB = (BZ * BX + 255) / 256;
+    stage<UE, 3, R, R>(&sE[0][0], EZ * EX, iE, EZ * EX, [&](int c) {
         const int lz = c / EX, lx = c - lz * EX;
-        const int g = wrapz(z0 - 1 + lz) * nx + wrapx(x0 - 1 + lx);
-        sE[0][c] = iE[0][g]; sE[1][c] = iE[1][g]; sE[2][c] = iE[2][g];
-    }
-    for (int c = tid; c < BZ * BX; c += blockDim.x) {
+        return wrap_near(z0 - 1 + lz, nz) * nx + wrap_near(x0 - 1 + lx, nx);
+    }, IdentityIx{}, PlainCv{});
+    stage<UB, 3, R, R>(&sB[0][0], BZ * BX, iB, BZ * BX, [&](int c) {
         const int lz = c / BX, lx = c - lz * BX;
-        const int g = wrapz(z0 - 2 + lz) * nx + wrapx(x0 - 2 + lx);
-        sB[0][c] = iB[0][g]; sB[1][c] = iB[1][g]; sB[2][c] = iB[2][g];
-    }
+        return wrap_near(z0 - 2 + lz, nz) * nx + wrap_near(x0 - 2 + lx, nx);
+    }, IdentityIx{}, PlainCv{});
     __syncthreads();
     const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
     // lE' on the whole E window: backward differences of lB (B local = E local + 1)

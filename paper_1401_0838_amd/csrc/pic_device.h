@@ -119,6 +119,54 @@ __device__ __forceinline__ void gatomic_add(gp<float> p, float v)
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ------------------------------------------------------------ LDS staging
+// For c in [0, n) and k < K:  dst[k * dpitch + dix(c)] = cv(k, src[k][addr(c)]).
+// U iterations of the block-strided loop are unrolled and all their loads are
+// issued before the first LDS store, so each thread keeps K * U global loads
+// in flight (a plain loop waits for every load before the next).
+template <int U, int K, class TS, class TD, class Addr, class Dix, class Cv>
+__device__ __forceinline__ void stage(TD *dst, int dpitch, const gp<const TS> *src, int n, Addr addr, Dix dix, Cv cv)
+{
+    const int bs = blockDim.x;
+    for (int c0 = threadIdx.x; c0 < n; c0 += U * bs) {
+        int g[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int c = c0 + u * bs;
+            g[u] = c < n ? addr(c) : 0;      // index 0 is always a valid address
+        }
+        TS v[U][K];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int k = 0; k < K; k++) v[u][k] = src[k][g[u]];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int c = c0 + u * bs;
+            if (c < n) {
+                const int d = dix(c);
+#pragma unroll
+                for (int k = 0; k < K; k++) dst[k * dpitch + d] = cv(k, v[u][k]);
+            }
+        }
+    }
+}
+
+struct IdentityIx {
+    __device__ __forceinline__ int operator()(int c) const { return c; }
+};
+struct PlainCv {
+    template <class T> __device__ __forceinline__ T operator()(int, T v) const { return v; }
+};
+
+// periodic index for g in [-n, 2n) (one compare each way), else a modulo
+__device__ __forceinline__ int wrap_near(int g, int n)
+{
+    g += g < 0 ? n : 0;
+    g -= g >= n ? n : 0;
+    return (g < 0 || g >= n) ? ((g % n) + n) % n : g;
+}
+
 // reciprocal and reciprocal square root: hardware approximations (1 ulp) in
 // float, exact division in double
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }

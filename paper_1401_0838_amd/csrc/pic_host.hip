@@ -78,6 +78,24 @@ void tile_shape(const pic_config &c, int tile[3], int &slack)
     }
 }
 
+// 2D default particle tiles are 16 x 16 cells.  When the whole batch has fewer
+// than four such tiles per compute unit (1024), instances that leave the tile
+// unset get 8 x 8 tiles so that the particle kernels still fill the chip.
+std::vector<pic_config> resolve_tiles(const pic_config *cfgs, int n)
+{
+    std::vector<pic_config> v(cfgs, cfgs + n);
+    if (n < 1 || v[0].dims != 2) return v;
+    long long total = 0;
+    for (const pic_config &c : v) {
+        const int tx = c.tile[0] > 0 ? c.tile[0] : 16, tz = c.tile[2] > 0 ? c.tile[2] : 16;
+        total += (long long)((c.nx + tx - 1) / tx) * ((c.nz + tz - 1) / tz);
+    }
+    if (total >= 1024) return v;
+    for (pic_config &c : v)
+        if (c.tile[0] <= 0 && c.tile[2] <= 0) { c.tile[0] = 8; c.tile[1] = 1; c.tile[2] = 8; }
+    return v;
+}
+
 int validate(const pic_config &c, int idx)
 {
     char buf[256];
@@ -169,6 +187,7 @@ struct pic_state {
     int graph_k = 8;                 // steps per captured graph (and re-sort period)
     int yee_tz = 8, seen_tz = 16;    // 2D field-kernel tile heights (tunable)
     int waves4 = 0;                  // particle kernel capped at four waves per SIMD (tunable)
+    int prefetch = 0;                // particle kernel loads one particle ahead (tunable)
     hipGraphExec_t gexec_k = nullptr, gexec_1 = nullptr;
     long long step = 0;
     int *trace_pos = nullptr;
@@ -197,6 +216,7 @@ LaunchCtx ctx(const pic_state *s)
     c.yee_tz = s->yee_tz;
     c.seen_tz = s->seen_tz;
     c.waves4 = s->waves4;
+    c.prefetch = s->prefetch;
     return c;
 }
 
@@ -752,7 +772,8 @@ extern "C" int pic_plan(const pic_config *cfgs, int n_inst, const int64_t *n_par
             return fail(PIC_EINVAL, "all instances must share dims, precision, shape_order and adjoint sizes");
         if (n_particles[i] < 0 || n_particles[i] > INT32_MAX) return fail(PIC_EINVAL, "particle count");
     }
-    *arena_bytes = layout(nullptr, cfgs, n_inst, n_particles, nullptr);
+    const std::vector<pic_config> rc = resolve_tiles(cfgs, n_inst);
+    *arena_bytes = layout(nullptr, rc.data(), n_inst, n_particles, nullptr);
     return PIC_OK;
 }
 
@@ -772,6 +793,8 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
     int rc = pic_plan(cfgs, n_inst, np.data(), &need);
     if (rc) return rc;
     if (arena_bytes < need) return fail(PIC_ENOMEM, "arena smaller than pic_plan reported");
+    const std::vector<pic_config> resolved = resolve_tiles(cfgs, n_inst);
+    cfgs = resolved.data();
     if (((uintptr_t)d_arena & 255) != 0) return fail(PIC_EINVAL, "arena must be 256-byte aligned");
 
     pic_state *s = new pic_state();
@@ -904,6 +927,9 @@ extern "C" int pic_set_option(pic_state *s, const char *name, int value)
     } else if (n == "particle_waves4") {
         if (value != 0 && value != 1) return fail(PIC_EINVAL, "particle_waves4 must be 0 or 1");
         s->waves4 = value;
+    } else if (n == "particle_prefetch") {
+        if (value != 0 && value != 1) return fail(PIC_EINVAL, "particle_prefetch must be 0 or 1");
+        s->prefetch = value;
     } else {
         return fail(PIC_EINVAL, "unknown option " + n);
     }
@@ -920,6 +946,7 @@ extern "C" int pic_get_option(pic_state *s, const char *name, int *value)
     else if (n == "resort_every") *value = s->graph_k;
     else if (n == "particle_block") *value = s->block;
     else if (n == "particle_waves4") *value = s->waves4;
+    else if (n == "particle_prefetch") *value = s->prefetch;
     else return fail(PIC_EINVAL, "unknown option " + n);
     return PIC_OK;
 }

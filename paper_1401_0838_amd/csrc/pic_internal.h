@@ -89,6 +89,7 @@ struct LaunchCtx {
     int dims, order, fp32;
     int yee_tz = 8, seen_tz = 16; // 2D field-kernel tile heights (x width 64)
     int waves4 = 0;               // 2D linear float particle kernel capped at 128 VGPRs
+    int prefetch = 0;             // 2D linear float particle kernel loads one particle ahead
 };
 
 int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork);

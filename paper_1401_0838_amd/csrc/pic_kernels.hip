@@ -199,8 +199,9 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 
 // ------------------------------------------------------------ particle kernel
 
-// P > 0 (2D only): LDS windows use the fixed row pitch P and plane size P*P
-template <int DIM, int L, class R, int P>
+// P > 0 (2D only): LDS windows use the fixed row pitch P and plane size P*P.
+// PF: load the next particle's state while the current one is processed.
+template <int DIM, int L, class R, int P, bool PF>
 __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                int nwork, int wmx, int wmy, int wmz)
 {
@@ -273,11 +274,11 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
             }
         }
 
-        // software pipelining: the next particle's state is loaded while the
-        // current one is processed (doubles the bytes in flight per wave)
+        // with PF, software pipelining: the next particle's state is loaded
+        // while the current one is processed (twice the bytes in flight per wave)
         unsigned nidx = 0;
         R noff[3] = {R(0), R(0), R(0)}, nu[3] = {R(0), R(0), R(0)};
-        if (p0 + tid < p1) {
+        if (PF && p0 + tid < p1) {
             const int q = p0 + tid;
             nidx = pidx[q];
 #pragma unroll
@@ -287,6 +288,14 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
             }
         }
         for (int p = p0 + tid; p < p1; p += bs) {
+            if (!PF) {
+                nidx = pidx[p];
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    if (!(DIM == 2 && a == 1)) noff[a] = poff[a][p];
+                    nu[a] = pu[a][p];
+                }
+            }
             int c[3];
             unpack_cell<DIM>(nidx, c);
             int lc[3];
@@ -301,7 +310,7 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
                 lc[a] = rel + JL;
                 off[a] = noff[a];
             }
-            if (p + bs < p1) {
+            if (PF && p + bs < p1) {
                 const int q = p + bs;
                 nidx = pidx[q];
 #pragma unroll
@@ -369,19 +378,19 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
     }
 }
 
-template <int DIM, int L, class R, int P>
+template <int DIM, int L, class R, int P, bool PF = false>
 __global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                    int nwork, int wmx, int wmy, int wmz)
 {
-    particles_body<DIM, L, R, P>(Dt, work, nwork, wmx, wmy, wmz);
+    particles_body<DIM, L, R, P, PF>(Dt, work, nwork, wmx, wmy, wmz);
 }
 
 // same body compiled for four waves per SIMD (at most 128 VGPRs)
-template <int DIM, int L, class R, int P>
+template <int DIM, int L, class R, int P, bool PF = false>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 k_particles_w4(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int nwork, int wmx, int wmy, int wmz)
 {
-    particles_body<DIM, L, R, P>(Dt, work, nwork, wmx, wmy, wmz);
+    particles_body<DIM, L, R, P, PF>(Dt, work, nwork, wmx, wmy, wmz);
 }
 
 // ------------------------------------------------------------- Yee sweeps
@@ -485,30 +494,26 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
     const int ntx = (nx + TX - 1) / TX;
     const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
     const int tid = threadIdx.x;
-    auto wrapx = [&](int g) { g += g < 0 ? nx : 0; g -= g >= nx ? nx : 0; return (g < 0 || g >= nx) ? ((g % nx) + nx) % nx : g; };
-    auto wrapz = [&](int g) { g += g < 0 ? nz : 0; g -= g >= nz ? nz : 0; return (g < 0 || g >= nz) ? ((g % nz) + nz) % nz : g; };
-    gp<R> E[3] = {G<R>(D.E[0]), G<R>(D.E[1]), G<R>(D.E[2])};
-    gp<R> B[3] = {G<R>(D.B[0]), G<R>(D.B[1]), G<R>(D.B[2])};
-    gp<const JT> J[3] = {G<JT>((const void *)D.J[0]), G<JT>((const void *)D.J[1]), G<JT>((const void *)D.J[2])};
+    const gp<const R> E[3] = {G<R>((const void *)D.E[0]), G<R>((const void *)D.E[1]), G<R>((const void *)D.E[2])};
+    const gp<const R> B[3] = {G<R>((const void *)D.B[0]), G<R>((const void *)D.B[1]), G<R>((const void *)D.B[2])};
+    const gp<const JT> J[3] = {G<JT>((const void *)D.J[0]), G<JT>((const void *)D.J[1]), G<JT>((const void *)D.J[2])};
     // E, B and J are read with halos that neighbouring tiles own, so the new
     // fields go to the scratch planes T1 (E then B); the seen pass commits them
     gp<R> O[6] = {G<R>(D.T1[0]), G<R>(D.T1[1]), G<R>(D.T1[2]), G<R>(D.T1[3]), G<R>(D.T1[4]), G<R>(D.T1[5])};
-    for (int c = tid; c < EZ * EX; c += blockDim.x) {
+    constexpr int UE = (EZ * EX + 255) / 256, UB = (BZ * BX + 255) / 256, UJ = (JZ * JX + 255) / 256;
+    stage<UE, 3, R, R>(&sE[0][0], EZ * EX, E, EZ * EX, [&](int c) {
         const int lz = c / EX, lx = c - lz * EX;
-        const int g = wrapz(z0 - 1 + lz) * nx + wrapx(x0 - 1 + lx);
-        sE[0][c] = E[0][g]; sE[1][c] = E[1][g]; sE[2][c] = E[2][g];
-    }
-    for (int c = tid; c < BZ * BX; c += blockDim.x) {
+        return wrap_near(z0 - 1 + lz, nz) * nx + wrap_near(x0 - 1 + lx, nx);
+    }, IdentityIx{}, PlainCv{});
+    stage<UB, 3, R, R>(&sB[0][0], BZ * BX, B, BZ * BX, [&](int c) {
         const int lz = c / BX, lx = c - lz * BX;
-        const int g = wrapz(z0 - 1 + lz) * nx + wrapx(x0 - 1 + lx);
-        sB[0][c] = B[0][g]; sB[1][c] = B[1][g]; sB[2][c] = B[2][g];
-    }
-    for (int c = tid; c < JZ * JX; c += blockDim.x) {
+        return wrap_near(z0 - 1 + lz, nz) * nx + wrap_near(x0 - 1 + lx, nx);
+    }, IdentityIx{}, PlainCv{});
+    const double jq = D.jq, jb[3] = {D.jbg[0], D.jbg[1], D.jbg[2]};
+    stage<UJ, 3, JT, R>(&sJ[0][0], JZ * JX, J, JZ * JX, [&](int c) {
         const int lz = c / JX, lx = c - lz * JX;
-        const int g = wrapz(z0 + lz) * nx + wrapx(x0 + lx);
-#pragma unroll
-        for (int k = 0; k < 3; k++) sJ[k][c] = (R)(jreal(J[k][g], D.jq) + D.jbg[k]);
-    }
+        return wrap_near(z0 + lz, nz) * nx + wrap_near(x0 + lx, nx);
+    }, IdentityIx{}, [&](int k, JT v) { return (R)(jreal(v, jq) + jb[k]); });
     __syncthreads();
     const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
     // B^{n-1/2} on the B window: forward differences of E (E local index = B local index)
@@ -631,17 +636,13 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     for (int i = threadIdx.x; i <= 2 * hz; i += blockDim.x) tz[i] = (R)tzs[i];
     for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)D.tx[i];
     const void *sp = commit ? D.T1[comp] : (comp < 3 ? D.E[comp] : D.B[comp - 3]);
-    gp<const R> src = G<R>(sp);
-    for (int c = threadIdx.x; c < wx * wz; c += blockDim.x) {
-        const int zz = (int)(((float)c + 0.5f) * (1.0f / (float)wx));
+    const gp<const R> src[1] = {G<R>(sp)};
+    const float iwx = 1.0f / (float)wx;
+    stage<8, 1, R, R>(win, 0, src, wx * wz, [&](int c) {
+        const int zz = (int)(((float)c + 0.5f) * iwx);
         const int xx = c - zz * wx;
-        int gx = x0 - hx + xx, gz = z0 - hz + zz;
-        gx += gx < 0 ? nx : 0; gx -= gx >= nx ? nx : 0;
-        gz += gz < 0 ? nz : 0; gz -= gz >= nz ? nz : 0;
-        if (gx < 0 || gx >= nx) gx = ((gx % nx) + nx) % nx;
-        if (gz < 0 || gz >= nz) gz = ((gz % nz) + nz) % nz;
-        win[c] = src[gz * nx + gx];
-    }
+        return wrap_near(z0 - hz + zz, nz) * nx + wrap_near(x0 - hx + xx, nx);
+    }, IdentityIx{}, PlainCv{});
     __syncthreads();
     for (int c = threadIdx.x; c < wx * SEEN_TZ; c += blockDim.x) {
         const int zz = (int)(((float)c + 0.5f) * (1.0f / (float)wx));
@@ -1024,11 +1025,13 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
     const size_t smem = particle_smem_bytes(c.dims, c.fp32, wm);
     dim3 g(grid > 0 ? grid : nwork), b(block);
 #define PK(D_, L_, P_) k_particles<D_, L_, R, P_><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2])
+#define PK24(K_, PF_) K_<2, 1, float, 24, PF_><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2])
     DISPATCH_R(c.fp32, {
         if (c.dims == 2 && c.order == 1) {
             if (wm[0] == 24 && wm[2] == 24) {
-                if (c.fp32 && c.waves4)
-                    k_particles_w4<2, 1, float, 24><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2]);
+                if (c.fp32 && c.waves4 && c.prefetch) PK24(k_particles_w4, true);
+                else if (c.fp32 && c.waves4) PK24(k_particles_w4, false);
+                else if (c.fp32 && c.prefetch) PK24(k_particles, true);
                 else PK(2, 1, 24);
             } else if (wm[0] == 32 && wm[2] == 32) PK(2, 1, 32);
             else PK(2, 1, 0);
@@ -1039,6 +1042,7 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
         else PK(3, 3, 0);
     });
 #undef PK
+#undef PK24
     return hip_ok(hipGetLastError());
 }
 
