@@ -621,11 +621,14 @@ __global__ void __launch_bounds__(256) k_zero_lseen(const InstDesc *__restrict__
 // ------------------------------------------------------------ fused 2D kernels
 // Adjoint of the fields as seen by the particles, 2D, one (64 x TZ) tile of one
 // component per block.  GRAD (components x, y): Lambda = F lambda_Et is formed
-// in LDS (filter passes only), then lambda_E += sum_j a_j S_z^j Lambda
-// (= Psi_E(S_z) F lambda_Et) and dW/da_j += <S_z^j Lambda, E1>.  Otherwise
-// (E_z and all of B): lambda += Psi_B(S_z) F lambda_t with the combined taps.
+// in LDS (filter passes only), then lambda_E + sum_j a_j S_z^j Lambda
+// (= lambda_E + Psi_E(S_z) F lambda_Et) and dW/da_j += <S_z^j Lambda, E1>.
+// Otherwise (E_z and all of B): lambda + Psi_B(S_z) F lambda_t with the
+// combined taps.  The sums go to the scratch planes T1: the reverse Yee kernel
+// reads them with halos and writes lambda_E, lambda_B.  HZ (half-width of the
+// z pass), HX and DEG >= 0 are compile-time widths; -1 reads the descriptor.
 #define ADJ_TX 64
-template <class R, int TZ, bool GRAD>
+template <class R, int TZ, bool GRAD, int HZ, int HX, int DEG>
 __global__ void __launch_bounds__(256) k_adj_seen_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                      int comp0)
 {
@@ -636,9 +639,9 @@ __global__ void __launch_bounds__(256) k_adj_seen_2d(const InstDesc *__restrict_
     const int nx = D.n[0], nz = D.n[2];
     const int ntx = (nx + ADJ_TX - 1) / ADJ_TX;
     const int x0 = (t % ntx) * ADJ_TX, z0 = (t / ntx) * TZ;
-    const int hx = D.hx;
-    const int deg = GRAD ? D.psi_deg : 0;
-    const int hz = GRAD ? D.hzf : D.hz;             // z half-width of the first pass
+    const int hx = HX >= 0 ? HX : D.hx;
+    const int deg = GRAD ? (DEG >= 0 ? DEG : D.psi_deg) : 0;
+    const int hz = HZ >= 0 ? HZ : (GRAD ? D.hzf : D.hz);   // z half-width of the first pass
     const int wx = ADJ_TX + 2 * hx;
     const int rows_mid = TZ + 2 * deg;              // rows kept after the z pass
     const int wz = rows_mid + 2 * hz;
@@ -649,8 +652,20 @@ __global__ void __launch_bounds__(256) k_adj_seen_2d(const InstDesc *__restrict_
     R *tx = tz + 2 * PIC_MAX_HZ + 1;
     __shared__ double red[9][4];
     const double *tzs = GRAD ? D.tzf : D.tz[comp < 2 ? 0 : 1];
-    for (int i = threadIdx.x; i <= 2 * hz; i += blockDim.x) tz[i] = (R)tzs[i];
-    for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)D.tx[i];
+    constexpr int NTZ = HZ >= 0 ? 2 * HZ + 1 : 1, NTX = HX >= 0 ? 2 * HX + 1 : 1;
+    R rz[NTZ], rx[NTX];
+    if constexpr (HZ >= 0) {
+#pragma unroll
+        for (int k = 0; k < NTZ; k++) rz[k] = (R)tzs[k];
+    } else {
+        for (int i = threadIdx.x; i <= 2 * hz; i += blockDim.x) tz[i] = (R)tzs[i];
+    }
+    if constexpr (HX >= 0) {
+#pragma unroll
+        for (int k = 0; k < NTX; k++) rx[k] = (R)D.tx[k];
+    } else {
+        for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)D.tx[i];
+    }
     const gp<const R> src[1] = {G<R>((const void *)(comp < 3 ? D.lEt[comp] : D.lBt[comp - 3]))};
     const float iwx = 1.0f / (float)wx;
     stage<8, 1, R, R>(win, 0, src, wx * wz, [&](int c) {
@@ -660,38 +675,55 @@ __global__ void __launch_bounds__(256) k_adj_seen_2d(const InstDesc *__restrict_
     }, IdentityIx{}, PlainCv{});
     __syncthreads();
     for (int c = threadIdx.x; c < wx * rows_mid; c += blockDim.x) {
-        const int zz = c / wx, xx = c - zz * wx;
+        const int zz = (int)(((float)c + 0.5f) * iwx);
+        const int xx = c - zz * wx;
+        const R *w = win + zz * wx + xx;
         R acc = R(0);
-        for (int k = 0; k <= 2 * hz; k++) acc += tz[k] * win[(zz + k) * wx + xx];
+        if constexpr (HZ >= 0) {
+#pragma unroll
+            for (int k = 0; k < NTZ; k++) acc += rz[k] * w[k * wx];
+        } else {
+            for (int k = 0; k <= 2 * hz; k++) acc += tz[k] * w[k * wx];
+        }
         mid[c] = acc;
     }
     __syncthreads();
     for (int c = threadIdx.x; c < ADJ_TX * rows_mid; c += blockDim.x) {
         const int zz = c / ADJ_TX, xx = c - zz * ADJ_TX;
+        const R *m = mid + zz * wx + xx;
         R acc = R(0);
-        for (int k = 0; k <= 2 * hx; k++) acc += tx[k] * mid[zz * wx + xx + k];
+        if constexpr (HX >= 0) {
+#pragma unroll
+            for (int k = 0; k < NTX; k++) acc += rx[k] * m[k];
+        } else {
+            for (int k = 0; k <= 2 * hx; k++) acc += tx[k] * m[k];
+        }
         lam[c] = acc;
     }
     __syncthreads();
-    // lambda_E, lambda_B plus this contribution go to the scratch planes T1: the
-    // reverse Yee kernel reads them with halos and writes lambda_E, lambda_B
-    gp<const R> own = G<R>((const void *)(comp < 3 ? D.lE[comp] : D.lB[comp - 3]));
+    const gp<const R> own = G<R>((const void *)(comp < 3 ? D.lE[comp] : D.lB[comp - 3]));
     gp<R> dst = G<R>(D.T1[comp]);
-    double gpart[9];
-    for (int j = 0; j < 9; j++) gpart[j] = 0.0;
+    constexpr int NJ = GRAD ? (DEG >= 0 ? DEG + 1 : 9) : 1;
+    R gpart[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; j++) gpart[j] = R(0);
     for (int c = threadIdx.x; c < ADJ_TX * TZ; c += blockDim.x) {
         const int zz = c / ADJ_TX, xx = c - zz * ADJ_TX;
         const int gx = x0 + xx, gz = z0 + zz;
         if (gx >= nx || gz >= nz) continue;
         const int g = gz * nx + gx;
         if constexpr (GRAD) {
-            const double e1 = (double)G<R>((const void *)D.E[comp])[g];
+            const R e1 = G<R>((const void *)D.E[comp])[g];
+            const R *l = lam + (zz + deg) * ADJ_TX + xx;
             R add = R(0);
-            for (int j = 0; j <= deg; j++) {
+#pragma unroll
+            for (int j = 0; j < NJ; j++) {
+                if (DEG < 0 && j > deg) break;
                 R tj = R(0);
-                for (int k = -j; k <= j; k++) tj += (R)D.sj[j][8 + k] * lam[(zz + deg + k) * ADJ_TX + xx];
+#pragma unroll
+                for (int k = -j; k <= j; k++) tj += (R)D.sj[j][8 + k] * l[k * ADJ_TX];
                 add += (R)D.psi_e[j] * tj;
-                gpart[j] += (double)tj * e1;
+                gpart[j] += tj * e1;
             }
             dst[g] = own[g] + add;
         } else {
@@ -700,8 +732,10 @@ __global__ void __launch_bounds__(256) k_adj_seen_2d(const InstDesc *__restrict_
     }
     if constexpr (GRAD) {
         const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        for (int j = 0; j <= deg; j++) {
-            const double v = wave_sum(gpart[j]);
+#pragma unroll
+        for (int j = 0; j < NJ; j++) {
+            if (DEG < 0 && j > deg) break;
+            const double v = wave_sum((double)gpart[j]);
             if (lane == 0) red[j][wave] = v;
         }
         __syncthreads();
@@ -715,76 +749,87 @@ __global__ void __launch_bounds__(256) k_adj_seen_2d(const InstDesc *__restrict_
 
 // Fused transposed Yee update (2D): with h = dt/2 and Cb = Cf^T,
 //   lE' = lE - h Cb lB;   lB' = lB + dt Cf lE';  lJ = -dt lE';   lE'' = lE' - h Cb lB'
-// Windows relative to the tile origin: lB on [-2, T], lE on [-1, T].
+// One window for the six input planes: cells [x0 - 2, x0 + TX + 1) x [z0 - 2, z0 + TZ + 1).
 template <class R, int TZ>
 __global__ void __launch_bounds__(256) k_adj_yee_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
 {
     constexpr int TX = PIC_YEE_TX;
-    constexpr int EX = TX + 2, EZ = TZ + 2, BX = TX + 3, BZ = TZ + 3;
-    __shared__ R sE[3][EZ * EX], sB[3][BZ * BX];
+    constexpr int WX = TX + 3, WZ = TZ + 3, WN = WX * WZ;
+    __shared__ R sE[3][WN], sB[3][WN];
     const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
     const InstDesc &D = Dt[inst];
     const int nx = D.n[0], nz = D.n[2];
     const int ntx = (nx + TX - 1) / TX;
     const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, bs = blockDim.x;
     // inputs: lambda_E, lambda_B as left in T1 by the reverse seen kernels
-    const gp<const R> iE[3] = {G<R>((const void *)D.T1[0]), G<R>((const void *)D.T1[1]), G<R>((const void *)D.T1[2])};
-    const gp<const R> iB[3] = {G<R>((const void *)D.T1[3]), G<R>((const void *)D.T1[4]), G<R>((const void *)D.T1[5])};
+    const gp<const R> in[6] = {G<R>((const void *)D.T1[0]), G<R>((const void *)D.T1[1]), G<R>((const void *)D.T1[2]),
+                               G<R>((const void *)D.T1[3]), G<R>((const void *)D.T1[4]), G<R>((const void *)D.T1[5])};
     gp<R> lE[3] = {G<R>(D.lE[0]), G<R>(D.lE[1]), G<R>(D.lE[2])};
     gp<R> lB[3] = {G<R>(D.lB[0]), G<R>(D.lB[1]), G<R>(D.lB[2])};
     gp<R> lJ[3] = {G<R>(D.lJ[0]), G<R>(D.lJ[1]), G<R>(D.lJ[2])};
-    constexpr int UE = (EZ * EX + 255) / 256, UB = (BZ * BX + 255) / 256;
-    stage<UE, 3, R, R>(&sE[0][0], EZ * EX, iE, EZ * EX, [&](int c) {
-        const int lz = c / EX, lx = c - lz * EX;
-        return wrap_near(z0 - 1 + lz, nz) * nx + wrap_near(x0 - 1 + lx, nx);
-    }, IdentityIx{}, PlainCv{});
-    stage<UB, 3, R, R>(&sB[0][0], BZ * BX, iB, BZ * BX, [&](int c) {
-        const int lz = c / BX, lx = c - lz * BX;
-        return wrap_near(z0 - 2 + lz, nz) * nx + wrap_near(x0 - 2 + lx, nx);
-    }, IdentityIx{}, PlainCv{});
-    __syncthreads();
-    const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
-    // lE' on the whole E window: backward differences of lB (B local = E local + 1)
-    for (int c = tid; c < EZ * EX; c += blockDim.x) {
-        const int lz = c / EX, lx = c - lz * EX;
-        const int b = (lz + 1) * BX + lx + 1, bxm = b - 1, bzm = b - BX;
-        const R cx = -(sB[1][b] - sB[1][bzm]) * idz;
-        const R cy = (sB[0][b] - sB[0][bzm]) * idz - (sB[2][b] - sB[2][bxm]) * idx;
-        const R cz = (sB[1][b] - sB[1][bxm]) * idx;
-        sE[0][c] -= h * cx;
-        sE[1][c] -= h * cy;
-        sE[2][c] -= h * cz;
+    constexpr int U = (WN + 255) / 256;
+    for (int c0 = tid; c0 < WN; c0 += U * bs) {
+        int g[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int c = c0 + u * bs, lz = c / WX, lx = c - lz * WX;
+            g[u] = c < WN ? wrap_near(z0 - 2 + lz, nz) * nx + wrap_near(x0 - 2 + lx, nx) : 0;
+        }
+        R v[U][6];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int k = 0; k < 6; k++) v[u][k] = in[k][g[u]];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int c = c0 + u * bs;
+            if (c < WN) {
+#pragma unroll
+                for (int k = 0; k < 3; k++) { sE[k][c] = v[u][k]; sB[k][c] = v[u][3 + k]; }
+            }
+        }
     }
     __syncthreads();
-    // lB' on B locals [1, T+1] x [1, TZ+1]: forward differences of lE' (E local = B local - 1)
-    for (int c = tid; c < (TZ + 1) * (TX + 1); c += blockDim.x) {
+    const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
+    // lE' on [-1, T]: backward differences of lB
+    for (int c = tid; c < (TZ + 2) * (TX + 2); c += bs) {
+        const int lz = c / (TX + 2) + 1, lx = c % (TX + 2) + 1;
+        const int e = lz * WX + lx, exm = e - 1, ezm = e - WX;
+        const R cx = -(sB[1][e] - sB[1][ezm]) * idz;
+        const R cy = (sB[0][e] - sB[0][ezm]) * idz - (sB[2][e] - sB[2][exm]) * idx;
+        const R cz = (sB[1][e] - sB[1][exm]) * idx;
+        sE[0][e] -= h * cx;
+        sE[1][e] -= h * cy;
+        sE[2][e] -= h * cz;
+    }
+    __syncthreads();
+    // lB' on [-1, T): forward differences of lE'
+    for (int c = tid; c < (TZ + 1) * (TX + 1); c += bs) {
         const int lz = c / (TX + 1) + 1, lx = c % (TX + 1) + 1;
-        const int b = lz * BX + lx;
-        const int e = (lz - 1) * EX + lx - 1, exp = e + 1, ezp = e + EX;
+        const int e = lz * WX + lx, exp = e + 1, ezp = e + WX;
         const R fx = -(sE[1][ezp] - sE[1][e]) * idz;
         const R fy = (sE[0][ezp] - sE[0][e]) * idz - (sE[2][exp] - sE[2][e]) * idx;
         const R fz = (sE[1][exp] - sE[1][e]) * idx;
-        sB[0][b] += dt * fx;
-        sB[1][b] += dt * fy;
-        sB[2][b] += dt * fz;
+        sB[0][e] += dt * fx;
+        sB[1][e] += dt * fy;
+        sB[2][e] += dt * fz;
     }
     __syncthreads();
-    for (int c = tid; c < TZ * TX; c += blockDim.x) {
+    for (int c = tid; c < TZ * TX; c += bs) {
         const int lz = c / TX, lx = c - lz * TX;
         const int gx = x0 + lx, gz = z0 + lz;
         if (gx >= nx || gz >= nz) continue;
-        const int e = (lz + 1) * EX + lx + 1;
-        const int b = (lz + 2) * BX + lx + 2, bxm = b - 1, bzm = b - BX;
-        const R cx = -(sB[1][b] - sB[1][bzm]) * idz;
-        const R cy = (sB[0][b] - sB[0][bzm]) * idz - (sB[2][b] - sB[2][bxm]) * idx;
-        const R cz = (sB[1][b] - sB[1][bxm]) * idx;
+        const int e = (lz + 2) * WX + lx + 2, exm = e - 1, ezm = e - WX;
+        const R cx = -(sB[1][e] - sB[1][ezm]) * idz;
+        const R cy = (sB[0][e] - sB[0][ezm]) * idz - (sB[2][e] - sB[2][exm]) * idx;
+        const R cz = (sB[1][e] - sB[1][exm]) * idx;
         const int g = gz * nx + gx;
         lJ[0][g] = -dt * sE[0][e]; lJ[1][g] = -dt * sE[1][e]; lJ[2][g] = -dt * sE[2][e];
         lE[0][g] = sE[0][e] - h * cx;
         lE[1][g] = sE[1][e] - h * cy;
         lE[2][g] = sE[2][e] - h * cz;
-        lB[0][g] = sB[0][b]; lB[1][g] = sB[1][b]; lB[2][g] = sB[2][b];
+        lB[0][g] = sB[0][e]; lB[1][g] = sB[1][e]; lB[2][g] = sB[2][e];
     }
 }
 
@@ -843,8 +888,15 @@ int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fw
         if (live.dims == 2) {
             // fused LDS kernels on 64 x 8 tiles (the awork list)
             const size_t sm = adj_seen_smem_bytes(live.fp32);
-            k_adj_seen_2d<R, PIC_ADJ_TZ, true><<<dim3(nawork, 2), bf, sm, st>>>(tape.desc, awork, 0);
-            k_adj_seen_2d<R, PIC_ADJ_TZ, false><<<dim3(nawork, 4), bf, sm, st>>>(live.desc, awork, 2);
+            const dim3 g2a(nawork, 2), g4a(nawork, 4);
+            if (live.hz == 8 && live.hx == 4 && live.psi_deg == 4 && live.hzf == 4) {
+                // correction of degree 4 with four filter passes: z filter 4, combined 8
+                k_adj_seen_2d<R, PIC_ADJ_TZ, true, 4, 4, 4><<<g2a, bf, sm, st>>>(tape.desc, awork, 0);
+                k_adj_seen_2d<R, PIC_ADJ_TZ, false, 8, 4, 0><<<g4a, bf, sm, st>>>(live.desc, awork, 2);
+            } else {
+                k_adj_seen_2d<R, PIC_ADJ_TZ, true, -1, -1, -1><<<g2a, bf, sm, st>>>(tape.desc, awork, 0);
+                k_adj_seen_2d<R, PIC_ADJ_TZ, false, -1, -1, 0><<<g4a, bf, sm, st>>>(live.desc, awork, 2);
+            }
             k_adj_yee_2d<R, PIC_ADJ_TZ><<<dim3(nawork), bf, 0, st>>>(live.desc, awork);
         } else {
             // lambda_E += M_E lambda_Et, lambda_B += M_B lambda_Bt

@@ -217,6 +217,15 @@ LaunchCtx ctx(const pic_state *s)
     c.seen_tz = s->seen_tz;
     c.waves4 = s->waves4;
     c.prefetch = s->prefetch;
+    if (!s->desc.empty()) {
+        const InstDesc &d0 = s->desc[0];
+        c.hz = d0.hz; c.hx = d0.hx; c.hzf = d0.hzf; c.psi_deg = d0.psi_deg;
+        for (const InstDesc &d : s->desc)
+            if (d.hz != d0.hz || d.hx != d0.hx || d.hzf != d0.hzf || d.psi_deg != d0.psi_deg) {
+                c.hz = c.hx = c.hzf = c.psi_deg = -1;
+                break;
+            }
+    }
     return c;
 }
 

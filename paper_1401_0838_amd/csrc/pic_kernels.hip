@@ -486,72 +486,86 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
 {
     typedef typename JOf<R>::T JT;
     constexpr int TX = YEE_TX;
-    constexpr int EX = TX + 3, EZ = TZ + 3, BX = TX + 2, BZ = TZ + 2, JX = TX + 1, JZ = TZ + 1;
-    __shared__ R sE[3][EZ * EX], sB[3][BZ * BX], sJ[3][JZ * JX];
+    // one window for all nine planes: cells [x0 - 1, x0 + TX + 2) x [z0 - 1, z0 + TZ + 2)
+    constexpr int WX = TX + 3, WZ = TZ + 3, WN = WX * WZ;
+    __shared__ R sE[3][WN], sB[3][WN], sJ[3][WN];
     const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
     const InstDesc &D = Dt[inst];
     const int nx = D.n[0], nz = D.n[2];
     const int ntx = (nx + TX - 1) / TX;
     const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, bs = blockDim.x;
     const gp<const R> E[3] = {G<R>((const void *)D.E[0]), G<R>((const void *)D.E[1]), G<R>((const void *)D.E[2])};
     const gp<const R> B[3] = {G<R>((const void *)D.B[0]), G<R>((const void *)D.B[1]), G<R>((const void *)D.B[2])};
     const gp<const JT> J[3] = {G<JT>((const void *)D.J[0]), G<JT>((const void *)D.J[1]), G<JT>((const void *)D.J[2])};
     // E, B and J are read with halos that neighbouring tiles own, so the new
     // fields go to the scratch planes T1 (E then B); the seen pass commits them
     gp<R> O[6] = {G<R>(D.T1[0]), G<R>(D.T1[1]), G<R>(D.T1[2]), G<R>(D.T1[3]), G<R>(D.T1[4]), G<R>(D.T1[5])};
-    constexpr int UE = (EZ * EX + 255) / 256, UB = (BZ * BX + 255) / 256, UJ = (JZ * JX + 255) / 256;
-    stage<UE, 3, R, R>(&sE[0][0], EZ * EX, E, EZ * EX, [&](int c) {
-        const int lz = c / EX, lx = c - lz * EX;
-        return wrap_near(z0 - 1 + lz, nz) * nx + wrap_near(x0 - 1 + lx, nx);
-    }, IdentityIx{}, PlainCv{});
-    stage<UB, 3, R, R>(&sB[0][0], BZ * BX, B, BZ * BX, [&](int c) {
-        const int lz = c / BX, lx = c - lz * BX;
-        return wrap_near(z0 - 1 + lz, nz) * nx + wrap_near(x0 - 1 + lx, nx);
-    }, IdentityIx{}, PlainCv{});
     const double jq = D.jq, jb[3] = {D.jbg[0], D.jbg[1], D.jbg[2]};
-    stage<UJ, 3, JT, R>(&sJ[0][0], JZ * JX, J, JZ * JX, [&](int c) {
-        const int lz = c / JX, lx = c - lz * JX;
-        return wrap_near(z0 + lz, nz) * nx + wrap_near(x0 + lx, nx);
-    }, IdentityIx{}, [&](int k, JT v) { return (R)(jreal(v, jq) + jb[k]); });
-    __syncthreads();
-    const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
-    // B^{n-1/2} on the B window: forward differences of E (E local index = B local index)
-    for (int c = tid; c < BZ * BX; c += blockDim.x) {
-        const int lz = c / BX, lx = c - lz * BX;
-        const int e = lz * EX + lx, ex = e + 1, ez = e + EX;
-        const R dzEy = (sE[1][ez] - sE[1][e]) * idz, dzEx = (sE[0][ez] - sE[0][e]) * idz;
-        const R dxEz = (sE[2][ex] - sE[2][e]) * idx, dxEy = (sE[1][ex] - sE[1][e]) * idx;
-        sB[0][c] -= h * (-dzEy);
-        sB[1][c] -= h * (dzEx - dxEz);
-        sB[2][c] -= h * dxEy;
+    // staging: U window cells per thread, all 9 U loads issued before any store
+    constexpr int U = (WN + 255) / 256;
+    for (int c0 = tid; c0 < WN; c0 += U * bs) {
+        int g[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int c = c0 + u * bs, lz = c / WX, lx = c - lz * WX;
+            g[u] = c < WN ? wrap_near(z0 - 1 + lz, nz) * nx + wrap_near(x0 - 1 + lx, nx) : 0;
+        }
+        R ve[U][3], vb[U][3];
+        JT vj[U][3];
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) { ve[u][k] = E[k][g[u]]; vb[u][k] = B[k][g[u]]; vj[u][k] = J[k][g[u]]; }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int c = c0 + u * bs;
+            if (c < WN) {
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    sE[k][c] = ve[u][k];
+                    sB[k][c] = vb[u][k];
+                    sJ[k][c] = (R)(jreal(vj[u][k], jq) + jb[k]);
+                }
+            }
+        }
     }
     __syncthreads();
-    // E^n on [0, T]: backward differences of B^{n-1/2}; J local = E local - 1
-    for (int c = tid; c < JZ * JX; c += blockDim.x) {
-        const int lz = c / JX, lx = c - lz * JX;
-        const int b = (lz + 1) * BX + lx + 1, bxm = b - 1, bzm = b - BX;
-        const int e = (lz + 1) * EX + lx + 1;
-        const R dzBy = (sB[1][b] - sB[1][bzm]) * idz, dzBx = (sB[0][b] - sB[0][bzm]) * idz;
-        const R dxBz = (sB[2][b] - sB[2][bxm]) * idx, dxBy = (sB[1][b] - sB[1][bxm]) * idx;
-        sE[0][e] += dt * (-dzBy - sJ[0][c]);
-        sE[1][e] += dt * (dzBx - dxBz - sJ[1][c]);
-        sE[2][e] += dt * (dxBy - sJ[2][c]);
+    const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
+    // B^{n-1/2} on [-1, T]: forward differences of E
+    for (int c = tid; c < (TZ + 2) * (TX + 2); c += bs) {
+        const int lz = c / (TX + 2), lx = c - lz * (TX + 2);
+        const int e = lz * WX + lx, ex = e + 1, ez = e + WX;
+        const R dzEy = (sE[1][ez] - sE[1][e]) * idz, dzEx = (sE[0][ez] - sE[0][e]) * idz;
+        const R dxEz = (sE[2][ex] - sE[2][e]) * idx, dxEy = (sE[1][ex] - sE[1][e]) * idx;
+        sB[0][e] -= h * (-dzEy);
+        sB[1][e] -= h * (dzEx - dxEz);
+        sB[2][e] -= h * dxEy;
+    }
+    __syncthreads();
+    // E^n on [0, T]: backward differences of B^{n-1/2}
+    for (int c = tid; c < (TZ + 1) * (TX + 1); c += bs) {
+        const int lz = c / (TX + 1), lx = c - lz * (TX + 1);
+        const int e = (lz + 1) * WX + lx + 1, exm = e - 1, ezm = e - WX;
+        const R dzBy = (sB[1][e] - sB[1][ezm]) * idz, dzBx = (sB[0][e] - sB[0][ezm]) * idz;
+        const R dxBz = (sB[2][e] - sB[2][exm]) * idx, dxBy = (sB[1][e] - sB[1][exm]) * idx;
+        sE[0][e] += dt * (-dzBy - sJ[0][e]);
+        sE[1][e] += dt * (dzBx - dxBz - sJ[1][e]);
+        sE[2][e] += dt * (dxBy - sJ[2][e]);
     }
     __syncthreads();
     // B^n on [0, T) and the stores
-    for (int c = tid; c < TZ * TX; c += blockDim.x) {
+    for (int c = tid; c < TZ * TX; c += bs) {
         const int lz = c / TX, lx = c - lz * TX;
         const int gx = x0 + lx, gz = z0 + lz;
         if (gx >= nx || gz >= nz) continue;
-        const int e = (lz + 1) * EX + lx + 1, ex = e + 1, ez = e + EX;
-        const int b = (lz + 1) * BX + lx + 1;
+        const int e = (lz + 1) * WX + lx + 1, ex = e + 1, ez = e + WX;
         const R dzEy = (sE[1][ez] - sE[1][e]) * idz, dzEx = (sE[0][ez] - sE[0][e]) * idz;
         const R dxEz = (sE[2][ex] - sE[2][e]) * idx, dxEy = (sE[1][ex] - sE[1][e]) * idx;
         const int g = gz * nx + gx;
-        O[3][g] = sB[0][b] - h * (-dzEy);
-        O[4][g] = sB[1][b] - h * (dzEx - dxEz);
-        O[5][g] = sB[2][b] - h * dxEy;
+        O[3][g] = sB[0][e] - h * (-dzEy);
+        O[4][g] = sB[1][e] - h * (dzEx - dxEz);
+        O[5][g] = sB[2][e] - h * dxEy;
         O[0][g] = sE[0][e]; O[1][g] = sE[1][e]; O[2][g] = sE[2][e];
     }
 }
@@ -613,8 +627,11 @@ __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ 
 // one component is loaded with its stencil halo into LDS, the combined z
 // stencil (Psi o z filter) is applied into a second LDS tile, then the x
 // filter stencil writes the output.  blockIdx.y = component, work = (inst, tile).
+// HZ, HX >= 0 fix the stencil half-widths at compile time (taps in registers,
+// loops unrolled so every LDS read of an output is in flight at once); -1
+// reads them from the descriptor.
 #define SEEN_TX PIC_SEEN_TX
-template <class R, int SEEN_TZ>
+template <class R, int SEEN_TZ, int HZ, int HX>
 __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                  int commit)
 {
@@ -626,15 +643,27 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     const int nx = D.n[0], nz = D.n[2];
     const int ntx = (nx + SEEN_TX - 1) / SEEN_TX;
     const int x0 = (t % ntx) * SEEN_TX, z0 = (t / ntx) * SEEN_TZ;
-    const int hz = D.hz, hx = D.hx;
+    const int hz = HZ >= 0 ? HZ : D.hz, hx = HX >= 0 ? HX : D.hx;
     const int wx = SEEN_TX + 2 * hx, wz = SEEN_TZ + 2 * hz;
     R *win = reinterpret_cast<R *>(smem);
     R *mid = win + wx * wz;
     R *tz = mid + wx * SEEN_TZ;
     R *tx = tz + 2 * PIC_MAX_HZ + 1;
     const double *tzs = D.tz[comp < 2 ? 0 : 1];
-    for (int i = threadIdx.x; i <= 2 * hz; i += blockDim.x) tz[i] = (R)tzs[i];
-    for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)D.tx[i];
+    constexpr int NTZ = HZ >= 0 ? 2 * HZ + 1 : 1, NTX = HX >= 0 ? 2 * HX + 1 : 1;
+    R rz[NTZ], rx[NTX];
+    if constexpr (HZ >= 0) {
+#pragma unroll
+        for (int k = 0; k < NTZ; k++) rz[k] = (R)tzs[k];
+    } else {
+        for (int i = threadIdx.x; i <= 2 * hz; i += blockDim.x) tz[i] = (R)tzs[i];
+    }
+    if constexpr (HX >= 0) {
+#pragma unroll
+        for (int k = 0; k < NTX; k++) rx[k] = (R)D.tx[k];
+    } else {
+        for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)D.tx[i];
+    }
     const void *sp = commit ? D.T1[comp] : (comp < 3 ? D.E[comp] : D.B[comp - 3]);
     const gp<const R> src[1] = {G<R>(sp)};
     const float iwx = 1.0f / (float)wx;
@@ -645,10 +674,16 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     }, IdentityIx{}, PlainCv{});
     __syncthreads();
     for (int c = threadIdx.x; c < wx * SEEN_TZ; c += blockDim.x) {
-        const int zz = (int)(((float)c + 0.5f) * (1.0f / (float)wx));
+        const int zz = (int)(((float)c + 0.5f) * iwx);
         const int xx = c - zz * wx;
+        const R *w = win + zz * wx + xx;
         R acc = R(0);
-        for (int k = 0; k <= 2 * hz; k++) acc += tz[k] * win[(zz + k) * wx + xx];
+        if constexpr (HZ >= 0) {
+#pragma unroll
+            for (int k = 0; k < NTZ; k++) acc += rz[k] * w[k * wx];
+        } else {
+            for (int k = 0; k <= 2 * hz; k++) acc += tz[k] * w[k * wx];
+        }
         mid[c] = acc;
     }
     __syncthreads();
@@ -657,8 +692,14 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
         const int zz = c / SEEN_TX, xx = c % SEEN_TX;
         const int gx = x0 + xx, gz = z0 + zz;
         if (gx >= nx || gz >= nz) continue;
+        const R *m = mid + zz * wx + xx;
         R acc = R(0);
-        for (int k = 0; k <= 2 * hx; k++) acc += tx[k] * mid[zz * wx + xx + k];
+        if constexpr (HX >= 0) {
+#pragma unroll
+            for (int k = 0; k < NTX; k++) acc += rx[k] * m[k];
+        } else {
+            for (int k = 0; k <= 2 * hx; k++) acc += tx[k] * m[k];
+        }
         const int g = gz * nx + gx;
         dst[g] = acc;
         if (commit) {
@@ -991,6 +1032,28 @@ size_t seen_smem_bytes(int fp32, int tz)
     return (size_t)(wx * wz + wx * tz + 2 * PIC_MAX_HZ + 1 + 2 * PIC_MAX_HX + 1) * (fp32 ? 4 : 8);
 }
 
+template <class R, int TZ>
+void launch_seen_2d_tz(const LaunchCtx &c, const int2 *swork, int nswork, int commit)
+{
+    const size_t sm = seen_smem_bytes(c.fp32, TZ);
+    const dim3 g(nswork, 6), b(PIC_FIELD_CHUNK);
+    // half-widths: correction of degree 4 with four filter passes (8, 4);
+    // filter alone (4, 4); correction alone (4, 0); neither (0, 0)
+    if (c.hz == 8 && c.hx == 4) k_seen_2d<R, TZ, 8, 4><<<g, b, sm, c.stream>>>(c.desc, swork, commit);
+    else if (c.hz == 4 && c.hx == 4) k_seen_2d<R, TZ, 4, 4><<<g, b, sm, c.stream>>>(c.desc, swork, commit);
+    else if (c.hz == 4 && c.hx == 0) k_seen_2d<R, TZ, 4, 0><<<g, b, sm, c.stream>>>(c.desc, swork, commit);
+    else if (c.hz == 0 && c.hx == 0) k_seen_2d<R, TZ, 0, 0><<<g, b, sm, c.stream>>>(c.desc, swork, commit);
+    else k_seen_2d<R, TZ, -1, -1><<<g, b, sm, c.stream>>>(c.desc, swork, commit);
+}
+
+template <class R>
+void launch_seen_2d(const LaunchCtx &c, const int2 *swork, int nswork, int commit)
+{
+    if (c.seen_tz == 8) launch_seen_2d_tz<R, 8>(c, swork, nswork, commit);
+    else if (c.seen_tz == 16) launch_seen_2d_tz<R, 16>(c, swork, nswork, commit);
+    else launch_seen_2d_tz<R, 32>(c, swork, nswork, commit);
+}
+
 int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork, int commit)
 {
     if (nwork <= 0) return 0;
@@ -998,9 +1061,7 @@ int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *sw
     DISPATCH_R(c.fp32, {
         if (c.dims == 2) {
             const size_t sm = seen_smem_bytes(c.fp32, c.seen_tz);
-            if (c.seen_tz == 8) k_seen_2d<R, 8><<<dim3(nswork, 6), b, sm, c.stream>>>(c.desc, swork, commit);
-            else if (c.seen_tz == 16) k_seen_2d<R, 16><<<dim3(nswork, 6), b, sm, c.stream>>>(c.desc, swork, commit);
-            else k_seen_2d<R, 32><<<dim3(nswork, 6), b, sm, c.stream>>>(c.desc, swork, commit);
+            launch_seen_2d<R>(c, swork, nswork, commit);
         } else {
             k_seen_pass<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1);
             k_seen_pass<0, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2);
