@@ -590,6 +590,8 @@ __global__ void __launch_bounds__(256) k_adj_seed(const InstDesc *__restrict__ D
             ((R *)D.lE[c])[cell] = c < 2 ? dV * e : R(0);
             ((R *)D.lB[c])[cell] = c < 2 ? dV * b : R(0);
             ((R *)D.lJ[c])[cell] = R(0);
+            ((R *)D.lEt[c])[cell] = R(0);
+            ((R *)D.lBt[c])[cell] = R(0);
             if (c < 2) w += 0.5 * D.dV * ((double)e * e + (double)b * b);
         }
     }
@@ -830,6 +832,10 @@ __global__ void __launch_bounds__(256) k_adj_yee_2d(const InstDesc *__restrict__
         lE[1][g] = sE[1][e] - h * cy;
         lE[2][g] = sE[2][e] - h * cz;
         lB[0][g] = sB[0][e]; lB[1][g] = sB[1][e]; lB[2][g] = sB[2][e];
+        // lambda_Et, lambda_Bt were consumed by the reverse seen kernels: clear
+        // them for the next reverse particle step
+#pragma unroll
+        for (int k = 0; k < 3; k++) { G<R>(D.lEt[k])[g] = R(0); G<R>(D.lBt[k])[g] = R(0); }
     }
 }
 
@@ -871,14 +877,17 @@ int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fw
                     int nswork, const int2 *awork, int nawork, const int2 *pwork, int npwork, int block,
                     const int wmax[3])
 {
-    if (launch_seen(tape, fwork, nfwork, swork, nswork, 0)) return -1;   // Et, Bt of this step
+    // Et, Bt of this step: recorded in the tape slot in 2D, recomputed in 3D
+    if (live.dims == 3 && launch_seen(tape, fwork, nfwork, swork, nswork, 0)) return -1;
     const int wm[3] = {wmax[0], live.dims == 3 ? wmax[1] : 1, wmax[2]};
     const size_t smem = adjoint_smem_bytes(live.dims, live.fp32, wm);
     const dim3 gf(nfwork), g6(nfwork, 6), g2(nfwork, 2), bf(PIC_FIELD_CHUNK);
     hipStream_t st = live.stream;
 #define AK(D_, L_) k_adj_particles<D_, L_, R><<<dim3(npwork), dim3(block), smem, st>>>(tape.desc, pwork, npwork, wm[0], wm[1], wm[2])
     DISPATCH_R(live.fp32, {
-        k_zero_lseen<R><<<gf, bf, 0, st>>>(live.desc, fwork);
+        // 2D: the reverse Yee kernel of the previous reverse step (or the seed)
+        // left lambda_Et, lambda_Bt zero
+        if (live.dims == 3) k_zero_lseen<R><<<gf, bf, 0, st>>>(live.desc, fwork);
         if (npwork > 0) {
             if (live.dims == 2 && live.order == 1) AK(2, 1);
             else if (live.dims == 2 && live.order == 3) AK(2, 3);

@@ -43,6 +43,7 @@ struct Snap {
     void *J[3] = {nullptr, nullptr, nullptr};
     int *pidx = nullptr, *tbox = nullptr;
     void *poff[3] = {nullptr, nullptr, nullptr}, *pu[3] = {nullptr, nullptr, nullptr};
+    void *Et[3] = {nullptr, nullptr, nullptr}, *Bt[3] = {nullptr, nullptr, nullptr};   // 2D tape slots
 };
 
 struct Layout {
@@ -191,6 +192,7 @@ struct pic_state {
     hipGraphExec_t gexec_k = nullptr, gexec_1 = nullptr;
     long long step = 0;
     int *trace_pos = nullptr;
+    int *any_resort = nullptr;       // device word shared by all instances: a re-sort is pending
     double *trace = nullptr;
     int trace_cap = 0;
     // reverse mode
@@ -200,6 +202,7 @@ struct pic_state {
     hipGraphExec_t gexec_adj_fwd = nullptr, gexec_adj_seg = nullptr;
     std::vector<std::vector<Snap>> ckpt, tape;   // [instance][slot]
     InstDesc *d_tape_desc = nullptr;             // adj_k * n_inst descriptors
+    InstDesc *d_rec_desc = nullptr;              // 2D: the live step recording into tape slot k
     int adj_wmax[3] = {1, 1, 1};
 };
 
@@ -217,6 +220,7 @@ LaunchCtx ctx(const pic_state *s)
     c.seen_tz = s->seen_tz;
     c.waves4 = s->waves4;
     c.prefetch = s->prefetch;
+    c.any_resort = s->any_resort;
     if (!s->desc.empty()) {
         const InstDesc &d0 = s->desc[0];
         c.hz = d0.hz; c.hx = d0.hx; c.hzf = d0.hzf; c.psi_deg = d0.psi_deg;
@@ -261,6 +265,8 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
     if (s) { s->fwork = fw; s->pwork = pw; s->cwork = cw; s->swork = sw; s->ywork = yw; s->awork = aw; }
     int *tpos = L.take<int>(64);
     if (s) s->trace_pos = tpos;
+    int *anyr = L.take<int>(64);
+    if (s) s->any_resort = anyr;
     int cap = 0;
     for (int i = 0; i < n_inst; i++) cap = std::max(cap, cfgs[i].trace_capacity);
     // one spare row: each step clears the row the next step writes, so a ring
@@ -270,6 +276,8 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
     if (cfgs[0].adjoint_steps > 0) {
         InstDesc *td = L.take<InstDesc>((size_t)cfgs[0].adjoint_ckpt * n_inst);
         if (s) s->d_tape_desc = td;
+        InstDesc *rd = L.take<InstDesc>((size_t)cfgs[0].adjoint_ckpt * n_inst);
+        if (s) s->d_rec_desc = rd;
     }
     for (int i = 0; i < n_inst; i++) {
         const pic_config &c = cfgs[i];
@@ -325,7 +333,7 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
             double *g = L.take<double>(16);
             if (D) { D->grad = g; D->loss = g + 9; }
             // same region order as the live arrays (see above)
-            auto snap = [&](bool with_j) {
+            auto snap = [&](bool with_j, bool with_seen) {
                 Snap sn;
                 for (int k = 0; k < 3; k++) sn.E[k] = plane(R);
                 for (int k = 0; k < 3; k++) sn.B[k] = plane(R);
@@ -336,11 +344,13 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
                     if (!(c.dims == 2 && a == 1)) sn.poff[a] = L.take<char>(n * R);
                 for (int a = 0; a < 3; a++) sn.pu[a] = L.take<char>(n * R);
                 sn.tbox = L.take<int>((size_t)ntiles[i] * 6);
+                if (with_seen)
+                    for (int k = 0; k < 3; k++) { sn.Et[k] = plane(R); sn.Bt[k] = plane(R); }
                 return sn;
             };
             std::vector<Snap> ck, tp;
-            for (int k = 0; k < nck; k++) ck.push_back(snap(true));
-            for (int k = 0; k < K; k++) tp.push_back(snap(false));
+            for (int k = 0; k < nck; k++) ck.push_back(snap(true, false));
+            for (int k = 0; k < K; k++) tp.push_back(snap(false, c.dims == 2));
             if (s) { s->ckpt.push_back(ck); s->tape.push_back(tp); }
         }
         if (D) {
@@ -635,10 +645,10 @@ int enqueue_resort(pic_state *s)
     if (s->no_resort) return PIC_OK;
     LaunchCtx c = ctx(s);
     if (s->sched == PIC_SCHED_BATCHED) {
-        if (launch_resort(c, s->cwork, s->ncwork, 0, s->n_inst)) return fail(PIC_EHIP, "resort launch");
+        if (launch_resort(c, s->cwork, s->ncwork, 0, s->n_inst, 1)) return fail(PIC_EHIP, "resort launch");
     } else {
         for (int i = 0; i < s->n_inst; i++)
-            if (launch_resort(c, s->cwork + s->crange[i].off, s->crange[i].n, i, 1))
+            if (launch_resort(c, s->cwork + s->crange[i].off, s->crange[i].n, i, 1, i == s->n_inst - 1))
                 return fail(PIC_EHIP, "resort launch");
     }
     return PIC_OK;
@@ -860,7 +870,7 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
         // allow the dynamic LDS size on every particle kernel instantiation
         (void)maxsm;
     }
-    for (int i = 0; i < n_inst; i++) s->desc[i].trace = s->trace;
+    for (int i = 0; i < n_inst; i++) { s->desc[i].trace = s->trace; s->desc[i].any_resort = s->any_resort; }
     if (cfgs[0].adjoint_steps > 0) {
         s->adj_steps = cfgs[0].adjoint_steps;
         s->adj_k = cfgs[0].adjoint_ckpt;
@@ -885,9 +895,32 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
                 }
                 d.pidx = sn.pidx;
                 d.tbox = sn.tbox;
+                if (s->dims == 2)
+                    for (int c = 0; c < 3; c++) { d.Et[c] = sn.Et[c]; d.Bt[c] = sn.Bt[c]; }
                 td[(size_t)k * n_inst + i] = d;
             }
+        // 2D: the recomputed step k runs on the live state but writes its seen
+        // fields into slot k and records E1, B2 and its starting particles there
+        std::vector<InstDesc> rd((size_t)s->adj_k * n_inst);
+        for (int k = 0; k < s->adj_k && s->dims == 2; k++)
+            for (int i = 0; i < n_inst; i++) {
+                InstDesc d = s->desc[i];
+                const Snap &sn = s->tape[i][k];
+                for (int c = 0; c < 3; c++) {
+                    d.Et[c] = sn.Et[c];
+                    d.Bt[c] = sn.Bt[c];
+                    d.rE[c] = sn.E[c];
+                    d.rB[c] = sn.B[c];
+                    d.roff[c] = sn.poff[c];
+                    d.ru[c] = sn.pu[c];
+                }
+                d.rpidx = sn.pidx;
+                d.rtbox = sn.tbox;
+                rd[(size_t)k * n_inst + i] = d;
+            }
         if (hipMemcpyAsync(s->d_tape_desc, td.data(), td.size() * sizeof(InstDesc), hipMemcpyHostToDevice,
+                           s->stream) != hipSuccess ||
+            hipMemcpyAsync(s->d_rec_desc, rd.data(), rd.size() * sizeof(InstDesc), hipMemcpyHostToDevice,
                            s->stream) != hipSuccess ||
             hipStreamSynchronize(s->stream) != hipSuccess)
             return bail(fail(PIC_EHIP, "tape descriptor upload"));
@@ -1107,7 +1140,7 @@ extern "C" int pic_profile(pic_state *s, int nsteps, pic_timing_t *out)
         HIP_TRY(hipEventRecord(ev[3], s->stream));
         s->step++;
         const bool res = s->step % s->graph_k == 0;
-        if (res && launch_resort(c, s->cwork, s->ncwork, 0, s->n_inst)) return fail(PIC_EHIP, "resort");
+        if (res && launch_resort(c, s->cwork, s->ncwork, 0, s->n_inst, 1)) return fail(PIC_EHIP, "resort");
         HIP_TRY(hipEventRecord(ev[4], s->stream));
         HIP_TRY(hipEventSynchronize(ev[4]));
         float t[4];
@@ -1169,6 +1202,17 @@ int enqueue_segment(pic_state *s, int m)
     LaunchCtx live = ctx(s);
     int rc = PIC_OK;
     for (int slot = 0; slot < m && rc == PIC_OK; slot++) {
+        if (s->dims == 2) {
+            // the kernels write the tape themselves (record descriptors)
+            LaunchCtx rec = live;
+            rec.desc = s->d_rec_desc + (size_t)slot * s->n_inst;
+            rec.record = 1;
+            if (launch_yee(live, s->fwork, s->nfwork, s->ywork, s->nywork) ||
+                launch_seen(rec, s->fwork, s->nfwork, s->swork, s->nswork, 1) ||
+                launch_particles(rec, s->pwork, s->npwork, 0, s->block, s->wmax))
+                return fail(PIC_EHIP, "recompute");
+            continue;
+        }
         for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy_particles(s, i, s->tape[i][slot], true);
         if (rc) break;
         if (launch_yee(live, s->fwork, s->nfwork, s->ywork, s->nywork) ||

@@ -68,6 +68,7 @@ struct InstDesc {
     int *tbox;             // per tile: lo[3] (wrapped cell coords), ext[3]
     int *tcount;
     int *flags;            // FLAG_*
+    int *any_resort;       // one word shared by all instances: some instance set FLAG_RESORT
     double *diag;          // DG_*
     double *trace;         // trace_cap rows of 6 doubles
     // reverse mode (null unless gradient runs were planned)
@@ -80,6 +81,11 @@ struct InstDesc {
     double sj[9][17];      // taps of S_z^j (half-width j), j <= psi_deg
     double cdep_r[3], cy2d_r;        // Esirkepov factors in real units (float mode unscaled)
     double psi_e[9];                 // Psi_E coefficients (1, 0, ... without the correction)
+    // recording one tape slot (2D reverse sweep; null otherwise): the seen pass
+    // also writes E1, B2 here, the particle kernel the state it starts from
+    void *rE[3], *rB[3];
+    int *rpidx, *rtbox;
+    void *roff[3], *ru[3];
 };
 
 // launch helpers implemented in pic_kernels.hip
@@ -92,6 +98,8 @@ struct LaunchCtx {
     int prefetch = 0;             // 2D linear float particle kernel loads one particle ahead
     // seen-stencil half-widths and Psi degree shared by every instance (-1: they differ)
     int hz = -1, hx = -1, hzf = -1, psi_deg = -1;
+    const int *any_resort = nullptr;  // device word: a re-sort is pending
+    int record = 0;                   // 2D: descriptors carry tape-recording pointers somewhere
 };
 
 int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork);
@@ -105,7 +113,8 @@ size_t seen_smem_bytes(int fp32, int tz);
 int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid, int block,
                      const int wmax[3]);
 size_t particle_smem_bytes(int dims, int fp32, const int wmax[3]);
-int launch_resort(const LaunchCtx &c, const int2 *cwork, int ncwork, int n_inst_first, int n_inst);
+// clear_any: the last re-sort launch of a step clears the shared pending word
+int launch_resort(const LaunchCtx &c, const int2 *cwork, int ncwork, int n_inst_first, int n_inst, int clear_any);
 int launch_clear_j(const LaunchCtx &c, const int2 *fwork, int nwork);
 int launch_rho(const LaunchCtx &c, const int2 *cwork, int ncwork, const int2 *fwork, int nfwork,
                int to_rho0);

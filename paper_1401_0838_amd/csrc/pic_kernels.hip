@@ -201,7 +201,9 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 
 // P > 0 (2D only): LDS windows use the fixed row pitch P and plane size P*P.
 // PF: load the next particle's state while the current one is processed.
-template <int DIM, int L, class R, int P, bool PF>
+// TP: also write the state each particle starts from, and each tile's box,
+// to the tape slot named by the descriptor (reverse sweep recompute).
+template <int DIM, int L, class R, int P, bool PF, bool TP = false>
 __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                int nwork, int wmx, int wmy, int wmz)
 {
@@ -224,6 +226,9 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
             if (DIM == 2 && a == 1) { o[a] = 0; wn[a] = 1; continue; }
             o[a] = wrapi(lo[a] - JL, D.n[a]);
             wn[a] = ext[a] + L + 2;
+        }
+        if constexpr (TP) {
+            if (tid < 6) D.rtbox[tile * 6 + tid] = tid < 3 ? lo[tid] : ext[tid - 3];
         }
         const bool fits = wn[0] <= wmx && wn[1] <= wmy && wn[2] <= wmz;
         // plane stride and row pitch of the LDS windows
@@ -249,6 +254,7 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
         } else if (tid == 0) {
             atomicAdd(&D.flags[FLAG_SLOW], 1);
             atomicExch(&D.flags[FLAG_RESORT], 1);
+            atomicExch(D.any_resort, 1);
         }
         __syncthreads();
 
@@ -301,6 +307,14 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
             int lc[3];
             R off[3], u[3], offn[3];
             int dc[3];
+            if constexpr (TP) {
+                G<unsigned>((void *)D.rpidx)[p] = nidx;
+#pragma unroll
+                for (int a = 0; a < 3; a++) {
+                    if (!(DIM == 2 && a == 1)) G<R>(D.roff[a])[p] = noff[a];
+                    G<R>(D.ru[a])[p] = nu[a];
+                }
+            }
 #pragma unroll
             for (int a = 0; a < 3; a++) {
                 u[a] = nu[a];
@@ -372,17 +386,17 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
                 D.tbox[tile * 6 + 3 + a] = e;
                 if (e > D.tile[a] + PIC_TILE_SLACK) regrow = true;
             }
-            if (regrow) atomicExch(&D.flags[FLAG_RESORT], 1);
+            if (regrow) { atomicExch(&D.flags[FLAG_RESORT], 1); atomicExch(D.any_resort, 1); }
         }
         __syncthreads();
     }
 }
 
-template <int DIM, int L, class R, int P, bool PF = false>
+template <int DIM, int L, class R, int P, bool PF = false, bool TP = false>
 __global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                    int nwork, int wmx, int wmy, int wmz)
 {
-    particles_body<DIM, L, R, P, PF>(Dt, work, nwork, wmx, wmy, wmz);
+    particles_body<DIM, L, R, P, PF, TP>(Dt, work, nwork, wmx, wmy, wmz);
 }
 
 // same body compiled for four waves per SIMD (at most 128 VGPRs)
@@ -703,8 +717,11 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
         const int g = gz * nx + gx;
         dst[g] = acc;
         if (commit) {
-            G<R>(comp < 3 ? D.E[comp] : D.B[comp - 3])[g] = win[(zz + hz) * wx + xx + hx];
+            const R v = win[(zz + hz) * wx + xx + hx];
+            G<R>(comp < 3 ? D.E[comp] : D.B[comp - 3])[g] = v;
             if (comp < 3) G<JT>(D.J[comp])[g] = JT(0);
+            void *rec = comp < 3 ? D.rE[comp] : D.rB[comp - 3];
+            if (rec) G<R>(rec)[g] = v;
         }
     }
 }
@@ -718,17 +735,17 @@ template <int DIM> __device__ __forceinline__ int tile_of(const InstDesc &D, uns
     return (c[2] / D.tile[2] * D.nt[1] + c[1] / D.tile[1]) * D.nt[0] + c[0] / D.tile[0];
 }
 
-// the re-sort kernels walk RESORT_ITEMS consecutive work items per block so
-// that their launches (made every few steps, mostly finding nothing to do)
-// stay small
-#define RESORT_ITEMS 16
+// The re-sort kernels run every few steps and mostly find nothing to do: each
+// wave first reads the shared pending word and leaves if it is clear.  They
+// walk the particle chunks with a block-strided loop over a small grid.
+#define RESORT_GRID 512
 
 template <int DIM>
 __global__ void __launch_bounds__(256) k_resort_count(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                                      int nwork)
+                                                      int nwork, const int *__restrict__ any)
 {
-    const int it1 = min(nwork, (int)(blockIdx.x + 1) * RESORT_ITEMS);
-    for (int it = blockIdx.x * RESORT_ITEMS; it < it1; it++) {
+    if (!*any) return;
+    for (int it = blockIdx.x; it < nwork; it += gridDim.x) {
         const InstDesc &D = Dt[work[it].x];
         if (!D.flags[FLAG_RESORT]) continue;
         const long long p = (long long)work[it].y * PIC_PART_CHUNK + threadIdx.x;
@@ -740,8 +757,10 @@ __global__ void __launch_bounds__(256) k_resort_count(const InstDesc *__restrict
 }
 
 // one 1024-thread block per instance: exclusive scan of the tile counts
-__global__ void __launch_bounds__(1024) k_resort_scan(const InstDesc *__restrict__ Dt, int inst0)
+__global__ void __launch_bounds__(1024) k_resort_scan(const InstDesc *__restrict__ Dt, int inst0,
+                                                      const int *__restrict__ any)
 {
+    if (!*any) return;
     const InstDesc &D = Dt[inst0 + blockIdx.x];
     if (!D.flags[FLAG_RESORT]) return;
     __shared__ int part[1024];
@@ -769,49 +788,52 @@ __global__ void __launch_bounds__(1024) k_resort_scan(const InstDesc *__restrict
 
 template <int DIM, class R>
 __global__ void __launch_bounds__(256) k_resort_scatter(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                                        int nwork)
+                                                        int nwork, const int *__restrict__ any)
 {
-    const int it1 = min(nwork, (int)(blockIdx.x + 1) * RESORT_ITEMS);
-    for (int it = blockIdx.x * RESORT_ITEMS; it < it1; it++) {
-    const InstDesc &D = Dt[work[it].x];
-    if (!D.flags[FLAG_RESORT]) continue;
-    const long long p = (long long)work[it].y * PIC_PART_CHUNK + threadIdx.x;
-    if (p >= D.np) continue;
-    const int q = D.tstart[D.stile[p]] + D.srank[p];
-    D.sidx[q] = D.pidx[p];
-    D.spid[q] = D.ppid[p];
+    if (!*any) return;
+    for (int it = blockIdx.x; it < nwork; it += gridDim.x) {
+        const InstDesc &D = Dt[work[it].x];
+        if (!D.flags[FLAG_RESORT]) continue;
+        const long long p = (long long)work[it].y * PIC_PART_CHUNK + threadIdx.x;
+        if (p >= D.np) continue;
+        const int q = D.tstart[D.stile[p]] + D.srank[p];
+        D.sidx[q] = D.pidx[p];
+        D.spid[q] = D.ppid[p];
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        if (!(DIM == 2 && a == 1)) ((R *)D.soff[a])[q] = ((const R *)D.poff[a])[p];
-        ((R *)D.su[a])[q] = ((const R *)D.pu[a])[p];
-    }
+        for (int a = 0; a < 3; a++) {
+            if (!(DIM == 2 && a == 1)) ((R *)D.soff[a])[q] = ((const R *)D.poff[a])[p];
+            ((R *)D.su[a])[q] = ((const R *)D.pu[a])[p];
+        }
     }
 }
 
 template <int DIM, class R>
 __global__ void __launch_bounds__(256) k_resort_copy(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                                     int nwork)
+                                                     int nwork, const int *__restrict__ any)
 {
-    const int it1 = min(nwork, (int)(blockIdx.x + 1) * RESORT_ITEMS);
-    for (int it = blockIdx.x * RESORT_ITEMS; it < it1; it++) {
-    const InstDesc &D = Dt[work[it].x];
-    if (!D.flags[FLAG_RESORT]) continue;
-    const long long p = (long long)work[it].y * PIC_PART_CHUNK + threadIdx.x;
-    if (p >= D.np) continue;
-    D.pidx[p] = D.sidx[p];
-    D.ppid[p] = D.spid[p];
+    if (!*any) return;
+    for (int it = blockIdx.x; it < nwork; it += gridDim.x) {
+        const InstDesc &D = Dt[work[it].x];
+        if (!D.flags[FLAG_RESORT]) continue;
+        const long long p = (long long)work[it].y * PIC_PART_CHUNK + threadIdx.x;
+        if (p >= D.np) continue;
+        D.pidx[p] = D.sidx[p];
+        D.ppid[p] = D.spid[p];
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        if (!(DIM == 2 && a == 1)) ((R *)D.poff[a])[p] = ((const R *)D.soff[a])[p];
-        ((R *)D.pu[a])[p] = ((const R *)D.su[a])[p];
-    }
+        for (int a = 0; a < 3; a++) {
+            if (!(DIM == 2 && a == 1)) ((R *)D.poff[a])[p] = ((const R *)D.soff[a])[p];
+            ((R *)D.pu[a])[p] = ((const R *)D.su[a])[p];
+        }
     }
 }
 
 // per instance: reset every tile's bounding box to the tile itself and clear the flag
-__global__ void __launch_bounds__(256) k_resort_done(const InstDesc *__restrict__ Dt, int inst0, int force)
+__global__ void __launch_bounds__(256) k_resort_done(const InstDesc *__restrict__ Dt, int inst0, int force,
+                                                     int *__restrict__ any, int clear_any)
 {
     const InstDesc &D = Dt[inst0 + blockIdx.x];
+    // no block of this kernel reads the shared word, so block 0 may clear it
+    if (clear_any && blockIdx.x == 0 && threadIdx.x == 0) *any = 0;
     if (!force && !D.flags[FLAG_RESORT]) return;
     for (int t = threadIdx.x; t < D.ntiles; t += blockDim.x) {
         const int tx = t % D.nt[0], r = t / D.nt[0];
@@ -1087,8 +1109,19 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
     dim3 g(grid > 0 ? grid : nwork), b(block);
 #define PK(D_, L_, P_) k_particles<D_, L_, R, P_><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2])
 #define PK24(K_, PF_) K_<2, 1, float, 24, PF_><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2])
+#define PKR(L_, P_) k_particles<2, L_, R, P_, false, true><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2])
     DISPATCH_R(c.fp32, {
-        if (c.dims == 2 && c.order == 1) {
+        if (c.record && c.dims == 2) {
+            // recording a tape slot (2D reverse sweep)
+            if (c.order == 1) {
+                if (wm[0] == 24 && wm[2] == 24) PKR(1, 24);
+                else if (wm[0] == 32 && wm[2] == 32) PKR(1, 32);
+                else PKR(1, 0);
+            } else {
+                if (wm[0] == 32 && wm[2] == 32) PKR(3, 32);
+                else PKR(3, 0);
+            }
+        } else if (c.dims == 2 && c.order == 1) {
             if (wm[0] == 24 && wm[2] == 24) {
                 if (c.fp32 && c.waves4 && c.prefetch) PK24(k_particles_w4, true);
                 else if (c.fp32 && c.waves4) PK24(k_particles_w4, false);
@@ -1104,26 +1137,29 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
     });
 #undef PK
 #undef PK24
+#undef PKR
     return hip_ok(hipGetLastError());
 }
 
-int launch_resort(const LaunchCtx &c, const int2 *cwork, int ncwork, int inst0, int n_inst)
+int launch_resort(const LaunchCtx &c, const int2 *cwork, int ncwork, int inst0, int n_inst, int clear_any)
 {
     if (ncwork <= 0) return 0;
-    dim3 g((ncwork + RESORT_ITEMS - 1) / RESORT_ITEMS), b(PIC_PART_CHUNK);
-    if (c.dims == 2) k_resort_count<2><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork);
-    else k_resort_count<3><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork);
-    k_resort_scan<<<dim3(n_inst), dim3(1024), 0, c.stream>>>(c.desc, inst0);
+    const int *any = c.any_resort;
+    int *anyw = const_cast<int *>(any);
+    dim3 g(ncwork < RESORT_GRID ? ncwork : RESORT_GRID), b(PIC_PART_CHUNK);
+    if (c.dims == 2) k_resort_count<2><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork, any);
+    else k_resort_count<3><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork, any);
+    k_resort_scan<<<dim3(n_inst), dim3(1024), 0, c.stream>>>(c.desc, inst0, any);
     DISPATCH_R(c.fp32, {
         if (c.dims == 2) {
-            k_resort_scatter<2, R><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork);
-            k_resort_copy<2, R><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork);
+            k_resort_scatter<2, R><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork, any);
+            k_resort_copy<2, R><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork, any);
         } else {
-            k_resort_scatter<3, R><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork);
-            k_resort_copy<3, R><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork);
+            k_resort_scatter<3, R><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork, any);
+            k_resort_copy<3, R><<<g, b, 0, c.stream>>>(c.desc, cwork, ncwork, any);
         }
     });
-    k_resort_done<<<dim3(n_inst), dim3(256), 0, c.stream>>>(c.desc, inst0, 0);
+    k_resort_done<<<dim3(n_inst), dim3(256), 0, c.stream>>>(c.desc, inst0, 0, anyw, clear_any);
     return hip_ok(hipGetLastError());
 }
 
@@ -1181,6 +1217,6 @@ int launch_trace_rows(const LaunchCtx &c, const int2 *fwork, int nfwork, int *po
 
 int launch_fill_bbox(const LaunchCtx &c, int inst0, int n_inst)
 {
-    k_resort_done<<<dim3(n_inst), dim3(256), 0, c.stream>>>(c.desc, inst0, 1);
+    k_resort_done<<<dim3(n_inst), dim3(256), 0, c.stream>>>(c.desc, inst0, 1, const_cast<int *>(c.any_resort), 0);
     return hip_ok(hipGetLastError());
 }
