@@ -170,7 +170,8 @@ int pic_set_schedule(pic_state *st, int sched, int use_graph);
 /* Tuning knobs (used by the autotuner); every one keeps results unchanged:
  *   "yee_tile_z"     rows of the 2D Yee tile: 4, 8 or 16 (16 is float only)
  *   "seen_tile_z"    rows of the 2D seen-field tile: 8, 16 or 32
- *   "resort_every"   steps between tile re-sort checks (and per captured graph)
+ *   "resort_every"   steps between tile re-sort checks (and per captured graph);
+ *                    default 16
  *   "particle_block" threads per particle workgroup: 256 or 512
  *   "particle_waves4" 1: 2D linear float particle kernel built for four waves
  *                    per SIMD (register cap 128)

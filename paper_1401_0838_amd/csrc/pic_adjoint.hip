@@ -631,12 +631,10 @@ __global__ void __launch_bounds__(256) k_zero_lseen(const InstDesc *__restrict__
 // z pass), HX and DEG >= 0 are compile-time widths; -1 reads the descriptor.
 #define ADJ_TX 64
 template <class R, int TZ, bool GRAD, int HZ, int HX, int DEG>
-__global__ void __launch_bounds__(256) k_adj_seen_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                                     int comp0)
+__device__ __forceinline__ void adj_seen_body(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int comp)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
-    const int comp = comp0 + blockIdx.y;
     const InstDesc &D = Dt[inst];
     const int nx = D.n[0], nz = D.n[2];
     const int ntx = (nx + ADJ_TX - 1) / ADJ_TX;
@@ -747,6 +745,15 @@ __global__ void __launch_bounds__(256) k_adj_seen_2d(const InstDesc *__restrict_
             if (v != 0.0) unsafeAtomicAdd(&D.grad[j], v);
         }
     }
+}
+
+// blockIdx.y = component: x and y take the gradient path (z filter half-width
+// HZE, Psi degree DEG), the others the combined stencil (half-width HZB).
+template <class R, int TZ, int HZE, int HX, int DEG, int HZB>
+__global__ void __launch_bounds__(256) k_adj_seen_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+{
+    if (blockIdx.y < 2) adj_seen_body<R, TZ, true, HZE, HX, DEG>(Dt, work, blockIdx.y);
+    else adj_seen_body<R, TZ, false, HZB, HX, 0>(Dt, work, blockIdx.y);
 }
 
 // Fused transposed Yee update (2D): with h = dt/2 and Cb = Cf^T,
@@ -897,15 +904,13 @@ int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fw
         if (live.dims == 2) {
             // fused LDS kernels on 64 x 8 tiles (the awork list)
             const size_t sm = adj_seen_smem_bytes(live.fp32);
-            const dim3 g2a(nawork, 2), g4a(nawork, 4);
-            if (live.hz == 8 && live.hx == 4 && live.psi_deg == 4 && live.hzf == 4) {
+            const dim3 g6a(nawork, 6);
+            // the tape descriptors share every adjoint plane with the live ones
+            if (live.hz == 8 && live.hx == 4 && live.psi_deg == 4 && live.hzf == 4)
                 // correction of degree 4 with four filter passes: z filter 4, combined 8
-                k_adj_seen_2d<R, PIC_ADJ_TZ, true, 4, 4, 4><<<g2a, bf, sm, st>>>(tape.desc, awork, 0);
-                k_adj_seen_2d<R, PIC_ADJ_TZ, false, 8, 4, 0><<<g4a, bf, sm, st>>>(live.desc, awork, 2);
-            } else {
-                k_adj_seen_2d<R, PIC_ADJ_TZ, true, -1, -1, -1><<<g2a, bf, sm, st>>>(tape.desc, awork, 0);
-                k_adj_seen_2d<R, PIC_ADJ_TZ, false, -1, -1, 0><<<g4a, bf, sm, st>>>(live.desc, awork, 2);
-            }
+                k_adj_seen_2d<R, PIC_ADJ_TZ, 4, 4, 4, 8><<<g6a, bf, sm, st>>>(tape.desc, awork);
+            else
+                k_adj_seen_2d<R, PIC_ADJ_TZ, -1, -1, -1, -1><<<g6a, bf, sm, st>>>(tape.desc, awork);
             k_adj_yee_2d<R, PIC_ADJ_TZ><<<dim3(nawork), bf, 0, st>>>(live.desc, awork);
         } else {
             // lambda_E += M_E lambda_Et, lambda_B += M_B lambda_Bt

@@ -185,7 +185,7 @@ struct pic_state {
     int wmax[3] = {1, 1, 1};
     int block = 256;
     int sched = PIC_SCHED_BATCHED, use_graph = 1;
-    int graph_k = 8;                 // steps per captured graph (and re-sort period)
+    int graph_k = 16;                // steps per captured graph (and re-sort period)
     int yee_tz = 8, seen_tz = 16;    // 2D field-kernel tile heights (tunable)
     int waves4 = 0;                  // particle kernel capped at four waves per SIMD (tunable)
     int prefetch = 0;                // particle kernel loads one particle ahead (tunable)
