@@ -177,9 +177,6 @@ int pic_set_schedule(pic_state *st, int sched, int use_graph);
  *                    per SIMD (register cap 128)
  *   "particle_prefetch" 1: 2D linear float particle kernel loads the next
  *                    particle's state while pushing the current one
- *   "particle_spread" 1: 2D linear float particle kernel assigns a tile's
- *                    particles to lanes in transposed order (lanes of a wave
- *                    deposit into distinct cells)
  * Returns PIC_EINVAL for an unknown name or value.  Drops captured graphs. */
 int pic_set_option(pic_state *st, const char *name, int value);
 int pic_get_option(pic_state *st, const char *name, int *value);

@@ -389,14 +389,7 @@ __global__ void __launch_bounds__(256) k_adj_particles(const InstDesc *__restric
                                    G<R>((const void *)D.poff[2])};
         const gp<R> plu[3] = {G<R>(D.lu[0]), G<R>(D.lu[1]), G<R>(D.lu[2])};
         const gp<R> plo[3] = {G<R>(D.loff[0]), G<R>(D.loff[1]), G<R>(D.loff[2])};
-        // Particles of a tile are sorted by cell, so consecutive lanes would add
-        // into the same LDS cells and the float atomics serialise.  Lane order is
-        // transposed instead: slot i handles particle (i % 64) * m + i / 64, so
-        // the 64 lanes of a wave touch particles m apart (distinct cells).
-        const int np_t = p1 - p0, m = (np_t + 63) / 64;
-        for (int i = tid; i < 64 * m; i += bs) {
-            const int p = p0 + (i & 63) * m + (i >> 6);
-            if (p >= p1) continue;
+        for (int p = p0 + tid; p < p1; p += bs) {
             int c[3];
             unpack_cell<DIM>(pidx[p], c);
             int lc[3];

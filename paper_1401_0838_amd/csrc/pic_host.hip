@@ -189,7 +189,6 @@ struct pic_state {
     int yee_tz = 8, seen_tz = 16;    // 2D field-kernel tile heights (tunable)
     int waves4 = 0;                  // particle kernel capped at four waves per SIMD (tunable)
     int prefetch = 0;                // particle kernel loads one particle ahead (tunable)
-    int spread = 0;                  // particle kernel lanes in transposed order (tunable)
     hipGraphExec_t gexec_k = nullptr, gexec_1 = nullptr;
     long long step = 0;
     int *trace_pos = nullptr;
@@ -221,7 +220,6 @@ LaunchCtx ctx(const pic_state *s)
     c.seen_tz = s->seen_tz;
     c.waves4 = s->waves4;
     c.prefetch = s->prefetch;
-    c.spread = s->spread;
     c.any_resort = s->any_resort;
     if (!s->desc.empty()) {
         const InstDesc &d0 = s->desc[0];
@@ -974,9 +972,6 @@ extern "C" int pic_set_option(pic_state *s, const char *name, int value)
     } else if (n == "particle_prefetch") {
         if (value != 0 && value != 1) return fail(PIC_EINVAL, "particle_prefetch must be 0 or 1");
         s->prefetch = value;
-    } else if (n == "particle_spread") {
-        if (value != 0 && value != 1) return fail(PIC_EINVAL, "particle_spread must be 0 or 1");
-        s->spread = value;
     } else {
         return fail(PIC_EINVAL, "unknown option " + n);
     }
@@ -994,7 +989,6 @@ extern "C" int pic_get_option(pic_state *s, const char *name, int *value)
     else if (n == "particle_block") *value = s->block;
     else if (n == "particle_waves4") *value = s->waves4;
     else if (n == "particle_prefetch") *value = s->prefetch;
-    else if (n == "particle_spread") *value = s->spread;
     else return fail(PIC_EINVAL, "unknown option " + n);
     return PIC_OK;
 }

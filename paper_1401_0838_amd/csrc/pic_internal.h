@@ -96,7 +96,6 @@ struct LaunchCtx {
     int yee_tz = 8, seen_tz = 16; // 2D field-kernel tile heights (x width 64)
     int waves4 = 0;               // 2D linear float particle kernel capped at 128 VGPRs
     int prefetch = 0;             // 2D linear float particle kernel loads one particle ahead
-    int spread = 0;               // 2D linear float particle kernel takes lanes in transposed order
     // seen-stencil half-widths and Psi degree shared by every instance (-1: they differ)
     int hz = -1, hx = -1, hzf = -1, psi_deg = -1;
     const int *any_resort = nullptr;  // device word: a re-sort is pending

@@ -203,7 +203,7 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 // PF: load the next particle's state while the current one is processed.
 // TP: also write the state each particle starts from, and each tile's box,
 // to the tape slot named by the descriptor (reverse sweep recompute).
-template <int DIM, int L, class R, int P, bool PF, bool TP = false, bool SP = false>
+template <int DIM, int L, class R, int P, bool PF, bool TP = false>
 __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                int nwork, int wmx, int wmy, int wmz)
 {
@@ -293,13 +293,7 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
                 nu[a] = pu[a][q];
             }
         }
-        // SP: lanes take particles in transposed order (slot i -> (i % 64) * m + i / 64)
-        // so that the lanes of a wave deposit into distinct cells
-        const int msp = SP ? (p1 - p0 + 63) / 64 : 0;
-        const int pend = SP ? p0 + 64 * msp : p1;
-        for (int pi = p0 + tid; pi < pend; pi += bs) {
-            const int p = SP ? p0 + ((pi - p0) & 63) * msp + ((pi - p0) >> 6) : pi;
-            if (SP && p >= p1) continue;
+        for (int p = p0 + tid; p < p1; p += bs) {
             if (!PF) {
                 nidx = pidx[p];
 #pragma unroll
@@ -330,7 +324,7 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
                 lc[a] = rel + JL;
                 off[a] = noff[a];
             }
-            if (PF && !SP && p + bs < p1) {
+            if (PF && p + bs < p1) {
                 const int q = p + bs;
                 nidx = pidx[q];
 #pragma unroll
@@ -398,11 +392,11 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
     }
 }
 
-template <int DIM, int L, class R, int P, bool PF = false, bool TP = false, bool SP = false>
+template <int DIM, int L, class R, int P, bool PF = false, bool TP = false>
 __global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                    int nwork, int wmx, int wmy, int wmz)
 {
-    particles_body<DIM, L, R, P, PF, TP, SP>(Dt, work, nwork, wmx, wmy, wmz);
+    particles_body<DIM, L, R, P, PF, TP>(Dt, work, nwork, wmx, wmy, wmz);
 }
 
 // same body compiled for four waves per SIMD (at most 128 VGPRs)
@@ -1129,9 +1123,7 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
             }
         } else if (c.dims == 2 && c.order == 1) {
             if (wm[0] == 24 && wm[2] == 24) {
-                if (c.fp32 && c.spread)
-                    k_particles<2, 1, float, 24, false, false, true><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2]);
-                else if (c.fp32 && c.waves4 && c.prefetch) PK24(k_particles_w4, true);
+                if (c.fp32 && c.waves4 && c.prefetch) PK24(k_particles_w4, true);
                 else if (c.fp32 && c.waves4) PK24(k_particles_w4, false);
                 else if (c.fp32 && c.prefetch) PK24(k_particles, true);
                 else PK(2, 1, 24);
