@@ -25,6 +25,9 @@ namespace {
 
 using namespace pic;
 
+// byte offset of the double accumulation planes after 9 planes of R
+__host__ __device__ inline size_t adj_lf_offset(size_t wc, size_t rsize) { return (9 * wc * rsize + 7) & ~(size_t)7; }
+
 // derivatives of the Shape weights with respect to the in-cell offset
 template <int L, class R> struct DShape;
 
@@ -50,21 +53,24 @@ template <class R> struct DShape<3, R> {
     }
 };
 
-__device__ __forceinline__ void fadd(float *p, float v) { atomicAdd(p, v); }
-__device__ __forceinline__ void fadd(double *p, double v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void gadd(float *p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void gadd(double *p, double v) { unsafeAtomicAdd(p, v); }
 
-// window of seen fields (read), adjoint current (read) and adjoint seen fields (accumulate)
+// window of seen fields (read), adjoint current (read) and adjoint seen fields
+// (accumulate).  The accumulation is in double whatever R is: LDS atomic adds
+// of doubles run at several times the rate of float ones on this chip.
 template <class R> struct AdjLds {
     const R *F;    // 6 planes
     const R *LJ;   // 3 planes
-    R *LF;         // 6 planes
+    double *LF;    // 6 planes
     int wx, wxy, wc;
     __device__ __forceinline__ int at(int x, int y, int z) const { return z * wxy + y * wx + x; }
     __device__ __forceinline__ R f(int c, int x, int y, int z) const { return F[c * wc + at(x, y, z)]; }
     __device__ __forceinline__ R lj(int c, int x, int y, int z) const { return LJ[c * wc + at(x, y, z)]; }
-    __device__ __forceinline__ void addf(int c, int x, int y, int z, R v) { fadd(&LF[c * wc + at(x, y, z)], v); }
+    __device__ __forceinline__ void addf(int c, int x, int y, int z, R v)
+    {
+        unsafeAtomicAdd(&LF[c * wc + at(x, y, z)], (double)v);
+    }
 };
 
 template <class R> struct AdjGlb {
@@ -356,7 +362,7 @@ __global__ void __launch_bounds__(256) k_adj_particles(const InstDesc *__restric
         const int wc = wn[0] * wn[1] * wn[2];
         R *sF = reinterpret_cast<R *>(smem);
         R *sLJ = sF + 6 * wcmax;
-        R *sLF = sLJ + 3 * wcmax;
+        double *sLF = reinterpret_cast<double *>(smem + adj_lf_offset(wcmax, sizeof(R)));
         const int nn[3] = {D.n[0], D.n[1], D.n[2]};
         if (fits) {
             const gp<const R> src[6] = {G<R>((const void *)D.Et[0]), G<R>((const void *)D.Et[1]),
@@ -367,7 +373,7 @@ __global__ void __launch_bounds__(256) k_adj_particles(const InstDesc *__restric
             auto addr = [&](int c) { return window_cell(c, wn, o, nn); };
             stage<2, 6, R, R>(sF, wc, src, wc, addr, IdentityIx{}, PlainCv{});
             stage<2, 3, R, R>(sLJ, wc, lsrc, wc, addr, IdentityIx{}, PlainCv{});
-            for (int c = tid; c < 6 * wc; c += bs) sLF[c] = R(0);
+            for (int c = tid; c < 6 * wc; c += bs) sLF[c] = 0.0;
         }
         __syncthreads();
         const R dtd[3] = {(R)D.dtd[0], (R)D.dtd[1], (R)D.dtd[2]};
@@ -421,8 +427,8 @@ __global__ void __launch_bounds__(256) k_adj_particles(const InstDesc *__restric
                 const int g = window_cell(c, wn, o, nn);
 #pragma unroll
                 for (int k = 0; k < 6; k++) {
-                    const R v = sLF[k * wc + c];
-                    if (v != R(0)) gatomic_add(dst[k] + g, v);
+                    const double v = sLF[k * wc + c];
+                    if (v != 0.0) gatomic_add(dst[k] + g, (R)v);
                 }
             }
         }
@@ -856,7 +862,7 @@ inline int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : -1; }
 size_t adjoint_smem_bytes(int dims, int fp32, const int wmax[3])
 {
     const size_t wc = (size_t)wmax[0] * (dims == 3 ? wmax[1] : 1) * wmax[2];
-    return wc * 15 * (fp32 ? 4 : 8);
+    return adj_lf_offset(wc, fp32 ? 4 : 8) + 6 * wc * sizeof(double);
 }
 
 int launch_adj_seed(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *cwork, int ncwork)
