@@ -194,9 +194,16 @@ def main():
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D cubic case")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling HBM counters)")
+    ap.add_argument("--only", choices=("batched", "adjoint", "3d"),
+                    help="run one secondary block alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.only:
+        blk = {"batched": lambda: batched_block(max(20, args.steps // 4), 5), "adjoint": adjoint_block,
+               "3d": lambda: beam3d_block(20, 3)}[args.only]()
+        print(json.dumps({args.only: blk}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
