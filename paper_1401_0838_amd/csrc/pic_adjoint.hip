@@ -672,31 +672,51 @@ __device__ __forceinline__ void adj_seen_body(const InstDesc *__restrict__ Dt, c
     } else {
         for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)D.tx[i];
     }
-    const gp<const R> src[1] = {G<R>((const void *)(comp < 3 ? D.lEt[comp] : D.lBt[comp - 3]))};
-    const float iwx = 1.0f / (float)wx;
-    stage<8, 1, R, R>(win, 0, src, wx * wz, [&](int c) {
-        const int zz = (int)(((float)c + 0.5f) * iwx);
-        const int xx = c - zz * wx;
-        return wrap_near(z0 - deg - hz + zz, nz) * nx + wrap_near(x0 - hx + xx, nx);
-    }, IdentityIx{}, PlainCv{});
-    __syncthreads();
-    for (int c = threadIdx.x; c < wx * rows_mid; c += blockDim.x) {
-        const int zz = (int)(((float)c + 0.5f) * iwx);
-        const int xx = c - zz * wx;
-        const R *w = win + zz * wx + xx;
-        R acc = R(0);
-        if constexpr (HZ >= 0) {
+    const gp<const R> src = G<R>((const void *)(comp < 3 ? D.lEt[comp] : D.lBt[comp - 3]));
+    // waves own rows, lanes own columns: a = lane, b = 64 + lane (right halo, lane < 2 hx)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const bool hasb = lane < 2 * hx;
+    const int gxa = wrap_near(x0 - hx + lane, nx);
+    const int gxb = hasb ? wrap_near(x0 - hx + ADJ_TX + lane, nx) : gxa;
+    constexpr int U = 4;
+    for (int r0 = wave; r0 < wz; r0 += U * nwave) {
+        R va[U], vb[U];
 #pragma unroll
-            for (int k = 0; k < NTZ; k++) acc += rz[k] * w[k * wx];
-        } else {
-            for (int k = 0; k <= 2 * hz; k++) acc += tz[k] * w[k * wx];
+        for (int u = 0; u < U; u++) {
+            const int row = min(r0 + u * nwave, wz - 1);
+            const int base = wrap_near(z0 - deg - hz + row, nz) * nx;
+            va[u] = src[base + gxa];
+            vb[u] = src[base + gxb];
         }
-        mid[c] = acc;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int row = r0 + u * nwave;
+            if (row < wz) {
+                win[row * wx + lane] = va[u];
+                if (hasb) win[row * wx + ADJ_TX + lane] = vb[u];
+            }
+        }
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < ADJ_TX * rows_mid; c += blockDim.x) {
-        const int zz = c / ADJ_TX, xx = c - zz * ADJ_TX;
-        const R *m = mid + zz * wx + xx;
+    for (int zz = wave; zz < rows_mid; zz += nwave) {
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            if (half == 1 && !hasb) break;
+            const int col = half ? ADJ_TX + lane : lane;
+            const R *w = win + zz * wx + col;
+            R acc = R(0);
+            if constexpr (HZ >= 0) {
+#pragma unroll
+                for (int k = 0; k < NTZ; k++) acc += rz[k] * w[k * wx];
+            } else {
+                for (int k = 0; k <= 2 * hz; k++) acc += tz[k] * w[k * wx];
+            }
+            mid[zz * wx + col] = acc;
+        }
+    }
+    __syncthreads();
+    for (int zz = wave; zz < rows_mid; zz += nwave) {
+        const R *m = mid + zz * wx + lane;
         R acc = R(0);
         if constexpr (HX >= 0) {
 #pragma unroll
@@ -704,7 +724,7 @@ __device__ __forceinline__ void adj_seen_body(const InstDesc *__restrict__ Dt, c
         } else {
             for (int k = 0; k <= 2 * hx; k++) acc += tx[k] * m[k];
         }
-        lam[c] = acc;
+        lam[zz * ADJ_TX + lane] = acc;
     }
     __syncthreads();
     const gp<const R> own = G<R>((const void *)(comp < 3 ? D.lE[comp] : D.lB[comp - 3]));
@@ -713,8 +733,8 @@ __device__ __forceinline__ void adj_seen_body(const InstDesc *__restrict__ Dt, c
     R gpart[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; j++) gpart[j] = R(0);
-    for (int c = threadIdx.x; c < ADJ_TX * TZ; c += blockDim.x) {
-        const int zz = c / ADJ_TX, xx = c - zz * ADJ_TX;
+    for (int zz = wave; zz < TZ; zz += nwave) {
+        const int xx = lane;
         const int gx = x0 + xx, gz = z0 + zz;
         if (gx >= nx || gz >= nz) continue;
         const int g = gz * nx + gx;
@@ -769,6 +789,7 @@ template <class R, int TZ>
 __global__ void __launch_bounds__(256) k_adj_yee_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
 {
     constexpr int TX = PIC_YEE_TX;
+    static_assert(TX == 64, "one lane per column");
     constexpr int WX = TX + 3, WZ = TZ + 3, WN = WX * WZ;
     __shared__ R sE[3][WN], sB[3][WN];
     const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
@@ -776,66 +797,81 @@ __global__ void __launch_bounds__(256) k_adj_yee_2d(const InstDesc *__restrict__
     const int nx = D.n[0], nz = D.n[2];
     const int ntx = (nx + TX - 1) / TX;
     const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
-    const int tid = threadIdx.x, bs = blockDim.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
     // inputs: lambda_E, lambda_B as left in T1 by the reverse seen kernels
     const gp<const R> in[6] = {G<R>((const void *)D.T1[0]), G<R>((const void *)D.T1[1]), G<R>((const void *)D.T1[2]),
                                G<R>((const void *)D.T1[3]), G<R>((const void *)D.T1[4]), G<R>((const void *)D.T1[5])};
     gp<R> lE[3] = {G<R>(D.lE[0]), G<R>(D.lE[1]), G<R>(D.lE[2])};
     gp<R> lB[3] = {G<R>(D.lB[0]), G<R>(D.lB[1]), G<R>(D.lB[2])};
     gp<R> lJ[3] = {G<R>(D.lJ[0]), G<R>(D.lJ[1]), G<R>(D.lJ[2])};
-    constexpr int U = (WN + 255) / 256;
-    for (int c0 = tid; c0 < WN; c0 += U * bs) {
-        int g[U];
+    const bool hasb = lane < WX - TX;
+    const int gxa = wrap_near(x0 - 2 + lane, nx);
+    const int gxb = hasb ? wrap_near(x0 - 2 + TX + lane, nx) : gxa;
+    constexpr int RW = (WZ + 3) / 4;
+    for (int r0 = wave; r0 < WZ; r0 += RW * nwave) {
+        R v[RW][2][6];
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int c = c0 + u * bs, lz = c / WX, lx = c - lz * WX;
-            g[u] = c < WN ? wrap_near(z0 - 2 + lz, nz) * nx + wrap_near(x0 - 2 + lx, nx) : 0;
+        for (int u = 0; u < RW; u++) {
+            const int row = min(r0 + u * nwave, WZ - 1);
+            const int base = wrap_near(z0 - 2 + row, nz) * nx;
+#pragma unroll
+            for (int hh = 0; hh < 2; hh++)
+#pragma unroll
+                for (int k = 0; k < 6; k++) v[u][hh][k] = in[k][base + (hh ? gxb : gxa)];
         }
-        R v[U][6];
 #pragma unroll
-        for (int u = 0; u < U; u++)
+        for (int u = 0; u < RW; u++) {
+            const int row = r0 + u * nwave;
+            if (row >= WZ) continue;
 #pragma unroll
-            for (int k = 0; k < 6; k++) v[u][k] = in[k][g[u]];
+            for (int hh = 0; hh < 2; hh++) {
+                if (hh == 1 && !hasb) continue;
+                const int c = row * WX + (hh ? TX : 0) + lane;
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int c = c0 + u * bs;
-            if (c < WN) {
-#pragma unroll
-                for (int k = 0; k < 3; k++) { sE[k][c] = v[u][k]; sB[k][c] = v[u][3 + k]; }
+                for (int k = 0; k < 3; k++) { sE[k][c] = v[u][hh][k]; sB[k][c] = v[u][hh][3 + k]; }
             }
         }
     }
     __syncthreads();
     const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
-    // lE' on [-1, T]: backward differences of lB
-    for (int c = tid; c < (TZ + 2) * (TX + 2); c += bs) {
-        const int lz = c / (TX + 2) + 1, lx = c % (TX + 2) + 1;
-        const int e = lz * WX + lx, exm = e - 1, ezm = e - WX;
-        const R cx = -(sB[1][e] - sB[1][ezm]) * idz;
-        const R cy = (sB[0][e] - sB[0][ezm]) * idz - (sB[2][e] - sB[2][exm]) * idx;
-        const R cz = (sB[1][e] - sB[1][exm]) * idx;
-        sE[0][e] -= h * cx;
-        sE[1][e] -= h * cy;
-        sE[2][e] -= h * cz;
+    // lE' on local [1, T + 3) (cells -1 .. T): backward differences of lB
+    for (int lz = 1 + wave; lz < TZ + 3; lz += nwave) {
+#pragma unroll
+        for (int hh = 0; hh < 2; hh++) {
+            const int lx = hh ? TX + 1 + lane : 1 + lane;
+            if (lx >= TX + 3) break;
+            const int e = lz * WX + lx, exm = e - 1, ezm = e - WX;
+            const R cx = -(sB[1][e] - sB[1][ezm]) * idz;
+            const R cy = (sB[0][e] - sB[0][ezm]) * idz - (sB[2][e] - sB[2][exm]) * idx;
+            const R cz = (sB[1][e] - sB[1][exm]) * idx;
+            sE[0][e] -= h * cx;
+            sE[1][e] -= h * cy;
+            sE[2][e] -= h * cz;
+        }
     }
     __syncthreads();
-    // lB' on [-1, T): forward differences of lE'
-    for (int c = tid; c < (TZ + 1) * (TX + 1); c += bs) {
-        const int lz = c / (TX + 1) + 1, lx = c % (TX + 1) + 1;
-        const int e = lz * WX + lx, exp = e + 1, ezp = e + WX;
-        const R fx = -(sE[1][ezp] - sE[1][e]) * idz;
-        const R fy = (sE[0][ezp] - sE[0][e]) * idz - (sE[2][exp] - sE[2][e]) * idx;
-        const R fz = (sE[1][exp] - sE[1][e]) * idx;
-        sB[0][e] += dt * fx;
-        sB[1][e] += dt * fy;
-        sB[2][e] += dt * fz;
+    // lB' on local [1, T + 2) (cells -1 .. T - 1): forward differences of lE'
+    for (int lz = 1 + wave; lz < TZ + 2; lz += nwave) {
+#pragma unroll
+        for (int hh = 0; hh < 2; hh++) {
+            const int lx = hh ? TX + 1 + lane : 1 + lane;
+            if (lx >= TX + 2) break;
+            const int e = lz * WX + lx, exp = e + 1, ezp = e + WX;
+            const R fx = -(sE[1][ezp] - sE[1][e]) * idz;
+            const R fy = (sE[0][ezp] - sE[0][e]) * idz - (sE[2][exp] - sE[2][e]) * idx;
+            const R fz = (sE[1][exp] - sE[1][e]) * idx;
+            sB[0][e] += dt * fx;
+            sB[1][e] += dt * fy;
+            sB[2][e] += dt * fz;
+        }
     }
     __syncthreads();
-    for (int c = tid; c < TZ * TX; c += bs) {
-        const int lz = c / TX, lx = c - lz * TX;
-        const int gx = x0 + lx, gz = z0 + lz;
-        if (gx >= nx || gz >= nz) continue;
-        const int e = (lz + 2) * WX + lx + 2, exm = e - 1, ezm = e - WX;
+    const int gx = x0 + lane;
+    if (gx >= nx) return;
+    for (int lz = wave; lz < TZ; lz += nwave) {
+        const int gz = z0 + lz;
+        if (gz >= nz) break;
+        const int e = (lz + 2) * WX + lane + 2, exm = e - 1, ezm = e - WX;
         const R cx = -(sB[1][e] - sB[1][ezm]) * idz;
         const R cy = (sB[0][e] - sB[0][ezm]) * idz - (sB[2][e] - sB[2][exm]) * idx;
         const R cz = (sB[1][e] - sB[1][exm]) * idx;

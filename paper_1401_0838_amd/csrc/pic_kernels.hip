@@ -500,7 +500,9 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
 {
     typedef typename JOf<R>::T JT;
     constexpr int TX = YEE_TX;
-    // one window for all nine planes: cells [x0 - 1, x0 + TX + 2) x [z0 - 1, z0 + TZ + 2)
+    static_assert(TX == 64, "one lane per column");
+    // one window for all nine planes: cells [x0 - 1, x0 + TX + 2) x [z0 - 1, z0 + TZ + 2);
+    // waves own rows, lanes own columns (lane, and 64 + lane for the last three)
     constexpr int WX = TX + 3, WZ = TZ + 3, WN = WX * WZ;
     __shared__ R sE[3][WN], sB[3][WN], sJ[3][WN];
     const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
@@ -508,7 +510,7 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
     const int nx = D.n[0], nz = D.n[2];
     const int ntx = (nx + TX - 1) / TX;
     const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
-    const int tid = threadIdx.x, bs = blockDim.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
     const gp<const R> E[3] = {G<R>((const void *)D.E[0]), G<R>((const void *)D.E[1]), G<R>((const void *)D.E[2])};
     const gp<const R> B[3] = {G<R>((const void *)D.B[0]), G<R>((const void *)D.B[1]), G<R>((const void *)D.B[2])};
     const gp<const JT> J[3] = {G<JT>((const void *)D.J[0]), G<JT>((const void *)D.J[1]), G<JT>((const void *)D.J[2])};
@@ -516,64 +518,80 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
     // fields go to the scratch planes T1 (E then B); the seen pass commits them
     gp<R> O[6] = {G<R>(D.T1[0]), G<R>(D.T1[1]), G<R>(D.T1[2]), G<R>(D.T1[3]), G<R>(D.T1[4]), G<R>(D.T1[5])};
     const double jq = D.jq, jb[3] = {D.jbg[0], D.jbg[1], D.jbg[2]};
-    // staging: U window cells per thread, all 9 U loads issued before any store
-    constexpr int U = (WN + 255) / 256;
-    for (int c0 = tid; c0 < WN; c0 += U * bs) {
-        int g[U];
+    const bool hasb = lane < WX - TX;
+    const int gxa = wrap_near(x0 - 1 + lane, nx);
+    const int gxb = hasb ? wrap_near(x0 - 1 + TX + lane, nx) : gxa;
+    constexpr int RW = (WZ + 3) / 4;   // rows per wave with four waves
+    for (int r0 = wave; r0 < WZ; r0 += RW * nwave) {
+        R ve[RW][2][3], vb[RW][2][3];
+        JT vj[RW][2][3];
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int c = c0 + u * bs, lz = c / WX, lx = c - lz * WX;
-            g[u] = c < WN ? wrap_near(z0 - 1 + lz, nz) * nx + wrap_near(x0 - 1 + lx, nx) : 0;
+        for (int u = 0; u < RW; u++) {
+            const int row = min(r0 + u * nwave, WZ - 1);
+            const int base = wrap_near(z0 - 1 + row, nz) * nx;
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int g = base + (h ? gxb : gxa);
+#pragma unroll
+                for (int k = 0; k < 3; k++) { ve[u][h][k] = E[k][g]; vb[u][h][k] = B[k][g]; vj[u][h][k] = J[k][g]; }
+            }
         }
-        R ve[U][3], vb[U][3];
-        JT vj[U][3];
 #pragma unroll
-        for (int u = 0; u < U; u++)
+        for (int u = 0; u < RW; u++) {
+            const int row = r0 + u * nwave;
+            if (row >= WZ) continue;
 #pragma unroll
-            for (int k = 0; k < 3; k++) { ve[u][k] = E[k][g[u]]; vb[u][k] = B[k][g[u]]; vj[u][k] = J[k][g[u]]; }
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            const int c = c0 + u * bs;
-            if (c < WN) {
+            for (int h = 0; h < 2; h++) {
+                if (h == 1 && !hasb) continue;
+                const int c = row * WX + (h ? TX : 0) + lane;
 #pragma unroll
                 for (int k = 0; k < 3; k++) {
-                    sE[k][c] = ve[u][k];
-                    sB[k][c] = vb[u][k];
-                    sJ[k][c] = (R)(jreal(vj[u][k], jq) + jb[k]);
+                    sE[k][c] = ve[u][h][k];
+                    sB[k][c] = vb[u][h][k];
+                    sJ[k][c] = (R)(jreal(vj[u][h][k], jq) + jb[k]);
                 }
             }
         }
     }
     __syncthreads();
     const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
-    // B^{n-1/2} on [-1, T]: forward differences of E
-    for (int c = tid; c < (TZ + 2) * (TX + 2); c += bs) {
-        const int lz = c / (TX + 2), lx = c - lz * (TX + 2);
-        const int e = lz * WX + lx, ex = e + 1, ez = e + WX;
-        const R dzEy = (sE[1][ez] - sE[1][e]) * idz, dzEx = (sE[0][ez] - sE[0][e]) * idz;
-        const R dxEz = (sE[2][ex] - sE[2][e]) * idx, dxEy = (sE[1][ex] - sE[1][e]) * idx;
-        sB[0][e] -= h * (-dzEy);
-        sB[1][e] -= h * (dzEx - dxEz);
-        sB[2][e] -= h * dxEy;
+    // B^{n-1/2} on local rows and columns [0, T + 2): forward differences of E
+    for (int lz = wave; lz < TZ + 2; lz += nwave) {
+#pragma unroll
+        for (int hh = 0; hh < 2; hh++) {
+            const int lx = hh ? TX + lane : lane;
+            if (lx >= TX + 2) break;
+            const int e = lz * WX + lx, ex = e + 1, ez = e + WX;
+            const R dzEy = (sE[1][ez] - sE[1][e]) * idz, dzEx = (sE[0][ez] - sE[0][e]) * idz;
+            const R dxEz = (sE[2][ex] - sE[2][e]) * idx, dxEy = (sE[1][ex] - sE[1][e]) * idx;
+            sB[0][e] -= h * (-dzEy);
+            sB[1][e] -= h * (dzEx - dxEz);
+            sB[2][e] -= h * dxEy;
+        }
     }
     __syncthreads();
-    // E^n on [0, T]: backward differences of B^{n-1/2}
-    for (int c = tid; c < (TZ + 1) * (TX + 1); c += bs) {
-        const int lz = c / (TX + 1), lx = c - lz * (TX + 1);
-        const int e = (lz + 1) * WX + lx + 1, exm = e - 1, ezm = e - WX;
-        const R dzBy = (sB[1][e] - sB[1][ezm]) * idz, dzBx = (sB[0][e] - sB[0][ezm]) * idz;
-        const R dxBz = (sB[2][e] - sB[2][exm]) * idx, dxBy = (sB[1][e] - sB[1][exm]) * idx;
-        sE[0][e] += dt * (-dzBy - sJ[0][e]);
-        sE[1][e] += dt * (dzBx - dxBz - sJ[1][e]);
-        sE[2][e] += dt * (dxBy - sJ[2][e]);
+    // E^n on local [1, T + 2): backward differences of B^{n-1/2}
+    for (int lz = 1 + wave; lz < TZ + 2; lz += nwave) {
+#pragma unroll
+        for (int hh = 0; hh < 2; hh++) {
+            const int lx = hh ? TX + 1 + lane : 1 + lane;
+            if (lx >= TX + 2) break;
+            const int e = lz * WX + lx, exm = e - 1, ezm = e - WX;
+            const R dzBy = (sB[1][e] - sB[1][ezm]) * idz, dzBx = (sB[0][e] - sB[0][ezm]) * idz;
+            const R dxBz = (sB[2][e] - sB[2][exm]) * idx, dxBy = (sB[1][e] - sB[1][exm]) * idx;
+            sE[0][e] += dt * (-dzBy - sJ[0][e]);
+            sE[1][e] += dt * (dzBx - dxBz - sJ[1][e]);
+            sE[2][e] += dt * (dxBy - sJ[2][e]);
+        }
     }
     __syncthreads();
-    // B^n on [0, T) and the stores
-    for (int c = tid; c < TZ * TX; c += bs) {
-        const int lz = c / TX, lx = c - lz * TX;
-        const int gx = x0 + lx, gz = z0 + lz;
-        if (gx >= nx || gz >= nz) continue;
-        const int e = (lz + 1) * WX + lx + 1, ex = e + 1, ez = e + WX;
+    // B^n on the tile and the stores
+    const int gx = x0 + lane;
+    if (gx >= nx) return;
+    for (int lz = wave; lz < TZ; lz += nwave) {
+        const int gz = z0 + lz;
+        if (gz >= nz) break;
+        const int e = (lz + 1) * WX + lane + 1, ex = e + 1, ez = e + WX;
         const R dzEy = (sE[1][ez] - sE[1][e]) * idz, dzEx = (sE[0][ez] - sE[0][e]) * idz;
         const R dxEz = (sE[2][ex] - sE[2][e]) * idx, dxEy = (sE[1][ex] - sE[1][e]) * idx;
         const int g = gz * nx + gx;
@@ -637,19 +655,20 @@ __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ 
     dst[cell] = acc;
 }
 
-// 2D fields as seen by the particles in one kernel: a (SX x SZ) output tile of
+// 2D fields as seen by the particles in one kernel: a (64 x SZ) output tile of
 // one component is loaded with its stencil halo into LDS, the combined z
 // stencil (Psi o z filter) is applied into a second LDS tile, then the x
 // filter stencil writes the output.  blockIdx.y = component, work = (inst, tile).
-// HZ, HX >= 0 fix the stencil half-widths at compile time (taps in registers,
-// loops unrolled so every LDS read of an output is in flight at once); -1
-// reads them from the descriptor.
+// Waves own rows and lanes own columns (64 + halo), so addresses are affine in
+// the lane.  HZ, HX >= 0 fix the stencil half-widths at compile time (taps in
+// registers, loops unrolled); -1 reads them from the descriptor.
 #define SEEN_TX PIC_SEEN_TX
 template <class R, int SEEN_TZ, int HZ, int HX>
 __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                  int commit)
 {
     typedef typename JOf<R>::T JT;
+    static_assert(SEEN_TX == 64, "one lane per column");
     extern __shared__ __align__(16) unsigned char smem[];
     const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
     const int comp = blockIdx.y;
@@ -659,6 +678,7 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     const int x0 = (t % ntx) * SEEN_TX, z0 = (t / ntx) * SEEN_TZ;
     const int hz = HZ >= 0 ? HZ : D.hz, hx = HX >= 0 ? HX : D.hx;
     const int wx = SEEN_TX + 2 * hx, wz = SEEN_TZ + 2 * hz;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
     R *win = reinterpret_cast<R *>(smem);
     R *mid = win + wx * wz;
     R *tz = mid + wx * SEEN_TZ;
@@ -679,34 +699,56 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
         for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)D.tx[i];
     }
     const void *sp = commit ? D.T1[comp] : (comp < 3 ? D.E[comp] : D.B[comp - 3]);
-    const gp<const R> src[1] = {G<R>(sp)};
-    const float iwx = 1.0f / (float)wx;
-    stage<8, 1, R, R>(win, 0, src, wx * wz, [&](int c) {
-        const int zz = (int)(((float)c + 0.5f) * iwx);
-        const int xx = c - zz * wx;
-        return wrap_near(z0 - hz + zz, nz) * nx + wrap_near(x0 - hx + xx, nx);
-    }, IdentityIx{}, PlainCv{});
-    __syncthreads();
-    for (int c = threadIdx.x; c < wx * SEEN_TZ; c += blockDim.x) {
-        const int zz = (int)(((float)c + 0.5f) * iwx);
-        const int xx = c - zz * wx;
-        const R *w = win + zz * wx + xx;
-        R acc = R(0);
-        if constexpr (HZ >= 0) {
+    const gp<const R> src = G<R>(sp);
+    // staging: column a = lane, column b = 64 + lane for the right halo (lane < 2 hx)
+    const bool hasb = lane < 2 * hx;
+    const int gxa = wrap_near(x0 - hx + lane, nx);
+    const int gxb = hasb ? wrap_near(x0 - hx + SEEN_TX + lane, nx) : gxa;
+    constexpr int U = 4;
+    for (int r0 = wave; r0 < wz; r0 += U * nwave) {
+        R va[U], vb[U];
 #pragma unroll
-            for (int k = 0; k < NTZ; k++) acc += rz[k] * w[k * wx];
-        } else {
-            for (int k = 0; k <= 2 * hz; k++) acc += tz[k] * w[k * wx];
+        for (int u = 0; u < U; u++) {
+            const int row = min(r0 + u * nwave, wz - 1);
+            const int base = wrap_near(z0 - hz + row, nz) * nx;
+            va[u] = src[base + gxa];
+            vb[u] = src[base + gxb];
         }
-        mid[c] = acc;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int row = r0 + u * nwave;
+            if (row < wz) {
+                win[row * wx + lane] = va[u];
+                if (hasb) win[row * wx + SEEN_TX + lane] = vb[u];
+            }
+        }
+    }
+    __syncthreads();
+    // z pass on all wx columns
+    for (int zz = wave; zz < SEEN_TZ; zz += nwave) {
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            if (half == 1 && !hasb) break;
+            const int col = half ? SEEN_TX + lane : lane;
+            const R *w = win + zz * wx + col;
+            R acc = R(0);
+            if constexpr (HZ >= 0) {
+#pragma unroll
+                for (int k = 0; k < NTZ; k++) acc += rz[k] * w[k * wx];
+            } else {
+                for (int k = 0; k <= 2 * hz; k++) acc += tz[k] * w[k * wx];
+            }
+            mid[zz * wx + col] = acc;
+        }
     }
     __syncthreads();
     gp<R> dst = G<R>(comp < 3 ? D.Et[comp] : D.Bt[comp - 3]);
-    for (int c = threadIdx.x; c < SEEN_TX * SEEN_TZ; c += blockDim.x) {
-        const int zz = c / SEEN_TX, xx = c % SEEN_TX;
-        const int gx = x0 + xx, gz = z0 + zz;
-        if (gx >= nx || gz >= nz) continue;
-        const R *m = mid + zz * wx + xx;
+    const int gx = x0 + lane;
+    if (gx >= nx) return;
+    for (int zz = wave; zz < SEEN_TZ; zz += nwave) {
+        const int gz = z0 + zz;
+        if (gz >= nz) break;
+        const R *m = mid + zz * wx + lane;
         R acc = R(0);
         if constexpr (HX >= 0) {
 #pragma unroll
@@ -717,7 +759,7 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
         const int g = gz * nx + gx;
         dst[g] = acc;
         if (commit) {
-            const R v = win[(zz + hz) * wx + xx + hx];
+            const R v = win[(zz + hz) * wx + lane + hx];
             G<R>(comp < 3 ? D.E[comp] : D.B[comp - 3])[g] = v;
             if (comp < 3) G<JT>(D.J[comp])[g] = JT(0);
             void *rec = comp < 3 ? D.rE[comp] : D.rB[comp - 3];
