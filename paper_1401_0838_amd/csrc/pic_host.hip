@@ -935,7 +935,7 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
     }
     LaunchCtx c = ctx(s);
     if (launch_fill_bbox(c, 0, n_inst)) return bail(fail(PIC_EHIP, "bbox init"));
-    if (launch_rho(c, s->cwork, s->ncwork, s->fwork, s->nfwork, 1)) return bail(fail(PIC_EHIP, "rho0"));
+    if (launch_rho(c, s->pwork, s->npwork, s->fwork, s->nfwork, s->wmax, 1)) return bail(fail(PIC_EHIP, "rho0"));
     if (hipStreamSynchronize(s->stream) != hipSuccess) return bail(fail(PIC_EHIP, "init sync"));
     *out = s;
     return PIC_OK;
@@ -1049,8 +1049,8 @@ extern "C" int pic_fields(pic_state *s, int inst, int which, int comp, double *h
     if (dir != PIC_GET) return fail(PIC_EINVAL, "pic_fields: dir");
     if (is_rho) {
         LaunchCtx c = ctx(s);
-        const Range &cr = s->crange[inst], &fr = s->frange[inst];
-        if (launch_rho(c, s->cwork + cr.off, cr.n, s->fwork + fr.off, fr.n, 0)) return fail(PIC_EHIP, "rho");
+        const Range &pr = s->prange[inst], &fr = s->frange[inst];
+        if (launch_rho(c, s->pwork + pr.off, pr.n, s->fwork + fr.off, fr.n, s->wmax, 0)) return fail(PIC_EHIP, "rho");
         HIP_TRY(hipMemcpyAsync(host, D.rho, n * 8, hipMemcpyDeviceToHost, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
         return PIC_OK;
@@ -1071,8 +1071,8 @@ extern "C" int pic_diag(pic_state *s, int inst, pic_diag_t *out)
     if (!s || inst < 0 || inst >= s->n_inst || !out) return fail(PIC_EINVAL, "pic_diag");
     const InstDesc &D = s->desc[inst];
     LaunchCtx c = ctx(s);
-    const Range &cr = s->crange[inst], &fr = s->frange[inst];
-    if (launch_diag(c, s->fwork + fr.off, fr.n, s->cwork + cr.off, cr.n, inst, 1)) return fail(PIC_EHIP, "diag");
+    const Range &pr = s->prange[inst], &fr = s->frange[inst];
+    if (launch_diag(c, s->fwork + fr.off, fr.n, s->pwork + pr.off, pr.n, s->wmax)) return fail(PIC_EHIP, "diag");
     double dg[DG_COUNT];
     int fl[FLAG_COUNT];
     HIP_TRY(hipMemcpyAsync(dg, D.diag, sizeof dg, hipMemcpyDeviceToHost, s->stream));

@@ -945,84 +945,156 @@ __global__ void __launch_bounds__(256) k_energy(const InstDesc *__restrict__ Dt,
 
 // charge density (order-L shape on integer nodes) of the current particles,
 // plus kinetic energy and non-finite momenta
-template <int DIM, int L, class R>
-__global__ void __launch_bounds__(256) k_rho(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                             int to_rho0, int with_kin)
+// block-wide sum / maximum into one global word (one atomic per block); red is
+// an LDS scratch of one double per wave
+__device__ __forceinline__ void block_atomic_sum(double v, double *dst, double *red)
 {
-    const InstDesc &D = Dt[work[blockIdx.x].x];
-    const long long p = (long long)work[blockIdx.x].y * PIC_PART_CHUNK + threadIdx.x;
-    double kin = 0.0, bad = 0.0;
-    if (p < D.np) {
-        int c[3];
-        unpack_cell<DIM>((unsigned)D.pidx[p], c);
-        double w[3][L + 1];
-        for (int a = 0; a < 3; a++) {
-            if (DIM == 2 && a == 1) continue;
-            Shape<L, double>::integer((double)((const R *)D.poff[a])[p], w[a]);
-        }
-        constexpr int H = (L - 1) / 2;
-        double *rho = to_rho0 ? D.rho0 : D.rho;
-        const int NY = DIM == 3 ? L + 1 : 1;
-        for (int kz = 0; kz < L + 1; kz++)
-            for (int ky = 0; ky < NY; ky++)
-                for (int kx = 0; kx < L + 1; kx++) {
-                    const int gx = ((c[0] - H + kx) % D.n[0] + D.n[0]) % D.n[0];
-                    const int gy = DIM == 3 ? ((c[1] - H + ky) % D.n[1] + D.n[1]) % D.n[1] : 0;
-                    const int gz = ((c[2] - H + kz) % D.n[2] + D.n[2]) % D.n[2];
-                    const double wt = w[0][kx] * (DIM == 3 ? w[1][ky] : 1.0) * w[2][kz];
-                    unsafeAtomicAdd(&rho[(gz * D.n[1] + gy) * D.n[0] + gx], D.rho_c * wt);
-                }
-        if (with_kin) {
-            const double u0 = ((const R *)D.pu[0])[p], u1 = ((const R *)D.pu[1])[p], u2 = ((const R *)D.pu[2])[p];
-            const double uu = u0 * u0 + u1 * u1 + u2 * u2;
-            kin = D.w * D.m * uu / (sqrt(1.0 + uu) + 1.0);   // gamma - 1 without cancellation
-            if (!isfinite(uu)) { bad = 1.0; kin = 0.0; }
-        }
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); i++) t += red[i];
+        if (t != 0.0) unsafeAtomicAdd(dst, t);
     }
-    if (with_kin) {
-        block_sum_to(kin, D.diag + DG_WKIN);
-        block_sum_to(bad, D.diag + DG_NONFIN);
+    __syncthreads();
+}
+__device__ __forceinline__ void block_atomic_max(double v, double *dst, double *red)
+{
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); i++) t = fmax(t, red[i]);
+        atomic_max_pos(dst, t);
+    }
+    __syncthreads();
+}
+
+// Charge density (order-L B-spline on the nodes) and kinetic energy, one particle
+// tile per work item: the tile's nodes are accumulated in an LDS window (double
+// atomics) and flushed once, as the particle kernel does for J.
+template <int DIM, int L, class R>
+__global__ void __launch_bounds__(256) k_rho(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int nwork,
+                                             int wmx, int wmy, int wmz, int to_rho0, int with_kin)
+{
+    constexpr int JL = (L + 1) / 2, H = (L - 1) / 2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *srho = reinterpret_cast<double *>(smem);
+    __shared__ double red[8];
+    const int tid = threadIdx.x, bs = blockDim.x;
+    for (int item = blockIdx.x; item < nwork; item += gridDim.x) {
+        const int inst = work[item].x, tile = work[item].y;
+        const InstDesc &D = Dt[inst];
+        const int p0 = D.tstart[tile], p1 = D.tstart[tile + 1];
+        if (p1 <= p0) continue;
+        int lo[3], o[3], wn[3];
+        for (int a = 0; a < 3; a++) {
+            lo[a] = D.tbox[tile * 6 + a];
+            const int ext = D.tbox[tile * 6 + 3 + a];
+            if (DIM == 2 && a == 1) { o[a] = 0; wn[a] = 1; continue; }
+            o[a] = wrapi(lo[a] - JL, D.n[a]);
+            wn[a] = ext + L + 2;
+        }
+        const int nn[3] = {D.n[0], D.n[1], D.n[2]};
+        const bool fits = wn[0] <= wmx && wn[1] <= wmy && wn[2] <= wmz;
+        const int wc = wn[0] * wn[1] * wn[2];
+        if (fits)
+            for (int c = tid; c < wc; c += bs) srho[c] = 0.0;
+        __syncthreads();
+        double *rho = to_rho0 ? D.rho0 : D.rho;
+        const double rc = D.rho_c;
+        double kin = 0.0, bad = 0.0;
+        for (int p = p0 + tid; p < p1; p += bs) {
+            int c[3];
+            unpack_cell<DIM>((unsigned)D.pidx[p], c);
+            double w[3][L + 1];
+            int lc[3] = {0, 0, 0};
+            for (int a = 0; a < 3; a++) {
+                if (DIM == 2 && a == 1) { w[a][0] = 1.0; continue; }
+                Shape<L, double>::integer((double)((const R *)D.poff[a])[p], w[a]);
+                int rel = c[a] - lo[a];
+                rel += rel < 0 ? nn[a] : 0;
+                lc[a] = rel + JL - H;
+            }
+            const int NY = DIM == 3 ? L + 1 : 1;
+            for (int kz = 0; kz < L + 1; kz++)
+                for (int ky = 0; ky < NY; ky++)
+                    for (int kx = 0; kx < L + 1; kx++) {
+                        const double v = rc * w[0][kx] * (DIM == 3 ? w[1][ky] : 1.0) * w[2][kz];
+                        const int x = lc[0] + kx, y = DIM == 3 ? lc[1] + ky : 0, z = lc[2] + kz;
+                        if (fits) {
+                            unsafeAtomicAdd(&srho[(z * wn[1] + y) * wn[0] + x], v);
+                        } else {
+                            const int gx = (o[0] + x) % nn[0], gy = (o[1] + y) % nn[1], gz = (o[2] + z) % nn[2];
+                            unsafeAtomicAdd(&rho[(gz * nn[1] + gy) * nn[0] + gx], v);
+                        }
+                    }
+            if (with_kin) {
+                const double u0 = ((const R *)D.pu[0])[p], u1 = ((const R *)D.pu[1])[p], u2 = ((const R *)D.pu[2])[p];
+                const double uu = u0 * u0 + u1 * u1 + u2 * u2;
+                if (!isfinite(uu)) bad = 1.0;
+                else kin += D.w * D.m * uu / (sqrt(1.0 + uu) + 1.0);   // gamma - 1 without cancellation
+            }
+        }
+        __syncthreads();
+        if (fits)
+            for (int c = tid; c < wc; c += bs) {
+                const double v = srho[c];
+                if (v != 0.0) unsafeAtomicAdd(&rho[window_cell(c, wn, o, nn)], v);
+            }
+        if (with_kin) {
+            block_atomic_sum(kin, D.diag + DG_WKIN, red);
+            block_atomic_sum(bad, D.diag + DG_NONFIN, red);
+        }
+        __syncthreads();
     }
 }
 
 // Gauss residual after a step: div E^n - dt div J^{n+1/2} - (rho^{n+1} - rho^0)
+#define GAUSS_ITEMS 16
 template <int DIM, class R>
-__global__ void __launch_bounds__(256) k_gauss(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+__global__ void __launch_bounds__(256) k_gauss(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int nwork)
 {
     typedef typename JOf<R>::T JT;
-    const InstDesc &D = Dt[work[blockIdx.x].x];
-    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    __shared__ double red[8];
+    const int it0 = blockIdx.x * GAUSS_ITEMS, it1 = min(nwork, it0 + GAUSS_ITEMS);
     double g2 = 0.0, gmax = 0.0, chg = 0.0, rmax = 0.0;
-    if (cell < D.ncell) {
-        int i, j, k;
-        cell_ijk<R>(D, cell, i, j, k);
-        const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
-        const int im = (i == 0 ? nx - 1 : i - 1) + (j + k * ny) * nx;
-        const int km = i + (j + (k == 0 ? nz - 1 : k - 1) * ny) * nx;
-        const R *E0 = (const R *)D.E[0], *E1 = (const R *)D.E[1], *E2 = (const R *)D.E[2];
-        const JT *J0 = (const JT *)D.J[0], *J1 = (const JT *)D.J[1], *J2 = (const JT *)D.J[2];
-        double divE = ((double)E0[cell] - (double)E0[im]) / D.d[0] + ((double)E2[cell] - (double)E2[km]) / D.d[2];
-        double divJ = (jreal(J0[cell], D.jq) - jreal(J0[im], D.jq)) / D.d[0] +
-                      (jreal(J2[cell], D.jq) - jreal(J2[km], D.jq)) / D.d[2];
-        if (DIM == 3) {
-            const int jm = i + ((j == 0 ? ny - 1 : j - 1) + k * ny) * nx;
-            divE += ((double)E1[cell] - (double)E1[jm]) / D.d[1];
-            divJ += (jreal(J1[cell], D.jq) - jreal(J1[jm], D.jq)) / D.d[1];
+    for (int it = it0; it < it1; it++) {
+        const InstDesc &D = Dt[work[it].x];
+        const int cell = work[it].y * PIC_FIELD_CHUNK + threadIdx.x;
+        if (cell < D.ncell) {
+            int i, j, k;
+            cell_ijk<R>(D, cell, i, j, k);
+            const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
+            const int im = (i == 0 ? nx - 1 : i - 1) + (j + k * ny) * nx;
+            const int km = i + (j + (k == 0 ? nz - 1 : k - 1) * ny) * nx;
+            const R *E0 = (const R *)D.E[0], *E1 = (const R *)D.E[1], *E2 = (const R *)D.E[2];
+            const JT *J0 = (const JT *)D.J[0], *J1 = (const JT *)D.J[1], *J2 = (const JT *)D.J[2];
+            double divE = ((double)E0[cell] - (double)E0[im]) / D.d[0] + ((double)E2[cell] - (double)E2[km]) / D.d[2];
+            double divJ = (jreal(J0[cell], D.jq) - jreal(J0[im], D.jq)) / D.d[0] +
+                          (jreal(J2[cell], D.jq) - jreal(J2[km], D.jq)) / D.d[2];
+            if (DIM == 3) {
+                const int jm = i + ((j == 0 ? ny - 1 : j - 1) + k * ny) * nx;
+                divE += ((double)E1[cell] - (double)E1[jm]) / D.d[1];
+                divJ += (jreal(J1[cell], D.jq) - jreal(J1[jm], D.jq)) / D.d[1];
+            }
+            const double rho = D.rho[cell];
+            const double res = divE - D.dt * divJ - (rho - D.rho0[cell]);
+            g2 += res * res;
+            gmax = fmax(gmax, fabs(res));
+            chg += rho * D.dV;
+            rmax = fmax(rmax, fabs(rho));
         }
-        const double rho = D.rho[cell];
-        const double res = divE - D.dt * divJ - (rho - D.rho0[cell]);
-        g2 = res * res;
-        gmax = fabs(res);
-        chg = rho * D.dV;
-        rmax = fabs(rho);
-    }
-    block_sum_to(g2, D.diag + DG_G2);
-    block_sum_to(chg, D.diag + DG_CHARGE);
-    gmax = wave_max(gmax);
-    rmax = wave_max(rmax);
-    if ((threadIdx.x & 63) == 0) {
-        atomic_max_pos(D.diag + DG_GMAX, gmax);
-        atomic_max_pos(D.diag + DG_RHOMAX, rmax);
+        // flush at the block's last item or where the next item is another instance
+        if (it + 1 == it1 || work[it + 1].x != work[it].x) {
+            block_atomic_sum(g2, D.diag + DG_G2, red);
+            block_atomic_sum(chg, D.diag + DG_CHARGE, red);
+            block_atomic_max(gmax, D.diag + DG_GMAX, red);
+            block_atomic_max(rmax, D.diag + DG_RHOMAX, red);
+            g2 = gmax = chg = rmax = 0.0;
+        }
     }
 }
 
@@ -1212,13 +1284,16 @@ int launch_clear_j(const LaunchCtx &c, const int2 *fwork, int nwork)
     return hip_ok(hipGetLastError());
 }
 
-int launch_rho(const LaunchCtx &c, const int2 *cwork, int ncwork, const int2 *fwork, int nfwork, int to_rho0)
+int launch_rho(const LaunchCtx &c, const int2 *pwork, int npwork, const int2 *fwork, int nfwork, const int wmax[3],
+               int to_rho0)
 {
     if (nfwork > 0)
         k_zero_rho_diag<<<dim3(nfwork), dim3(PIC_FIELD_CHUNK), 0, c.stream>>>(c.desc, fwork, to_rho0);
-    if (ncwork > 0) {
-        dim3 g(ncwork), b(PIC_PART_CHUNK);
-#define RK(D_, L_) k_rho<D_, L_, R><<<g, b, 0, c.stream>>>(c.desc, cwork, to_rho0, to_rho0 ? 0 : 1)
+    if (npwork > 0) {
+        const int wm[3] = {wmax[0], c.dims == 3 ? wmax[1] : 1, wmax[2]};
+        const size_t sm = (size_t)wm[0] * wm[1] * wm[2] * sizeof(double);
+        dim3 g(npwork), b(256);
+#define RK(D_, L_) k_rho<D_, L_, R><<<g, b, sm, c.stream>>>(c.desc, pwork, npwork, wm[0], wm[1], wm[2], to_rho0, to_rho0 ? 0 : 1)
         DISPATCH_R(c.fp32, {
             if (c.dims == 2 && c.order == 1) RK(2, 1);
             else if (c.dims == 2 && c.order == 3) RK(2, 3);
@@ -1230,17 +1305,18 @@ int launch_rho(const LaunchCtx &c, const int2 *cwork, int ncwork, const int2 *fw
     return hip_ok(hipGetLastError());
 }
 
-int launch_diag(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *cwork, int ncwork, int, int)
+int launch_diag(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *pwork, int npwork, const int wmax[3])
 {
     // zero rho and the accumulators, deposit rho (+ kinetic energy), then the grid reductions
-    if (launch_rho(c, cwork, ncwork, fwork, nfwork, 0)) return -1;
+    if (launch_rho(c, pwork, npwork, fwork, nfwork, wmax, 0)) return -1;
     if (nfwork <= 0) return 0;
-    dim3 g(nfwork), b(PIC_FIELD_CHUNK);
+    dim3 b(PIC_FIELD_CHUNK);
     DISPATCH_R(c.fp32, {
         k_energy<R><<<dim3((nfwork + ENERGY_ITEMS - 1) / ENERGY_ITEMS), b, 0, c.stream>>>(c.desc, fwork, nfwork,
                                                                                       nullptr, 0, nullptr, 1);
-        if (c.dims == 2) k_gauss<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
-        else k_gauss<3, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
+        const dim3 gg((nfwork + GAUSS_ITEMS - 1) / GAUSS_ITEMS);
+        if (c.dims == 2) k_gauss<2, R><<<gg, b, 0, c.stream>>>(c.desc, fwork, nfwork);
+        else k_gauss<3, R><<<gg, b, 0, c.stream>>>(c.desc, fwork, nfwork);
     });
     return hip_ok(hipGetLastError());
 }

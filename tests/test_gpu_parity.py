@@ -147,6 +147,27 @@ def test_3d_parity(order, prec, tol):
     sim.close()
 
 
+@pytest.mark.parametrize("dims,order,sigma", [(2, 1, 0.05), (2, 3, 0.05), (3, 1, 0.05), (3, 3, 0.05),
+                                               (2, 1, 3.0)])
+def test_charge_density_and_diagnostics_match_oracle(dims, order, sigma):
+    """rho on the nodes (tiled LDS deposit), kinetic energy, charge and the Gauss
+    residual after a few steps; sigma 3 makes a hot beam whose tiles outgrow their
+    windows (global fallback path)."""
+    base = "beam2d_64_fp64" if dims == 2 else "beam3d_128x128x256"
+    n = (48, 40) if dims == 2 else (12, 10, 16)
+    wl = pi.workload(base, n=n, order=order, ppc=3, gamma=3.0)
+    sim, ref = _pair(wl, 6, "fp64", sigma=sigma)
+    r = sim.field("rho", 0)
+    rr = ref.rho()
+    _say("rho dims %d order %d sigma %g: rel %.3e" % (dims, order, sigma, _rel(r, rr)))
+    assert _rel(r, rr) < 1e-12
+    d, od = sim.diag(), ref.diag()
+    assert abs(d["Wkin"] - od["Wkin"]) < 1e-11 * od["Wkin"]
+    assert abs(d["charge"] - od["charge"]) < 1e-11 * abs(od["charge"])
+    assert abs(d["gauss_linf"] - od["gauss_linf"]) < 1e-9 * d["rho_max"]
+    sim.close()
+
+
 # ----------------------------------------------------------- edge cases
 
 def test_ragged_grid_and_tiny_grid():
