@@ -442,7 +442,7 @@ enum { PL_EB = 0, PL_T1 = 1, PL_T2 = 2, PL_SEEN = 3, PL_LSEEN = 4, PL_LEB = 5 };
 __device__ __forceinline__ void *plane(const InstDesc &D, int sel, int comp)
 {
     switch (sel) {
-    case PL_EB: return comp < 3 ? D.E[comp] : D.B[comp - 3];
+    case PL_EB: return comp < 3 ? D.E[0][comp] : D.B[0][comp - 3];
     case PL_T1: return D.T1[comp];
     case PL_T2: return D.T2[comp];
     case PL_SEEN: return comp < 3 ? D.Et[comp] : D.Bt[comp - 3];
@@ -506,7 +506,7 @@ __global__ void __launch_bounds__(256) k_adj_grad(const InstDesc *__restrict__ D
     for (int j = 0; j < 9; j++) v[j] = 0.0;
     if (cell < D.ncell) {
         const R *lam = (const R *)plane(D, lam_sel, comp);
-        const double e1 = (double)((const R *)D.E[comp])[cell];
+        const double e1 = (double)((const R *)D.E[0][comp])[cell];
         const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
         const int i = cell % nx, r = cell / nx, j0 = r % ny, k = r / ny;
         const int rowoff = i + j0 * nx, pl = nx * ny;
@@ -584,7 +584,7 @@ __global__ void __launch_bounds__(256) k_adj_yee_b(const InstDesc *__restrict__ 
 
 // loss W and its gradient seed lambda_E = dV (Ex, Ey, 0), lambda_B = dV (Bx, By, 0)
 template <class R>
-__global__ void __launch_bounds__(256) k_adj_seed(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+__global__ void __launch_bounds__(256) k_adj_seed(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int par)
 {
     const InstDesc &D = Dt[work[blockIdx.x].x];
     const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
@@ -592,7 +592,7 @@ __global__ void __launch_bounds__(256) k_adj_seed(const InstDesc *__restrict__ D
     if (cell < D.ncell) {
         const R dV = (R)D.dV;
         for (int c = 0; c < 3; c++) {
-            const R e = ((const R *)D.E[c])[cell], b = ((const R *)D.B[c])[cell];
+            const R e = ((const R *)D.E[par][c])[cell], b = ((const R *)D.B[par][c])[cell];
             ((R *)D.lE[c])[cell] = c < 2 ? dV * e : R(0);
             ((R *)D.lB[c])[cell] = c < 2 ? dV * b : R(0);
             ((R *)D.lJ[c])[cell] = R(0);
@@ -739,7 +739,7 @@ __device__ __forceinline__ void adj_seen_body(const InstDesc *__restrict__ Dt, c
         if (gx >= nx || gz >= nz) continue;
         const int g = gz * nx + gx;
         if constexpr (GRAD) {
-            const R e1 = G<R>((const void *)D.E[comp])[g];
+            const R e1 = G<R>((const void *)D.E[0][comp])[g];
             const R *l = lam + (zz + deg) * ADJ_TX + xx;
             R add = R(0);
 #pragma unroll
@@ -904,7 +904,7 @@ size_t adjoint_smem_bytes(int dims, int fp32, const int wmax[3])
 int launch_adj_seed(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *cwork, int ncwork)
 {
     DISPATCH_R(c.fp32, {
-        if (nfwork > 0) k_adj_seed<R><<<dim3(nfwork), dim3(PIC_FIELD_CHUNK), 0, c.stream>>>(c.desc, fwork);
+        if (nfwork > 0) k_adj_seed<R><<<dim3(nfwork), dim3(PIC_FIELD_CHUNK), 0, c.stream>>>(c.desc, fwork, c.par);
         if (ncwork > 0) k_adj_seed_particles<R><<<dim3(ncwork), dim3(PIC_PART_CHUNK), 0, c.stream>>>(c.desc, cwork);
     });
     return hip_ok(hipGetLastError());
@@ -927,7 +927,7 @@ int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fw
                     const int wmax[3])
 {
     // Et, Bt of this step: recorded in the tape slot in 2D, recomputed in 3D
-    if (live.dims == 3 && launch_seen(tape, fwork, nfwork, swork, nswork, 0)) return -1;
+    if (live.dims == 3 && launch_seen(tape, fwork, nfwork, swork, nswork)) return -1;
     const int wm[3] = {wmax[0], live.dims == 3 ? wmax[1] : 1, wmax[2]};
     const size_t smem = adjoint_smem_bytes(live.dims, live.fp32, wm);
     const dim3 gf(nfwork), g6(nfwork, 6), g2(nfwork, 2), bf(PIC_FIELD_CHUNK);

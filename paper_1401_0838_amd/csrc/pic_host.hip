@@ -189,7 +189,9 @@ struct pic_state {
     int yee_tz = 8, seen_tz = 16;    // 2D field-kernel tile heights (tunable)
     int waves4 = 0;                  // particle kernel capped at four waves per SIMD (tunable)
     int prefetch = 0;                // particle kernel loads one particle ahead (tunable)
-    hipGraphExec_t gexec_k = nullptr, gexec_1 = nullptr;
+    // captured graphs, one per parity of the state they start from
+    hipGraphExec_t gexec_k[2] = {nullptr, nullptr}, gexec_1[2] = {nullptr, nullptr};
+    int parity = 0;                  // which set of E, B, J planes is current
     long long step = 0;
     int *trace_pos = nullptr;
     int *any_resort = nullptr;       // device word shared by all instances: a re-sort is pending
@@ -199,7 +201,7 @@ struct pic_state {
     int adj_steps = 0, adj_k = 0;
     bool no_resort = false;
     int adj_pending = 0;                         // steps of the last pic_adjoint_forward
-    hipGraphExec_t gexec_adj_fwd = nullptr, gexec_adj_seg = nullptr;
+    hipGraphExec_t gexec_adj_fwd[2] = {nullptr, nullptr}, gexec_adj_seg = nullptr;
     std::vector<std::vector<Snap>> ckpt, tape;   // [instance][slot]
     InstDesc *d_tape_desc = nullptr;             // adj_k * n_inst descriptors
     InstDesc *d_rec_desc = nullptr;              // 2D: the live step recording into tape slot k
@@ -221,6 +223,7 @@ LaunchCtx ctx(const pic_state *s)
     c.waves4 = s->waves4;
     c.prefetch = s->prefetch;
     c.any_resort = s->any_resort;
+    c.par = s->parity;
     if (!s->desc.empty()) {
         const InstDesc &d0 = s->desc[0];
         c.hz = d0.hz; c.hx = d0.hx; c.hzf = d0.hzf; c.psi_deg = d0.psi_deg;
@@ -287,14 +290,20 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
         auto plane = [&](size_t bytes_per) { return (void *)L.take<char>(ncell * bytes_per); };
         // E, B and J each occupy one contiguous region (planes in component
         // order) so that checkpoints copy them with one transfer each
-        void *pe[3], *pb[3], *pj[3], *pet[3], *pbt[3];
-        for (int k = 0; k < 3; k++) pe[k] = plane(R);
-        for (int k = 0; k < 3; k++) pb[k] = plane(R);
-        for (int k = 0; k < 3; k++) pj[k] = plane(8);
+        void *pe[2][3], *pb[2][3], *pj[2][3], *pet[3], *pbt[3];
+        for (int q = 0; q < 2; q++) {
+            for (int k = 0; k < 3; k++) pe[q][k] = plane(R);
+            for (int k = 0; k < 3; k++) pb[q][k] = plane(R);
+            for (int k = 0; k < 3; k++) pj[q][k] = plane(8);
+        }
         for (int k = 0; k < 3; k++) pet[k] = plane(R);
         for (int k = 0; k < 3; k++) pbt[k] = plane(R);
         if (D)
-            for (int k = 0; k < 3; k++) { D->E[k] = pe[k]; D->B[k] = pb[k]; D->J[k] = pj[k]; D->Et[k] = pet[k]; D->Bt[k] = pbt[k]; }
+            for (int k = 0; k < 3; k++) {
+                for (int q = 0; q < 2; q++) { D->E[q][k] = pe[q][k]; D->B[q][k] = pb[q][k]; D->J[q][k] = pj[q][k]; }
+                D->Et[k] = pet[k];
+                D->Bt[k] = pbt[k];
+            }
         const bool adj = c.adjoint_steps > 0;
         for (int k = 0; k < 6; k++) {
             void *t1 = plane(R);
@@ -515,8 +524,11 @@ int upload_particles(pic_state *s, int inst, const pic_particles &p)
 }
 
 // bytes of the contiguous regions [E..B], [J], [cell index..momenta]
-size_t region_fields(const InstDesc &D, size_t R) { return (size_t)((char *)D.B[2] - (char *)D.E[0]) + D.ncell * R; }
-size_t region_j(const InstDesc &D) { return (size_t)((char *)D.J[2] - (char *)D.J[0]) + (size_t)D.ncell * 8; }
+size_t region_fields(const InstDesc &D, size_t R)
+{
+    return (size_t)((char *)D.B[0][2] - (char *)D.E[0][0]) + D.ncell * R;
+}
+size_t region_j(const InstDesc &D) { return (size_t)((char *)D.J[0][2] - (char *)D.J[0][0]) + (size_t)D.ncell * 8; }
 size_t region_particles(const InstDesc &D, size_t R)
 {
     return (size_t)((char *)D.pu[2] - (char *)D.pidx) + (size_t)D.np * R;
@@ -537,11 +549,12 @@ int snap_copy_particles(pic_state *s, int inst, const Snap &sn, bool save)
     return PIC_OK;
 }
 
-// E and B of one instance into a snapshot
-int snap_copy_fields(pic_state *s, int inst, const Snap &sn)
+// E and B (set q) of one instance into a snapshot
+int snap_copy_fields(pic_state *s, int inst, const Snap &sn, int q)
 {
     const InstDesc &D = s->desc[inst];
-    HIP_TRY(hipMemcpyAsync(sn.E[0], D.E[0], region_fields(D, s->fp32 ? 4 : 8), hipMemcpyDeviceToDevice, s->stream));
+    HIP_TRY(hipMemcpyAsync(sn.E[0], D.E[q][0], region_fields(D, s->fp32 ? 4 : 8), hipMemcpyDeviceToDevice,
+                           s->stream));
     return PIC_OK;
 }
 
@@ -610,11 +623,13 @@ int build_worklists(pic_state *s)
 }
 
 // one step's launches for instances [i0, i0 + ni) using the given work ranges
+// one step's launches; the Yee launch reads the current parity, the rest see the new one
 int enqueue_step_range(pic_state *s, const Range &f, const Range &sr, const Range &yr, const Range &p, bool trace)
 {
     LaunchCtx c = ctx(s);
     if (launch_yee(c, s->fwork + f.off, f.n, s->ywork + yr.off, yr.n)) return fail(PIC_EHIP, "yee launch");
-    if (launch_seen(c, s->fwork + f.off, f.n, s->swork + sr.off, sr.n, 1)) return fail(PIC_EHIP, "seen launch");
+    c.par ^= 1;
+    if (launch_seen(c, s->fwork + f.off, f.n, s->swork + sr.off, sr.n)) return fail(PIC_EHIP, "seen launch");
     if (launch_particles(c, s->pwork + p.off, p.n, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particle launch");
     (void)trace;
     return PIC_OK;
@@ -632,6 +647,7 @@ int enqueue_step(pic_state *s)
             if (rc) return rc;
         }
     }
+    s->parity ^= 1;
     if (s->trace_cap > 0) {
         LaunchCtx c = ctx(s);
         if (launch_trace_rows(c, s->fwork, s->nfwork, s->trace_pos, s->trace, s->n_inst, s->trace_cap))
@@ -656,18 +672,24 @@ int enqueue_resort(pic_state *s)
 
 void drop_graphs(pic_state *s)
 {
-    if (s->gexec_k) { (void)hipGraphExecDestroy(s->gexec_k); s->gexec_k = nullptr; }
-    if (s->gexec_1) { (void)hipGraphExecDestroy(s->gexec_1); s->gexec_1 = nullptr; }
-    if (s->gexec_adj_fwd) { (void)hipGraphExecDestroy(s->gexec_adj_fwd); s->gexec_adj_fwd = nullptr; }
+    for (int q = 0; q < 2; q++) {
+        if (s->gexec_k[q]) { (void)hipGraphExecDestroy(s->gexec_k[q]); s->gexec_k[q] = nullptr; }
+        if (s->gexec_1[q]) { (void)hipGraphExecDestroy(s->gexec_1[q]); s->gexec_1[q] = nullptr; }
+        if (s->gexec_adj_fwd[q]) { (void)hipGraphExecDestroy(s->gexec_adj_fwd[q]); s->gexec_adj_fwd[q] = nullptr; }
+    }
     if (s->gexec_adj_seg) { (void)hipGraphExecDestroy(s->gexec_adj_seg); s->gexec_adj_seg = nullptr; }
 }
 
 // capture whatever `body` enqueues on the state's stream into an executable graph
+// (the enqueue functions advance the host's parity as they record steps; a
+// capture records without running, so the parity is put back afterwards)
 template <class F> int capture_fn(pic_state *s, F body, hipGraphExec_t *out)
 {
     hipGraph_t g = nullptr;
+    const int par0 = s->parity;
     HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
     int rc = body();
+    s->parity = par0;
     hipError_t e = hipStreamEndCapture(s->stream, &g);
     if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
     if (e != hipSuccess) return fail(PIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
@@ -680,10 +702,12 @@ template <class F> int capture_fn(pic_state *s, F body, hipGraphExec_t *out)
 int capture(pic_state *s, int k, bool with_resort, hipGraphExec_t *out)
 {
     hipGraph_t g = nullptr;
+    const int par0 = s->parity;
     HIP_TRY(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
     int rc = PIC_OK;
     for (int i = 0; i < k && rc == PIC_OK; i++) rc = enqueue_step(s);
     if (rc == PIC_OK && with_resort) rc = enqueue_resort(s);
+    s->parity = par0;
     hipError_t e = hipStreamEndCapture(s->stream, &g);
     if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
     if (e != hipSuccess) return fail(PIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
@@ -888,8 +912,8 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
                 InstDesc d = s->desc[i];
                 const Snap &sn = s->tape[i][k];
                 for (int c = 0; c < 3; c++) {
-                    d.E[c] = sn.E[c];
-                    d.B[c] = sn.B[c];
+                    d.E[0][c] = d.E[1][c] = sn.E[c];
+                    d.B[0][c] = d.B[1][c] = sn.B[c];
                     d.poff[c] = sn.poff[c];
                     d.pu[c] = sn.pu[c];
                 }
@@ -1005,23 +1029,33 @@ extern "C" int pic_step(pic_state *s, int nsteps)
         }
         return PIC_OK;
     }
-    if (!s->gexec_k && (rc = capture(s, s->graph_k, true, &s->gexec_k))) return rc;
-    if (!s->gexec_1 && (rc = capture(s, 1, false, &s->gexec_1))) return rc;
+    auto one = [&]() -> int {
+        const int q = s->parity;
+        int r;
+        if (!s->gexec_1[q] && (r = capture(s, 1, false, &s->gexec_1[q]))) return r;
+        HIP_TRY(hipGraphLaunch(s->gexec_1[q], s->stream));
+        s->parity ^= 1;
+        s->step++;
+        return PIC_OK;
+    };
     int n = 0;
     // single steps until the step count is a multiple of the graph length, then whole graphs
     while (n < nsteps && (s->step % s->graph_k) != 0) {
-        HIP_TRY(hipGraphLaunch(s->gexec_1, s->stream));
-        s->step++; n++;
+        if ((rc = one())) return rc;
+        n++;
         if (s->step % s->graph_k == 0 && (rc = enqueue_resort(s))) return rc;
     }
     while (nsteps - n >= s->graph_k) {
-        HIP_TRY(hipGraphLaunch(s->gexec_k, s->stream));
+        const int q = s->parity;
+        if (!s->gexec_k[q] && (rc = capture(s, s->graph_k, true, &s->gexec_k[q]))) return rc;
+        HIP_TRY(hipGraphLaunch(s->gexec_k[q], s->stream));
+        s->parity ^= s->graph_k & 1;
         s->step += s->graph_k;
         n += s->graph_k;
     }
     while (n < nsteps) {
-        HIP_TRY(hipGraphLaunch(s->gexec_1, s->stream));
-        s->step++; n++;
+        if ((rc = one())) return rc;
+        n++;
     }
     return PIC_OK;
 }
@@ -1034,9 +1068,9 @@ extern "C" int pic_fields(pic_state *s, int inst, int which, int comp, double *h
     void *src = nullptr;
     bool is_j = false, is_rho = false;
     switch (which) {
-    case PIC_FIELD_E: src = D.E[comp]; break;
-    case PIC_FIELD_B: src = D.B[comp]; break;
-    case PIC_FIELD_J: src = D.J[comp]; is_j = true; break;
+    case PIC_FIELD_E: src = D.E[s->parity][comp]; break;
+    case PIC_FIELD_B: src = D.B[s->parity][comp]; break;
+    case PIC_FIELD_J: src = D.J[s->parity][comp]; is_j = true; break;
     case PIC_FIELD_SEEN_E: src = D.Et[comp]; break;
     case PIC_FIELD_SEEN_B: src = D.Bt[comp]; break;
     case PIC_FIELD_RHO: is_rho = true; break;
@@ -1132,9 +1166,12 @@ extern "C" int pic_profile(pic_state *s, int nsteps, pic_timing_t *out)
     for (int n = 0; n < nsteps; n++) {
         const Range f{0, s->nfwork}, p{0, s->npwork};
         HIP_TRY(hipEventRecord(ev[0], s->stream));
+        c.par = s->parity;
         if (launch_yee(c, s->fwork, f.n, s->ywork, s->nywork)) return fail(PIC_EHIP, "yee");
+        c.par ^= 1;
+        s->parity ^= 1;
         HIP_TRY(hipEventRecord(ev[1], s->stream));
-        if (launch_seen(c, s->fwork, f.n, s->swork, s->nswork, 1)) return fail(PIC_EHIP, "seen");
+        if (launch_seen(c, s->fwork, f.n, s->swork, s->nswork)) return fail(PIC_EHIP, "seen");
         HIP_TRY(hipEventRecord(ev[2], s->stream));
         if (launch_particles(c, s->pwork, p.n, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particles");
         HIP_TRY(hipEventRecord(ev[3], s->stream));
@@ -1161,16 +1198,19 @@ extern "C" int pic_profile(pic_state *s, int nsteps, pic_timing_t *out)
 
 namespace {
 
+// save: from the current set of E, B, J planes; restore: into set 0 (the caller
+// makes set 0 current once every instance is restored)
 int snap_copy(pic_state *s, int inst, const Snap &sn, bool save, bool with_j)
 {
     const InstDesc &D = s->desc[inst];
     const size_t R = s->fp32 ? 4 : 8;
     const hipMemcpyKind kd = hipMemcpyDeviceToDevice;
+    const int q = save ? s->parity : 0;
     auto cp = [&](void *live, void *snapp, size_t bytes) {
         return save ? hipMemcpyAsync(snapp, live, bytes, kd, s->stream) : hipMemcpyAsync(live, snapp, bytes, kd, s->stream);
     };
-    HIP_TRY(cp(D.E[0], sn.E[0], region_fields(D, R)));
-    if (with_j) HIP_TRY(cp(D.J[0], sn.J[0], region_j(D)));
+    HIP_TRY(cp(D.E[q][0], sn.E[0], region_fields(D, R)));
+    if (with_j) HIP_TRY(cp(D.J[q][0], sn.J[0], region_j(D)));
     return snap_copy_particles(s, inst, sn, save);
 }
 
@@ -1190,8 +1230,10 @@ int forward_step_eager(pic_state *s)
 {
     LaunchCtx live = ctx(s);
     if (launch_yee(live, s->fwork, s->nfwork, s->ywork, s->nywork)) return fail(PIC_EHIP, "yee");
-    if (launch_seen(live, s->fwork, s->nfwork, s->swork, s->nswork, 1)) return fail(PIC_EHIP, "seen");
+    live.par ^= 1;
+    if (launch_seen(live, s->fwork, s->nfwork, s->swork, s->nswork)) return fail(PIC_EHIP, "seen");
     if (launch_particles(live, s->pwork, s->npwork, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particles");
+    s->parity ^= 1;
     return PIC_OK;
 }
 
@@ -1207,20 +1249,26 @@ int enqueue_segment(pic_state *s, int m)
             LaunchCtx rec = live;
             rec.desc = s->d_rec_desc + (size_t)slot * s->n_inst;
             rec.record = 1;
-            if (launch_yee(live, s->fwork, s->nfwork, s->ywork, s->nywork) ||
-                launch_seen(rec, s->fwork, s->nfwork, s->swork, s->nswork, 1) ||
+            rec.par = s->parity;
+            if (launch_yee(rec, s->fwork, s->nfwork, s->ywork, s->nywork)) return fail(PIC_EHIP, "recompute");
+            rec.par ^= 1;
+            if (launch_seen(rec, s->fwork, s->nfwork, s->swork, s->nswork) ||
                 launch_particles(rec, s->pwork, s->npwork, 0, s->block, s->wmax))
                 return fail(PIC_EHIP, "recompute");
+            s->parity ^= 1;
             continue;
         }
         for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy_particles(s, i, s->tape[i][slot], true);
         if (rc) break;
-        if (launch_yee(live, s->fwork, s->nfwork, s->ywork, s->nywork) ||
-            launch_seen(live, s->fwork, s->nfwork, s->swork, s->nswork, 1))
-            return fail(PIC_EHIP, "recompute");
-        for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy_fields(s, i, s->tape[i][slot]);
+        LaunchCtx c = live;
+        c.par = s->parity;
+        if (launch_yee(c, s->fwork, s->nfwork, s->ywork, s->nywork)) return fail(PIC_EHIP, "recompute");
+        c.par ^= 1;
+        if (launch_seen(c, s->fwork, s->nfwork, s->swork, s->nswork)) return fail(PIC_EHIP, "recompute");
+        for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy_fields(s, i, s->tape[i][slot], c.par);
         if (rc) break;
-        if (launch_particles(live, s->pwork, s->npwork, 0, s->block, s->wmax)) return fail(PIC_EHIP, "recompute");
+        if (launch_particles(c, s->pwork, s->npwork, 0, s->block, s->wmax)) return fail(PIC_EHIP, "recompute");
+        s->parity ^= 1;
     }
     for (int slot = m - 1; slot >= 0 && rc == PIC_OK; slot--) {
         LaunchCtx tp = live;
@@ -1258,10 +1306,12 @@ extern "C" int pic_adjoint_forward(pic_state *s, int nsteps, double *loss)
         if (rc) break;
         const int m = std::min(K, nsteps - seg * K);
         if (m == K && s->use_graph) {
-            if (!s->gexec_adj_fwd &&
-                (rc = capture_fn(s, [&]() { return enqueue_forward_steps(s, K); }, &s->gexec_adj_fwd)))
+            const int q = s->parity;
+            if (!s->gexec_adj_fwd[q] &&
+                (rc = capture_fn(s, [&]() { return enqueue_forward_steps(s, K); }, &s->gexec_adj_fwd[q])))
                 break;
-            if (hipGraphLaunch(s->gexec_adj_fwd, s->stream) != hipSuccess) rc = fail(PIC_EHIP, "graph launch");
+            if (hipGraphLaunch(s->gexec_adj_fwd[q], s->stream) != hipSuccess) rc = fail(PIC_EHIP, "graph launch");
+            s->parity ^= K & 1;
         } else {
             rc = enqueue_forward_steps(s, m);
         }
@@ -1294,6 +1344,7 @@ extern "C" int pic_adjoint_backward(pic_state *s, double *grad)
     for (int seg = nseg - 1; seg >= 0 && rc == PIC_OK; seg--) {
         for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy(s, i, s->ckpt[i][seg], false, true);
         if (rc) break;
+        s->parity = 0;
         const int m = std::min(K, nsteps - seg * K);
         if (m == K && s->use_graph) {
             if (!s->gexec_adj_seg &&
@@ -1306,6 +1357,7 @@ extern "C" int pic_adjoint_backward(pic_state *s, double *grad)
     }
     // back to the forward end state
     for (int i = 0; i < s->n_inst && rc == PIC_OK; i++) rc = snap_copy(s, i, s->ckpt[i][nseg], false, true);
+    s->parity = 0;
     s->no_resort = false;
     s->adj_pending = 0;
     if (rc) return rc;

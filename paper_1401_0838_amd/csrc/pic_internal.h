@@ -52,9 +52,11 @@ struct InstDesc {
     double tx[2 * PIC_MAX_HX + 1];     // x filter taps
     double ty[2 * PIC_MAX_HX + 1];     // y filter taps (3D)
     // grid planes (element type follows the precision)
-    void *E[3], *B[3], *Et[3], *Bt[3];
+    // E, B and J alternate between two sets of planes from step to step (index =
+    // parity): the field kernels read one set with halos and write the other
+    void *E[2][3], *B[2][3], *J[2][3];
+    void *Et[3], *Bt[3];
     void *T1[6], *T2[6];   // intermediates of the separable seen-field passes
-    void *J[3];            // long long fixed point (float mode) or double
     double *rho0, *rho;
     // particles
     int *pidx;             // packed cell index: 2D x | z << 16, 3D x | y << 11 | z << 21
@@ -99,16 +101,16 @@ struct LaunchCtx {
     // seen-stencil half-widths and Psi degree shared by every instance (-1: they differ)
     int hz = -1, hx = -1, hzf = -1, psi_deg = -1;
     const int *any_resort = nullptr;  // device word: a re-sort is pending
-    int record = 0;                   // 2D: descriptors carry tape-recording pointers somewhere
+    int record = 0;                   // 2D: descriptors carry tape-recording pointers
+    // parity of the current E, B (and of the J they were advanced with): the
+    // Yee launch reads set par and writes set par ^ 1; every later launch of the
+    // step is given the new parity
+    int par = 0;
 };
 
 int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork);
 #define PIC_YEE_TX 64
-// commit = 1: the step's own seen pass.  In 2D the fused Yee kernel leaves the
-// new E, B in T1 (it cannot update in place: neighbouring tiles read its halo),
-// and this pass copies them to E, B and clears J for the deposit.
-// commit = 0: recompute Et, Bt from E, B as they are (reverse sweep).
-int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork, int commit);
+int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork);
 size_t seen_smem_bytes(int fp32, int tz);
 int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid, int block,
                      const int wmax[3]);

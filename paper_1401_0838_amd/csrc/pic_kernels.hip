@@ -205,7 +205,7 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 // to the tape slot named by the descriptor (reverse sweep recompute).
 template <int DIM, int L, class R, int P, bool PF, bool TP = false>
 __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                               int nwork, int wmx, int wmy, int wmz)
+                                               int nwork, int wmx, int wmy, int wmz, int par)
 {
     typedef typename JOf<R>::T JT;
     constexpr int JL = (L + 1) / 2;      // guard cells below the bounding box
@@ -274,7 +274,7 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
             for (int k = 0; k < 3; k++) {
                 gw.F[k] = G<R>((const void *)D.Et[k]);
                 gw.F[3 + k] = G<R>((const void *)D.Bt[k]);
-                gw.J[k] = G<JT>(D.J[k]);
+                gw.J[k] = G<JT>(D.J[par][k]);
                 gw.o[k] = o[k];
                 gw.n[k] = D.n[k];
             }
@@ -361,7 +361,7 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
         }
         __syncthreads();
         if (fits) {
-            gp<JT> gJ[3] = {G<JT>(D.J[0]), G<JT>(D.J[1]), G<JT>(D.J[2])};
+            gp<JT> gJ[3] = {G<JT>(D.J[par][0]), G<JT>(D.J[par][1]), G<JT>(D.J[par][2])};
             const int nwin = wn[0] * wn[1] * wn[2];
             for (int c = tid; c < nwin; c += bs) {
                 const int g = window_cell(c, wn, o, D.n);
@@ -394,17 +394,18 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
 
 template <int DIM, int L, class R, int P, bool PF = false, bool TP = false>
 __global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                                   int nwork, int wmx, int wmy, int wmz)
+                                                   int nwork, int wmx, int wmy, int wmz, int par)
 {
-    particles_body<DIM, L, R, P, PF, TP>(Dt, work, nwork, wmx, wmy, wmz);
+    particles_body<DIM, L, R, P, PF, TP>(Dt, work, nwork, wmx, wmy, wmz, par);
 }
 
 // same body compiled for four waves per SIMD (at most 128 VGPRs)
 template <int DIM, int L, class R, int P, bool PF = false>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
-k_particles_w4(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int nwork, int wmx, int wmy, int wmz)
+k_particles_w4(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int nwork, int wmx, int wmy, int wmz,
+               int par)
 {
-    particles_body<DIM, L, R, P, PF>(Dt, work, nwork, wmx, wmy, wmz);
+    particles_body<DIM, L, R, P, PF>(Dt, work, nwork, wmx, wmy, wmz, par);
 }
 
 // ------------------------------------------------------------- Yee sweeps
@@ -418,9 +419,10 @@ __device__ __forceinline__ void cell_ijk(const InstDesc &D, int cell, int &i, in
     k = r / D.n[1];
 }
 
-// B -= (dt/2) curl E with forward differences
+// B[pbo] = B[pbi] - (dt/2) curl E[pe] with forward differences
 template <int DIM, class R>
-__global__ void __launch_bounds__(256) k_yee_b(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+__global__ void __launch_bounds__(256) k_yee_b(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int pe,
+                                               int pbi, int pbo)
 {
     const int inst = work[blockIdx.x].x;
     const InstDesc &D = Dt[inst];
@@ -431,8 +433,9 @@ __global__ void __launch_bounds__(256) k_yee_b(const InstDesc *__restrict__ Dt, 
     const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
     const int ip = (i + 1 == nx ? 0 : i + 1) + (j + (k * ny)) * nx;
     const int kp = i + (j + (k + 1 == nz ? 0 : k + 1) * ny) * nx;
-    const R *Ex = (const R *)D.E[0], *Ey = (const R *)D.E[1], *Ez = (const R *)D.E[2];
-    R *Bx = (R *)D.B[0], *By = (R *)D.B[1], *Bz = (R *)D.B[2];
+    const R *Ex = (const R *)D.E[pe][0], *Ey = (const R *)D.E[pe][1], *Ez = (const R *)D.E[pe][2];
+    const R *Bix = (const R *)D.B[pbi][0], *Biy = (const R *)D.B[pbi][1], *Biz = (const R *)D.B[pbi][2];
+    R *Bx = (R *)D.B[pbo][0], *By = (R *)D.B[pbo][1], *Bz = (R *)D.B[pbo][2];
     const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2];
     const R h = R(0.5) * (R)D.dt;
     const R ex = Ex[cell], ey = Ey[cell], ez = Ez[cell];
@@ -445,14 +448,16 @@ __global__ void __launch_bounds__(256) k_yee_b(const InstDesc *__restrict__ Dt, 
     }
     const R dzEy = (Ey[kp] - ey) * idz, dzEx = (Ex[kp] - ex) * idz;
     const R dxEz = (Ez[ip] - ez) * idx, dxEy = (Ey[ip] - ey) * idx;
-    Bx[cell] -= h * (dyEz - dzEy);
-    By[cell] -= h * (dzEx - dxEz);
-    Bz[cell] -= h * (dxEy - dyEx);
+    Bx[cell] = Bix[cell] - h * (dyEz - dzEy);
+    By[cell] = Biy[cell] - h * (dzEx - dxEz);
+    Bz[cell] = Biz[cell] - h * (dxEy - dyEx);
 }
 
-// E += dt (curl B - J - J_bg) with backward differences; clears J afterwards
+// E[po] = E[pi] + dt (curl B[po] - J[pi] - J_bg) with backward differences;
+// clears J[po] for the coming deposit
 template <int DIM, class R>
-__global__ void __launch_bounds__(256) k_yee_e(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+__global__ void __launch_bounds__(256) k_yee_e(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int pi,
+                                               int po)
 {
     typedef typename JOf<R>::T JT;
     const int inst = work[blockIdx.x].x;
@@ -464,9 +469,10 @@ __global__ void __launch_bounds__(256) k_yee_e(const InstDesc *__restrict__ Dt, 
     const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
     const int im = (i == 0 ? nx - 1 : i - 1) + (j + k * ny) * nx;
     const int km = i + (j + (k == 0 ? nz - 1 : k - 1) * ny) * nx;
-    const R *Bx = (const R *)D.B[0], *By = (const R *)D.B[1], *Bz = (const R *)D.B[2];
-    R *Ex = (R *)D.E[0], *Ey = (R *)D.E[1], *Ez = (R *)D.E[2];
-    JT *J0 = (JT *)D.J[0], *J1 = (JT *)D.J[1], *J2 = (JT *)D.J[2];
+    const R *Bx = (const R *)D.B[po][0], *By = (const R *)D.B[po][1], *Bz = (const R *)D.B[po][2];
+    const R *Eix = (const R *)D.E[pi][0], *Eiy = (const R *)D.E[pi][1], *Eiz = (const R *)D.E[pi][2];
+    R *Ex = (R *)D.E[po][0], *Ey = (R *)D.E[po][1], *Ez = (R *)D.E[po][2];
+    const JT *J0 = (const JT *)D.J[pi][0], *J1 = (const JT *)D.J[pi][1], *J2 = (const JT *)D.J[pi][2];
     const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2];
     const R dt = (R)D.dt;
     const R bx = Bx[cell], by = By[cell], bz = Bz[cell];
@@ -482,10 +488,11 @@ __global__ void __launch_bounds__(256) k_yee_e(const InstDesc *__restrict__ Dt, 
     const R jx = (R)(jreal(J0[cell], D.jq) + D.jbg[0]);
     const R jy = (R)(jreal(J1[cell], D.jq) + D.jbg[1]);
     const R jz = (R)(jreal(J2[cell], D.jq) + D.jbg[2]);
-    Ex[cell] += dt * (dyBz - dzBy - jx);
-    Ey[cell] += dt * (dzBx - dxBz - jy);
-    Ez[cell] += dt * (dxBy - dyBx - jz);
-    J0[cell] = JT(0); J1[cell] = JT(0); J2[cell] = JT(0);
+    Ex[cell] = Eix[cell] + dt * (dyBz - dzBy - jx);
+    Ey[cell] = Eiy[cell] + dt * (dzBx - dxBz - jy);
+    Ez[cell] = Eiz[cell] + dt * (dxBy - dyBx - jz);
+#pragma unroll
+    for (int c = 0; c < 3; c++) ((JT *)D.J[po][c])[cell] = JT(0);
 }
 
 // Fused 2D Yee update: B half step, E step (J read and cleared), B half step
@@ -496,7 +503,7 @@ __global__ void __launch_bounds__(256) k_yee_e(const InstDesc *__restrict__ Dt, 
 #define YEE_TX PIC_YEE_TX
 
 template <class R, int TZ>
-__global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+__global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int par)
 {
     typedef typename JOf<R>::T JT;
     constexpr int TX = YEE_TX;
@@ -511,12 +518,17 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
     const int ntx = (nx + TX - 1) / TX;
     const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-    const gp<const R> E[3] = {G<R>((const void *)D.E[0]), G<R>((const void *)D.E[1]), G<R>((const void *)D.E[2])};
-    const gp<const R> B[3] = {G<R>((const void *)D.B[0]), G<R>((const void *)D.B[1]), G<R>((const void *)D.B[2])};
-    const gp<const JT> J[3] = {G<JT>((const void *)D.J[0]), G<JT>((const void *)D.J[1]), G<JT>((const void *)D.J[2])};
+    const gp<const R> E[3] = {G<R>((const void *)D.E[par][0]), G<R>((const void *)D.E[par][1]),
+                              G<R>((const void *)D.E[par][2])};
+    const gp<const R> B[3] = {G<R>((const void *)D.B[par][0]), G<R>((const void *)D.B[par][1]),
+                              G<R>((const void *)D.B[par][2])};
+    const gp<const JT> J[3] = {G<JT>((const void *)D.J[par][0]), G<JT>((const void *)D.J[par][1]),
+                               G<JT>((const void *)D.J[par][2])};
     // E, B and J are read with halos that neighbouring tiles own, so the new
-    // fields go to the scratch planes T1 (E then B); the seen pass commits them
-    gp<R> O[6] = {G<R>(D.T1[0]), G<R>(D.T1[1]), G<R>(D.T1[2]), G<R>(D.T1[3]), G<R>(D.T1[4]), G<R>(D.T1[5])};
+    // fields go to the other set of planes (E then B), and that set's J is cleared
+    const int po = par ^ 1;
+    gp<R> O[6] = {G<R>(D.E[po][0]), G<R>(D.E[po][1]), G<R>(D.E[po][2]),
+                  G<R>(D.B[po][0]), G<R>(D.B[po][1]), G<R>(D.B[po][2])};
     const double jq = D.jq, jb[3] = {D.jbg[0], D.jbg[1], D.jbg[2]};
     const bool hasb = lane < WX - TX;
     const int gxa = wrap_near(x0 - 1 + lane, nx);
@@ -595,10 +607,16 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
         const R dzEy = (sE[1][ez] - sE[1][e]) * idz, dzEx = (sE[0][ez] - sE[0][e]) * idz;
         const R dxEz = (sE[2][ex] - sE[2][e]) * idx, dxEy = (sE[1][ex] - sE[1][e]) * idx;
         const int g = gz * nx + gx;
-        O[3][g] = sB[0][e] - h * (-dzEy);
-        O[4][g] = sB[1][e] - h * (dzEx - dxEz);
-        O[5][g] = sB[2][e] - h * dxEy;
+        const R b0 = sB[0][e] - h * (-dzEy), b1 = sB[1][e] - h * (dzEx - dxEz), b2 = sB[2][e] - h * dxEy;
+        O[3][g] = b0; O[4][g] = b1; O[5][g] = b2;
         O[0][g] = sE[0][e]; O[1][g] = sE[1][e]; O[2][g] = sE[2][e];
+#pragma unroll
+        for (int k = 0; k < 3; k++) G<JT>(D.J[po][k])[g] = JT(0);
+        if (D.rE[0]) {
+            // recording a tape slot: E^n, B^n of this step
+            G<R>(D.rE[0])[g] = sE[0][e]; G<R>(D.rE[1])[g] = sE[1][e]; G<R>(D.rE[2])[g] = sE[2][e];
+            G<R>(D.rB[0])[g] = b0; G<R>(D.rB[1])[g] = b1; G<R>(D.rB[2])[g] = b2;
+        }
     }
 }
 
@@ -607,7 +625,7 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
 // axis 0 / 1: filter taps along x / y.  blockIdx.y selects the component.
 template <int AXIS, class R>
 __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                                   int src_sel, int dst_sel)
+                                                   int src_sel, int dst_sel, int par)
 {
     const int inst = work[blockIdx.x].x;
     const InstDesc &D = Dt[inst];
@@ -615,7 +633,7 @@ __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ 
     const int comp = blockIdx.y;
     if (cell >= D.ncell) return;
     const R *src;
-    if (src_sel == 0) src = comp < 3 ? (const R *)D.E[comp] : (const R *)D.B[comp - 3];
+    if (src_sel == 0) src = comp < 3 ? (const R *)D.E[par][comp] : (const R *)D.B[par][comp - 3];
     else if (src_sel == 1) src = (const R *)D.T1[comp];
     else src = (const R *)D.T2[comp];
     R *dst;
@@ -665,7 +683,7 @@ __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ 
 #define SEEN_TX PIC_SEEN_TX
 template <class R, int SEEN_TZ, int HZ, int HX>
 __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                                 int commit)
+                                                 int par)
 {
     typedef typename JOf<R>::T JT;
     static_assert(SEEN_TX == 64, "one lane per column");
@@ -698,7 +716,7 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     } else {
         for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)D.tx[i];
     }
-    const void *sp = commit ? D.T1[comp] : (comp < 3 ? D.E[comp] : D.B[comp - 3]);
+    const void *sp = comp < 3 ? D.E[par][comp] : D.B[par][comp - 3];
     const gp<const R> src = G<R>(sp);
     // staging: column a = lane, column b = 64 + lane for the right halo (lane < 2 hx)
     const bool hasb = lane < 2 * hx;
@@ -756,15 +774,7 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
         } else {
             for (int k = 0; k <= 2 * hx; k++) acc += tx[k] * m[k];
         }
-        const int g = gz * nx + gx;
-        dst[g] = acc;
-        if (commit) {
-            const R v = win[(zz + hz) * wx + lane + hx];
-            G<R>(comp < 3 ? D.E[comp] : D.B[comp - 3])[g] = v;
-            if (comp < 3) G<JT>(D.J[comp])[g] = JT(0);
-            void *rec = comp < 3 ? D.rE[comp] : D.rB[comp - 3];
-            if (rec) G<R>(rec)[g] = v;
-        }
+        dst[gz * nx + gx] = acc;
     }
 }
 
@@ -910,7 +920,8 @@ __device__ __forceinline__ void block_sum_to(double v, double *dst)
 // chunks (all of one instance or split where instances change)
 template <class R>
 __global__ void __launch_bounds__(256) k_energy(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                                int nwork, double *out, int out_stride, const int *pos, int cap)
+                                                int nwork, double *out, int out_stride, const int *pos, int cap,
+                                                int par)
 {
     const int it0 = blockIdx.x * ENERGY_ITEMS, it1 = min(nwork, it0 + ENERGY_ITEMS);
     int inst = work[it0].x;
@@ -933,8 +944,8 @@ __global__ void __launch_bounds__(256) k_energy(const InstDesc *__restrict__ Dt,
         const int cell = work[it].y * PIC_FIELD_CHUNK + threadIdx.x;
         if (cell < D.ncell) {
             for (int c = 0; c < 3; c++) {
-                const double e = (double)G<R>((const void *)D.E[c])[cell];
-                const double b = (double)G<R>((const void *)D.B[c])[cell];
+                const double e = (double)G<R>((const void *)D.E[par][c])[cell];
+                const double b = (double)G<R>((const void *)D.B[par][c])[cell];
                 v[c] += e * e;
                 v[3 + c] += b * b;
                 if (!isfinite(e) || !isfinite(b)) bad = 1.0;
@@ -1055,7 +1066,8 @@ __global__ void __launch_bounds__(256) k_rho(const InstDesc *__restrict__ Dt, co
 // Gauss residual after a step: div E^n - dt div J^{n+1/2} - (rho^{n+1} - rho^0)
 #define GAUSS_ITEMS 16
 template <int DIM, class R>
-__global__ void __launch_bounds__(256) k_gauss(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int nwork)
+__global__ void __launch_bounds__(256) k_gauss(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int nwork,
+                                               int par)
 {
     typedef typename JOf<R>::T JT;
     __shared__ double red[8];
@@ -1070,8 +1082,8 @@ __global__ void __launch_bounds__(256) k_gauss(const InstDesc *__restrict__ Dt, 
             const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
             const int im = (i == 0 ? nx - 1 : i - 1) + (j + k * ny) * nx;
             const int km = i + (j + (k == 0 ? nz - 1 : k - 1) * ny) * nx;
-            const R *E0 = (const R *)D.E[0], *E1 = (const R *)D.E[1], *E2 = (const R *)D.E[2];
-            const JT *J0 = (const JT *)D.J[0], *J1 = (const JT *)D.J[1], *J2 = (const JT *)D.J[2];
+            const R *E0 = (const R *)D.E[par][0], *E1 = (const R *)D.E[par][1], *E2 = (const R *)D.E[par][2];
+            const JT *J0 = (const JT *)D.J[par][0], *J1 = (const JT *)D.J[par][1], *J2 = (const JT *)D.J[par][2];
             double divE = ((double)E0[cell] - (double)E0[im]) / D.d[0] + ((double)E2[cell] - (double)E2[km]) / D.d[2];
             double divJ = (jreal(J0[cell], D.jq) - jreal(J0[im], D.jq)) / D.d[0] +
                           (jreal(J2[cell], D.jq) - jreal(J2[km], D.jq)) / D.d[2];
@@ -1116,13 +1128,13 @@ __global__ void k_trace_tick(int *pos, double *trace, int n_inst, int cap)
 }
 
 template <class R>
-__global__ void __launch_bounds__(256) k_clear_j(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
+__global__ void __launch_bounds__(256) k_clear_j(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int par)
 {
     typedef typename JOf<R>::T JT;
     const InstDesc &D = Dt[work[blockIdx.x].x];
     const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
     if (cell >= D.ncell) return;
-    for (int c = 0; c < 3; c++) ((JT *)D.J[c])[cell] = JT(0);
+    for (int c = 0; c < 3; c++) ((JT *)D.J[par][c])[cell] = JT(0);
 }
 
 inline int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : -1; }
@@ -1137,12 +1149,12 @@ inline int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : -1; }
 template <class R> void launch_yee_2d(const LaunchCtx &c, const int2 *ywork, int nywork)
 {
     const dim3 g(nywork), b(PIC_FIELD_CHUNK);
-    if (c.yee_tz == 4) k_yee_2d<R, 4><<<g, b, 0, c.stream>>>(c.desc, ywork);
+    if (c.yee_tz == 4) k_yee_2d<R, 4><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);
     else if constexpr (sizeof(R) == 4) {
-        if (c.yee_tz == 16) k_yee_2d<R, 16><<<g, b, 0, c.stream>>>(c.desc, ywork);
-        else k_yee_2d<R, 8><<<g, b, 0, c.stream>>>(c.desc, ywork);
+        if (c.yee_tz == 16) k_yee_2d<R, 16><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);
+        else k_yee_2d<R, 8><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);
     } else {
-        k_yee_2d<R, 8><<<g, b, 0, c.stream>>>(c.desc, ywork);   // 16 rows of doubles exceed the LDS
+        k_yee_2d<R, 8><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);   // 16 rows of doubles exceed the LDS
     }
 }
 
@@ -1154,9 +1166,10 @@ int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywo
         if (c.dims == 2) {
             launch_yee_2d<R>(c, ywork, nywork);
         } else {
-            k_yee_b<3, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
-            k_yee_e<3, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
-            k_yee_b<3, R><<<g, b, 0, c.stream>>>(c.desc, fwork);
+            const int p = c.par, q = c.par ^ 1;
+            k_yee_b<3, R><<<g, b, 0, c.stream>>>(c.desc, fwork, p, p, q);
+            k_yee_e<3, R><<<g, b, 0, c.stream>>>(c.desc, fwork, p, q);
+            k_yee_b<3, R><<<g, b, 0, c.stream>>>(c.desc, fwork, q, q, q);
         }
     });
     return hip_ok(hipGetLastError());
@@ -1169,39 +1182,38 @@ size_t seen_smem_bytes(int fp32, int tz)
 }
 
 template <class R, int TZ>
-void launch_seen_2d_tz(const LaunchCtx &c, const int2 *swork, int nswork, int commit)
+void launch_seen_2d_tz(const LaunchCtx &c, const int2 *swork, int nswork)
 {
     const size_t sm = seen_smem_bytes(c.fp32, TZ);
     const dim3 g(nswork, 6), b(PIC_FIELD_CHUNK);
     // half-widths: correction of degree 4 with four filter passes (8, 4);
     // filter alone (4, 4); correction alone (4, 0); neither (0, 0)
-    if (c.hz == 8 && c.hx == 4) k_seen_2d<R, TZ, 8, 4><<<g, b, sm, c.stream>>>(c.desc, swork, commit);
-    else if (c.hz == 4 && c.hx == 4) k_seen_2d<R, TZ, 4, 4><<<g, b, sm, c.stream>>>(c.desc, swork, commit);
-    else if (c.hz == 4 && c.hx == 0) k_seen_2d<R, TZ, 4, 0><<<g, b, sm, c.stream>>>(c.desc, swork, commit);
-    else if (c.hz == 0 && c.hx == 0) k_seen_2d<R, TZ, 0, 0><<<g, b, sm, c.stream>>>(c.desc, swork, commit);
-    else k_seen_2d<R, TZ, -1, -1><<<g, b, sm, c.stream>>>(c.desc, swork, commit);
+    if (c.hz == 8 && c.hx == 4) k_seen_2d<R, TZ, 8, 4><<<g, b, sm, c.stream>>>(c.desc, swork, c.par);
+    else if (c.hz == 4 && c.hx == 4) k_seen_2d<R, TZ, 4, 4><<<g, b, sm, c.stream>>>(c.desc, swork, c.par);
+    else if (c.hz == 4 && c.hx == 0) k_seen_2d<R, TZ, 4, 0><<<g, b, sm, c.stream>>>(c.desc, swork, c.par);
+    else if (c.hz == 0 && c.hx == 0) k_seen_2d<R, TZ, 0, 0><<<g, b, sm, c.stream>>>(c.desc, swork, c.par);
+    else k_seen_2d<R, TZ, -1, -1><<<g, b, sm, c.stream>>>(c.desc, swork, c.par);
 }
 
 template <class R>
-void launch_seen_2d(const LaunchCtx &c, const int2 *swork, int nswork, int commit)
+void launch_seen_2d(const LaunchCtx &c, const int2 *swork, int nswork)
 {
-    if (c.seen_tz == 8) launch_seen_2d_tz<R, 8>(c, swork, nswork, commit);
-    else if (c.seen_tz == 16) launch_seen_2d_tz<R, 16>(c, swork, nswork, commit);
-    else launch_seen_2d_tz<R, 32>(c, swork, nswork, commit);
+    if (c.seen_tz == 8) launch_seen_2d_tz<R, 8>(c, swork, nswork);
+    else if (c.seen_tz == 16) launch_seen_2d_tz<R, 16>(c, swork, nswork);
+    else launch_seen_2d_tz<R, 32>(c, swork, nswork);
 }
 
-int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork, int commit)
+int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork)
 {
     if (nwork <= 0) return 0;
     dim3 g(nwork, 6), b(PIC_FIELD_CHUNK);
     DISPATCH_R(c.fp32, {
         if (c.dims == 2) {
-            const size_t sm = seen_smem_bytes(c.fp32, c.seen_tz);
-            launch_seen_2d<R>(c, swork, nswork, commit);
+            launch_seen_2d<R>(c, swork, nswork);
         } else {
-            k_seen_pass<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1);
-            k_seen_pass<0, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2);
-            k_seen_pass<1, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 2, 0);
+            k_seen_pass<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1, c.par);
+            k_seen_pass<0, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
+            k_seen_pass<1, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 2, 0, c.par);
         }
     });
     return hip_ok(hipGetLastError());
@@ -1221,9 +1233,9 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
     const int wm[3] = {wmax[0], wy, wmax[2]};
     const size_t smem = particle_smem_bytes(c.dims, c.fp32, wm);
     dim3 g(grid > 0 ? grid : nwork), b(block);
-#define PK(D_, L_, P_) k_particles<D_, L_, R, P_><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2])
-#define PK24(K_, PF_) K_<2, 1, float, 24, PF_><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2])
-#define PKR(L_, P_) k_particles<2, L_, R, P_, false, true><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2])
+#define PK(D_, L_, P_) k_particles<D_, L_, R, P_><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2], c.par)
+#define PK24(K_, PF_) K_<2, 1, float, 24, PF_><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2], c.par)
+#define PKR(L_, P_) k_particles<2, L_, R, P_, false, true><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2], c.par)
     DISPATCH_R(c.fp32, {
         if (c.record && c.dims == 2) {
             // recording a tape slot (2D reverse sweep)
@@ -1280,7 +1292,7 @@ int launch_resort(const LaunchCtx &c, const int2 *cwork, int ncwork, int inst0, 
 int launch_clear_j(const LaunchCtx &c, const int2 *fwork, int nwork)
 {
     if (nwork <= 0) return 0;
-    DISPATCH_R(c.fp32, { k_clear_j<R><<<dim3(nwork), dim3(PIC_FIELD_CHUNK), 0, c.stream>>>(c.desc, fwork); });
+    DISPATCH_R(c.fp32, { k_clear_j<R><<<dim3(nwork), dim3(PIC_FIELD_CHUNK), 0, c.stream>>>(c.desc, fwork, c.par); });
     return hip_ok(hipGetLastError());
 }
 
@@ -1313,10 +1325,10 @@ int launch_diag(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *p
     dim3 b(PIC_FIELD_CHUNK);
     DISPATCH_R(c.fp32, {
         k_energy<R><<<dim3((nfwork + ENERGY_ITEMS - 1) / ENERGY_ITEMS), b, 0, c.stream>>>(c.desc, fwork, nfwork,
-                                                                                      nullptr, 0, nullptr, 1);
+                                                                                      nullptr, 0, nullptr, 1, c.par);
         const dim3 gg((nfwork + GAUSS_ITEMS - 1) / GAUSS_ITEMS);
-        if (c.dims == 2) k_gauss<2, R><<<gg, b, 0, c.stream>>>(c.desc, fwork, nfwork);
-        else k_gauss<3, R><<<gg, b, 0, c.stream>>>(c.desc, fwork, nfwork);
+        if (c.dims == 2) k_gauss<2, R><<<gg, b, 0, c.stream>>>(c.desc, fwork, nfwork, c.par);
+        else k_gauss<3, R><<<gg, b, 0, c.stream>>>(c.desc, fwork, nfwork, c.par);
     });
     return hip_ok(hipGetLastError());
 }
@@ -1327,7 +1339,7 @@ int launch_trace_rows(const LaunchCtx &c, const int2 *fwork, int nfwork, int *po
     if (nfwork <= 0 || cap <= 0) return 0;
     DISPATCH_R(c.fp32, {
         k_energy<R><<<dim3((nfwork + ENERGY_ITEMS - 1) / ENERGY_ITEMS), dim3(PIC_FIELD_CHUNK), 0, c.stream>>>(
-            c.desc, fwork, nfwork, trace, n_inst, pos, cap);
+            c.desc, fwork, nfwork, trace, n_inst, pos, cap, c.par);
     });
     k_trace_tick<<<dim3(1), dim3(256), 0, c.stream>>>(pos, trace, n_inst, cap);
     return hip_ok(hipGetLastError());
