@@ -175,9 +175,6 @@ int pic_set_schedule(pic_state *st, int sched, int use_graph);
  *   "particle_block" threads per particle workgroup: 256 or 512
  *   "particle_waves4" 1: 2D linear float particle kernel built for four waves
  *                    per SIMD (register cap 128)
- *   "fused_fields"   1 (default): 2D FP32 runs the Yee update and the seen
- *                    fields as one kernel when the correction is quartic and the
- *                    filter has four passes; 0: two kernels
  *   "particle_prefetch" 1: 2D linear float particle kernel loads the next
  *                    particle's state while pushing the current one
  * Returns PIC_EINVAL for an unknown name or value.  Drops captured graphs. */

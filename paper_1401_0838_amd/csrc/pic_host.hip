@@ -181,7 +181,7 @@ struct pic_state {
     InstDesc *d_desc = nullptr;
     int2 *fwork = nullptr, *pwork = nullptr, *cwork = nullptr, *swork = nullptr, *ywork = nullptr, *awork = nullptr;
     int nfwork = 0, npwork = 0, ncwork = 0, nswork = 0, nywork = 0, nawork = 0;
-    std::vector<Range> frange, prange, crange, srange, yrange, arange;
+    std::vector<Range> frange, prange, crange, srange, yrange;
     int wmax[3] = {1, 1, 1};
     int block = 256;
     int sched = PIC_SCHED_BATCHED, use_graph = 1;
@@ -189,7 +189,6 @@ struct pic_state {
     int yee_tz = 8, seen_tz = 16;    // 2D field-kernel tile heights (tunable)
     int waves4 = 0;                  // particle kernel capped at four waves per SIMD (tunable)
     int prefetch = 0;                // particle kernel loads one particle ahead (tunable)
-    int fused = 1;                   // 2D FP32: Yee and seen fields in one kernel (tunable)
     // captured graphs, one per parity of the state they start from
     hipGraphExec_t gexec_k[2] = {nullptr, nullptr}, gexec_1[2] = {nullptr, nullptr};
     int parity = 0;                  // which set of E, B, J planes is current
@@ -225,7 +224,6 @@ LaunchCtx ctx(const pic_state *s)
     c.prefetch = s->prefetch;
     c.any_resort = s->any_resort;
     c.par = s->parity;
-    c.fused = s->fused;
     if (!s->desc.empty()) {
         const InstDesc &d0 = s->desc[0];
         c.hz = d0.hz; c.hx = d0.hx; c.hzf = d0.hzf; c.psi_deg = d0.psi_deg;
@@ -577,7 +575,6 @@ int build_worklists(pic_state *s)
 {
     std::vector<int2> fw, pw, cw, sw, yw, aw;
     s->frange.clear(); s->prange.clear(); s->crange.clear(); s->srange.clear(); s->yrange.clear();
-    s->arange.clear();
     const int ytz = yee_tz_eff(s->yee_tz, s->fp32), stz = s->seen_tz;
     std::vector<int> ord;
     for (int i = 0; i < s->n_inst; i++) {
@@ -601,11 +598,8 @@ int build_worklists(pic_state *s)
         for (int k = 0; k < nyt; k++) yw.push_back(make_int2(i, k));
         yr.n = (int)yw.size() - yr.off;
         s->yrange.push_back(yr);
-        Range ar{(int)aw.size(), 0};
         const int nat = ((D.n[0] + PIC_SEEN_TX - 1) / PIC_SEEN_TX) * ((D.n[2] + PIC_ADJ_TZ - 1) / PIC_ADJ_TZ);
         for (int k = 0; k < nat; k++) aw.push_back(make_int2(i, k));
-        ar.n = (int)aw.size() - ar.off;
-        s->arange.push_back(ar);
         Range c{(int)cw.size(), 0};
         for (long long k = 0; k < (D.np + PIC_PART_CHUNK - 1) / PIC_PART_CHUNK; k++) cw.push_back(make_int2(i, (int)k));
         c.n = (int)cw.size() - c.off;
@@ -630,14 +624,12 @@ int build_worklists(pic_state *s)
 
 // one step's launches for instances [i0, i0 + ni) using the given work ranges
 // one step's launches; the Yee launch reads the current parity, the rest see the new one
-int enqueue_step_range(pic_state *s, const Range &f, const Range &sr, const Range &yr, const Range &ar,
-                       const Range &p, bool trace)
+int enqueue_step_range(pic_state *s, const Range &f, const Range &sr, const Range &yr, const Range &p, bool trace)
 {
     LaunchCtx c = ctx(s);
-    if (launch_fields(c, s->fwork + f.off, f.n, s->ywork + yr.off, yr.n, s->swork + sr.off, sr.n, s->awork + ar.off,
-                      ar.n))
-        return fail(PIC_EHIP, "field launch");
+    if (launch_yee(c, s->fwork + f.off, f.n, s->ywork + yr.off, yr.n)) return fail(PIC_EHIP, "yee launch");
     c.par ^= 1;
+    if (launch_seen(c, s->fwork + f.off, f.n, s->swork + sr.off, sr.n)) return fail(PIC_EHIP, "seen launch");
     if (launch_particles(c, s->pwork + p.off, p.n, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particle launch");
     (void)trace;
     return PIC_OK;
@@ -647,12 +639,11 @@ int enqueue_step(pic_state *s)
 {
     if (s->sched == PIC_SCHED_BATCHED) {
         int rc = enqueue_step_range(s, Range{0, s->nfwork}, Range{0, s->nswork}, Range{0, s->nywork},
-                                    Range{0, s->nawork}, Range{0, s->npwork}, false);
+                                    Range{0, s->npwork}, false);
         if (rc) return rc;
     } else {
         for (int i = 0; i < s->n_inst; i++) {
-            int rc = enqueue_step_range(s, s->frange[i], s->srange[i], s->yrange[i], s->arange[i], s->prange[i],
-                                        false);
+            int rc = enqueue_step_range(s, s->frange[i], s->srange[i], s->yrange[i], s->prange[i], false);
             if (rc) return rc;
         }
     }
@@ -1002,9 +993,6 @@ extern "C" int pic_set_option(pic_state *s, const char *name, int value)
     } else if (n == "particle_waves4") {
         if (value != 0 && value != 1) return fail(PIC_EINVAL, "particle_waves4 must be 0 or 1");
         s->waves4 = value;
-    } else if (n == "fused_fields") {
-        if (value != 0 && value != 1) return fail(PIC_EINVAL, "fused_fields must be 0 or 1");
-        s->fused = value;
     } else if (n == "particle_prefetch") {
         if (value != 0 && value != 1) return fail(PIC_EINVAL, "particle_prefetch must be 0 or 1");
         s->prefetch = value;
@@ -1025,7 +1013,6 @@ extern "C" int pic_get_option(pic_state *s, const char *name, int *value)
     else if (n == "particle_block") *value = s->block;
     else if (n == "particle_waves4") *value = s->waves4;
     else if (n == "particle_prefetch") *value = s->prefetch;
-    else if (n == "fused_fields") *value = s->fused;
     else return fail(PIC_EINVAL, "unknown option " + n);
     return PIC_OK;
 }
@@ -1180,15 +1167,11 @@ extern "C" int pic_profile(pic_state *s, int nsteps, pic_timing_t *out)
         const Range f{0, s->nfwork}, p{0, s->npwork};
         HIP_TRY(hipEventRecord(ev[0], s->stream));
         c.par = s->parity;
-        // the fused 2D kernel counts as the Yee part; its seen part is then zero
-        if (fused_fields_ok(c) ? launch_fields(c, s->fwork, f.n, s->ywork, s->nywork, s->swork, s->nswork, s->awork,
-                                               s->nawork)
-                               : launch_yee(c, s->fwork, f.n, s->ywork, s->nywork))
-            return fail(PIC_EHIP, "yee");
+        if (launch_yee(c, s->fwork, f.n, s->ywork, s->nywork)) return fail(PIC_EHIP, "yee");
         c.par ^= 1;
         s->parity ^= 1;
         HIP_TRY(hipEventRecord(ev[1], s->stream));
-        if (!fused_fields_ok(c) && launch_seen(c, s->fwork, f.n, s->swork, s->nswork)) return fail(PIC_EHIP, "seen");
+        if (launch_seen(c, s->fwork, f.n, s->swork, s->nswork)) return fail(PIC_EHIP, "seen");
         HIP_TRY(hipEventRecord(ev[2], s->stream));
         if (launch_particles(c, s->pwork, p.n, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particles");
         HIP_TRY(hipEventRecord(ev[3], s->stream));
@@ -1246,9 +1229,9 @@ int gradient_preconditions(pic_state *s)
 int forward_step_eager(pic_state *s)
 {
     LaunchCtx live = ctx(s);
-    if (launch_fields(live, s->fwork, s->nfwork, s->ywork, s->nywork, s->swork, s->nswork, s->awork, s->nawork))
-        return fail(PIC_EHIP, "fields");
+    if (launch_yee(live, s->fwork, s->nfwork, s->ywork, s->nywork)) return fail(PIC_EHIP, "yee");
     live.par ^= 1;
+    if (launch_seen(live, s->fwork, s->nfwork, s->swork, s->nswork)) return fail(PIC_EHIP, "seen");
     if (launch_particles(live, s->pwork, s->npwork, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particles");
     s->parity ^= 1;
     return PIC_OK;
@@ -1267,11 +1250,11 @@ int enqueue_segment(pic_state *s, int m)
             rec.desc = s->d_rec_desc + (size_t)slot * s->n_inst;
             rec.record = 1;
             rec.par = s->parity;
-            if (launch_fields(rec, s->fwork, s->nfwork, s->ywork, s->nywork, s->swork, s->nswork, s->awork,
-                              s->nawork))
-                return fail(PIC_EHIP, "recompute");
+            if (launch_yee(rec, s->fwork, s->nfwork, s->ywork, s->nywork)) return fail(PIC_EHIP, "recompute");
             rec.par ^= 1;
-            if (launch_particles(rec, s->pwork, s->npwork, 0, s->block, s->wmax)) return fail(PIC_EHIP, "recompute");
+            if (launch_seen(rec, s->fwork, s->nfwork, s->swork, s->nswork) ||
+                launch_particles(rec, s->pwork, s->npwork, 0, s->block, s->wmax))
+                return fail(PIC_EHIP, "recompute");
             s->parity ^= 1;
             continue;
         }

@@ -106,19 +106,9 @@ struct LaunchCtx {
     // Yee launch reads set par and writes set par ^ 1; every later launch of the
     // step is given the new parity
     int par = 0;
-    int fused = 1;                    // allow the fused 2D field kernel
 };
 
 int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork);
-// the Yee update and the seen fields of a step (c.par = the set being read):
-// one fused kernel in 2D FP32 when the stencils have the usual widths, else the
-// Yee launch followed by the seen launch
-int launch_fields(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork, const int2 *swork,
-                  int nswork, const int2 *awork, int nawork);
-inline bool fused_fields_ok(const LaunchCtx &c)
-{
-    return c.fused && c.dims == 2 && c.fp32 && c.hz == 8 && c.hx == 4;
-}
 #define PIC_YEE_TX 64
 int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork);
 size_t seen_smem_bytes(int fp32, int tz);

@@ -620,176 +620,6 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
     }
 }
 
-// ------------------------------------------------- fused 2D field update
-// Yee update and the fields as seen by the particles for one 64 x TZ tile in
-// one kernel.  The Yee update runs in LDS on the tile grown by the seen
-// stencil's half-widths (HX, HZ) so that the seen stencils need nothing from
-// other blocks; the window of inputs is one cell wider on the low side and two
-// on the high side.  Reads E, B, J of set par, writes E, B of set par ^ 1 and
-// clears that set's J on the tile, then writes the six seen components.
-template <class R, int TZ, int HZ, int HX>
-__global__ void __launch_bounds__(256) k_fields_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                                   int par)
-{
-    typedef typename JOf<R>::T JT;
-    constexpr int TX = 64;
-    constexpr int MX = TX + 2 * HX;                                 // columns of the z pass
-    constexpr int WX = MX + 3, WZ = TZ + 2 * HZ + 3, WN = WX * WZ;  // origin (x0 - HX - 1, z0 - HZ - 1)
-    constexpr int NTZ = 2 * HZ + 1, NTX = 2 * HX + 1;
-    __shared__ R sE[3][WN], sB[3][WN], sJ[3][WN];
-    __shared__ R mid[TZ * MX];
-    const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
-    const InstDesc &D = Dt[inst];
-    const int nx = D.n[0], nz = D.n[2];
-    const int ntx = (nx + TX - 1) / TX;
-    const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-    const gp<const R> E[3] = {G<R>((const void *)D.E[par][0]), G<R>((const void *)D.E[par][1]),
-                              G<R>((const void *)D.E[par][2])};
-    const gp<const R> B[3] = {G<R>((const void *)D.B[par][0]), G<R>((const void *)D.B[par][1]),
-                              G<R>((const void *)D.B[par][2])};
-    const gp<const JT> J[3] = {G<JT>((const void *)D.J[par][0]), G<JT>((const void *)D.J[par][1]),
-                               G<JT>((const void *)D.J[par][2])};
-    const double jq = D.jq, jb[3] = {D.jbg[0], D.jbg[1], D.jbg[2]};
-    // staging: waves own rows, lanes own columns (lane, and 64 + lane for the rest)
-    const bool hasb = lane < WX - TX;
-    const int gxa = wrap_near(x0 - HX - 1 + lane, nx);
-    const int gxb = hasb ? wrap_near(x0 - HX - 1 + TX + lane, nx) : gxa;
-    constexpr int RU = 2;
-    for (int r0 = wave; r0 < WZ; r0 += RU * nwave) {
-        R ve[RU][2][3], vb[RU][2][3];
-        JT vj[RU][2][3];
-#pragma unroll
-        for (int u = 0; u < RU; u++) {
-            const int row = min(r0 + u * nwave, WZ - 1);
-            const int base = wrap_near(z0 - HZ - 1 + row, nz) * nx;
-#pragma unroll
-            for (int h = 0; h < 2; h++) {
-                const int g = base + (h ? gxb : gxa);
-#pragma unroll
-                for (int k = 0; k < 3; k++) { ve[u][h][k] = E[k][g]; vb[u][h][k] = B[k][g]; vj[u][h][k] = J[k][g]; }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < RU; u++) {
-            const int row = r0 + u * nwave;
-            if (row >= WZ) continue;
-#pragma unroll
-            for (int h = 0; h < 2; h++) {
-                if (h == 1 && !hasb) continue;
-                const int c = row * WX + (h ? TX : 0) + lane;
-#pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    sE[k][c] = ve[u][h][k];
-                    sB[k][c] = vb[u][h][k];
-                    sJ[k][c] = (R)(jreal(vj[u][h][k], jq) + jb[k]);
-                }
-            }
-        }
-    }
-    __syncthreads();
-    const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
-    // B^{n-1/2} on local [0, WX - 1) x [0, WZ - 1): forward differences of E^{n-1}
-    for (int lz = wave; lz < WZ - 1; lz += nwave) {
-#pragma unroll
-        for (int hh = 0; hh < 2; hh++) {
-            const int lx = hh ? TX + lane : lane;
-            if (lx >= WX - 1) break;
-            const int e = lz * WX + lx, ex = e + 1, ez = e + WX;
-            const R dzEy = (sE[1][ez] - sE[1][e]) * idz, dzEx = (sE[0][ez] - sE[0][e]) * idz;
-            const R dxEz = (sE[2][ex] - sE[2][e]) * idx, dxEy = (sE[1][ex] - sE[1][e]) * idx;
-            sB[0][e] -= h * (-dzEy);
-            sB[1][e] -= h * (dzEx - dxEz);
-            sB[2][e] -= h * dxEy;
-        }
-    }
-    __syncthreads();
-    // E^n on local [1, WX - 1) x [1, WZ - 1): backward differences of B^{n-1/2}
-    for (int lz = 1 + wave; lz < WZ - 1; lz += nwave) {
-#pragma unroll
-        for (int hh = 0; hh < 2; hh++) {
-            const int lx = hh ? TX + 1 + lane : 1 + lane;
-            if (lx >= WX - 1) break;
-            const int e = lz * WX + lx, exm = e - 1, ezm = e - WX;
-            const R dzBy = (sB[1][e] - sB[1][ezm]) * idz, dzBx = (sB[0][e] - sB[0][ezm]) * idz;
-            const R dxBz = (sB[2][e] - sB[2][exm]) * idx, dxBy = (sB[1][e] - sB[1][exm]) * idx;
-            sE[0][e] += dt * (-dzBy - sJ[0][e]);
-            sE[1][e] += dt * (dzBx - dxBz - sJ[1][e]);
-            sE[2][e] += dt * (dxBy - sJ[2][e]);
-        }
-    }
-    __syncthreads();
-    // B^n on local [1, WX - 2) x [1, WZ - 2) (in place: only E^n neighbours are read);
-    // the tile's own cells go to set par ^ 1
-    const int po = par ^ 1;
-    for (int lz = 1 + wave; lz < WZ - 2; lz += nwave) {
-#pragma unroll
-        for (int hh = 0; hh < 2; hh++) {
-            const int lx = hh ? TX + 1 + lane : 1 + lane;
-            if (lx >= WX - 2) break;
-            const int e = lz * WX + lx, ex = e + 1, ez = e + WX;
-            const R dzEy = (sE[1][ez] - sE[1][e]) * idz, dzEx = (sE[0][ez] - sE[0][e]) * idz;
-            const R dxEz = (sE[2][ex] - sE[2][e]) * idx, dxEy = (sE[1][ex] - sE[1][e]) * idx;
-            const R b0 = sB[0][e] - h * (-dzEy), b1 = sB[1][e] - h * (dzEx - dxEz), b2 = sB[2][e] - h * dxEy;
-            sB[0][e] = b0; sB[1][e] = b1; sB[2][e] = b2;
-            const int ox = lx - 1 - HX, oz = lz - 1 - HZ;   // tile coordinates
-            if (ox >= 0 && ox < TX && oz >= 0 && oz < TZ) {
-                const int gx = x0 + ox, gz = z0 + oz;
-                if (gx < nx && gz < nz) {
-                    const int g = gz * nx + gx;
-                    G<R>(D.E[po][0])[g] = sE[0][e]; G<R>(D.E[po][1])[g] = sE[1][e]; G<R>(D.E[po][2])[g] = sE[2][e];
-                    G<R>(D.B[po][0])[g] = b0; G<R>(D.B[po][1])[g] = b1; G<R>(D.B[po][2])[g] = b2;
-#pragma unroll
-                    for (int k = 0; k < 3; k++) G<JT>(D.J[po][k])[g] = JT(0);
-                    if (D.rE[0]) {
-                        // recording a tape slot: E^n, B^n of this step
-                        G<R>(D.rE[0])[g] = sE[0][e]; G<R>(D.rE[1])[g] = sE[1][e]; G<R>(D.rE[2])[g] = sE[2][e];
-                        G<R>(D.rB[0])[g] = b0; G<R>(D.rB[1])[g] = b1; G<R>(D.rB[2])[g] = b2;
-                    }
-                }
-            }
-        }
-    }
-    __syncthreads();
-    // fields as seen by the particles: combined z stencil into mid, then x filter
-    R rx[NTX];
-#pragma unroll
-    for (int k = 0; k < NTX; k++) rx[k] = (R)D.tx[k];
-    const int gx = x0 + lane;
-    for (int comp = 0; comp < 6; comp++) {
-        const double *tzs = D.tz[comp < 2 ? 0 : 1];
-        R rz[NTZ];
-#pragma unroll
-        for (int k = 0; k < NTZ; k++) rz[k] = (R)tzs[k];
-        const R *pl = comp < 3 ? sE[comp] : sB[comp - 3];
-        for (int zz = wave; zz < TZ; zz += nwave) {
-#pragma unroll
-            for (int hh = 0; hh < 2; hh++) {
-                const int xx = hh ? TX + lane : lane;
-                if (xx >= MX) break;
-                const R *w = pl + (1 + zz) * WX + 1 + xx;
-                R acc = R(0);
-#pragma unroll
-                for (int k = 0; k < NTZ; k++) acc += rz[k] * w[k * WX];
-                mid[zz * MX + xx] = acc;
-            }
-        }
-        __syncthreads();
-        gp<R> dst = G<R>(comp < 3 ? D.Et[comp] : D.Bt[comp - 3]);
-        if (gx < nx)
-            for (int zz = wave; zz < TZ; zz += nwave) {
-                const int gz = z0 + zz;
-                if (gz >= nz) break;
-                const R *m = mid + zz * MX + lane;
-                R acc = R(0);
-#pragma unroll
-                for (int k = 0; k < NTX; k++) acc += rx[k] * m[k];
-                dst[gz * nx + gx] = acc;
-            }
-        __syncthreads();
-    }
-}
-
 // ------------------------------------------------------ seen-field passes
 // axis 2: combined z taps (tz[0] for Ex, Ey; tz[1] for Ez, Bx, By, Bz)
 // axis 0 / 1: filter taps along x / y.  blockIdx.y selects the component.
@@ -1343,21 +1173,6 @@ int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywo
         }
     });
     return hip_ok(hipGetLastError());
-}
-
-int launch_fields(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork, const int2 *swork,
-                  int nswork, const int2 *awork, int nawork)
-{
-    if (nwork <= 0) return 0;
-    if (fused_fields_ok(c)) {
-        // one kernel per 64 x 8 tile (the awork list)
-        k_fields_2d<float, PIC_ADJ_TZ, 8, 4><<<dim3(nawork), dim3(256), 0, c.stream>>>(c.desc, awork, c.par);
-        return hip_ok(hipGetLastError());
-    }
-    if (launch_yee(c, fwork, nwork, ywork, nywork)) return -1;
-    LaunchCtx n = c;
-    n.par ^= 1;
-    return launch_seen(n, fwork, nwork, swork, nswork);
 }
 
 size_t seen_smem_bytes(int fp32, int tz)

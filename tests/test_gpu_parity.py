@@ -226,28 +226,6 @@ def test_fp32_bitwise_deterministic_and_graph_equals_eager():
         assert np.array_equal(out[0][k], out[2][k])
 
 
-def test_fused_field_kernel_equals_two_kernels():
-    """The fused 2D FP32 field kernel (Yee + seen fields in one pass) gives the
-    same bits as the separate Yee and seen kernels, on grids that are not
-    multiples of the 64 x 8 tile and in a batch."""
-    wls = [pi.workload("beam2d_512", n=(96, 40), ppc=2, tag="a"),
-           pi.workload("beam2d_512", n=(200, 13), ppc=2, alpha=0.4, tag="b"),
-           pi.workload("beam2d_512", n=(64, 64), ppc=2, alpha=0.6, tag="c")]
-    parts = [pi.load_beam(2, w["n"], w["ppc"], w["gamma"], 1e-3, 40 + i) for i, w in enumerate(wls)]
-    out = []
-    for fused in (1, 0):
-        sim = _sim(wls, parts, precision="fp32")
-        sim.set_option("fused_fields", fused)
-        assert sim.get_option("fused_fields") == fused
-        sim.step(13)
-        out.append([(sim.fields("E", i), sim.fields("B", i), sim.fields("J", i), sim.fields("Et", i),
-                     sim.fields("Bt", i)) for i in range(3)])
-        sim.close()
-    for a, b in zip(*out):
-        for x, y in zip(a, b):
-            assert np.array_equal(x, y)
-
-
 def test_batched_instances_match_own_oracle_and_plain():
     wls = [pi.workload("beam2d_512", n=(64, 32), alpha=0.35, ppc=4, precision="fp64", tag="a"),
            pi.workload("beam2d_512", n=(32, 96), alpha=0.55, ppc=4, gamma=10.0, precision="fp64", tag="b"),
