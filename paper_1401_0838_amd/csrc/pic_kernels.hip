@@ -115,9 +115,15 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
     }
     JT *tag = nullptr;
     if constexpr (DIM == 2) {
+        // A particle that stays in its cell along an axis has old and new shapes on
+        // the first L + 1 of the L + 2 nodes, so everything it deposits on the last
+        // node of that axis is zero.  When no lane of the wave changed cell along
+        // the axis, the wave skips those updates (whole LDS atomics, not just lanes).
+        const bool lastx = __ballot(dc[0] != 0) != 0, lastz = __ballot(dc[2] != 0) != 0;
         // J_x: running sum along x
 #pragma unroll
         for (int k = 0; k < L + 2; k++) {
+            if (k == L + 1 && !lastz) break;
             R tz = S0[2][k] + R(0.5) * DS[2][k];
             R acc = R(0);
 #pragma unroll
@@ -129,6 +135,7 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
         // J_z: running sum along z
 #pragma unroll
         for (int i = 0; i < L + 2; i++) {
+            if (i == L + 1 && !lastx) break;
             R tx = S0[0][i] + R(0.5) * DS[0][i];
             R acc = R(0);
 #pragma unroll
@@ -141,11 +148,13 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
         const R cy = cy2d * u[1] * ig;
 #pragma unroll
         for (int k = 0; k < L + 2; k++) {
+            if (k == L + 1 && !lastz) break;
             const R s1z = S0[2][k] + DS[2][k];
             const R az = cy * (R(1.0 / 3.0) * S0[2][k] + R(1.0 / 6.0) * s1z);
             const R bz = cy * (R(1.0 / 6.0) * S0[2][k] + R(1.0 / 3.0) * s1z);
 #pragma unroll
             for (int i = 0; i < L + 2; i++) {
+                if (i == L + 1 && !lastx) break;
                 const R wy = S0[0][i] * az + (S0[0][i] + DS[0][i]) * bz;
                 W.add(1, base[0] + i, 0, base[2] + k, jcvt(wy, tag));
             }
