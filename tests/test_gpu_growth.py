@@ -97,3 +97,44 @@ def test_growth_rate_full_size_fp32_vs_fp64():
         _say("512 alpha %.1f: Gamma fp32 %.6e fp64 %.6e (Gamma dt %.2e) window %s W %.3e..%.3e"
              % (alpha, g32, g64, g64 * alpha, win, W64[10], W64[-1]))
         assert _close(g32, g64, W64, alpha)
+
+
+def test_batched_scan_growth_rates_fp32_vs_fp64():
+    """The 64-instance scan (uneven grids, alpha in [0.3, 0.7], gamma in {10, 50,
+    130}, 8 ppc), 1000 steps in one batched run per precision: every instance's
+    FP32 growth rate equals its FP64 one (same bar).  Candidates whose
+    correction breaks down are skipped and counted."""
+    from paper_1401_0838_amd import _lib as L
+    from paper_1401_0838_amd.sim import Simulation
+    wls, parts, skipped = [], [], 0
+    for cand in pi.batched_candidates(0):
+        rc, _, _ = L.pic_psi_coeffs(L.PIC_GALERKIN, cand["alpha"], 4)
+        if rc != L.PIC_OK:
+            skipped += 1
+            continue
+        wls.append(cand)
+        parts.append(pi.load_beam(2, cand["n"], cand["ppc"], cand["gamma"], cand["sigma"], cand["seeds"][0]))
+        if len(wls) == 64:
+            break
+    nsteps = wls[0]["steps"]
+    traces, wkin = {}, {}
+    for prec in ("fp32", "fp64"):
+        sim = Simulation(wls, parts, precision=prec, trace_capacity=nsteps)
+        wkin[prec] = [sim.diag(i)["Wkin"] for i in range(len(wls))]
+        sim.step(nsteps)
+        traces[prec] = []
+        for i in range(len(wls)):
+            tr = sim.trace(i)
+            traces[prec].append(tr[:, 0] + tr[:, 1] + tr[:, 3] + tr[:, 4])
+        sim.close()
+    _say("batched scan: %d instances, %d candidates skipped for a broken-down correction" % (len(wls), skipped))
+    bad = []
+    for i, w in enumerate(wls):
+        W32, W64 = traces["fp32"][i], traces["fp64"][i]
+        assert len(W32) == nsteps and len(W64) == nsteps
+        g32, _ = gfit.growth_rate(W32, w["alpha"], wkin["fp64"][i])
+        g64, _ = gfit.growth_rate(W64, w["alpha"], wkin["fp64"][i])
+        if not _close(g32, g64, W64, w["alpha"]):
+            bad.append((i, w["n"], w["alpha"], w["gamma"], g32, g64))
+    _say("  mismatches: %s" % bad)
+    assert not bad
