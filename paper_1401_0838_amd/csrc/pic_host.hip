@@ -224,6 +224,7 @@ LaunchCtx ctx(const pic_state *s)
     c.prefetch = s->prefetch;
     c.any_resort = s->any_resort;
     c.par = s->parity;
+    c.single = s->n_inst == 1;
     if (!s->desc.empty()) {
         const InstDesc &d0 = s->desc[0];
         c.hz = d0.hz; c.hx = d0.hx; c.hzf = d0.hzf; c.psi_deg = d0.psi_deg;
@@ -567,8 +568,7 @@ void tile_order(int nt, std::vector<int> &out)
         for (int t = 0; t < nt; t++) out[t] = t;
         return;
     }
-    const int per = nt / 8;
-    for (int b = 0; b < nt; b++) out[b] = (b % 8) * per + b / 8;
+    for (int b = 0; b < nt; b++) out[b] = xcd_tile(b, nt);
 }
 
 int build_worklists(pic_state *s)

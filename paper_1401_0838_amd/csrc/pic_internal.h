@@ -90,6 +90,13 @@ struct InstDesc {
     void *roff[3], *ru[3];
 };
 
+// Launch slot b -> tile in XCD-aware order: slot b runs on XCD b % 8, and each
+// XCD gets a contiguous run of tiles (whose guard cells then share its L2)
+__host__ __device__ inline int xcd_tile(int b, int nt)
+{
+    return (nt % 8 != 0) ? b : (b % 8) * (nt / 8) + b / 8;
+}
+
 // launch helpers implemented in pic_kernels.hip
 struct LaunchCtx {
     const InstDesc *desc;       // device table
@@ -106,6 +113,7 @@ struct LaunchCtx {
     // Yee launch reads set par and writes set par ^ 1; every later launch of the
     // step is given the new parity
     int par = 0;
+    int single = 0;                   // one instance: 2D field kernels take tile = block index
 };
 
 int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork);

@@ -223,8 +223,10 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
     const int tid = threadIdx.x, bs = blockDim.x;
 
     for (int item = blockIdx.x; item < nwork; item += gridDim.x) {
-        const int inst = work[item].x, tile = work[item].y;
+        // work == nullptr: one instance, slot -> tile in the host's XCD order
+        const int inst = work ? work[item].x : 0;
         const InstDesc &D = Dt[inst];
+        const int tile = work ? work[item].y : xcd_tile(item, D.ntiles);
         const int p0 = D.tstart[tile], p1 = D.tstart[tile + 1];
         if (p1 <= p0) continue;
         int lo[3], ext[3], o[3], wn[3];
@@ -521,7 +523,8 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
     // waves own rows, lanes own columns (lane, and 64 + lane for the last three)
     constexpr int WX = TX + 3, WZ = TZ + 3, WN = WX * WZ;
     __shared__ R sE[3][WN], sB[3][WN], sJ[3][WN];
-    const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
+    // work == nullptr: one instance, block b is tile b (saves a dependent load)
+    const int inst = work ? work[blockIdx.x].x : 0, t = work ? work[blockIdx.x].y : (int)blockIdx.x;
     const InstDesc &D = Dt[inst];
     const int nx = D.n[0], nz = D.n[2];
     const int ntx = (nx + TX - 1) / TX;
@@ -697,7 +700,8 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     typedef typename JOf<R>::T JT;
     static_assert(SEEN_TX == 64, "one lane per column");
     extern __shared__ __align__(16) unsigned char smem[];
-    const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
+    // work == nullptr: one instance, block b is tile b (saves a dependent load)
+    const int inst = work ? work[blockIdx.x].x : 0, t = work ? work[blockIdx.x].y : (int)blockIdx.x;
     const int comp = blockIdx.y;
     const InstDesc &D = Dt[inst];
     const int nx = D.n[0], nz = D.n[2];
@@ -731,7 +735,7 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     const bool hasb = lane < 2 * hx;
     const int gxa = wrap_near(x0 - hx + lane, nx);
     const int gxb = hasb ? wrap_near(x0 - hx + SEEN_TX + lane, nx) : gxa;
-    constexpr int U = 4;
+    constexpr int U = 8;
     for (int r0 = wave; r0 < wz; r0 += U * nwave) {
         R va[U], vb[U];
 #pragma unroll
@@ -1158,6 +1162,7 @@ inline int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : -1; }
 template <class R> void launch_yee_2d(const LaunchCtx &c, const int2 *ywork, int nywork)
 {
     const dim3 g(nywork), b(PIC_FIELD_CHUNK);
+    if (c.single) ywork = nullptr;
     if (c.yee_tz == 4) k_yee_2d<R, 4><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);
     else if constexpr (sizeof(R) == 4) {
         if (c.yee_tz == 16) k_yee_2d<R, 16><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);
@@ -1195,6 +1200,7 @@ void launch_seen_2d_tz(const LaunchCtx &c, const int2 *swork, int nswork)
 {
     const size_t sm = seen_smem_bytes(c.fp32, TZ);
     const dim3 g(nswork, 6), b(PIC_FIELD_CHUNK);
+    if (c.single) swork = nullptr;
     // half-widths: correction of degree 4 with four filter passes (8, 4);
     // filter alone (4, 4); correction alone (4, 0); neither (0, 0)
     if (c.hz == 8 && c.hx == 4) k_seen_2d<R, TZ, 8, 4><<<g, b, sm, c.stream>>>(c.desc, swork, c.par);
@@ -1242,9 +1248,9 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
     const int wm[3] = {wmax[0], wy, wmax[2]};
     const size_t smem = particle_smem_bytes(c.dims, c.fp32, wm);
     dim3 g(grid > 0 ? grid : nwork), b(block);
-#define PK(D_, L_, P_) k_particles<D_, L_, R, P_><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2], c.par)
-#define PK24(K_, PF_) K_<2, 1, float, 24, PF_><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2], c.par)
-#define PKR(L_, P_) k_particles<2, L_, R, P_, false, true><<<g, b, smem, c.stream>>>(c.desc, pwork, nwork, wm[0], wm[1], wm[2], c.par)
+#define PK(D_, L_, P_) k_particles<D_, L_, R, P_><<<g, b, smem, c.stream>>>(c.desc, c.single ? nullptr : pwork, nwork, wm[0], wm[1], wm[2], c.par)
+#define PK24(K_, PF_) K_<2, 1, float, 24, PF_><<<g, b, smem, c.stream>>>(c.desc, c.single ? nullptr : pwork, nwork, wm[0], wm[1], wm[2], c.par)
+#define PKR(L_, P_) k_particles<2, L_, R, P_, false, true><<<g, b, smem, c.stream>>>(c.desc, c.single ? nullptr : pwork, nwork, wm[0], wm[1], wm[2], c.par)
     DISPATCH_R(c.fp32, {
         if (c.record && c.dims == 2) {
             // recording a tape slot (2D reverse sweep)
