@@ -295,3 +295,34 @@ def test_full_size_512_fp32_parity_10_steps():
     d = sim.diag()
     assert d["gauss_linf"] < 1e-5 * d["rho_max"]
     sim.close()
+
+
+def test_tuning_knobs_leave_fp32_results_bitwise_unchanged():
+    """Tile shape, workgroup size, field tile heights, re-sort period and the
+    particle-kernel variants change only the schedule: with the fixed-point
+    current every FP32 result is bitwise the same.  Also runs the autotuner on a
+    short candidate list."""
+    from paper_1401_0838_amd import tune
+    wl = pi.workload("beam2d_512", n=(128, 96), ppc=4)
+    x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], 1e-3, 11)
+    runs = [dict(), dict(tile=(8, 1, 8)), dict(tile=(32, 1, 16), block=512),
+            dict(opts={"yee_tile_z": 4, "seen_tile_z": 32, "resort_every": 5}),
+            dict(opts={"particle_waves4": 1}), dict(opts={"particle_prefetch": 1}),
+            dict(opts={"particle_waves4": 1, "particle_prefetch": 1})]
+    ref = None
+    for r in runs:
+        sim = _sim(wl, (x, u), precision="fp32", tile=r.get("tile"), block=r.get("block", 0))
+        for k, v in r.get("opts", {}).items():
+            sim.set_option(k, v)
+        sim.step(21)
+        got = (sim.fields("E"), sim.fields("B"), sim.fields("J"))
+        sim.close()
+        if ref is None:
+            ref = got
+        else:
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), r
+    best = tune.tune(wl, (x, u), precision="fp32", steps=3, warmup=1, cache=None,
+                     candidates=[((16, 1, 16), 256), ((8, 1, 8), 256)])
+    _say("tuner picked %s" % best)
+    assert best["tile"] in ([16, 1, 16], [8, 1, 8]) and best["step_ms"] > 0
