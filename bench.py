@@ -136,6 +136,29 @@ def beam3d_block(steps, warmup):
             "gauss_linf_rel": d["gauss_linf"] / max(d["rho_max"], 1e-300), "slow_tiles": d["slow_tiles"]}
 
 
+def fp64_block(steps, warmup):
+    """The 512x512, 16 ppc step in FP64 (44 B of particle state, FP64 current):
+    particle-steps/s and the particle kernel's HBM fraction."""
+    import pic_inputs as pi
+    from paper_1401_0838_amd.sim import Simulation
+    wl = pi.workload("beam2d_512", alpha=0.5, precision="fp64")
+    x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], wl["sigma"], 0)
+    sim = Simulation(wl, (x, u), precision="fp64")
+    n_part, n_cells = x.shape[0], wl["n"][0] * wl["n"][1]
+    sim.step(warmup)
+    sim.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    dt = time.perf_counter() - t0
+    prof = sim.profile(5)
+    sim.close()
+    pk = particle_kernel_bytes(n_part, n_cells, word=8, state_bytes=44)
+    return {"particle_steps_per_s": n_part * steps / dt, "ms_per_step": 1e3 * dt / steps,
+            "particle_kernel_ms": prof["particle_ms"],
+            "particle_kernel_hbm_frac": pk / (prof["particle_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def adjoint_block():
     """256x256, 8 ppc, 200 steps, checkpoints every 20 (FP32): backward (recompute +
     reverse sweep) time over forward time."""
@@ -192,9 +215,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost ratio")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D cubic case")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 512x512 case")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling HBM counters)")
-    ap.add_argument("--only", choices=("batched", "adjoint", "3d"),
+    ap.add_argument("--only", choices=("batched", "adjoint", "3d", "fp64"),
                     help="run one secondary block alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -202,7 +226,7 @@ def main():
         return
     if args.only:
         blk = {"batched": lambda: batched_block(max(20, args.steps // 4), 5), "adjoint": adjoint_block,
-               "3d": lambda: beam3d_block(20, 3)}[args.only]()
+               "3d": lambda: beam3d_block(20, 3), "fp64": lambda: fp64_block(50, 5)}[args.only]()
         print(json.dumps({args.only: blk}), flush=True)
         return
     if args.gpus != 1:
@@ -274,6 +298,8 @@ def main():
         out["adjoint"] = adjoint_block()
     if not args.no_3d:
         out["beam3d"] = beam3d_block(20, 3)
+    if not args.no_fp64:
+        out["beam2d_fp64"] = fp64_block(50, 5)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, x, u, args.cpu_steps)
     print(json.dumps(out), flush=True)
