@@ -117,8 +117,10 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
     if constexpr (DIM == 2) {
         // A particle that stays in its cell along an axis has old and new shapes on
         // the first L + 1 of the L + 2 nodes, so everything it deposits on the last
-        // node of that axis is zero.  When no lane of the wave changed cell along
-        // the axis, the wave skips those updates (whole LDS atomics, not just lanes).
+        // node of that axis is zero, and so is the running sum of its shape change
+        // up to node L (the changes sum to zero; the sum left at node L is rounding
+        // only).  When no lane of the wave changed cell along the axis, the wave
+        // skips those updates (whole LDS atomics, not just lanes).
         const bool lastx = __ballot(dc[0] != 0) != 0, lastz = __ballot(dc[2] != 0) != 0;
         // J_x: running sum along x
 #pragma unroll
@@ -128,6 +130,7 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
             R acc = R(0);
 #pragma unroll
             for (int i = 0; i < L + 1; i++) {
+                if (i == L && !lastx) break;
                 acc += DS[0][i] * tz;
                 W.add(0, base[0] + i, 0, base[2] + k, jcvt(cdep[0] * acc, tag));
             }
@@ -140,6 +143,7 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
             R acc = R(0);
 #pragma unroll
             for (int k = 0; k < L + 1; k++) {
+                if (k == L && !lastz) break;
                 acc += DS[2][k] * tx;
                 W.add(2, base[0] + i, 0, base[2] + k, jcvt(cdep[2] * acc, tag));
             }
