@@ -132,7 +132,10 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
             for (int i = 0; i < L + 1; i++) {
                 if (i == L && !lastx) break;
                 acc += DS[0][i] * tz;
-                W.add(0, base[0] + i, 0, base[2] + k, jcvt(cdep[0] * acc, tag));
+                // exactly zero (not a rounding residue) for a particle that kept its
+                // x cell, so the result does not depend on which lanes share a wave
+                const R v = (i == L && dc[0] == 0) ? R(0) : cdep[0] * acc;
+                W.add(0, base[0] + i, 0, base[2] + k, jcvt(v, tag));
             }
         }
         // J_z: running sum along z
@@ -145,7 +148,8 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
             for (int k = 0; k < L + 1; k++) {
                 if (k == L && !lastz) break;
                 acc += DS[2][k] * tx;
-                W.add(2, base[0] + i, 0, base[2] + k, jcvt(cdep[2] * acc, tag));
+                const R v = (k == L && dc[2] == 0) ? R(0) : cdep[2] * acc;
+                W.add(2, base[0] + i, 0, base[2] + k, jcvt(v, tag));
             }
         }
         // J_y: out of plane, with v_y.  W_y = S0x (S0z/3 + S1z/6) + S1x (S0z/6 + S1z/3)
