@@ -643,10 +643,12 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
 // ------------------------------------------------------ seen-field passes
 // axis 2: combined z taps (tz[0] for Ex, Ey; tz[1] for Ez, Bx, By, Bz)
 // axis 0 / 1: filter taps along x / y.  blockIdx.y selects the component.
-template <int AXIS, class R>
+template <int AXIS, class R, int HW>
 __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                    int src_sel, int dst_sel, int par)
 {
+    // HW >= 0: the pass's half-width at compile time (taps unrolled, all loads
+    // of a cell in flight at once); -1: read it from the descriptor
     const int inst = work[blockIdx.x].x;
     const InstDesc &D = Dt[inst];
     const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
@@ -663,34 +665,22 @@ __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ 
     int i, j, k;
     cell_ijk<R>(D, cell, i, j, k);
     const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
+    const double *tap = AXIS == 2 ? D.tz[comp < 2 ? 0 : 1] : (AXIS == 0 ? D.tx : D.ty);
+    const int h = HW >= 0 ? HW : (AXIS == 2 ? D.hz : (AXIS == 0 ? D.hx : D.hy));
+    // index along the axis, its extent and the stride between neighbours
+    const int q = AXIS == 2 ? k : (AXIS == 0 ? i : j);
+    const int nq = AXIS == 2 ? nz : (AXIS == 0 ? nx : ny);
+    const int stride = AXIS == 2 ? nx * ny : (AXIS == 0 ? 1 : nx);
+    const int base = cell - q * stride;
+    const gp<const R> s = G<R>((const void *)src);
     R acc = R(0);
-    if constexpr (AXIS == 2) {
-        const double *tap = D.tz[comp < 2 ? 0 : 1];
-        const int h = D.hz;
-        const int rowoff = i + j * nx, plane = nx * ny;
-        for (int t = -h; t <= h; t++) {
-            int kk = k + t;
-            kk = ((kk % nz) + nz) % nz;
-            acc += (R)tap[t + h] * src[rowoff + kk * plane];
-        }
-    } else if constexpr (AXIS == 0) {
-        const int h = D.hx;
-        const int rowbase = cell - i;
-        for (int t = -h; t <= h; t++) {
-            int ii = i + t;
-            ii = ((ii % nx) + nx) % nx;
-            acc += (R)D.tx[t + h] * src[rowbase + ii];
-        }
+    if constexpr (HW >= 0) {
+#pragma unroll
+        for (int t = -HW; t <= HW; t++) acc += (R)tap[t + HW] * s[base + wrap_near(q + t, nq) * stride];
     } else {
-        const int h = D.hy;
-        const int base = i + k * ny * nx;
-        for (int t = -h; t <= h; t++) {
-            int jj = j + t;
-            jj = ((jj % ny) + ny) % ny;
-            acc += (R)D.ty[t + h] * src[base + jj * nx];
-        }
+        for (int t = -h; t <= h; t++) acc += (R)tap[t + h] * s[base + wrap_near(q + t, nq) * stride];
     }
-    dst[cell] = acc;
+    G<R>(dst)[cell] = acc;
 }
 
 // 2D fields as seen by the particles in one kernel: a (64 x SZ) output tile of
@@ -1234,9 +1224,16 @@ int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *sw
         if (c.dims == 2) {
             launch_seen_2d<R>(c, swork, nswork);
         } else {
-            k_seen_pass<2, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1, c.par);
-            k_seen_pass<0, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
-            k_seen_pass<1, R><<<g, b, 0, c.stream>>>(c.desc, fwork, 2, 0, c.par);
+            // usual widths: correction of degree 4 with four filter passes (z 8, x and y 4)
+            if (c.hz == 8 && c.hx == 4) {
+                k_seen_pass<2, R, 8><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1, c.par);
+                k_seen_pass<0, R, 4><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
+                k_seen_pass<1, R, 4><<<g, b, 0, c.stream>>>(c.desc, fwork, 2, 0, c.par);
+            } else {
+                k_seen_pass<2, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1, c.par);
+                k_seen_pass<0, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
+                k_seen_pass<1, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 2, 0, c.par);
+            }
         }
     });
     return hip_ok(hipGetLastError());
