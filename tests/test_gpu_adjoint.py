@@ -96,7 +96,7 @@ def test_adjoint_fp32_close_to_oracle_and_autograd():
     p = torch.tensor(a0[None, :], dtype=torch.float64, requires_grad=True)
     W = AG.wperp(p, make2, nsteps)
     W.sum().backward()
-    assert abs(float(W[0]) - L) <= 1e-6 * L
+    assert abs(float(W.detach()[0]) - L) <= 1e-6 * L
     assert np.allclose(p.grad.numpy()[0], g, rtol=1e-6, atol=0)
 
 
