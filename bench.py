@@ -230,8 +230,9 @@ def main():
         print(json.dumps({args.only: blk}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the domain would shard along z with halo exchange; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(batches would shard by instance; one large domain along z in slabs, with guard-layer "
+              "exchange of E, B and J and particle migration across slab faces)", file=sys.stderr)
         sys.exit(2)
 
     import torch

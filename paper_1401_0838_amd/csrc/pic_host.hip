@@ -795,7 +795,7 @@ extern "C" const char *pic_strerror(int code)
     case PIC_EHIP: return "HIP runtime error";
     case PIC_ENONFINITE: return "non-finite value in fields or particles";
     case PIC_EPARTICLE: return "particle moved a full cell or more in one step";
-    case PIC_EUNSUPPORTED: return "configuration not supported by this build";
+    case PIC_EUNSUPPORTED: return "configuration not supported by this library";
     case PIC_ESTATE: return "invalid state";
     }
     return "unknown error";
