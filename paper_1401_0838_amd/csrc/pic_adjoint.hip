@@ -437,15 +437,13 @@ __global__ void __launch_bounds__(256) k_adj_particles(const InstDesc *__restric
 }
 
 // ------------------------------------------------------------ stencil passes
-enum { PL_EB = 0, PL_T1 = 1, PL_T2 = 2, PL_SEEN = 3, PL_LSEEN = 4, PL_LEB = 5 };
+enum { PL_T1 = 1, PL_T2 = 2, PL_LSEEN = 4, PL_LEB = 5 };
 
 __device__ __forceinline__ void *plane(const InstDesc &D, int sel, int comp)
 {
     switch (sel) {
-    case PL_EB: return comp < 3 ? D.E[0][comp] : D.B[0][comp - 3];
     case PL_T1: return D.T1[comp];
     case PL_T2: return D.T2[comp];
-    case PL_SEEN: return comp < 3 ? D.Et[comp] : D.Bt[comp - 3];
     case PL_LSEEN: return comp < 3 ? D.lEt[comp] : D.lBt[comp - 3];
     default: return comp < 3 ? D.lE[comp] : D.lB[comp - 3];
     }

@@ -125,7 +125,6 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
 size_t particle_smem_bytes(int dims, int fp32, const int wmax[3]);
 // clear_any: the last re-sort launch of a step clears the shared pending word
 int launch_resort(const LaunchCtx &c, const int2 *cwork, int ncwork, int n_inst_first, int n_inst, int clear_any);
-int launch_clear_j(const LaunchCtx &c, const int2 *fwork, int nwork);
 int launch_rho(const LaunchCtx &c, const int2 *pwork, int npwork, const int2 *fwork, int nfwork, const int wmax[3],
                int to_rho0);
 int launch_diag(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *pwork, int npwork, const int wmax[3]);

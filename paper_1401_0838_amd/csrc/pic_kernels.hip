@@ -1138,15 +1138,6 @@ __global__ void k_trace_tick(int *pos, double *trace, int n_inst, int cap)
     if (threadIdx.x == 0) *pos += 1;
 }
 
-template <class R>
-__global__ void __launch_bounds__(256) k_clear_j(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int par)
-{
-    typedef typename JOf<R>::T JT;
-    const InstDesc &D = Dt[work[blockIdx.x].x];
-    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
-    if (cell >= D.ncell) return;
-    for (int c = 0; c < 3; c++) ((JT *)D.J[par][c])[cell] = JT(0);
-}
 
 inline int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : -1; }
 
@@ -1309,12 +1300,6 @@ int launch_resort(const LaunchCtx &c, const int2 *cwork, int ncwork, int inst0, 
     return hip_ok(hipGetLastError());
 }
 
-int launch_clear_j(const LaunchCtx &c, const int2 *fwork, int nwork)
-{
-    if (nwork <= 0) return 0;
-    DISPATCH_R(c.fp32, { k_clear_j<R><<<dim3(nwork), dim3(PIC_FIELD_CHUNK), 0, c.stream>>>(c.desc, fwork, c.par); });
-    return hip_ok(hipGetLastError());
-}
 
 int launch_rho(const LaunchCtx &c, const int2 *pwork, int npwork, const int2 *fwork, int nfwork, const int wmax[3],
                int to_rho0)
