@@ -168,49 +168,66 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
             }
         }
     } else {
+        // same skips as in 2D, per axis (see above)
+        const bool last[3] = {__ballot(dc[0] != 0) != 0, __ballot(dc[1] != 0) != 0, __ballot(dc[2] != 0) != 0};
         // J_x (outer loops stay rolled for cubic shapes to bound register use)
         constexpr int UNROLL_OUTER = L == 1 ? L + 2 : 1;
 #pragma unroll UNROLL_OUTER
-        for (int kz = 0; kz < L + 2; kz++)
+        for (int kz = 0; kz < L + 2; kz++) {
+            if (kz == L + 1 && !last[2]) break;
 #pragma unroll
             for (int ky = 0; ky < L + 2; ky++) {
+                if (ky == L + 1 && !last[1]) break;
                 R tr = S0[1][ky] * S0[2][kz] + R(0.5) * DS[1][ky] * S0[2][kz] + R(0.5) * S0[1][ky] * DS[2][kz]
                      + R(1.0 / 3.0) * DS[1][ky] * DS[2][kz];
                 R acc = R(0);
 #pragma unroll
                 for (int kx = 0; kx < L + 1; kx++) {
+                    if (kx == L && !last[0]) break;
                     acc += DS[0][kx] * tr;
-                    W.add(0, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(cdep[0] * acc, tag));
+                    const R v = (kx == L && dc[0] == 0) ? R(0) : cdep[0] * acc;
+                    W.add(0, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(v, tag));
                 }
             }
+        }
         // J_y
 #pragma unroll UNROLL_OUTER
-        for (int kz = 0; kz < L + 2; kz++)
+        for (int kz = 0; kz < L + 2; kz++) {
+            if (kz == L + 1 && !last[2]) break;
 #pragma unroll
             for (int kx = 0; kx < L + 2; kx++) {
+                if (kx == L + 1 && !last[0]) break;
                 R tr = S0[2][kz] * S0[0][kx] + R(0.5) * DS[2][kz] * S0[0][kx] + R(0.5) * S0[2][kz] * DS[0][kx]
                      + R(1.0 / 3.0) * DS[2][kz] * DS[0][kx];
                 R acc = R(0);
 #pragma unroll
                 for (int ky = 0; ky < L + 1; ky++) {
+                    if (ky == L && !last[1]) break;
                     acc += DS[1][ky] * tr;
-                    W.add(1, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(cdep[1] * acc, tag));
+                    const R v = (ky == L && dc[1] == 0) ? R(0) : cdep[1] * acc;
+                    W.add(1, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(v, tag));
                 }
             }
+        }
         // J_z
 #pragma unroll UNROLL_OUTER
-        for (int ky = 0; ky < L + 2; ky++)
+        for (int ky = 0; ky < L + 2; ky++) {
+            if (ky == L + 1 && !last[1]) break;
 #pragma unroll
             for (int kx = 0; kx < L + 2; kx++) {
+                if (kx == L + 1 && !last[0]) break;
                 R tr = S0[0][kx] * S0[1][ky] + R(0.5) * DS[0][kx] * S0[1][ky] + R(0.5) * S0[0][kx] * DS[1][ky]
                      + R(1.0 / 3.0) * DS[0][kx] * DS[1][ky];
                 R acc = R(0);
 #pragma unroll
                 for (int kz = 0; kz < L + 1; kz++) {
+                    if (kz == L && !last[2]) break;
                     acc += DS[2][kz] * tr;
-                    W.add(2, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(cdep[2] * acc, tag));
+                    const R v = (kz == L && dc[2] == 0) ? R(0) : cdep[2] * acc;
+                    W.add(2, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(v, tag));
                 }
             }
+        }
     }
 }
 
