@@ -98,7 +98,7 @@ typedef struct pic_config {
     int    ion_mode;          /* PIC_IONS_* */
     int    tile[3];           /* particle tile in cells along x, y, z (0 = default: 2D 16 x 16, or
                                  8 x 8 when the whole batch has fewer than 1024 default tiles;
-                                 3D 8x4x4 linear, 4x4x4 cubic) */
+                                 3D 8x4x4 linear, 8x2x4 cubic) */
     int    block;             /* threads per particle workgroup: 0 (default), 256 or 512 */
     int    trace_capacity;    /* steps of per-step field-energy trace kept on the device */
     int    adjoint_steps;     /* longest gradient run pic_wperp_gradient may do (0: none) */

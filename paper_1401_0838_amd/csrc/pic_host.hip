@@ -69,7 +69,8 @@ void tile_shape(const pic_config &c, int tile[3], int &slack)
         def[0] = 16; def[1] = 1; def[2] = 16;
         slack = 4;
     } else {
-        def[0] = c.shape_order == 1 ? 8 : 4; def[1] = c.shape_order == 1 ? 4 : 4; def[2] = c.shape_order == 1 ? 4 : 4;
+        // measured on the 128 x 128 x 256 cubic beam: 8 x 2 x 4 beat 4 x 4 x 4 by ~5 %
+        def[0] = 8; def[1] = c.shape_order == 1 ? 4 : 2; def[2] = 4;
         slack = 2;
     }
     for (int a = 0; a < 3; a++) {

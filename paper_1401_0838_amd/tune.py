@@ -16,7 +16,7 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.jso
 
 CANDIDATES_2D = [((16, 1, 16), 256), ((16, 1, 16), 512), ((32, 1, 16), 256), ((16, 1, 32), 256),
                  ((32, 1, 32), 512), ((8, 1, 16), 256), ((8, 1, 8), 256)]
-CANDIDATES_3D = [((8, 4, 4), 256), ((4, 4, 8), 256), ((8, 8, 4), 256), ((4, 4, 4), 256)]
+CANDIDATES_3D = [((8, 4, 4), 256), ((8, 2, 4), 256), ((4, 4, 8), 256), ((8, 8, 4), 256), ((4, 4, 4), 256)]
 
 
 def key(workloads, precision):
