@@ -93,3 +93,17 @@ def test_plan_grows_with_batch():
     one = L.pic_plan([_cfg()], [1024])
     two = L.pic_plan([_cfg(), _cfg(n=(32, 16))], [1024, 2048])
     assert two > one
+
+
+def test_default_tiles_shrink_only_for_small_batches():
+    """2D tiles default to 16 x 16 cells, or 8 x 8 when the whole batch has fewer
+    than 1024 of the 16 x 16 tiles; the arena that pic_plan sizes shows which."""
+    def plan(n, tile=None, count=1):
+        wl = pi.workload("beam2d_64_fp64", n=n)
+        cfgs = [make_config(wl, tile=tile) for _ in range(count)]
+        return L.pic_plan(cfgs, [n[0] * n[1] * 4] * count)
+    assert plan((256, 256)) == plan((256, 256), tile=(8, 1, 8))
+    assert plan((256, 256)) != plan((256, 256), tile=(16, 1, 16))
+    assert plan((512, 512)) == plan((512, 512), tile=(16, 1, 16))
+    assert plan((256, 256), count=4) == plan((256, 256), tile=(16, 1, 16), count=4)
+    assert plan((256, 256), count=3) == plan((256, 256), tile=(8, 1, 8), count=3)
