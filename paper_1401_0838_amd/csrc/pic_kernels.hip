@@ -1,10 +1,14 @@
 // HIP kernels (gfx950) of one FDTD-Esirkepov PIC step with the small-k_z
 // correction stencils of Godfrey & Vay (arXiv:1401.0838).
 //
-//   yee        three sweeps: B half step, E full step (reads J, then clears it),
-//              B half step (textbook Yee on the staggered mesh, Sec. 2)
-//   seen       separable passes: combined z stencil (Psi(S_z) of Sec. 2 composed
-//              with the z filter passes of Sec. 3 / Eq. 6), then x (then y)
+//   yee        B half step, E full step, B half step (textbook Yee on the
+//              staggered mesh, Sec. 2).  E, B and J alternate between two sets of
+//              planes: a step reads set p and writes set p ^ 1 (and clears that
+//              set's J for the deposit), so no plane is written while other
+//              workgroups read it as halo.  2D: one LDS tile kernel; 3D: sweeps.
+//   seen       combined z stencil (Psi(S_z) of Sec. 2 composed with the z filter
+//              passes of Sec. 3 / Eq. 6), then x (then y): one LDS tile kernel
+//              per component in 2D, separable passes in 3D
 //   particles  one workgroup per particle tile: stage the seen fields of the
 //              tile's bounding window (plus guard cells) in LDS, then per
 //              particle Galerkin gather (Eq. 3 scheme), Boris push, move and
