@@ -195,7 +195,35 @@ def test_empty_and_clumped_beams():
     d = sim.diag()
     _say("clumped %s resorts=%d slow=%d" % (errs, d["resorts"], d["slow_tiles"]))
     assert max(errs.values()) < 1e-10
+    assert d["resorts"] >= 1           # the clump outgrew its tiles' windows and was re-sorted
     sim.close()
+
+
+def test_resort_in_a_batch_keeps_parity():
+    """Two instances, one hot (re-sorted every 4 steps) and one cold, stepped as a
+    batch in FP32 and FP64: each matches its own oracle and only the hot one is
+    re-sorted."""
+    wl_hot = pi.workload("beam2d_64_fp64", n=(48, 32), correction=True, filter=pi.workloads.BINOMIAL4, tag="hot")
+    wl_cold = pi.workload("beam2d_64_fp64", n=(32, 48), correction=True, filter=pi.workloads.BINOMIAL4,
+                          alpha=0.4, tag="cold")
+    hot = pi.load_beam(2, wl_hot["n"], 4, 1.5, 0.9, 21)
+    cold = pi.load_beam(2, wl_cold["n"], 4, 130.0, 1e-6, 22)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
+        sim = _sim([wl_hot, wl_cold], [hot, cold], precision=prec)
+        sim.set_option("resort_every", 4)
+        sim.step(30)
+        for i, (w, (x, u)) in enumerate(((wl_hot, hot), (wl_cold, cold))):
+            ref = OracleSim(w, x, u)
+            ref.step(30)
+            e = max(_rel(sim.fields(k, i), getattr(ref, k)) for k in ("E", "B", "J"))
+            d = sim.diag(i)
+            _say("batch resort %s inst %d: err %.3e resorts %d slow %d" % (prec, i, e, d["resorts"], d["slow_tiles"]))
+            assert e < tol
+            if i == 0:
+                assert d["resorts"] >= 1
+            else:
+                assert d["resorts"] == 0
+        sim.close()
 
 
 def test_strong_instability_growth_fp64():
