@@ -40,9 +40,11 @@ extern "C" {
 #define PIC_OK            0
 #define PIC_EINVAL       -1   /* bad argument, shape or order */
 #define PIC_ECOURANT     -2   /* c dt >= 1 / sqrt(sum 1/d^2): Yee unstable */
-#define PIC_EPSI         -3   /* Psi_E or Psi_B <= 0 somewhere on s in [0,1], or
-                                 a singular interpolation system (Sec. 3 notes a
-                                 breakdown window of the determination) */
+#define PIC_EPSI         -3   /* Psi_B <= 0 somewhere on s in [0,1], Psi_E <= 0
+                                 on [0,1) (at s = 1 it may vanish to rounding,
+                                 as Eq. 5 does), or a singular interpolation
+                                 system (Sec. 3 notes a breakdown window of the
+                                 determination) */
 #define PIC_ENOMEM       -4   /* arena smaller than pic_plan() asked for */
 #define PIC_EHIP         -5   /* a HIP runtime call failed */
 #define PIC_ENONFINITE   -6   /* pic_diag found a NaN or Inf */
@@ -143,8 +145,10 @@ typedef struct pic_state pic_state;
  * (9 nodes, quartics, for deg = 4), with psi_b[0] = 1.  alpha = c dt / dz.
  * Solved in 113-bit binary floating point and rounded to double.  Returns
  * PIC_EPSI if the system is singular (except where the multiplier is
- * identically 1, which gives Psi_E = Psi_B = 1) or if either polynomial is
- * <= 0 somewhere on s in [0, 1].  Writes deg+1 doubles to each output. */
+ * identically 1, which gives Psi_E = Psi_B = 1), if Psi_B <= 0 somewhere on
+ * s in [0, 1], or if Psi_E <= 0 on [0, 1).  At s = 1 the Eq. 5 multiplier is
+ * exactly 0, so Psi_E(1) is accepted down to -1e-12 sum |psi_e[i]|.  Writes
+ * deg+1 doubles to each output. */
 int pic_psi_coeffs(int interp, double alpha, int deg, double *psi_e, double *psi_b);
 
 /* Size in bytes of the device arena for n_inst instances with the given

@@ -52,7 +52,10 @@ def forward_with_tape(sim, nsteps):
 
 def reverse(sim, tape, lE, lB, lJ, lx, lu):
     """Run the reverse sweep over `tape`; the adjoint arrays are updated in place.
-    Returns dL/da_j (length psi_deg + 1)."""
+    Returns dL/da_j (length psi_deg + 1).  The transposed gather covers the
+    Galerkin and Uniform schemes (samples at the Yee locations)."""
+    if sim.s.interp == 2:
+        raise NotImplementedError("reverse sweep of the momentum-conserving gather")
     lib = _lib()
     grad = np.zeros(max(1, sim.s.psi_deg + 1))
     lEt = np.zeros_like(sim.E)

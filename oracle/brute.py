@@ -130,6 +130,15 @@ class BruteSim:
                 vecs.append(np.ones(1))
                 continue
             c = pos[a] / self.d[a]
+            if self.interp == "momentum":
+                # weights w_n on the integer nodes, each node holding the mean of
+                # the Yee samples at n - 1/2 and n + 1/2 (array slots n - 1 and n):
+                # sample m then carries (w_m + w_{m+1}) / 2
+                w = spline(ords[a], _minimg(c - np.arange(n[a]), n[a]))
+                if stag[a]:
+                    w = 0.5 * (w + np.roll(w, -1))
+                vecs.append(w)
+                continue
             nodes = np.arange(n[a]) + 0.5 * stag[a]
             vecs.append(spline(ords[a], _minimg(c - nodes, n[a])))
         return vecs[2][:, None, None] * vecs[1][None, :, None] * vecs[0][None, None, :]

@@ -19,8 +19,9 @@
  *   1. Yee: B -= dt/2 curl E;  E += dt (curl B - J - Jbg);  B -= dt/2 curl E
  *   2. fields as seen by the particles: Psi series along z (Sec. 2), then the
  *      3-point digital filter passes along z, then x, then y (Sec. 3, Eq. 6)
- *   3. J = 0; per particle, in order: Galerkin gather (Eq. 3 scheme; Sec. 3
- *      on E_z's lowered spline order), Boris push, move, Esirkepov deposit
+ *   3. J = 0; per particle, in order: gather (Galerkin, Uniform or
+ *      momentum-conserving: the schemes of Eqs. 3, 4 and 5), Boris push, move,
+ *      Esirkepov deposit
  */
 #include <math.h>
 #include <stdlib.h>
@@ -31,7 +32,7 @@ typedef struct {
     int nx, ny, nz;           /* ny == 1 when dims == 2 */
     double dx, dy, dz, dt;
     int order;                /* charge shape order l (1 or 3) */
-    int interp;               /* 0 Galerkin, 1 Uniform */
+    int interp;               /* 0 Galerkin, 1 Uniform, 2 momentum-conserving */
     double q, m, w;           /* charge, mass, macro-particle weight */
     int correction;           /* 1: apply Psi_E / Psi_B */
     int psi_deg;              /* polynomial degree of Psi (<= 8) */
@@ -212,29 +213,50 @@ double o_spline(int o, double t)
 
 /* ------------------------------------------------------------ gather ----- */
 
-/* interpolate plane F with per-axis orders ord[] and staggering stag[] at the
- * point whose cell-unit coordinates are c[] (c[1] ignored in 2D) */
-static double interp(const OSim *s, const double *F, const int *stag, const int *ord, const double *c)
+/* value of plane F (staggering stag) on the Yee mesh, or, with avg, averaged
+ * onto the integer node (i, j, k): the mean over the Yee locations half a cell
+ * either side of the node along each staggered axis (y-invariant in 2D) */
+static double node_value(const OSim *s, const double *F, const int *stag, int avg, long i, long j, long k)
+{
+    if (!avg) return F[at(s, i, j, k)];
+    double sum = 0.0;
+    int cnt = 0;
+    for (long dk = -stag[2]; dk <= 0; dk++)
+        for (long dj = s->dims == 3 ? -stag[1] : 0; dj <= 0; dj++)
+            for (long di = -stag[0]; di <= 0; di++) {
+                sum += F[at(s, i + di, j + dj, k + dk)];
+                cnt++;
+            }
+    return sum / cnt;
+}
+
+/* interpolate plane F with per-axis orders ord[] at the point whose cell-unit
+ * coordinates are c[] (c[1] ignored in 2D).  The samples sit at F's own Yee
+ * locations (offsets stag[] / 2), or, with avg, at the integer nodes holding
+ * node_value averages. */
+static double interp(const OSim *s, const double *F, const int *stag, int avg, const int *ord, const double *c)
 {
     long lo[3], hi[3];
+    int pos[3];
+    for (int a = 0; a < 3; a++) pos[a] = avg ? 0 : stag[a];
     for (int a = 0; a < 3; a++) {
         if (a == 1 && s->dims == 2) { lo[a] = hi[a] = 0; continue; }
-        double shift = 0.5 * stag[a];
+        double shift = 0.5 * pos[a];
         double half = 0.5 * (ord[a] + 1);
         lo[a] = (long)floor(c[a] - shift - half);
         hi[a] = (long)floor(c[a] - shift + half);
     }
     double sum = 0.0;
     for (long k = lo[2]; k <= hi[2]; k++) {
-        double wz = o_spline(ord[2], c[2] - k - 0.5 * stag[2]);
+        double wz = o_spline(ord[2], c[2] - k - 0.5 * pos[2]);
         if (wz == 0.0) continue;
         for (long j = lo[1]; j <= hi[1]; j++) {
-            double wy = s->dims == 2 ? 1.0 : o_spline(ord[1], c[1] - j - 0.5 * stag[1]);
+            double wy = s->dims == 2 ? 1.0 : o_spline(ord[1], c[1] - j - 0.5 * pos[1]);
             if (wy == 0.0) continue;
             for (long i = lo[0]; i <= hi[0]; i++) {
-                double wx = o_spline(ord[0], c[0] - i - 0.5 * stag[0]);
+                double wx = o_spline(ord[0], c[0] - i - 0.5 * pos[0]);
                 if (wx == 0.0) continue;
-                sum += wx * wy * wz * F[at(s, i, j, k)];
+                sum += wx * wy * wz * node_value(s, F, stag, avg, i, j, k);
             }
         }
     }
@@ -243,7 +265,9 @@ static double interp(const OSim *s, const double *F, const int *stag, const int 
 
 /* Galerkin: order l on axes where the component sits on integer nodes and
  * l-1 where it sits half a cell off (Eq. 3 scheme; Sec. 3 for E_z).
- * Uniform: order l on every axis from each component's own location. */
+ * Uniform: order l on every axis from each component's own location (Eq. 4).
+ * Momentum-conserving: the fields are first averaged from the Yee mesh to the
+ * integer nodes, then interpolated with order l on every axis (Eq. 5). */
 static void comp_orders(const OSim *s, const int *stag, int *ord)
 {
     for (int a = 0; a < 3; a++) ord[a] = s->interp == 0 ? s->order - stag[a] : s->order;
@@ -252,12 +276,13 @@ static void comp_orders(const OSim *s, const int *stag, int *ord)
 void o_gather(const OSim *s, const double *pos, double *Eo, double *Bo)
 {
     double c[3] = {pos[0] / s->dx, s->dims == 3 ? pos[1] / s->dy : 0.0, pos[2] / s->dz};
+    const int avg = s->interp == 2;
     int ord[3];
     for (int comp = 0; comp < 3; comp++) {
         comp_orders(s, STAG_E[comp], ord);
-        Eo[comp] = interp(s, s->Et[comp], STAG_E[comp], ord, c);
+        Eo[comp] = interp(s, s->Et[comp], STAG_E[comp], avg, ord, c);
         comp_orders(s, STAG_B[comp], ord);
-        Bo[comp] = interp(s, s->Bt[comp], STAG_B[comp], ord, c);
+        Bo[comp] = interp(s, s->Bt[comp], STAG_B[comp], avg, ord, c);
     }
 }
 

@@ -94,10 +94,17 @@ def poly(c, s):
 
 
 def psi_positive(a, b, npts=4096):
-    """True when Psi_E and Psi_B stay > 0 on a uniform grid of [0, 1]
-    (the determination is taken to have broken down otherwise; Sec. 3)."""
+    """True when the determination has not broken down (Sec. 3): Psi_B > 0 on a
+    uniform grid of [0, 1] and Psi_E > 0 on [0, 1).  At s = 1 (k_z dz = pi)
+    the momentum-conserving multiplier of Eq. 5 is exactly zero (the cotangent
+    vanishes), so the interpolant's Psi_E(1) is zero up to rounding there;
+    Psi_E(1) only has to be >= -1e-12 sum |a_i|."""
+    tol = 1e-12 * sum(abs(v) for v in a)
     for i in range(npts + 1):
         s = i / npts
-        if poly(a, s) <= 0.0 or poly(b, s) <= 0.0:
+        pe, pb = poly(a, s), poly(b, s)
+        if pb <= 0.0:
+            return False
+        if pe <= 0.0 and not (i == npts and pe >= -tol):
             return False
     return True

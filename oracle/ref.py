@@ -92,7 +92,7 @@ class OracleSim:
         s.dx, s.dy, s.dz = dx, dy, dz
         s.dt = float(wl["alpha"]) * dz
         s.order = int(wl["order"])
-        s.interp = {"galerkin": 0, "uniform": 1}[wl.get("interp", "galerkin")]
+        s.interp = {"galerkin": 0, "uniform": 1, "momentum": 2}[wl.get("interp", "galerkin")]
         s.q, s.m = float(wl["q"]), float(wl["m"])
         if weight is None:
             n0 = wl["omega_p"] ** 2 * wl["m"] / wl["q"] ** 2

@@ -122,11 +122,8 @@ int validate(const pic_config &c, int idx)
     if (c.correction) {
         if (c.psi_deg < 1 || c.psi_deg > 8) return bad(PIC_EINVAL, "psi_deg must be in [1, 8]");
         if (c.psi_deg + c.filter_npass > PIC_MAX_HZ) return bad(PIC_EINVAL, "z stencil too wide");
-        for (int k = 0; k <= 4096; k++) {
-            double x = k / 4096.0, pe = 0, pb = 0;
-            for (int i = c.psi_deg; i >= 0; i--) { pe = pe * x + c.psi_e[i]; pb = pb * x + c.psi_b[i]; }
-            if (!(pe > 0.0) || !(pb > 0.0)) return bad(PIC_EPSI, "Psi_E or Psi_B <= 0 on s in [0,1]");
-        }
+        if (!psi_positive(c.psi_e, c.psi_b, c.psi_deg))
+            return bad(PIC_EPSI, "Psi_B <= 0 on s in [0,1] or Psi_E <= 0 on [0,1)");
     }
     if (!(c.m > 0) || !(c.weight >= 0) || !std::isfinite(c.q)) return bad(PIC_EINVAL, "species parameters");
     if (c.ion_mode != PIC_IONS_CHARGE && c.ion_mode != PIC_IONS_CHARGE_AND_CURRENT) return bad(PIC_EINVAL, "ion_mode");

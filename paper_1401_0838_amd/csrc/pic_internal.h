@@ -97,6 +97,9 @@ __host__ __device__ inline int xcd_tile(int b, int nt)
     return (nt % 8 != 0) ? b : (b % 8) * (nt / 8) + b / 8;
 }
 
+// breakdown test of the correction polynomials (psi_setup.cpp)
+bool psi_positive(const double *psi_e, const double *psi_b, int deg);
+
 // launch helpers implemented in pic_kernels.hip
 struct LaunchCtx {
     const InstDesc *desc;       // device table

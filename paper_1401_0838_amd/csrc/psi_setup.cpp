@@ -32,6 +32,24 @@ quad multiplier(int interp, quad alpha, quad s)
 
 }  // namespace
 
+// Breakdown test (Sec. 3): Psi_B > 0 on [0, 1] and Psi_E > 0 on [0, 1), on a
+// 4097-point grid.  The Eq. 5 multiplier is exactly zero at s = 1 (its
+// cotangent vanishes at k_z dz = pi), so there Psi_E only has to be zero up
+// to rounding: Psi_E(1) >= -1e-12 sum |psi_e[i]|.
+bool psi_positive(const double *psi_e, const double *psi_b, int deg)
+{
+    double tol = 0.0;
+    for (int i = 0; i <= deg; i++) tol += std::fabs(psi_e[i]);
+    tol *= 1e-12;
+    for (int k = 0; k <= 4096; k++) {
+        double s = k / 4096.0, pe = 0, pb = 0;
+        for (int i = deg; i >= 0; i--) { pe = pe * s + psi_e[i]; pb = pb * s + psi_b[i]; }
+        if (!(pb > 0.0)) return false;
+        if (!(pe > 0.0) && !(k == 4096 && pe >= -tol)) return false;
+    }
+    return true;
+}
+
 extern "C" int pic_psi_coeffs(int interp, double alpha_d, int deg, double *psi_e, double *psi_b)
 {
     if (!psi_e || !psi_b || deg < 1 || deg > 8 || !(alpha_d > 0.0) || alpha_d >= 1.0 ||
@@ -84,11 +102,5 @@ extern "C" int pic_psi_coeffs(int interp, double alpha_d, int deg, double *psi_e
     }
     for (int i = 0; i <= deg; i++) psi_e[i] = (double)x[i];
     for (int i = 1; i <= deg; i++) psi_b[i] = (double)x[deg + i];
-    // both polynomials must stay positive on [0, 1]
-    for (int k = 0; k <= 4096; k++) {
-        double s = k / 4096.0, pe = 0, pb = 0;
-        for (int i = deg; i >= 0; i--) { pe = pe * s + psi_e[i]; pb = pb * s + psi_b[i]; }
-        if (!(pe > 0.0) || !(pb > 0.0)) return PIC_EPSI;
-    }
-    return PIC_OK;
+    return psi_positive(psi_e, psi_b, deg) ? PIC_OK : PIC_EPSI;
 }

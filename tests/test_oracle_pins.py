@@ -19,7 +19,8 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 FACTS = json.load(open(os.path.join(GOLDEN, "paper_facts.json")))
 
 CASES = [("galerkin", 0.3), ("galerkin", 0.5), ("galerkin", 0.7),
-         ("uniform", 0.3), ("uniform", 0.7), ("uniform", 0.9), ("momentum", 0.5)]
+         ("uniform", 0.3), ("uniform", 0.7), ("uniform", 0.9),
+         ("momentum", 0.3), ("momentum", 0.5), ("momentum", 0.7)]
 
 
 def _wl(**kw):
@@ -80,6 +81,22 @@ def test_psi_uniform_magic_step_is_identity():
         assert abs(float(psi.multiplier("uniform", alpha, s)) - 1.0) < 1e-40
     a, b, ident = psi.psi_coeffs("uniform", alpha)
     assert ident and a == [1.0, 0, 0, 0, 0] and b == [1.0, 0, 0, 0, 0]
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.5, 0.7])
+def test_psi_momentum_vanishes_at_nyquist(alpha):
+    """Eq. 5 carries cot(k_z dz / 2), which is exactly zero at k_z dz = pi (s = 1):
+    the interpolant, which passes through the node s = 1, has Psi_E(1) = 0 up to
+    rounding and Psi_B(1) > 0, and that is not a breakdown of the determination."""
+    assert float(psi.multiplier("momentum", alpha, 1)) == pytest.approx(0.0, abs=1e-40)
+    a, b, ident = psi.psi_coeffs("momentum", alpha)
+    assert not ident
+    assert abs(psi.poly(a, 1.0)) < 1e-13 * sum(abs(v) for v in a)
+    assert psi.poly(b, 1.0) > 1e-4
+    assert psi.psi_positive(a, b)
+    bad = list(a)
+    bad[0] -= 1e-9      # Psi_E(1) clearly below zero: rejected
+    assert not psi.psi_positive(bad, b)
 
 
 def test_multipliers_in_k_form():
@@ -250,11 +267,14 @@ def test_boris_uniform_E_acceleration():
 
 # --------------------------------------------------------------- gather
 
+@pytest.mark.parametrize("interp", ["galerkin", "uniform", "momentum"])
 @pytest.mark.parametrize("dims,order", [(2, 1), (2, 3), (3, 1), (3, 3)])
-def test_gather_partition_of_unity(dims, order):
-    """Every spline set sums to one, so uniform seen fields are reproduced exactly."""
+def test_gather_partition_of_unity(dims, order, interp):
+    """Every spline set sums to one (and a node average of a constant is that
+    constant), so uniform seen fields are reproduced exactly."""
     n = (16, 16) if dims == 2 else (8, 8, 8)
-    wl = _wl(dims=dims, n=n, order=order, correction=True, filter=pi.workloads.BINOMIAL4)
+    wl = _wl(dims=dims, n=n, order=order, correction=True, filter=pi.workloads.BINOMIAL4,
+             interp=interp)
     sim = _empty_sim(wl)
     vals = [0.3, -1.1, 2.5, 0.7, -0.2, 1.9]
     for c in range(3):
@@ -267,6 +287,73 @@ def test_gather_partition_of_unity(dims, order):
         p = rng.random(3) * L
         Eo, Bo = sim.gather_at(p)
         assert np.max(np.abs(np.concatenate([Eo, Bo]) - vals)) < 1e-14
+
+
+STAG = {"Ex": (1, 0, 0), "Ey": (0, 1, 0), "Ez": (0, 0, 1),
+        "Bx": (0, 1, 1), "By": (1, 0, 1), "Bz": (1, 1, 0)}
+
+
+def _gather_response(sim, axis, kk, npt=12):
+    """Cell average of g(x_a) exp(-i k x_a) for every gathered component, where
+    g is the gather of the plane wave exp(i k x_a) sampled at each component's
+    own Yee location.  By Poisson summation this average is the Fourier
+    transform of the component's interpolation function along the axis (the
+    shape factor S of the Eq. 1 ratio)."""
+    names = ["Ex", "Ey", "Ez", "Bx", "By", "Bz"]
+    nz, ny, nx = sim.shape
+    coord = {0: np.arange(nx)[None, None, :], 1: np.arange(ny)[None, :, None],
+             2: np.arange(nz)[:, None, None]}[axis]
+    gl, gw = np.polynomial.legendre.leggauss(npt)
+    # the interpolation functions are polynomial on each half cell
+    pts = np.concatenate([0.25 + 0.25 * gl, 0.75 + 0.25 * gl])
+    wts = np.concatenate([0.25 * gw, 0.25 * gw])
+    acc = np.zeros(6, complex)
+    for part, fn in ((1.0, np.cos), (1j, np.sin)):
+        for c, nm in enumerate(names):
+            plane = fn(kk * (coord + 0.5 * STAG[nm][axis])) * np.ones(sim.shape)
+            (sim.Et if c < 3 else sim.Bt)[c % 3][:] = plane
+        for t, wgt in zip(pts, wts):
+            p = np.array([2.3, 1.7, 3.1])   # off-node in every other axis
+            p[axis] = 3.0 + t
+            Eo, Bo = sim.gather_at(p)
+            g = np.concatenate([Eo, Bo])
+            acc += part * wgt * g * np.exp(-1j * kk * p[axis])
+    return dict(zip(names, acc))
+
+
+@pytest.mark.parametrize("interp", ["galerkin", "uniform", "momentum"])
+@pytest.mark.parametrize("dims,order", [(2, 1), (2, 3), (3, 1), (3, 3)])
+def test_gather_shape_factors_match_eqs_3_to_5(dims, order, interp):
+    """Fourier transform of each component's gather along each axis against its
+    closed form: a centred order-o B-spline has transform sinc(k/2)^(o+1);
+    Galerkin lowers o by one along half-staggered axes, Uniform keeps o = l,
+    and the node average of the momentum-conserving scheme multiplies by
+    cos(k/2) along half-staggered axes.  The z ratio S^By / S^Ex then equals the
+    ratio of the scheme's multiplier to the Uniform one, since the Eq. 1
+    multiplier differs between schemes only through S^By / S^Ex, which is 1 for
+    Uniform (Eqs. 3-5: theta / sin(theta), 1 and cos(theta), theta = k_z dz / 2).
+    A wrong order, a wrong stagger offset (a phase) or a node average taken
+    from the wrong neighbours fails here."""
+    n = (16, 16) if dims == 2 else (8, 8, 8)
+    wl = _wl(dims=dims, n=n, order=order, correction=False, filter=[], interp=interp)
+    sim = _empty_sim(wl)
+    axes = (0, 2) if dims == 2 else (0, 1, 2)
+    for axis in axes:
+        na = n[axis] if dims == 3 else n[0 if axis == 0 else 1]
+        for m in range(1, na // 2 + 1):
+            kk = 2.0 * math.pi * m / na
+            th = 0.5 * kk
+            R = _gather_response(sim, axis, kk)
+            for nm, st in STAG.items():
+                o = order - st[axis] if interp == "galerkin" else order
+                want = (math.sin(th) / th) ** (o + 1)
+                if interp == "momentum" and st[axis]:
+                    want *= math.cos(th)
+                assert abs(R[nm] - want) < 1e-13, (axis, m, nm, R[nm], want)
+            if axis == 2:
+                s = math.sin(th) ** 2
+                ratio = float(psi.multiplier(interp, 0.5, s) / psi.multiplier("uniform", 0.5, s))
+                assert abs(R["By"] - ratio * R["Ex"]) < 1e-13, (m, R["By"], R["Ex"], ratio)
 
 
 # ------------------------------------------------------------ Esirkepov
@@ -312,9 +399,9 @@ def test_gauss_invariant_over_long_run():
 
 # ---------------------------------------------------- brute force (8x8 etc.)
 
-def _brute_pair(dims, n, order, filt, corr=True, npart=10, seed=3, steps=20):
+def _brute_pair(dims, n, order, filt, corr=True, npart=10, seed=3, steps=20, interp="galerkin"):
     wl = _wl(dims=dims, n=n, order=order, correction=corr, filter=list(filt),
-             alpha=0.45 if dims == 2 else 0.4, gamma=3.0)
+             alpha=0.45 if dims == 2 else 0.4, gamma=3.0, interp=interp)
     rng = np.random.default_rng(seed)
     x = rng.random((npart, dims)) * np.array(n, float)
     u = rng.normal(size=(npart, 3)) * 0.8 + np.array([0.0, 0.0, 1.5])
@@ -324,7 +411,7 @@ def _brute_pair(dims, n, order, filt, corr=True, npart=10, seed=3, steps=20):
     s = o.s
     b = BruteSim(dims, o.shape, (s.dx, s.dy, s.dz), s.dt, order, s.q, s.m, s.w,
                  psi_e=o.psi[0] if o.psi else None, psi_b=o.psi[1] if o.psi else None,
-                 filt=filt, jbg=tuple(s.jbg))
+                 filt=filt, jbg=tuple(s.jbg), interp=interp)
     b.E[:] = o.E
     b.B[:] = o.B
     bx, bu = o.x.copy(), o.u.copy()
@@ -334,13 +421,14 @@ def _brute_pair(dims, n, order, filt, corr=True, npart=10, seed=3, steps=20):
     return o, b, bx, bu
 
 
+@pytest.mark.parametrize("interp", ["galerkin", "uniform", "momentum"])
 @pytest.mark.parametrize("dims,n,order,steps", [
     (2, (8, 8), 1, 20), (2, (8, 10), 3, 20), (3, (8, 8, 8), 1, 4), (3, (8, 8, 9), 3, 2)])
-def test_oracle_matches_brute_force(dims, n, order, steps):
-    """Full step (Yee, Psi, filter, Galerkin gather, Boris, move, Esirkepov) against the
-    dense/DFT brute force on tiny grids."""
+def test_oracle_matches_brute_force(dims, n, order, steps, interp):
+    """Full step (Yee, Psi, filter, gather of each scheme, Boris, move, Esirkepov)
+    against the dense/DFT brute force on tiny grids."""
     o, b, bx, bu = _brute_pair(dims, n, order, (0.25, 0.25, -1.0), steps=steps,
-                               npart=10 if dims == 2 else 4)
+                               npart=10 if dims == 2 else 4, interp=interp)
 
     def rel(a, r):
         return np.linalg.norm(a - r) / np.linalg.norm(r)
