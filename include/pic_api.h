@@ -49,13 +49,21 @@ extern "C" {
 #define PIC_EHIP         -5   /* a HIP runtime call failed */
 #define PIC_ENONFINITE   -6   /* pic_diag found a NaN or Inf */
 #define PIC_EPARTICLE    -7   /* a particle moved a full cell or more in a step */
-#define PIC_EUNSUPPORTED -8   /* valid but not built (e.g. Uniform gather) */
+#define PIC_EUNSUPPORTED -8   /* valid but not built (e.g. the reverse sweep of a
+                                 non-Galerkin gather) */
 #define PIC_ESTATE       -9   /* call not valid in the current state */
 
 /* ------------------------------------------------------------- enumerations */
-#define PIC_GALERKIN 0        /* Eq. 3 scheme (gather built) */
-#define PIC_UNIFORM  1        /* Eq. 4 scheme (coefficients only) */
-#define PIC_MOMENTUM 2        /* Eq. 5 scheme (coefficients only) */
+/* gather (interpolation) schemes, with the multiplier each one's Psi fits */
+#define PIC_GALERKIN 0        /* Eq. 3: order l, lowered by one along axes where
+                                 the component sits half a cell off the nodes */
+#define PIC_UNIFORM  1        /* Eq. 4: order l on every axis, from each
+                                 component's own Yee location */
+#define PIC_MOMENTUM 2        /* Eq. 5: seen fields averaged from the Yee mesh
+                                 onto the integer nodes, then order l on every
+                                 axis; PIC_FIELD_SEEN_E/B then read the node
+                                 values, and every seen stencil is one cell
+                                 wider (filter_npass <= 7) */
 
 #define PIC_FP64 0            /* fields, offsets, momenta and J in double */
 #define PIC_FP32 1            /* float fields/offsets/momenta, int32 cell index,
@@ -86,7 +94,9 @@ typedef struct pic_config {
     double dx, dy, dz;        /* cell sizes (dy ignored in 2D) */
     double cdt;               /* c * dt */
     int    shape_order;       /* charge shape order l: 1 or 3 */
-    int    interp;            /* PIC_GALERKIN */
+    int    interp;            /* PIC_GALERKIN, PIC_UNIFORM or PIC_MOMENTUM; equal
+                                 for all instances; the reverse sweep needs
+                                 PIC_GALERKIN */
     int    precision;         /* PIC_FP64 or PIC_FP32; equal for all instances */
     int    correction;        /* 1: apply Psi_E / Psi_B (Sec. 2) */
     int    psi_deg;           /* polynomial degree of Psi_E and Psi_B, <= 8 */

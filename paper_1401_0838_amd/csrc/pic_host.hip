@@ -116,12 +116,19 @@ int validate(const pic_config &c, int idx)
     double s = 1.0 / (c.dx * c.dx) + 1.0 / (c.dz * c.dz) + (c.dims == 3 ? 1.0 / (c.dy * c.dy) : 0.0);
     if (c.cdt * std::sqrt(s) >= 1.0) return bad(PIC_ECOURANT, "Courant limit c dt < 1/sqrt(sum 1/d^2) violated");
     if (c.shape_order != 1 && c.shape_order != 3) return bad(PIC_EINVAL, "shape_order must be 1 or 3");
-    if (c.interp != PIC_GALERKIN) return bad(PIC_EUNSUPPORTED, "only the Galerkin gather is built");
+    if (c.interp != PIC_GALERKIN && c.interp != PIC_UNIFORM && c.interp != PIC_MOMENTUM)
+        return bad(PIC_EINVAL, "interp must be PIC_GALERKIN, PIC_UNIFORM or PIC_MOMENTUM");
+    if (c.interp != PIC_GALERKIN && c.adjoint_steps > 0)
+        return bad(PIC_EUNSUPPORTED, "the reverse sweep is built for the Galerkin gather only");
     if (c.precision != PIC_FP32 && c.precision != PIC_FP64) return bad(PIC_EINVAL, "precision");
     if (c.filter_npass < 0 || c.filter_npass > 8) return bad(PIC_EINVAL, "filter_npass must be in [0, 8]");
+    // the node average of the momentum-conserving gather widens every stencil by one cell
+    if (c.interp == PIC_MOMENTUM && c.filter_npass + 1 > PIC_MAX_HX)
+        return bad(PIC_EINVAL, "filter_npass must be <= 7 with the momentum-conserving gather");
     if (c.correction) {
         if (c.psi_deg < 1 || c.psi_deg > 8) return bad(PIC_EINVAL, "psi_deg must be in [1, 8]");
-        if (c.psi_deg + c.filter_npass > PIC_MAX_HZ) return bad(PIC_EINVAL, "z stencil too wide");
+        if (c.psi_deg + c.filter_npass + (c.interp == PIC_MOMENTUM) > PIC_MAX_HZ)
+            return bad(PIC_EINVAL, "z stencil too wide");
         if (!psi_positive(c.psi_e, c.psi_b, c.psi_deg))
             return bad(PIC_EPSI, "Psi_B <= 0 on s in [0,1] or Psi_E <= 0 on [0,1)");
     }
@@ -169,6 +176,7 @@ std::vector<double> filter_taps(const pic_config &c)
 
 struct pic_state {
     int n_inst = 0, dims = 2, order = 1, fp32 = 1;
+    int gather = GATHER_GALERKIN;    // gather scheme of every instance
     hipStream_t stream = nullptr;
     bool own_stream = false;
     char *arena = nullptr;
@@ -223,6 +231,7 @@ LaunchCtx ctx(const pic_state *s)
     c.any_resort = s->any_resort;
     c.par = s->parity;
     c.single = s->n_inst == 1;
+    c.gather = s->gather;
     if (!s->desc.empty()) {
         const InstDesc &d0 = s->desc[0];
         c.hz = d0.hz; c.hx = d0.hx; c.hzf = d0.hzf; c.psi_deg = d0.psi_deg;
@@ -422,8 +431,31 @@ void fill_desc(InstDesc &D, const pic_config &c, const pic_particles &p)
     std::memset(D.tz, 0, sizeof D.tz);
     std::memset(D.tx, 0, sizeof D.tx);
     std::memset(D.ty, 0, sizeof D.ty);
+    std::memset(D.tzn, 0, sizeof D.tzn);
+    std::memset(D.txn, 0, sizeof D.txn);
+    std::memset(D.tyn, 0, sizeof D.tyn);
+    D.nodal = c.interp == PIC_MOMENTUM;
+    if (D.nodal) {
+        // fields seen on the integer nodes: node n of a component half-staggered
+        // along an axis is the mean of its samples at n - 1/2 and n + 1/2 (array
+        // slots n - 1 and n), i.e. the taps composed with (1/2 at -1, 1/2 at 0);
+        // every stencil grows by one cell (zero-padded where not staggered)
+        const std::vector<double> avg = {0.5, 0.5, 0.0};
+        const std::vector<double> pad = {0.0, 1.0, 0.0};
+        const std::vector<double> zn = conv(zb, avg), fn = conv(fz, avg);
+        ze = conv(ze, pad);
+        zb = conv(zb, pad);
+        const std::vector<double> fp = conv(fz, pad);
+        D.hz = (int)(ze.size() / 2);
+        D.hx = (int)(fp.size() / 2);
+        D.hy = c.dims == 3 ? D.hx : 0;
+        for (size_t t = 0; t < zn.size(); t++) D.tzn[t] = zn[t];
+        for (size_t t = 0; t < fn.size(); t++) { D.txn[t] = fn[t]; D.tyn[t] = fn[t]; }
+        for (size_t t = 0; t < fp.size(); t++) { D.tx[t] = fp[t]; D.ty[t] = fp[t]; }
+    } else {
+        for (size_t t = 0; t < fz.size(); t++) { D.tx[t] = fz[t]; D.ty[t] = fz[t]; }
+    }
     for (size_t t = 0; t < ze.size(); t++) { D.tz[0][t] = ze[t]; D.tz[1][t] = zb[t]; }
-    for (size_t t = 0; t < fz.size(); t++) { D.tx[t] = fz[t]; D.ty[t] = fz[t]; }
     // reverse mode: filter-only z taps, taps of S_z^j, unscaled deposit factors
     std::memset(D.tzf, 0, sizeof D.tzf);
     D.hzf = (int)(fz.size() / 2);
@@ -809,8 +841,9 @@ extern "C" int pic_plan(const pic_config *cfgs, int n_inst, const int64_t *n_par
         if (rc) return rc;
         if (cfgs[i].dims != cfgs[0].dims || cfgs[i].precision != cfgs[0].precision ||
             cfgs[i].shape_order != cfgs[0].shape_order || cfgs[i].adjoint_steps != cfgs[0].adjoint_steps ||
+            cfgs[i].interp != cfgs[0].interp ||
             (cfgs[0].adjoint_steps > 0 && cfgs[i].adjoint_ckpt != cfgs[0].adjoint_ckpt))
-            return fail(PIC_EINVAL, "all instances must share dims, precision, shape_order and adjoint sizes");
+            return fail(PIC_EINVAL, "all instances must share dims, precision, shape_order, interp and adjoint sizes");
         if (n_particles[i] < 0 || n_particles[i] > INT32_MAX) return fail(PIC_EINVAL, "particle count");
     }
     const std::vector<pic_config> rc = resolve_tiles(cfgs, n_inst);
@@ -843,6 +876,8 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
     s->dims = cfgs[0].dims;
     s->order = cfgs[0].shape_order;
     s->fp32 = cfgs[0].precision == PIC_FP32;
+    s->gather = cfgs[0].interp == PIC_UNIFORM ? GATHER_UNIFORM
+              : cfgs[0].interp == PIC_MOMENTUM ? GATHER_NODAL : GATHER_GALERKIN;
     s->cfg.assign(cfgs, cfgs + n_inst);
     s->np = np;
     s->desc.resize(n_inst);

@@ -51,6 +51,15 @@ struct InstDesc {
     double tz[2][2 * PIC_MAX_HZ + 1];  // combined z taps: [0] Psi_E o filter, [1] Psi_B o filter
     double tx[2 * PIC_MAX_HX + 1];     // x filter taps
     double ty[2 * PIC_MAX_HX + 1];     // y filter taps (3D)
+    // momentum-conserving gather (Eq. 5 scheme): the seen fields are written on
+    // the integer nodes.  Along an axis where a component is half-staggered its
+    // taps are those above composed with the two-point node average (tzn: Psi_B o
+    // filter; txn, tyn: filter); the other taps are padded by one zero on each
+    // side, and hz, hx, hy include the extra cell
+    int nodal;
+    double tzn[2 * PIC_MAX_HZ + 1];
+    double txn[2 * PIC_MAX_HX + 1];
+    double tyn[2 * PIC_MAX_HX + 1];
     // grid planes (element type follows the precision)
     // E, B and J alternate between two sets of planes from step to step (index =
     // parity): the field kernels read one set with halos and write the other
@@ -90,6 +99,13 @@ struct InstDesc {
     void *roff[3], *ru[3];
 };
 
+// gather schemes (template argument of the particle kernel)
+enum {
+    GATHER_GALERKIN = 0,   // Eq. 3: order l, lowered by one along half-staggered axes
+    GATHER_UNIFORM = 1,    // Eq. 4: order l from each component's own Yee location
+    GATHER_NODAL = 2       // Eq. 5: order l from the integer nodes (seen fields averaged there)
+};
+
 // Launch slot b -> tile in XCD-aware order: slot b runs on XCD b % 8, and each
 // XCD gets a contiguous run of tiles (whose guard cells then share its L2)
 __host__ __device__ inline int xcd_tile(int b, int nt)
@@ -117,6 +133,7 @@ struct LaunchCtx {
     // step is given the new parity
     int par = 0;
     int single = 0;                   // one instance: 2D field kernels take tile = block index
+    int gather = GATHER_GALERKIN;     // gather scheme shared by every instance
 };
 
 int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork);

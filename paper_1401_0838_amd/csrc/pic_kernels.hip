@@ -30,7 +30,8 @@ namespace {
 
 using namespace pic;
 
-// Galerkin interpolation of one component with staggering (SX, SY, SZ).
+// Galerkin interpolation (Eq. 3 scheme) of one component with staggering (SX,
+// SY, SZ): order l, lowered by one along half-staggered axes.
 template <int SX, int SY, int SZ, int DIM, int L, class R, class Win>
 __device__ __forceinline__ R interp(const Win &W, int comp, const int *lc, const R (*wi)[L + 1],
                                     const R (*wh)[L])
@@ -61,31 +62,106 @@ __device__ __forceinline__ R interp(const Win &W, int comp, const int *lc, const
     return s;
 }
 
+// Order-l interpolation of one component on every axis: the weights w[a][0..L]
+// apply to the window cells b[a] .. b[a] + L.
+template <int DIM, int L, class R, class Win>
+__device__ __forceinline__ R interp_l(const Win &W, int comp, const int *b, const R *wx, const R *wy, const R *wz)
+{
+    constexpr int NY = DIM == 3 ? L + 1 : 1;
+    R s = R(0);
+#pragma unroll
+    for (int kz = 0; kz <= L; kz++) {
+#pragma unroll
+        for (int ky = 0; ky < NY; ky++) {
+            R row = R(0);
+#pragma unroll
+            for (int kx = 0; kx <= L; kx++) row += wx[kx] * W.f(comp, b[0] + kx, DIM == 3 ? b[1] + ky : 0, b[2] + kz);
+            s += (DIM == 3 ? wy[ky] : R(1)) * wz[kz] * row;
+        }
+    }
+    return s;
+}
+
+// Uniform interpolation (Eq. 4 scheme) of a component with staggering (SX, SY,
+// SZ): order l from its own Yee location, i.e. along a half-staggered axis the
+// weights wu of the coordinate shifted by half a cell, from window cell bu.
+template <int SX, int SY, int SZ, int DIM, int L, class R, class Win>
+__device__ __forceinline__ R interp_u(const Win &W, int comp, const int *bi, const int *bu, const R (*wi)[L + 1],
+                                      const R (*wu)[L + 1])
+{
+    const int b[3] = {SX ? bu[0] : bi[0], SY ? bu[1] : bi[1], SZ ? bu[2] : bi[2]};
+    return interp_l<DIM, L, R>(W, comp, b, SX ? wu[0] : wi[0], SY ? wu[1] : wi[1], SZ ? wu[2] : wi[2]);
+}
+
+// The six seen-field components at one particle with gather scheme IP.
+template <int DIM, int L, int IP, class R, class Win>
+__device__ __forceinline__ void gather6(const Win &W, const int *lc, const R *off, R *Ev, R *Bv)
+{
+    constexpr int H = (L - 1) / 2;
+    R wi[3][L + 1];
+    int bi[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        bi[a] = lc[a] - H;
+        if (DIM == 2 && a == 1) continue;
+        Shape<L, R>::integer(off[a], wi[a]);
+    }
+    // staggering: Ex(1,0,0) Ey(0,1,0) Ez(0,0,1) Bx(0,1,1) By(1,0,1) Bz(1,1,0)
+    if constexpr (IP == GATHER_GALERKIN) {
+        R wh[3][L];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            if (DIM == 2 && a == 1) continue;
+            Shape<L, R>::half(off[a], wh[a]);
+        }
+        Ev[0] = interp<1, 0, 0, DIM, L, R>(W, 0, lc, wi, wh);
+        Ev[1] = interp<0, 1, 0, DIM, L, R>(W, 1, lc, wi, wh);
+        Ev[2] = interp<0, 0, 1, DIM, L, R>(W, 2, lc, wi, wh);
+        Bv[0] = interp<0, 1, 1, DIM, L, R>(W, 3, lc, wi, wh);
+        Bv[1] = interp<1, 0, 1, DIM, L, R>(W, 4, lc, wi, wh);
+        Bv[2] = interp<1, 1, 0, DIM, L, R>(W, 5, lc, wi, wh);
+    } else if constexpr (IP == GATHER_UNIFORM) {
+        // half-staggered samples sit at cell + 1/2: the shifted coordinate's cell
+        // is this one when off >= 1/2, else the one below
+        R wu[3][L + 1];
+        int bu[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            bu[a] = bi[a];
+            if (DIM == 2 && a == 1) continue;
+            const bool up = off[a] >= R(0.5);
+            bu[a] -= up ? 0 : 1;
+            Shape<L, R>::integer(up ? off[a] - R(0.5) : off[a] + R(0.5), wu[a]);
+        }
+        Ev[0] = interp_u<1, 0, 0, DIM, L, R>(W, 0, bi, bu, wi, wu);
+        Ev[1] = interp_u<0, 1, 0, DIM, L, R>(W, 1, bi, bu, wi, wu);
+        Ev[2] = interp_u<0, 0, 1, DIM, L, R>(W, 2, bi, bu, wi, wu);
+        Bv[0] = interp_u<0, 1, 1, DIM, L, R>(W, 3, bi, bu, wi, wu);
+        Bv[1] = interp_u<1, 0, 1, DIM, L, R>(W, 4, bi, bu, wi, wu);
+        Bv[2] = interp_u<1, 1, 0, DIM, L, R>(W, 5, bi, bu, wi, wu);
+    } else {
+        // momentum-conserving (Eq. 5 scheme): the seen fields were averaged onto
+        // the integer nodes, so every component shares one weight set
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            Ev[k] = interp_l<DIM, L, R>(W, k, bi, wi[0], wi[1], wi[2]);
+            Bv[k] = interp_l<DIM, L, R>(W, 3 + k, bi, wi[0], wi[1], wi[2]);
+        }
+    }
+}
+
 // One particle: gather, Boris, move, Esirkepov deposit.
 // lc: window-local cell; off: in-cell offsets; u: momenta (updated);
 // dc / offn: cell step and new offsets (outputs).
-template <int DIM, int L, class R, class JT, class Win>
+template <int DIM, int L, class R, class JT, int IP, class Win>
 __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *off, R *u, int *dc, R *offn,
                                               const R *dtd, R qdt2m, const R *cdep, R cy2d, int &err)
 {
     constexpr int H = (L - 1) / 2;
-    R wi[3][L + 1], wh[3][L];
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        if (DIM == 2 && a == 1) continue;
-        Shape<L, R>::integer(off[a], wi[a]);
-        Shape<L, R>::half(off[a], wh[a]);
-    }
-    // staggering: Ex(1,0,0) Ey(0,1,0) Ez(0,0,1) Bx(0,1,1) By(1,0,1) Bz(1,1,0)
-    R E0 = interp<1, 0, 0, DIM, L, R>(W, 0, lc, wi, wh);
-    R E1 = interp<0, 1, 0, DIM, L, R>(W, 1, lc, wi, wh);
-    R E2 = interp<0, 0, 1, DIM, L, R>(W, 2, lc, wi, wh);
-    R B0 = interp<0, 1, 1, DIM, L, R>(W, 3, lc, wi, wh);
-    R B1 = interp<1, 0, 1, DIM, L, R>(W, 4, lc, wi, wh);
-    R B2 = interp<1, 1, 0, DIM, L, R>(W, 5, lc, wi, wh);
+    R Ev[3], Bv[3];
+    gather6<DIM, L, IP, R>(W, lc, off, Ev, Bv);
 
     // Boris (textbook): half electric kick, magnetic rotation, half kick; then move
-    const R Ev[3] = {E0, E1, E2}, Bv[3] = {B0, B1, B2};
     R un[3];
     BorisTrace<R> bt;
     boris_push<R>(u, Ev, Bv, qdt2m, un, bt);
@@ -241,7 +317,7 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 // PF: load the next particle's state while the current one is processed.
 // TP: also write the state each particle starts from, and each tile's box,
 // to the tape slot named by the descriptor (reverse sweep recompute).
-template <int DIM, int L, class R, int P, bool PF, bool TP = false>
+template <int DIM, int L, class R, int P, bool PF, bool TP = false, int IP = GATHER_GALERKIN>
 __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                int nwork, int wmx, int wmy, int wmz, int par)
 {
@@ -374,10 +450,10 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
                 }
             }
             if (fits) {
-                if constexpr (P > 0) push_particle<DIM, L, R, JT>(lwp, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
-                else push_particle<DIM, L, R, JT>(lw, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
+                if constexpr (P > 0) push_particle<DIM, L, R, JT, IP>(lwp, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
+                else push_particle<DIM, L, R, JT, IP>(lw, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
             } else
-                push_particle<DIM, L, R, JT>(gw, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
+                push_particle<DIM, L, R, JT, IP>(gw, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
             int nc[3];
 #pragma unroll
             for (int a = 0; a < 3; a++) {
@@ -432,11 +508,11 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
     }
 }
 
-template <int DIM, int L, class R, int P, bool PF = false, bool TP = false>
+template <int DIM, int L, class R, int P, bool PF = false, bool TP = false, int IP = GATHER_GALERKIN>
 __global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                    int nwork, int wmx, int wmy, int wmz, int par)
 {
-    particles_body<DIM, L, R, P, PF, TP>(Dt, work, nwork, wmx, wmy, wmz, par);
+    particles_body<DIM, L, R, P, PF, TP, IP>(Dt, work, nwork, wmx, wmy, wmz, par);
 }
 
 // same body compiled for four waves per SIMD (at most 128 VGPRs)
@@ -662,8 +738,25 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
 }
 
 // ------------------------------------------------------ seen-field passes
-// axis 2: combined z taps (tz[0] for Ex, Ey; tz[1] for Ez, Bx, By, Bz)
-// axis 0 / 1: filter taps along x / y.  blockIdx.y selects the component.
+// Taps of component comp (Ex Ey Ez Bx By Bz) along z, x and y.  With the
+// momentum-conserving gather, the axes along which a component is
+// half-staggered (z: Ez Bx By; x: Ex By Bz; y: Ey Bx Bz) take the taps composed
+// with the node average.
+__device__ __forceinline__ const double *ztaps(const InstDesc &D, int comp)
+{
+    return (D.nodal && comp >= 2 && comp <= 4) ? D.tzn : D.tz[comp < 2 ? 0 : 1];
+}
+__device__ __forceinline__ const double *xtaps(const InstDesc &D, int comp)
+{
+    return (D.nodal && (comp == 0 || comp >= 4)) ? D.txn : D.tx;
+}
+__device__ __forceinline__ const double *ytaps(const InstDesc &D, int comp)
+{
+    return (D.nodal && (comp & 1)) ? D.tyn : D.ty;
+}
+
+// axis 2: combined z taps (Psi_E o filter for Ex, Ey; Psi_B o filter for Ez, Bx,
+// By, Bz); axis 0 / 1: filter taps along x / y.  blockIdx.y selects the component.
 template <int AXIS, class R, int HW>
 __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                    int src_sel, int dst_sel, int par)
@@ -686,7 +779,7 @@ __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ 
     int i, j, k;
     cell_ijk<R>(D, cell, i, j, k);
     const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
-    const double *tap = AXIS == 2 ? D.tz[comp < 2 ? 0 : 1] : (AXIS == 0 ? D.tx : D.ty);
+    const double *tap = AXIS == 2 ? ztaps(D, comp) : (AXIS == 0 ? xtaps(D, comp) : ytaps(D, comp));
     const int h = HW >= 0 ? HW : (AXIS == 2 ? D.hz : (AXIS == 0 ? D.hx : D.hy));
     // index along the axis, its extent and the stride between neighbours
     const int q = AXIS == 2 ? k : (AXIS == 0 ? i : j);
@@ -733,7 +826,7 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     R *mid = win + wx * wz;
     R *tz = mid + wx * SEEN_TZ;
     R *tx = tz + 2 * PIC_MAX_HZ + 1;
-    const double *tzs = D.tz[comp < 2 ? 0 : 1];
+    const double *tzs = ztaps(D, comp), *txs = xtaps(D, comp);
     constexpr int NTZ = HZ >= 0 ? 2 * HZ + 1 : 1, NTX = HX >= 0 ? 2 * HX + 1 : 1;
     R rz[NTZ], rx[NTX];
     if constexpr (HZ >= 0) {
@@ -744,9 +837,9 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     }
     if constexpr (HX >= 0) {
 #pragma unroll
-        for (int k = 0; k < NTX; k++) rx[k] = (R)D.tx[k];
+        for (int k = 0; k < NTX; k++) rx[k] = (R)txs[k];
     } else {
-        for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)D.tx[i];
+        for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)txs[i];
     }
     const void *sp = comp < 3 ? D.E[par][comp] : D.B[par][comp - 3];
     const gp<const R> src = G<R>(sp);
@@ -1212,8 +1305,10 @@ void launch_seen_2d_tz(const LaunchCtx &c, const int2 *swork, int nswork)
     const dim3 g(nswork, 6), b(PIC_FIELD_CHUNK);
     if (c.single) swork = nullptr;
     // half-widths: correction of degree 4 with four filter passes (8, 4);
-    // filter alone (4, 4); correction alone (4, 0); neither (0, 0)
+    // filter alone (4, 4); correction alone (4, 0); neither (0, 0); the first
+    // with the node average of the momentum-conserving gather (9, 5)
     if (c.hz == 8 && c.hx == 4) k_seen_2d<R, TZ, 8, 4><<<g, b, sm, c.stream>>>(c.desc, swork, c.par);
+    else if (c.hz == 9 && c.hx == 5) k_seen_2d<R, TZ, 9, 5><<<g, b, sm, c.stream>>>(c.desc, swork, c.par);
     else if (c.hz == 4 && c.hx == 4) k_seen_2d<R, TZ, 4, 4><<<g, b, sm, c.stream>>>(c.desc, swork, c.par);
     else if (c.hz == 4 && c.hx == 0) k_seen_2d<R, TZ, 4, 0><<<g, b, sm, c.stream>>>(c.desc, swork, c.par);
     else if (c.hz == 0 && c.hx == 0) k_seen_2d<R, TZ, 0, 0><<<g, b, sm, c.stream>>>(c.desc, swork, c.par);
@@ -1236,11 +1331,16 @@ int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *sw
         if (c.dims == 2) {
             launch_seen_2d<R>(c, swork, nswork);
         } else {
-            // usual widths: correction of degree 4 with four filter passes (z 8, x and y 4)
+            // usual widths: correction of degree 4 with four filter passes (z 8, x and y 4),
+            // one more with the node average of the momentum-conserving gather
             if (c.hz == 8 && c.hx == 4) {
                 k_seen_pass<2, R, 8><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1, c.par);
                 k_seen_pass<0, R, 4><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
                 k_seen_pass<1, R, 4><<<g, b, 0, c.stream>>>(c.desc, fwork, 2, 0, c.par);
+            } else if (c.hz == 9 && c.hx == 5) {
+                k_seen_pass<2, R, 9><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1, c.par);
+                k_seen_pass<0, R, 5><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
+                k_seen_pass<1, R, 5><<<g, b, 0, c.stream>>>(c.desc, fwork, 2, 0, c.par);
             } else {
                 k_seen_pass<2, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1, c.par);
                 k_seen_pass<0, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
@@ -1268,8 +1368,25 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
 #define PK(D_, L_, P_) k_particles<D_, L_, R, P_><<<g, b, smem, c.stream>>>(c.desc, c.single ? nullptr : pwork, nwork, wm[0], wm[1], wm[2], c.par)
 #define PK24(K_, PF_) K_<2, 1, float, 24, PF_><<<g, b, smem, c.stream>>>(c.desc, c.single ? nullptr : pwork, nwork, wm[0], wm[1], wm[2], c.par)
 #define PKR(L_, P_) k_particles<2, L_, R, P_, false, true><<<g, b, smem, c.stream>>>(c.desc, c.single ? nullptr : pwork, nwork, wm[0], wm[1], wm[2], c.par)
+#define PKS(D_, L_, P_, IP_) k_particles<D_, L_, R, P_, false, false, IP_><<<g, b, smem, c.stream>>>(c.desc, c.single ? nullptr : pwork, nwork, wm[0], wm[1], wm[2], c.par)
+#define PK_SCHEME(IP_)                                                              \
+    do {                                                                            \
+        if (c.dims == 2 && c.order == 1) {                                          \
+            if (wm[0] == 24 && wm[2] == 24) PKS(2, 1, 24, IP_);                     \
+            else if (wm[0] == 32 && wm[2] == 32) PKS(2, 1, 32, IP_);                \
+            else PKS(2, 1, 0, IP_);                                                 \
+        } else if (c.dims == 2) {                                                   \
+            if (wm[0] == 32 && wm[2] == 32) PKS(2, 3, 32, IP_);                     \
+            else PKS(2, 3, 0, IP_);                                                 \
+        } else if (c.order == 1) PKS(3, 1, 0, IP_);                                 \
+        else PKS(3, 3, 0, IP_);                                                     \
+    } while (0)
     DISPATCH_R(c.fp32, {
-        if (c.record && c.dims == 2) {
+        if (c.gather == GATHER_UNIFORM) {
+            PK_SCHEME(GATHER_UNIFORM);
+        } else if (c.gather == GATHER_NODAL) {
+            PK_SCHEME(GATHER_NODAL);
+        } else if (c.record && c.dims == 2) {
             // recording a tape slot (2D reverse sweep)
             if (c.order == 1) {
                 if (wm[0] == 24 && wm[2] == 24) PKR(1, 24);
@@ -1296,6 +1413,8 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
 #undef PK
 #undef PK24
 #undef PKR
+#undef PKS
+#undef PK_SCHEME
     return hip_ok(hipGetLastError());
 }
 

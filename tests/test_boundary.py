@@ -81,7 +81,23 @@ def test_plan_validates_configs():
     with pytest.raises(L.PicError) as e:
         L.pic_plan([c], [16])
     assert e.value.code == L.PIC_EINVAL
+    assert L.pic_plan([_cfg(interp="uniform")], [16]) > 0
+    assert L.pic_plan([_cfg(interp="momentum", correction=True)], [16]) > 0
     c = _cfg(interp="uniform")
+    c.interp = 7
+    with pytest.raises(L.PicError) as e:
+        L.pic_plan([c], [16])
+    assert e.value.code == L.PIC_EINVAL
+    with pytest.raises(L.PicError) as e:     # schemes are shared by a batch
+        L.pic_plan([_cfg(), _cfg(interp="uniform")], [16, 16])
+    assert e.value.code == L.PIC_EINVAL
+    c = _cfg(interp="momentum")
+    c.filter_npass = 8                        # node average needs one more x cell
+    with pytest.raises(L.PicError) as e:
+        L.pic_plan([c], [16])
+    assert e.value.code == L.PIC_EINVAL
+    c = _cfg(interp="uniform")
+    c.adjoint_steps, c.adjoint_ckpt = 4, 2
     with pytest.raises(L.PicError) as e:
         L.pic_plan([c], [16])
     assert e.value.code == L.PIC_EUNSUPPORTED
