@@ -56,6 +56,8 @@ def reverse(sim, tape, lE, lB, lJ, lx, lu):
     Galerkin and Uniform schemes (samples at the Yee locations)."""
     if sim.s.interp == 2:
         raise NotImplementedError("reverse sweep of the momentum-conserving gather")
+    if sim.s.solver != 0:
+        raise NotImplementedError("reverse sweep of the Cole-Karkkainen solver")
     lib = _lib()
     grad = np.zeros(max(1, sim.s.psi_deg + 1))
     lEt = np.zeros_like(sim.E)

@@ -4,7 +4,8 @@ Written independently of pic_oracle.c, in a different formulation, so that a
 dropped term, a sign, an index or a transposed operand in either one shows up
 as a mismatch:
   * curls are dense matrices built from periodic shift matrices (Kronecker
-    products), not stencil loops;
+    products), not stencil loops (the Cole-Karkkainen curl as the product of
+    an averaging matrix and the difference matrix);
   * the correction polynomials and filter passes are applied in Fourier space
     by an explicit DFT multiply: symbol s = sin^2(k_z dz / 2) for Psi (Sec. 2)
     and 1 - 4 w sin^2(k dx / 2) per (w, 1-2w, w) pass (Sec. 3, Eq. 6);
@@ -48,7 +49,7 @@ class BruteSim:
     STAG_B = ((0, 1, 1), (1, 0, 1), (1, 1, 0))
 
     def __init__(self, dims, shape, d, dt, order, q, m, w, psi_e=None, psi_b=None,
-                 filt=(), jbg=(0.0, 0.0, 0.0), interp="galerkin"):
+                 filt=(), jbg=(0.0, 0.0, 0.0), interp="galerkin", solver="yee"):
         self.dims = dims
         self.shape = tuple(shape)                 # (nz, ny, nx)
         self.d = tuple(d)                         # (dx, dy, dz)
@@ -76,6 +77,15 @@ class BruteSim:
         if dims == 2:
             self.Df[1] = np.zeros_like(I)
             self.Db[1] = np.zeros_like(I)
+        # Faraday's law differences: Yee, or Cole-Karkkainen (2D): the x difference
+        # smoothed along z and the z difference along x by the symmetric
+        # (1/8, 3/4, 1/8) average, as matrix products
+        self.DfF = list(self.Df)
+        if solver == "ck":
+            beta = 0.125
+            avg = [(1 - 2 * beta) * I + beta * (self.Sh[a] + self.Sh[a].T) for a in range(3)]
+            self.DfF[0] = avg[2] @ self.Df[0]
+            self.DfF[2] = avg[0] @ self.Df[2]
 
     # ---------------------------------------------------------- fields
     def _curl(self, F, D):
@@ -86,10 +96,10 @@ class BruteSim:
         return np.stack([cx, cy, cz]).reshape((3,) + self.shape)
 
     def yee(self):
-        self.B -= 0.5 * self.dt * self._curl(self.E, self.Df)
+        self.B -= 0.5 * self.dt * self._curl(self.E, self.DfF)
         jt = self.J + self.jbg[:, None, None, None]
         self.E += self.dt * (self._curl(self.B, self.Db) - jt)
-        self.B -= 0.5 * self.dt * self._curl(self.E, self.Df)
+        self.B -= 0.5 * self.dt * self._curl(self.E, self.DfF)
 
     def _symbols(self):
         nz, ny, nx = self.shape

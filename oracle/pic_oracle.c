@@ -17,6 +17,8 @@
  *
  * One step (the order used throughout this project):
  *   1. Yee: B -= dt/2 curl E;  E += dt (curl B - J - Jbg);  B -= dt/2 curl E
+ *      (with the Cole-Karkkainen solver named in Secs. 2-4, the curl of E in the
+ *      two B half steps is its modified one; see yee_b_half)
  *   2. fields as seen by the particles: Psi series along z (Sec. 2), then the
  *      3-point digital filter passes along z, then x, then y (Sec. 3, Eq. 6)
  *   3. J = 0; per particle, in order: gather (Galerkin, Uniform or
@@ -33,6 +35,7 @@ typedef struct {
     double dx, dy, dz, dt;
     int order;                /* charge shape order l (1 or 3) */
     int interp;               /* 0 Galerkin, 1 Uniform, 2 momentum-conserving */
+    int solver;               /* 0 Yee, 1 Cole-Karkkainen (2D, square cells) */
     double q, m, w;           /* charge, mass, macro-particle weight */
     int correction;           /* 1: apply Psi_E / Psi_B */
     int psi_deg;              /* polynomial degree of Psi (<= 8) */
@@ -67,8 +70,46 @@ static long at(const OSim *s, long i, long j, long k)
 
 /* ---------------------------------------------------------------- Yee ---- */
 
+/* forward differences of plane F at (i, j, k) along x and along z */
+static double fdx(const OSim *s, const double *F, long i, long j, long k)
+{
+    return (F[at(s, i + 1, j, k)] - F[at(s, i, j, k)]) / s->dx;
+}
+
+static double fdz(const OSim *s, const double *F, long i, long j, long k)
+{
+    return (F[at(s, i, j, k + 1)] - F[at(s, i, j, k)]) / s->dz;
+}
+
+/* Cole-Karkkainen half step of B in 2D (the paper uses it with beta = 1/8,
+ * Secs. 2-3).  Reading: on square cells, each forward difference of E in
+ * Faraday's law is replaced by the weighted mean, with weights (beta, 1 - 2 beta,
+ * beta), of the same difference on the line itself and on its two neighbours
+ * along the other in-plane axis; Ampere's law stays the Yee one.  Along a
+ * mesh axis (transverse wave number zero) the operator is the Yee one. */
+static void ck_b_half(OSim *s)
+{
+    const double h = 0.5 * s->dt, beta = 0.125, mid = 1.0 - 2.0 * beta;
+    double *Ex = s->E[0], *Ey = s->E[1], *Ez = s->E[2];
+    for (long k = 0; k < s->nz; k++)
+        for (long i = 0; i < s->nx; i++) {
+            long p = at(s, i, 0, k);
+            double dzEy = mid * fdz(s, Ey, i, 0, k) + beta * (fdz(s, Ey, i - 1, 0, k) + fdz(s, Ey, i + 1, 0, k));
+            double dzEx = mid * fdz(s, Ex, i, 0, k) + beta * (fdz(s, Ex, i - 1, 0, k) + fdz(s, Ex, i + 1, 0, k));
+            double dxEz = mid * fdx(s, Ez, i, 0, k) + beta * (fdx(s, Ez, i, 0, k - 1) + fdx(s, Ez, i, 0, k + 1));
+            double dxEy = mid * fdx(s, Ey, i, 0, k) + beta * (fdx(s, Ey, i, 0, k - 1) + fdx(s, Ey, i, 0, k + 1));
+            s->B[0][p] -= h * (-dzEy);
+            s->B[1][p] -= h * (dzEx - dxEz);
+            s->B[2][p] -= h * dxEy;
+        }
+}
+
 static void yee_b_half(OSim *s)
 {
+    if (s->solver == 1) {
+        ck_b_half(s);
+        return;
+    }
     const double h = 0.5 * s->dt;
     double *Ex = s->E[0], *Ey = s->E[1], *Ez = s->E[2];
     for (long k = 0; k < s->nz; k++)

@@ -17,7 +17,7 @@ _P = C.POINTER(C.c_double)
 class _OSim(C.Structure):
     _fields_ = [("dims", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double), ("dt", C.c_double),
-                ("order", C.c_int), ("interp", C.c_int),
+                ("order", C.c_int), ("interp", C.c_int), ("solver", C.c_int),
                 ("q", C.c_double), ("m", C.c_double), ("w", C.c_double),
                 ("correction", C.c_int), ("psi_deg", C.c_int),
                 ("psi_e", C.c_double * 9), ("psi_b", C.c_double * 9),
@@ -93,6 +93,9 @@ class OracleSim:
         s.dt = float(wl["alpha"]) * dz
         s.order = int(wl["order"])
         s.interp = {"galerkin": 0, "uniform": 1, "momentum": 2}[wl.get("interp", "galerkin")]
+        s.solver = {"yee": 0, "ck": 1}[wl.get("solver", "yee")]
+        if s.solver == 1 and (self.dims != 2 or dx != dz):
+            raise ValueError("the Cole-Karkkainen solver is taken on square 2D cells only")
         s.q, s.m = float(wl["q"]), float(wl["m"])
         if weight is None:
             n0 = wl["omega_p"] ** 2 * wl["m"] / wl["q"] ** 2

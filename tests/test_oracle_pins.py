@@ -219,6 +219,63 @@ def test_yee_standing_mode_dispersion(dims, comp):
     assert err < 1e-11, err
 
 
+@pytest.mark.parametrize("comp", ["Ey", "By"])
+@pytest.mark.parametrize("alpha", [0.5, 0.9, 0.99])
+def test_ck_standing_mode_dispersion(comp, alpha):
+    """Cole-Karkkainen (beta = 1/8, square cells): Faraday's differences are
+    averaged across lines with (1/8, 3/4, 1/8), whose symbol is 1 - sin^2(k/2)/2,
+    so a standing mode oscillates as cos(n w dt) with
+    sin^2(w dt/2)/dt^2 = sx (1 - sz/2) + sz (1 - sx/2), sx = sin^2(kx/2), sz = sin^2(kz/2),
+    also above the 2D Yee limit alpha < 1/sqrt(2) (Secs. 2-3 run it up to alpha near 1)."""
+    n = (24, 32)
+    wl = _wl(dims=2, n=n, alpha=alpha, correction=False, filter=[], solver="ck")
+    sim = _empty_sim(wl)
+    nz, ny, nx = sim.shape
+    kx, kz = 2 * math.pi * 5 / nx, 2 * math.pi * 7 / nz
+    i = np.arange(nx)[None, None, :]
+    k = np.arange(nz)[:, None, None]
+    if comp == "Ey":
+        mode = np.sin(kx * i) * np.sin(kz * k) * np.ones((1, ny, 1))
+        sim.E[1][:] = mode
+    else:
+        mode = np.cos(kx * (i + 0.5)) * np.cos(kz * (k + 0.5)) * np.ones((1, ny, 1))
+        sim.B[1][:] = mode
+    dt = sim.s.dt
+    sx, sz = math.sin(kx / 2) ** 2, math.sin(kz / 2) ** 2
+    w = 2.0 / dt * math.asin(dt * math.sqrt(sx * (1 - sz / 2) + sz * (1 - sx / 2)))
+    nsteps = 1000
+    for _ in range(nsteps):
+        sim.yee()
+    got = sim.E[1] if comp == "Ey" else sim.B[1]
+    err = np.max(np.abs(got - math.cos(nsteps * w * dt) * mode))
+    assert err < 1e-10, err
+
+
+def test_ck_stable_where_yee_is_not():
+    """At alpha = 0.95 on square 2D cells the Yee update amplifies the grid's
+    highest mode (Courant limit 1/sqrt(2)); the Cole-Karkkainen update keeps
+    random vacuum fields bounded over 2000 steps (its limit is alpha = 1)."""
+    rng = np.random.default_rng(9)
+    E0 = rng.normal(size=(3, 16, 1, 16))
+    B0 = rng.normal(size=(3, 16, 1, 16))
+    peak = {}
+    for solver in ("yee", "ck"):
+        wl = _wl(dims=2, n=(16, 16), alpha=0.95, correction=False, filter=[], solver=solver)
+        sim = _empty_sim(wl)
+        sim.E[:] = E0
+        sim.B[:] = B0
+        e0 = float(np.sum(sim.E ** 2) + np.sum(sim.B ** 2))
+        worst = 1.0
+        for _ in range(2000):
+            sim.yee()
+            worst = max(worst, float(np.sum(sim.E ** 2) + np.sum(sim.B ** 2)) / e0)
+            if worst > 1e6:
+                break
+        peak[solver] = worst
+    assert peak["yee"] > 1e6
+    assert peak["ck"] < 20.0, peak
+
+
 # ---------------------------------------------------------- Boris (textbook)
 
 def _single_particle_sim(dims, B=None, E=None, gamma=3.0, order=1, corr=True):
@@ -399,9 +456,12 @@ def test_gauss_invariant_over_long_run():
 
 # ---------------------------------------------------- brute force (8x8 etc.)
 
-def _brute_pair(dims, n, order, filt, corr=True, npart=10, seed=3, steps=20, interp="galerkin"):
+def _brute_pair(dims, n, order, filt, corr=True, npart=10, seed=3, steps=20, interp="galerkin",
+                solver="yee", alpha=None):
+    if alpha is None:
+        alpha = 0.45 if dims == 2 else 0.4
     wl = _wl(dims=dims, n=n, order=order, correction=corr, filter=list(filt),
-             alpha=0.45 if dims == 2 else 0.4, gamma=3.0, interp=interp)
+             alpha=alpha, gamma=3.0, interp=interp, solver=solver)
     rng = np.random.default_rng(seed)
     x = rng.random((npart, dims)) * np.array(n, float)
     u = rng.normal(size=(npart, 3)) * 0.8 + np.array([0.0, 0.0, 1.5])
@@ -411,7 +471,7 @@ def _brute_pair(dims, n, order, filt, corr=True, npart=10, seed=3, steps=20, int
     s = o.s
     b = BruteSim(dims, o.shape, (s.dx, s.dy, s.dz), s.dt, order, s.q, s.m, s.w,
                  psi_e=o.psi[0] if o.psi else None, psi_b=o.psi[1] if o.psi else None,
-                 filt=filt, jbg=tuple(s.jbg), interp=interp)
+                 filt=filt, jbg=tuple(s.jbg), interp=interp, solver=solver)
     b.E[:] = o.E
     b.B[:] = o.B
     bx, bu = o.x.copy(), o.u.copy()
@@ -439,6 +499,20 @@ def test_oracle_matches_brute_force(dims, n, order, steps, interp):
     for a in range(3):
         dx[a] = np.minimum(dx[a], L[a] - dx[a])
     assert dx.max() < 1e-12
+
+
+@pytest.mark.parametrize("order,interp", [(1, "galerkin"), (3, "galerkin"), (1, "uniform")])
+def test_oracle_ck_matches_brute_force(order, interp):
+    """Full 2D steps with the Cole-Karkkainen solver at alpha = 0.9 against the
+    brute force, whose modified curl is a product of dense matrices."""
+    n = (8, 10)
+    o, b, bx, bu = _brute_pair(2, n, order, (0.25, 0.25, -1.0), steps=15, interp=interp,
+                               solver="ck", alpha=0.9)
+
+    def rel(a, r):
+        return np.linalg.norm(a - r) / np.linalg.norm(r)
+    assert rel(o.E, b.E) < 1e-13 and rel(o.B, b.B) < 1e-13 and rel(o.J, b.J) < 1e-13
+    assert rel(o.u, bu) < 1e-13
 
 
 # --------------------------------------------------------- growth fit
