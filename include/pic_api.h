@@ -65,6 +65,14 @@ extern "C" {
                                  values, and every seen stencil is one cell
                                  wider (filter_npass <= 7) */
 
+/* field solvers (Faraday's law; Ampere's law is always the Yee one) */
+#define PIC_YEE 0             /* textbook Yee */
+#define PIC_CK  1             /* Cole-Karkkainen with beta = 1/8 (named in Secs. 2-4):
+                                 2D, square cells (dx == dz), c dt < dx; every
+                                 forward difference of E in Faraday's law is the
+                                 (1/8, 3/4, 1/8) mean of that difference on its
+                                 line and the two neighbouring lines across it */
+
 #define PIC_FP64 0            /* fields, offsets, momenta and J in double */
 #define PIC_FP32 1            /* float fields/offsets/momenta, int32 cell index,
                                  J accumulated as 64-bit fixed point */
@@ -115,6 +123,8 @@ typedef struct pic_config {
     int    trace_capacity;    /* steps of per-step field-energy trace kept on the device */
     int    adjoint_steps;     /* longest gradient run pic_wperp_gradient may do (0: none) */
     int    adjoint_ckpt;      /* checkpoint interval of gradient runs (steps, >= 1) */
+    int    solver;            /* PIC_YEE or PIC_CK; equal for all instances; the
+                                 reverse sweep needs PIC_YEE */
 } pic_config;
 
 /* particles of one instance as host float64 arrays (structure of arrays) */

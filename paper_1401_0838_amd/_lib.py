@@ -22,6 +22,7 @@ PIC_EUNSUPPORTED = -8
 PIC_ESTATE = -9
 
 PIC_GALERKIN, PIC_UNIFORM, PIC_MOMENTUM = 0, 1, 2
+PIC_YEE, PIC_CK = 0, 1
 PIC_FP64, PIC_FP32 = 0, 1
 PIC_IONS_CHARGE, PIC_IONS_CHARGE_AND_CURRENT = 0, 1
 PIC_FIELD_E, PIC_FIELD_B, PIC_FIELD_J, PIC_FIELD_SEEN_E, PIC_FIELD_SEEN_B, PIC_FIELD_RHO = range(6)
@@ -40,7 +41,8 @@ class pic_config(C.Structure):
                 ("filter_npass", C.c_int), ("filter_w", C.c_double * 8),
                 ("q", C.c_double), ("m", C.c_double), ("weight", C.c_double),
                 ("ion_mode", C.c_int), ("tile", C.c_int * 3), ("block", C.c_int),
-                ("trace_capacity", C.c_int), ("adjoint_steps", C.c_int), ("adjoint_ckpt", C.c_int)]
+                ("trace_capacity", C.c_int), ("adjoint_steps", C.c_int), ("adjoint_ckpt", C.c_int),
+                ("solver", C.c_int)]
 
 
 class pic_particles(C.Structure):

@@ -113,8 +113,16 @@ int validate(const pic_config &c, int idx)
         return bad(PIC_EINVAL, "3D cell counts must be <= 2048 x 1024 x 2048 (packed int32 cell index)");
     if (!(c.dx > 0) || !(c.dz > 0) || (c.dims == 3 && !(c.dy > 0))) return bad(PIC_EINVAL, "cell sizes must be > 0");
     if (!(c.cdt > 0)) return bad(PIC_EINVAL, "c dt must be > 0");
-    double s = 1.0 / (c.dx * c.dx) + 1.0 / (c.dz * c.dz) + (c.dims == 3 ? 1.0 / (c.dy * c.dy) : 0.0);
-    if (c.cdt * std::sqrt(s) >= 1.0) return bad(PIC_ECOURANT, "Courant limit c dt < 1/sqrt(sum 1/d^2) violated");
+    if (c.solver != PIC_YEE && c.solver != PIC_CK) return bad(PIC_EINVAL, "solver must be PIC_YEE or PIC_CK");
+    if (c.solver == PIC_CK) {
+        if (c.dims != 2) return bad(PIC_EUNSUPPORTED, "the Cole-Karkkainen solver is built for 2D");
+        if (c.dx != c.dz) return bad(PIC_EUNSUPPORTED, "the Cole-Karkkainen solver needs square cells (dx == dz)");
+        if (c.cdt >= c.dx) return bad(PIC_ECOURANT, "Cole-Karkkainen limit c dt < dx violated");
+        if (c.adjoint_steps > 0) return bad(PIC_EUNSUPPORTED, "the reverse sweep is built for the Yee solver only");
+    } else {
+        double s = 1.0 / (c.dx * c.dx) + 1.0 / (c.dz * c.dz) + (c.dims == 3 ? 1.0 / (c.dy * c.dy) : 0.0);
+        if (c.cdt * std::sqrt(s) >= 1.0) return bad(PIC_ECOURANT, "Courant limit c dt < 1/sqrt(sum 1/d^2) violated");
+    }
     if (c.shape_order != 1 && c.shape_order != 3) return bad(PIC_EINVAL, "shape_order must be 1 or 3");
     if (c.interp != PIC_GALERKIN && c.interp != PIC_UNIFORM && c.interp != PIC_MOMENTUM)
         return bad(PIC_EINVAL, "interp must be PIC_GALERKIN, PIC_UNIFORM or PIC_MOMENTUM");
@@ -177,6 +185,7 @@ std::vector<double> filter_taps(const pic_config &c)
 struct pic_state {
     int n_inst = 0, dims = 2, order = 1, fp32 = 1;
     int gather = GATHER_GALERKIN;    // gather scheme of every instance
+    int ck = 0;                      // Cole-Karkkainen solver (every instance)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     char *arena = nullptr;
@@ -232,6 +241,7 @@ LaunchCtx ctx(const pic_state *s)
     c.par = s->parity;
     c.single = s->n_inst == 1;
     c.gather = s->gather;
+    c.ck = s->ck;
     if (!s->desc.empty()) {
         const InstDesc &d0 = s->desc[0];
         c.hz = d0.hz; c.hx = d0.hx; c.hzf = d0.hzf; c.psi_deg = d0.psi_deg;
@@ -841,9 +851,9 @@ extern "C" int pic_plan(const pic_config *cfgs, int n_inst, const int64_t *n_par
         if (rc) return rc;
         if (cfgs[i].dims != cfgs[0].dims || cfgs[i].precision != cfgs[0].precision ||
             cfgs[i].shape_order != cfgs[0].shape_order || cfgs[i].adjoint_steps != cfgs[0].adjoint_steps ||
-            cfgs[i].interp != cfgs[0].interp ||
+            cfgs[i].interp != cfgs[0].interp || cfgs[i].solver != cfgs[0].solver ||
             (cfgs[0].adjoint_steps > 0 && cfgs[i].adjoint_ckpt != cfgs[0].adjoint_ckpt))
-            return fail(PIC_EINVAL, "all instances must share dims, precision, shape_order, interp and adjoint sizes");
+            return fail(PIC_EINVAL, "all instances must share dims, precision, shape_order, interp, solver and adjoint sizes");
         if (n_particles[i] < 0 || n_particles[i] > INT32_MAX) return fail(PIC_EINVAL, "particle count");
     }
     const std::vector<pic_config> rc = resolve_tiles(cfgs, n_inst);
@@ -876,6 +886,7 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
     s->dims = cfgs[0].dims;
     s->order = cfgs[0].shape_order;
     s->fp32 = cfgs[0].precision == PIC_FP32;
+    s->ck = cfgs[0].solver == PIC_CK;
     s->gather = cfgs[0].interp == PIC_UNIFORM ? GATHER_UNIFORM
               : cfgs[0].interp == PIC_MOMENTUM ? GATHER_NODAL : GATHER_GALERKIN;
     s->cfg.assign(cfgs, cfgs + n_inst);

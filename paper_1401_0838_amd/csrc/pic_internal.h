@@ -134,6 +134,7 @@ struct LaunchCtx {
     int par = 0;
     int single = 0;                   // one instance: 2D field kernels take tile = block index
     int gather = GATHER_GALERKIN;     // gather scheme shared by every instance
+    int ck = 0;                       // 2D Cole-Karkkainen curl in Faraday's law (every instance)
 };
 
 int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork);

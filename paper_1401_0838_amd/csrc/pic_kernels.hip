@@ -616,17 +616,26 @@ __global__ void __launch_bounds__(256) k_yee_e(const InstDesc *__restrict__ Dt, 
 // relative to the tile origin (x0, z0):
 //   E^{n-1} on [-1, T+1], B^{n-1} on [-1, T], J on [0, T]
 // B^{n-1/2} is formed on [-1, T], E^n on [0, T], B^n and the stores on [0, T).
+// CK: the Cole-Karkkainen curl in Faraday's law (2D, square cells): each
+// forward difference of E is the (1/8, 3/4, 1/8) mean of that difference on
+// its line and on the two neighbouring lines across it.  The window grows by
+// two cells on the low side: E^{n-1} on [-3, T+1], B^{n-1/2} formed on
+// [-2, T], E^n on [-1, T].
 #define YEE_TX PIC_YEE_TX
 
-template <class R, int TZ>
+template <class R, int TZ, bool CK = false>
 __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int par)
 {
     typedef typename JOf<R>::T JT;
     constexpr int TX = YEE_TX;
     static_assert(TX == 64, "one lane per column");
-    // one window for all nine planes: cells [x0 - 1, x0 + TX + 2) x [z0 - 1, z0 + TZ + 2);
-    // waves own rows, lanes own columns (lane, and 64 + lane for the last three)
-    constexpr int WX = TX + 3, WZ = TZ + 3, WN = WX * WZ;
+    // one window for all nine planes: cells [x0 - LO, x0 + TX + 2) x [z0 - LO, z0 + TZ + 2);
+    // waves own rows, lanes own columns (lane, and 64 + lane for the last few)
+    constexpr int LO = CK ? 3 : 1;
+    constexpr int WX = TX + LO + 2, WZ = TZ + LO + 2, WN = WX * WZ;
+    // local ranges: B^{n-1/2} on [ELO - 1, EH), E^n on [ELO, EH), the tile on [LO, T + LO)
+    constexpr int ELO = CK ? LO - 1 : LO;
+    constexpr int EHZ = TZ + LO + 1, EHX = TX + LO + 1;
     __shared__ R sE[3][WN], sB[3][WN], sJ[3][WN];
     // work == nullptr: one instance, block b is tile b (saves a dependent load)
     const int inst = work ? work[blockIdx.x].x : 0, t = work ? work[blockIdx.x].y : (int)blockIdx.x;
@@ -648,8 +657,8 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
                   G<R>(D.B[po][0]), G<R>(D.B[po][1]), G<R>(D.B[po][2])};
     const double jq = D.jq, jb[3] = {D.jbg[0], D.jbg[1], D.jbg[2]};
     const bool hasb = lane < WX - TX;
-    const int gxa = wrap_near(x0 - 1 + lane, nx);
-    const int gxb = hasb ? wrap_near(x0 - 1 + TX + lane, nx) : gxa;
+    const int gxa = wrap_near(x0 - LO + lane, nx);
+    const int gxb = hasb ? wrap_near(x0 - LO + TX + lane, nx) : gxa;
     constexpr int RW = (WZ + 3) / 4;   // rows per wave with four waves
     for (int r0 = wave; r0 < WZ; r0 += RW * nwave) {
         R ve[RW][2][3], vb[RW][2][3];
@@ -657,7 +666,7 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
 #pragma unroll
         for (int u = 0; u < RW; u++) {
             const int row = min(r0 + u * nwave, WZ - 1);
-            const int base = wrap_near(z0 - 1 + row, nz) * nx;
+            const int base = wrap_near(z0 - LO + row, nz) * nx;
 #pragma unroll
             for (int h = 0; h < 2; h++) {
                 const int g = base + (h ? gxb : gxa);
@@ -684,27 +693,43 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
     }
     __syncthreads();
     const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
-    // B^{n-1/2} on local rows and columns [0, T + 2): forward differences of E
-    for (int lz = wave; lz < TZ + 2; lz += nwave) {
+    // Faraday's forward differences at window cell e: Yee, or averaged across
+    // the difference's direction with (1/8, 3/4, 1/8)
+    auto fdx = [&](const R *F, int e) {
+        if constexpr (CK)
+            return (R(0.75) * (F[e + 1] - F[e]) +
+                    R(0.125) * ((F[e + 1 - WX] - F[e - WX]) + (F[e + 1 + WX] - F[e + WX]))) * idx;
+        else
+            return (F[e + 1] - F[e]) * idx;
+    };
+    auto fdz = [&](const R *F, int e) {
+        if constexpr (CK)
+            return (R(0.75) * (F[e + WX] - F[e]) +
+                    R(0.125) * ((F[e - 1 + WX] - F[e - 1]) + (F[e + 1 + WX] - F[e + 1]))) * idz;
+        else
+            return (F[e + WX] - F[e]) * idz;
+    };
+    // B^{n-1/2} on local rows and columns [ELO - 1, EH): forward differences of E
+    for (int lz = ELO - 1 + wave; lz < EHZ; lz += nwave) {
 #pragma unroll
         for (int hh = 0; hh < 2; hh++) {
-            const int lx = hh ? TX + lane : lane;
-            if (lx >= TX + 2) break;
-            const int e = lz * WX + lx, ex = e + 1, ez = e + WX;
-            const R dzEy = (sE[1][ez] - sE[1][e]) * idz, dzEx = (sE[0][ez] - sE[0][e]) * idz;
-            const R dxEz = (sE[2][ex] - sE[2][e]) * idx, dxEy = (sE[1][ex] - sE[1][e]) * idx;
+            const int lx = ELO - 1 + (hh ? TX : 0) + lane;
+            if (lx >= EHX) break;
+            const int e = lz * WX + lx;
+            const R dzEy = fdz(sE[1], e), dzEx = fdz(sE[0], e);
+            const R dxEz = fdx(sE[2], e), dxEy = fdx(sE[1], e);
             sB[0][e] -= h * (-dzEy);
             sB[1][e] -= h * (dzEx - dxEz);
             sB[2][e] -= h * dxEy;
         }
     }
     __syncthreads();
-    // E^n on local [1, T + 2): backward differences of B^{n-1/2}
-    for (int lz = 1 + wave; lz < TZ + 2; lz += nwave) {
+    // E^n on local [ELO, EH): backward differences of B^{n-1/2}
+    for (int lz = ELO + wave; lz < EHZ; lz += nwave) {
 #pragma unroll
         for (int hh = 0; hh < 2; hh++) {
-            const int lx = hh ? TX + 1 + lane : 1 + lane;
-            if (lx >= TX + 2) break;
+            const int lx = ELO + (hh ? TX : 0) + lane;
+            if (lx >= EHX) break;
             const int e = lz * WX + lx, exm = e - 1, ezm = e - WX;
             const R dzBy = (sB[1][e] - sB[1][ezm]) * idz, dzBx = (sB[0][e] - sB[0][ezm]) * idz;
             const R dxBz = (sB[2][e] - sB[2][exm]) * idx, dxBy = (sB[1][e] - sB[1][exm]) * idx;
@@ -720,9 +745,9 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
     for (int lz = wave; lz < TZ; lz += nwave) {
         const int gz = z0 + lz;
         if (gz >= nz) break;
-        const int e = (lz + 1) * WX + lane + 1, ex = e + 1, ez = e + WX;
-        const R dzEy = (sE[1][ez] - sE[1][e]) * idz, dzEx = (sE[0][ez] - sE[0][e]) * idz;
-        const R dxEz = (sE[2][ex] - sE[2][e]) * idx, dxEy = (sE[1][ex] - sE[1][e]) * idx;
+        const int e = (lz + LO) * WX + lane + LO;
+        const R dzEy = fdz(sE[1], e), dzEx = fdz(sE[0], e);
+        const R dxEz = fdx(sE[2], e), dxEy = fdx(sE[1], e);
         const int g = gz * nx + gx;
         const R b0 = sB[0][e] - h * (-dzEy), b1 = sB[1][e] - h * (dzEx - dxEz), b2 = sB[2][e] - h * dxEy;
         O[3][g] = b0; O[4][g] = b1; O[5][g] = b2;
@@ -1262,17 +1287,23 @@ inline int hip_ok(hipError_t e) { return e == hipSuccess ? 0 : -1; }
 #define DISPATCH_R(fp32, ...) \
     do { if (fp32) { typedef float R; __VA_ARGS__; } else { typedef double R; __VA_ARGS__; } } while (0)
 
-template <class R> void launch_yee_2d(const LaunchCtx &c, const int2 *ywork, int nywork)
+template <class R, bool CK> void launch_yee_2d_s(const LaunchCtx &c, const int2 *ywork, int nywork)
 {
     const dim3 g(nywork), b(PIC_FIELD_CHUNK);
     if (c.single) ywork = nullptr;
-    if (c.yee_tz == 4) k_yee_2d<R, 4><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);
+    if (c.yee_tz == 4) k_yee_2d<R, 4, CK><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);
     else if constexpr (sizeof(R) == 4) {
-        if (c.yee_tz == 16) k_yee_2d<R, 16><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);
-        else k_yee_2d<R, 8><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);
+        if (c.yee_tz == 16) k_yee_2d<R, 16, CK><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);
+        else k_yee_2d<R, 8, CK><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);
     } else {
-        k_yee_2d<R, 8><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);   // 16 rows of doubles exceed the LDS
+        k_yee_2d<R, 8, CK><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);   // 16 rows of doubles exceed the LDS
     }
+}
+
+template <class R> void launch_yee_2d(const LaunchCtx &c, const int2 *ywork, int nywork)
+{
+    if (c.ck) launch_yee_2d_s<R, true>(c, ywork, nywork);
+    else launch_yee_2d_s<R, false>(c, ywork, nywork);
 }
 
 int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork)

@@ -41,6 +41,7 @@ def make_config(wl, precision=None, tile=None, block=0, trace_capacity=0, psi=No
     c.shape_order = int(wl["order"])
     c.interp = {"galerkin": L.PIC_GALERKIN, "uniform": L.PIC_UNIFORM,
                 "momentum": L.PIC_MOMENTUM}[wl.get("interp", "galerkin")]
+    c.solver = {"yee": L.PIC_YEE, "ck": L.PIC_CK}[wl.get("solver", "yee")]
     prec = precision or wl.get("precision", "fp32")
     c.precision = L.PIC_FP32 if prec == "fp32" else L.PIC_FP64
     c.correction = 1 if wl.get("correction") else 0

@@ -11,7 +11,7 @@ axis (0.25 = bilinear, -1 = compensation).
 """
 import numpy as np
 
-_COMMON = dict(q=-1.0, m=1.0, omega_p=0.1, interp="galerkin", ion_mode=1)
+_COMMON = dict(q=-1.0, m=1.0, omega_p=0.1, interp="galerkin", solver="yee", ion_mode=1)
 
 BINOMIAL4 = [0.25, 0.25, 0.25, 0.25]
 PAPER_EQ6 = [0.25, 0.25, -1.0, -1.0]      # two bilinear + two compensation passes
@@ -30,6 +30,11 @@ WORKLOADS = {
     "beam3d_128x128x256": dict(_COMMON, dims=3, n=(128, 128, 256), alpha=0.5, gamma=130.0,
                                ppc=8, order=3, correction=True, filter=BINOMIAL4,
                                precision="fp32", steps=500, seeds=(0,), sigma=1e-6),
+    # Sec. 3 setting: 128x128, cubic shapes, Cole-Karkkainen solver (beta = 1/8),
+    # correction + the Eq. 6 filter, gamma 130, c dt / dz up to ~1
+    "beam2d_128_ck": dict(_COMMON, dims=2, n=(128, 128), alpha=0.9, alphas=(0.5, 0.7, 0.9, 0.99),
+                          gamma=130.0, ppc=16, order=3, correction=True, filter=PAPER_EQ6,
+                          solver="ck", precision="fp32", steps=2000, seeds=(0,), sigma=1e-6),
     # 256x256 differentiation case, FP32 forward, 200 steps, checkpoints every 20
     "beam2d_256_adjoint": dict(_COMMON, dims=2, n=(256, 256), alpha=0.5, gamma=130.0, ppc=8,
                                order=1, correction=True, filter=BINOMIAL4, precision="fp32",

@@ -101,6 +101,25 @@ def test_plan_validates_configs():
     with pytest.raises(L.PicError) as e:
         L.pic_plan([c], [16])
     assert e.value.code == L.PIC_EUNSUPPORTED
+    # Cole-Karkkainen: 2D square cells, c dt < dx, shared by a batch, forward only
+    assert L.pic_plan([_cfg(solver="ck", alpha=0.95)], [16]) > 0
+    with pytest.raises(L.PicError) as e:
+        L.pic_plan([_cfg(solver="ck", alpha=1.0)], [16])
+    assert e.value.code == L.PIC_ECOURANT
+    with pytest.raises(L.PicError) as e:
+        L.pic_plan([_cfg(solver="ck", d=(1.0, 0.8))], [16])
+    assert e.value.code == L.PIC_EUNSUPPORTED
+    with pytest.raises(L.PicError) as e:
+        L.pic_plan([_cfg(solver="ck", dims=3, n=(8, 8, 8))], [16])
+    assert e.value.code == L.PIC_EUNSUPPORTED
+    with pytest.raises(L.PicError) as e:
+        L.pic_plan([_cfg(), _cfg(solver="ck")], [16, 16])
+    assert e.value.code == L.PIC_EINVAL
+    c = _cfg(solver="ck")
+    c.adjoint_steps, c.adjoint_ckpt = 4, 2
+    with pytest.raises(L.PicError) as e:
+        L.pic_plan([c], [16])
+    assert e.value.code == L.PIC_EUNSUPPORTED
     with pytest.raises(L.PicError):
         L.pic_plan([_cfg(), _cfg(dims=3, n=(8, 8, 8))], [16, 16])
 
