@@ -188,6 +188,36 @@ def schemes_block(steps, warmup):
     return out
 
 
+def ck_block(steps, warmup):
+    """Cole-Karkkainen solver (2D, beta = 1/8), FP32: the 512x512 x 16 ppc step at
+    alpha = 0.9 (above the Yee limit 1/sqrt(2)), and the Sec. 3 setting
+    (128x128 x 16 ppc, cubic shapes, Eq. 6 filter, correction, alpha = 0.9)."""
+    import pic_inputs as pi
+    from paper_1401_0838_amd.sim import Simulation
+    out = {}
+    cases = (("beam2d_512_alpha0.9", pi.workload("beam2d_512", alpha=0.9, solver="ck")),
+             ("beam2d_128_cubic_eq6", pi.workload("beam2d_128_ck")))
+    for name, wl in cases:
+        x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], wl["sigma"], 0)
+        sim = Simulation(wl, (x, u), precision="fp32")
+        sim.set_schedule("batched", True)
+        n_part, n_cells = x.shape[0], wl["n"][0] * wl["n"][1]
+        sim.step(warmup)
+        sim.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.synchronize()
+        dt = time.perf_counter() - t0
+        prof = sim.profile(10)
+        sim.close()
+        pk = particle_kernel_bytes(n_part, n_cells)
+        out[name] = {"particles": n_part, "particle_steps_per_s": n_part * steps / dt,
+                     "ms_per_step": 1e3 * dt / steps,
+                     "kernels_ms": {k: prof[k] for k in ("yee_ms", "seen_ms", "particle_ms", "step_ms")},
+                     "particle_kernel_hbm_frac": pk / (prof["particle_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
+
+
 def adjoint_block():
     """256x256, 8 ppc, 200 steps, checkpoints every 20 (FP32): backward (recompute +
     reverse sweep) time over forward time."""
@@ -247,9 +277,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 512x512 case")
     ap.add_argument("--no-schemes", action="store_true",
                     help="skip the Uniform and momentum-conserving gather cases")
+    ap.add_argument("--no-ck", action="store_true", help="skip the Cole-Karkkainen solver cases")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling HBM counters)")
-    ap.add_argument("--only", choices=("batched", "adjoint", "3d", "fp64", "schemes"),
+    ap.add_argument("--only", choices=("batched", "adjoint", "3d", "fp64", "schemes", "ck"),
                     help="run one secondary block alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -258,7 +289,7 @@ def main():
     if args.only:
         blk = {"batched": lambda: batched_block(max(20, args.steps // 4), 5), "adjoint": adjoint_block,
                "3d": lambda: beam3d_block(20, 3), "fp64": lambda: fp64_block(50, 5),
-               "schemes": lambda: schemes_block(100, 10)}[args.only]()
+               "schemes": lambda: schemes_block(100, 10), "ck": lambda: ck_block(100, 10)}[args.only]()
         print(json.dumps({args.only: blk}), flush=True)
         return
     if args.gpus != 1:
@@ -335,6 +366,8 @@ def main():
         out["beam2d_fp64"] = fp64_block(50, 5)
     if not args.no_schemes:
         out["schemes"] = schemes_block(100, 10)
+    if not args.no_ck:
+        out["ck"] = ck_block(100, 10)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, x, u, args.cpu_steps)
     print(json.dumps(out), flush=True)
