@@ -218,6 +218,35 @@ def ck_block(steps, warmup):
     return out
 
 
+def gamma_scan_block(steps):
+    """Sec. 3 growth-rate scan through the batched engine: the 128x128 x 16 ppc
+    cubic CK setting with the Eq. 6 filter, gamma in {3, 10, 30, 130} x alpha in
+    {0.3 .. 0.99}, with and without the correction, FP32, `steps` steps per batch.
+    Reports the scan's throughput, each gamma's peak growth rate and the fitted
+    power of gamma (the paper reads about -1/2 for its peaks)."""
+    import pic_inputs as pi
+    from paper_1401_0838_amd import scan
+    alphas = [0.3, 0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 0.99]
+    gammas = [3.0, 10.0, 30.0, 130.0]
+    out = {"workload": "beam2d_128_ck (128x128, 16 ppc, cubic, CK, Eq. 6 filter)", "steps": steps,
+           "alphas": alphas, "gammas": gammas}
+    for corr in (True, False):
+        base = pi.workload("beam2d_128_ck", correction=corr)
+        pts, wls, parts, skipped = scan.scan_instances(base, alphas, gammas)
+        n_part = sum(p[0].shape[0] for p in parts)
+        t0 = time.perf_counter()
+        traces, wkin = scan.run_scan(pts, wls, parts, steps, "fp32")
+        dt = time.perf_counter() - t0
+        rates, peaks, power = scan.growth_table(pts, traces, wkin)
+        key = "corrected" if corr else "uncorrected"
+        out[key] = {"instances": len(pts), "skipped": skipped,
+                    "particle_steps_per_s": n_part * steps / dt, "wall_s": dt,
+                    "growth_rates": {"%g/%g" % p: r for p, r in zip(pts, rates)},
+                    "peak_growth": {"%g" % g: {"rate": v[0], "alpha": v[1]} for g, v in sorted(peaks.items())},
+                    "peak_power_of_gamma": power}
+    return out
+
+
 def adjoint_block():
     """256x256, 8 ppc, 200 steps, checkpoints every 20 (FP32): backward (recompute +
     reverse sweep) time over forward time."""
@@ -278,9 +307,10 @@ def main():
     ap.add_argument("--no-schemes", action="store_true",
                     help="skip the Uniform and momentum-conserving gather cases")
     ap.add_argument("--no-ck", action="store_true", help="skip the Cole-Karkkainen solver cases")
+    ap.add_argument("--no-scan", action="store_true", help="skip the gamma / alpha growth-rate scan")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling HBM counters)")
-    ap.add_argument("--only", choices=("batched", "adjoint", "3d", "fp64", "schemes", "ck"),
+    ap.add_argument("--only", choices=("batched", "adjoint", "3d", "fp64", "schemes", "ck", "scan"),
                     help="run one secondary block alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -289,7 +319,8 @@ def main():
     if args.only:
         blk = {"batched": lambda: batched_block(max(20, args.steps // 4), 5), "adjoint": adjoint_block,
                "3d": lambda: beam3d_block(20, 3), "fp64": lambda: fp64_block(50, 5),
-               "schemes": lambda: schemes_block(100, 10), "ck": lambda: ck_block(100, 10)}[args.only]()
+               "schemes": lambda: schemes_block(100, 10), "ck": lambda: ck_block(100, 10),
+               "scan": lambda: gamma_scan_block(2000)}[args.only]()
         print(json.dumps({args.only: blk}), flush=True)
         return
     if args.gpus != 1:
@@ -368,6 +399,8 @@ def main():
         out["schemes"] = schemes_block(100, 10)
     if not args.no_ck:
         out["ck"] = ck_block(100, 10)
+    if not args.no_scan:
+        out["gamma_scan"] = gamma_scan_block(2000)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, x, u, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -102,6 +102,10 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libpic.so not built: run paper_1401_0838_amd/build.py (%s)" % LIB_PATH)
+        # torch first: libpic.so must bind to the HIP runtime torch brings into the
+        # process.  Loaded before torch, it would pull in a second HIP runtime
+        # that sees no device once torch has initialised its own.
+        import torch  # noqa: F401
         lib = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(lib, name)

@@ -905,7 +905,12 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
     }
     auto bail = [&](int code) { pic_destroy(s); return code; };
     layout(s, cfgs, n_inst, np.data(), s->arena);
-    if (hipMemsetAsync(s->arena, 0, need - 256, s->stream) != hipSuccess) return bail(fail(PIC_EHIP, "arena clear"));
+    {
+        const hipError_t e = hipMemsetAsync(s->arena, 0, need - 256, s->stream);
+        if (e != hipSuccess)
+            return bail(fail(PIC_EHIP, std::string("arena clear (") + std::to_string(need - 256) + " bytes): " +
+                                           hipGetErrorString(e)));
+    }
     s->block = cfgs[0].block ? cfgs[0].block : default_block();
     // largest LDS window over the instances
     int maxsm = 0;

@@ -142,3 +142,23 @@ def test_default_tiles_shrink_only_for_small_batches():
     assert plan((512, 512)) == plan((512, 512), tile=(16, 1, 16))
     assert plan((256, 256), count=4) == plan((256, 256), tile=(16, 1, 16), count=4)
     assert plan((256, 256), count=3) == plan((256, 256), tile=(8, 1, 8), count=3)
+
+
+def test_scan_growth_table_on_synthetic_traces():
+    """Peak over alpha per gamma and the fitted power of gamma, on traces that
+    grow as exp(2 Gamma t) with Gamma = 0.01 gamma^-0.5 at the best alpha."""
+    from paper_1401_0838_amd import scan
+    pts, traces, wkin = [], [], []
+    for g in (3.0, 10.0, 30.0, 130.0):
+        for a, f in ((0.5, 0.6), (0.7, 1.0), (0.9, 0.8)):
+            gam = 0.01 * g ** -0.5 * f
+            t = np.arange(3000) * a
+            pts.append((g, a))
+            traces.append(1e-6 * np.exp(2 * gam * t))
+            wkin.append(1e30)
+    rates, peaks, power = scan.growth_table(pts, traces, wkin)
+    for (g, a), r in zip(pts, rates):
+        f = {0.5: 0.6, 0.7: 1.0, 0.9: 0.8}[a]
+        assert abs(r - 0.01 * g ** -0.5 * f) < 1e-9
+    assert all(peaks[g][1] == 0.7 for g in peaks)
+    assert abs(power + 0.5) < 1e-9

@@ -138,3 +138,42 @@ def test_batched_scan_growth_rates_fp32_vs_fp64():
             bad.append((i, w["n"], w["alpha"], w["gamma"], g32, g64))
     _say("  mismatches: %s" % bad)
     assert not bad
+
+
+def test_growth_rate_ck_cubic_eq6_vs_oracle():
+    """The Sec. 3 setting (cubic, CK, Eq. 6 filter, correction) at 32x32, 4 ppc,
+    alpha = 0.9: the GPU traces follow the oracle and the fitted rates agree."""
+    wl = pi.workload("beam2d_128_ck", n=(32, 32), ppc=4, alpha=0.9, correction=False)
+    x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], wl["sigma"], 0)
+    n = 400
+    Wo, wk = _oracle_trace(wl, x, u, n)
+    go, _ = ofit.growth_rate(list(Wo), wl["alpha"], wk)
+    for prec in ("fp64", "fp32"):
+        Wg, wkg = _gpu_trace(wl, x, u, prec, n)
+        gg, win = gfit.growth_rate(Wg, wl["alpha"], wkg)
+        _say("ck cubic eq6 %s: Gamma gpu %.6e oracle %.6e window %s" % (prec, gg, go, win))
+        if prec == "fp64":
+            assert np.max(np.abs(Wg - Wo)) < 1e-9 * np.max(Wo)
+        assert _close(gg, go, Wo, wl["alpha"])
+
+
+def test_gamma_scan_growth_rates_fp32_vs_fp64():
+    """A gamma x alpha scan at the Sec. 3 setting (64x64, 8 ppc, cubic, CK, Eq. 6
+    filter; gamma 3 and 130, alpha 0.5 and 0.9, with and without correction),
+    1000 steps in one batched run per precision: every FP32 growth rate equals
+    its FP64 one (same bar)."""
+    from paper_1401_0838_amd import scan
+    bad = []
+    for corr in (True, False):
+        base = pi.workload("beam2d_128_ck", n=(64, 64), ppc=8, correction=corr)
+        pts, wls, parts, skipped = scan.scan_instances(base, [0.5, 0.9], [3.0, 130.0])
+        tr32, wk32 = scan.run_scan(pts, wls, parts, 1000, "fp32")
+        tr64, wk64 = scan.run_scan(pts, wls, parts, 1000, "fp64")
+        r32, _, _ = scan.growth_table(pts, tr32, wk64)
+        r64, peaks, power = scan.growth_table(pts, tr64, wk64)
+        _say("gamma scan corr=%s: fp64 rates %s peaks %s power %s" % (corr, r64, peaks, power))
+        for p, g32, g64, W in zip(pts, r32, r64, tr64):
+            if not _close(g32, g64, W, p[1]):
+                bad.append((corr, p, g32, g64))
+    _say("  mismatches: %s" % bad)
+    assert not bad
