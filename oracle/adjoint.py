@@ -58,6 +58,8 @@ def reverse(sim, tape, lE, lB, lJ, lx, lu):
         raise NotImplementedError("reverse sweep of the momentum-conserving gather")
     if sim.s.solver != 0:
         raise NotImplementedError("reverse sweep of the Cole-Karkkainen solver")
+    if sim.s.correction == 2:
+        raise NotImplementedError("reverse sweep of the exact Psi_E / Psi_B ratio")
     lib = _lib()
     grad = np.zeros(max(1, sim.s.psi_deg + 1))
     lEt = np.zeros_like(sim.E)

@@ -49,7 +49,7 @@ class BruteSim:
     STAG_B = ((0, 1, 1), (1, 0, 1), (1, 1, 0))
 
     def __init__(self, dims, shape, d, dt, order, q, m, w, psi_e=None, psi_b=None,
-                 filt=(), jbg=(0.0, 0.0, 0.0), interp="galerkin", solver="yee"):
+                 filt=(), jbg=(0.0, 0.0, 0.0), interp="galerkin", solver="yee", ratio=False):
         self.dims = dims
         self.shape = tuple(shape)                 # (nz, ny, nx)
         self.d = tuple(d)                         # (dx, dy, dz)
@@ -58,6 +58,7 @@ class BruteSim:
         self.filt = list(filt)
         self.jbg = np.asarray(jbg, dtype=np.float64)
         self.interp = interp
+        self.ratio = ratio
         nz, ny, nx = self.shape
         self.N = nx * ny * nz
         self.E = np.zeros((3,) + self.shape)
@@ -124,6 +125,14 @@ class BruteSim:
 
     def seen(self):
         pe, pb = self.psi_e, self.psi_b
+        if self.ratio:
+            # Psi_E / Psi_B as one Fourier multiplier on the transverse E only
+            sz, filt = self._symbols()
+            mult = sum(a * sz ** j for j, a in enumerate(pe)) / sum(b * sz ** j for j, b in enumerate(pb))
+            Et = np.stack([np.real(np.fft.ifftn(np.fft.fftn(self.E[c]) * mult * filt)) for c in range(2)]
+                          + [self.seen_plane(self.E[2], None)])
+            Bt = np.stack([self.seen_plane(self.B[c], None) for c in range(3)])
+            return Et, Bt
         Et = np.stack([self.seen_plane(self.E[0], pe), self.seen_plane(self.E[1], pe),
                        self.seen_plane(self.E[2], pb)])
         Bt = np.stack([self.seen_plane(self.B[c], pb) for c in range(3)])

@@ -37,7 +37,8 @@ typedef struct {
     int interp;               /* 0 Galerkin, 1 Uniform, 2 momentum-conserving */
     int solver;               /* 0 Yee, 1 Cole-Karkkainen (2D, square cells) */
     double q, m, w;           /* charge, mass, macro-particle weight */
-    int correction;           /* 1: apply Psi_E / Psi_B */
+    int correction;           /* 0 none; 1 Psi_E on transverse E, Psi_B on the rest;
+                                 2 the ratio Psi_E / Psi_B on transverse E only */
     int psi_deg;              /* polynomial degree of Psi (<= 8) */
     double psi_e[9], psi_b[9];/* power-series coefficients in s = sin^2(kz dz/2) */
     int nfilt;                /* number of 3-point passes per axis (<= 16) */
@@ -182,9 +183,71 @@ static void filter_pass(const OSim *s, int axis, double wt, const double *in, do
             }
 }
 
+/* F <- Psi(S_z)^{-1} F along z.  Sec. 2 names this the inversion of the
+ * denominator by tri-diagonal solves; written here as what it computes: for
+ * every z column, the dense nz x nz matrix Psi(S_z) = sum_j c_j S_z^j (S_z the
+ * periodic -(1/4)(1, -2, 1) matrix) is LU-factored with partial pivoting and
+ * solved, which is exact up to rounding and obviously so. */
+static void solve_psi_z(const OSim *s, const double *coef, double *F)
+{
+    const long n = s->nz;
+    double *M = calloc((size_t)(n * n), sizeof(double));
+    double *P = calloc((size_t)(n * n), sizeof(double));
+    double *Q = calloc((size_t)(n * n), sizeof(double));
+    double *col = malloc((size_t)n * sizeof(double));
+    long *perm = malloc((size_t)n * sizeof(long));
+    for (long r = 0; r < n; r++) {
+        P[r * n + r] = 1.0;
+        M[r * n + r] = coef[0];
+    }
+    for (int j = 1; j <= s->psi_deg; j++) {
+        /* P <- S_z P, row r of S_z: -1/4 at r-1, 1/2 at r, -1/4 at r+1 (periodic) */
+        for (long r = 0; r < n; r++)
+            for (long c = 0; c < n; c++)
+                Q[r * n + c] = -0.25 * P[wrap(r - 1, n) * n + c] + 0.5 * P[r * n + c] - 0.25 * P[wrap(r + 1, n) * n + c];
+        memcpy(P, Q, (size_t)(n * n) * sizeof(double));
+        for (long q = 0; q < n * n; q++) M[q] += coef[j] * P[q];
+    }
+    /* LU with partial pivoting, in place */
+    for (long r = 0; r < n; r++) perm[r] = r;
+    for (long c = 0; c < n; c++) {
+        long piv = c;
+        for (long r = c + 1; r < n; r++)
+            if (fabs(M[r * n + c]) > fabs(M[piv * n + c])) piv = r;
+        if (piv != c) {
+            for (long q = 0; q < n; q++) {
+                double t = M[c * n + q];
+                M[c * n + q] = M[piv * n + q];
+                M[piv * n + q] = t;
+            }
+            long t = perm[c];
+            perm[c] = perm[piv];
+            perm[piv] = t;
+        }
+        for (long r = c + 1; r < n; r++) {
+            double f = M[r * n + c] / M[c * n + c];
+            M[r * n + c] = f;
+            for (long q = c + 1; q < n; q++) M[r * n + q] -= f * M[c * n + q];
+        }
+    }
+    for (long j = 0; j < s->ny; j++)
+        for (long i = 0; i < s->nx; i++) {
+            for (long r = 0; r < n; r++) col[r] = F[at(s, i, j, perm[r])];
+            for (long r = 0; r < n; r++)
+                for (long q = 0; q < r; q++) col[r] -= M[r * n + q] * col[q];
+            for (long r = n - 1; r >= 0; r--) {
+                for (long q = r + 1; q < n; q++) col[r] -= M[r * n + q] * col[q];
+                col[r] /= M[r * n + r];
+            }
+            for (long r = 0; r < n; r++) F[at(s, i, j, r)] = col[r];
+        }
+    free(M); free(P); free(Q); free(col); free(perm);
+}
+
 /* Psi(S_z) F = sum_j a_j S_z^j F, written as the power series (Sec. 2);
- * coef == NULL means the identity.  Then the filter passes along z, x, y. */
-static void seen_one(OSim *s, const double *coef, const double *F, double *out)
+ * coef == NULL means the identity; with den, then Psi_den(S_z)^{-1} (the
+ * ratio applied exactly).  Then the filter passes along z, x, y. */
+static void seen_ratio(OSim *s, const double *coef, const double *den, const double *F, double *out)
 {
     long nc = ncell(s);
     if (coef) {
@@ -199,6 +262,7 @@ static void seen_one(OSim *s, const double *coef, const double *F, double *out)
     } else {
         memcpy(out, F, nc * sizeof(double));
     }
+    if (den) solve_psi_z(s, den, out);
     static const int axes[3] = {2, 0, 1};
     for (int a = 0; a < 3; a++) {
         int axis = axes[a];
@@ -210,9 +274,23 @@ static void seen_one(OSim *s, const double *coef, const double *F, double *out)
     }
 }
 
-/* Psi_E on both transverse E components; Psi_B on E_z and every B (Sec. 2) */
+static void seen_one(OSim *s, const double *coef, const double *F, double *out)
+{
+    seen_ratio(s, coef, NULL, F, out);
+}
+
+/* Psi_E on both transverse E components; Psi_B on E_z and every B (Sec. 2).
+ * correction 2: the full multiplier Psi_E / Psi_B on the transverse E
+ * components only, the others filtered only (a variant Sec. 3 compares). */
 void o_seen(OSim *s)
 {
+    if (s->correction == 2) {
+        seen_ratio(s, s->psi_e, s->psi_b, s->E[0], s->Et[0]);
+        seen_ratio(s, s->psi_e, s->psi_b, s->E[1], s->Et[1]);
+        seen_one(s, NULL, s->E[2], s->Et[2]);
+        for (int c = 0; c < 3; c++) seen_one(s, NULL, s->B[c], s->Bt[c]);
+        return;
+    }
     const double *pe = s->correction ? s->psi_e : NULL;
     const double *pb = s->correction ? s->psi_b : NULL;
     seen_one(s, pe, s->E[0], s->Et[0]);
@@ -222,9 +300,14 @@ void o_seen(OSim *s)
 }
 
 /* apply the seen-field operator with polynomial `which` (0 Psi_E, 1 Psi_B,
- * 2 identity) to one plane; used by the stencil-response tests */
+ * 2 identity, 3 the ratio Psi_E / Psi_B) to one plane; used by the
+ * stencil-response tests */
 void o_seen_plane(OSim *s, int which, const double *in, double *out)
 {
+    if (which == 3) {
+        seen_ratio(s, s->psi_e, s->psi_b, in, out);
+        return;
+    }
     const double *coef = which == 0 ? s->psi_e : which == 1 ? s->psi_b : NULL;
     seen_one(s, coef, in, out);
 }

@@ -101,7 +101,8 @@ class OracleSim:
             n0 = wl["omega_p"] ** 2 * wl["m"] / wl["q"] ** 2
             weight = n0 * self.dV / wl["ppc"]
         s.w = float(weight)
-        s.correction = 1 if wl.get("correction") else 0
+        corr = wl.get("correction")
+        s.correction = 2 if corr == "ratio" else (1 if corr else 0)
         if psi is None and s.correction:
             a, b, _ = _psi.psi_coeffs(wl.get("interp", "galerkin"), wl["alpha"])
             psi = (a, b)

@@ -158,6 +158,37 @@ def test_psi_stencil_fourier_response(which):
     assert np.count_nonzero(np.abs(h) > 0) == 9  # quartic -> 9 taps in z
 
 
+@pytest.mark.parametrize("interp,alpha", [("galerkin", 0.5), ("galerkin", 0.7), ("uniform", 0.9),
+                                          ("momentum", 0.5)])
+def test_psi_ratio_applied_exactly_is_the_multiplier(interp, alpha):
+    """Sec. 2: Psi_E applied through the stencil and Psi_B inverted along z give,
+    at every wavenumber of the periodic grid, exactly Psi_E(s)/Psi_B(s) (an
+    inverse is a circulant, diagonal in the DFT), and that ratio is the
+    scheme's multiplier (Eqs. 3-5) to the paper's stated accuracy, taken as in
+    the coefficient pin: 1e-6 for k_z dz <= pi/2, 1e-5 up to k_z dz = 2."""
+    nz, nx = 64, 8
+    wl = _wl(n=(nx, nz), correction="ratio", filter=[], alpha=alpha, interp=interp)
+    sim = _empty_sim(wl)
+    a, b = sim.psi
+    delta = np.zeros(sim.shape)
+    delta[0, 0, 3] = 1.0
+    h = sim.seen_plane(3, delta)[:, 0, 3]
+    assert np.max(np.abs(sim.seen_plane(3, delta)[:, 0, np.arange(nx) != 3])) == 0.0
+    H = np.fft.fft(h)
+    for m in range(nz):
+        kz = 2 * math.pi * m / nz
+        s2 = math.sin(kz / 2) ** 2
+        ratio = psi.poly(a, s2) / psi.poly(b, s2)
+        # rounding: about eps sum|coef| in each applied polynomial, amplified by 1/Psi_B(s)
+        tol = 1e-14 * (sum(abs(v) for v in a) + sum(abs(v) for v in b) * abs(ratio)) / psi.poly(b, s2)
+        assert abs(H[m] - ratio) < tol, (m, H[m], ratio, tol)
+        kk = min(kz, 2 * math.pi - kz)
+        if kk <= 2.0:
+            M = float(psi.multiplier(interp, alpha, math.sin(kk / 2) ** 2))
+            tol_m = FACTS["rational_accuracy"]["small_k" if kk <= math.pi / 2 else "largest_k"]
+            assert abs(H[m] - M) < tol_m, (m, H[m], M)
+
+
 @pytest.mark.parametrize("preset", ["binomial4", "paper-eq6", "paper-eq6-sqrt"])
 def test_filter_fourier_response(preset):
     """Sec. 3, Eq. 6: two bilinear plus two compensation passes per axis respond as
@@ -458,6 +489,7 @@ def test_gauss_invariant_over_long_run():
 
 def _brute_pair(dims, n, order, filt, corr=True, npart=10, seed=3, steps=20, interp="galerkin",
                 solver="yee", alpha=None):
+    """corr: False, True (Psi_E / Psi_B split over the components) or "ratio"."""
     if alpha is None:
         alpha = 0.45 if dims == 2 else 0.4
     wl = _wl(dims=dims, n=n, order=order, correction=corr, filter=list(filt),
@@ -471,7 +503,7 @@ def _brute_pair(dims, n, order, filt, corr=True, npart=10, seed=3, steps=20, int
     s = o.s
     b = BruteSim(dims, o.shape, (s.dx, s.dy, s.dz), s.dt, order, s.q, s.m, s.w,
                  psi_e=o.psi[0] if o.psi else None, psi_b=o.psi[1] if o.psi else None,
-                 filt=filt, jbg=tuple(s.jbg), interp=interp, solver=solver)
+                 filt=filt, jbg=tuple(s.jbg), interp=interp, solver=solver, ratio=(corr == "ratio"))
     b.E[:] = o.E
     b.B[:] = o.B
     bx, bu = o.x.copy(), o.u.copy()
@@ -508,6 +540,20 @@ def test_oracle_ck_matches_brute_force(order, interp):
     n = (8, 10)
     o, b, bx, bu = _brute_pair(2, n, order, (0.25, 0.25, -1.0), steps=15, interp=interp,
                                solver="ck", alpha=0.9)
+
+    def rel(a, r):
+        return np.linalg.norm(a - r) / np.linalg.norm(r)
+    assert rel(o.E, b.E) < 1e-13 and rel(o.B, b.B) < 1e-13 and rel(o.J, b.J) < 1e-13
+    assert rel(o.u, bu) < 1e-13
+
+
+@pytest.mark.parametrize("dims,n,steps", [(2, (8, 10), 15), (3, (8, 8, 8), 3)])
+def test_oracle_exact_ratio_matches_brute_force(dims, n, steps):
+    """The exact-ratio variant (Psi_E / Psi_B on the transverse E only, by dense
+    LU solves along z) against the brute force, which multiplies by the ratio in
+    Fourier space."""
+    o, b, bx, bu = _brute_pair(dims, n, 1, (0.25, 0.25, -1.0), corr="ratio", steps=steps,
+                               npart=10 if dims == 2 else 4)
 
     def rel(a, r):
         return np.linalg.norm(a - r) / np.linalg.norm(r)
