@@ -65,6 +65,16 @@ extern "C" {
                                  values, and every seen stencil is one cell
                                  wider (filter_npass <= 7) */
 
+/* correction modes (Sec. 2) */
+#define PIC_CORR_NONE  0      /* fields seen by the particles are only filtered */
+#define PIC_CORR_SPLIT 1      /* Psi_E on the transverse E, Psi_B on E_z and B
+                                 (the Sec. 2 approach, Psi_B acting as a filter) */
+#define PIC_CORR_RATIO 2      /* the full Psi_E / Psi_B on the transverse E only,
+                                 Psi_B inverted along z (Sec. 2's tri-diagonal
+                                 route; a Sec. 3 variant); E_z and B are filtered
+                                 only; needs nz <= 1024, Psi_B with real roots,
+                                 forward runs only */
+
 /* field solvers (Faraday's law; Ampere's law is always the Yee one) */
 #define PIC_YEE 0             /* textbook Yee */
 #define PIC_CK  1             /* Cole-Karkkainen with beta = 1/8 (named in Secs. 2-4):
@@ -106,7 +116,8 @@ typedef struct pic_config {
                                  for all instances; the reverse sweep needs
                                  PIC_GALERKIN */
     int    precision;         /* PIC_FP64 or PIC_FP32; equal for all instances */
-    int    correction;        /* 1: apply Psi_E / Psi_B (Sec. 2) */
+    int    correction;        /* PIC_CORR_NONE, PIC_CORR_SPLIT or PIC_CORR_RATIO; the
+                                 ratio choice is equal for all instances */
     int    psi_deg;           /* polynomial degree of Psi_E and Psi_B, <= 8 */
     double psi_e[9];          /* Psi_E(s) = sum_j psi_e[j] s^j, psi_e[0] = 1 */
     double psi_b[9];          /* Psi_B(s) = sum_j psi_b[j] s^j, psi_b[0] = 1 */

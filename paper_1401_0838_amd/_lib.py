@@ -23,6 +23,7 @@ PIC_ESTATE = -9
 
 PIC_GALERKIN, PIC_UNIFORM, PIC_MOMENTUM = 0, 1, 2
 PIC_YEE, PIC_CK = 0, 1
+PIC_CORR_NONE, PIC_CORR_SPLIT, PIC_CORR_RATIO = 0, 1, 2
 PIC_FP64, PIC_FP32 = 0, 1
 PIC_IONS_CHARGE, PIC_IONS_CHARGE_AND_CURRENT = 0, 1
 PIC_FIELD_E, PIC_FIELD_B, PIC_FIELD_J, PIC_FIELD_SEEN_E, PIC_FIELD_SEEN_B, PIC_FIELD_RHO = range(6)

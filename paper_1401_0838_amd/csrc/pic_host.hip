@@ -133,6 +133,19 @@ int validate(const pic_config &c, int idx)
     // the node average of the momentum-conserving gather widens every stencil by one cell
     if (c.interp == PIC_MOMENTUM && c.filter_npass + 1 > PIC_MAX_HX)
         return bad(PIC_EINVAL, "filter_npass must be <= 7 with the momentum-conserving gather");
+    if (c.correction != PIC_CORR_NONE && c.correction != PIC_CORR_SPLIT && c.correction != PIC_CORR_RATIO)
+        return bad(PIC_EINVAL, "correction must be PIC_CORR_NONE, PIC_CORR_SPLIT or PIC_CORR_RATIO");
+    if (c.correction == PIC_CORR_RATIO) {
+        if (c.nz > PIC_RATIO_MAXNZ) return bad(PIC_EUNSUPPORTED, "the exact ratio needs nz <= 1024");
+        if (c.adjoint_steps > 0) return bad(PIC_EUNSUPPORTED, "the reverse sweep needs the split correction");
+        double roots[8], lead;
+        if (c.psi_deg >= 1 && c.psi_deg <= 8) {
+            const int nr = psi_real_roots(c.psi_b, c.psi_deg, roots, &lead);
+            if (nr < 0) return bad(PIC_EUNSUPPORTED, "the exact ratio needs Psi_B with real roots only");
+            for (int q = 0; q < nr; q++)
+                if (roots[q] >= 0.0 && roots[q] <= 1.0) return bad(PIC_EPSI, "Psi_B has a root in [0, 1]");
+        }
+    }
     if (c.correction) {
         if (c.psi_deg < 1 || c.psi_deg > 8) return bad(PIC_EINVAL, "psi_deg must be in [1, 8]");
         if (c.psi_deg + c.filter_npass + (c.interp == PIC_MOMENTUM) > PIC_MAX_HZ)
@@ -186,6 +199,7 @@ struct pic_state {
     int n_inst = 0, dims = 2, order = 1, fp32 = 1;
     int gather = GATHER_GALERKIN;    // gather scheme of every instance
     int ck = 0;                      // Cole-Karkkainen solver (every instance)
+    int ratio = 0;                   // exact Psi_E / Psi_B on the transverse E (every instance)
     hipStream_t stream = nullptr;
     bool own_stream = false;
     char *arena = nullptr;
@@ -242,6 +256,13 @@ LaunchCtx ctx(const pic_state *s)
     c.single = s->n_inst == 1;
     c.gather = s->gather;
     c.ck = s->ck;
+    c.ninst = s->n_inst;
+    c.ratio = s->ratio;
+    for (const InstDesc &d : s->desc) {
+        const int tc = PIC_RATIO_TC(s->fp32);
+        c.rtiles = std::max(c.rtiles, (d.n[0] * d.n[1] + tc - 1) / tc);
+        c.rnz = std::max(c.rnz, d.n[2]);
+    }
     if (!s->desc.empty()) {
         const InstDesc &d0 = s->desc[0];
         c.hz = d0.hz; c.hx = d0.hx; c.hzf = d0.hzf; c.psi_deg = d0.psi_deg;
@@ -434,6 +455,27 @@ void fill_desc(InstDesc &D, const pic_config &c, const pic_particles &p)
     if (c.correction) {
         ze = conv(psi_taps(c.psi_e, c.psi_deg), fz);
         zb = conv(psi_taps(c.psi_b, c.psi_deg), fz);
+    }
+    D.ratio = c.correction == PIC_CORR_RATIO;
+    D.nroot = 0;
+    D.rscale = 1.0;
+    std::memset(D.lam, 0, sizeof D.lam);
+    if (D.ratio) {
+        // E_z and B are filtered only; the transverse E get Psi_E here and
+        // Psi_B(S_z)^{-1} after the seen pass, one (S_z - r) factor per root:
+        // (S_z - r) y = x  <=>  (1 - l E^-1)(1 - l E) y = 4 l x,  l + 1/l = 2 - 4 r
+        zb.assign(ze.size(), 0.0);
+        const size_t off = (ze.size() - fz.size()) / 2;
+        for (size_t t = 0; t < fz.size(); t++) zb[off + t] = fz[t];
+        double roots[8], lead;
+        D.nroot = psi_real_roots(c.psi_b, c.psi_deg, roots, &lead);
+        D.rscale = 1.0 / lead;
+        for (int q = 0; q < D.nroot; q++) {
+            const double cq = 2.0 - 4.0 * roots[q];
+            const double l = 0.5 * cq - std::copysign(std::sqrt(0.25 * cq * cq - 1.0), cq);
+            D.lam[q] = l;
+            D.rscale *= 4.0 * l;
+        }
     }
     D.hz = (int)(ze.size() / 2);
     D.hx = (int)(fz.size() / 2);
@@ -664,14 +706,16 @@ int build_worklists(pic_state *s)
 
 // one step's launches for instances [i0, i0 + ni) using the given work ranges
 // one step's launches; the Yee launch reads the current parity, the rest see the new one
-int enqueue_step_range(pic_state *s, const Range &f, const Range &sr, const Range &yr, const Range &p, bool trace)
+int enqueue_step_range(pic_state *s, const Range &f, const Range &sr, const Range &yr, const Range &p, int i0,
+                       int ni)
 {
     LaunchCtx c = ctx(s);
+    c.inst0 = i0;
+    c.ninst = ni;
     if (launch_yee(c, s->fwork + f.off, f.n, s->ywork + yr.off, yr.n)) return fail(PIC_EHIP, "yee launch");
     c.par ^= 1;
     if (launch_seen(c, s->fwork + f.off, f.n, s->swork + sr.off, sr.n)) return fail(PIC_EHIP, "seen launch");
     if (launch_particles(c, s->pwork + p.off, p.n, 0, s->block, s->wmax)) return fail(PIC_EHIP, "particle launch");
-    (void)trace;
     return PIC_OK;
 }
 
@@ -679,11 +723,11 @@ int enqueue_step(pic_state *s)
 {
     if (s->sched == PIC_SCHED_BATCHED) {
         int rc = enqueue_step_range(s, Range{0, s->nfwork}, Range{0, s->nswork}, Range{0, s->nywork},
-                                    Range{0, s->npwork}, false);
+                                    Range{0, s->npwork}, 0, s->n_inst);
         if (rc) return rc;
     } else {
         for (int i = 0; i < s->n_inst; i++) {
-            int rc = enqueue_step_range(s, s->frange[i], s->srange[i], s->yrange[i], s->prange[i], false);
+            int rc = enqueue_step_range(s, s->frange[i], s->srange[i], s->yrange[i], s->prange[i], i, 1);
             if (rc) return rc;
         }
     }
@@ -852,8 +896,9 @@ extern "C" int pic_plan(const pic_config *cfgs, int n_inst, const int64_t *n_par
         if (cfgs[i].dims != cfgs[0].dims || cfgs[i].precision != cfgs[0].precision ||
             cfgs[i].shape_order != cfgs[0].shape_order || cfgs[i].adjoint_steps != cfgs[0].adjoint_steps ||
             cfgs[i].interp != cfgs[0].interp || cfgs[i].solver != cfgs[0].solver ||
+            (cfgs[i].correction == PIC_CORR_RATIO) != (cfgs[0].correction == PIC_CORR_RATIO) ||
             (cfgs[0].adjoint_steps > 0 && cfgs[i].adjoint_ckpt != cfgs[0].adjoint_ckpt))
-            return fail(PIC_EINVAL, "all instances must share dims, precision, shape_order, interp, solver and adjoint sizes");
+            return fail(PIC_EINVAL, "all instances must share dims, precision, shape_order, interp, solver, the exact-ratio choice and adjoint sizes");
         if (n_particles[i] < 0 || n_particles[i] > INT32_MAX) return fail(PIC_EINVAL, "particle count");
     }
     const std::vector<pic_config> rc = resolve_tiles(cfgs, n_inst);
@@ -887,6 +932,7 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
     s->order = cfgs[0].shape_order;
     s->fp32 = cfgs[0].precision == PIC_FP32;
     s->ck = cfgs[0].solver == PIC_CK;
+    s->ratio = cfgs[0].correction == PIC_CORR_RATIO;
     s->gather = cfgs[0].interp == PIC_UNIFORM ? GATHER_UNIFORM
               : cfgs[0].interp == PIC_MOMENTUM ? GATHER_NODAL : GATHER_GALERKIN;
     s->cfg.assign(cfgs, cfgs + n_inst);

@@ -60,6 +60,12 @@ struct InstDesc {
     double tzn[2 * PIC_MAX_HZ + 1];
     double txn[2 * PIC_MAX_HX + 1];
     double tyn[2 * PIC_MAX_HX + 1];
+    // exact ratio variant: the transverse E are multiplied by Psi_E / Psi_B, the
+    // denominator applied as Psi_B(S_z)^{-1} = rscale prod_q [(1 - l_q E^-1)(1 - l_q E)]^{-1}
+    // along z (E = shift by one cell, one factor per real root of Psi_B)
+    int ratio, nroot;
+    double lam[8];
+    double rscale;
     // grid planes (element type follows the precision)
     // E, B and J alternate between two sets of planes from step to step (index =
     // parity): the field kernels read one set with halos and write the other
@@ -115,6 +121,8 @@ __host__ __device__ inline int xcd_tile(int b, int nt)
 
 // breakdown test of the correction polynomials (psi_setup.cpp)
 bool psi_positive(const double *psi_e, const double *psi_b, int deg);
+// real roots of a polynomial in s; -1 if one is not real (psi_setup.cpp)
+int psi_real_roots(const double *coef, int deg, double *roots, double *lead);
 
 // launch helpers implemented in pic_kernels.hip
 struct LaunchCtx {
@@ -135,11 +143,18 @@ struct LaunchCtx {
     int single = 0;                   // one instance: 2D field kernels take tile = block index
     int gather = GATHER_GALERKIN;     // gather scheme shared by every instance
     int ck = 0;                       // 2D Cole-Karkkainen curl in Faraday's law (every instance)
+    int ratio = 0;                    // exact Psi_E / Psi_B on the transverse E (every instance)
+    int inst0 = 0, ninst = 1;         // instances the launches cover (ratio solve grid)
+    int rtiles = 0;                   // column tiles of the widest instance (ratio solve grid)
+    int rnz = 0;                      // largest nz (ratio solve LDS)
 };
 
 int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork);
 #define PIC_YEE_TX 64
 int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork);
+// columns per workgroup of the Psi_B inversion along z (LDS <= 64 KB), and its largest nz
+#define PIC_RATIO_TC(fp32) ((fp32) ? 8 : 4)
+#define PIC_RATIO_MAXNZ 1024
 size_t seen_smem_bytes(int fp32, int tz);
 int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid, int block,
                      const int wmax[3]);

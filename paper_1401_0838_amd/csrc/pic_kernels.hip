@@ -928,6 +928,100 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     }
 }
 
+// ------------------------------------------- exact ratio: Psi_B^{-1} along z
+// The variant that multiplies the transverse E by the full Psi_E / Psi_B
+// applies Psi_B(S_z)^{-1} after the seen pass (Sec. 2: the denominator
+// inverted by tri-diagonal solves).  With Psi_B(s) = b prod_q (s - r_q) over
+// its real roots (outside [0, 1]), each factor S_z - r_q is the periodic
+// tri-diagonal (-1/4, 1/2 - r_q, -1/4) = -(1 / (4 l_q)) (1 - l_q E^-1)(1 - l_q E),
+// l_q + 1/l_q = 2 - 4 r_q, |l_q| < 1: a causal then an anti-causal first-order
+// recursion, the constants gathered in rscale.  A workgroup stages
+// PIC_RATIO_TC whole columns in LDS (8 in float, 4 in double); a wave solves
+// one column, its 64 lanes owning contiguous segments of ceil(nz / 64) rows in
+// registers: each lane
+// runs the recursion over its segment from a zero state, a wave scan of the
+// segments' affine maps s -> A s + e gives every segment its exact periodic
+// incoming state, and the lane adds that state's decaying contribution.
+template <class R>
+__global__ void __launch_bounds__(256) k_psi_inv_z(const InstDesc *__restrict__ Dt, int inst0)
+{
+    constexpr int TC = PIC_RATIO_TC(sizeof(R) == 4), MAXL = PIC_RATIO_MAXNZ / 64;
+    extern __shared__ __align__(16) unsigned char smem[];
+    R *buf = reinterpret_cast<R *>(smem);
+    const int inst = inst0 + blockIdx.y, comp = blockIdx.z;
+    const InstDesc &D = Dt[inst];
+    const int ncol = D.n[0] * D.n[1], nz = D.n[2];
+    const int c0 = blockIdx.x * TC;
+    if (c0 >= ncol) return;
+    const int Ls = (nz + 63) / 64, pitch = Ls * 64 + 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    const gp<R> F = G<R>(D.Et[comp]);
+    // row r of column c sits at c * pitch + (r % Ls) * 64 + r / Ls: lane j's
+    // segment [j Ls, (j + 1) Ls) becomes a stride-64 run (no bank conflicts)
+    for (int q = tid; q < nz * TC; q += blockDim.x) {
+        const int r = q / TC, c = q % TC;
+        if (c0 + c < ncol) buf[c * pitch + (r % Ls) * 64 + r / Ls] = F[(size_t)r * ncol + c0 + c];
+    }
+    __syncthreads();
+    const int len = max(0, min(Ls, nz - lane * Ls));
+    for (int c = wave; c < TC && c0 + c < ncol; c += nwave) {
+        R *col = buf + c * pitch + lane;
+        R v[MAXL];
+#pragma unroll
+        for (int i = 0; i < MAXL; i++) v[i] = i < len ? col[i * 64] : R(0);
+        for (int q = 0; q < D.nroot; q++) {
+            const R l = (R)D.lam[q];
+            // causal: w[k] = v[k] + l w[k-1]
+            R st = R(0), A = R(1);
+#pragma unroll
+            for (int i = 0; i < MAXL; i++)
+                if (i < len) { st = v[i] + l * st; v[i] = st; A *= l; }
+            // prefix composition over lanes 0..63 (F_j = f_j o F_{j-1})
+            R P = A, Q = st;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const R Pp = __shfl_up(P, d), Qp = __shfl_up(Q, d);
+                if (lane >= d) { Q = P * Qp + Q; P = P * Pp; }
+            }
+            // periodic: the state entering lane 0 is the one leaving lane 63
+            const R C0 = __shfl(Q, 63) / (R(1) - __shfl(P, 63));
+            const R Pm = __shfl_up(P, 1), Qm = __shfl_up(Q, 1);
+            R C = lane == 0 ? C0 : Pm * C0 + Qm;
+#pragma unroll
+            for (int i = 0; i < MAXL; i++)
+                if (i < len) { C *= l; v[i] += C; }
+            // anti-causal: y[k] = w[k] + l y[k+1]
+            st = R(0); A = R(1);
+#pragma unroll
+            for (int i = MAXL - 1; i >= 0; i--)
+                if (i < len) { st = v[i] + l * st; v[i] = st; A *= l; }
+            // suffix composition over lanes 63..0 (G_j = f_j o G_{j+1})
+            P = A; Q = st;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const R Pn = __shfl_down(P, d), Qn = __shfl_down(Q, d);
+                if (lane + d < 64) { Q = P * Qn + Q; P = P * Pn; }
+            }
+            // periodic: the state entering lane 63 is the one leaving lane 0
+            const R C63 = __shfl(Q, 0) / (R(1) - __shfl(P, 0));
+            const R Pn1 = __shfl_down(P, 1), Qn1 = __shfl_down(Q, 1);
+            C = lane == 63 ? C63 : Pn1 * C63 + Qn1;
+#pragma unroll
+            for (int i = MAXL - 1; i >= 0; i--)
+                if (i < len) { C *= l; v[i] += C; }
+        }
+        const R sc = (R)D.rscale;
+#pragma unroll
+        for (int i = 0; i < MAXL; i++)
+            if (i < len) col[i * 64] = sc * v[i];
+    }
+    __syncthreads();
+    for (int q = tid; q < nz * TC; q += blockDim.x) {
+        const int r = q / TC, c = q % TC;
+        if (c0 + c < ncol) F[(size_t)r * ncol + c0 + c] = buf[c * pitch + (r % Ls) * 64 + r / Ls];
+    }
+}
+
 // ------------------------------------------------------------------ resort
 
 template <int DIM> __device__ __forceinline__ int tile_of(const InstDesc &D, unsigned idx)
@@ -1377,6 +1471,11 @@ int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *sw
                 k_seen_pass<0, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
                 k_seen_pass<1, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 2, 0, c.par);
             }
+        }
+        if (c.ratio && c.rtiles > 0) {
+            // the exact-ratio variant: the transverse E then get Psi_B(S_z)^{-1}
+            const size_t sm = (size_t)PIC_RATIO_TC(sizeof(R) == 4) * ((c.rnz + 63) / 64 * 64 + 1) * sizeof(R);
+            k_psi_inv_z<R><<<dim3(c.rtiles, c.ninst, 2), dim3(256), sm, c.stream>>>(c.desc, c.inst0);
         }
     });
     return hip_ok(hipGetLastError());

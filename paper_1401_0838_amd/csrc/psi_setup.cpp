@@ -10,6 +10,7 @@
 #include <quadmath.h>
 
 #include <cmath>
+#include <complex>
 
 #include "pic_api.h"
 
@@ -31,6 +32,53 @@ quad multiplier(int interp, quad alpha, quad s)
 }
 
 }  // namespace
+
+// Real roots of sum_j coef[j] s^j (degree deg, trailing zero coefficients
+// dropped): Weierstrass (Durand-Kerner) iteration in long double, each root
+// then polished by Newton steps on the real axis.  Returns the number of
+// roots written to roots[] and the leading coefficient in *lead, or -1 if a
+// root is not real (|Im r| > 1e-9 (1 + |r|)).
+int psi_real_roots(const double *coef, int deg, double *roots, double *lead)
+{
+    typedef std::complex<long double> cl;
+    while (deg > 0 && coef[deg] == 0.0) deg--;
+    *lead = coef[deg];
+    if (deg == 0) return 0;
+    auto p = [&](cl z) {
+        cl acc = 0;
+        for (int i = deg; i >= 0; i--) acc = acc * z + (long double)coef[i];
+        return acc;
+    };
+    cl z[8];
+    const cl seed(0.4L, 0.9L);
+    z[0] = 1;
+    for (int k = 1; k < deg; k++) z[k] = z[k - 1] * seed;
+    for (int k = 0; k < deg; k++) z[k] *= seed;
+    for (int it = 0; it < 2000; it++) {
+        long double moved = 0;
+        for (int k = 0; k < deg; k++) {
+            cl den = (long double)coef[deg];
+            for (int j = 0; j < deg; j++)
+                if (j != k) den *= z[k] - z[j];
+            const cl step = p(z[k]) / den;
+            z[k] -= step;
+            moved = std::max(moved, std::abs(step) / (1.0L + std::abs(z[k])));
+        }
+        if (moved < 1e-18L) break;
+    }
+    for (int k = 0; k < deg; k++) {
+        if (std::fabs(z[k].imag()) > 1e-9L * (1.0L + std::abs(z[k]))) return -1;
+        long double r = z[k].real();
+        for (int it = 0; it < 8; it++) {
+            long double f = 0, df = 0;
+            for (int i = deg; i >= 0; i--) { df = df * r + f; f = f * r + (long double)coef[i]; }
+            if (df == 0) break;
+            r -= f / df;
+        }
+        roots[k] = (double)r;
+    }
+    return deg;
+}
 
 // Breakdown test (Sec. 3): Psi_B > 0 on [0, 1] and Psi_E > 0 on [0, 1), on a
 // 4097-point grid.  The Eq. 5 multiplier is exactly zero at s = 1 (its

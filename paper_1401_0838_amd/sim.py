@@ -44,7 +44,8 @@ def make_config(wl, precision=None, tile=None, block=0, trace_capacity=0, psi=No
     c.solver = {"yee": L.PIC_YEE, "ck": L.PIC_CK}[wl.get("solver", "yee")]
     prec = precision or wl.get("precision", "fp32")
     c.precision = L.PIC_FP32 if prec == "fp32" else L.PIC_FP64
-    c.correction = 1 if wl.get("correction") else 0
+    corr = wl.get("correction")
+    c.correction = L.PIC_CORR_RATIO if corr == "ratio" else (L.PIC_CORR_SPLIT if corr else L.PIC_CORR_NONE)
     if c.correction:
         if psi is None:
             rc, a, b = L.pic_psi_coeffs(c.interp, float(wl["alpha"]), 4)

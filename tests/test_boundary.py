@@ -101,6 +101,19 @@ def test_plan_validates_configs():
     with pytest.raises(L.PicError) as e:
         L.pic_plan([c], [16])
     assert e.value.code == L.PIC_EUNSUPPORTED
+    # exact ratio: nz <= 1024, shared by a batch, forward only
+    assert L.pic_plan([_cfg(correction="ratio")], [16]) > 0
+    with pytest.raises(L.PicError) as e:
+        L.pic_plan([_cfg(correction="ratio", n=(16, 2048))], [16])
+    assert e.value.code == L.PIC_EUNSUPPORTED
+    with pytest.raises(L.PicError) as e:
+        L.pic_plan([_cfg(correction=True), _cfg(correction="ratio")], [16, 16])
+    assert e.value.code == L.PIC_EINVAL
+    c = _cfg(correction="ratio")
+    c.adjoint_steps, c.adjoint_ckpt = 4, 2
+    with pytest.raises(L.PicError) as e:
+        L.pic_plan([c], [16])
+    assert e.value.code == L.PIC_EUNSUPPORTED
     # Cole-Karkkainen: 2D square cells, c dt < dx, shared by a batch, forward only
     assert L.pic_plan([_cfg(solver="ck", alpha=0.95)], [16]) > 0
     with pytest.raises(L.PicError) as e:
