@@ -247,6 +247,28 @@ def gamma_scan_block(steps):
     return out
 
 
+def variants_block(steps):
+    """Sec. 3's variants of its setting (128x128 x 16 ppc cubic CK, Eq. 6 filter,
+    correction): no filter apart from Psi_B, the exact Psi_E / Psi_B on the
+    transverse E only, no compensation passes; growth rates at gamma = 130 and
+    3 over alpha, and each variant's rate over the baseline's (the paper reads
+    about 2x, 3x and 'moderately lower' at large alpha)."""
+    import pic_inputs as pi
+    from paper_1401_0838_amd import scan
+    alphas = [0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 0.99]
+    out = {"workload": "beam2d_128_ck (128x128, 16 ppc, cubic, CK, Eq. 6 filter)", "steps": steps,
+           "alphas": alphas}
+    for gamma in (130.0, 3.0):
+        t0 = time.perf_counter()
+        rates, skipped = scan.variant_sweep(pi.workload("beam2d_128_ck"), alphas, gamma, steps)
+        base = rates["baseline"]
+        out["gamma_%g" % gamma] = {
+            "wall_s": time.perf_counter() - t0, "skipped": skipped, "growth_rates": rates,
+            "over_baseline": {k: [None if (x is None or y in (None, 0)) else x / y for x, y in zip(v, base)]
+                              for k, v in rates.items() if k != "baseline"}}
+    return out
+
+
 def adjoint_block():
     """256x256, 8 ppc, 200 steps, checkpoints every 20 (FP32): backward (recompute +
     reverse sweep) time over forward time."""
@@ -308,9 +330,10 @@ def main():
                     help="skip the Uniform and momentum-conserving gather cases")
     ap.add_argument("--no-ck", action="store_true", help="skip the Cole-Karkkainen solver cases")
     ap.add_argument("--no-scan", action="store_true", help="skip the gamma / alpha growth-rate scan")
+    ap.add_argument("--no-variants", action="store_true", help="skip the Sec. 3 variant growth rates")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling HBM counters)")
-    ap.add_argument("--only", choices=("batched", "adjoint", "3d", "fp64", "schemes", "ck", "scan"),
+    ap.add_argument("--only", choices=("batched", "adjoint", "3d", "fp64", "schemes", "ck", "scan", "variants"),
                     help="run one secondary block alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -320,7 +343,7 @@ def main():
         blk = {"batched": lambda: batched_block(max(20, args.steps // 4), 5), "adjoint": adjoint_block,
                "3d": lambda: beam3d_block(20, 3), "fp64": lambda: fp64_block(50, 5),
                "schemes": lambda: schemes_block(100, 10), "ck": lambda: ck_block(100, 10),
-               "scan": lambda: gamma_scan_block(2000)}[args.only]()
+               "scan": lambda: gamma_scan_block(2000), "variants": lambda: variants_block(2000)}[args.only]()
         print(json.dumps({args.only: blk}), flush=True)
         return
     if args.gpus != 1:
@@ -401,6 +424,8 @@ def main():
         out["ck"] = ck_block(100, 10)
     if not args.no_scan:
         out["gamma_scan"] = gamma_scan_block(2000)
+    if not args.no_variants:
+        out["variants"] = variants_block(2000)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, x, u, args.cpu_steps)
     print(json.dumps(out), flush=True)

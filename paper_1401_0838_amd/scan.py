@@ -1,4 +1,5 @@
-"""Growth-rate scans through the batched engine (Sec. 3, Figs. 2-3).
+"""Growth-rate scans through the batched engine (Sec. 3, Figs. 2-3, and the
+variants Sec. 3 compares).
 
 Sec. 3 plots the maximum growth rate of the numerical instability against
 c dt / dz for gamma = 130 and gamma = 3, and reads the peak growth rates as
@@ -73,3 +74,39 @@ def growth_table(points, traces, wkin):
     if len(gs) >= 2:
         power = float(np.polyfit([math.log(g) for g in gs], [math.log(peaks[g][0]) for g in gs], 1)[0])
     return rates, peaks, power
+
+
+# Sec. 3's variants of its Fig. 2 setting (correction, Eq. 6 filter): (1) no
+# digital filtering apart from Psi_B; (2) Psi_E / Psi_B applied to the
+# transverse E only (Psi_B inverted); (3) no compensation passes.
+VARIANTS = {
+    "baseline": dict(correction=True),
+    "no_filter": dict(correction=True, filter=[]),
+    "ratio_on_transverse_E": dict(correction="ratio"),
+    "no_compensation": dict(correction=True, filter=[0.25, 0.25]),
+}
+
+
+def variant_sweep(base, alphas, gamma, nsteps, precision="fp32", seed=0):
+    """Growth rate of every variant at every alpha (one gamma).  Variants that
+    share the split correction run as one batch; the exact-ratio one as another
+    (a batch shares that choice).  Returns {variant: [rate per alpha]} and the
+    points skipped for a broken-down correction."""
+    groups = {}
+    for name, over in VARIANTS.items():
+        groups.setdefault(over["correction"] == "ratio", []).append(name)
+    rates, skipped = {}, []
+    for names in groups.values():
+        pts, wls, parts, tags = [], [], [], []
+        for name in names:
+            p, w, pa, sk = scan_instances(dict(base, **VARIANTS[name]), alphas, [gamma], seed)
+            pts += p
+            wls += w
+            parts += pa
+            tags += [name] * len(p)
+            skipped += [(name,) + k for k in sk]
+        traces, wkin = run_scan(pts, wls, parts, nsteps, precision)
+        r, _, _ = growth_table(pts, traces, wkin)
+        for name, (g, a), v in zip(tags, pts, r):
+            rates.setdefault(name, {})[a] = v
+    return {name: [rates[name].get(float(a)) for a in alphas] for name in VARIANTS}, skipped

@@ -175,3 +175,15 @@ def test_scan_growth_table_on_synthetic_traces():
         assert abs(r - 0.01 * g ** -0.5 * f) < 1e-9
     assert all(peaks[g][1] == 0.7 for g in peaks)
     assert abs(power + 0.5) < 1e-9
+
+
+def test_variant_configs_plan():
+    """Every Sec. 3 variant of the CK cubic Eq. 6 setting is a valid plan, and a
+    batch mixing the split variants is accepted (the exact ratio goes alone)."""
+    from paper_1401_0838_amd import scan
+    base = pi.workload("beam2d_128_ck", n=(32, 32))
+    cfgs = {k: make_config(dict(base, **v)) for k, v in scan.VARIANTS.items()}
+    for k, c in cfgs.items():
+        assert L.pic_plan([c], [64]) > 0, k
+    split = [c for k, c in cfgs.items() if k != "ratio_on_transverse_E"]
+    assert L.pic_plan(split, [64] * len(split)) > 0

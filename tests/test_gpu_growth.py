@@ -177,3 +177,17 @@ def test_gamma_scan_growth_rates_fp32_vs_fp64():
                 bad.append((corr, p, g32, g64))
     _say("  mismatches: %s" % bad)
     assert not bad
+
+
+def test_variant_sweep_growth_rates_fp32_vs_fp64():
+    """Sec. 3's variants (no filter, exact ratio on the transverse E, no
+    compensation) at 64x64, 8 ppc, cubic CK, gamma 130, alpha 0.7 and 0.95,
+    1000 steps: FP32 growth rates equal FP64 ones for every variant."""
+    from paper_1401_0838_amd import scan
+    base = pi.workload("beam2d_128_ck", n=(64, 64), ppc=8)
+    r32, _ = scan.variant_sweep(base, [0.7, 0.95], 130.0, 1000, "fp32")
+    r64, _ = scan.variant_sweep(base, [0.7, 0.95], 130.0, 1000, "fp64")
+    _say("variants fp32 %s\n         fp64 %s" % (r32, r64))
+    for name in r64:
+        for g32, g64, a in zip(r32[name], r64[name], (0.7, 0.95)):
+            assert abs(g32 - g64) <= 0.05 * abs(g64) or abs(g32 - g64) * a <= 5e-5, (name, a, g32, g64)
