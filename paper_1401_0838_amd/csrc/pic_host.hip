@@ -259,9 +259,7 @@ LaunchCtx ctx(const pic_state *s)
     c.ninst = s->n_inst;
     c.ratio = s->ratio;
     for (const InstDesc &d : s->desc) {
-        const int tc = PIC_RATIO_TC(s->fp32);
-        c.rtiles = std::max(c.rtiles, (d.n[0] * d.n[1] + tc - 1) / tc);
-        c.rnz = std::max(c.rnz, d.n[2]);
+        c.rtiles = std::max(c.rtiles, (d.n[0] * d.n[1] + PIC_RATIO_TC - 1) / PIC_RATIO_TC);
     }
     if (!s->desc.empty()) {
         const InstDesc &d0 = s->desc[0];

@@ -146,14 +146,13 @@ struct LaunchCtx {
     int ratio = 0;                    // exact Psi_E / Psi_B on the transverse E (every instance)
     int inst0 = 0, ninst = 1;         // instances the launches cover (ratio solve grid)
     int rtiles = 0;                   // column tiles of the widest instance (ratio solve grid)
-    int rnz = 0;                      // largest nz (ratio solve LDS)
 };
 
 int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork);
 #define PIC_YEE_TX 64
 int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork);
-// columns per workgroup of the Psi_B inversion along z (LDS <= 64 KB), and its largest nz
-#define PIC_RATIO_TC(fp32) ((fp32) ? 8 : 4)
+// columns (one wave each) per workgroup of the Psi_B inversion along z, and its largest nz
+#define PIC_RATIO_TC 4
 #define PIC_RATIO_MAXNZ 1024
 size_t seen_smem_bytes(int fp32, int tz);
 int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid, int block,

@@ -935,91 +935,76 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
 // its real roots (outside [0, 1]), each factor S_z - r_q is the periodic
 // tri-diagonal (-1/4, 1/2 - r_q, -1/4) = -(1 / (4 l_q)) (1 - l_q E^-1)(1 - l_q E),
 // l_q + 1/l_q = 2 - 4 r_q, |l_q| < 1: a causal then an anti-causal first-order
-// recursion, the constants gathered in rscale.  A workgroup stages
-// PIC_RATIO_TC whole columns in LDS (8 in float, 4 in double); a wave solves
-// one column, its 64 lanes owning contiguous segments of ceil(nz / 64) rows in
-// registers: each lane
-// runs the recursion over its segment from a zero state, a wave scan of the
-// segments' affine maps s -> A s + e gives every segment its exact periodic
-// incoming state, and the lane adds that state's decaying contribution.
+// recursion, the constants gathered in rscale.  One wave solves one z column
+// (PIC_RATIO_TC columns per workgroup): its 64 lanes own contiguous segments of
+// ceil(nz / 64) rows, loaded straight into registers (all loads of a lane in
+// flight at once; the neighbouring columns of the same cache lines belong to
+// the sibling waves).  Each lane runs the recursion over its segment from a
+// zero state, a wave scan of the segments' affine maps s -> A s + e gives
+// every segment its exact periodic incoming state, and the lane adds that
+// state's decaying contribution.
 template <class R>
 __global__ void __launch_bounds__(256) k_psi_inv_z(const InstDesc *__restrict__ Dt, int inst0)
 {
-    constexpr int TC = PIC_RATIO_TC(sizeof(R) == 4), MAXL = PIC_RATIO_MAXNZ / 64;
-    extern __shared__ __align__(16) unsigned char smem[];
-    R *buf = reinterpret_cast<R *>(smem);
+    constexpr int MAXL = PIC_RATIO_MAXNZ / 64;
     const int inst = inst0 + blockIdx.y, comp = blockIdx.z;
     const InstDesc &D = Dt[inst];
     const int ncol = D.n[0] * D.n[1], nz = D.n[2];
-    const int c0 = blockIdx.x * TC;
-    if (c0 >= ncol) return;
-    const int Ls = (nz + 63) / 64, pitch = Ls * 64 + 1;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
-    const gp<R> F = G<R>(D.Et[comp]);
-    // row r of column c sits at c * pitch + (r % Ls) * 64 + r / Ls: lane j's
-    // segment [j Ls, (j + 1) Ls) becomes a stride-64 run (no bank conflicts)
-    for (int q = tid; q < nz * TC; q += blockDim.x) {
-        const int r = q / TC, c = q % TC;
-        if (c0 + c < ncol) buf[c * pitch + (r % Ls) * 64 + r / Ls] = F[(size_t)r * ncol + c0 + c];
-    }
-    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = blockIdx.x * PIC_RATIO_TC + wave;
+    if (col >= ncol) return;
+    const int Ls = (nz + 63) / 64;
     const int len = max(0, min(Ls, nz - lane * Ls));
-    for (int c = wave; c < TC && c0 + c < ncol; c += nwave) {
-        R *col = buf + c * pitch + lane;
-        R v[MAXL];
+    const gp<R> F = G<R>(D.Et[comp]) + col;
+    const size_t base = (size_t)lane * Ls * ncol;
+    R v[MAXL];
 #pragma unroll
-        for (int i = 0; i < MAXL; i++) v[i] = i < len ? col[i * 64] : R(0);
-        for (int q = 0; q < D.nroot; q++) {
-            const R l = (R)D.lam[q];
-            // causal: w[k] = v[k] + l w[k-1]
-            R st = R(0), A = R(1);
-#pragma unroll
-            for (int i = 0; i < MAXL; i++)
-                if (i < len) { st = v[i] + l * st; v[i] = st; A *= l; }
-            // prefix composition over lanes 0..63 (F_j = f_j o F_{j-1})
-            R P = A, Q = st;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const R Pp = __shfl_up(P, d), Qp = __shfl_up(Q, d);
-                if (lane >= d) { Q = P * Qp + Q; P = P * Pp; }
-            }
-            // periodic: the state entering lane 0 is the one leaving lane 63
-            const R C0 = __shfl(Q, 63) / (R(1) - __shfl(P, 63));
-            const R Pm = __shfl_up(P, 1), Qm = __shfl_up(Q, 1);
-            R C = lane == 0 ? C0 : Pm * C0 + Qm;
-#pragma unroll
-            for (int i = 0; i < MAXL; i++)
-                if (i < len) { C *= l; v[i] += C; }
-            // anti-causal: y[k] = w[k] + l y[k+1]
-            st = R(0); A = R(1);
-#pragma unroll
-            for (int i = MAXL - 1; i >= 0; i--)
-                if (i < len) { st = v[i] + l * st; v[i] = st; A *= l; }
-            // suffix composition over lanes 63..0 (G_j = f_j o G_{j+1})
-            P = A; Q = st;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const R Pn = __shfl_down(P, d), Qn = __shfl_down(Q, d);
-                if (lane + d < 64) { Q = P * Qn + Q; P = P * Pn; }
-            }
-            // periodic: the state entering lane 63 is the one leaving lane 0
-            const R C63 = __shfl(Q, 0) / (R(1) - __shfl(P, 0));
-            const R Pn1 = __shfl_down(P, 1), Qn1 = __shfl_down(Q, 1);
-            C = lane == 63 ? C63 : Pn1 * C63 + Qn1;
-#pragma unroll
-            for (int i = MAXL - 1; i >= 0; i--)
-                if (i < len) { C *= l; v[i] += C; }
-        }
-        const R sc = (R)D.rscale;
+    for (int i = 0; i < MAXL; i++) v[i] = i < len ? F[base + (size_t)i * ncol] : R(0);
+    for (int q = 0; q < D.nroot; q++) {
+        const R l = (R)D.lam[q];
+        // causal: w[k] = v[k] + l w[k-1]
+        R st = R(0), A = R(1);
 #pragma unroll
         for (int i = 0; i < MAXL; i++)
-            if (i < len) col[i * 64] = sc * v[i];
+            if (i < len) { st = v[i] + l * st; v[i] = st; A *= l; }
+        // prefix composition over lanes 0..63 (F_j = f_j o F_{j-1})
+        R P = A, Q = st;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const R Pp = __shfl_up(P, d), Qp = __shfl_up(Q, d);
+            if (lane >= d) { Q = P * Qp + Q; P = P * Pp; }
+        }
+        // periodic: the state entering lane 0 is the one leaving lane 63
+        const R C0 = __shfl(Q, 63) / (R(1) - __shfl(P, 63));
+        const R Pm = __shfl_up(P, 1), Qm = __shfl_up(Q, 1);
+        R C = lane == 0 ? C0 : Pm * C0 + Qm;
+#pragma unroll
+        for (int i = 0; i < MAXL; i++)
+            if (i < len) { C *= l; v[i] += C; }
+        // anti-causal: y[k] = w[k] + l y[k+1]
+        st = R(0); A = R(1);
+#pragma unroll
+        for (int i = MAXL - 1; i >= 0; i--)
+            if (i < len) { st = v[i] + l * st; v[i] = st; A *= l; }
+        // suffix composition over lanes 63..0 (G_j = f_j o G_{j+1})
+        P = A; Q = st;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const R Pn = __shfl_down(P, d), Qn = __shfl_down(Q, d);
+            if (lane + d < 64) { Q = P * Qn + Q; P = P * Pn; }
+        }
+        // periodic: the state entering lane 63 is the one leaving lane 0
+        const R C63 = __shfl(Q, 0) / (R(1) - __shfl(P, 0));
+        const R Pn1 = __shfl_down(P, 1), Qn1 = __shfl_down(Q, 1);
+        C = lane == 63 ? C63 : Pn1 * C63 + Qn1;
+#pragma unroll
+        for (int i = MAXL - 1; i >= 0; i--)
+            if (i < len) { C *= l; v[i] += C; }
     }
-    __syncthreads();
-    for (int q = tid; q < nz * TC; q += blockDim.x) {
-        const int r = q / TC, c = q % TC;
-        if (c0 + c < ncol) F[(size_t)r * ncol + c0 + c] = buf[c * pitch + (r % Ls) * 64 + r / Ls];
-    }
+    const R sc = (R)D.rscale;
+#pragma unroll
+    for (int i = 0; i < MAXL; i++)
+        if (i < len) F[base + (size_t)i * ncol] = sc * v[i];
 }
 
 // ------------------------------------------------------------------ resort
@@ -1474,8 +1459,7 @@ int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *sw
         }
         if (c.ratio && c.rtiles > 0) {
             // the exact-ratio variant: the transverse E then get Psi_B(S_z)^{-1}
-            const size_t sm = (size_t)PIC_RATIO_TC(sizeof(R) == 4) * ((c.rnz + 63) / 64 * 64 + 1) * sizeof(R);
-            k_psi_inv_z<R><<<dim3(c.rtiles, c.ninst, 2), dim3(256), sm, c.stream>>>(c.desc, c.inst0);
+            k_psi_inv_z<R><<<dim3(c.rtiles, c.ninst, 2), dim3(64 * PIC_RATIO_TC), 0, c.stream>>>(c.desc, c.inst0);
         }
     });
     return hip_ok(hipGetLastError());
