@@ -56,8 +56,6 @@ def reverse(sim, tape, lE, lB, lJ, lx, lu):
     Galerkin and Uniform schemes (samples at the Yee locations)."""
     if sim.s.interp == 2:
         raise NotImplementedError("reverse sweep of the momentum-conserving gather")
-    if sim.s.solver != 0:
-        raise NotImplementedError("reverse sweep of the Cole-Karkkainen solver")
     if sim.s.correction == 2:
         raise NotImplementedError("reverse sweep of the exact Psi_E / Psi_B ratio")
     lib = _lib()

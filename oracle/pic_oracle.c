@@ -671,6 +671,41 @@ static void curl_b(const OSim *s, double *const F[3], double *out[3])
             }
 }
 
+/* transpose of Faraday's curl: the backward-difference curl for Yee; for the
+ * Cole-Karkkainen solver every backward difference is averaged across its
+ * direction with (beta, 1 - 2 beta, beta) (the transpose of an average of
+ * forward differences, the average being symmetric) */
+static void curl_faraday_t(const OSim *s, double *const F[3], double *out[3])
+{
+    if (s->solver != 1) {
+        curl_b(s, F, out);
+        return;
+    }
+    const double beta = 0.125, mid = 1.0 - 2.0 * beta;
+    for (long k = 0; k < s->nz; k++)
+        for (long i = 0; i < s->nx; i++) {
+            long p = at(s, i, 0, k);
+            double dz[2], dx[2];
+            for (int c = 0; c < 2; c++) {
+                const double *G = c == 0 ? F[1] : F[0];   /* dz of Fy, dz of Fx */
+                double m0 = (G[at(s, i, 0, k)] - G[at(s, i, 0, k - 1)]) / s->dz;
+                double mm = (G[at(s, i - 1, 0, k)] - G[at(s, i - 1, 0, k - 1)]) / s->dz;
+                double mp = (G[at(s, i + 1, 0, k)] - G[at(s, i + 1, 0, k - 1)]) / s->dz;
+                dz[c] = mid * m0 + beta * (mm + mp);
+            }
+            for (int c = 0; c < 2; c++) {
+                const double *G = c == 0 ? F[2] : F[1];   /* dx of Fz, dx of Fy */
+                double m0 = (G[at(s, i, 0, k)] - G[at(s, i - 1, 0, k)]) / s->dx;
+                double mm = (G[at(s, i, 0, k - 1)] - G[at(s, i - 1, 0, k - 1)]) / s->dx;
+                double mp = (G[at(s, i, 0, k + 1)] - G[at(s, i - 1, 0, k + 1)]) / s->dx;
+                dx[c] = mid * m0 + beta * (mm + mp);
+            }
+            out[0][p] = -dz[0];
+            out[1][p] = dz[1] - dx[0];
+            out[2][p] = dx[1];
+        }
+}
+
 /* adjoint of the gather of one component: scatter w * lv into lF and add
  * d(value)/d(position) * lv to lpos (physical units) */
 static void interp_adj(const OSim *s, const double *F, double *lF, const int *stag, const int *ord,
@@ -947,8 +982,8 @@ void o_adj_step(OSim *s, double *const E1[3], double *const B2[3], double *const
     /* Yee reverse */
     double *w0 = s->Et[0], *w1 = s->Et[1], *w2 = s->Et[2];
     double *cw[3] = {w0, w1, w2};
-    /* B2 = B1 - h Cf E1  ->  lB1 = lB2 ;  lE1 -= h Cb lB2 */
-    curl_b(s, lB, cw);
+    /* B2 = B1 - h Cf E1  ->  lB1 = lB2 ;  lE1 -= h Cf^T lB2 (Cf^T = Cb for Yee) */
+    curl_faraday_t(s, lB, cw);
     for (int c = 0; c < 3; c++)
         for (long q = 0; q < nc; q++) lE[c][q] -= h * cw[c][q];
     /* E1 = E + dt (Cb B1 - J) -> lB1 += dt Cf lE1 ; lJ = -dt lE1 ; lE = lE1 */
@@ -958,8 +993,8 @@ void o_adj_step(OSim *s, double *const E1[3], double *const B2[3], double *const
             lB[c][q] += s->dt * cw[c][q];
             lJ[c][q] = -s->dt * lE[c][q];
         }
-    /* B1 = B - h Cf E -> lB = lB1 ; lE -= h Cb lB1 */
-    curl_b(s, lB, cw);
+    /* B1 = B - h Cf E -> lB = lB1 ; lE -= h Cf^T lB1 */
+    curl_faraday_t(s, lB, cw);
     for (int c = 0; c < 3; c++)
         for (long q = 0; q < nc; q++) lE[c][q] -= h * cw[c][q];
 }

@@ -18,12 +18,14 @@ from oracle.ref import OracleSim, _ptr
 _P = C.POINTER(C.c_double)
 
 
-def _maker(dims, n, order, seed=3, gamma=4.0, ppc=2):
+def _maker(dims, n, order, seed=3, gamma=4.0, ppc=2, interp="galerkin", solver="yee", alpha=None):
     base = "beam2d_64_fp64" if dims == 2 else "beam3d_128x128x256"
+    if alpha is None:
+        alpha = 0.45 if dims == 2 else 0.4
     wl = pi.workload(base, n=n, ppc=ppc, order=order, correction=True, filter=pi.workloads.BINOMIAL4,
-                     gamma=gamma, alpha=0.45 if dims == 2 else 0.4)
+                     gamma=gamma, alpha=alpha, interp=interp, solver=solver)
     x, u = pi.load_beam(dims, n, ppc, gamma, 0.05, seed)
-    a0, b0, _ = psi.psi_coeffs("galerkin", wl["alpha"])
+    a0, b0, _ = psi.psi_coeffs(interp, wl["alpha"])
 
     def mk(a=a0):
         s = OracleSim(wl, x, u, psi=(list(a), b0))
@@ -40,10 +42,14 @@ def _loss(mk, a, nsteps):
     return A.wperp(s)
 
 
-@pytest.mark.parametrize("dims,n,order,nsteps", [(2, (16, 24), 1, 30), (2, (16, 16), 3, 12),
-                                                 (3, (8, 8, 10), 1, 6)])
-def test_adjoint_gradient_matches_finite_differences(dims, n, order, nsteps):
-    mk, a0 = _maker(dims, n, order)
+@pytest.mark.parametrize("dims,n,order,nsteps,interp,solver,alpha", [
+    (2, (16, 24), 1, 30, "galerkin", "yee", None), (2, (16, 16), 3, 12, "galerkin", "yee", None),
+    (3, (8, 8, 10), 1, 6, "galerkin", "yee", None), (2, (16, 24), 1, 30, "uniform", "yee", 0.45),
+    (3, (8, 8, 10), 3, 4, "uniform", "yee", None), (2, (16, 24), 1, 30, "galerkin", "ck", 0.9),
+    (2, (16, 16), 3, 12, "uniform", "ck", 0.9)])
+def test_adjoint_gradient_matches_finite_differences(dims, n, order, nsteps, interp, solver, alpha):
+    """Also with the Uniform gather and the Cole-Karkkainen solver (alpha 0.9)."""
+    mk, a0 = _maker(dims, n, order, interp=interp, solver=solver, alpha=alpha)
     L, g, _ = A.loss_and_grad(lambda: mk(), nsteps)
     assert abs(L - _loss(mk, a0, nsteps)) < 1e-14 * L
     # directional derivative along the gradient (well above the cancellation floor)
@@ -59,11 +65,16 @@ def test_adjoint_gradient_matches_finite_differences(dims, n, order, nsteps):
         assert abs(fdj - g[j]) < 1e-5 * abs(g[j]) + 1e-9 * np.abs(g).max(), (j, fdj, g[j])
 
 
-def test_yee_reverse_is_exact_transpose():
+@pytest.mark.parametrize("solver", ["yee", "ck"])
+def test_yee_reverse_is_exact_transpose(solver):
     """With no particles the step is linear in (E, B, J); its reverse must be its
-    transpose."""
-    wl = pi.workload("beam2d_64_fp64", n=(12, 10), correction=True, filter=pi.workloads.BINOMIAL4,
-                     ion_mode=0, d=(1.0, 0.8))
+    transpose (also with the Cole-Karkkainen curl, on square cells at alpha 0.9)."""
+    if solver == "ck":
+        wl = pi.workload("beam2d_64_fp64", n=(12, 10), correction=True, filter=pi.workloads.BINOMIAL4,
+                         ion_mode=0, solver="ck", alpha=0.9)
+    else:
+        wl = pi.workload("beam2d_64_fp64", n=(12, 10), correction=True, filter=pi.workloads.BINOMIAL4,
+                         ion_mode=0, d=(1.0, 0.8))
     sim = OracleSim(wl, np.zeros((0, 2)), np.zeros((0, 3)))
     rng = np.random.default_rng(1)
     dE, dB, dJ = (rng.normal(size=sim.E.shape) for _ in range(3))
