@@ -78,7 +78,8 @@ extern "C" {
 /* field solvers (Faraday's law; Ampere's law is always the Yee one) */
 #define PIC_YEE 0             /* textbook Yee */
 #define PIC_CK  1             /* Cole-Karkkainen with beta = 1/8 (named in Secs. 2-4):
-                                 2D, square cells (dx == dz), c dt < dx; every
+                                 2D, square cells (dx == dz), c dt < dx, forward
+                                 and reverse runs; every
                                  forward difference of E in Faraday's law is the
                                  (1/8, 3/4, 1/8) mean of that difference on its
                                  line and the two neighbouring lines across it */
@@ -113,8 +114,8 @@ typedef struct pic_config {
     double cdt;               /* c * dt */
     int    shape_order;       /* charge shape order l: 1 or 3 */
     int    interp;            /* PIC_GALERKIN, PIC_UNIFORM or PIC_MOMENTUM; equal
-                                 for all instances; the reverse sweep needs
-                                 PIC_GALERKIN */
+                                 for all instances; the reverse sweep is built
+                                 for PIC_GALERKIN and PIC_UNIFORM */
     int    precision;         /* PIC_FP64 or PIC_FP32; equal for all instances */
     int    correction;        /* PIC_CORR_NONE, PIC_CORR_SPLIT or PIC_CORR_RATIO; the
                                  ratio choice is equal for all instances */
@@ -134,8 +135,7 @@ typedef struct pic_config {
     int    trace_capacity;    /* steps of per-step field-energy trace kept on the device */
     int    adjoint_steps;     /* longest gradient run pic_wperp_gradient may do (0: none) */
     int    adjoint_ckpt;      /* checkpoint interval of gradient runs (steps, >= 1) */
-    int    solver;            /* PIC_YEE or PIC_CK; equal for all instances; the
-                                 reverse sweep needs PIC_YEE */
+    int    solver;            /* PIC_YEE or PIC_CK; equal for all instances */
 } pic_config;
 
 /* particles of one instance as host float64 arrays (structure of arrays) */

@@ -147,29 +147,131 @@ __device__ __forceinline__ void interp_adj(Win &W, int comp, const int *lc, cons
     }
 }
 
-// Reverse of one particle's step.  loff / lu hold the adjoints of the new
-// offset / momentum on entry and of the old ones on exit.
+// Order-l interpolation on every axis from window cells b[a] .. b[a] + L
+// (Uniform scheme), and its adjoint: scatter w * lv, accumulate d/doffset.
 template <int DIM, int L, class R, class Win>
+__device__ __forceinline__ R interp_fl(const Win &W, int comp, const int *b, const R *const *w)
+{
+    constexpr int NY = DIM == 3 ? L + 1 : 1;
+    R s = R(0);
+#pragma unroll
+    for (int kz = 0; kz <= L; kz++)
+#pragma unroll
+        for (int ky = 0; ky < NY; ky++) {
+            R row = R(0);
+#pragma unroll
+            for (int kx = 0; kx <= L; kx++) row += w[0][kx] * W.f(comp, b[0] + kx, DIM == 3 ? b[1] + ky : 0, b[2] + kz);
+            s += (DIM == 3 ? w[1][ky] : R(1)) * w[2][kz] * row;
+        }
+    return s;
+}
+
+template <int DIM, int L, class R, class Win>
+__device__ __forceinline__ void interp_adjl(Win &W, int comp, const int *b, const R *const *w, const R *const *dw,
+                                            R lv, R *lo)
+{
+    constexpr int NY = DIM == 3 ? L + 1 : 1;
+#pragma unroll
+    for (int kz = 0; kz <= L; kz++)
+#pragma unroll
+        for (int ky = 0; ky < NY; ky++) {
+            const R wy = DIM == 3 ? w[1][ky] : R(1), dwy = DIM == 3 ? dw[1][ky] : R(0);
+#pragma unroll
+            for (int kx = 0; kx <= L; kx++) {
+                const int x = b[0] + kx, y = DIM == 3 ? b[1] + ky : 0, z = b[2] + kz;
+                W.addf(comp, x, y, z, w[0][kx] * wy * w[2][kz] * lv);
+                const R fv = W.f(comp, x, y, z) * lv;
+                lo[0] += dw[0][kx] * wy * w[2][kz] * fv;
+                if constexpr (DIM == 3) lo[1] += w[0][kx] * dwy * w[2][kz] * fv;
+                lo[2] += w[0][kx] * wy * dw[2][kz] * fv;
+            }
+        }
+}
+
+// Uniform weights of one particle: integer-node weights wi from window cell
+// bi, and for half-staggered samples the weights wu of the coordinate shifted
+// by half a cell from window cell bu (one lower when the offset is below 1/2)
+template <int DIM, int L, class R> struct UniformW {
+    R wi[3][L + 1], wu[3][L + 1], dwi[3][L + 1], dwu[3][L + 1];
+    int bi[3], bu[3];
+    __device__ __forceinline__ UniformW(const int *lc, const R *off)
+    {
+        constexpr int H = (L - 1) / 2;
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            bi[a] = bu[a] = lc[a] - H;
+            if (DIM == 2 && a == 1) continue;
+            const bool up = off[a] >= R(0.5);
+            const R sh = up ? off[a] - R(0.5) : off[a] + R(0.5);
+            bu[a] -= up ? 0 : 1;
+            Shape<L, R>::integer(off[a], wi[a]);
+            DShape<L, R>::integer(off[a], dwi[a]);
+            Shape<L, R>::integer(sh, wu[a]);
+            DShape<L, R>::integer(sh, dwu[a]);
+        }
+    }
+    // component with staggering (SX, SY, SZ): its window start, weights and derivatives
+    template <int SX, int SY, int SZ>
+    __device__ __forceinline__ void pick(int *b, const R **w, const R **dw) const
+    {
+        b[0] = SX ? bu[0] : bi[0]; b[1] = SY ? bu[1] : bi[1]; b[2] = SZ ? bu[2] : bi[2];
+        w[0] = SX ? wu[0] : wi[0]; w[1] = SY ? wu[1] : wi[1]; w[2] = SZ ? wu[2] : wi[2];
+        dw[0] = SX ? dwu[0] : dwi[0]; dw[1] = SY ? dwu[1] : dwi[1]; dw[2] = SZ ? dwu[2] : dwi[2];
+    }
+    template <int SX, int SY, int SZ, class Win>
+    __device__ __forceinline__ R f(const Win &W, int comp) const
+    {
+        int b[3];
+        const R *w[3], *dw[3];
+        pick<SX, SY, SZ>(b, w, dw);
+        return interp_fl<DIM, L, R>(W, comp, b, w);
+    }
+    template <int SX, int SY, int SZ, class Win>
+    __device__ __forceinline__ void adj(Win &W, int comp, R lv, R *lo) const
+    {
+        int b[3];
+        const R *w[3], *dw[3];
+        pick<SX, SY, SZ>(b, w, dw);
+        interp_adjl<DIM, L, R>(W, comp, b, w, dw, lv, lo);
+    }
+};
+
+// Reverse of one particle's step.  loff / lu hold the adjoints of the new
+// offset / momentum on entry and of the old ones on exit.  IP: gather scheme
+// (Galerkin or Uniform).
+template <int DIM, int L, class R, int IP, class Win>
 __device__ __forceinline__ void adjoint_particle(Win &W, const int *lc, const R *off, const R *u, R *loff, R *lu,
                                                  const R *dtd, R qdt2m, const R *cdr, R cyr)
 {
     constexpr int H = (L - 1) / 2;
     R wi[3][L + 1], wh[3][L], dwi[3][L + 1], dwh[3][L];
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        if (DIM == 2 && a == 1) continue;
-        Shape<L, R>::integer(off[a], wi[a]);
-        Shape<L, R>::half(off[a], wh[a]);
-        DShape<L, R>::integer(off[a], dwi[a]);
-        DShape<L, R>::half(off[a], dwh[a]);
-    }
     R E[3], B[3];
-    E[0] = interp_f<1, 0, 0, DIM, L, R>(W, 0, lc, wi, wh);
-    E[1] = interp_f<0, 1, 0, DIM, L, R>(W, 1, lc, wi, wh);
-    E[2] = interp_f<0, 0, 1, DIM, L, R>(W, 2, lc, wi, wh);
-    B[0] = interp_f<0, 1, 1, DIM, L, R>(W, 3, lc, wi, wh);
-    B[1] = interp_f<1, 0, 1, DIM, L, R>(W, 4, lc, wi, wh);
-    B[2] = interp_f<1, 1, 0, DIM, L, R>(W, 5, lc, wi, wh);
+    // staggering: Ex(1,0,0) Ey(0,1,0) Ez(0,0,1) Bx(0,1,1) By(1,0,1) Bz(1,1,0)
+    // (unused, and so removed by the compiler, with the Galerkin gather)
+    const UniformW<DIM, L, R> uw(lc, off);
+    if constexpr (IP == GATHER_UNIFORM) {
+        E[0] = uw.template f<1, 0, 0>(W, 0);
+        E[1] = uw.template f<0, 1, 0>(W, 1);
+        E[2] = uw.template f<0, 0, 1>(W, 2);
+        B[0] = uw.template f<0, 1, 1>(W, 3);
+        B[1] = uw.template f<1, 0, 1>(W, 4);
+        B[2] = uw.template f<1, 1, 0>(W, 5);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            if (DIM == 2 && a == 1) continue;
+            Shape<L, R>::integer(off[a], wi[a]);
+            Shape<L, R>::half(off[a], wh[a]);
+            DShape<L, R>::integer(off[a], dwi[a]);
+            DShape<L, R>::half(off[a], dwh[a]);
+        }
+        E[0] = interp_f<1, 0, 0, DIM, L, R>(W, 0, lc, wi, wh);
+        E[1] = interp_f<0, 1, 0, DIM, L, R>(W, 1, lc, wi, wh);
+        E[2] = interp_f<0, 0, 1, DIM, L, R>(W, 2, lc, wi, wh);
+        B[0] = interp_f<0, 1, 1, DIM, L, R>(W, 3, lc, wi, wh);
+        B[1] = interp_f<1, 0, 1, DIM, L, R>(W, 4, lc, wi, wh);
+        B[2] = interp_f<1, 1, 0, DIM, L, R>(W, 5, lc, wi, wh);
+    }
     // Boris and move, recomputed with the forward kernel's own routines
     R un[3];
     BorisTrace<R> bt;
@@ -326,17 +428,26 @@ __device__ __forceinline__ void adjoint_particle(Win &W, const int *lc, const R 
         lu[a] = lum[a];
     }
     // gather reverse
-    interp_adj<1, 0, 0, DIM, L, R>(W, 0, lc, wi, wh, dwi, dwh, lE[0], lo);
-    interp_adj<0, 1, 0, DIM, L, R>(W, 1, lc, wi, wh, dwi, dwh, lE[1], lo);
-    interp_adj<0, 0, 1, DIM, L, R>(W, 2, lc, wi, wh, dwi, dwh, lE[2], lo);
-    interp_adj<0, 1, 1, DIM, L, R>(W, 3, lc, wi, wh, dwi, dwh, lB[0], lo);
-    interp_adj<1, 0, 1, DIM, L, R>(W, 4, lc, wi, wh, dwi, dwh, lB[1], lo);
-    interp_adj<1, 1, 0, DIM, L, R>(W, 5, lc, wi, wh, dwi, dwh, lB[2], lo);
+    if constexpr (IP == GATHER_UNIFORM) {
+        uw.template adj<1, 0, 0>(W, 0, lE[0], lo);
+        uw.template adj<0, 1, 0>(W, 1, lE[1], lo);
+        uw.template adj<0, 0, 1>(W, 2, lE[2], lo);
+        uw.template adj<0, 1, 1>(W, 3, lB[0], lo);
+        uw.template adj<1, 0, 1>(W, 4, lB[1], lo);
+        uw.template adj<1, 1, 0>(W, 5, lB[2], lo);
+    } else {
+        interp_adj<1, 0, 0, DIM, L, R>(W, 0, lc, wi, wh, dwi, dwh, lE[0], lo);
+        interp_adj<0, 1, 0, DIM, L, R>(W, 1, lc, wi, wh, dwi, dwh, lE[1], lo);
+        interp_adj<0, 0, 1, DIM, L, R>(W, 2, lc, wi, wh, dwi, dwh, lE[2], lo);
+        interp_adj<0, 1, 1, DIM, L, R>(W, 3, lc, wi, wh, dwi, dwh, lB[0], lo);
+        interp_adj<1, 0, 1, DIM, L, R>(W, 4, lc, wi, wh, dwi, dwh, lB[1], lo);
+        interp_adj<1, 1, 0, DIM, L, R>(W, 5, lc, wi, wh, dwi, dwh, lB[2], lo);
+    }
 #pragma unroll
     for (int a = 0; a < 3; a++) loff[a] = lo[a];
 }
 
-template <int DIM, int L, class R>
+template <int DIM, int L, class R, int IP>
 __global__ void __launch_bounds__(256) k_adj_particles(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                        int nwork, int wmx, int wmy, int wmz)
 {
@@ -411,8 +522,8 @@ __global__ void __launch_bounds__(256) k_adj_particles(const InstDesc *__restric
                 off[a] = po[a][p];
                 loff[a] = plo[a][p];
             }
-            if (fits) adjoint_particle<DIM, L, R>(lw, lc, off, u, loff, lu, dtd, qdt2m, cdr, cyr);
-            else adjoint_particle<DIM, L, R>(gw, lc, off, u, loff, lu, dtd, qdt2m, cdr, cyr);
+            if (fits) adjoint_particle<DIM, L, R, IP>(lw, lc, off, u, loff, lu, dtd, qdt2m, cdr, cyr);
+            else adjoint_particle<DIM, L, R, IP>(gw, lc, off, u, loff, lu, dtd, qdt2m, cdr, cyr);
 #pragma unroll
             for (int a = 0; a < 3; a++) {
                 plu[a][p] = lu[a];
@@ -783,12 +894,18 @@ __global__ void __launch_bounds__(256) k_adj_seen_2d(const InstDesc *__restrict_
 // Fused transposed Yee update (2D): with h = dt/2 and Cb = Cf^T,
 //   lE' = lE - h Cb lB;   lB' = lB + dt Cf lE';  lJ = -dt lE';   lE'' = lE' - h Cb lB'
 // One window for the six input planes: cells [x0 - 2, x0 + TX + 1) x [z0 - 2, z0 + TZ + 1).
-template <class R, int TZ>
+// CK: with the Cole-Karkkainen curl, the transposed Faraday curl averages each
+// backward difference across its direction with (1/8, 3/4, 1/8); the window
+// grows by two cells on the high side: lambda_E' on [-1, T+1], lambda_B'' on [-1, T].
+template <class R, int TZ, bool CK = false>
 __global__ void __launch_bounds__(256) k_adj_yee_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
 {
     constexpr int TX = PIC_YEE_TX;
     static_assert(TX == 64, "one lane per column");
-    constexpr int WX = TX + 3, WZ = TZ + 3, WN = WX * WZ;
+    constexpr int WX = TX + (CK ? 5 : 3), WZ = TZ + (CK ? 5 : 3), WN = WX * WZ;
+    // local ranges (local = global + 2): lambda_E' on [1, EH), lambda_B'' on [1, BH)
+    constexpr int EHX = TX + (CK ? 4 : 3), EHZ = TZ + (CK ? 4 : 3);
+    constexpr int BHX = TX + (CK ? 3 : 2), BHZ = TZ + (CK ? 3 : 2);
     __shared__ R sE[3][WN], sB[3][WN];
     const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
     const InstDesc &D = Dt[inst];
@@ -832,28 +949,43 @@ __global__ void __launch_bounds__(256) k_adj_yee_2d(const InstDesc *__restrict__
     }
     __syncthreads();
     const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
-    // lE' on local [1, T + 3) (cells -1 .. T): backward differences of lB
-    for (int lz = 1 + wave; lz < TZ + 3; lz += nwave) {
+    // transposed Faraday differences at window cell e: backward, CK-averaged across
+    auto bdx = [&](const R *F, int e) {
+        if constexpr (CK)
+            return (R(0.75) * (F[e] - F[e - 1]) +
+                    R(0.125) * ((F[e - WX] - F[e - WX - 1]) + (F[e + WX] - F[e + WX - 1]))) * idx;
+        else
+            return (F[e] - F[e - 1]) * idx;
+    };
+    auto bdz = [&](const R *F, int e) {
+        if constexpr (CK)
+            return (R(0.75) * (F[e] - F[e - WX]) +
+                    R(0.125) * ((F[e - 1] - F[e - 1 - WX]) + (F[e + 1] - F[e + 1 - WX]))) * idz;
+        else
+            return (F[e] - F[e - WX]) * idz;
+    };
+    // lE' on local [1, EH) (cells -1 .. T, or T + 1 with CK): transposed Faraday of lB
+    for (int lz = 1 + wave; lz < EHZ; lz += nwave) {
 #pragma unroll
         for (int hh = 0; hh < 2; hh++) {
             const int lx = hh ? TX + 1 + lane : 1 + lane;
-            if (lx >= TX + 3) break;
-            const int e = lz * WX + lx, exm = e - 1, ezm = e - WX;
-            const R cx = -(sB[1][e] - sB[1][ezm]) * idz;
-            const R cy = (sB[0][e] - sB[0][ezm]) * idz - (sB[2][e] - sB[2][exm]) * idx;
-            const R cz = (sB[1][e] - sB[1][exm]) * idx;
+            if (lx >= EHX) break;
+            const int e = lz * WX + lx;
+            const R cx = -bdz(sB[1], e);
+            const R cy = bdz(sB[0], e) - bdx(sB[2], e);
+            const R cz = bdx(sB[1], e);
             sE[0][e] -= h * cx;
             sE[1][e] -= h * cy;
             sE[2][e] -= h * cz;
         }
     }
     __syncthreads();
-    // lB' on local [1, T + 2) (cells -1 .. T - 1): forward differences of lE'
-    for (int lz = 1 + wave; lz < TZ + 2; lz += nwave) {
+    // lB' on local [1, BH) (cells -1 .. T - 1, or T with CK): forward differences of lE'
+    for (int lz = 1 + wave; lz < BHZ; lz += nwave) {
 #pragma unroll
         for (int hh = 0; hh < 2; hh++) {
             const int lx = hh ? TX + 1 + lane : 1 + lane;
-            if (lx >= TX + 2) break;
+            if (lx >= BHX) break;
             const int e = lz * WX + lx, exp = e + 1, ezp = e + WX;
             const R fx = -(sE[1][ezp] - sE[1][e]) * idz;
             const R fy = (sE[0][ezp] - sE[0][e]) * idz - (sE[2][exp] - sE[2][e]) * idx;
@@ -869,10 +1001,10 @@ __global__ void __launch_bounds__(256) k_adj_yee_2d(const InstDesc *__restrict__
     for (int lz = wave; lz < TZ; lz += nwave) {
         const int gz = z0 + lz;
         if (gz >= nz) break;
-        const int e = (lz + 2) * WX + lane + 2, exm = e - 1, ezm = e - WX;
-        const R cx = -(sB[1][e] - sB[1][ezm]) * idz;
-        const R cy = (sB[0][e] - sB[0][ezm]) * idz - (sB[2][e] - sB[2][exm]) * idx;
-        const R cz = (sB[1][e] - sB[1][exm]) * idx;
+        const int e = (lz + 2) * WX + lane + 2;
+        const R cx = -bdz(sB[1], e);
+        const R cy = bdz(sB[0], e) - bdx(sB[2], e);
+        const R cz = bdx(sB[1], e);
         const int g = gz * nx + gx;
         lJ[0][g] = -dt * sE[0][e]; lJ[1][g] = -dt * sE[1][e]; lJ[2][g] = -dt * sE[2][e];
         lE[0][g] = sE[0][e] - h * cx;
@@ -930,7 +1062,15 @@ int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fw
     const size_t smem = adjoint_smem_bytes(live.dims, live.fp32, wm);
     const dim3 gf(nfwork), g6(nfwork, 6), g2(nfwork, 2), bf(PIC_FIELD_CHUNK);
     hipStream_t st = live.stream;
-#define AK(D_, L_) k_adj_particles<D_, L_, R><<<dim3(npwork), dim3(block), smem, st>>>(tape.desc, pwork, npwork, wm[0], wm[1], wm[2])
+#define AK(D_, L_)                                                                                             \
+    do {                                                                                                       \
+        if (live.gather == GATHER_UNIFORM)                                                                     \
+            k_adj_particles<D_, L_, R, GATHER_UNIFORM><<<dim3(npwork), dim3(block), smem, st>>>(tape.desc, pwork, \
+                                                                                              npwork, wm[0], wm[1], wm[2]); \
+        else                                                                                                   \
+            k_adj_particles<D_, L_, R, GATHER_GALERKIN><<<dim3(npwork), dim3(block), smem, st>>>(tape.desc, pwork, \
+                                                                                               npwork, wm[0], wm[1], wm[2]); \
+    } while (0)
     DISPATCH_R(live.fp32, {
         // 2D: the reverse Yee kernel of the previous reverse step (or the seed)
         // left lambda_Et, lambda_Bt zero
@@ -951,7 +1091,8 @@ int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fw
                 k_adj_seen_2d<R, PIC_ADJ_TZ, 4, 4, 4, 8><<<g6a, bf, sm, st>>>(tape.desc, awork);
             else
                 k_adj_seen_2d<R, PIC_ADJ_TZ, -1, -1, -1, -1><<<g6a, bf, sm, st>>>(tape.desc, awork);
-            k_adj_yee_2d<R, PIC_ADJ_TZ><<<dim3(nawork), bf, 0, st>>>(live.desc, awork);
+            if (live.ck) k_adj_yee_2d<R, PIC_ADJ_TZ, true><<<dim3(nawork), bf, 0, st>>>(live.desc, awork);
+            else k_adj_yee_2d<R, PIC_ADJ_TZ, false><<<dim3(nawork), bf, 0, st>>>(live.desc, awork);
         } else {
             // lambda_E += M_E lambda_Et, lambda_B += M_B lambda_Bt
             k_pass<2, R><<<g6, bf, 0, st>>>(live.desc, fwork, PL_LSEEN, PL_T1, 0, 0);

@@ -118,7 +118,6 @@ int validate(const pic_config &c, int idx)
         if (c.dims != 2) return bad(PIC_EUNSUPPORTED, "the Cole-Karkkainen solver is built for 2D");
         if (c.dx != c.dz) return bad(PIC_EUNSUPPORTED, "the Cole-Karkkainen solver needs square cells (dx == dz)");
         if (c.cdt >= c.dx) return bad(PIC_ECOURANT, "Cole-Karkkainen limit c dt < dx violated");
-        if (c.adjoint_steps > 0) return bad(PIC_EUNSUPPORTED, "the reverse sweep is built for the Yee solver only");
     } else {
         double s = 1.0 / (c.dx * c.dx) + 1.0 / (c.dz * c.dz) + (c.dims == 3 ? 1.0 / (c.dy * c.dy) : 0.0);
         if (c.cdt * std::sqrt(s) >= 1.0) return bad(PIC_ECOURANT, "Courant limit c dt < 1/sqrt(sum 1/d^2) violated");
@@ -126,8 +125,8 @@ int validate(const pic_config &c, int idx)
     if (c.shape_order != 1 && c.shape_order != 3) return bad(PIC_EINVAL, "shape_order must be 1 or 3");
     if (c.interp != PIC_GALERKIN && c.interp != PIC_UNIFORM && c.interp != PIC_MOMENTUM)
         return bad(PIC_EINVAL, "interp must be PIC_GALERKIN, PIC_UNIFORM or PIC_MOMENTUM");
-    if (c.interp != PIC_GALERKIN && c.adjoint_steps > 0)
-        return bad(PIC_EUNSUPPORTED, "the reverse sweep is built for the Galerkin gather only");
+    if (c.interp == PIC_MOMENTUM && c.adjoint_steps > 0)
+        return bad(PIC_EUNSUPPORTED, "the reverse sweep is built for the Galerkin and Uniform gathers");
     if (c.precision != PIC_FP32 && c.precision != PIC_FP64) return bad(PIC_EINVAL, "precision");
     if (c.filter_npass < 0 || c.filter_npass > 8) return bad(PIC_EINVAL, "filter_npass must be in [0, 8]");
     // the node average of the momentum-conserving gather widens every stencil by one cell

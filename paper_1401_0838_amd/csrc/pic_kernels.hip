@@ -1495,8 +1495,19 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
         } else if (c.order == 1) PKS(3, 1, 0, IP_);                                 \
         else PKS(3, 3, 0, IP_);                                                     \
     } while (0)
+#define PKRU(L_, P_) k_particles<2, L_, R, P_, false, true, GATHER_UNIFORM><<<g, b, smem, c.stream>>>(c.desc, c.single ? nullptr : pwork, nwork, wm[0], wm[1], wm[2], c.par)
     DISPATCH_R(c.fp32, {
-        if (c.gather == GATHER_UNIFORM) {
+        if (c.gather == GATHER_UNIFORM && c.record && c.dims == 2) {
+            // recording a tape slot (2D reverse sweep) with the Uniform gather
+            if (c.order == 1) {
+                if (wm[0] == 24 && wm[2] == 24) PKRU(1, 24);
+                else if (wm[0] == 32 && wm[2] == 32) PKRU(1, 32);
+                else PKRU(1, 0);
+            } else {
+                if (wm[0] == 32 && wm[2] == 32) PKRU(3, 32);
+                else PKRU(3, 0);
+            }
+        } else if (c.gather == GATHER_UNIFORM) {
             PK_SCHEME(GATHER_UNIFORM);
         } else if (c.gather == GATHER_NODAL) {
             PK_SCHEME(GATHER_NODAL);
@@ -1528,6 +1539,7 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
 #undef PK24
 #undef PKR
 #undef PKS
+#undef PKRU
 #undef PK_SCHEME
     return hip_ok(hipGetLastError());
 }

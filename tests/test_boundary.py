@@ -96,11 +96,14 @@ def test_plan_validates_configs():
     with pytest.raises(L.PicError) as e:
         L.pic_plan([c], [16])
     assert e.value.code == L.PIC_EINVAL
-    c = _cfg(interp="uniform")
+    c = _cfg(interp="momentum")
     c.adjoint_steps, c.adjoint_ckpt = 4, 2
     with pytest.raises(L.PicError) as e:
         L.pic_plan([c], [16])
     assert e.value.code == L.PIC_EUNSUPPORTED
+    c = _cfg(interp="uniform")
+    c.adjoint_steps, c.adjoint_ckpt = 4, 2
+    assert L.pic_plan([c], [16]) > 0
     # exact ratio: nz <= 1024, shared by a batch, forward only
     assert L.pic_plan([_cfg(correction="ratio")], [16]) > 0
     with pytest.raises(L.PicError) as e:
@@ -130,9 +133,7 @@ def test_plan_validates_configs():
     assert e.value.code == L.PIC_EINVAL
     c = _cfg(solver="ck")
     c.adjoint_steps, c.adjoint_ckpt = 4, 2
-    with pytest.raises(L.PicError) as e:
-        L.pic_plan([c], [16])
-    assert e.value.code == L.PIC_EUNSUPPORTED
+    assert L.pic_plan([c], [16]) > 0
     with pytest.raises(L.PicError):
         L.pic_plan([_cfg(), _cfg(dims=3, n=(8, 8, 8))], [16, 16])
 

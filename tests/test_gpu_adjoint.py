@@ -24,10 +24,12 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _setup(dims, n, order, ppc=2, gamma=4.0, seed=3, sigma=0.05):
+def _setup(dims, n, order, ppc=2, gamma=4.0, seed=3, sigma=0.05, interp="galerkin", solver="yee", alpha=None):
     base = "beam2d_64_fp64" if dims == 2 else "beam3d_128x128x256"
+    if alpha is None:
+        alpha = 0.45 if dims == 2 else 0.4
     wl = pi.workload(base, n=n, ppc=ppc, order=order, correction=True, filter=pi.workloads.BINOMIAL4,
-                     gamma=gamma, alpha=0.45 if dims == 2 else 0.4)
+                     gamma=gamma, alpha=alpha, interp=interp, solver=solver)
     x, u = pi.load_beam(dims, n, ppc, gamma, sigma, seed)
     rng = np.random.default_rng(seed)
     shape = (3,) + ((n[1], 1, n[0]) if dims == 2 else (n[2], n[1], n[0]))
@@ -70,6 +72,31 @@ def test_adjoint_fp64_matches_oracle(dims, n, order, nsteps, ckpt):
     # the state is back at the end of the forward run
     assert np.linalg.norm(sim.fields("E") - ref.E) < 1e-10 * np.linalg.norm(ref.E)
     sim.close()
+
+
+@pytest.mark.parametrize("dims,n,order,nsteps,ckpt,interp,solver,alpha", [
+    (2, (32, 32), 1, 30, 10, "uniform", "yee", 0.45), (2, (24, 32), 3, 12, 5, "uniform", "yee", 0.45),
+    (3, (8, 8, 12), 1, 8, 4, "uniform", "yee", None), (2, (32, 32), 1, 30, 10, "galerkin", "ck", 0.9),
+    (2, (24, 32), 3, 12, 5, "uniform", "ck", 0.95)])
+def test_adjoint_schemes_and_ck_fp64_match_oracle(dims, n, order, nsteps, ckpt, interp, solver, alpha):
+    """The reverse sweep with the Uniform gather and with the Cole-Karkkainen
+    solver (alpha up to 0.95), FP64, against the oracle's adjoint."""
+    wl, x, u, E0, B0 = _setup(dims, n, order, interp=interp, solver=solver, alpha=alpha)
+    _say("adjoint fp64 %s order %d steps %d %s %s alpha %s" % (n, order, nsteps, interp, solver, alpha))
+    L_ref, g_ref, ref = _oracle(wl, x, u, E0, B0, nsteps)
+    sim = _gpu(wl, x, u, E0, B0, "fp64", nsteps, ckpt)
+    L = sim.adjoint_forward(nsteps)[0]
+    g = sim.adjoint_backward()[0]
+    _say("  L %.12e ref %.12e  g %s ref %s" % (L, L_ref, g, g_ref))
+    assert abs(L - L_ref) < 1e-10 * L_ref
+    assert np.max(np.abs(g - g_ref)) < 1e-8 * np.max(np.abs(g_ref))
+    sim.close()
+    # FP32 within the FP32 bar
+    sim = _gpu(wl, x, u, E0, B0, "fp32", nsteps, ckpt)
+    sim.adjoint_forward(nsteps)
+    g32 = sim.adjoint_backward()[0]
+    sim.close()
+    assert np.max(np.abs(g32 - g_ref)) < 1e-2 * np.max(np.abs(g_ref))
 
 
 def test_adjoint_fp32_close_to_oracle_and_autograd():
