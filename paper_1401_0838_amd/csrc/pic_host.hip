@@ -273,6 +273,8 @@ LaunchCtx ctx(const pic_state *s)
 }
 
 int yee_tz_eff(int tz, int fp32) { return (!fp32 && tz > 8) ? 8 : tz; }
+// 2D seen-field tile height: 32 rows of doubles with the widest stencils exceed 64 KB of LDS
+int seen_tz_eff(int tz, int fp32) { return (!fp32 && tz > 16) ? 16 : tz; }
 
 // Lay out all arrays; with base == nullptr only the size is computed.
 size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *np, char *base)
@@ -1075,7 +1077,7 @@ extern "C" int pic_set_option(pic_state *s, const char *name, int value)
         s->yee_tz = yee_tz_eff(value, s->fp32);
     } else if (n == "seen_tile_z") {
         if (value != 8 && value != 16 && value != 32) return fail(PIC_EINVAL, "seen_tile_z must be 8, 16 or 32");
-        s->seen_tz = value;
+        s->seen_tz = seen_tz_eff(value, s->fp32);
     } else if (n == "resort_every") {
         if (value < 1 || value > 1024) return fail(PIC_EINVAL, "resort_every must be in [1, 1024]");
         s->graph_k = value;

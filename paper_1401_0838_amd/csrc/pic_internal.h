@@ -154,7 +154,7 @@ int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *sw
 // columns (one wave each) per workgroup of the Psi_B inversion along z, and its largest nz
 #define PIC_RATIO_TC 4
 #define PIC_RATIO_MAXNZ 1024
-size_t seen_smem_bytes(int fp32, int tz);
+size_t seen_smem_bytes(int fp32, int tz, int hz, int hx);
 int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid, int block,
                      const int wmax[3]);
 size_t particle_smem_bytes(int dims, int fp32, const int wmax[3]);

@@ -822,20 +822,24 @@ __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ 
     G<R>(dst)[cell] = acc;
 }
 
-// 2D fields as seen by the particles in one kernel: a (64 x SZ) output tile of
-// one component is loaded with its stencil halo into LDS, the combined z
-// stencil (Psi o z filter) is applied into a second LDS tile, then the x
-// filter stencil writes the output.  blockIdx.y = component, work = (inst, tile).
-// Waves own rows and lanes own columns (64 + halo), so addresses are affine in
-// the lane.  HZ, HX >= 0 fix the stencil half-widths at compile time (taps in
-// registers, loops unrolled); -1 reads them from the descriptor.
+// 2D fields as seen by the particles in one kernel: one component's (64 x SEEN_TZ)
+// output tile is staged in LDS with its stencil halo (waves own rows, lanes own
+// columns, so addresses are affine in the lane); the x filter stencil then runs
+// on every staged row for the 64 output columns, four neighbouring columns per
+// thread with their shared inputs read once; last, the combined z stencil
+// (Psi o z filter) walks down each column, SEEN_TZ / 4 consecutive output rows
+// per wave, the rows they share read once.  The two stencils act on different
+// axes of a periodic grid, so they commute: x then z is the same operator as
+// z then x.  blockIdx.y = component, work = (inst, tile); four waves per block.
+// HZ, HX >= 0 fix the stencil half-widths at compile time (taps in registers,
+// loops unrolled); -1 reads them from the descriptor.
 #define SEEN_TX PIC_SEEN_TX
 template <class R, int SEEN_TZ, int HZ, int HX>
 __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                  int par)
 {
-    typedef typename JOf<R>::T JT;
     static_assert(SEEN_TX == 64, "one lane per column");
+    static_assert(SEEN_TZ % 4 == 0, "the four waves split the output rows");
     extern __shared__ __align__(16) unsigned char smem[];
     // work == nullptr: one instance, block b is tile b (saves a dependent load)
     const int inst = work ? work[blockIdx.x].x : 0, t = work ? work[blockIdx.x].y : (int)blockIdx.x;
@@ -847,9 +851,9 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     const int hz = HZ >= 0 ? HZ : D.hz, hx = HX >= 0 ? HX : D.hx;
     const int wx = SEEN_TX + 2 * hx, wz = SEEN_TZ + 2 * hz;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
-    R *win = reinterpret_cast<R *>(smem);
-    R *mid = win + wx * wz;
-    R *tz = mid + wx * SEEN_TZ;
+    R *win = reinterpret_cast<R *>(smem);   // wz x wx: the staged window
+    R *mid = win + wx * wz;                 // wz x 64: after the x stencil
+    R *tz = mid + SEEN_TX * wz;
     R *tx = tz + 2 * PIC_MAX_HZ + 1;
     const double *tzs = ztaps(D, comp), *txs = xtaps(D, comp);
     constexpr int NTZ = HZ >= 0 ? 2 * HZ + 1 : 1, NTX = HX >= 0 ? 2 * HX + 1 : 1;
@@ -892,39 +896,58 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
         }
     }
     __syncthreads();
-    // z pass on all wx columns
-    for (int zz = wave; zz < SEEN_TZ; zz += nwave) {
+    // x stencil: item (row r, output columns [4 q, 4 q + 4)) of wz x 16 items
+    constexpr int XQ = 4, NQ = SEEN_TX / XQ;
+    for (int it = threadIdx.x; it < wz * NQ; it += blockDim.x) {
+        const int r = it / NQ, c0 = (it % NQ) * XQ;
+        const R *w = win + r * wx + c0;
+        R *o = mid + r * SEEN_TX + c0;
+        if constexpr (HX >= 0) {
+            R v[XQ + 2 * HX];
 #pragma unroll
-        for (int half = 0; half < 2; half++) {
-            if (half == 1 && !hasb) break;
-            const int col = half ? SEEN_TX + lane : lane;
-            const R *w = win + zz * wx + col;
-            R acc = R(0);
-            if constexpr (HZ >= 0) {
+            for (int k = 0; k < XQ + 2 * HX; k++) v[k] = w[k];
 #pragma unroll
-                for (int k = 0; k < NTZ; k++) acc += rz[k] * w[k * wx];
-            } else {
-                for (int k = 0; k <= 2 * hz; k++) acc += tz[k] * w[k * wx];
+            for (int q = 0; q < XQ; q++) {
+                R acc = R(0);
+#pragma unroll
+                for (int k = 0; k < NTX; k++) acc += rx[k] * v[q + k];
+                o[q] = acc;
             }
-            mid[zz * wx + col] = acc;
+        } else {
+            for (int q = 0; q < XQ; q++) {
+                R acc = R(0);
+                for (int k = 0; k <= 2 * hx; k++) acc += tx[k] * w[q + k];
+                o[q] = acc;
+            }
         }
     }
     __syncthreads();
+    // z stencil: wave -> output rows [RB wave, RB wave + RB), lane -> column
+    constexpr int RB = SEEN_TZ / 4;
     gp<R> dst = G<R>(comp < 3 ? D.Et[comp] : D.Bt[comp - 3]);
-    const int gx = x0 + lane;
+    const int gx = x0 + lane, zr = wave * RB;
     if (gx >= nx) return;
-    for (int zz = wave; zz < SEEN_TZ; zz += nwave) {
-        const int gz = z0 + zz;
-        if (gz >= nz) break;
-        const R *m = mid + zz * wx + lane;
-        R acc = R(0);
-        if constexpr (HX >= 0) {
+    const R *m = mid + zr * SEEN_TX + lane;
+    if constexpr (HZ >= 0) {
+        R v[RB + 2 * HZ];
 #pragma unroll
-            for (int k = 0; k < NTX; k++) acc += rx[k] * m[k];
-        } else {
-            for (int k = 0; k <= 2 * hx; k++) acc += tx[k] * m[k];
+        for (int k = 0; k < RB + 2 * HZ; k++) v[k] = m[k * SEEN_TX];
+#pragma unroll
+        for (int j = 0; j < RB; j++) {
+            const int gz = z0 + zr + j;
+            R acc = R(0);
+#pragma unroll
+            for (int k = 0; k < NTZ; k++) acc += rz[k] * v[j + k];
+            if (gz < nz) dst[gz * nx + gx] = acc;
         }
-        dst[gz * nx + gx] = acc;
+    } else {
+        for (int j = 0; j < RB; j++) {
+            const int gz = z0 + zr + j;
+            if (gz >= nz) break;
+            R acc = R(0);
+            for (int k = 0; k <= 2 * hz; k++) acc += tz[k] * m[(j + k) * SEEN_TX];
+            dst[gz * nx + gx] = acc;
+        }
     }
 }
 
@@ -1402,16 +1425,17 @@ int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywo
     return hip_ok(hipGetLastError());
 }
 
-size_t seen_smem_bytes(int fp32, int tz)
+size_t seen_smem_bytes(int fp32, int tz, int hz, int hx)
 {
-    const int wx = SEEN_TX + 2 * PIC_MAX_HX, wz = tz + 2 * PIC_MAX_HZ;
-    return (size_t)(wx * wz + wx * tz + 2 * PIC_MAX_HZ + 1 + 2 * PIC_MAX_HX + 1) * (fp32 ? 4 : 8);
+    const int wx = SEEN_TX + 2 * hx, wz = tz + 2 * hz;
+    return (size_t)(wx * wz + SEEN_TX * wz + 2 * PIC_MAX_HZ + 1 + 2 * PIC_MAX_HX + 1) * (fp32 ? 4 : 8);
 }
 
 template <class R, int TZ>
 void launch_seen_2d_tz(const LaunchCtx &c, const int2 *swork, int nswork)
 {
-    const size_t sm = seen_smem_bytes(c.fp32, TZ);
+    // instances with different stencils (c.hz < 0) size the window for the widest
+    const size_t sm = seen_smem_bytes(c.fp32, TZ, c.hz < 0 ? PIC_MAX_HZ : c.hz, c.hx < 0 ? PIC_MAX_HX : c.hx);
     const dim3 g(nswork, 6), b(PIC_FIELD_CHUNK);
     if (c.single) swork = nullptr;
     // half-widths: correction of degree 4 with four filter passes (8, 4);
