@@ -709,34 +709,29 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
         else
             return (F[e + WX] - F[e]) * idz;
     };
+    // The two halo phases cover a few more columns than the 64 lanes; their
+    // (row, column) cells are dealt out to the block's threads in order, so no
+    // wave runs a second pass for those few columns.
     // B^{n-1/2} on local rows and columns [ELO - 1, EH): forward differences of E
-    for (int lz = ELO - 1 + wave; lz < EHZ; lz += nwave) {
-#pragma unroll
-        for (int hh = 0; hh < 2; hh++) {
-            const int lx = ELO - 1 + (hh ? TX : 0) + lane;
-            if (lx >= EHX) break;
-            const int e = lz * WX + lx;
-            const R dzEy = fdz(sE[1], e), dzEx = fdz(sE[0], e);
-            const R dxEz = fdx(sE[2], e), dxEy = fdx(sE[1], e);
-            sB[0][e] -= h * (-dzEy);
-            sB[1][e] -= h * (dzEx - dxEz);
-            sB[2][e] -= h * dxEy;
-        }
+    constexpr int C1 = EHX - ELO + 1, N1 = (EHZ - ELO + 1) * C1;
+    for (int it = threadIdx.x; it < N1; it += blockDim.x) {
+        const int e = (ELO - 1 + it / C1) * WX + ELO - 1 + it % C1;
+        const R dzEy = fdz(sE[1], e), dzEx = fdz(sE[0], e);
+        const R dxEz = fdx(sE[2], e), dxEy = fdx(sE[1], e);
+        sB[0][e] -= h * (-dzEy);
+        sB[1][e] -= h * (dzEx - dxEz);
+        sB[2][e] -= h * dxEy;
     }
     __syncthreads();
     // E^n on local [ELO, EH): backward differences of B^{n-1/2}
-    for (int lz = ELO + wave; lz < EHZ; lz += nwave) {
-#pragma unroll
-        for (int hh = 0; hh < 2; hh++) {
-            const int lx = ELO + (hh ? TX : 0) + lane;
-            if (lx >= EHX) break;
-            const int e = lz * WX + lx, exm = e - 1, ezm = e - WX;
-            const R dzBy = (sB[1][e] - sB[1][ezm]) * idz, dzBx = (sB[0][e] - sB[0][ezm]) * idz;
-            const R dxBz = (sB[2][e] - sB[2][exm]) * idx, dxBy = (sB[1][e] - sB[1][exm]) * idx;
-            sE[0][e] += dt * (-dzBy - sJ[0][e]);
-            sE[1][e] += dt * (dzBx - dxBz - sJ[1][e]);
-            sE[2][e] += dt * (dxBy - sJ[2][e]);
-        }
+    constexpr int C2 = EHX - ELO, N2 = (EHZ - ELO) * C2;
+    for (int it = threadIdx.x; it < N2; it += blockDim.x) {
+        const int e = (ELO + it / C2) * WX + ELO + it % C2, exm = e - 1, ezm = e - WX;
+        const R dzBy = (sB[1][e] - sB[1][ezm]) * idz, dzBx = (sB[0][e] - sB[0][ezm]) * idz;
+        const R dxBz = (sB[2][e] - sB[2][exm]) * idx, dxBy = (sB[1][e] - sB[1][exm]) * idx;
+        sE[0][e] += dt * (-dzBy - sJ[0][e]);
+        sE[1][e] += dt * (dzBx - dxBz - sJ[1][e]);
+        sE[2][e] += dt * (dxBy - sJ[2][e]);
     }
     __syncthreads();
     // B^n on the tile and the stores
