@@ -964,36 +964,30 @@ __global__ void __launch_bounds__(256) k_adj_yee_2d(const InstDesc *__restrict__
         else
             return (F[e] - F[e - WX]) * idz;
     };
+    // The two halo phases cover a few more columns than the 64 lanes: their
+    // (row, column) cells are dealt out to the block's threads in order.
     // lE' on local [1, EH) (cells -1 .. T, or T + 1 with CK): transposed Faraday of lB
-    for (int lz = 1 + wave; lz < EHZ; lz += nwave) {
-#pragma unroll
-        for (int hh = 0; hh < 2; hh++) {
-            const int lx = hh ? TX + 1 + lane : 1 + lane;
-            if (lx >= EHX) break;
-            const int e = lz * WX + lx;
-            const R cx = -bdz(sB[1], e);
-            const R cy = bdz(sB[0], e) - bdx(sB[2], e);
-            const R cz = bdx(sB[1], e);
-            sE[0][e] -= h * cx;
-            sE[1][e] -= h * cy;
-            sE[2][e] -= h * cz;
-        }
+    constexpr int C1 = EHX - 1, N1 = (EHZ - 1) * C1;
+    for (int it = threadIdx.x; it < N1; it += blockDim.x) {
+        const int e = (1 + it / C1) * WX + 1 + it % C1;
+        const R cx = -bdz(sB[1], e);
+        const R cy = bdz(sB[0], e) - bdx(sB[2], e);
+        const R cz = bdx(sB[1], e);
+        sE[0][e] -= h * cx;
+        sE[1][e] -= h * cy;
+        sE[2][e] -= h * cz;
     }
     __syncthreads();
     // lB' on local [1, BH) (cells -1 .. T - 1, or T with CK): forward differences of lE'
-    for (int lz = 1 + wave; lz < BHZ; lz += nwave) {
-#pragma unroll
-        for (int hh = 0; hh < 2; hh++) {
-            const int lx = hh ? TX + 1 + lane : 1 + lane;
-            if (lx >= BHX) break;
-            const int e = lz * WX + lx, exp = e + 1, ezp = e + WX;
-            const R fx = -(sE[1][ezp] - sE[1][e]) * idz;
-            const R fy = (sE[0][ezp] - sE[0][e]) * idz - (sE[2][exp] - sE[2][e]) * idx;
-            const R fz = (sE[1][exp] - sE[1][e]) * idx;
-            sB[0][e] += dt * fx;
-            sB[1][e] += dt * fy;
-            sB[2][e] += dt * fz;
-        }
+    constexpr int C2 = BHX - 1, N2 = (BHZ - 1) * C2;
+    for (int it = threadIdx.x; it < N2; it += blockDim.x) {
+        const int e = (1 + it / C2) * WX + 1 + it % C2, exp = e + 1, ezp = e + WX;
+        const R fx = -(sE[1][ezp] - sE[1][e]) * idz;
+        const R fy = (sE[0][ezp] - sE[0][e]) * idz - (sE[2][exp] - sE[2][e]) * idx;
+        const R fz = (sE[1][exp] - sE[1][e]) * idx;
+        sB[0][e] += dt * fx;
+        sB[1][e] += dt * fy;
+        sB[2][e] += dt * fz;
     }
     __syncthreads();
     const int gx = x0 + lane;

@@ -104,6 +104,16 @@ template <class R> struct Shape<3, R> {
 template <class T> using gp = __attribute__((address_space(1))) T *;
 template <class T> __device__ __forceinline__ gp<T> G(void *p) { return (gp<T>)p; }
 template <class T> __device__ __forceinline__ gp<const T> G(const void *p) { return (gp<const T>)p; }
+// base plus a 32-bit byte offset (zero-extended): with a uniform base the
+// compiler addresses it as scalar base + vector offset
+template <class T> __device__ __forceinline__ gp<T> lane_ptr(gp<T> base, unsigned byte_off)
+{
+    return (gp<T>)((__attribute__((address_space(1))) char *)base + byte_off);
+}
+template <class T> __device__ __forceinline__ gp<const T> lane_ptr(gp<const T> base, unsigned byte_off)
+{
+    return (gp<const T>)((const __attribute__((address_space(1))) char *)base + byte_off);
+}
 
 __device__ __forceinline__ void gatomic_add(gp<long long> p, long long v)
 {

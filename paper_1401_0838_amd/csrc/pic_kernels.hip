@@ -38,7 +38,9 @@ __device__ __forceinline__ R interp(const Win &W, int comp, const int *lc, const
 {
     constexpr int H = (L - 1) / 2;
     constexpr int NX = L + 1 - SX, NZ = L + 1 - SZ, NY = DIM == 3 ? L + 1 - SY : 1;
-    R s = R(0);
+    // sums start from their first term (not from zero: an addition of zero is
+    // an instruction the compiler may not drop)
+    R s;
 #pragma unroll
     for (int kz = 0; kz < NZ; kz++) {
         R wz;
@@ -49,14 +51,16 @@ __device__ __forceinline__ R interp(const Win &W, int comp, const int *lc, const
             if constexpr (DIM == 3) {
                 if constexpr (SY) wy = wh[1][ky]; else wy = wi[1][ky];
             }
-            R row = R(0);
+            R row;
 #pragma unroll
             for (int kx = 0; kx < NX; kx++) {
                 R wx;
                 if constexpr (SX) wx = wh[0][kx]; else wx = wi[0][kx];
-                row += wx * W.f(comp, lc[0] - H + kx, DIM == 3 ? lc[1] - H + ky : 0, lc[2] - H + kz);
+                const R t = wx * W.f(comp, lc[0] - H + kx, DIM == 3 ? lc[1] - H + ky : 0, lc[2] - H + kz);
+                row = kx == 0 ? t : row + t;
             }
-            s += wy * wz * row;
+            const R t = wy * wz * row;
+            s = (kz == 0 && ky == 0) ? t : s + t;
         }
     }
     return s;
@@ -68,15 +72,19 @@ template <int DIM, int L, class R, class Win>
 __device__ __forceinline__ R interp_l(const Win &W, int comp, const int *b, const R *wx, const R *wy, const R *wz)
 {
     constexpr int NY = DIM == 3 ? L + 1 : 1;
-    R s = R(0);
+    R s;
 #pragma unroll
     for (int kz = 0; kz <= L; kz++) {
 #pragma unroll
         for (int ky = 0; ky < NY; ky++) {
-            R row = R(0);
+            R row;
 #pragma unroll
-            for (int kx = 0; kx <= L; kx++) row += wx[kx] * W.f(comp, b[0] + kx, DIM == 3 ? b[1] + ky : 0, b[2] + kz);
-            s += (DIM == 3 ? wy[ky] : R(1)) * wz[kz] * row;
+            for (int kx = 0; kx <= L; kx++) {
+                const R t = wx[kx] * W.f(comp, b[0] + kx, DIM == 3 ? b[1] + ky : 0, b[2] + kz);
+                row = kx == 0 ? t : row + t;
+            }
+            const R t = (DIM == 3 ? wy[ky] : R(1)) * wz[kz] * row;
+            s = (kz == 0 && ky == 0) ? t : s + t;
         }
     }
     return s;
@@ -207,11 +215,11 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
         for (int k = 0; k < L + 2; k++) {
             if (k == L + 1 && !lastz) break;
             R tz = S0[2][k] + R(0.5) * DS[2][k];
-            R acc = R(0);
+            R acc;
 #pragma unroll
             for (int i = 0; i < L + 1; i++) {
                 if (i == L && !lastx) break;
-                acc += DS[0][i] * tz;
+                acc = i == 0 ? DS[0][i] * tz : acc + DS[0][i] * tz;
                 // exactly zero (not a rounding residue) for a particle that kept its
                 // x cell, so the result does not depend on which lanes share a wave
                 const R v = (i == L && dc[0] == 0) ? R(0) : cdep[0] * acc;
@@ -223,11 +231,11 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
         for (int i = 0; i < L + 2; i++) {
             if (i == L + 1 && !lastx) break;
             R tx = S0[0][i] + R(0.5) * DS[0][i];
-            R acc = R(0);
+            R acc;
 #pragma unroll
             for (int k = 0; k < L + 1; k++) {
                 if (k == L && !lastz) break;
-                acc += DS[2][k] * tx;
+                acc = k == 0 ? DS[2][k] * tx : acc + DS[2][k] * tx;
                 const R v = (k == L && dc[2] == 0) ? R(0) : cdep[2] * acc;
                 W.add(2, base[0] + i, 0, base[2] + k, jcvt(v, tag));
             }
@@ -260,11 +268,11 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
                 if (ky == L + 1 && !last[1]) break;
                 R tr = S0[1][ky] * S0[2][kz] + R(0.5) * DS[1][ky] * S0[2][kz] + R(0.5) * S0[1][ky] * DS[2][kz]
                      + R(1.0 / 3.0) * DS[1][ky] * DS[2][kz];
-                R acc = R(0);
+                R acc;
 #pragma unroll
                 for (int kx = 0; kx < L + 1; kx++) {
                     if (kx == L && !last[0]) break;
-                    acc += DS[0][kx] * tr;
+                    acc = kx == 0 ? DS[0][kx] * tr : acc + DS[0][kx] * tr;
                     const R v = (kx == L && dc[0] == 0) ? R(0) : cdep[0] * acc;
                     W.add(0, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(v, tag));
                 }
@@ -279,11 +287,11 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
                 if (kx == L + 1 && !last[0]) break;
                 R tr = S0[2][kz] * S0[0][kx] + R(0.5) * DS[2][kz] * S0[0][kx] + R(0.5) * S0[2][kz] * DS[0][kx]
                      + R(1.0 / 3.0) * DS[2][kz] * DS[0][kx];
-                R acc = R(0);
+                R acc;
 #pragma unroll
                 for (int ky = 0; ky < L + 1; ky++) {
                     if (ky == L && !last[1]) break;
-                    acc += DS[1][ky] * tr;
+                    acc = ky == 0 ? DS[1][ky] * tr : acc + DS[1][ky] * tr;
                     const R v = (ky == L && dc[1] == 0) ? R(0) : cdep[1] * acc;
                     W.add(1, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(v, tag));
                 }
@@ -298,11 +306,11 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
                 if (kx == L + 1 && !last[0]) break;
                 R tr = S0[0][kx] * S0[1][ky] + R(0.5) * DS[0][kx] * S0[1][ky] + R(0.5) * S0[0][kx] * DS[1][ky]
                      + R(1.0 / 3.0) * DS[0][kx] * DS[1][ky];
-                R acc = R(0);
+                R acc;
 #pragma unroll
                 for (int kz = 0; kz < L + 1; kz++) {
                     if (kz == L && !last[2]) break;
-                    acc += DS[2][kz] * tr;
+                    acc = kz == 0 ? DS[2][kz] * tr : acc + DS[2][kz] * tr;
                     const R v = (kz == L && dc[2] == 0) ? R(0) : cdep[2] * acc;
                     W.add(2, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(v, tag));
                 }
@@ -332,7 +340,10 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
         const int inst = work ? work[item].x : 0;
         const InstDesc &D = Dt[inst];
         const int tile = work ? work[item].y : xcd_tile(item, D.ntiles);
-        const int p0 = D.tstart[tile], p1 = D.tstart[tile + 1];
+        // the tile's range is uniform: kept in scalar registers, so are the
+        // per-pass array bases derived from it
+        const int p0 = __builtin_amdgcn_readfirstlane(D.tstart[tile]);
+        const int p1 = __builtin_amdgcn_readfirstlane(D.tstart[tile + 1]);
         if (p1 <= p0) continue;
         int lo[3], ext[3], o[3], wn[3];
 #pragma unroll
@@ -401,15 +412,16 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
         unsigned nidx = 0;
         R noff[3] = {R(0), R(0), R(0)}, nu[3] = {R(0), R(0), R(0)};
         if (PF && p0 + tid < p1) {
-            const int q = p0 + tid;
-            nidx = pidx[q];
+            nidx = pidx[p0 + tid];
 #pragma unroll
             for (int a = 0; a < 3; a++) {
-                if (!(DIM == 2 && a == 1)) noff[a] = poff[a][q];
-                nu[a] = pu[a][q];
+                if (!(DIM == 2 && a == 1)) noff[a] = poff[a][p0 + tid];
+                nu[a] = pu[a][p0 + tid];
             }
         }
-        for (int p = p0 + tid; p < p1; p += bs) {
+        for (int pb = p0; pb < p1; pb += bs) {
+            const int p = pb + tid;
+            if (p >= p1) continue;   // last pass only; the loop exit stays uniform
             if (!PF) {
                 nidx = pidx[p];
 #pragma unroll
@@ -465,7 +477,8 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
                 bmin[a] = min(bmin[a], l1);
                 bmax[a] = max(bmax[a], l1);
             }
-            pu[0][p] = u[0]; pu[1][p] = u[1]; pu[2][p] = u[2];
+#pragma unroll
+            for (int a = 0; a < 3; a++) pu[a][p] = u[a];
             pidx[p] = pack_cell<DIM>(nc[0], nc[1], nc[2]);
         }
         if (err) atomicExch(&D.flags[FLAG_PERR], 1);
@@ -903,9 +916,9 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
             for (int k = 0; k < XQ + 2 * HX; k++) v[k] = w[k];
 #pragma unroll
             for (int q = 0; q < XQ; q++) {
-                R acc = R(0);
+                R acc = rx[0] * v[q];
 #pragma unroll
-                for (int k = 0; k < NTX; k++) acc += rx[k] * v[q + k];
+                for (int k = 1; k < NTX; k++) acc += rx[k] * v[q + k];
                 o[q] = acc;
             }
         } else {
@@ -930,9 +943,9 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
 #pragma unroll
         for (int j = 0; j < RB; j++) {
             const int gz = z0 + zr + j;
-            R acc = R(0);
+            R acc = rz[0] * v[j];
 #pragma unroll
-            for (int k = 0; k < NTZ; k++) acc += rz[k] * v[j + k];
+            for (int k = 1; k < NTZ; k++) acc += rz[k] * v[j + k];
             if (gz < nz) dst[gz * nx + gx] = acc;
         }
     } else {

@@ -171,7 +171,8 @@ def test_charge_density_and_diagnostics_match_oracle(dims, order, sigma):
 # ----------------------------------------------------------- edge cases
 
 def test_ragged_grid_and_tiny_grid():
-    for n in [(50, 37), (8, 8), (5, 70)]:
+    # (100, 70) and (130, 21): several 64-column field tiles with a ragged last one
+    for n in [(50, 37), (8, 8), (5, 70), (100, 70), (130, 21)]:
         wl = pi.workload("beam2d_64_fp64", n=n, correction=True, filter=pi.workloads.BINOMIAL4)
         sim, ref = _pair(wl, 25, "fp64", sigma=1e-2)
         errs = _field_errors(sim, ref)
