@@ -20,6 +20,13 @@ __device__ __forceinline__ int wrapi(int i, int n)
     // i in (-n, 2n)
     return i < 0 ? i + n : (i >= n ? i - n : i);
 }
+// the same for i in (-n, 2n) through two unsigned minima: for i < 0, i + n is
+// the smaller as unsigned; for i >= n, i - n is (four instructions, no compares)
+__device__ __forceinline__ int wrapu(int i, int n)
+{
+    const unsigned a = min((unsigned)i, (unsigned)(i + n));
+    return (int)min(a, a - (unsigned)n);
+}
 
 __device__ __forceinline__ void jadd(long long *p, long long v)
 {
@@ -199,6 +206,10 @@ template <int DIM> __host__ __device__ __forceinline__ void unpack_cell(unsigned
 // ------------------------------------------------- Boris push and move
 // Shared by the forward kernel and the adjoint's recomputation so both take
 // bit-identical cell steps.
+// x clamped into [-1, 2): the largest value below 2 is the upper bound
+__device__ __forceinline__ float clamp_step(float x) { return __builtin_amdgcn_fmed3f(x, -1.0f, 0x1.fffffep0f); }
+__device__ __forceinline__ double clamp_step(double x) { return fmin(fmax(x, -1.0), 0x1.fffffffffffffp0); }
+
 template <class R> struct BorisTrace {
     R um[3], t[3], sv[3], up[3];
     R igm, f;
@@ -231,10 +242,16 @@ __device__ __forceinline__ R move_cells(const R *off, const R *un, const R *dtd,
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         if (DIM == 2 && a == 1) { dc[a] = 0; offn[a] = R(0); continue; }
-        R x1 = off[a] + dtd[a] * un[a] * ig;
-        int c = x1 >= R(1) ? 1 : (x1 < R(0) ? -1 : 0);
-        if (x1 >= R(2) || x1 < R(-1)) { err = 1; x1 = x1 < R(0) ? R(-0.5) : R(1.5); c = x1 < R(0) ? -1 : 1; }
-        R on = x1 - R(c);
+        const R x = off[a] + dtd[a] * un[a] * ig;
+        // More than one cell per step (c dt above the cell size) is an error:
+        // flagged, and the position clamped into [-1, 2) to keep the state in
+        // range (a NaN position is flagged the same way).
+        const R x1 = clamp_step(x);
+        err |= x1 != x;
+        const R fl = floor(x1);
+        int c = (int)fl;
+        R on = x1 - fl;
+        // x1 in [-1, 0): x1 + 1 may round up to 1
         if (on >= R(1)) { on -= R(1); c += 1; }
         dc[a] = c;
         offn[a] = on;

@@ -392,6 +392,10 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
         gp<R> pu[3] = {G<R>(D.pu[0]), G<R>(D.pu[1]), G<R>(D.pu[2])};
         gp<unsigned> pidx = G<unsigned>(D.pidx);
         int bmin[3] = {INT_MAX, INT_MAX, INT_MAX}, bmax[3] = {INT_MIN, INT_MIN, INT_MIN};
+        // grid extents in registers: the loop's stores could alias the
+        // descriptor, so reads of it inside the loop would be repeated (and
+        // wait on the scalar cache, and with it on LDS) every pass
+        const int nn[3] = {D.n[0], D.n[1], D.n[2]};
         int err = 0;
 
         LdsWin<R, JT> lw{sF, sJ, pitch, pitch * wn[1], wc};
@@ -448,7 +452,7 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
                 u[a] = nu[a];
                 if (DIM == 2 && a == 1) { lc[a] = 0; off[a] = R(0); continue; }
                 int rel = c[a] - lo[a];
-                rel += rel < 0 ? D.n[a] : 0;
+                rel += rel < 0 ? nn[a] : 0;
                 lc[a] = rel + JL;
                 off[a] = noff[a];
             }
@@ -471,7 +475,7 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
             for (int a = 0; a < 3; a++) {
                 nc[a] = c[a];
                 if (DIM == 2 && a == 1) continue;
-                nc[a] = wrapi(c[a] + dc[a], D.n[a]);
+                nc[a] = wrapu(c[a] + dc[a], nn[a]);
                 poff[a][p] = offn[a];
                 const int l1 = lc[a] + dc[a];
                 bmin[a] = min(bmin[a], l1);
