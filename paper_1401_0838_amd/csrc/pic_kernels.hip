@@ -210,6 +210,11 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
         // only).  When no lane of the wave changed cell along the axis, the wave
         // skips those updates (whole LDS atomics, not just lanes).
         const bool lastx = __ballot(dc[0] != 0) != 0, lastz = __ballot(dc[2] != 0) != 0;
+        // the running sums use the shape changes with the deposit constant
+        // folded in (one multiply per node instead of one per update)
+        R cx[L + 1], cz[L + 1];
+#pragma unroll
+        for (int i = 0; i < L + 1; i++) { cx[i] = cdep[0] * DS[0][i]; cz[i] = cdep[2] * DS[2][i]; }
         // J_x: running sum along x
 #pragma unroll
         for (int k = 0; k < L + 2; k++) {
@@ -219,10 +224,10 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 #pragma unroll
             for (int i = 0; i < L + 1; i++) {
                 if (i == L && !lastx) break;
-                acc = i == 0 ? DS[0][i] * tz : acc + DS[0][i] * tz;
+                acc = i == 0 ? cx[i] * tz : acc + cx[i] * tz;
                 // exactly zero (not a rounding residue) for a particle that kept its
                 // x cell, so the result does not depend on which lanes share a wave
-                const R v = (i == L && dc[0] == 0) ? R(0) : cdep[0] * acc;
+                const R v = (i == L && dc[0] == 0) ? R(0) : acc;
                 W.add(0, base[0] + i, 0, base[2] + k, jcvt(v, tag));
             }
         }
@@ -235,8 +240,8 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 #pragma unroll
             for (int k = 0; k < L + 1; k++) {
                 if (k == L && !lastz) break;
-                acc = k == 0 ? DS[2][k] * tx : acc + DS[2][k] * tx;
-                const R v = (k == L && dc[2] == 0) ? R(0) : cdep[2] * acc;
+                acc = k == 0 ? cz[k] * tx : acc + cz[k] * tx;
+                const R v = (k == L && dc[2] == 0) ? R(0) : acc;
                 W.add(2, base[0] + i, 0, base[2] + k, jcvt(v, tag));
             }
         }
@@ -258,6 +263,12 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
     } else {
         // same skips as in 2D, per axis (see above)
         const bool last[3] = {__ballot(dc[0] != 0) != 0, __ballot(dc[1] != 0) != 0, __ballot(dc[2] != 0) != 0};
+        // shape changes with the deposit constant folded in, for the running sums
+        R cd[3][L + 1];
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+#pragma unroll
+            for (int i = 0; i < L + 1; i++) cd[a][i] = cdep[a] * DS[a][i];
         // J_x (outer loops stay rolled for cubic shapes to bound register use)
         constexpr int UNROLL_OUTER = L == 1 ? L + 2 : 1;
 #pragma unroll UNROLL_OUTER
@@ -272,8 +283,8 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 #pragma unroll
                 for (int kx = 0; kx < L + 1; kx++) {
                     if (kx == L && !last[0]) break;
-                    acc = kx == 0 ? DS[0][kx] * tr : acc + DS[0][kx] * tr;
-                    const R v = (kx == L && dc[0] == 0) ? R(0) : cdep[0] * acc;
+                    acc = kx == 0 ? cd[0][kx] * tr : acc + cd[0][kx] * tr;
+                    const R v = (kx == L && dc[0] == 0) ? R(0) : acc;
                     W.add(0, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(v, tag));
                 }
             }
@@ -291,8 +302,8 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 #pragma unroll
                 for (int ky = 0; ky < L + 1; ky++) {
                     if (ky == L && !last[1]) break;
-                    acc = ky == 0 ? DS[1][ky] * tr : acc + DS[1][ky] * tr;
-                    const R v = (ky == L && dc[1] == 0) ? R(0) : cdep[1] * acc;
+                    acc = ky == 0 ? cd[1][ky] * tr : acc + cd[1][ky] * tr;
+                    const R v = (ky == L && dc[1] == 0) ? R(0) : acc;
                     W.add(1, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(v, tag));
                 }
             }
@@ -310,8 +321,8 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 #pragma unroll
                 for (int kz = 0; kz < L + 1; kz++) {
                     if (kz == L && !last[2]) break;
-                    acc = kz == 0 ? DS[2][kz] * tr : acc + DS[2][kz] * tr;
-                    const R v = (kz == L && dc[2] == 0) ? R(0) : cdep[2] * acc;
+                    acc = kz == 0 ? cd[2][kz] * tr : acc + cd[2][kz] * tr;
+                    const R v = (kz == L && dc[2] == 0) ? R(0) : acc;
                     W.add(2, base[0] + kx, base[1] + ky, base[2] + kz, jcvt(v, tag));
                 }
             }
