@@ -783,7 +783,7 @@ __device__ __forceinline__ void adj_seen_body(const InstDesc *__restrict__ Dt, c
     }
     const gp<const R> src = G<R>((const void *)(comp < 3 ? D.lEt[comp] : D.lBt[comp - 3]));
     // waves own rows, lanes own columns: a = lane, b = 64 + lane (right halo, lane < 2 hx)
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id(), nwave = blockDim.x >> 6;
     const bool hasb = lane < 2 * hx;
     const int gxa = wrap_near(x0 - hx + lane, nx);
     const int gxb = hasb ? wrap_near(x0 - hx + ADJ_TX + lane, nx) : gxa;
@@ -866,7 +866,7 @@ __device__ __forceinline__ void adj_seen_body(const InstDesc *__restrict__ Dt, c
         }
     }
     if constexpr (GRAD) {
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const int wave = wave_id(), lane = threadIdx.x & 63;
 #pragma unroll
         for (int j = 0; j < NJ; j++) {
             if (DEG < 0 && j > deg) break;
@@ -912,7 +912,7 @@ __global__ void __launch_bounds__(256) k_adj_yee_2d(const InstDesc *__restrict__
     const int nx = D.n[0], nz = D.n[2];
     const int ntx = (nx + TX - 1) / TX;
     const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id(), nwave = blockDim.x >> 6;
     // inputs: lambda_E, lambda_B as left in T1 by the reverse seen kernels
     const gp<const R> in[6] = {G<R>((const void *)D.T1[0]), G<R>((const void *)D.T1[1]), G<R>((const void *)D.T1[2]),
                                G<R>((const void *)D.T1[3]), G<R>((const void *)D.T1[4]), G<R>((const void *)D.T1[5])};

@@ -104,6 +104,12 @@ template <class R> struct Shape<3, R> {
     }
 };
 
+// Index of the calling wave in its block.  threadIdx.x >> 6 is the same on
+// every lane of a wave, but the compiler does not know it; read from the first
+// lane it is a scalar, and the row and address arithmetic that depends only on
+// it runs on the scalar unit instead of the vector ALUs.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // -------------------------------------------------------- global pointers
 // Pointers read from the descriptor are generic; casting them to the global
 // address space makes the compiler emit global (not flat) loads, stores and

@@ -671,7 +671,7 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
     const int nx = D.n[0], nz = D.n[2];
     const int ntx = (nx + TX - 1) / TX;
     const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id(), nwave = blockDim.x >> 6;
     const gp<const R> E[3] = {G<R>((const void *)D.E[par][0]), G<R>((const void *)D.E[par][1]),
                               G<R>((const void *)D.E[par][2])};
     const gp<const R> B[3] = {G<R>((const void *)D.B[par][0]), G<R>((const void *)D.B[par][1]),
@@ -873,7 +873,7 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     const int x0 = (t % ntx) * SEEN_TX, z0 = (t / ntx) * SEEN_TZ;
     const int hz = HZ >= 0 ? HZ : D.hz, hx = HX >= 0 ? HX : D.hx;
     const int wx = SEEN_TX + 2 * hx, wz = SEEN_TZ + 2 * hz;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id(), nwave = blockDim.x >> 6;
     R *win = reinterpret_cast<R *>(smem);   // wz x wx: the staged window
     R *mid = win + wx * wz;                 // wz x 64: after the x stencil
     R *tz = mid + SEEN_TX * wz;
@@ -996,7 +996,7 @@ __global__ void __launch_bounds__(256) k_psi_inv_z(const InstDesc *__restrict__ 
     const int inst = inst0 + blockIdx.y, comp = blockIdx.z;
     const InstDesc &D = Dt[inst];
     const int ncol = D.n[0] * D.n[1], nz = D.n[2];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const int col = blockIdx.x * PIC_RATIO_TC + wave;
     if (col >= ncol) return;
     const int Ls = (nz + 63) / 64;
