@@ -212,6 +212,11 @@ int pic_set_schedule(pic_state *st, int sched, int use_graph);
  *                    per SIMD (register cap 128)
  *   "particle_prefetch" 1: 2D linear float particle kernel loads the next
  *                    particle's state while pushing the current one
+ *   "particle_defer" 2D: 0 steps a tile whose particles outgrew its LDS window
+ *                    inside the particle kernel; 1 leaves such tiles to a second
+ *                    launch (fewer registers in the first, more waves per SIMD);
+ *                    -1 (default) picks 1 when there are more than four tiles per
+ *                    compute unit.  3D always uses the second launch.
  * Returns PIC_EINVAL for an unknown name or value.  Drops captured graphs. */
 int pic_set_option(pic_state *st, const char *name, int value);
 int pic_get_option(pic_state *st, const char *name, int *value);

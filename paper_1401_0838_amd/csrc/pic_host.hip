@@ -223,6 +223,9 @@ struct pic_state {
     long long step = 0;
     int *trace_pos = nullptr;
     int *any_resort = nullptr;       // device word shared by all instances: a re-sort is pending
+    int *defer = nullptr;            // deferred-tile list of the particle kernel (InstDesc::defer)
+    int cus = 256;                   // compute units of the device
+    int defer_mode = -1;             // particle launch form: -1 by tile count, 0 inline, 1 deferring (2D)
     double *trace = nullptr;
     int trace_cap = 0;
     // reverse mode
@@ -251,6 +254,8 @@ LaunchCtx ctx(const pic_state *s)
     c.waves4 = s->waves4;
     c.prefetch = s->prefetch;
     c.any_resort = s->any_resort;
+    c.cus = s->cus;
+    c.defer_mode = s->defer_mode;
     c.par = s->parity;
     c.single = s->n_inst == 1;
     c.gather = s->gather;
@@ -308,6 +313,8 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
     if (s) s->trace_pos = tpos;
     int *anyr = L.take<int>(64);
     if (s) s->any_resort = anyr;
+    int *defer = L.take<int>(2 + 2 * std::max<size_t>(npw, 1));
+    if (s) s->defer = defer;
     int cap = 0;
     for (int i = 0; i < n_inst; i++) cap = std::max(cap, cfgs[i].trace_capacity);
     // one spare row: each step clears the row the next step writes, so a ring
@@ -960,6 +967,12 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
     // largest LDS window over the instances
     int maxsm = 0;
     if (hipDeviceGetAttribute(&maxsm, hipDeviceAttributeMaxSharedMemoryPerBlock, 0) != hipSuccess) maxsm = 65536;
+    {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            s->cus = v;
+    }
     for (int i = 0; i < n_inst; i++) {
         fill_desc(s->desc[i], cfgs[i], parts[i]);
         int tile[3], slack;
@@ -988,7 +1001,11 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
         // allow the dynamic LDS size on every particle kernel instantiation
         (void)maxsm;
     }
-    for (int i = 0; i < n_inst; i++) { s->desc[i].trace = s->trace; s->desc[i].any_resort = s->any_resort; }
+    for (int i = 0; i < n_inst; i++) {
+        s->desc[i].trace = s->trace;
+        s->desc[i].any_resort = s->any_resort;
+        s->desc[i].defer = s->defer;
+    }
     if (cfgs[0].adjoint_steps > 0) {
         s->adj_steps = cfgs[0].adjoint_steps;
         s->adj_k = cfgs[0].adjoint_ckpt;
@@ -1090,6 +1107,9 @@ extern "C" int pic_set_option(pic_state *s, const char *name, int value)
     } else if (n == "particle_prefetch") {
         if (value != 0 && value != 1) return fail(PIC_EINVAL, "particle_prefetch must be 0 or 1");
         s->prefetch = value;
+    } else if (n == "particle_defer") {
+        if (value < -1 || value > 1) return fail(PIC_EINVAL, "particle_defer must be -1, 0 or 1");
+        s->defer_mode = value;
     } else {
         return fail(PIC_EINVAL, "unknown option " + n);
     }
@@ -1107,6 +1127,7 @@ extern "C" int pic_get_option(pic_state *s, const char *name, int *value)
     else if (n == "particle_block") *value = s->block;
     else if (n == "particle_waves4") *value = s->waves4;
     else if (n == "particle_prefetch") *value = s->prefetch;
+    else if (n == "particle_defer") *value = s->defer_mode;
     else return fail(PIC_EINVAL, "unknown option " + n);
     return PIC_OK;
 }

@@ -86,6 +86,10 @@ struct InstDesc {
     int *tcount;
     int *flags;            // FLAG_*
     int *any_resort;       // one word shared by all instances: some instance set FLAG_RESORT
+    // tiles whose particle box outgrew the LDS window, left by the particle kernel
+    // for its global-memory pass (shared by all instances): [0] count, [1] blocks
+    // of the pass that are done, then (instance, tile) pairs from [2]
+    int *defer;
     double *diag;          // DG_*
     double *trace;         // trace_cap rows of 6 doubles
     // reverse mode (null unless gradient runs were planned)
@@ -146,6 +150,8 @@ struct LaunchCtx {
     int ratio = 0;                    // exact Psi_E / Psi_B on the transverse E (every instance)
     int inst0 = 0, ninst = 1;         // instances the launches cover (ratio solve grid)
     int rtiles = 0;                   // column tiles of the widest instance (ratio solve grid)
+    int cus = 256;                    // compute units of the device
+    int defer_mode = -1;              // particle launch form: -1 by tile count, 0 inline, 1 deferring (2D)
 };
 
 int launch_yee(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *ywork, int nywork);

@@ -336,7 +336,15 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 // PF: load the next particle's state while the current one is processed.
 // TP: also write the state each particle starts from, and each tile's box,
 // to the tape slot named by the descriptor (reverse sweep recompute).
-template <int DIM, int L, class R, int P, bool PF, bool TP = false, int IP = GATHER_GALERKIN>
+// MODE: how a tile whose particle box has outgrown the LDS window is stepped
+// (fields read and current added straight in global memory).
+//   PM_INLINE  in this kernel, on a branch of the particle loop;
+//   PM_DEFER   not here: the tile goes on a list for a second launch, so the
+//              global-memory code and its registers stay out of this kernel
+//              (more waves per SIMD; pays off when tiles outnumber the slots);
+//   PM_GLOBAL  that second launch: the listed tiles only.
+enum { PM_INLINE = 0, PM_DEFER = 1, PM_GLOBAL = 2 };
+template <int DIM, int L, class R, int P, bool PF, bool TP = false, int IP = GATHER_GALERKIN, int MODE = PM_INLINE>
 __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                int nwork, int wmx, int wmy, int wmz, int par)
 {
@@ -345,12 +353,23 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sbox[6];
     const int tid = threadIdx.x, bs = blockDim.x;
+    constexpr bool SLOW = MODE == PM_GLOBAL;
+    // the deferred list is shared by all instances; its count was final when
+    // the deferring launch ended
+    const int *dfr = Dt[0].defer;
+    if constexpr (SLOW) nwork = __hip_atomic_load(const_cast<int *>(dfr), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 
     for (int item = blockIdx.x; item < nwork; item += gridDim.x) {
         // work == nullptr: one instance, slot -> tile in the host's XCD order
-        const int inst = work ? work[item].x : 0;
+        int inst, tile;
+        if constexpr (SLOW) {
+            inst = dfr[2 + 2 * item];
+            tile = dfr[3 + 2 * item];
+        } else {
+            inst = work ? work[item].x : 0;
+        }
         const InstDesc &D = Dt[inst];
-        const int tile = work ? work[item].y : xcd_tile(item, D.ntiles);
+        if constexpr (!SLOW) tile = work ? work[item].y : xcd_tile(item, D.ntiles);
         // the tile's range is uniform: kept in scalar registers, so are the
         // per-pass array bases derived from it
         const int p0 = __builtin_amdgcn_readfirstlane(D.tstart[tile]);
@@ -368,7 +387,25 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
         if constexpr (TP) {
             if (tid < 6) D.rtbox[tile * 6 + tid] = tid < 3 ? lo[tid] : ext[tid - 3];
         }
-        const bool fits = wn[0] <= wmx && wn[1] <= wmy && wn[2] <= wmz;
+        // PM_DEFER leaves a tile whose window does not fit to the PM_GLOBAL
+        // launch, which takes only such tiles
+        const bool fits = !SLOW && wn[0] <= wmx && wn[1] <= wmy && wn[2] <= wmz;
+        if (!fits && MODE == PM_INLINE && tid == 0) {
+            atomicAdd(&D.flags[FLAG_SLOW], 1);
+            atomicExch(&D.flags[FLAG_RESORT], 1);
+            atomicExch(D.any_resort, 1);
+        }
+        if (!fits && MODE == PM_DEFER) {
+            if (tid == 0) {
+                atomicAdd(&D.flags[FLAG_SLOW], 1);
+                atomicExch(&D.flags[FLAG_RESORT], 1);
+                atomicExch(D.any_resort, 1);
+                const int k = atomicAdd(D.defer, 1);
+                D.defer[2 + 2 * k] = inst;
+                D.defer[3 + 2 * k] = tile;
+            }
+            continue;
+        }
         // plane stride and row pitch of the LDS windows
         const int wc = P > 0 ? P * P : wn[0] * wn[1] * wn[2];
         const int pitch = P > 0 ? P : wn[0];
@@ -389,10 +426,6 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
 #pragma unroll
                 for (int k = 0; k < 3; k++) sJ[k * wc + l] = JT(0);
             }
-        } else if (tid == 0) {
-            atomicAdd(&D.flags[FLAG_SLOW], 1);
-            atomicExch(&D.flags[FLAG_RESORT], 1);
-            atomicExch(D.any_resort, 1);
         }
         __syncthreads();
 
@@ -412,7 +445,7 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
         LdsWin<R, JT> lw{sF, sJ, pitch, pitch * wn[1], wc};
         LdsWinP<R, JT, (P > 0 ? P : 1)> lwp{sF, sJ};
         GlbWin<R, JT> gw;
-        if (!fits) {
+        if (SLOW || (MODE == PM_INLINE && !fits)) {
             for (int k = 0; k < 3; k++) {
                 gw.F[k] = G<R>((const void *)D.Et[k]);
                 gw.F[3 + k] = G<R>((const void *)D.Bt[k]);
@@ -427,22 +460,26 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
         unsigned nidx = 0;
         R noff[3] = {R(0), R(0), R(0)}, nu[3] = {R(0), R(0), R(0)};
         if (PF && p0 + tid < p1) {
-            nidx = pidx[p0 + tid];
+            const unsigned b4 = (unsigned)(p0 + tid) * 4u, bR = (unsigned)(p0 + tid) * (unsigned)sizeof(R);
+            nidx = *lane_ptr(pidx, b4);
 #pragma unroll
             for (int a = 0; a < 3; a++) {
-                if (!(DIM == 2 && a == 1)) noff[a] = poff[a][p0 + tid];
-                nu[a] = pu[a][p0 + tid];
+                if (!(DIM == 2 && a == 1)) noff[a] = *lane_ptr(poff[a], bR);
+                nu[a] = *lane_ptr(pu[a], bR);
             }
         }
         for (int pb = p0; pb < p1; pb += bs) {
             const int p = pb + tid;
             if (p >= p1) continue;   // last pass only; the loop exit stays uniform
+            // per-lane byte offsets (32-bit, zero-extended) from the uniform array
+            // bases: the loads and stores take the scalar-base + vector-offset form
+            const unsigned b4 = (unsigned)p * 4u, bR = (unsigned)p * (unsigned)sizeof(R);
             if (!PF) {
-                nidx = pidx[p];
+                nidx = *lane_ptr(pidx, b4);
 #pragma unroll
                 for (int a = 0; a < 3; a++) {
-                    if (!(DIM == 2 && a == 1)) noff[a] = poff[a][p];
-                    nu[a] = pu[a][p];
+                    if (!(DIM == 2 && a == 1)) noff[a] = *lane_ptr(poff[a], bR);
+                    nu[a] = *lane_ptr(pu[a], bR);
                 }
             }
             int c[3];
@@ -468,33 +505,39 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
                 off[a] = noff[a];
             }
             if (PF && p + bs < p1) {
-                const int q = p + bs;
-                nidx = pidx[q];
+                const unsigned q4 = (unsigned)(p + bs) * 4u, qR = (unsigned)(p + bs) * (unsigned)sizeof(R);
+                nidx = *lane_ptr(pidx, q4);
 #pragma unroll
                 for (int a = 0; a < 3; a++) {
-                    if (!(DIM == 2 && a == 1)) noff[a] = poff[a][q];
-                    nu[a] = pu[a][q];
+                    if (!(DIM == 2 && a == 1)) noff[a] = *lane_ptr(poff[a], qR);
+                    nu[a] = *lane_ptr(pu[a], qR);
                 }
             }
-            if (fits) {
+            if (!SLOW && (MODE == PM_DEFER || fits)) {
                 if constexpr (P > 0) push_particle<DIM, L, R, JT, IP>(lwp, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
                 else push_particle<DIM, L, R, JT, IP>(lw, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
-            } else
+            } else if constexpr (MODE != PM_DEFER)
                 push_particle<DIM, L, R, JT, IP>(gw, lc, off, u, dc, offn, dtd, qdt2m, cdep, cy2d, err);
+            // the store offsets are taken from here as plain 32-bit values (an
+            // empty asm the compiler cannot look through), so the stores too get
+            // the scalar-base + vector-offset form rather than 64-bit addresses
+            // formed before the branches above
+            unsigned s4 = b4, sR = bR;
+            asm volatile("" : "+v"(s4), "+v"(sR));
             int nc[3];
 #pragma unroll
             for (int a = 0; a < 3; a++) {
                 nc[a] = c[a];
                 if (DIM == 2 && a == 1) continue;
                 nc[a] = wrapu(c[a] + dc[a], nn[a]);
-                poff[a][p] = offn[a];
+                *lane_ptr(poff[a], sR) = offn[a];
                 const int l1 = lc[a] + dc[a];
                 bmin[a] = min(bmin[a], l1);
                 bmax[a] = max(bmax[a], l1);
             }
 #pragma unroll
-            for (int a = 0; a < 3; a++) pu[a][p] = u[a];
-            pidx[p] = pack_cell<DIM>(nc[0], nc[1], nc[2]);
+            for (int a = 0; a < 3; a++) *lane_ptr(pu[a], sR) = u[a];
+            *lane_ptr(pidx, s4) = pack_cell<DIM>(nc[0], nc[1], nc[2]);
         }
         if (err) atomicExch(&D.flags[FLAG_PERR], 1);
         // bounding box of the moved particles (window-local coordinates)
@@ -534,13 +577,33 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
         }
         __syncthreads();
     }
+    if constexpr (SLOW) {
+        // the last block to finish empties the list for the next step's LDS pass
+        // (every block read the count before it counted itself done)
+        if (tid == 0) {
+            __threadfence();
+            int *dw = const_cast<int *>(dfr);
+            if (atomicAdd(dw + 1, 1) == (int)gridDim.x - 1) {
+                atomicExch(dw, 0);
+                atomicExch(dw + 1, 0);
+            }
+        }
+    }
 }
 
-template <int DIM, int L, class R, int P, bool PF = false, bool TP = false, int IP = GATHER_GALERKIN>
+template <int DIM, int L, class R, int P, bool PF = false, bool TP = false, int IP = GATHER_GALERKIN,
+          int MODE = PM_INLINE>
 __global__ void __launch_bounds__(512) k_particles(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                    int nwork, int wmx, int wmy, int wmz, int par)
 {
-    particles_body<DIM, L, R, P, PF, TP, IP>(Dt, work, nwork, wmx, wmy, wmz, par);
+    particles_body<DIM, L, R, P, PF, TP, IP, MODE>(Dt, work, nwork, wmx, wmy, wmz, par);
+}
+
+// the tiles a PM_DEFER launch left, in global memory (launched right after it)
+template <int DIM, int L, class R, bool TP = false, int IP = GATHER_GALERKIN>
+__global__ void __launch_bounds__(256) k_particles_deferred(const InstDesc *__restrict__ Dt, int par)
+{
+    particles_body<DIM, L, R, 0, false, TP, IP, PM_GLOBAL>(Dt, nullptr, 0, 0, 0, 0, par);
 }
 
 // same body compiled for four waves per SIMD (at most 128 VGPRs)
@@ -1519,17 +1582,26 @@ size_t particle_smem_bytes(int dims, int fp32, const int wmax[3])
     return wc * (3 * 8 + 6 * r);
 }
 
-int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid, int block, const int wmax[3])
+// the deferred-tile pass for the gather scheme in use
+template <class R, int D, int L, bool TP> void launch_deferred(const LaunchCtx &c, dim3 g)
 {
-    if (nwork <= 0) return 0;
-    const int wy = c.dims == 3 ? wmax[1] : 1;
-    const int wm[3] = {wmax[0], wy, wmax[2]};
-    const size_t smem = particle_smem_bytes(c.dims, c.fp32, wm);
-    dim3 g(grid > 0 ? grid : nwork), b(block);
-#define PK(D_, L_, P_) k_particles<D_, L_, R, P_><<<g, b, smem, c.stream>>>(c.desc, c.single ? nullptr : pwork, nwork, wm[0], wm[1], wm[2], c.par)
-#define PK24(K_, PF_) K_<2, 1, float, 24, PF_><<<g, b, smem, c.stream>>>(c.desc, c.single ? nullptr : pwork, nwork, wm[0], wm[1], wm[2], c.par)
-#define PKR(L_, P_) k_particles<2, L_, R, P_, false, true><<<g, b, smem, c.stream>>>(c.desc, c.single ? nullptr : pwork, nwork, wm[0], wm[1], wm[2], c.par)
-#define PKS(D_, L_, P_, IP_) k_particles<D_, L_, R, P_, false, false, IP_><<<g, b, smem, c.stream>>>(c.desc, c.single ? nullptr : pwork, nwork, wm[0], wm[1], wm[2], c.par)
+    if (c.gather == GATHER_UNIFORM) k_particles_deferred<D, L, R, TP, GATHER_UNIFORM><<<g, 256, 0, c.stream>>>(c.desc, c.par);
+    else if constexpr (!TP) {
+        if (c.gather == GATHER_NODAL) k_particles_deferred<D, L, R, false, GATHER_NODAL><<<g, 256, 0, c.stream>>>(c.desc, c.par);
+        else k_particles_deferred<D, L, R, false, GATHER_GALERKIN><<<g, 256, 0, c.stream>>>(c.desc, c.par);
+    } else k_particles_deferred<D, L, R, true, GATHER_GALERKIN><<<g, 256, 0, c.stream>>>(c.desc, c.par);
+}
+
+// one launch of the particle kernel in mode M (3D is always launched deferring)
+template <int M>
+void launch_particles_m(const LaunchCtx &c, const int2 *pwork, int nwork, dim3 g, dim3 b, size_t smem, const int *wm)
+{
+    const int2 *w = c.single ? nullptr : pwork;
+#define PK(D_, L_, P_) k_particles<D_, L_, R, P_, false, false, GATHER_GALERKIN, M><<<g, b, smem, c.stream>>>(c.desc, w, nwork, wm[0], wm[1], wm[2], c.par)
+#define PK24(K_, PF_) K_<2, 1, float, 24, PF_><<<g, b, smem, c.stream>>>(c.desc, w, nwork, wm[0], wm[1], wm[2], c.par)
+#define PKR(L_, P_) k_particles<2, L_, R, P_, false, true, GATHER_GALERKIN, M><<<g, b, smem, c.stream>>>(c.desc, w, nwork, wm[0], wm[1], wm[2], c.par)
+#define PKS(D_, L_, P_, IP_) k_particles<D_, L_, R, P_, false, false, IP_, M><<<g, b, smem, c.stream>>>(c.desc, w, nwork, wm[0], wm[1], wm[2], c.par)
+#define PKRU(L_, P_) k_particles<2, L_, R, P_, false, true, GATHER_UNIFORM, M><<<g, b, smem, c.stream>>>(c.desc, w, nwork, wm[0], wm[1], wm[2], c.par)
 #define PK_SCHEME(IP_)                                                              \
     do {                                                                            \
         if (c.dims == 2 && c.order == 1) {                                          \
@@ -1539,10 +1611,11 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
         } else if (c.dims == 2) {                                                   \
             if (wm[0] == 32 && wm[2] == 32) PKS(2, 3, 32, IP_);                     \
             else PKS(2, 3, 0, IP_);                                                 \
-        } else if (c.order == 1) PKS(3, 1, 0, IP_);                                 \
-        else PKS(3, 3, 0, IP_);                                                     \
+        } else if constexpr (M == PM_DEFER) {                                       \
+            if (c.order == 1) PKS(3, 1, 0, IP_);                                    \
+            else PKS(3, 3, 0, IP_);                                                 \
+        }                                                                           \
     } while (0)
-#define PKRU(L_, P_) k_particles<2, L_, R, P_, false, true, GATHER_UNIFORM><<<g, b, smem, c.stream>>>(c.desc, c.single ? nullptr : pwork, nwork, wm[0], wm[1], wm[2], c.par)
     DISPATCH_R(c.fp32, {
         if (c.gather == GATHER_UNIFORM && c.record && c.dims == 2) {
             // recording a tape slot (2D reverse sweep) with the Uniform gather
@@ -1570,17 +1643,20 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
             }
         } else if (c.dims == 2 && c.order == 1) {
             if (wm[0] == 24 && wm[2] == 24) {
-                if (c.fp32 && c.waves4 && c.prefetch) PK24(k_particles_w4, true);
-                else if (c.fp32 && c.waves4) PK24(k_particles_w4, false);
-                else if (c.fp32 && c.prefetch) PK24(k_particles, true);
+                // the tuning variants exist in the inline mode only
+                if (M == PM_INLINE && c.fp32 && c.waves4 && c.prefetch) PK24(k_particles_w4, true);
+                else if (M == PM_INLINE && c.fp32 && c.waves4) PK24(k_particles_w4, false);
+                else if (M == PM_INLINE && c.fp32 && c.prefetch) PK24(k_particles, true);
                 else PK(2, 1, 24);
             } else if (wm[0] == 32 && wm[2] == 32) PK(2, 1, 32);
             else PK(2, 1, 0);
         } else if (c.dims == 2 && c.order == 3) {
             if (wm[0] == 32 && wm[2] == 32) PK(2, 3, 32);
             else PK(2, 3, 0);
-        } else if (c.dims == 3 && c.order == 1) PK(3, 1, 0);
-        else PK(3, 3, 0);
+        } else if constexpr (M == PM_DEFER) {
+            if (c.order == 1) PK(3, 1, 0);
+            else PK(3, 3, 0);
+        }
     });
 #undef PK
 #undef PK24
@@ -1588,6 +1664,40 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
 #undef PKS
 #undef PKRU
 #undef PK_SCHEME
+}
+
+int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid, int block, const int wmax[3])
+{
+    if (nwork <= 0) return 0;
+    const int wy = c.dims == 3 ? wmax[1] : 1;
+    const int wm[3] = {wmax[0], wy, wmax[2]};
+    const size_t smem = particle_smem_bytes(c.dims, c.fp32, wm);
+    const dim3 g(grid > 0 ? grid : nwork), b(block);
+    // Keeping the global-memory path out of the kernel lowers its registers (2D
+    // linear FP32 72 against 126 VGPRs, 3D cubic 167 against 256 with spills)
+    // and lets more waves share a SIMD, at the cost of a second launch per
+    // step.  The extra waves pay only when tiles queue for slots; with at most
+    // four tiles per compute unit the one-launch form is faster.
+    const bool defer = c.dims == 3 || (c.defer_mode < 0 ? nwork > 4 * c.cus : c.defer_mode == 1);
+    if (!defer) {
+        launch_particles_m<PM_INLINE>(c, pwork, nwork, g, b, smem, wm);
+        return hip_ok(hipGetLastError());
+    }
+    launch_particles_m<PM_DEFER>(c, pwork, nwork, g, b, smem, wm);
+    // tiles whose window did not fit were left in the deferred list; when there
+    // are none every block of this pass leaves after one read
+    const dim3 gd(nwork < 128 ? nwork : 128);
+    DISPATCH_R(c.fp32, {
+        const bool rec = c.record && c.dims == 2;
+        if (c.dims == 2 && c.order == 1) {
+            if (rec) launch_deferred<R, 2, 1, true>(c, gd);
+            else launch_deferred<R, 2, 1, false>(c, gd);
+        } else if (c.dims == 2) {
+            if (rec) launch_deferred<R, 2, 3, true>(c, gd);
+            else launch_deferred<R, 2, 3, false>(c, gd);
+        } else if (c.order == 1) launch_deferred<R, 3, 1, false>(c, gd);
+        else launch_deferred<R, 3, 3, false>(c, gd);
+    });
     return hip_ok(hipGetLastError());
 }
 

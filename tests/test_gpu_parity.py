@@ -200,6 +200,40 @@ def test_empty_and_clumped_beams():
     sim.close()
 
 
+@pytest.mark.parametrize("dims,order,prec,interp", [(2, 1, "fp64", "galerkin"), (2, 1, "fp32", "galerkin"),
+                                                     (2, 3, "fp64", "galerkin"), (2, 1, "fp64", "uniform"),
+                                                     (2, 1, "fp64", "momentum"), (3, 1, "fp64", "galerkin"),
+                                                     (3, 3, "fp32", "galerkin")])
+@pytest.mark.parametrize("defer", [0, 1])
+def test_deferred_tiles_match_oracle(dims, order, prec, interp, defer):
+    """A hot beam with re-sorting held off: tile boxes outgrow their LDS windows
+    and are stepped in global memory, inside the particle kernel (defer 0) or by
+    the second launch (defer 1; 3D always), and the step still matches the
+    oracle."""
+    if dims == 3 and defer == 0:
+        pytest.skip("3D always defers")
+    if dims == 2:
+        wl = pi.workload("beam2d_64_fp64", n=(40, 48), ppc=4, order=order, correction=True,
+                         filter=pi.workloads.BINOMIAL4, interp=interp)
+    else:
+        wl = pi.workload("beam3d_128x128x256", n=(16, 12, 24), ppc=2, order=order)
+    nsteps = 24
+    x, u = pi.load_beam(dims, wl["n"], wl["ppc"], 1.5, 0.8, 5)
+    _say("deferred case dims=%d order=%d %s %s defer=%d steps=%d" % (dims, order, prec, interp, defer, nsteps))
+    sim = _sim(wl, (x, u), precision=prec)
+    sim.set_option("resort_every", 1024)
+    sim.set_option("particle_defer", defer)
+    ref = OracleSim(wl, x, u)
+    sim.step(nsteps)
+    ref.step(nsteps)
+    errs = _field_errors(sim, ref)
+    d = sim.diag()
+    _say("deferred %s slow=%d resorts=%d" % (errs, d["slow_tiles"], d["resorts"]))
+    assert d["slow_tiles"] >= 1        # the deferred pass did run
+    assert max(errs.values()) < (1e-10 if prec == "fp64" else 1e-4)
+    sim.close()
+
+
 def test_resort_in_a_batch_keeps_parity():
     """Two instances, one hot (re-sorted every 4 steps) and one cold, stepped as a
     batch in FP32 and FP64: each matches its own oracle and only the hot one is
@@ -337,7 +371,8 @@ def test_tuning_knobs_leave_fp32_results_bitwise_unchanged():
     runs = [dict(), dict(tile=(8, 1, 8)), dict(tile=(32, 1, 16), block=512),
             dict(opts={"yee_tile_z": 4, "seen_tile_z": 32, "resort_every": 5}),
             dict(opts={"particle_waves4": 1}), dict(opts={"particle_prefetch": 1}),
-            dict(opts={"particle_waves4": 1, "particle_prefetch": 1})]
+            dict(opts={"particle_waves4": 1, "particle_prefetch": 1}),
+            dict(opts={"particle_defer": 1}), dict(opts={"particle_defer": 0})]
     ref = None
     for r in runs:
         sim = _sim(wl, (x, u), precision="fp32", tile=r.get("tile"), block=r.get("block", 0))
