@@ -53,6 +53,26 @@ def stored_traffic(name):
     return doc.get("hbm_bytes_per_launch")
 
 
+VALU_PEAK_LANE_INSTR = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock (no packed FP32)
+
+
+def valu_issue(case, n_part, launch_ms):
+    """Fraction of the vector-ALU issue ceiling a particle-kernel launch reaches:
+    lane instructions per particle from committed SQ_INSTS_VALU counter runs
+    (only if they were taken on the current kernel source) times the particles,
+    over the measured launch duration."""
+    path = os.path.join(PROFILE_DIR, "valu_k_particles.json")
+    if not os.path.exists(path):
+        return None
+    doc = json.load(open(path))
+    if doc.get("kernel_source_sha") != kernel_sha() or case not in doc.get("cases", {}):
+        return None
+    per = doc["cases"][case]["valu_lane_instr_per_particle"]
+    achieved = per * n_part / (launch_ms * 1e-3)
+    return {"bound": "alu", "valu_lane_instr_per_particle": per, "achieved": achieved / 1e12,
+            "peak": VALU_PEAK_LANE_INSTR / 1e12, "unit": "T lane-instr/s", "frac": achieved / VALU_PEAK_LANE_INSTR}
+
+
 def cpu_baseline(wl, x, u, steps):
     """The FP64 oracle (single thread, as it stands) on a bounded sample: `steps`
     steps of the same 512x512, 16 ppc workload."""
@@ -133,6 +153,7 @@ def beam3d_block(steps, warmup):
     return {"particles": n_part, "cells": n_cells, "particle_steps_per_s": n_part * steps / dt,
             "ms_per_step": 1e3 * dt / steps, "kernels_ms": {k: prof[k] for k in ("yee_ms", "seen_ms", "particle_ms")},
             "particle_kernel_hbm_frac": pk / (prof["particle_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "particle_kernel_valu": valu_issue("beam3d_128x128x256_ppc8_cubic_fp32", n_part, prof["particle_ms"]),
             "gauss_linf_rel": d["gauss_linf"] / max(d["rho_max"], 1e-300), "slow_tiles": d["slow_tiles"]}
 
 
@@ -323,7 +344,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-instance batched comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost ratio")
@@ -409,6 +430,7 @@ def main():
                      "kernel": "k_particles<2,1,float>", "bytes_per_launch": pk_bytes,
                      "avg_launch_ms": prof["particle_ms"]},
         "kernels_ms": {k: prof[k] for k in ("yee_ms", "seen_ms", "particle_ms", "resort_ms", "step_ms")},
+        "particle_kernel_valu": valu_issue("beam2d_512x512_ppc16_fp32", n_part, prof["particle_ms"]),
         "grid_cell_updates_per_s": n_cells * args.steps / elapsed,
         "gauss_linf_rel": d["gauss_linf"] / max(d["rho_max"], 1e-300),
         "kernel_source_sha": kernel_sha(),
