@@ -203,8 +203,10 @@ int pic_step(pic_state *st, int nsteps);
 int pic_set_schedule(pic_state *st, int sched, int use_graph);
 
 /* Tuning knobs (used by the autotuner); every one keeps results unchanged:
- *   "yee_tile_z"     rows of the 2D Yee tile: 4, 8 or 16 (16 is float only)
- *   "seen_tile_z"    rows of the 2D seen-field tile: 8, 16 or 32
+ *   "yee_tile_z"     rows of the 2D Yee tile: 4, 8 or 16 (16 is float only);
+ *                    default 8, or 16 for FP32 batches of more than 4 * 512^2 cells
+ *   "seen_tile_z"    rows of the 2D seen-field tile: 8, 16 or 32; default 16, or
+ *                    32 for FP32 batches of more than 4 * 512^2 cells
  *   "resort_every"   steps between tile re-sort checks (and per captured graph);
  *                    default 16
  *   "particle_block" threads per particle workgroup: 256 or 512

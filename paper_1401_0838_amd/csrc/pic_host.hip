@@ -964,6 +964,15 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
                                            hipGetErrorString(e)));
     }
     s->block = cfgs[0].block ? cfgs[0].block : default_block();
+    // 2D FP32 field tiles: taller tiles (fewer halo rows per output row) pay once
+    // the launches are bandwidth-bound, measured on a 64-instance batch of 3.9 M
+    // cells (seen 74 -> 60 us, Yee 111 -> 109 us per step); a single 512 x 512
+    // grid is latency-bound and keeps the shorter ones (the options override)
+    if (s->dims == 2 && s->fp32) {
+        long long cells = 0;
+        for (int i = 0; i < n_inst; i++) cells += (long long)cfgs[i].nx * cfgs[i].nz;
+        if (cells > 4LL * 512 * 512) { s->seen_tz = 32; s->yee_tz = 16; }
+    }
     // largest LDS window over the instances
     int maxsm = 0;
     if (hipDeviceGetAttribute(&maxsm, hipDeviceAttributeMaxSharedMemoryPerBlock, 0) != hipSuccess) maxsm = 65536;

@@ -274,11 +274,13 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 #pragma unroll UNROLL_OUTER
         for (int kz = 0; kz < L + 2; kz++) {
             if (kz == L + 1 && !last[2]) break;
+            // the transverse weight S0y S0z + (dSy S0z + S0y dSz) / 2 + dSy dSz / 3,
+            // grouped as S0y az + dSy bz with az, bz once per z node
+            const R az = S0[2][kz] + R(0.5) * DS[2][kz], bz = R(0.5) * S0[2][kz] + R(1.0 / 3.0) * DS[2][kz];
 #pragma unroll
             for (int ky = 0; ky < L + 2; ky++) {
                 if (ky == L + 1 && !last[1]) break;
-                R tr = S0[1][ky] * S0[2][kz] + R(0.5) * DS[1][ky] * S0[2][kz] + R(0.5) * S0[1][ky] * DS[2][kz]
-                     + R(1.0 / 3.0) * DS[1][ky] * DS[2][kz];
+                const R tr = S0[1][ky] * az + DS[1][ky] * bz;
                 R acc;
 #pragma unroll
                 for (int kx = 0; kx < L + 1; kx++) {
@@ -293,11 +295,11 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 #pragma unroll UNROLL_OUTER
         for (int kz = 0; kz < L + 2; kz++) {
             if (kz == L + 1 && !last[2]) break;
+            const R az = S0[2][kz] + R(0.5) * DS[2][kz], bz = R(0.5) * S0[2][kz] + R(1.0 / 3.0) * DS[2][kz];
 #pragma unroll
             for (int kx = 0; kx < L + 2; kx++) {
                 if (kx == L + 1 && !last[0]) break;
-                R tr = S0[2][kz] * S0[0][kx] + R(0.5) * DS[2][kz] * S0[0][kx] + R(0.5) * S0[2][kz] * DS[0][kx]
-                     + R(1.0 / 3.0) * DS[2][kz] * DS[0][kx];
+                const R tr = S0[0][kx] * az + DS[0][kx] * bz;
                 R acc;
 #pragma unroll
                 for (int ky = 0; ky < L + 1; ky++) {
@@ -312,11 +314,11 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
 #pragma unroll UNROLL_OUTER
         for (int ky = 0; ky < L + 2; ky++) {
             if (ky == L + 1 && !last[1]) break;
+            const R ay = S0[1][ky] + R(0.5) * DS[1][ky], by = R(0.5) * S0[1][ky] + R(1.0 / 3.0) * DS[1][ky];
 #pragma unroll
             for (int kx = 0; kx < L + 2; kx++) {
                 if (kx == L + 1 && !last[0]) break;
-                R tr = S0[0][kx] * S0[1][ky] + R(0.5) * DS[0][kx] * S0[1][ky] + R(0.5) * S0[0][kx] * DS[1][ky]
-                     + R(1.0 / 3.0) * DS[0][kx] * DS[1][ky];
+                const R tr = S0[0][kx] * ay + DS[0][kx] * by;
                 R acc;
 #pragma unroll
                 for (int kz = 0; kz < L + 1; kz++) {
