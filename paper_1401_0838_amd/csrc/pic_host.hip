@@ -264,6 +264,11 @@ LaunchCtx ctx(const pic_state *s)
     c.ratio = s->ratio;
     for (const InstDesc &d : s->desc) {
         c.rtiles = std::max(c.rtiles, (d.n[0] * d.n[1] + PIC_RATIO_TC - 1) / PIC_RATIO_TC);
+        // 3D column passes: one thread per column and run of PIC_COL_RUN cells
+        const long long tz = (long long)d.n[0] * d.n[1] * ((d.n[2] + PIC_COL_RUN - 1) / PIC_COL_RUN);
+        const long long ty = (long long)d.n[0] * d.n[2] * ((d.n[1] + PIC_COL_RUN - 1) / PIC_COL_RUN);
+        c.col_blocks[0] = std::max(c.col_blocks[0], (int)((tz + 255) / 256));
+        c.col_blocks[1] = std::max(c.col_blocks[1], (int)((ty + 255) / 256));
     }
     if (!s->desc.empty()) {
         const InstDesc &d0 = s->desc[0];

@@ -10,6 +10,7 @@
 #define PIC_PART_CHUNK 256      // particles per particle-chunk work item
 #define PIC_SEEN_TX 64          // 2D seen-field tile (x)
 #define PIC_TILE_SLACK 4        // cells a tile's particle bounding box may grow before a re-sort
+#define PIC_COL_RUN 16          // cells per thread along the axis of a 3D column stencil pass
 
 // device flag slots (per instance)
 enum { FLAG_RESORT = 0, FLAG_PERR = 1, FLAG_SLOW = 2, FLAG_NRESORT = 3, FLAG_COUNT = 8 };
@@ -151,6 +152,7 @@ struct LaunchCtx {
     int inst0 = 0, ninst = 1;         // instances the launches cover (ratio solve grid)
     int rtiles = 0;                   // column tiles of the widest instance (ratio solve grid)
     int cus = 256;                    // compute units of the device
+    int col_blocks[2] = {0, 0};       // 3D column passes (z, y): 256-thread blocks for the largest instance
     int defer_mode = -1;              // particle launch form: -1 by tile count, 0 inline, 1 deferring (2D)
 };
 

@@ -910,6 +910,62 @@ __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ 
     G<R>(dst)[cell] = acc;
 }
 
+// One pass of the 3D seen-field stencils along a strided axis (AXIS 2: z,
+// 1: y), HW taps either side: each thread walks one column of the grid (lanes
+// on consecutive x, so every load of a wave is one contiguous row), keeps the
+// RUN + 2 HW values of its run of RUN output cells in registers and writes the
+// RUN outputs.  The taps are converted to R once per thread and every input
+// value is loaded once per run instead of once per tap.  blockIdx.y =
+// component, blockIdx.z = instance (from inst0).
+template <int AXIS, class R, int HW, int RUN>
+__global__ void __launch_bounds__(256) k_seen_col(const InstDesc *__restrict__ Dt, int inst0, int src_sel,
+                                                  int dst_sel, int par)
+{
+    const InstDesc &D = Dt[inst0 + blockIdx.z];
+    const int comp = blockIdx.y;
+    const int nx = D.n[0], ny = D.n[1], nz = D.n[2];
+    const int nq = AXIS == 2 ? nz : ny;              // cells along the pass
+    const int ncol = AXIS == 2 ? nx * ny : nx * nz;  // columns
+    const int nseg = (nq + RUN - 1) / RUN;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ncol * nseg) return;
+    const int seg = g / ncol, col = g - seg * ncol;
+    const int i = col % nx, o = col / nx;            // o: y index (z pass) or z index (y pass)
+    const int stride = AXIS == 2 ? nx * ny : nx;
+    const int base = AXIS == 2 ? i + o * nx : i + o * nx * ny;
+    const R *src;
+    if (src_sel == 0) src = comp < 3 ? (const R *)D.E[par][comp] : (const R *)D.B[par][comp - 3];
+    else if (src_sel == 1) src = (const R *)D.T1[comp];
+    else src = (const R *)D.T2[comp];
+    R *dst;
+    if (dst_sel == 1) dst = (R *)D.T1[comp];
+    else if (dst_sel == 2) dst = (R *)D.T2[comp];
+    else dst = comp < 3 ? (R *)D.Et[comp] : (R *)D.Bt[comp - 3];
+    const double *tap = AXIS == 2 ? ztaps(D, comp) : ytaps(D, comp);
+    R tp[2 * HW + 1];
+#pragma unroll
+    for (int t = 0; t <= 2 * HW; t++) tp[t] = (R)tap[t];
+    const gp<const R> sp = G<R>((const void *)src);
+    const gp<R> dp = G<R>((void *)dst);
+    const int q0 = seg * RUN;
+    // the run's inputs q0 - HW .. q0 + RUN + HW - 1, periodic along the axis
+    int q = ((q0 - HW) % nq + nq) % nq;
+    R w[RUN + 2 * HW];
+#pragma unroll
+    for (int t = 0; t < RUN + 2 * HW; t++) {
+        w[t] = sp[base + q * stride];
+        q = q + 1 == nq ? 0 : q + 1;
+    }
+#pragma unroll
+    for (int r = 0; r < RUN; r++) {
+        if (q0 + r >= nq) break;
+        R acc = R(0);
+#pragma unroll
+        for (int t = 0; t <= 2 * HW; t++) acc += tp[t] * w[r + t];
+        dp[base + (q0 + r) * stride] = acc;
+    }
+}
+
 // 2D fields as seen by the particles in one kernel: one component's (64 x SEEN_TZ)
 // output tile is staged in LDS with its stencil halo (waves own rows, lanes own
 // columns, so addresses are affine in the lane); the x filter stencil then runs
@@ -1555,14 +1611,16 @@ int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *sw
         } else {
             // usual widths: correction of degree 4 with four filter passes (z 8, x and y 4),
             // one more with the node average of the momentum-conserving gather
+            // z and y: column passes; x (contiguous): one cell per thread
+            const dim3 gz(c.col_blocks[0], 6, c.ninst), gy(c.col_blocks[1], 6, c.ninst);
             if (c.hz == 8 && c.hx == 4) {
-                k_seen_pass<2, R, 8><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1, c.par);
+                k_seen_col<2, R, 8, PIC_COL_RUN><<<gz, b, 0, c.stream>>>(c.desc, c.inst0, 0, 1, c.par);
                 k_seen_pass<0, R, 4><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
-                k_seen_pass<1, R, 4><<<g, b, 0, c.stream>>>(c.desc, fwork, 2, 0, c.par);
+                k_seen_col<1, R, 4, PIC_COL_RUN><<<gy, b, 0, c.stream>>>(c.desc, c.inst0, 2, 0, c.par);
             } else if (c.hz == 9 && c.hx == 5) {
-                k_seen_pass<2, R, 9><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1, c.par);
+                k_seen_col<2, R, 9, PIC_COL_RUN><<<gz, b, 0, c.stream>>>(c.desc, c.inst0, 0, 1, c.par);
                 k_seen_pass<0, R, 5><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
-                k_seen_pass<1, R, 5><<<g, b, 0, c.stream>>>(c.desc, fwork, 2, 0, c.par);
+                k_seen_col<1, R, 5, PIC_COL_RUN><<<gy, b, 0, c.stream>>>(c.desc, c.inst0, 2, 0, c.par);
             } else {
                 k_seen_pass<2, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1, c.par);
                 k_seen_pass<0, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
