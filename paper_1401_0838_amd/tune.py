@@ -1,9 +1,11 @@
-"""Autotuner for the particle-tile shape, workgroup size and launch schedule.
+"""Autotuner for the particle-tile shape, workgroup size, launch options and schedule.
 
 For a workload it builds short-lived simulations with each candidate
 (tile shape, threads per workgroup), times a few steps with HIP events
-(pic_profile) and keeps the fastest; for batches it also compares the batched
-and the per-instance schedules.  Results are cached in a JSON file keyed by
+(pic_profile) and keeps the fastest; with that tile it then times the launch
+options (2D field-tile heights, inline or deferred particle launch) and keeps
+the fastest set; for batches it also compares the batched and the
+per-instance schedules.  Results are cached in a JSON file keyed by
 the workload's shape so later runs reuse them.
 """
 import json
@@ -17,6 +19,11 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.jso
 CANDIDATES_2D = [((16, 1, 16), 256), ((16, 1, 16), 512), ((32, 1, 16), 256), ((16, 1, 32), 256),
                  ((32, 1, 32), 512), ((8, 1, 16), 256), ((8, 1, 8), 256)]
 CANDIDATES_3D = [((8, 4, 4), 256), ((8, 2, 4), 256), ((4, 4, 8), 256), ((8, 8, 4), 256), ((4, 4, 4), 256)]
+# launch options tried with the chosen tile ({} = the library's defaults);
+# every one leaves the results unchanged
+OPTIONS_2D = [{}, {"seen_tile_z": 16, "yee_tile_z": 8}, {"seen_tile_z": 32}, {"seen_tile_z": 32, "yee_tile_z": 16},
+              {"particle_defer": 0}, {"particle_defer": 1}]
+OPTIONS_3D = [{}]
 
 
 def key(workloads, precision):
@@ -35,8 +42,16 @@ def _load_cache(path):
     return {}
 
 
-def tune(workloads, particles, precision="fp32", steps=10, warmup=3, cache=CACHE, candidates=None):
-    """Return {"tile": [tx, ty, tz], "block": b, "schedule": "batched"|"plain", "step_ms": t}."""
+def apply_options(sim, options):
+    """Set the launch options a tuning result chose on a Simulation."""
+    for name, value in (options or {}).items():
+        sim.set_option(name, value)
+
+
+def tune(workloads, particles, precision="fp32", steps=10, warmup=3, cache=CACHE, candidates=None,
+         options=None):
+    """Return {"tile": [tx, ty, tz], "block": b, "options": {...}, "schedule": "batched"|"plain",
+    "step_ms": t}; apply "options" with apply_options."""
     if isinstance(workloads, dict):
         workloads, particles = [workloads], [particles]
     k = key(workloads, precision)
@@ -53,11 +68,23 @@ def tune(workloads, particles, precision="fp32", steps=10, warmup=3, cache=CACHE
         sim.close()
         if best is None or prof["step_ms"] < best["step_ms"]:
             best = {"tile": list(tile), "block": block, "step_ms": prof["step_ms"]}
+    best["options"] = {}
+    for opts in (options if options is not None else (OPTIONS_2D if dims == 2 else OPTIONS_3D)):
+        if not opts:
+            continue
+        sim = Simulation(workloads, particles, precision=precision, tile=best["tile"], block=best["block"])
+        apply_options(sim, opts)
+        sim.step(warmup)
+        prof = sim.profile(steps)
+        sim.close()
+        if prof["step_ms"] < best["step_ms"]:
+            best["options"], best["step_ms"] = dict(opts), prof["step_ms"]
     best["schedule"] = "batched"
     if len(workloads) > 1:
         times = {}
         for sched in ("batched", "plain"):
             sim = Simulation(workloads, particles, precision=precision, tile=best["tile"], block=best["block"])
+            apply_options(sim, best["options"])
             sim.set_schedule(sched, True)
             sim.step(warmup)
             sim.synchronize()

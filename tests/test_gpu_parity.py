@@ -387,6 +387,8 @@ def test_tuning_knobs_leave_fp32_results_bitwise_unchanged():
             for a, b in zip(ref, got):
                 assert np.array_equal(a, b), r
     best = tune.tune(wl, (x, u), precision="fp32", steps=3, warmup=1, cache=None,
-                     candidates=[((16, 1, 16), 256), ((8, 1, 8), 256)])
+                     candidates=[((16, 1, 16), 256), ((8, 1, 8), 256)],
+                     options=[{}, {"seen_tile_z": 32}, {"particle_defer": 1}])
     _say("tuner picked %s" % best)
     assert best["tile"] in ([16, 1, 16], [8, 1, 8]) and best["step_ms"] > 0
+    assert best["options"] in ({}, {"seen_tile_z": 32}, {"particle_defer": 1})
