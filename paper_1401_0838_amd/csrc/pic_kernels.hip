@@ -246,17 +246,18 @@ __device__ __forceinline__ void push_particle(Win &W, const int *lc, const R *of
             }
         }
         // J_y: out of plane, with v_y.  W_y = S0x (S0z/3 + S1z/6) + S1x (S0z/6 + S1z/3)
-        const R cy = cy2d * u[1] * ig;
+        // with S1 = S0 + dS is S0x (S0z + dSz/2) + dSx (S0z/2 + dSz/3): two
+        // factors per z node, two operations per node
+        const R cy = cy2d * u[1] * ig, cy2 = R(0.5) * cy, cy3 = R(1.0 / 3.0) * cy;
 #pragma unroll
         for (int k = 0; k < L + 2; k++) {
             if (k == L + 1 && !lastz) break;
-            const R s1z = S0[2][k] + DS[2][k];
-            const R az = cy * (R(1.0 / 3.0) * S0[2][k] + R(1.0 / 6.0) * s1z);
-            const R bz = cy * (R(1.0 / 6.0) * S0[2][k] + R(1.0 / 3.0) * s1z);
+            const R pz = cy * S0[2][k] + cy2 * DS[2][k];
+            const R qz = cy2 * S0[2][k] + cy3 * DS[2][k];
 #pragma unroll
             for (int i = 0; i < L + 2; i++) {
                 if (i == L + 1 && !lastx) break;
-                const R wy = S0[0][i] * az + (S0[0][i] + DS[0][i]) * bz;
+                const R wy = S0[0][i] * pz + DS[0][i] * qz;
                 W.add(1, base[0] + i, 0, base[2] + k, jcvt(wy, tag));
             }
         }
