@@ -121,6 +121,7 @@ def batched_block(steps, warmup):
         sim.close()
         out[sched + "_particle_steps_per_s"] = n_part * steps / dt
         out[sched + "_ms_per_step"] = 1e3 * dt / steps
+        out[sched + "_grid_cell_updates_per_s"] = out["cells"] * steps / dt
     out["speedup_batched_vs_plain"] = out["batched_particle_steps_per_s"] / out["plain_particle_steps_per_s"]
     out["batched_hbm_frac"] = (out["batched_bytes_per_particle_launch"] / (out["batched_particle_ms"] * 1e-3)
                                / 1e9 / HBM_PEAK_GBS)
@@ -151,6 +152,7 @@ def beam3d_block(steps, warmup):
     sim.close()
     pk = particle_kernel_bytes(n_part, n_cells, state_bytes=28)
     return {"particles": n_part, "cells": n_cells, "particle_steps_per_s": n_part * steps / dt,
+            "grid_cell_updates_per_s": n_cells * steps / dt,
             "ms_per_step": 1e3 * dt / steps, "kernels_ms": {k: prof[k] for k in ("yee_ms", "seen_ms", "particle_ms")},
             "particle_kernel_hbm_frac": pk / (prof["particle_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "particle_kernel_valu": valu_issue("beam3d_128x128x256_ppc8_cubic_fp32", n_part, prof["particle_ms"]),
