@@ -186,7 +186,14 @@ int pic_psi_coeffs(int interp, double alpha, int deg, double *psi_e, double *psi
  * particle counts. */
 int pic_plan(const pic_config *cfgs, int n_inst, const int64_t *n_particles, size_t *arena_bytes);
 
-/* Validate the configurations, lay them out in the arena, upload the
+/* Set up the problem Sec. 3 simulates: a uniform relativistic beam drifting
+ * along z through a periodic box on the Yee mesh of Sec. 2, with the
+ * correction polynomials Psi_E / Psi_B of Sec. 2 (psi_e, psi_b; see
+ * pic_psi_coeffs), the digital filter of Sec. 3 / Eq. 6 (filter_w; Sec. 4's
+ * variant with one pass of each kind is the same list with two entries), the
+ * gather scheme whose multiplier Eqs. 3-5 give, and the time step
+ * alpha = c dt / dz that Secs. 3-4 scan.
+ * Validate the configurations, lay them out in the arena, upload the
  * particles (host float64 -> device; converted to cell index + in-cell
  * offset), sort them by tile and record the initial charge density.
  * d_arena: device pointer of arena_bytes bytes (256-byte aligned), owned by
@@ -195,7 +202,12 @@ int pic_plan(const pic_config *cfgs, int n_inst, const int64_t *n_particles, siz
 int pic_init(const pic_config *cfgs, int n_inst, const pic_particles *parts,
              void *d_arena, size_t arena_bytes, void *hip_stream, pic_state **out);
 
-/* Advance every instance by nsteps steps.  Asynchronous on the bound stream. */
+/* Advance every instance by nsteps steps of the explicit scheme Sec. 2
+ * analyses: the Yee field update, then the fields as seen by the particles
+ * (Psi_E(S_z) on the transverse E and Psi_B(S_z) on the rest, Sec. 2,
+ * followed by the filter passes of Sec. 3 / Eq. 6), then per particle the
+ * gather of those fields, the Boris push, the move and the current-conserving
+ * deposit.  Asynchronous on the bound stream. */
 int pic_step(pic_state *st, int nsteps);
 
 /* Choose the launch schedule (PIC_SCHED_*) and whether steps are replayed
@@ -223,7 +235,11 @@ int pic_set_schedule(pic_state *st, int sched, int use_graph);
 int pic_set_option(pic_state *st, const char *name, int value);
 int pic_get_option(pic_state *st, const char *name, int *value);
 
-/* Copy one component of a grid quantity (PIC_FIELD_*) of instance inst to
+/* Grid fields of the scheme: E and B on the Yee mesh (Sec. 2), the fields as
+ * seen by the particles after the correction and filter (Sec. 2: the
+ * multipliers act on what the particles see, not on the grid fields), J and
+ * the charge density.
+ * Copy one component of a grid quantity (PIC_FIELD_*) of instance inst to
  * (GET) or from (SET) a host float64 array of n = nx*ny*nz values laid out
  * [z][y][x], x fastest, half-integer locations stored at the lower index.
  * SET is allowed for E and B only.  Synchronises the stream. */
@@ -234,7 +250,10 @@ int pic_fields(pic_state *st, int inst, int which, int comp, double *host, size_
  * pos[1] may be NULL in 2D.  Synchronises the stream. */
 int pic_get_particles(pic_state *st, int inst, double *pos[3], double *mom[3], int64_t n);
 
-/* Diagnostics of instance inst (float64 reductions on the device).
+/* Diagnostics of instance inst (float64 reductions on the device): the field
+ * energies whose transverse part gives the growth rates of Sec. 3 and whose
+ * total Sec. 4 tracks, the beam's kinetic energy, and the Gauss-law residual
+ * that the current-conserving deposit keeps at rounding level.
  * Synchronises the stream.  Returns PIC_ENONFINITE or PIC_EPARTICLE when the
  * corresponding flag is set (out is filled in either case). */
 int pic_diag(pic_state *st, int inst, pic_diag_t *out);

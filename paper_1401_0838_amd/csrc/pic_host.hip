@@ -910,7 +910,13 @@ extern "C" int pic_plan(const pic_config *cfgs, int n_inst, const int64_t *n_par
             (cfgs[i].correction == PIC_CORR_RATIO) != (cfgs[0].correction == PIC_CORR_RATIO) ||
             (cfgs[0].adjoint_steps > 0 && cfgs[i].adjoint_ckpt != cfgs[0].adjoint_ckpt))
             return fail(PIC_EINVAL, "all instances must share dims, precision, shape_order, interp, solver, the exact-ratio choice and adjoint sizes");
-        if (n_particles[i] < 0 || n_particles[i] > INT32_MAX) return fail(PIC_EINVAL, "particle count");
+        // the particle kernels address an instance's particle arrays with 32-bit
+        // byte offsets (p * sizeof(element)), so n * max(sizeof(R), 4) must stay
+        // below 2^32: 2^30 particles in FP32, 2^29 in FP64
+        const int64_t nmax = (int64_t)(UINT32_MAX / (cfgs[0].precision == PIC_FP64 ? 8u : 4u));
+        if (n_particles[i] < 0 || n_particles[i] > nmax)
+            return fail(PIC_EINVAL, "particle count must be in [0, " + std::to_string(nmax) +
+                                        "] (32-bit byte offsets into the particle arrays)");
     }
     const std::vector<pic_config> rc = resolve_tiles(cfgs, n_inst);
     *arena_bytes = layout(nullptr, rc.data(), n_inst, n_particles, nullptr);

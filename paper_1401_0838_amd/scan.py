@@ -78,13 +78,14 @@ def growth_table(points, traces, wkin):
 
 # Sec. 3's variants of its Fig. 2 setting (correction, Eq. 6 filter): (1) no
 # digital filtering apart from Psi_B; (2) Psi_E / Psi_B applied to the
-# transverse E only (Psi_B inverted); (3) no compensation passes.
-VARIANTS = {
-    "baseline": dict(correction=True),
-    "no_filter": dict(correction=True, filter=[]),
-    "ratio_on_transverse_E": dict(correction="ratio"),
-    "no_compensation": dict(correction=True, filter=[0.25, 0.25]),
-}
+# transverse E only (Psi_B inverted); (3) no compensation passes; and Sec. 4's
+# filter with one bilinear and one compensation pass (the square root of Eq. 6)
+def _variants():
+    import pic_inputs as pi
+    return dict(pi.VARIANTS)
+
+
+VARIANTS = _variants()
 
 
 def variant_sweep(base, alphas, gamma, nsteps, precision="fp32", seed=0):

@@ -73,3 +73,47 @@ def batched_candidates(seed=0, count=256):
                         steps=1000, seeds=(1000 * seed + i,), sigma=1e-6,
                         name="batched_%d" % i))
     return out
+
+
+# Sec. 3 variants of its CK / Eq. 6 setting, as workload overrides: no digital
+# filtering apart from Psi_B; Psi_E / Psi_B on the transverse E only (Psi_B
+# inverted); no compensation passes; the Sec. 4 filter with one pass of each
+# kind (the square root of Eq. 6)
+VARIANTS = {
+    "baseline": dict(correction=True),
+    "no_filter": dict(correction=True, filter=[]),
+    "ratio_on_transverse_E": dict(correction="ratio"),
+    "no_compensation": dict(correction=True, filter=[0.25, 0.25]),
+    "sqrt_eq6": dict(correction=True, filter=PAPER_EQ6_SQRT),
+}
+
+
+def growth_cases():
+    """Instances whose FP64 growth traces are stored as goldens, as
+    (key, workload, particle seed, steps).  The 64-instance batch is not listed
+    here: it is the first 64 accepted entries of batched_candidates(0).
+
+    c1   : the 512x512 workload at its three alphas, 2000 steps
+    scan : the Sec. 3 setting on a 64x64 grid with 8 ppc (gamma 3 and 130, alpha
+           0.5 and 0.9, with and without the correction), 1000 steps; the seed of
+           point (gamma index gi, alpha index ai) is 1000 gi + ai
+    var  : the variants above in that setting at gamma 130, alpha 0.7 and 0.95,
+           1000 steps; seed = alpha index
+    """
+    out = []
+    base512 = workload("beam2d_512")
+    for a in base512["alphas"]:
+        out.append(("c1_a%g" % a, dict(base512, alpha=a, name="c1_a%g" % a), 0, 2000))
+    for corr in (True, False):
+        base = workload("beam2d_128_ck", n=(64, 64), ppc=8, correction=corr)
+        for gi, g in enumerate((3.0, 130.0)):
+            for ai, a in enumerate((0.5, 0.9)):
+                k = "scan_%s_g%g_a%g" % ("corr" if corr else "plain", g, a)
+                out.append((k, dict(base, alpha=a, gamma=g, name=k), 1000 * gi + ai, 1000))
+    for name, over in VARIANTS.items():
+        base = workload("beam2d_128_ck", n=(64, 64), ppc=8, gamma=130.0)
+        base.update(over)
+        for ai, a in enumerate((0.7, 0.95)):
+            k = "var_%s_a%g" % (name, a)
+            out.append((k, dict(base, alpha=a, name=k), ai, 1000))
+    return out

@@ -138,6 +138,20 @@ def test_plan_validates_configs():
         L.pic_plan([_cfg(), _cfg(dims=3, n=(8, 8, 8))], [16, 16])
 
 
+def test_plan_rejects_particle_counts_beyond_32bit_offsets():
+    """Particle arrays are addressed with 32-bit byte offsets: at most 2^30 - 1
+    particles per instance in FP32 (4-byte elements) and 2^29 - 1 in FP64."""
+    c32 = _cfg(precision="fp32")
+    assert L.pic_plan([c32], [(1 << 30) - 1]) > 0
+    with pytest.raises(L.PicError):
+        L.pic_plan([c32], [1 << 30])
+    c64 = _cfg(precision="fp64")
+    with pytest.raises(L.PicError):
+        L.pic_plan([c64], [1 << 29])
+    with pytest.raises(L.PicError):
+        L.pic_plan([c32], [-1])
+
+
 def test_plan_grows_with_batch():
     one = L.pic_plan([_cfg()], [1024])
     two = L.pic_plan([_cfg(), _cfg(n=(32, 16))], [1024, 2048])

@@ -151,7 +151,9 @@ def test_adjoint_many_batched_instances_match_oracle():
 
 def test_adjoint_full_size_fd_and_cost_ratio():
     """256x256, 8 ppc, gamma 130, alpha 0.5, 200 steps with checkpoints every 20:
-    FP32 adjoint gradient vs FP64 central differences (h = 1e-6) of the GPU forward."""
+    FP32 adjoint gradient vs FP64 central differences (h = 1e-6) of the GPU forward,
+    and the backward sweep (recompute + reverse) within 3x the plain forward run
+    (timed after one warm-up pair that captures the segment graphs)."""
     wl = pi.workload("beam2d_256_adjoint")
     x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], wl["sigma"], 0)
     from paper_1401_0838_amd.sim import Simulation
@@ -167,12 +169,19 @@ def test_adjoint_full_size_fd_and_cost_ratio():
     fwd.synchronize()
     t_plain = time.perf_counter() - t0
     fwd.close()
+    tsim = Simulation(wl, (x, u), precision="fp32", adjoint_steps=nsteps, adjoint_ckpt=wl["checkpoint"])
+    tsim.adjoint_forward(wl["checkpoint"])
+    tsim.adjoint_backward()
+    tsim.synchronize()
     t0 = time.perf_counter()
-    L = sim.adjoint_forward(nsteps)[0]
+    tsim.adjoint_forward(nsteps)
     t_f = time.perf_counter() - t0
     t0 = time.perf_counter()
-    g = sim.adjoint_backward()[0]
+    tsim.adjoint_backward()
     t_b = time.perf_counter() - t0
+    tsim.close()
+    L = sim.adjoint_forward(nsteps)[0]
+    g = sim.adjoint_backward()[0]
     a0 = sim.psi()[0]
     sim.close()
     _, _, b0 = Lb.pic_psi_coeffs(Lb.PIC_GALERKIN, wl["alpha"], 4)
@@ -189,3 +198,4 @@ def test_adjoint_full_size_fd_and_cost_ratio():
     fd = np.array([(W64(a0 + h * e) - W64(a0 - h * e)) / (2 * h) for e in np.eye(len(a0))])
     _say("c4 FD %s" % fd)
     assert np.max(np.abs(g - fd)) < 1e-2 * np.max(np.abs(fd))
+    assert t_b / t_plain <= 3.0, (t_b, t_plain)

@@ -124,6 +124,20 @@ def test_ck_paper_setting_cubic_eq6_fp64():
     sim.close()
 
 
+@pytest.mark.parametrize("prec,steps,tol", [("fp64", 50, 1e-10), ("fp32", 10, 1e-4)])
+def test_ck_sqrt_eq6_filter_one_pass_each(prec, steps, tol):
+    """Sec. 4's filter with one bilinear and one compensation pass per axis (the
+    square root of Eq. 6) in the Sec. 3 setting (cubic, CK, correction,
+    alpha = 0.9) on a ragged 50 x 70 grid: fields, current and particles follow
+    the oracle (FP64 within 1e-10 after 50 steps, FP32 within 1e-4 after 10)."""
+    wl = pi.workload("beam2d_128_ck", n=(50, 70), ppc=4, filter=pi.workloads.PAPER_EQ6_SQRT)
+    sim, ref = _pair(wl, steps, prec)
+    errs = _errors(sim, ref, wl)
+    _say("  sqrt eq6 %s %s" % (prec, errs))
+    assert max(errs["E"], errs["B"], errs["J"]) < tol
+    sim.close()
+
+
 def test_ck_batched_matches_oracle_plain_and_tile_heights():
     """Two CK instances in one batch match their oracles; FP32 results are
     bitwise the same batched or plain and for every Yee tile height."""

@@ -143,7 +143,7 @@ def test_batched_scan_growth_rates_fp32_vs_fp64():
 def test_growth_rate_ck_cubic_eq6_vs_oracle():
     """The Sec. 3 setting (cubic, CK, Eq. 6 filter, correction) at 32x32, 4 ppc,
     alpha = 0.9: the GPU traces follow the oracle and the fitted rates agree."""
-    wl = pi.workload("beam2d_128_ck", n=(32, 32), ppc=4, alpha=0.9, correction=False)
+    wl = pi.workload("beam2d_128_ck", n=(32, 32), ppc=4, alpha=0.9, correction=True)
     x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], wl["sigma"], 0)
     n = 400
     Wo, wk = _oracle_trace(wl, x, u, n)

@@ -503,7 +503,8 @@ def _brute_pair(dims, n, order, filt, corr=True, npart=10, seed=3, steps=20, int
     s = o.s
     b = BruteSim(dims, o.shape, (s.dx, s.dy, s.dz), s.dt, order, s.q, s.m, s.w,
                  psi_e=o.psi[0] if o.psi else None, psi_b=o.psi[1] if o.psi else None,
-                 filt=filt, jbg=tuple(s.jbg), interp=interp, solver=solver, ratio=(corr == "ratio"))
+                 filt=filt, jbg=tuple(_loader_background_current(wl, u, s.w, o.dV * float(np.prod(o.shape)))),
+                 interp=interp, solver=solver, ratio=(corr == "ratio"))
     b.E[:] = o.E
     b.B[:] = o.B
     bx, bu = o.x.copy(), o.u.copy()
@@ -571,6 +572,44 @@ def test_growth_fit_recovers_rate():
     assert lo > 0 and abs(G - gam) < 0.02 * gam
 
 
+def _ramp_then_growth(dt, gam, n_ramp, n, w_sat):
+    """A run's shape: W climbs from ~0 along a straight ramp (the start-up rise to
+    the noise level), then grows as exp(2 gam t) until it saturates at w_sat."""
+    t = np.arange(n) * dt
+    W = 1e-3 * (np.arange(n) + 1e-12)
+    W[n_ramp:] = W[n_ramp - 1] * np.exp(2 * gam * (t[n_ramp:] - t[n_ramp - 1]))
+    return np.minimum(W, w_sat)
+
+
+@pytest.mark.parametrize("dt,gam,n_ramp", [(0.5, 0.01, 300), (0.3, 0.006, 500), (0.7, 0.02, 150)])
+def test_growth_fit_leaves_out_the_startup_ramp(dt, gam, n_ramp):
+    """The start-up rise has a steep log-slope (1/t) early on; the window must sit
+    in the exponential phase and recover its rate within 1 %, on both fits, and
+    stop before the saturation cap."""
+    from paper_1401_0838_amd import fit as gfit
+    wkin0 = 1e4
+    W = _ramp_then_growth(dt, gam, n_ramp, 2000, 0.5 * wkin0)
+    for G, (lo, hi) in (ofit.growth_rate(list(W), dt, wkin0), gfit.growth_rate(W, dt, wkin0)):
+        assert lo >= n_ramp - 1, (lo, hi)
+        assert W[hi - 1] <= 1e-2 * wkin0 * math.exp(2 * gam * dt) + 1e-12
+        assert abs(G - gam) < 0.01 * gam, (G, gam)
+    # a planted mistake: starting the search at step 1 fits the ramp's 1/t slope
+    G_bad = ofit.growth_rate(list(W), dt, wkin0, omega_p=1e6)[0]
+    assert abs(G_bad - gam) > 0.1 * gam
+
+
+def test_growth_fits_agree_on_a_noisy_trace():
+    """The oracle's plain-loop fit and the library's running-sum fit give the same
+    rate and window on an irregular trace."""
+    from paper_1401_0838_amd import fit as gfit
+    rng = np.random.default_rng(4)
+    n, dt = 1200, 0.45
+    W = _ramp_then_growth(dt, 0.008, 250, n, 1e9) * np.exp(0.2 * rng.standard_normal(n))
+    a = ofit.growth_rate(list(W), dt, 1e4)
+    b = gfit.growth_rate(W, dt, 1e4)
+    assert a[1] == b[1] and abs(a[0] - b[0]) < 1e-9 * abs(a[0])
+
+
 # --------------------------------------------------------------- loader
 
 def test_loader_is_stratified_and_seeded():
@@ -581,3 +620,77 @@ def test_loader_is_stratified_and_seeded():
     x2, u2 = pi.load_beam(2, (8, 6), 4, 130.0, 1e-4, 11)
     assert np.array_equal(x, x2) and np.array_equal(u, u2)
     assert abs(np.mean(u[:, 2]) / math.sqrt(130.0 ** 2 - 1) - 1) < 1e-4
+
+
+# ------------------------------------------------- ion background current
+
+def _loader_background_current(wl, u, weight, V):
+    """Closed form of the immobile ions' uniform current, computed here from the
+    loader's momenta and not read from the oracle: minus the beam's initial mean
+    current q w sum_p v_p / V, with v = u / sqrt(1 + u^2)."""
+    if wl.get("ion_mode", 1) != 1:
+        return np.zeros(3)
+    v = u / np.sqrt(1.0 + np.sum(u * u, axis=1))[:, None]
+    return -wl["q"] * weight * v.sum(axis=0) / V
+
+
+@pytest.mark.parametrize("ion_mode,sigma", [(0, 1e-3), (1, 1e-3), (1, 0.0)])
+def test_uniform_mode_of_E_follows_ampere_with_ion_current(ion_mode, sigma):
+    """The k = 0 mode of E obeys dE/dt = -(mean J + J_ion) exactly on a periodic
+    grid (the curl of B has zero mean), and the Esirkepov current's mean is the
+    beam's charge times its displacement per step.  A step's Yee update uses the
+    current deposited by the step before, so after N steps
+        mean E_a = -(q w / V) sum_p (displacement of p along a in steps 1..N-1)
+                   - N dt J_ion,a
+    (2D y: the displacement is dt sum_n v_y^{n+1/2}).  J_ion is the closed form
+    above; with ions carrying charge only it is zero and E_z ramps."""
+    wl = _wl(n=(16, 12), ppc=4, correction=False, filter=[], ion_mode=ion_mode)
+    x, u = pi.load_beam(2, (16, 12), 4, 130.0, sigma, 5)
+    sim = OracleSim(wl, x, u)
+    q, w, dt = wl["q"], sim.s.w, sim.s.dt
+    V = 16 * 12 * sim.dV
+    jion = _loader_background_current(wl, u, w, V)
+    L = np.array([16.0, 12.0])
+    disp = np.zeros(3)
+    prev = sim.positions()
+    N = 200
+    for n in range(N):
+        if n == N - 1:
+            held = disp.copy()          # the last deposit is not in E yet
+        sim.step(1)
+        cur = sim.positions()
+        d = cur - prev
+        d -= L * np.round(d / L)            # minimum image: |step| < one cell
+        disp[0] += d[:, 0].sum()
+        disp[2] += d[:, 1].sum()
+        gam = np.sqrt(1.0 + np.sum(sim.u ** 2, axis=0))
+        disp[1] += dt * np.sum(sim.u[1] / gam)
+        prev = cur
+    assert sim.status == 0
+    scale = N * dt * abs(q) * w * x.shape[0] / V      # |ramp| if every particle moved at c
+    for a in range(3):
+        pred = -(q * w / V) * held[a] - N * dt * jion[a]
+        got = float(np.mean(sim.E[a]))
+        assert abs(got - pred) < 1e-12 * scale, (a, got, pred)
+    Ez = float(np.mean(sim.E[2]))
+    if ion_mode == 0:
+        # the beam's own current ramps E_z at about -N dt q n0 v
+        assert Ez > 0.9 * scale
+    elif sigma == 0.0:
+        # cold beam with the ion current: no ramp.  The uniform E_z holds the one
+        # step of ion current the first update applied before any deposit
+        # (J^{-1/2} = 0), -dt J_ion,z, up to the small changes of the particles'
+        # velocities in the noise fields (the exact balance is asserted above)
+        assert abs(Ez + dt * jion[2]) < 1e-5 * scale, (Ez, -dt * jion[2])
+
+
+def test_oracle_background_current_matches_closed_form():
+    """The value the oracle uses equals the closed form from the loader's momenta
+    (sign and scale), for a drifting beam with transverse spread."""
+    wl = _wl(n=(8, 6), ppc=3)
+    x, u = pi.load_beam(2, (8, 6), 3, 50.0, 0.3, 9)
+    sim = OracleSim(wl, x, u)
+    V = 8 * 6 * sim.dV
+    ref = _loader_background_current(wl, u, sim.s.w, V)
+    assert np.allclose(np.array(sim.s.jbg[:]), ref, rtol=1e-14, atol=0.0)
+    assert ref[2] > 0      # electrons (q < 0) drifting along +z: the ions' current is +z
