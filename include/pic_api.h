@@ -52,6 +52,11 @@ extern "C" {
 #define PIC_EUNSUPPORTED -8   /* valid but not built (e.g. the reverse sweep of a
                                  non-Galerkin gather) */
 #define PIC_ESTATE       -9   /* call not valid in the current state */
+#define PIC_ERANGE      -10   /* float mode: a current value left the checked range of
+                                 the 32-bit fixed-point current planes (at least 2^9
+                                 times the current of a beam moving at c through the
+                                 densest cell of the initial load); the run's current
+                                 is wrong */
 
 /* ------------------------------------------------------------- enumerations */
 /* gather (interpolation) schemes, with the multiplier each one's Psi fits */
@@ -85,8 +90,14 @@ extern "C" {
                                  line and the two neighbouring lines across it */
 
 #define PIC_FP64 0            /* fields, offsets, momenta and J in double */
-#define PIC_FP32 1            /* float fields/offsets/momenta, int32 cell index,
-                                 J accumulated as 64-bit fixed point */
+#define PIC_FP32 1            /* float fields/offsets/momenta, int32 cell index;
+                                 J summed per tile in 64-bit fixed point (quantum 2^-28
+                                 of the largest single-particle contribution) and
+                                 kept in HBM as 32-bit fixed point (quantum about 2^-21
+                                 of the current of a beam moving at c through the
+                                 densest initial cell; each tile's sum is rounded to it
+                                 once per step).  Integer sums: a run is bitwise
+                                 reproducible for a given particle tiling */
 
 #define PIC_IONS_CHARGE             0  /* immobile ions carry charge only */
 #define PIC_IONS_CHARGE_AND_CURRENT 1  /* plus a fixed uniform current equal to
@@ -158,6 +169,7 @@ typedef struct pic_diag_t {
     int     particle_error;   /* 1 if a particle moved a full cell or more */
     int     resorts;          /* tile re-sorts done since pic_init */
     int     slow_tiles;       /* tile visits that overflowed the LDS window */
+    int     current_range;    /* 1 if a float-mode current value left its checked range */
 } pic_diag_t;
 
 /* per-kernel average durations measured with HIP events (milliseconds) */
@@ -210,6 +222,14 @@ int pic_init(const pic_config *cfgs, int n_inst, const pic_particles *parts,
  * deposit.  Asynchronous on the bound stream. */
 int pic_step(pic_state *st, int nsteps);
 
+/* Capture (without running) the HIP graphs that a following
+ * pic_step(st, nsteps) from the current state replays, so that call pays no
+ * capture (for timed regions and serving loops).  With graph replay a call
+ * launches at most three kinds of graph: the steps up to the next re-sort
+ * check, whole re-sort periods, and the rest; graphs are cached until the
+ * schedule or an option changes.  Synchronous; a no-op for eager stepping. */
+int pic_prepare(pic_state *st, int nsteps);
+
 /* Choose the launch schedule (PIC_SCHED_*) and whether steps are replayed
  * from a captured HIP graph (use_graph = 1) or launched eagerly. */
 int pic_set_schedule(pic_state *st, int sched, int use_graph);
@@ -217,8 +237,9 @@ int pic_set_schedule(pic_state *st, int sched, int use_graph);
 /* Tuning knobs (used by the autotuner); every one keeps results unchanged:
  *   "yee_tile_z"     rows of the 2D Yee tile: 4, 8 or 16 (16 is float only);
  *                    default 8, or 16 for FP32 batches of more than 4 * 512^2 cells
- *   "seen_tile_z"    rows of the 2D seen-field tile: 8, 16 or 32; default 16, or
- *                    32 for FP32 batches of more than 4 * 512^2 cells
+ *   "seen_tile_z"    rows of the 2D seen-field tile: 8, 16, 32 or 64 (32 and 64
+ *                    are float only); default 16, or 32 for FP32 batches of more
+ *                    than 4 * 512^2 cells
  *   "resort_every"   steps between tile re-sort checks (and per captured graph);
  *                    default 16
  *   "particle_block" threads per particle workgroup: 256 or 512
@@ -254,8 +275,8 @@ int pic_get_particles(pic_state *st, int inst, double *pos[3], double *mom[3], i
  * energies whose transverse part gives the growth rates of Sec. 3 and whose
  * total Sec. 4 tracks, the beam's kinetic energy, and the Gauss-law residual
  * that the current-conserving deposit keeps at rounding level.
- * Synchronises the stream.  Returns PIC_ENONFINITE or PIC_EPARTICLE when the
- * corresponding flag is set (out is filled in either case). */
+ * Synchronises the stream.  Returns PIC_ENONFINITE, PIC_EPARTICLE or PIC_ERANGE
+ * when the corresponding flag is set (out is filled in either case). */
 int pic_diag(pic_state *st, int inst, pic_diag_t *out);
 
 /* Per-step transverse and total field energies recorded since pic_init when

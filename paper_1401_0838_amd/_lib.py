@@ -20,6 +20,7 @@ PIC_ENONFINITE = -6
 PIC_EPARTICLE = -7
 PIC_EUNSUPPORTED = -8
 PIC_ESTATE = -9
+PIC_ERANGE = -10
 
 PIC_GALERKIN, PIC_UNIFORM, PIC_MOMENTUM = 0, 1, 2
 PIC_YEE, PIC_CK = 0, 1
@@ -55,7 +56,7 @@ class pic_diag_t(C.Structure):
                 ("gauss_l2", C.c_double), ("gauss_linf", C.c_double), ("charge", C.c_double),
                 ("rho_max", C.c_double), ("n_particles", C.c_int64), ("step", C.c_int64),
                 ("nonfinite", C.c_int), ("particle_error", C.c_int), ("resorts", C.c_int),
-                ("slow_tiles", C.c_int)]
+                ("slow_tiles", C.c_int), ("current_range", C.c_int)]
 
 
 class pic_timing_t(C.Structure):
@@ -78,6 +79,7 @@ _SIGS = {
     "pic_init": (C.c_int, [C.POINTER(pic_config), C.c_int, C.POINTER(pic_particles), C.c_void_p,
                            C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
     "pic_step": (C.c_int, [C.c_void_p, C.c_int]),
+    "pic_prepare": (C.c_int, [C.c_void_p, C.c_int]),
     "pic_set_option": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int]),
     "pic_get_option": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int)]),
     "pic_set_schedule": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
@@ -168,6 +170,10 @@ def pic_init(cfgs, parts, arena_ptr, arena_bytes, stream_ptr):
 
 def pic_step(st, nsteps):
     return check(load().pic_step(st, int(nsteps)), "pic_step")
+
+
+def pic_prepare(st, nsteps):
+    return check(load().pic_prepare(st, int(nsteps)), "pic_prepare")
 
 
 def pic_set_option(st, name, value):

@@ -11,9 +11,16 @@ namespace pic {
 
 // ------------------------------------------------------------------ helpers
 
+// current accumulator in LDS (JOf) and current planes in HBM (JGOf): in float
+// mode a tile sums its particles' contributions in 64-bit fixed point and adds
+// the sums, rounded to a coarser 32-bit fixed point, to HBM; integer sums do
+// not depend on the order of the adds, so float runs are bitwise reproducible
 template <class R> struct JOf;
 template <> struct JOf<float> { typedef long long T; };   // 64-bit fixed point
 template <> struct JOf<double> { typedef double T; };
+template <class R> struct JGOf;
+template <> struct JGOf<float> { typedef int T; };        // 32-bit fixed point
+template <> struct JGOf<double> { typedef double T; };
 
 __device__ __forceinline__ int wrapi(int i, int n)
 {
@@ -40,6 +47,7 @@ __device__ __forceinline__ long long jcvt(float v, long long *) { return (long l
 __device__ __forceinline__ double jcvt(double v, double *) { return v; }
 
 __device__ __forceinline__ double jreal(long long v, double q) { return (double)v * q; }
+__device__ __forceinline__ double jreal(int v, double q) { return (double)v * q; }
 __device__ __forceinline__ double jreal(double v, double) { return v; }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -104,6 +112,17 @@ template <class R> struct Shape<3, R> {
     }
 };
 
+// Workgroup barrier for LDS traffic only: waits for the wave's own LDS
+// operations (lgkmcnt 0, vmcnt and expcnt left at their maxima) and meets the
+// other waves at s_barrier.  Unlike __syncthreads() it does not wait for
+// outstanding global loads, so loads issued for a later tile stay in flight
+// across it; only for kernels whose threads share data through LDS alone.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_s_barrier();
+}
+
 // Index of the calling wave in its block.  threadIdx.x >> 6 is the same on
 // every lane of a wave, but the compiler does not know it; read from the first
 // lane it is a scalar, and the row and address arithmetic that depends only on
@@ -133,6 +152,10 @@ __device__ __forceinline__ void gatomic_add(gp<long long> p, long long v)
     __hip_atomic_fetch_add((gp<unsigned long long>)p, (unsigned long long)v, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void gatomic_add(gp<int> p, int v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ void gatomic_add(gp<double> p, double v)
 {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -141,6 +164,29 @@ __device__ __forceinline__ void gatomic_add(gp<float> p, float v)
 {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// Add a fixed-point current sum v (LDS quantum) to an HBM current word whose
+// quantum is 2^s coarser: v is rounded to the nearest HBM quantum (ties up).
+// Returns true when the sum or the word's new value leaves the 32-bit range
+// (the add is then skipped or wraps, and the caller flags the instance).
+__device__ __forceinline__ bool jflush(gp<int> p, long long v, int s)
+{
+    const long long r = (v + (s > 0 ? (1LL << (s - 1)) : 0)) >> s;
+    if (r == 0) return false;
+    if (r > INT_MAX || r < INT_MIN) return true;
+    const int old = __hip_atomic_fetch_add(p, (int)r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long nw = (long long)old + r;
+    return nw > INT_MAX || nw < INT_MIN;
+}
+__device__ __forceinline__ bool jflush(gp<double> p, double v, int)
+{
+    gatomic_add(p, v);
+    return false;
+}
+
+// a float-mode current word outside +-2^30: the sum it holds may have wrapped
+__device__ __forceinline__ bool jrange_bad(int v) { return (unsigned)v + (1u << 30) >= (1u << 31); }
+__device__ __forceinline__ bool jrange_bad(double) { return false; }
 
 // ------------------------------------------------------------ LDS staging
 // For c in [0, n) and k < K:  dst[k * dpitch + dix(c)] = cv(k, src[k][addr(c)]).
@@ -181,6 +227,13 @@ struct IdentityIx {
 struct PlainCv {
     template <class T> __device__ __forceinline__ T operator()(int, T v) const { return v; }
 };
+
+// periodic index by a remainder: no branch, for any g > -n * 2^20
+__device__ __forceinline__ int pmod(int g, int n)
+{
+    const int r = (g + (n << 20)) % n;
+    return r;
+}
 
 // periodic index for g in [-n, 2n) (one compare each way), else a modulo
 __device__ __forceinline__ int wrap_near(int g, int n)
@@ -305,17 +358,25 @@ template <class R, class JT, int P> struct LdsWinP {
     __device__ __forceinline__ void add(int comp, int x, int y, int z, JT v) { jadd(&J[comp * wc + at(x, y, z)], v); }
 };
 
+// fields and current straight in global memory (a tile whose particles
+// outgrew the LDS window): each contribution goes to the HBM current on its own
 template <class R, class JT> struct GlbWin {
+    typedef typename JGOf<R>::T JG;
     gp<const R> F[6];
-    gp<JT> J[3];
+    gp<JG> J[3];
     int o[3], n[3];
+    int shift;          // LDS -> HBM quantum shift (float mode)
+    bool ovf;           // some add left the 32-bit range
     __device__ __forceinline__ int at(int x, int y, int z) const
     {
         int gx = (o[0] + x) % n[0], gy = (o[1] + y) % n[1], gz = (o[2] + z) % n[2];
         return (gz * n[1] + gy) * n[0] + gx;
     }
     __device__ __forceinline__ R f(int comp, int x, int y, int z) const { return F[comp][at(x, y, z)]; }
-    __device__ __forceinline__ void add(int comp, int x, int y, int z, JT v) { gatomic_add(J[comp] + at(x, y, z), v); }
+    __device__ __forceinline__ void add(int comp, int x, int y, int z, JT v)
+    {
+        if (jflush(J[comp] + at(x, y, z), v, shift)) ovf = true;
+    }
 };
 
 

@@ -8,7 +8,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "pic_api.h"
@@ -217,8 +219,10 @@ struct pic_state {
     int yee_tz = 8, seen_tz = 16;    // 2D field-kernel tile heights (tunable)
     int waves4 = 0;                  // particle kernel capped at four waves per SIMD (tunable)
     int prefetch = 0;                // particle kernel loads one particle ahead (tunable)
-    // captured graphs, one per parity of the state they start from
-    hipGraphExec_t gexec_k[2] = {nullptr, nullptr}, gexec_1[2] = {nullptr, nullptr};
+    // captured step graphs keyed by (steps, re-sort check at the end, parity of
+    // the state they start from); a pic_step call replays at most three kinds:
+    // a head up to the next re-sort point, whole periods, and a tail
+    std::map<std::tuple<int, int, int>, hipGraphExec_t> gexec;
     int parity = 0;                  // which set of E, B, J planes is current
     long long step = 0;
     int *trace_pos = nullptr;
@@ -292,6 +296,8 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
     Layout L;
     L.base = base;
     const size_t R = cfgs[0].precision == PIC_FP32 ? 4 : 8;
+    // current planes: 32-bit fixed point in float mode, double otherwise
+    const size_t JB = cfgs[0].precision == PIC_FP32 ? 4 : 8;
     InstDesc *dd = L.take<InstDesc>(n_inst);
     if (s) s->d_desc = dd;
     size_t nf = 0, npw = 0, nc = 0, ns = 0, ny = 0;
@@ -344,7 +350,7 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
         for (int q = 0; q < 2; q++) {
             for (int k = 0; k < 3; k++) pe[q][k] = plane(R);
             for (int k = 0; k < 3; k++) pb[q][k] = plane(R);
-            for (int k = 0; k < 3; k++) pj[q][k] = plane(8);
+            for (int k = 0; k < 3; k++) pj[q][k] = plane(JB);
         }
         for (int k = 0; k < 3; k++) pet[k] = plane(R);
         for (int k = 0; k < 3; k++) pbt[k] = plane(R);
@@ -397,7 +403,7 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
                 for (int k = 0; k < 3; k++) sn.E[k] = plane(R);
                 for (int k = 0; k < 3; k++) sn.B[k] = plane(R);
                 if (with_j)
-                    for (int k = 0; k < 3; k++) sn.J[k] = plane(8);
+                    for (int k = 0; k < 3; k++) sn.J[k] = plane(JB);
                 sn.pidx = L.take<int>(n);
                 for (int a = 0; a < 3; a++)
                     if (!(c.dims == 2 && a == 1)) sn.poff[a] = L.take<char>(n * R);
@@ -446,6 +452,29 @@ void fill_desc(InstDesc &D, const pic_config &c, const pic_particles &p)
     double U = std::fabs(qw) / D.dV;
     for (int a = 0; a < 3; a++) U = std::max(U, std::fabs(qw) * D.d[a] / (c.cdt * D.dV));
     D.jq = (f32 && U > 0) ? U * std::ldexp(1.0, -28) : 1.0;
+    // HBM planes (float mode): the quantum is about 2^-21 of the current a
+    // beam moving at c carries through the densest cell of the initial load,
+    // J_s = kmax |q w| / dV, so a current word holds at least 2^9 J_s inside the
+    // checked range +-2^30 (beyond it the instance is flagged); a tile's LDS sum
+    // is rounded to it once per step
+    D.jshift = 0;
+    if (f32 && U > 0) {
+        std::vector<int> cnt((size_t)D.ncell, 0);
+        int kmax = 0;
+        for (int64_t i = 0; i < p.n; i++) {
+            long long cell = 0;
+            for (int a = 2; a >= 0; a--) {
+                if (c.dims == 2 && a == 1) continue;
+                long long ci = (long long)std::floor(p.pos[a][i] / D.d[a]) % D.n[a];
+                ci += ci < 0 ? D.n[a] : 0;
+                cell = cell * D.n[a] + ci;
+            }
+            kmax = std::max(kmax, ++cnt[(size_t)cell]);
+        }
+        const double js = kmax * std::fabs(qw) / D.dV;
+        if (js > 0) D.jshift = std::min(24, std::max(0, (int)std::floor(std::log2(js / U * 128.0))));
+    }
+    D.jqg = D.jq * std::ldexp(1.0, D.jshift);
     const double sc = f32 ? 1.0 / D.jq : 1.0;
     for (int a = 0; a < 3; a++) D.cdep[a] = -qw * D.d[a] / (c.cdt * D.dV) * sc;
     D.cy2d = qw / D.dV * sc;
@@ -622,7 +651,10 @@ size_t region_fields(const InstDesc &D, size_t R)
 {
     return (size_t)((char *)D.B[0][2] - (char *)D.E[0][0]) + D.ncell * R;
 }
-size_t region_j(const InstDesc &D) { return (size_t)((char *)D.J[0][2] - (char *)D.J[0][0]) + (size_t)D.ncell * 8; }
+size_t region_j(const InstDesc &D, size_t jb)
+{
+    return (size_t)((char *)D.J[0][2] - (char *)D.J[0][0]) + (size_t)D.ncell * jb;
+}
 size_t region_particles(const InstDesc &D, size_t R)
 {
     return (size_t)((char *)D.pu[2] - (char *)D.pidx) + (size_t)D.np * R;
@@ -681,14 +713,19 @@ int build_worklists(pic_state *s)
         for (int t = 0; t < D.ntiles; t++) pw.push_back(make_int2(i, ord[t]));
         q.n = (int)pw.size() - q.off;
         s->prange.push_back(q);
+        // the 2D field tiles in the same XCD-aware order as the particle tiles:
+        // each XCD takes a contiguous run of rows of tiles, so the halo rows a
+        // tile shares with its neighbour along z are read into one L2
         Range sr{(int)sw.size(), 0};
         const int nst = ((D.n[0] + PIC_SEEN_TX - 1) / PIC_SEEN_TX) * ((D.n[2] + stz - 1) / stz);
-        for (int k = 0; k < nst; k++) sw.push_back(make_int2(i, k));
+        tile_order(nst, ord);
+        for (int k = 0; k < nst; k++) sw.push_back(make_int2(i, ord[k]));
         sr.n = (int)sw.size() - sr.off;
         s->srange.push_back(sr);
         Range yr{(int)yw.size(), 0};
         const int nyt = ((D.n[0] + PIC_YEE_TX - 1) / PIC_YEE_TX) * ((D.n[2] + ytz - 1) / ytz);
-        for (int k = 0; k < nyt; k++) yw.push_back(make_int2(i, k));
+        tile_order(nyt, ord);
+        for (int k = 0; k < nyt; k++) yw.push_back(make_int2(i, ord[k]));
         yr.n = (int)yw.size() - yr.off;
         s->yrange.push_back(yr);
         const int nat = ((D.n[0] + PIC_SEEN_TX - 1) / PIC_SEEN_TX) * ((D.n[2] + PIC_ADJ_TZ - 1) / PIC_ADJ_TZ);
@@ -768,11 +805,12 @@ int enqueue_resort(pic_state *s)
 void drop_graphs(pic_state *s)
 {
     for (int q = 0; q < 2; q++) {
-        if (s->gexec_k[q]) { (void)hipGraphExecDestroy(s->gexec_k[q]); s->gexec_k[q] = nullptr; }
-        if (s->gexec_1[q]) { (void)hipGraphExecDestroy(s->gexec_1[q]); s->gexec_1[q] = nullptr; }
+
         if (s->gexec_adj_fwd[q]) { (void)hipGraphExecDestroy(s->gexec_adj_fwd[q]); s->gexec_adj_fwd[q] = nullptr; }
     }
     if (s->gexec_adj_seg) { (void)hipGraphExecDestroy(s->gexec_adj_seg); s->gexec_adj_seg = nullptr; }
+    for (auto &kv : s->gexec) (void)hipGraphExecDestroy(kv.second);
+    s->gexec.clear();
 }
 
 // capture whatever `body` enqueues on the state's stream into an executable graph
@@ -816,8 +854,8 @@ template <class R>
 int copy_plane_out(pic_state *s, const void *src, size_t n, double *host, double scale, bool is_j)
 {
     if (is_j && s->fp32) {
-        std::vector<long long> tmp(n);
-        HIP_TRY(hipMemcpyAsync(tmp.data(), src, n * 8, hipMemcpyDeviceToHost, s->stream));
+        std::vector<int> tmp(n);
+        HIP_TRY(hipMemcpyAsync(tmp.data(), src, n * 4, hipMemcpyDeviceToHost, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
         for (size_t i = 0; i < n; i++) host[i] = (double)tmp[i] * scale;
         return PIC_OK;
@@ -892,6 +930,7 @@ extern "C" const char *pic_strerror(int code)
     case PIC_EPARTICLE: return "particle moved a full cell or more in one step";
     case PIC_EUNSUPPORTED: return "configuration not supported by this library";
     case PIC_ESTATE: return "invalid state";
+    case PIC_ERANGE: return "current outside the fixed-point range of the float-mode current planes";
     }
     return "unknown error";
 }
@@ -1113,7 +1152,8 @@ extern "C" int pic_set_option(pic_state *s, const char *name, int value)
         if (value != 4 && value != 8 && value != 16) return fail(PIC_EINVAL, "yee_tile_z must be 4, 8 or 16");
         s->yee_tz = yee_tz_eff(value, s->fp32);
     } else if (n == "seen_tile_z") {
-        if (value != 8 && value != 16 && value != 32) return fail(PIC_EINVAL, "seen_tile_z must be 8, 16 or 32");
+        if (value != 8 && value != 16 && value != 32 && value != 64)
+            return fail(PIC_EINVAL, "seen_tile_z must be 8, 16, 32 or 64");
         s->seen_tz = seen_tz_eff(value, s->fp32);
     } else if (n == "resort_every") {
         if (value < 1 || value > 1024) return fail(PIC_EINVAL, "resort_every must be in [1, 1024]");
@@ -1130,6 +1170,13 @@ extern "C" int pic_set_option(pic_state *s, const char *name, int value)
     } else if (n == "particle_defer") {
         if (value < -1 || value > 1) return fail(PIC_EINVAL, "particle_defer must be -1, 0 or 1");
         s->defer_mode = value;
+    } else if (n == "current_quantum_shift") {
+        if (!s->fp32 || value < 0 || value > 24 || s->step != 0)
+            return fail(PIC_EINVAL, "current_quantum_shift: float mode, in [0, 24], before the first step");
+        for (InstDesc &d : s->desc) { d.jshift = value; d.jqg = d.jq * std::ldexp(1.0, value); }
+        HIP_TRY(hipMemcpyAsync(s->d_desc, s->desc.data(), s->n_inst * sizeof(InstDesc), hipMemcpyHostToDevice,
+                               s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
     } else {
         return fail(PIC_EINVAL, "unknown option " + n);
     }
@@ -1148,9 +1195,52 @@ extern "C" int pic_get_option(pic_state *s, const char *name, int *value)
     else if (n == "particle_waves4") *value = s->waves4;
     else if (n == "particle_prefetch") *value = s->prefetch;
     else if (n == "particle_defer") *value = s->defer_mode;
+    else if (n == "current_quantum_shift") *value = s->desc.empty() ? 0 : s->desc[0].jshift;
     else return fail(PIC_EINVAL, "unknown option " + n);
     return PIC_OK;
 }
+
+namespace {
+
+// The pieces a graph-replayed run of nsteps from the current state is made
+// of: steps up to the next multiple of the re-sort period (with the re-sort
+// check at its end when it gets there), whole periods (each ending with the
+// check), and the remaining steps.  Eager stepping checks at the same steps;
+// no check while re-sorting is suspended (between the adjoint calls).
+struct Piece { int len, resort; };
+std::vector<Piece> plan_run(const pic_state *s, int nsteps)
+{
+    std::vector<Piece> out;
+    long long step = s->step;
+    int n = 0;
+    while (n < nsteps) {
+        const int to_check = s->graph_k - (int)(step % s->graph_k);
+        const int len = std::min(to_check, nsteps - n);
+        out.push_back(Piece{len, (len == to_check && !s->no_resort) ? 1 : 0});
+        step += len;
+        n += len;
+    }
+    return out;
+}
+
+// the graph of one piece starting from parity q, captured on first use
+int piece_graph(pic_state *s, const Piece &p, int q, hipGraphExec_t *out)
+{
+    const auto key = std::make_tuple(p.len, p.resort, q);
+    auto it = s->gexec.find(key);
+    if (it != s->gexec.end()) { *out = it->second; return PIC_OK; }
+    const int par0 = s->parity;
+    s->parity = q;
+    hipGraphExec_t g = nullptr;
+    const int rc = capture(s, p.len, p.resort != 0, &g);
+    s->parity = par0;
+    if (rc) return rc;
+    s->gexec[key] = g;
+    *out = g;
+    return PIC_OK;
+}
+
+}  // namespace
 
 extern "C" int pic_step(pic_state *s, int nsteps)
 {
@@ -1164,33 +1254,26 @@ extern "C" int pic_step(pic_state *s, int nsteps)
         }
         return PIC_OK;
     }
-    auto one = [&]() -> int {
-        const int q = s->parity;
-        int r;
-        if (!s->gexec_1[q] && (r = capture(s, 1, false, &s->gexec_1[q]))) return r;
-        HIP_TRY(hipGraphLaunch(s->gexec_1[q], s->stream));
-        s->parity ^= 1;
-        s->step++;
-        return PIC_OK;
-    };
-    int n = 0;
-    // single steps until the step count is a multiple of the graph length, then whole graphs
-    while (n < nsteps && (s->step % s->graph_k) != 0) {
-        if ((rc = one())) return rc;
-        n++;
-        if (s->step % s->graph_k == 0 && (rc = enqueue_resort(s))) return rc;
+    for (const Piece &p : plan_run(s, nsteps)) {
+        hipGraphExec_t g = nullptr;
+        if ((rc = piece_graph(s, p, s->parity, &g))) return rc;
+        HIP_TRY(hipGraphLaunch(g, s->stream));
+        s->parity ^= p.len & 1;
+        s->step += p.len;
     }
-    while (nsteps - n >= s->graph_k) {
-        const int q = s->parity;
-        if (!s->gexec_k[q] && (rc = capture(s, s->graph_k, true, &s->gexec_k[q]))) return rc;
-        HIP_TRY(hipGraphLaunch(s->gexec_k[q], s->stream));
-        s->parity ^= s->graph_k & 1;
-        s->step += s->graph_k;
-        n += s->graph_k;
-    }
-    while (n < nsteps) {
-        if ((rc = one())) return rc;
-        n++;
+    return PIC_OK;
+}
+
+extern "C" int pic_prepare(pic_state *s, int nsteps)
+{
+    if (!s || nsteps < 0) return fail(PIC_EINVAL, "pic_prepare");
+    if (!s->use_graph) return PIC_OK;
+    int q = s->parity;
+    for (const Piece &p : plan_run(s, nsteps)) {
+        hipGraphExec_t g = nullptr;
+        const int rc = piece_graph(s, p, q, &g);
+        if (rc) return rc;
+        q ^= p.len & 1;
     }
     return PIC_OK;
 }
@@ -1224,8 +1307,8 @@ extern "C" int pic_fields(pic_state *s, int inst, int which, int comp, double *h
         HIP_TRY(hipStreamSynchronize(s->stream));
         return PIC_OK;
     }
-    return s->fp32 ? copy_plane_out<float>(s, src, n, host, D.jq, is_j)
-                   : copy_plane_out<double>(s, src, n, host, D.jq, is_j);
+    return s->fp32 ? copy_plane_out<float>(s, src, n, host, D.jqg, is_j)
+                   : copy_plane_out<double>(s, src, n, host, D.jqg, is_j);
 }
 
 extern "C" int pic_get_particles(pic_state *s, int inst, double *pos[3], double *mom[3], int64_t n)
@@ -1264,8 +1347,10 @@ extern "C" int pic_diag(pic_state *s, int inst, pic_diag_t *out)
     out->particle_error = fl[FLAG_PERR] ? 1 : 0;
     out->resorts = fl[FLAG_NRESORT];
     out->slow_tiles = fl[FLAG_SLOW];
+    out->current_range = fl[FLAG_JRANGE] ? 1 : 0;
     if (out->nonfinite) return fail(PIC_ENONFINITE, "non-finite value found");
     if (out->particle_error) return fail(PIC_EPARTICLE, "particle moved a full cell");
+    if (out->current_range) return fail(PIC_ERANGE, "current outside the 32-bit fixed-point range");
     return PIC_OK;
 }
 
@@ -1345,7 +1430,7 @@ int snap_copy(pic_state *s, int inst, const Snap &sn, bool save, bool with_j)
         return save ? hipMemcpyAsync(snapp, live, bytes, kd, s->stream) : hipMemcpyAsync(live, snapp, bytes, kd, s->stream);
     };
     HIP_TRY(cp(D.E[q][0], sn.E[0], region_fields(D, R)));
-    if (with_j) HIP_TRY(cp(D.J[q][0], sn.J[0], region_j(D)));
+    if (with_j) HIP_TRY(cp(D.J[q][0], sn.J[0], region_j(D, s->fp32 ? 4 : 8)));
     return snap_copy_particles(s, inst, sn, save);
 }
 

@@ -13,7 +13,8 @@
 #define PIC_COL_RUN 16          // cells per thread along the axis of a 3D column stencil pass
 
 // device flag slots (per instance)
-enum { FLAG_RESORT = 0, FLAG_PERR = 1, FLAG_SLOW = 2, FLAG_NRESORT = 3, FLAG_COUNT = 8 };
+// FLAG_JRANGE: a current sum left the 32-bit fixed-point range of the HBM planes (float mode)
+enum { FLAG_RESORT = 0, FLAG_PERR = 1, FLAG_SLOW = 2, FLAG_NRESORT = 3, FLAG_JRANGE = 4, FLAG_COUNT = 8 };
 
 // per-instance diagnostic accumulator slots (doubles)
 enum {
@@ -44,7 +45,9 @@ struct InstDesc {
     double w, m;           // weight, mass
     double dV;
     double jbg[3];         // uniform background current
-    double jq;             // fixed-point quantum of J (float mode): J = int * jq
+    double jq;             // fixed-point quantum of the LDS current sums (float mode): J = int64 * jq
+    double jqg;            // quantum of the HBM current planes (float mode): J = int32 * jqg, jqg = jq * 2^jshift
+    int jshift;            // float mode: bits the LDS sums are rounded off by when they go to HBM (0 in double)
     double cdep[3];        // Esirkepov factors -q w d_a / (dt dV) (times 1/jq in float mode)
     double cy2d;           // q w / dV (times 1/jq in float mode): J_y = cy2d * v_y * W_y in 2D
     double rho_c;          // q w / dV for the charge density

@@ -20,6 +20,7 @@
 //              the Gauss-law residual
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <climits>
 
@@ -352,6 +353,7 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
                                                int nwork, int wmx, int wmy, int wmz, int par)
 {
     typedef typename JOf<R>::T JT;
+    typedef typename JGOf<R>::T JG;
     constexpr int JL = (L + 1) / 2;      // guard cells below the bounding box
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sbox[6];
@@ -360,7 +362,12 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
     // the deferred list is shared by all instances; its count was final when
     // the deferring launch ended
     const int *dfr = Dt[0].defer;
-    if constexpr (SLOW) nwork = __hip_atomic_load(const_cast<int *>(dfr), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if constexpr (SLOW) {
+        nwork = __hip_atomic_load(const_cast<int *>(dfr), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // nothing deferred (the usual case): the list is already empty, so no
+        // block needs to count itself done
+        if (nwork == 0) return;
+    }
 
     for (int item = blockIdx.x; item < nwork; item += gridDim.x) {
         // work == nullptr: one instance, slot -> tile in the host's XCD order
@@ -448,14 +455,16 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
         LdsWin<R, JT> lw{sF, sJ, pitch, pitch * wn[1], wc};
         LdsWinP<R, JT, (P > 0 ? P : 1)> lwp{sF, sJ};
         GlbWin<R, JT> gw;
+        gw.ovf = false;
         if (SLOW || (MODE == PM_INLINE && !fits)) {
             for (int k = 0; k < 3; k++) {
                 gw.F[k] = G<R>((const void *)D.Et[k]);
                 gw.F[3 + k] = G<R>((const void *)D.Bt[k]);
-                gw.J[k] = G<JT>(D.J[par][k]);
+                gw.J[k] = G<JG>(D.J[par][k]);
                 gw.o[k] = o[k];
                 gw.n[k] = D.n[k];
             }
+            gw.shift = D.jshift;
         }
 
         // with PF, software pipelining: the next particle's state is loaded
@@ -543,6 +552,7 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
             *lane_ptr(pidx, s4) = pack_cell<DIM>(nc[0], nc[1], nc[2]);
         }
         if (err) atomicExch(&D.flags[FLAG_PERR], 1);
+        if (gw.ovf) atomicExch(&D.flags[FLAG_JRANGE], 1);
         // bounding box of the moved particles (window-local coordinates)
 #pragma unroll
         for (int a = 0; a < 3; a++) {
@@ -551,15 +561,41 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
         }
         __syncthreads();
         if (fits) {
-            gp<JT> gJ[3] = {G<JT>(D.J[par][0]), G<JT>(D.J[par][1]), G<JT>(D.J[par][2])};
+            // the window's sums go to HBM (rounded to its coarser quantum in float mode)
+            gp<JG> gJ[3] = {G<JG>(D.J[par][0]), G<JG>(D.J[par][1]), G<JG>(D.J[par][2])};
             const int nwin = wn[0] * wn[1] * wn[2];
-            for (int c = tid; c < nwin; c += bs) {
-                const int g = window_cell(c, wn, o, D.n);
-                const int l = P > 0 ? (c / wn[0]) * P + c % wn[0] : c;
+            if constexpr (sizeof(JG) == 4) {
+                // Adds that return nothing (a returning add would make every
+                // thread wait for it).  Range check in two parts: a rounded window
+                // sum must stay below BND in magnitude (else it is dropped and flagged),
+                // and the Yee update, which reads every current word, flags a word
+                // outside +-2^30.  At most nine windows (27 in 3D) cover a node, so
+                // a word that wrapped past 32 bits lands outside +-2^30.
+                const int js = D.jshift;
+                const long long half = js > 0 ? (1LL << (js - 1)) : 0;
+                constexpr long long BND = DIM == 2 ? (1LL << 28) : (1LL << 26);
+                bool ovf = false;
+                for (int c = tid; c < nwin; c += bs) {
+                    const int g = window_cell(c, wn, o, D.n);
+                    const int l = P > 0 ? (c / wn[0]) * P + c % wn[0] : c;
 #pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    JT v = sJ[k * wc + l];
-                    if (v != JT(0)) gatomic_add(gJ[k] + g, v);
+                    for (int k = 0; k < 3; k++) {
+                        const long long r = (sJ[k * wc + l] + half) >> js;
+                        const bool big = r >= BND || r <= -BND;
+                        ovf |= big;
+                        if (r != 0 && !big) gatomic_add(gJ[k] + g, (int)r);
+                    }
+                }
+                if (ovf) atomicExch(&D.flags[FLAG_JRANGE], 1);
+            } else {
+                for (int c = tid; c < nwin; c += bs) {
+                    const int g = window_cell(c, wn, o, D.n);
+                    const int l = P > 0 ? (c / wn[0]) * P + c % wn[0] : c;
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        JT v = sJ[k * wc + l];
+                        if (v != JT(0)) gatomic_add(gJ[k] + g, v);
+                    }
                 }
             }
         }
@@ -669,7 +705,7 @@ template <int DIM, class R>
 __global__ void __launch_bounds__(256) k_yee_e(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int pi,
                                                int po)
 {
-    typedef typename JOf<R>::T JT;
+    typedef typename JGOf<R>::T JG;
     const int inst = work[blockIdx.x].x;
     const InstDesc &D = Dt[inst];
     const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
@@ -682,7 +718,7 @@ __global__ void __launch_bounds__(256) k_yee_e(const InstDesc *__restrict__ Dt, 
     const R *Bx = (const R *)D.B[po][0], *By = (const R *)D.B[po][1], *Bz = (const R *)D.B[po][2];
     const R *Eix = (const R *)D.E[pi][0], *Eiy = (const R *)D.E[pi][1], *Eiz = (const R *)D.E[pi][2];
     R *Ex = (R *)D.E[po][0], *Ey = (R *)D.E[po][1], *Ez = (R *)D.E[po][2];
-    const JT *J0 = (const JT *)D.J[pi][0], *J1 = (const JT *)D.J[pi][1], *J2 = (const JT *)D.J[pi][2];
+    const JG *J0 = (const JG *)D.J[pi][0], *J1 = (const JG *)D.J[pi][1], *J2 = (const JG *)D.J[pi][2];
     const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2];
     const R dt = (R)D.dt;
     const R bx = Bx[cell], by = By[cell], bz = Bz[cell];
@@ -695,20 +731,21 @@ __global__ void __launch_bounds__(256) k_yee_e(const InstDesc *__restrict__ Dt, 
     }
     const R dzBy = (by - By[km]) * idz, dzBx = (bx - Bx[km]) * idz;
     const R dxBz = (bz - Bz[im]) * idx, dxBy = (by - By[im]) * idx;
-    const R jx = (R)(jreal(J0[cell], D.jq) + D.jbg[0]);
-    const R jy = (R)(jreal(J1[cell], D.jq) + D.jbg[1]);
-    const R jz = (R)(jreal(J2[cell], D.jq) + D.jbg[2]);
+    const R jx = (R)(jreal(J0[cell], D.jqg) + D.jbg[0]);
+    const R jy = (R)(jreal(J1[cell], D.jqg) + D.jbg[1]);
+    const R jz = (R)(jreal(J2[cell], D.jqg) + D.jbg[2]);
+    if (jrange_bad(J0[cell]) | jrange_bad(J1[cell]) | jrange_bad(J2[cell])) atomicExch(&D.flags[FLAG_JRANGE], 1);
     Ex[cell] = Eix[cell] + dt * (dyBz - dzBy - jx);
     Ey[cell] = Eiy[cell] + dt * (dzBx - dxBz - jy);
     Ez[cell] = Eiz[cell] + dt * (dxBy - dyBx - jz);
 #pragma unroll
-    for (int c = 0; c < 3; c++) ((JT *)D.J[po][c])[cell] = JT(0);
+    for (int c = 0; c < 3; c++) ((JG *)D.J[po][c])[cell] = JG(0);
 }
 
 // Fused 2D Yee update: B half step, E step (J read and cleared), B half step
 // for a (YEE_TX x TZ) tile in one pass.  LDS windows, in global coordinates
 // relative to the tile origin (x0, z0):
-//   E^{n-1} on [-1, T+1], B^{n-1} on [-1, T], J on [0, T]
+//   E^{n-1} on [-1, T+1], B^{n-1} on [-1, T]; J on [0, T] in registers
 // B^{n-1/2} is formed on [-1, T], E^n on [0, T], B^n and the stores on [0, T).
 // CK: the Cole-Karkkainen curl in Faraday's law (2D, square cells): each
 // forward difference of E is the (1/8, 3/4, 1/8) mean of that difference on
@@ -718,135 +755,202 @@ __global__ void __launch_bounds__(256) k_yee_e(const InstDesc *__restrict__ Dt, 
 #define YEE_TX PIC_YEE_TX
 
 template <class R, int TZ, bool CK = false>
-__global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int par)
+__global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                                int nwork, int par)
 {
-    typedef typename JOf<R>::T JT;
+    typedef typename JGOf<R>::T JT;
     constexpr int TX = YEE_TX;
     static_assert(TX == 64, "one lane per column");
-    // one window for all nine planes: cells [x0 - LO, x0 + TX + 2) x [z0 - LO, z0 + TZ + 2);
-    // waves own rows, lanes own columns (lane, and 64 + lane for the last few)
+    // one window for all nine planes: cells [x0 - LO, x0 + TX + 2) x [z0 - LO, z0 + TZ + 2)
     constexpr int LO = CK ? 3 : 1;
     constexpr int WX = TX + LO + 2, WZ = TZ + LO + 2, WN = WX * WZ;
     // local ranges: B^{n-1/2} on [ELO - 1, EH), E^n on [ELO, EH), the tile on [LO, T + LO)
     constexpr int ELO = CK ? LO - 1 : LO;
     constexpr int EHZ = TZ + LO + 1, EHX = TX + LO + 1;
-    __shared__ R sE[3][WN], sB[3][WN], sJ[3][WN];
-    // work == nullptr: one instance, block b is tile b (saves a dependent load)
-    const int inst = work ? work[blockIdx.x].x : 0, t = work ? work[blockIdx.x].y : (int)blockIdx.x;
-    const InstDesc &D = Dt[inst];
-    const int nx = D.n[0], nz = D.n[2];
-    const int ntx = (nx + TX - 1) / TX;
-    const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
-    const int lane = threadIdx.x & 63, wave = wave_id(), nwave = blockDim.x >> 6;
-    const gp<const R> E[3] = {G<R>((const void *)D.E[par][0]), G<R>((const void *)D.E[par][1]),
-                              G<R>((const void *)D.E[par][2])};
-    const gp<const R> B[3] = {G<R>((const void *)D.B[par][0]), G<R>((const void *)D.B[par][1]),
-                              G<R>((const void *)D.B[par][2])};
-    const gp<const JT> J[3] = {G<JT>((const void *)D.J[par][0]), G<JT>((const void *)D.J[par][1]),
-                               G<JT>((const void *)D.J[par][2])};
-    // E, B and J are read with halos that neighbouring tiles own, so the new
-    // fields go to the other set of planes (E then B), and that set's J is cleared
-    const int po = par ^ 1;
-    gp<R> O[6] = {G<R>(D.E[po][0]), G<R>(D.E[po][1]), G<R>(D.E[po][2]),
-                  G<R>(D.B[po][0]), G<R>(D.B[po][1]), G<R>(D.B[po][2])};
-    const double jq = D.jq, jb[3] = {D.jbg[0], D.jbg[1], D.jbg[2]};
-    const bool hasb = lane < WX - TX;
-    const int gxa = wrap_near(x0 - LO + lane, nx);
-    const int gxb = hasb ? wrap_near(x0 - LO + TX + lane, nx) : gxa;
+    // Staging: wave w stages rows w, w + 4, ... of the window's first 64 columns
+    // (lane = column; one round: four waves), and the block's first NH threads
+    // stage the NHX columns past them, one (row, column) cell each.  J enters
+    // only the E step, at the cell itself, so it stays in the staging threads'
+    // registers and the same threads form E^n on the cells they staged: no LDS
+    // for J.  A wave keeps at most 9 (RW + 1) loads in flight per item, within
+    // what its load counter tracks, so the waits below are exact.
     constexpr int RW = (WZ + 3) / 4;   // rows per wave with four waves
-    for (int r0 = wave; r0 < WZ; r0 += RW * nwave) {
-        R ve[RW][2][3], vb[RW][2][3];
-        JT vj[RW][2][3];
+    static_assert(RW * 4 >= WZ, "one staging round");
+    constexpr int NHX = WX - TX, NH = NHX * WZ;
+    static_assert(NH <= 256, "one halo cell per thread");
+    // 64 spare words per plane after the window: a lane with no cell to stage
+    // stores into its own spare word, so the staging stores have no branches (a
+    // branch there makes the compiler wait for every outstanding load,
+    // including the next item's)
+    __shared__ R sE[3][WN + 64], sB[3][WN + 64];
+    const int lane = threadIdx.x & 63, wave = wave_id(), nwave = blockDim.x >> 6;
+    const int tid = threadIdx.x;
+    const bool hth = tid < NH;                 // this thread stages a halo cell
+    const int hrow = hth ? tid / NHX : 0, hcol = TX + (hth ? tid % NHX : 0);
+    // One block per item (tile).  Threads share data through LDS only, so the
+    // barriers are LDS-only (no wait for outstanding global memory operations).
+    // work == nullptr: one instance, item b is tile b in the host's XCD order
+    // (saves a dependent load)
+    auto tile_of = [&](int item, int &inst, int &t) {
+        inst = work ? work[item].x : 0;
+        t = work ? work[item].y : xcd_tile(item, nwork);
+    };
+    R ve[RW][3], vb[RW][3], he[3], hb[3];
+    // E, B of an item's window into ve, vb (columns 0..63) and he, hb (halo cell)
+    auto load_eb = [&](int item) {
+        int inst, t;
+        tile_of(item, inst, t);
+        const InstDesc &D = Dt[inst];
+        const int nx = D.n[0], nz = D.n[2];
+        const int ntx = (nx + TX - 1) / TX;
+        const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
+        const gp<const R> E[3] = {G<R>((const void *)D.E[par][0]), G<R>((const void *)D.E[par][1]),
+                                  G<R>((const void *)D.E[par][2])};
+        const gp<const R> B[3] = {G<R>((const void *)D.B[par][0]), G<R>((const void *)D.B[par][1]),
+                                  G<R>((const void *)D.B[par][2])};
+        // branch-free addresses (a branch between the loads and their use costs
+        // exact waits); the row of a wave is uniform, so its wrap is scalar
+        const int gxa = pmod(x0 - LO + lane, nx);
 #pragma unroll
         for (int u = 0; u < RW; u++) {
-            const int row = min(r0 + u * nwave, WZ - 1);
-            const int base = wrap_near(z0 - LO + row, nz) * nx;
+            const int zr = __builtin_amdgcn_readfirstlane(pmod(z0 - LO + min(wave + u * nwave, WZ - 1), nz));
+            const int g = zr * nx + gxa;
 #pragma unroll
-            for (int h = 0; h < 2; h++) {
-                const int g = base + (h ? gxb : gxa);
-#pragma unroll
-                for (int k = 0; k < 3; k++) { ve[u][h][k] = E[k][g]; vb[u][h][k] = B[k][g]; vj[u][h][k] = J[k][g]; }
-            }
+            for (int k = 0; k < 3; k++) { ve[u][k] = E[k][g]; vb[u][k] = B[k][g]; }
         }
+        const int gh = pmod(z0 - LO + hrow, nz) * nx + pmod(x0 - LO + hcol, nx);
+#pragma unroll
+        for (int k = 0; k < 3; k++) { he[k] = E[k][gh]; hb[k] = B[k][gh]; }
+    };
+    const int item = blockIdx.x;
+    load_eb(item);
+    {
+        int inst, t;
+        tile_of(item, inst, t);
+        const InstDesc &D = Dt[inst];
+        const int nx = D.n[0], nz = D.n[2];
+        const int ntx = (nx + TX - 1) / TX;
+        const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
+        const gp<const JT> J[3] = {G<JT>((const void *)D.J[par][0]), G<JT>((const void *)D.J[par][1]),
+                                   G<JT>((const void *)D.J[par][2])};
+        // E, B and J are read with halos that neighbouring tiles own, so the new
+        // fields go to the other set of planes (E then B), and that set's J is cleared
+        const int po = par ^ 1;
+        gp<R> O[6] = {G<R>(D.E[po][0]), G<R>(D.E[po][1]), G<R>(D.E[po][2]),
+                      G<R>(D.B[po][0]), G<R>(D.B[po][1]), G<R>(D.B[po][2])};
+        const double jq = D.jqg, jb[3] = {D.jbg[0], D.jbg[1], D.jbg[2]};
 #pragma unroll
         for (int u = 0; u < RW; u++) {
-            const int row = r0 + u * nwave;
-            if (row >= WZ) continue;
+            const int row = wave + u * nwave;
+            const int c = row < WZ ? row * WX + lane : WN + lane;
 #pragma unroll
-            for (int h = 0; h < 2; h++) {
-                if (h == 1 && !hasb) continue;
-                const int c = row * WX + (h ? TX : 0) + lane;
+            for (int k = 0; k < 3; k++) { sE[k][c] = ve[u][k]; sB[k][c] = vb[u][k]; }
+        }
+        {
+            const int c = hth ? hrow * WX + hcol : WN + lane;
 #pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    sE[k][c] = ve[u][h][k];
-                    sB[k][c] = vb[u][h][k];
-                    sJ[k][c] = (R)(jreal(vj[u][h][k], jq) + jb[k]);
+            for (int k = 0; k < 3; k++) { sE[k][c] = he[k]; sB[k][c] = hb[k]; }
+        }
+        // J of every staged cell, loaded without a branch (a window cell is always
+        // a valid address; only the cells where E^n is formed use it) after the
+        // LDS stores, so the wait for the staged E, B does not include these;
+        // they are used after the B half step
+        JT vj[RW][3], hj[3];
+        bool jbad = false;
+        {
+            const int gxa = pmod(x0 - LO + lane, nx);
+#pragma unroll
+            for (int u = 0; u < RW; u++) {
+                const int zr = __builtin_amdgcn_readfirstlane(pmod(z0 - LO + min(wave + u * nwave, WZ - 1), nz));
+                const int g = zr * nx + gxa;
+#pragma unroll
+                for (int k = 0; k < 3; k++) vj[u][k] = J[k][g];
+            }
+            const int gh = pmod(z0 - LO + hrow, nz) * nx + pmod(x0 - LO + hcol, nx);
+#pragma unroll
+            for (int k = 0; k < 3; k++) hj[k] = J[k][gh];
+        }
+        lds_barrier();
+        const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
+        // Faraday's forward differences at window cell e: Yee, or averaged across
+        // the difference's direction with (1/8, 3/4, 1/8)
+        auto fdx = [&](const R *F, int e) {
+            if constexpr (CK)
+                return (R(0.75) * (F[e + 1] - F[e]) +
+                        R(0.125) * ((F[e + 1 - WX] - F[e - WX]) + (F[e + 1 + WX] - F[e + WX]))) * idx;
+            else
+                return (F[e + 1] - F[e]) * idx;
+        };
+        auto fdz = [&](const R *F, int e) {
+            if constexpr (CK)
+                return (R(0.75) * (F[e + WX] - F[e]) +
+                        R(0.125) * ((F[e - 1 + WX] - F[e - 1]) + (F[e + 1 + WX] - F[e + 1]))) * idz;
+            else
+                return (F[e + WX] - F[e]) * idz;
+        };
+        // The first halo phase covers a few more columns than the 64 lanes; its
+        // (row, column) cells are dealt out to the block's threads in order, so no
+        // wave runs a second pass for those few columns.
+        // B^{n-1/2} on local rows and columns [ELO - 1, EH): forward differences of E
+        constexpr int C1 = EHX - ELO + 1, N1 = (EHZ - ELO + 1) * C1;
+        for (int it = threadIdx.x; it < N1; it += blockDim.x) {
+            const int e = (ELO - 1 + it / C1) * WX + ELO - 1 + it % C1;
+            const R dzEy = fdz(sE[1], e), dzEx = fdz(sE[0], e);
+            const R dxEz = fdx(sE[2], e), dxEy = fdx(sE[1], e);
+            sB[0][e] -= h * (-dzEy);
+            sB[1][e] -= h * (dzEx - dxEz);
+            sB[2][e] -= h * dxEy;
+        }
+        lds_barrier();
+        // E^n on local [ELO, EH): backward differences of B^{n-1/2}, by the threads
+        // that staged each cell (their J is in registers)
+        auto e_step = [&](int e, const JT *j) {
+            const int exm = e - 1, ezm = e - WX;
+            const R dzBy = (sB[1][e] - sB[1][ezm]) * idz, dzBx = (sB[0][e] - sB[0][ezm]) * idz;
+            const R dxBz = (sB[2][e] - sB[2][exm]) * idx, dxBy = (sB[1][e] - sB[1][exm]) * idx;
+            const R j0 = (R)(jreal(j[0], jq) + jb[0]);
+            const R j1 = (R)(jreal(j[1], jq) + jb[1]);
+            const R j2 = (R)(jreal(j[2], jq) + jb[2]);
+            sE[0][e] += dt * (-dzBy - j0);
+            sE[1][e] += dt * (dzBx - dxBz - j1);
+            sE[2][e] += dt * (dxBy - j2);
+            jbad |= jrange_bad(j[0]) | jrange_bad(j[1]) | jrange_bad(j[2]);
+        };
+#pragma unroll
+        for (int u = 0; u < RW; u++) {
+            const int row = wave + u * nwave;
+            if (row >= ELO && row < EHZ && lane >= ELO) e_step(row * WX + lane, vj[u]);
+        }
+        if (hth && hrow >= ELO && hrow < EHZ && hcol < EHX) e_step(hrow * WX + hcol, hj);
+        // a plain global store (every writer writes 1): an atomic that returns a
+        // value, or a flat store, makes the wave wait for all its loads, the next
+        // item's included
+        if (jbad) G<int>((void *)D.flags)[FLAG_JRANGE] = 1;
+        lds_barrier();
+        // B^n on the tile and the stores (rows unrolled: a loop here would make
+        // the compiler wait for every outstanding load before it)
+        const int gx = x0 + lane;
+        if (gx < nx) {
+#pragma unroll
+            for (int r = 0; r < (TZ + 3) / 4; r++) {
+                const int lz = wave + r * 4;
+                const int gz = z0 + lz;
+                if (lz >= TZ || gz >= nz) continue;
+                const int e = (lz + LO) * WX + lane + LO;
+                const R dzEy = fdz(sE[1], e), dzEx = fdz(sE[0], e);
+                const R dxEz = fdx(sE[2], e), dxEy = fdx(sE[1], e);
+                const int g = gz * nx + gx;
+                const R b0 = sB[0][e] - h * (-dzEy), b1 = sB[1][e] - h * (dzEx - dxEz), b2 = sB[2][e] - h * dxEy;
+                O[3][g] = b0; O[4][g] = b1; O[5][g] = b2;
+                O[0][g] = sE[0][e]; O[1][g] = sE[1][e]; O[2][g] = sE[2][e];
+#pragma unroll
+                for (int k = 0; k < 3; k++) G<JT>(D.J[po][k])[g] = JT(0);
+                if (D.rE[0]) {
+                    // recording a tape slot: E^n, B^n of this step
+                    G<R>(D.rE[0])[g] = sE[0][e]; G<R>(D.rE[1])[g] = sE[1][e]; G<R>(D.rE[2])[g] = sE[2][e];
+                    G<R>(D.rB[0])[g] = b0; G<R>(D.rB[1])[g] = b1; G<R>(D.rB[2])[g] = b2;
                 }
             }
-        }
-    }
-    __syncthreads();
-    const R idx = R(1) / (R)D.d[0], idz = R(1) / (R)D.d[2], dt = (R)D.dt, h = R(0.5) * dt;
-    // Faraday's forward differences at window cell e: Yee, or averaged across
-    // the difference's direction with (1/8, 3/4, 1/8)
-    auto fdx = [&](const R *F, int e) {
-        if constexpr (CK)
-            return (R(0.75) * (F[e + 1] - F[e]) +
-                    R(0.125) * ((F[e + 1 - WX] - F[e - WX]) + (F[e + 1 + WX] - F[e + WX]))) * idx;
-        else
-            return (F[e + 1] - F[e]) * idx;
-    };
-    auto fdz = [&](const R *F, int e) {
-        if constexpr (CK)
-            return (R(0.75) * (F[e + WX] - F[e]) +
-                    R(0.125) * ((F[e - 1 + WX] - F[e - 1]) + (F[e + 1 + WX] - F[e + 1]))) * idz;
-        else
-            return (F[e + WX] - F[e]) * idz;
-    };
-    // The two halo phases cover a few more columns than the 64 lanes; their
-    // (row, column) cells are dealt out to the block's threads in order, so no
-    // wave runs a second pass for those few columns.
-    // B^{n-1/2} on local rows and columns [ELO - 1, EH): forward differences of E
-    constexpr int C1 = EHX - ELO + 1, N1 = (EHZ - ELO + 1) * C1;
-    for (int it = threadIdx.x; it < N1; it += blockDim.x) {
-        const int e = (ELO - 1 + it / C1) * WX + ELO - 1 + it % C1;
-        const R dzEy = fdz(sE[1], e), dzEx = fdz(sE[0], e);
-        const R dxEz = fdx(sE[2], e), dxEy = fdx(sE[1], e);
-        sB[0][e] -= h * (-dzEy);
-        sB[1][e] -= h * (dzEx - dxEz);
-        sB[2][e] -= h * dxEy;
-    }
-    __syncthreads();
-    // E^n on local [ELO, EH): backward differences of B^{n-1/2}
-    constexpr int C2 = EHX - ELO, N2 = (EHZ - ELO) * C2;
-    for (int it = threadIdx.x; it < N2; it += blockDim.x) {
-        const int e = (ELO + it / C2) * WX + ELO + it % C2, exm = e - 1, ezm = e - WX;
-        const R dzBy = (sB[1][e] - sB[1][ezm]) * idz, dzBx = (sB[0][e] - sB[0][ezm]) * idz;
-        const R dxBz = (sB[2][e] - sB[2][exm]) * idx, dxBy = (sB[1][e] - sB[1][exm]) * idx;
-        sE[0][e] += dt * (-dzBy - sJ[0][e]);
-        sE[1][e] += dt * (dzBx - dxBz - sJ[1][e]);
-        sE[2][e] += dt * (dxBy - sJ[2][e]);
-    }
-    __syncthreads();
-    // B^n on the tile and the stores
-    const int gx = x0 + lane;
-    if (gx >= nx) return;
-    for (int lz = wave; lz < TZ; lz += nwave) {
-        const int gz = z0 + lz;
-        if (gz >= nz) break;
-        const int e = (lz + LO) * WX + lane + LO;
-        const R dzEy = fdz(sE[1], e), dzEx = fdz(sE[0], e);
-        const R dxEz = fdx(sE[2], e), dxEy = fdx(sE[1], e);
-        const int g = gz * nx + gx;
-        const R b0 = sB[0][e] - h * (-dzEy), b1 = sB[1][e] - h * (dzEx - dxEz), b2 = sB[2][e] - h * dxEy;
-        O[3][g] = b0; O[4][g] = b1; O[5][g] = b2;
-        O[0][g] = sE[0][e]; O[1][g] = sE[1][e]; O[2][g] = sE[2][e];
-#pragma unroll
-        for (int k = 0; k < 3; k++) G<JT>(D.J[po][k])[g] = JT(0);
-        if (D.rE[0]) {
-            // recording a tape slot: E^n, B^n of this step
-            G<R>(D.rE[0])[g] = sE[0][e]; G<R>(D.rE[1])[g] = sE[1][e]; G<R>(D.rE[2])[g] = sE[2][e];
-            G<R>(D.rB[0])[g] = b0; G<R>(D.rB[1])[g] = b1; G<R>(D.rB[2])[g] = b2;
         }
     }
 }
@@ -986,8 +1090,10 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     static_assert(SEEN_TX == 64, "one lane per column");
     static_assert(SEEN_TZ % 4 == 0, "the four waves split the output rows");
     extern __shared__ __align__(16) unsigned char smem[];
-    // work == nullptr: one instance, block b is tile b (saves a dependent load)
-    const int inst = work ? work[blockIdx.x].x : 0, t = work ? work[blockIdx.x].y : (int)blockIdx.x;
+    // work == nullptr: one instance, block b is tile b in the host's XCD order
+    // (saves a dependent load)
+    const int inst = work ? work[blockIdx.x].x : 0;
+    const int t = work ? work[blockIdx.x].y : xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int comp = blockIdx.y;
     const InstDesc &D = Dt[inst];
     const int nx = D.n[0], nz = D.n[2];
@@ -1466,7 +1572,7 @@ template <int DIM, class R>
 __global__ void __launch_bounds__(256) k_gauss(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int nwork,
                                                int par)
 {
-    typedef typename JOf<R>::T JT;
+    typedef typename JGOf<R>::T JT;
     __shared__ double red[8];
     const int it0 = blockIdx.x * GAUSS_ITEMS, it1 = min(nwork, it0 + GAUSS_ITEMS);
     double g2 = 0.0, gmax = 0.0, chg = 0.0, rmax = 0.0;
@@ -1482,12 +1588,12 @@ __global__ void __launch_bounds__(256) k_gauss(const InstDesc *__restrict__ Dt, 
             const R *E0 = (const R *)D.E[par][0], *E1 = (const R *)D.E[par][1], *E2 = (const R *)D.E[par][2];
             const JT *J0 = (const JT *)D.J[par][0], *J1 = (const JT *)D.J[par][1], *J2 = (const JT *)D.J[par][2];
             double divE = ((double)E0[cell] - (double)E0[im]) / D.d[0] + ((double)E2[cell] - (double)E2[km]) / D.d[2];
-            double divJ = (jreal(J0[cell], D.jq) - jreal(J0[im], D.jq)) / D.d[0] +
-                          (jreal(J2[cell], D.jq) - jreal(J2[km], D.jq)) / D.d[2];
+            double divJ = (jreal(J0[cell], D.jqg) - jreal(J0[im], D.jqg)) / D.d[0] +
+                          (jreal(J2[cell], D.jqg) - jreal(J2[km], D.jqg)) / D.d[2];
             if (DIM == 3) {
                 const int jm = i + ((j == 0 ? ny - 1 : j - 1) + k * ny) * nx;
                 divE += ((double)E1[cell] - (double)E1[jm]) / D.d[1];
-                divJ += (jreal(J1[cell], D.jq) - jreal(J1[jm], D.jq)) / D.d[1];
+                divJ += (jreal(J1[cell], D.jqg) - jreal(J1[jm], D.jqg)) / D.d[1];
             }
             const double rho = D.rho[cell];
             const double res = divE - D.dt * divJ - (rho - D.rho0[cell]);
@@ -1538,12 +1644,13 @@ template <class R, bool CK> void launch_yee_2d_s(const LaunchCtx &c, const int2 
 {
     const dim3 g(nywork), b(PIC_FIELD_CHUNK);
     if (c.single) ywork = nullptr;
-    if (c.yee_tz == 4) k_yee_2d<R, 4, CK><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);
+    if (c.yee_tz == 4) k_yee_2d<R, 4, CK><<<g, b, 0, c.stream>>>(c.desc, ywork, nywork, c.par);
     else if constexpr (sizeof(R) == 4) {
-        if (c.yee_tz == 16) k_yee_2d<R, 16, CK><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);
-        else k_yee_2d<R, 8, CK><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);
+        if (c.yee_tz == 16) k_yee_2d<R, 16, CK><<<g, b, 0, c.stream>>>(c.desc, ywork, nywork, c.par);
+        else k_yee_2d<R, 8, CK><<<g, b, 0, c.stream>>>(c.desc, ywork, nywork, c.par);
     } else {
-        k_yee_2d<R, 8, CK><<<g, b, 0, c.stream>>>(c.desc, ywork, c.par);   // 16 rows of doubles exceed the LDS
+        // 16 rows of doubles exceed the LDS
+        k_yee_2d<R, 8, CK><<<g, b, 0, c.stream>>>(c.desc, ywork, nywork, c.par);
     }
 }
 
@@ -1599,7 +1706,11 @@ void launch_seen_2d(const LaunchCtx &c, const int2 *swork, int nswork)
 {
     if (c.seen_tz == 8) launch_seen_2d_tz<R, 8>(c, swork, nswork);
     else if (c.seen_tz == 16) launch_seen_2d_tz<R, 16>(c, swork, nswork);
-    else launch_seen_2d_tz<R, 32>(c, swork, nswork);
+    else if constexpr (sizeof(R) == 4) {
+        // 64 rows of doubles with the widest stencils exceed 64 KB of LDS
+        if (c.seen_tz == 64) launch_seen_2d_tz<R, 64>(c, swork, nswork);
+        else launch_seen_2d_tz<R, 32>(c, swork, nswork);
+    } else launch_seen_2d_tz<R, 32>(c, swork, nswork);
 }
 
 int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork)

@@ -126,6 +126,10 @@ class Simulation:
         L.pic_step(self.st, n)
         self.steps_taken += n
 
+    def prepare(self, n):
+        """Capture the graphs a following step(n) replays (no stepping)."""
+        L.pic_prepare(self.st, n)
+
     def set_schedule(self, sched="batched", use_graph=True):
         L.pic_set_schedule(self.st, L.PIC_SCHED_BATCHED if sched == "batched" else L.PIC_SCHED_PLAIN,
                            1 if use_graph else 0)
@@ -177,7 +181,8 @@ class Simulation:
         out = dict(WE=np.array(d.WE[:]), WB=np.array(d.WB[:]), Wkin=d.Wkin, gauss_l2=d.gauss_l2,
                    gauss_linf=d.gauss_linf, charge=d.charge, rho_max=d.rho_max,
                    n_particles=d.n_particles, step=d.step, nonfinite=d.nonfinite,
-                   particle_error=d.particle_error, resorts=d.resorts, slow_tiles=d.slow_tiles, rc=rc)
+                   particle_error=d.particle_error, resorts=d.resorts, slow_tiles=d.slow_tiles,
+                   current_range=d.current_range, rc=rc)
         out["Wperp"] = float(out["WE"][0] + out["WE"][1] + out["WB"][0] + out["WB"][1])
         return out
 

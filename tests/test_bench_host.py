@@ -12,14 +12,34 @@ def test_particle_kernel_bytes():
     assert bench.particle_kernel_bytes(10, 3, word=8, state_bytes=44) == 2 * 44 * 10 + 9 * 8 * 3
 
 
+def test_step_bytes_of_the_batch():
+    # 8 ppc: 48 B of particle state and 24 words of 4 B per cell shared by 8 particles
+    assert bench.step_bytes(8, 1) == 2 * 24 * 8 + 24 * 4
+    assert bench.step_bytes(8, 1) / 8 == 60
+
+
+def test_batch_is_64_instances_accepted_by_the_oracle():
+    insts = bench.batch_instances(bench._oracle_accepts)
+    assert len(insts) == 64
+    assert len({w["name"] for w in insts}) == 64
+    assert all(0.3 <= w["alpha"] <= 0.7 and w["ppc"] == 8 for w in insts)
+
+
+def test_gpus_above_one_exit_with_a_message():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
 def test_stored_counters_follow_the_kernel_source(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "PROFILE_DIR", str(tmp_path))
     sha = bench.kernel_sha()
     (tmp_path / "t.json").write_text(json.dumps({"kernel_source_sha": sha, "hbm_bytes_per_launch": 123.0}))
-    assert bench.stored_traffic("t.json") == 123.0
+    assert bench.stored_traffic("t.json") == (123.0, "profiles/t.json")
     (tmp_path / "t.json").write_text(json.dumps({"kernel_source_sha": "0" * 16, "hbm_bytes_per_launch": 123.0}))
-    assert bench.stored_traffic("t.json") is None
-    assert bench.stored_traffic("missing.json") is None
+    assert bench.stored_traffic("t.json") == (None, None)
+    assert bench.stored_traffic("missing.json") == (None, None)
     doc = {"kernel_source_sha": sha, "cases": {"w": {"valu_lane_instr_per_particle": 200.0}}}
     (tmp_path / "valu_k_particles.json").write_text(json.dumps(doc))
     v = bench.valu_issue("w", 1000, 1e-3)          # 2e5 lane instructions in 1 us
