@@ -3,8 +3,14 @@
 Growth rate of the transverse field energy (fit window and definition in
 paper_1401_0838_amd/fit.py; the oracle side uses its own oracle/fit.py).
 Bar: within 5 %, or |dGamma| dt <= 5e-5 when the growth is too weak for a
-relative comparison (Gamma dt < 1e-4 or less than ten-fold total growth).
+relative comparison (Gamma dt < 1e-4 or less than ten-fold growth).  Small
+cases run the oracle here; the 512x512 runs, the 64-instance batch and the
+Sec. 3 scan and variant points compare with the oracle's stored traces
+(tests/golden/growth_oracle.*, written by tests/golden/make_growth_golden.py
+from the oracle alone).
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -83,59 +89,77 @@ def test_growth_rate_corrected_vs_oracle():
     assert _close(gg, go, Wo, wl["alpha"])
 
 
-def test_growth_rate_full_size_fp32_vs_fp64():
-    """512x512, 16 ppc, 2000 steps at alpha 0.3, 0.5, 0.7: the FP32 growth rate equals
-    the FP64 one (a property that holds at any size; the oracle is checked at 64x64)."""
-    wl0 = pi.workload("beam2d_512")
-    x, u = pi.load_beam(2, wl0["n"], wl0["ppc"], wl0["gamma"], wl0["sigma"], 0)
-    for alpha in wl0["alphas"]:
-        wl = dict(wl0, alpha=alpha)
-        W64, wk = _gpu_trace(wl, x, u, "fp64", wl["steps"])
-        W32, _ = _gpu_trace(wl, x, u, "fp32", wl["steps"])
-        g64, win = gfit.growth_rate(W64, alpha, wk)
-        g32, _ = gfit.growth_rate(W32, alpha, wk)
-        _say("512 alpha %.1f: Gamma fp32 %.6e fp64 %.6e (Gamma dt %.2e) window %s W %.3e..%.3e"
-             % (alpha, g32, g64, g64 * alpha, win, W64[10], W64[-1]))
-        assert _close(g32, g64, W64, alpha)
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def test_batched_scan_growth_rates_fp32_vs_fp64():
-    """The 64-instance scan (uneven grids, alpha in [0.3, 0.7], gamma in {10, 50,
-    130}, 8 ppc), 1000 steps in one batched run per precision: every instance's
-    FP32 growth rate equals its FP64 one (same bar).  Candidates whose
-    correction breaks down are skipped and counted."""
+def _golden():
+    meta = json.load(open(os.path.join(GOLDEN, "growth_oracle.json")))["cases"]
+    traces = np.load(os.path.join(GOLDEN, "growth_oracle.npz"))
+    return meta, traces
+
+
+def _vs_golden(key, W, wkin0, dt, meta, traces):
+    """(ok, report) for one GPU FP32 trace against the oracle's FP64 golden trace
+    of the same instance: both fitted by the same window rule; within 5 %, or
+    |dGamma| dt <= 5e-5 where the oracle's growth is weak (Gamma dt < 1e-4 or
+    less than ten-fold growth over its window)."""
+    Wo = traces[key]
+    go, (lo, hi) = gfit.growth_rate(Wo, dt, meta[key]["wkin0"])
+    gg, win = gfit.growth_rate(W, dt, wkin0)
+    weak = abs(go) * dt < 1e-4 or Wo[hi - 1] < 10 * Wo[lo]
+    ok = abs(gg - go) <= 0.05 * abs(go) or (weak and abs(gg - go) * dt <= 5e-5)
+    return ok, "%s: Gamma gpu %.6e oracle %.6e (window %s / %s, weak %s)" % (key, gg, go, win, (lo, hi), weak)
+
+
+def test_growth_rate_full_size_fp32_vs_oracle_golden():
+    """512x512, 16 ppc, 2000 steps at alpha 0.3, 0.5, 0.7 (the 512x512 workload):
+    the FP32 GPU growth rate against the FP64 oracle's stored trace of the same
+    run (tests/golden/make_growth_golden.py)."""
+    meta, traces = _golden()
+    bad = []
+    for key, wl, seed, steps in pi.growth_cases():
+        if not key.startswith("c1_"):
+            continue
+        x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], wl["sigma"], seed)
+        _say("case %s" % key)
+        W, wk = _gpu_trace(wl, x, u, "fp32", steps)
+        assert len(W) == steps and meta[key]["steps"] == steps
+        ok, rep = _vs_golden(key, W, wk, wl["alpha"], meta, traces)
+        _say("  " + rep)
+        if not ok:
+            bad.append(rep)
+    assert not bad
+
+
+def test_batched_scan_growth_rates_vs_oracle_golden():
+    """The 64-instance batch (uneven grids, alpha in [0.3, 0.7], gamma in {10, 50,
+    130}, 8 ppc), 1000 steps in one batched FP32 run: every instance's growth rate
+    against the FP64 oracle's stored trace of the same instance.  The instances
+    are the ones the oracle accepted; the library must accept each of them too."""
     from paper_1401_0838_amd import _lib as L
     from paper_1401_0838_amd.sim import Simulation
-    wls, parts, skipped = [], [], 0
-    for cand in pi.batched_candidates(0):
-        rc, _, _ = L.pic_psi_coeffs(L.PIC_GALERKIN, cand["alpha"], 4)
-        if rc != L.PIC_OK:
-            skipped += 1
-            continue
-        wls.append(cand)
-        parts.append(pi.load_beam(2, cand["n"], cand["ppc"], cand["gamma"], cand["sigma"], cand["seeds"][0]))
-        if len(wls) == 64:
-            break
+    meta, traces = _golden()
+    cands = pi.batched_candidates(0)
+    keys = sorted(k for k in meta if k.startswith("c3_"))
+    assert len(keys) == 64
+    wls = [cands[int(k[3:])] for k in keys]
+    for w in wls:
+        assert L.pic_psi_coeffs(L.PIC_GALERKIN, w["alpha"], 4)[0] == L.PIC_OK
+    parts = [pi.load_beam(2, w["n"], w["ppc"], w["gamma"], w["sigma"], w["seeds"][0]) for w in wls]
     nsteps = wls[0]["steps"]
-    traces, wkin = {}, {}
-    for prec in ("fp32", "fp64"):
-        sim = Simulation(wls, parts, precision=prec, trace_capacity=nsteps)
-        wkin[prec] = [sim.diag(i)["Wkin"] for i in range(len(wls))]
-        sim.step(nsteps)
-        traces[prec] = []
-        for i in range(len(wls)):
-            tr = sim.trace(i)
-            traces[prec].append(tr[:, 0] + tr[:, 1] + tr[:, 3] + tr[:, 4])
-        sim.close()
-    _say("batched scan: %d instances, %d candidates skipped for a broken-down correction" % (len(wls), skipped))
+    _say("case batched 64 growth, %d steps" % nsteps)
+    sim = Simulation(wls, parts, precision="fp32", trace_capacity=nsteps)
+    wkin = [sim.diag(i)["Wkin"] for i in range(len(wls))]
+    sim.step(nsteps)
     bad = []
-    for i, w in enumerate(wls):
-        W32, W64 = traces["fp32"][i], traces["fp64"][i]
-        assert len(W32) == nsteps and len(W64) == nsteps
-        g32, _ = gfit.growth_rate(W32, w["alpha"], wkin["fp64"][i])
-        g64, _ = gfit.growth_rate(W64, w["alpha"], wkin["fp64"][i])
-        if not _close(g32, g64, W64, w["alpha"]):
-            bad.append((i, w["n"], w["alpha"], w["gamma"], g32, g64))
+    for i, (k, w) in enumerate(zip(keys, wls)):
+        tr = sim.trace(i)
+        W = tr[:, 0] + tr[:, 1] + tr[:, 3] + tr[:, 4]
+        assert len(W) == nsteps
+        ok, rep = _vs_golden(k, W, wkin[i], w["alpha"], meta, traces)
+        if not ok:
+            bad.append(rep)
+    sim.close()
     _say("  mismatches: %s" % bad)
     assert not bad
 
@@ -157,37 +181,47 @@ def test_growth_rate_ck_cubic_eq6_vs_oracle():
         assert _close(gg, go, Wo, wl["alpha"])
 
 
-def test_gamma_scan_growth_rates_fp32_vs_fp64():
-    """A gamma x alpha scan at the Sec. 3 setting (64x64, 8 ppc, cubic, CK, Eq. 6
-    filter; gamma 3 and 130, alpha 0.5 and 0.9, with and without correction),
-    1000 steps in one batched run per precision: every FP32 growth rate equals
-    its FP64 one (same bar)."""
+def _golden_batch(keys, meta, traces, cases):
+    """Run the listed golden cases in batched FP32 runs (one per exact-ratio
+    choice, which a batch shares) and compare each with its golden trace."""
     from paper_1401_0838_amd import scan
     bad = []
-    for corr in (True, False):
-        base = pi.workload("beam2d_128_ck", n=(64, 64), ppc=8, correction=corr)
-        pts, wls, parts, skipped = scan.scan_instances(base, [0.5, 0.9], [3.0, 130.0])
-        tr32, wk32 = scan.run_scan(pts, wls, parts, 1000, "fp32")
-        tr64, wk64 = scan.run_scan(pts, wls, parts, 1000, "fp64")
-        r32, _, _ = scan.growth_table(pts, tr32, wk64)
-        r64, peaks, power = scan.growth_table(pts, tr64, wk64)
-        _say("gamma scan corr=%s: fp64 rates %s peaks %s power %s" % (corr, r64, peaks, power))
-        for p, g32, g64, W in zip(pts, r32, r64, tr64):
-            if not _close(g32, g64, W, p[1]):
-                bad.append((corr, p, g32, g64))
-    _say("  mismatches: %s" % bad)
+    groups = {}
+    for key in keys:
+        wl, seed, steps = cases[key]
+        groups.setdefault(wl.get("correction") == "ratio", []).append(key)
+    for ks in groups.values():
+        wls = [cases[k][0] for k in ks]
+        parts = [pi.load_beam(2, w["n"], w["ppc"], w["gamma"], w["sigma"], cases[k][1]) for k, w in zip(ks, wls)]
+        steps = cases[ks[0]][2]
+        pts = [(w["gamma"], w["alpha"]) for w in wls]
+        _say("case golden batch %s" % ks)
+        tr, wk = scan.run_scan(pts, wls, parts, steps, "fp32")
+        for k, w, W, w0 in zip(ks, wls, tr, wk):
+            ok, rep = _vs_golden(k, W, w0, w["alpha"], meta, traces)
+            _say("  " + rep)
+            if not ok:
+                bad.append(rep)
+    return bad
+
+
+def test_gamma_scan_growth_rates_vs_oracle_golden():
+    """A gamma x alpha scan at the Sec. 3 setting (64x64, 8 ppc, cubic, CK, Eq. 6
+    filter; gamma 3 and 130, alpha 0.5 and 0.9, with and without correction),
+    1000 steps in batched FP32 runs: every growth rate against the FP64 oracle's
+    stored trace of the same instance."""
+    meta, traces = _golden()
+    cases = {k: (w, s, n) for k, w, s, n in pi.growth_cases()}
+    bad = _golden_batch([k for k in cases if k.startswith("scan_")], meta, traces, cases)
     assert not bad
 
 
-def test_variant_sweep_growth_rates_fp32_vs_fp64():
+def test_variant_sweep_growth_rates_vs_oracle_golden():
     """Sec. 3's variants (no filter, exact ratio on the transverse E, no
-    compensation) at 64x64, 8 ppc, cubic CK, gamma 130, alpha 0.7 and 0.95,
-    1000 steps: FP32 growth rates equal FP64 ones for every variant."""
-    from paper_1401_0838_amd import scan
-    base = pi.workload("beam2d_128_ck", n=(64, 64), ppc=8)
-    r32, _ = scan.variant_sweep(base, [0.7, 0.95], 130.0, 1000, "fp32")
-    r64, _ = scan.variant_sweep(base, [0.7, 0.95], 130.0, 1000, "fp64")
-    _say("variants fp32 %s\n         fp64 %s" % (r32, r64))
-    for name in r64:
-        for g32, g64, a in zip(r32[name], r64[name], (0.7, 0.95)):
-            assert abs(g32 - g64) <= 0.05 * abs(g64) or abs(g32 - g64) * a <= 5e-5, (name, a, g32, g64)
+    compensation) and Sec. 4's one-pass-each filter at 64x64, 8 ppc, cubic CK,
+    gamma 130, alpha 0.7 and 0.95, 1000 steps: FP32 growth rates against the FP64
+    oracle's stored traces."""
+    meta, traces = _golden()
+    cases = {k: (w, s, n) for k, w, s, n in pi.growth_cases()}
+    bad = _golden_batch([k for k in cases if k.startswith("var_")], meta, traces, cases)
+    assert not bad
