@@ -214,6 +214,23 @@ int pic_plan(const pic_config *cfgs, int n_inst, const int64_t *n_particles, siz
 int pic_init(const pic_config *cfgs, int n_inst, const pic_particles *parts,
              void *d_arena, size_t arena_bytes, void *hip_stream, pic_state **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): pic_init with the
+ * arena taken from a static device array of PIC_STATIC_ARENA_BYTES that the
+ * library holds on every device it runs on until the process ends (64 MiB: one
+ * 2D FP32 instance of 256 x 256 cells at 8 particles per cell needs 41 MiB).
+ * Arguments as for pic_init less the arena; hip_stream must be a stream of the
+ * current device (NULL is rejected: no stream is created).  Allocates no device
+ * memory.  The array holds one state per device: while a state made by this
+ * call on a device is alive, a further call there returns PIC_ESTATE (calls
+ * that overlapped on one device would otherwise overwrite each other's state);
+ * pic_destroy releases the array.  Each call clears what the scheme needs at
+ * zero, as pic_init does.  PIC_ENOMEM when pic_plan asks for more than
+ * PIC_STATIC_ARENA_BYTES. */
+#define PIC_STATIC_ARENA_BYTES (64u << 20)
+int pic_init_static(const pic_config *cfgs, int n_inst, const pic_particles *parts, void *hip_stream,
+                    pic_state **out);
+
 /* Advance every instance by nsteps steps of the explicit scheme Sec. 2
  * analyses: the Yee field update, then the fields as seen by the particles
  * (Psi_E(S_z) on the transverse E and Psi_B(S_z) on the rest, Sec. 2,

@@ -78,6 +78,8 @@ _SIGS = {
     "pic_plan": (C.c_int, [C.POINTER(pic_config), C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
     "pic_init": (C.c_int, [C.POINTER(pic_config), C.c_int, C.POINTER(pic_particles), C.c_void_p,
                            C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pic_init_static": (C.c_int, [C.POINTER(pic_config), C.c_int, C.POINTER(pic_particles), C.c_void_p,
+                                  C.POINTER(C.c_void_p)]),
     "pic_step": (C.c_int, [C.c_void_p, C.c_int]),
     "pic_prepare": (C.c_int, [C.c_void_p, C.c_int]),
     "pic_set_option": (C.c_int, [C.c_void_p, C.c_char_p, C.c_int]),
@@ -165,6 +167,15 @@ def pic_init(cfgs, parts, arena_ptr, arena_bytes, stream_ptr):
     st = C.c_void_p(0)
     check(load().pic_init(arr, n, parr, C.c_void_p(arena_ptr), C.c_size_t(arena_bytes),
                           C.c_void_p(stream_ptr), C.byref(st)), "pic_init")
+    return st
+
+
+def pic_init_static(cfgs, parts, stream_ptr):
+    n = len(cfgs)
+    arr = (pic_config * n)(*cfgs)
+    parr = (pic_particles * n)(*parts)
+    st = C.c_void_p(0)
+    check(load().pic_init_static(arr, n, parr, C.c_void_p(stream_ptr), C.byref(st)), "pic_init_static")
     return st
 
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -203,6 +204,7 @@ struct pic_state {
     int ratio = 0;                   // exact Psi_E / Psi_B on the transverse E (every instance)
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int static_dev = -1;             // device whose static arena holds this state (pic_init_static)
     char *arena = nullptr;
     size_t arena_bytes = 0;
     std::vector<pic_config> cfg;
@@ -1135,6 +1137,57 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
     return PIC_OK;
 }
 
+// ------------------------------------------------------------ static arena
+// For callers that cannot allocate: the arena lives in a fixed device array.
+// On the host, `scratch` names the symbol only, never device memory; its device
+// address comes from hipGetSymbolAddress, once per device with that device
+// current, and only that address is handed on.  One live state per device owns
+// the array; pic_destroy releases it.
+static __device__ __align__(256) unsigned char scratch[PIC_STATIC_ARENA_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices];             // device address of scratch, per device
+const pic_state *g_static_owner[kMaxDevices];  // live state in that device's array
+}  // namespace
+
+extern "C" int pic_init_static(const pic_config *cfgs, int n_inst, const pic_particles *parts, void *hip_stream,
+                               pic_state **out)
+{
+    if (!out || !parts || !cfgs) return fail(PIC_EINVAL, "null argument");
+    *out = nullptr;
+    if (!hip_stream) return fail(PIC_EINVAL, "pic_init_static: a stream is required (none is created)");
+    if (n_inst < 1) return fail(PIC_EINVAL, "n_inst");
+    std::vector<int64_t> np(n_inst);
+    for (int i = 0; i < n_inst; i++) np[i] = parts[i].n;
+    size_t need = 0;
+    int rc = pic_plan(cfgs, n_inst, np.data(), &need);
+    if (rc) return rc;
+    if (need > (size_t)PIC_STATIC_ARENA_BYTES)
+        return fail(PIC_ENOMEM, "pic_init_static: the instances need " + std::to_string(need) +
+                                    " arena bytes; the static arena holds " +
+                                    std::to_string((size_t)PIC_STATIC_ARENA_BYTES));
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(PIC_EHIP, "pic_init_static: current device");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_owner[dev])
+        return fail(PIC_ESTATE, "pic_init_static: the static arena of this device holds a live state");
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PIC_EHIP, std::string("pic_init_static: hipGetSymbolAddress: ") + hipGetErrorString(e));
+        g_static_ptr[dev] = p;
+    }
+    rc = pic_init(cfgs, n_inst, parts, g_static_ptr[dev], (size_t)PIC_STATIC_ARENA_BYTES, hip_stream, out);
+    if (rc) return rc;
+    (*out)->static_dev = dev;
+    g_static_owner[dev] = *out;
+    return PIC_OK;
+}
+
 extern "C" int pic_set_schedule(pic_state *s, int sched, int use_graph)
 {
     if (!s || (sched != PIC_SCHED_BATCHED && sched != PIC_SCHED_PLAIN)) return fail(PIC_EINVAL, "schedule");
@@ -1607,5 +1660,9 @@ extern "C" void pic_destroy(pic_state *s)
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     drop_graphs(s);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (g_static_owner[s->static_dev] == s) g_static_owner[s->static_dev] = nullptr;
+    }
     delete s;
 }

@@ -80,10 +80,14 @@ class Simulation:
 
     workloads : list of workload dicts
     particles : list of (x, u) loader arrays, x (N, dims) absolute positions, u (N, 3)
+    static_arena : take the arena from the library's static device array
+                   (pic_init_static, 64 MiB, one live state per device) instead
+                   of allocating it
     """
 
     def __init__(self, workloads, particles, precision=None, tile=None, block=0,
-                 trace_capacity=0, psi=None, stream=None, adjoint_steps=0, adjoint_ckpt=20):
+                 trace_capacity=0, psi=None, stream=None, adjoint_steps=0, adjoint_ckpt=20,
+                 static_arena=False):
         torch = _require_gpu()
         L.load()
         if isinstance(workloads, dict):
@@ -96,9 +100,12 @@ class Simulation:
         self.n_inst = len(self.cfgs)
         self.np = [int(p[0].shape[0]) for p in particles]
         nbytes = L.pic_plan(self.cfgs, self.np)
-        self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
-        base = self.arena.data_ptr()
-        aligned = (base + 255) & ~255
+        if static_arena:
+            # the library's static device array (pic_init_static): nothing allocated here
+            self.arena = None
+        else:
+            self.arena = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            aligned = (self.arena.data_ptr() + 255) & ~255
         self.stream = stream or torch.cuda.Stream()
         keep = []
         parts = []
@@ -118,7 +125,10 @@ class Simulation:
                 p.mom[a] = L.dptr(mom[a])
             parts.append(p)
         torch.cuda.synchronize()
-        self.st = L.pic_init(self.cfgs, parts, aligned, nbytes, self.stream.cuda_stream)
+        if static_arena:
+            self.st = L.pic_init_static(self.cfgs, parts, self.stream.cuda_stream)
+        else:
+            self.st = L.pic_init(self.cfgs, parts, aligned, nbytes, self.stream.cuda_stream)
         self.steps_taken = 0
 
     # ------------------------------------------------------------ stepping
