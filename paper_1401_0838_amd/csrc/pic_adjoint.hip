@@ -29,6 +29,11 @@ using namespace pic;
 __host__ __device__ inline size_t adj_lf_offset(size_t wc, size_t rsize) { return (9 * wc * rsize + 7) & ~(size_t)7; }
 
 // derivatives of the Shape weights with respect to the in-cell offset
+// Blocks add their gradient partial sums to one of PIC_GRAD_COPIES copies of
+// the gradient (by block index), so that a few blocks, not all, meet at each
+// address; the host sums the copies.
+__device__ __forceinline__ int grad_copy() { return 16 * (int)(blockIdx.x & (PIC_GRAD_COPIES - 1)); }
+
 template <int L, class R> struct DShape;
 
 template <class R> struct DShape<1, R> {
@@ -506,22 +511,39 @@ __global__ void __launch_bounds__(256) k_adj_particles(const InstDesc *__restric
                                    G<R>((const void *)D.poff[2])};
         const gp<R> plu[3] = {G<R>(D.lu[0]), G<R>(D.lu[1]), G<R>(D.lu[2])};
         const gp<R> plo[3] = {G<R>(D.loff[0]), G<R>(D.loff[1]), G<R>(D.loff[2])};
+        // the next particle's state is loaded while this one is reversed (its
+        // index clamped to the tile's last particle, so every load is valid)
+        unsigned nidx = 0;
+        R nu[3], nlu[3], noff[3], nloff[3];
+        auto fetch = [&](int q) {
+            nidx = pidx[q];
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                nu[a] = pu[a][q];
+                nlu[a] = plu[a][q];
+                if (DIM == 2 && a == 1) { noff[a] = R(0); nloff[a] = R(0); continue; }
+                noff[a] = po[a][q];
+                nloff[a] = plo[a][q];
+            }
+        };
+        if (p0 + tid < p1) fetch(p0 + tid);
         for (int p = p0 + tid; p < p1; p += bs) {
             int c[3];
-            unpack_cell<DIM>(pidx[p], c);
+            unpack_cell<DIM>(nidx, c);
             int lc[3];
             R off[3], u[3], loff[3], lu[3];
 #pragma unroll
             for (int a = 0; a < 3; a++) {
-                u[a] = pu[a][p];
-                lu[a] = plu[a][p];
-                if (DIM == 2 && a == 1) { lc[a] = 0; off[a] = R(0); loff[a] = R(0); continue; }
+                u[a] = nu[a];
+                lu[a] = nlu[a];
+                off[a] = noff[a];
+                loff[a] = nloff[a];
+                if (DIM == 2 && a == 1) { lc[a] = 0; continue; }
                 int rel = c[a] - lo[a];
                 rel += rel < 0 ? nn[a] : 0;
                 lc[a] = rel + JL;
-                off[a] = po[a][p];
-                loff[a] = plo[a][p];
             }
+            fetch(min(p + bs, p1 - 1));
             if (fits) adjoint_particle<DIM, L, R, IP>(lw, lc, off, u, loff, lu, dtd, qdt2m, cdr, cyr);
             else adjoint_particle<DIM, L, R, IP>(gw, lc, off, u, loff, lu, dtd, qdt2m, cdr, cyr);
 #pragma unroll
@@ -632,7 +654,7 @@ __global__ void __launch_bounds__(256) k_adj_grad(const InstDesc *__restrict__ D
     for (int j = 0; j < 9; j++) {
         if (j > D.psi_deg) break;
         const double w = wave_sum(v[j]);
-        if ((threadIdx.x & 63) == 0 && w != 0.0) unsafeAtomicAdd(&D.grad[j], w);
+        if ((threadIdx.x & 63) == 0 && w != 0.0) unsafeAtomicAdd(&D.grad[grad_copy() + j], w);
     }
 }
 
@@ -737,17 +759,26 @@ __global__ void __launch_bounds__(256) k_zero_lseen(const InstDesc *__restrict__
 
 // ------------------------------------------------------------ fused 2D kernels
 // Adjoint of the fields as seen by the particles, 2D, one (64 x TZ) tile of one
-// component per block.  GRAD (components x, y): Lambda = F lambda_Et is formed
-// in LDS (filter passes only), then lambda_E + sum_j a_j S_z^j Lambda
+// component per block.  GRAD (components x, y): Lambda = F lambda_Et (filter
+// passes only), then lambda_E + sum_j a_j S_z^j Lambda
 // (= lambda_E + Psi_E(S_z) F lambda_Et) and dW/da_j += <S_z^j Lambda, E1>.
 // Otherwise (E_z and all of B): lambda + Psi_B(S_z) F lambda_t with the
 // combined taps.  The sums go to the scratch planes T1: the reverse Yee kernel
-// reads them with halos and writes lambda_E, lambda_B.  HZ (half-width of the
-// z pass), HX and DEG >= 0 are compile-time widths; -1 reads the descriptor.
+// reads them with halos and writes lambda_E, lambda_B.
+// The window (tile plus the z halo deg + hz and the x halo hx) is staged in LDS
+// with waves on rows and lanes on columns; the x filter runs on every staged
+// row, four neighbouring output columns per thread; then each wave walks down
+// its TZ / 4 output rows of each column in registers: the z pass, and for GRAD
+// the S_z^j stencils on the z-filtered column.  Stencils on different axes of
+// the periodic grid commute, so x first is the same operator.  HZ (half-width
+// of the z pass), HX and DEG >= 0 are compile-time widths (loops unrolled,
+// taps in registers); -1 reads the descriptor.
 #define ADJ_TX 64
 template <class R, int TZ, bool GRAD, int HZ, int HX, int DEG>
 __device__ __forceinline__ void adj_seen_body(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work, int comp)
 {
+    constexpr int NW = PIC_FIELD_CHUNK / 64, RB = TZ / NW;
+    static_assert(TZ % NW == 0, "the four waves split the output rows");
     extern __shared__ __align__(16) unsigned char smem[];
     const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
     const InstDesc &D = Dt[inst];
@@ -756,16 +787,31 @@ __device__ __forceinline__ void adj_seen_body(const InstDesc *__restrict__ Dt, c
     const int x0 = (t % ntx) * ADJ_TX, z0 = (t / ntx) * TZ;
     const int hx = HX >= 0 ? HX : D.hx;
     const int deg = GRAD ? (DEG >= 0 ? DEG : D.psi_deg) : 0;
-    const int hz = HZ >= 0 ? HZ : (GRAD ? D.hzf : D.hz);   // z half-width of the first pass
-    const int wx = ADJ_TX + 2 * hx;
-    const int rows_mid = TZ + 2 * deg;              // rows kept after the z pass
-    const int wz = rows_mid + 2 * hz;
-    R *win = reinterpret_cast<R *>(smem);
-    R *mid = win + wx * wz;
-    R *lam = mid + wx * rows_mid;
-    R *tz = lam + ADJ_TX * rows_mid;
+    const int hz = HZ >= 0 ? HZ : (GRAD ? D.hzf : D.hz);
+    const int ez = deg + hz;                    // z halo of the window
+    const int wx = ADJ_TX + 2 * hx, wz = TZ + 2 * ez;
+    R *win = reinterpret_cast<R *>(smem);       // wz x wx: lambda_t with halos
+    R *mid = win + wx * wz;                     // wz x 64: after the x filter
+    R *tz = mid + ADJ_TX * wz;
     R *tx = tz + 2 * PIC_MAX_HZ + 1;
-    __shared__ double red[9][4];
+    __shared__ double red[9][NW];
+    const int lane = threadIdx.x & 63, wave = wave_id();
+    const int zr = wave * RB;                   // this wave's first output row
+    const int gx = x0 + lane;
+    // what the last phase reads at its own cells, loaded first (rows and
+    // columns clamped into the grid) so that its latency overlaps the window's
+    const gp<const R> own = G<R>((const void *)(comp < 3 ? D.lE[comp] : D.lB[comp - 3]));
+    R pown[RB], pe1[RB];
+    {
+        const gp<const R> e1p = G<R>((const void *)D.E[0][comp < 3 ? comp : 0]);
+        const int gxc = min(gx, nx - 1);
+#pragma unroll
+        for (int j = 0; j < RB; j++) {
+            const int g = min(z0 + zr + j, nz - 1) * nx + gxc;
+            pown[j] = own[g];
+            pe1[j] = GRAD ? e1p[g] : R(0);
+        }
+    }
     const double *tzs = GRAD ? D.tzf : D.tz[comp < 2 ? 0 : 1];
     constexpr int NTZ = HZ >= 0 ? 2 * HZ + 1 : 1, NTX = HX >= 0 ? 2 * HX + 1 : 1;
     R rz[NTZ], rx[NTX];
@@ -782,24 +828,25 @@ __device__ __forceinline__ void adj_seen_body(const InstDesc *__restrict__ Dt, c
         for (int i = threadIdx.x; i <= 2 * hx; i += blockDim.x) tx[i] = (R)D.tx[i];
     }
     const gp<const R> src = G<R>((const void *)(comp < 3 ? D.lEt[comp] : D.lBt[comp - 3]));
-    // waves own rows, lanes own columns: a = lane, b = 64 + lane (right halo, lane < 2 hx)
-    const int lane = threadIdx.x & 63, wave = wave_id(), nwave = blockDim.x >> 6;
+    // staging: column a = lane, column b = 64 + lane for the right halo (lane < 2 hx)
     const bool hasb = lane < 2 * hx;
     const int gxa = wrap_near(x0 - hx + lane, nx);
     const int gxb = hasb ? wrap_near(x0 - hx + ADJ_TX + lane, nx) : gxa;
-    constexpr int U = 4;
-    for (int r0 = wave; r0 < wz; r0 += U * nwave) {
+    // rows per wave: the whole window in one round when its height is a constant
+    constexpr int WZC = (HZ >= 0 && (!GRAD || DEG >= 0)) ? TZ + 2 * ((GRAD ? DEG : 0) + HZ) : 0;
+    constexpr int U = WZC > 0 ? (WZC + NW - 1) / NW : 4;
+    for (int r0 = wave; r0 < wz; r0 += U * NW) {
         R va[U], vb[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int row = min(r0 + u * nwave, wz - 1);
-            const int base = wrap_near(z0 - deg - hz + row, nz) * nx;
+            const int row = min(r0 + u * NW, wz - 1);
+            const int base = wrap_near(z0 - ez + row, nz) * nx;
             va[u] = src[base + gxa];
             vb[u] = src[base + gxb];
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int row = r0 + u * nwave;
+            const int row = r0 + u * NW;
             if (row < wz) {
                 win[row * wx + lane] = va[u];
                 if (hasb) win[row * wx + ADJ_TX + lane] = vb[u];
@@ -807,66 +854,115 @@ __device__ __forceinline__ void adj_seen_body(const InstDesc *__restrict__ Dt, c
         }
     }
     __syncthreads();
-    for (int zz = wave; zz < rows_mid; zz += nwave) {
-#pragma unroll
-        for (int half = 0; half < 2; half++) {
-            if (half == 1 && !hasb) break;
-            const int col = half ? ADJ_TX + lane : lane;
-            const R *w = win + zz * wx + col;
-            R acc = R(0);
-            if constexpr (HZ >= 0) {
-#pragma unroll
-                for (int k = 0; k < NTZ; k++) acc += rz[k] * w[k * wx];
-            } else {
-                for (int k = 0; k <= 2 * hz; k++) acc += tz[k] * w[k * wx];
-            }
-            mid[zz * wx + col] = acc;
-        }
-    }
-    __syncthreads();
-    for (int zz = wave; zz < rows_mid; zz += nwave) {
-        const R *m = mid + zz * wx + lane;
-        R acc = R(0);
+    // x filter: item (row r, output columns [4 q, 4 q + 4)) of wz x 16 items
+    constexpr int XQ = 4, NQ = ADJ_TX / XQ;
+    for (int it = threadIdx.x; it < wz * NQ; it += blockDim.x) {
+        const int r = it / NQ, c0 = (it % NQ) * XQ;
+        const R *w = win + r * wx + c0;
+        R *o = mid + r * ADJ_TX + c0;
         if constexpr (HX >= 0) {
+            R v[XQ + 2 * HX];
 #pragma unroll
-            for (int k = 0; k < NTX; k++) acc += rx[k] * m[k];
+            for (int k = 0; k < XQ + 2 * HX; k++) v[k] = w[k];
+#pragma unroll
+            for (int q = 0; q < XQ; q++) {
+                R acc = R(0);
+#pragma unroll
+                for (int k = 0; k < NTX; k++) acc += rx[k] * v[q + k];
+                o[q] = acc;
+            }
         } else {
-            for (int k = 0; k <= 2 * hx; k++) acc += tx[k] * m[k];
+            for (int q = 0; q < XQ; q++) {
+                R acc = R(0);
+                for (int k = 0; k <= 2 * hx; k++) acc += tx[k] * w[q + k];
+                o[q] = acc;
+            }
         }
-        lam[zz * ADJ_TX + lane] = acc;
     }
     __syncthreads();
-    const gp<const R> own = G<R>((const void *)(comp < 3 ? D.lE[comp] : D.lB[comp - 3]));
+    // z: output row zr + j of this column takes mid rows zr + j .. zr + j + 2 ez
     gp<R> dst = G<R>(D.T1[comp]);
+    const R *m = mid + zr * ADJ_TX + lane;
     constexpr int NJ = GRAD ? (DEG >= 0 ? DEG + 1 : 9) : 1;
     R gpart[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; j++) gpart[j] = R(0);
-    for (int zz = wave; zz < TZ; zz += nwave) {
-        const int xx = lane;
-        const int gx = x0 + xx, gz = z0 + zz;
-        if (gx >= nx || gz >= nz) continue;
-        const int g = gz * nx + gx;
+    R out[RB];
+    if constexpr (HZ >= 0 && (!GRAD || DEG >= 0)) {
+        constexpr int DG = GRAD ? DEG : 0, NL = RB + 2 * DG;
+        R v[NL + 2 * HZ];
+#pragma unroll
+        for (int k = 0; k < NL + 2 * HZ; k++) v[k] = m[k * ADJ_TX];
+        // z pass: rows zr - deg .. zr + RB + deg of Lambda (GRAD) or the output rows
+        R lz[NL];
+#pragma unroll
+        for (int i = 0; i < NL; i++) {
+            R acc = R(0);
+#pragma unroll
+            for (int k = 0; k < NTZ; k++) acc += rz[k] * v[i + k];
+            lz[i] = acc;
+        }
         if constexpr (GRAD) {
-            const R e1 = G<R>((const void *)D.E[0][comp])[g];
-            const R *l = lam + (zz + deg) * ADJ_TX + xx;
-            R add = R(0);
 #pragma unroll
-            for (int j = 0; j < NJ; j++) {
-                if (DEG < 0 && j > deg) break;
-                R tj = R(0);
+            for (int j = 0; j < RB; j++) {
+                R add = R(0);
 #pragma unroll
-                for (int k = -j; k <= j; k++) tj += (R)D.sj[j][8 + k] * l[k * ADJ_TX];
-                add += (R)D.psi_e[j] * tj;
-                gpart[j] += tj * e1;
+                for (int p = 0; p <= DG; p++) {
+                    R tj = R(0);
+#pragma unroll
+                    for (int k = -p; k <= p; k++) tj += (R)D.sj[p][8 + k] * lz[j + DG + k];
+                    add += (R)D.psi_e[p] * tj;
+                    gpart[p] += tj * pe1[j];
+                }
+                out[j] = add;
             }
-            dst[g] = own[g] + add;
         } else {
-            dst[g] = own[g] + lam[zz * ADJ_TX + xx];
+#pragma unroll
+            for (int j = 0; j < RB; j++) out[j] = lz[j];
+        }
+    } else {
+        // widths from the descriptor: the same sums read straight from LDS
+        auto ztap = [&](int q) -> R {
+            if constexpr (HZ >= 0) return rz[q];
+            else return tz[q];
+        };
+#pragma unroll
+        for (int j = 0; j < RB; j++) {
+            R add = R(0);
+            if constexpr (GRAD) {
+#pragma unroll
+                for (int p = 0; p < NJ; p++) {
+                    if (p > deg) break;
+                    R tj = R(0);
+                    for (int k = -p; k <= p; k++) {
+                        // Lambda at output row zr + j + k: mid rows zr + j + deg + k + [0, 2 hz]
+                        const R *mm = m + (j + deg + k) * ADJ_TX;
+                        R lam = R(0);
+                        for (int q = 0; q <= 2 * hz; q++) lam += ztap(q) * mm[q * ADJ_TX];
+                        tj += (R)D.sj[p][8 + k] * lam;
+                    }
+                    add += (R)D.psi_e[p] * tj;
+                    gpart[p] += tj * pe1[j];
+                }
+            } else {
+                const R *mm = m + j * ADJ_TX;
+                for (int q = 0; q <= 2 * hz; q++) add += ztap(q) * mm[q * ADJ_TX];
+            }
+            out[j] = add;
+        }
+    }
+    if (gx < nx) {
+#pragma unroll
+        for (int j = 0; j < RB; j++) {
+            const int gz = z0 + zr + j;
+            if (gz < nz) dst[gz * nx + gx] = pown[j] + out[j];
         }
     }
     if constexpr (GRAD) {
-        const int wave = wave_id(), lane = threadIdx.x & 63;
+        // columns beyond the grid (gx >= nx) read clamped E1 and must not count
+        if (gx >= nx)
+#pragma unroll
+            for (int j = 0; j < NJ; j++) gpart[j] = R(0);
 #pragma unroll
         for (int j = 0; j < NJ; j++) {
             if (DEG < 0 && j > deg) break;
@@ -876,8 +972,10 @@ __device__ __forceinline__ void adj_seen_body(const InstDesc *__restrict__ Dt, c
         __syncthreads();
         if (threadIdx.x <= deg) {
             const int j = threadIdx.x;
-            const double v = red[j][0] + red[j][1] + red[j][2] + red[j][3];
-            if (v != 0.0) unsafeAtomicAdd(&D.grad[j], v);
+            double v = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; w++) v += red[j][w];
+            if (v != 0.0) unsafeAtomicAdd(&D.grad[grad_copy() + j], v);
         }
     }
 }
@@ -1038,12 +1136,10 @@ int launch_adj_seed(const LaunchCtx &c, const int2 *fwork, int nfwork, const int
 // tile boxes; `live` the shared planes (identical for everything else).
 size_t adj_seen_smem_bytes(int fp32)
 {
-    // worst case halos: filter 8 passes, Psi degree 8 (GRAD) or combined z stencil 16
-    const int wx = ADJ_TX + 2 * PIC_MAX_HX, tz = PIC_ADJ_TZ;
-    const int rows_mid = tz + 2 * 8, wz = rows_mid + 2 * PIC_MAX_HX;
-    const int g = wx * wz + wx * rows_mid + ADJ_TX * rows_mid;
-    const int wz2 = tz + 2 * PIC_MAX_HZ, g2 = wx * wz2 + wx * tz + ADJ_TX * tz;
-    return (size_t)((g > g2 ? g : g2) + 2 * PIC_MAX_HZ + 1 + 2 * PIC_MAX_HX + 1) * (fp32 ? 4 : 8);
+    // worst case z halo: Psi degree + filter passes (GRAD) or the combined
+    // stencil, both at most PIC_MAX_HZ; x halo PIC_MAX_HX
+    const int wx = ADJ_TX + 2 * PIC_MAX_HX, wz = PIC_ADJ_TZ + 2 * PIC_MAX_HZ;
+    return (size_t)(wx * wz + ADJ_TX * wz + 2 * PIC_MAX_HZ + 1 + 2 * PIC_MAX_HX + 1) * (fp32 ? 4 : 8);
 }
 
 int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fwork, int nfwork, const int2 *swork,

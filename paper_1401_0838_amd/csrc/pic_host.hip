@@ -397,7 +397,7 @@ size_t layout(pic_state *s, const pic_config *cfgs, int n_inst, const int64_t *n
                 void *lu = L.take<char>(n * R);
                 if (D) { D->loff[a] = lo; D->lu[a] = lu; }
             }
-            double *g = L.take<double>(16);
+            double *g = L.take<double>(16 * PIC_GRAD_COPIES);
             if (D) { D->grad = g; D->loss = g + 9; }
             // same region order as the live arrays (see above)
             auto snap = [&](bool with_j, bool with_seen) {
@@ -1594,7 +1594,7 @@ extern "C" int pic_adjoint_forward(pic_state *s, int nsteps, double *loss)
     s->step += nsteps;
     // W of the final fields (the seed kernel also writes lambda_E, lambda_B, lambda_J)
     for (int i = 0; i < s->n_inst; i++)
-        HIP_TRY(hipMemsetAsync(s->desc[i].grad, 0, 16 * sizeof(double), s->stream));
+        HIP_TRY(hipMemsetAsync(s->desc[i].grad, 0, 16 * PIC_GRAD_COPIES * sizeof(double), s->stream));
     LaunchCtx live = ctx(s);
     if (launch_adj_seed(live, s->fwork, s->nfwork, s->cwork, s->ncwork)) return fail(PIC_EHIP, "seed");
     std::vector<double> g(16);
@@ -1634,11 +1634,16 @@ extern "C" int pic_adjoint_backward(pic_state *s, double *grad)
     s->no_resort = false;
     s->adj_pending = 0;
     if (rc) return rc;
-    std::vector<double> g(16);
+    std::vector<double> g(16 * PIC_GRAD_COPIES);
     for (int i = 0; i < s->n_inst; i++) {
-        HIP_TRY(hipMemcpyAsync(g.data(), s->desc[i].grad, 16 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipMemcpyAsync(g.data(), s->desc[i].grad, g.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
-        for (int j = 0; j < 9; j++) grad[i * 9 + j] = j <= s->desc[i].psi_deg ? g[j] : 0.0;
+        for (int j = 0; j < 9; j++) {
+            double v = 0.0;
+            for (int k = 0; k < PIC_GRAD_COPIES; k++) v += g[16 * k + j];
+            grad[i * 9 + j] = j <= s->desc[i].psi_deg ? v : 0.0;
+        }
     }
     return PIC_OK;
 }

@@ -7,6 +7,7 @@
 #define PIC_MAX_HZ 16           // half-width of the combined z stencil (Psi degree + passes)
 #define PIC_MAX_HX 8            // half-width of the x / y filter stencils
 #define PIC_FIELD_CHUNK 256     // cells per field work item
+#define PIC_GRAD_COPIES 64      // copies of the gradient sums (power of two)
 #define PIC_PART_CHUNK 256      // particles per particle-chunk work item
 #define PIC_SEEN_TX 64          // 2D seen-field tile (x)
 #define PIC_TILE_SLACK 4        // cells a tile's particle bounding box may grow before a re-sort
@@ -99,7 +100,7 @@ struct InstDesc {
     // reverse mode (null unless gradient runs were planned)
     void *lE[3], *lB[3], *lJ[3], *lEt[3], *lBt[3];   // adjoint grid planes
     void *loff[3], *lu[3];                            // adjoint particle offsets / momenta
-    double *grad;          // dW/dpsi_e[j], 9 slots
+    double *grad;          // dW/dpsi_e[j]: PIC_GRAD_COPIES copies of 16 slots (j < 9), summed on the host
     double *loss;          // W
     int psi_deg, hzf;
     double tzf[2 * PIC_MAX_HZ + 1];  // z filter taps alone
