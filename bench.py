@@ -191,19 +191,21 @@ def batched_headline(steps, warmup, profile_steps):
     # the plain schedules first (same steps), so that the batched run is timed on a
     # GPU whose clocks have left their idle state
     for graph in (False, True):
-        sim = Simulation(wls, parts, precision="fp32")
+        sim = Simulation(wls, parts, precision="fp32", tuned=True)
         sim.set_schedule("plain", graph)
         sim.step(warmup)
         out["plain_%s_s" % ("graph" if graph else "eager")] = timed(sim, steps)
         sim.close()
-    sim = Simulation(wls, parts, precision="fp32")
+    sim = Simulation(wls, parts, precision="fp32", tuned=True)
     sim.set_schedule("batched", True)
+    out["tuning"] = sim.tuning
     sim.prepare(warmup)
     # per-kernel durations (HIP events, eager steps) on a second, identical batch,
     # measured right before the timed run: its 2 x profile_steps steps also bring
     # the GPU's clocks from the idle of the host setup to their sustained state
     # (see clock_preheat), so the timed sample is not the ramp
-    ps = Simulation(wls, parts, precision="fp32")
+    ps = Simulation(wls, parts, precision="fp32", tuned=True)
+    ps.set_schedule("batched", True)
     ps.step(profile_steps)
     prof = ps.profile(profile_steps)
     ps.close()
@@ -226,7 +228,8 @@ def batched_steps_only(steps, warmup):
     wls = batch_instances(lambda c: L.pic_psi_coeffs(L.PIC_GALERKIN, c["alpha"], 4)[0] == L.PIC_OK)
     parts = [pi.load_beam(2, w["n"], w["ppc"], w["gamma"], w["sigma"], w["seeds"][0]) for w in wls]
     n_part = sum(p[0].shape[0] for p in parts)
-    sim = Simulation(wls, parts, precision="fp32")
+    sim = Simulation(wls, parts, precision="fp32", tuned=True)
+    sim.set_schedule("batched", True)
     sim.step(warmup)
     dt = timed(sim, steps)
     sim.close()
@@ -242,11 +245,12 @@ def adjoint_block():
     wl = pi.workload("beam2d_256_adjoint")
     x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], wl["sigma"], 0)
     n, k = wl["steps"], wl["checkpoint"]
-    fwd = Simulation(wl, (x, u), precision="fp32")
+    fwd = Simulation(wl, (x, u), precision="fp32", tuned=True)
     fwd.step(5)
     t_step = timed(fwd, n)
     fwd.close()
-    sim = Simulation(wl, (x, u), precision="fp32", adjoint_steps=n, adjoint_ckpt=k)
+    sim = Simulation(wl, (x, u), precision="fp32", adjoint_steps=n, adjoint_ckpt=k, tuned=True)
+    tuning = sim.tuning
     sim.adjoint_forward(k)
     sim.adjoint_backward()
     sim.synchronize()
@@ -258,7 +262,7 @@ def adjoint_block():
     t_b = time.perf_counter() - t0
     sim.close()
     return {"steps": n, "checkpoint_every": k, "forward_s": t_step, "forward_with_checkpoints_s": t_f,
-            "backward_s": t_b, "ratio": t_b / t_step}
+            "backward_s": t_b, "ratio": t_b / t_step, "tuning": tuning}
 
 
 def single_block(wl, steps, warmup, word=4, state_bytes=24, precision="fp32"):
@@ -267,7 +271,8 @@ def single_block(wl, steps, warmup, word=4, state_bytes=24, precision="fp32"):
     import pic_inputs as pi
     from paper_1401_0838_amd.sim import Simulation
     x, u = pi.load_beam(wl["dims"], wl["n"], wl["ppc"], wl["gamma"], wl["sigma"], 0)
-    sim = Simulation(wl, (x, u), precision=precision)
+    sim = Simulation(wl, (x, u), precision=precision, tuned=True)
+    tuning = sim.tuning
     n_part = x.shape[0]
     n_cells = 1
     for v in wl["n"]:
@@ -281,7 +286,8 @@ def single_block(wl, steps, warmup, word=4, state_bytes=24, precision="fp32"):
     return {"particles": n_part, "particle_steps_per_s": n_part * steps / dt, "ms_per_step": 1e3 * dt / steps,
             "grid_cell_updates_per_s": n_cells * steps / dt,
             "kernels_ms": {k: round(prof[k], 5) for k in ("yee_ms", "seen_ms", "particle_ms")},
-            "particle_kernel_hbm_frac": pk / (prof["particle_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            "particle_kernel_hbm_frac": pk / (prof["particle_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "tuning": tuning}
 
 
 def extra_blocks():
@@ -318,14 +324,15 @@ def gamma_scan_block(steps):
         base = pi.workload("beam2d_128_ck", correction=corr)
         pts, wls, parts, skipped = scan.scan_instances(base, alphas, gammas)
         n_part = sum(p[0].shape[0] for p in parts)
+        info = {}
         t0 = time.perf_counter()
-        traces, wkin = scan.run_scan(pts, wls, parts, steps, "fp32")
+        traces, wkin = scan.run_scan(pts, wls, parts, steps, "fp32", info)
         dt = time.perf_counter() - t0
         rates, peaks, power = scan.growth_table(pts, traces, wkin)
         out["corrected" if corr else "uncorrected"] = {
             "instances": len(pts), "skipped": skipped, "particle_steps_per_s": n_part * steps / dt,
             "peak_growth": {"%g" % g: {"rate": v[0], "alpha": v[1]} for g, v in sorted(peaks.items())},
-            "peak_power_of_gamma": power}
+            "peak_power_of_gamma": power, "tuning": info["tuning"][0]}
     return out
 
 
@@ -335,11 +342,55 @@ def variants_block(steps):
     import pic_inputs as pi
     from paper_1401_0838_amd import scan
     alphas = [0.5, 0.7, 0.9, 0.99]
-    rates, skipped = scan.variant_sweep(pi.workload("beam2d_128_ck"), alphas, 130.0, steps)
+    info = {}
+    rates, skipped = scan.variant_sweep(pi.workload("beam2d_128_ck"), alphas, 130.0, steps, info=info)
     base = rates["baseline"]
-    return {"steps": steps, "alphas": alphas, "gamma": 130.0, "skipped": skipped,
+    return {"steps": steps, "alphas": alphas, "gamma": 130.0, "skipped": skipped, "tuning": info["tuning"],
             "over_baseline": {k: [None if (x is None or y in (None, 0)) else x / y for x, y in zip(v, base)]
                               for k, v in rates.items() if k != "baseline"}}
+
+
+def tune_configs():
+    """Run the autotuner (tune.py) on every workload this bench times and store its
+    picks in the package's tune cache, which the timed blocks then read."""
+    import pic_inputs as pi
+    from paper_1401_0838_amd import _lib as L
+    from paper_1401_0838_amd import scan, tune
+    if os.path.exists(tune.CACHE):
+        os.remove(tune.CACHE)
+
+    def beam(wl, seed=0):
+        return pi.load_beam(wl["dims"], wl["n"], wl["ppc"], wl["gamma"], wl["sigma"], seed)
+
+    def jobs():
+        wls = batch_instances(lambda c: L.pic_psi_coeffs(L.PIC_GALERKIN, c["alpha"], 4)[0] == L.PIC_OK)
+        yield "batched64_uneven_2d_ppc8_fp32", wls, [beam(w, w["seeds"][0]) for w in wls], "fp32"
+        wl = pi.workload("beam2d_256_adjoint")
+        yield "beam2d_256_adjoint", [wl], [beam(wl)], "fp32"
+        singles = [("beam2d_512_fp32", pi.workload("beam2d_512", alpha=0.5), "fp32"),
+                   ("beam2d_512_fp64", pi.workload("beam2d_512", alpha=0.5, precision="fp64"), "fp64"),
+                   ("beam3d_128x128x256_cubic", pi.workload("beam3d_128x128x256"), "fp32"),
+                   ("beam2d_512_uniform", pi.workload("beam2d_512", alpha=0.5, interp="uniform"), "fp32"),
+                   ("beam2d_512_momentum", pi.workload("beam2d_512", alpha=0.5, interp="momentum"), "fp32"),
+                   ("beam2d_512_exact_ratio", pi.workload("beam2d_512", alpha=0.5, correction="ratio"), "fp32"),
+                   ("beam2d_512_ck_alpha0.9", pi.workload("beam2d_512", alpha=0.9, solver="ck"), "fp32"),
+                   ("beam2d_128_ck_cubic_eq6", pi.workload("beam2d_128_ck"), "fp32")]
+        for name, wl, prec in singles:
+            yield name, [wl], [beam(wl)], prec
+        for corr in (True, False):
+            pts, wls, parts, _ = scan.scan_instances(pi.workload("beam2d_128_ck", correction=corr),
+                                                     [0.3, 0.5, 0.6, 0.7, 0.8, 0.9, 0.95, 0.99],
+                                                     [3.0, 10.0, 30.0, 130.0])
+            yield "gamma_scan_%s" % ("corrected" if corr else "uncorrected"), wls, parts, "fp32"
+        for i, (pts, wls, parts, tags, _) in enumerate(scan.variant_batches(pi.workload("beam2d_128_ck"),
+                                                                              [0.5, 0.7, 0.9, 0.99], 130.0)):
+            yield "variants_%d" % i, wls, parts, "fp32"
+
+    for name, wls, parts, prec in jobs():
+        t0 = time.perf_counter()
+        best = tune.tune(wls, parts, precision=prec, steps=20, warmup=30)
+        print(json.dumps({"tuned": name, "key": tune.key(wls, prec), "pick": best,
+                          "seconds": round(time.perf_counter() - t0, 1)}), flush=True)
 
 
 def copy_calibration(gib=1.0, reps=5):
@@ -368,6 +419,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint cost ratio")
     ap.add_argument("--extra", action="store_true", help="also time the secondary workloads")
+    ap.add_argument("--tune", action="store_true",
+                    help="only run the autotuner on every timed workload and rewrite its cache")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling HBM counters)")
     ap.add_argument("--only", choices=("batched", "adjoint", "extra", "cpu", "step"),
@@ -381,6 +434,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.tune:
+        tune_configs()
         return
     if args.only:
         blk = {"batched": lambda: batched_headline(args.steps, args.warmup, args.profile_steps),
@@ -438,6 +494,7 @@ def main():
                           "unit": "GB/s", "frac": sb / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           "bytes_per_step": sb, "bytes_per_particle_step": sb / n_part},
         "kernels_ms": b["kernels_ms"],
+        "tuning": b["tuning"],
         "particle_kernel_valu": valu_issue("batched64_fp32", n_part, pk_ms),
         "gauss_linf_rel_max": b["gauss_linf_rel_max"],
         "kernel_profile_before_timing_steps": 2 * args.profile_steps,

@@ -44,11 +44,15 @@ def scan_instances(base, alphas, gammas, seed=0):
     return points, wls, parts, skipped
 
 
-def run_scan(points, wls, parts, nsteps, precision="fp32"):
-    """Step every instance nsteps in one batched run; return the transverse
-    field-energy traces (list of arrays) and each instance's initial kinetic energy."""
+def run_scan(points, wls, parts, nsteps, precision="fp32", info=None):
+    """Step every instance nsteps in one batched run (tile, launch options and
+    schedule from the autotuner's cache when it has the batch); return the
+    transverse field-energy traces (list of arrays) and each instance's initial
+    kinetic energy.  info (a dict), if given, collects the tuner's picks."""
     from .sim import Simulation
-    sim = Simulation(wls, parts, precision=precision, trace_capacity=nsteps)
+    sim = Simulation(wls, parts, precision=precision, trace_capacity=nsteps, tuned=True)
+    if info is not None:
+        info.setdefault("tuning", []).append(sim.tuning)
     try:
         wkin = [sim.diag(i)["Wkin"] for i in range(len(wls))]
         sim.step(nsteps)
@@ -88,17 +92,15 @@ def _variants():
 VARIANTS = _variants()
 
 
-def variant_sweep(base, alphas, gamma, nsteps, precision="fp32", seed=0):
-    """Growth rate of every variant at every alpha (one gamma).  Variants that
-    share the split correction run as one batch; the exact-ratio one as another
-    (a batch shares that choice).  Returns {variant: [rate per alpha]} and the
-    points skipped for a broken-down correction."""
+def variant_batches(base, alphas, gamma, seed=0):
+    """The batches of a variant sweep: variants that share the split correction
+    form one, the exact-ratio one another (a batch shares that choice).  Yields
+    (points, workloads, particles, variant of each instance, skipped points)."""
     groups = {}
     for name, over in VARIANTS.items():
         groups.setdefault(over["correction"] == "ratio", []).append(name)
-    rates, skipped = {}, []
     for names in groups.values():
-        pts, wls, parts, tags = [], [], [], []
+        pts, wls, parts, tags, skipped = [], [], [], [], []
         for name in names:
             p, w, pa, sk = scan_instances(dict(base, **VARIANTS[name]), alphas, [gamma], seed)
             pts += p
@@ -106,7 +108,18 @@ def variant_sweep(base, alphas, gamma, nsteps, precision="fp32", seed=0):
             parts += pa
             tags += [name] * len(p)
             skipped += [(name,) + k for k in sk]
-        traces, wkin = run_scan(pts, wls, parts, nsteps, precision)
+        yield pts, wls, parts, tags, skipped
+
+
+def variant_sweep(base, alphas, gamma, nsteps, precision="fp32", seed=0, info=None):
+    """Growth rate of every variant at every alpha (one gamma).  Variants that
+    share the split correction run as one batch; the exact-ratio one as another
+    (a batch shares that choice).  Returns {variant: [rate per alpha]} and the
+    points skipped for a broken-down correction."""
+    rates, skipped = {}, []
+    for pts, wls, parts, tags, sk in variant_batches(base, alphas, gamma, seed):
+        skipped += sk
+        traces, wkin = run_scan(pts, wls, parts, nsteps, precision, info)
         r, _, _ = growth_table(pts, traces, wkin)
         for name, (g, a), v in zip(tags, pts, r):
             rates.setdefault(name, {})[a] = v

@@ -83,17 +83,29 @@ class Simulation:
     static_arena : take the arena from the library's static device array
                    (pic_init_static, 64 MiB, one live state per device) instead
                    of allocating it
+    tuned : take the tile, workgroup size, launch options and schedule from
+            the autotuner's cache (tune.py; the tuner is not run here).  The
+            entry, or None when the batch has none, is kept in self.tuning
     """
 
     def __init__(self, workloads, particles, precision=None, tile=None, block=0,
                  trace_capacity=0, psi=None, stream=None, adjoint_steps=0, adjoint_ckpt=20,
-                 static_arena=False):
+                 static_arena=False, tuned=False):
         torch = _require_gpu()
         L.load()
         if isinstance(workloads, dict):
             workloads, particles = [workloads], [particles]
         self.workloads = list(workloads)
         self.dims = int(self.workloads[0]["dims"])
+        self.tuning = None
+        pick = None
+        if tuned:
+            from . import tune
+            prec = precision or self.workloads[0].get("precision", "fp32")
+            pick = tune.lookup(self.workloads, prec)
+            self.tuning = {"key": tune.key(self.workloads, prec), "pick": pick}
+            if pick is not None and tile is None and not block:
+                tile, block = tuple(pick["tile"]), int(pick["block"])
         self.cfgs = [make_config(wl, precision, tile, block, trace_capacity,
                                  None if psi is None else psi[i], adjoint_steps, adjoint_ckpt)
                      for i, wl in enumerate(self.workloads)]
@@ -130,6 +142,10 @@ class Simulation:
         else:
             self.st = L.pic_init(self.cfgs, parts, aligned, nbytes, self.stream.cuda_stream)
         self.steps_taken = 0
+        if pick is not None:
+            for name, value in pick.get("options", {}).items():
+                self.set_option(name, value)
+            self.set_schedule(pick.get("schedule", "batched"), True)
 
     # ------------------------------------------------------------ stepping
     def step(self, n=1):

@@ -12,6 +12,7 @@ import json
 import os
 import time
 
+from . import _lib as L
 from .sim import Simulation
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
@@ -21,16 +22,32 @@ CANDIDATES_2D = [((16, 1, 16), 256), ((16, 1, 16), 512), ((32, 1, 16), 256), ((1
 CANDIDATES_3D = [((8, 4, 4), 256), ((8, 2, 4), 256), ((4, 4, 8), 256), ((8, 8, 4), 256), ((4, 4, 4), 256)]
 # launch options tried with the chosen tile ({} = the library's defaults);
 # every one leaves the results unchanged
+# (the field-tile heights and particle launch forms are bitwise neutral; the
+# re-sort period changes which tile deposits a particle, so FP32 results move
+# within rounding)
 OPTIONS_2D = [{}, {"seen_tile_z": 16, "yee_tile_z": 8}, {"seen_tile_z": 32}, {"seen_tile_z": 32, "yee_tile_z": 16},
-              {"particle_defer": 0}, {"particle_defer": 1}]
-OPTIONS_3D = [{}]
+              {"seen_tile_z": 64, "yee_tile_z": 16}, {"particle_defer": 0}, {"particle_defer": 1},
+              {"particle_prefetch": 1}, {"particle_waves4": 1}, {"resort_every": 8}, {"resort_every": 32}]
+OPTIONS_3D = [{}, {"resort_every": 8}, {"resort_every": 32}]
 
 
 def key(workloads, precision):
+    """Cache key: dimensions, order, density, precision, scheme (gather, solver,
+    correction) and the batch's size and leading grid shapes."""
     w = workloads[0]
     sizes = sorted(tuple(x["n"]) for x in workloads)
-    return "%dd_o%d_ppc%d_%s_n%d_%s" % (w["dims"], w["order"], w["ppc"], precision, len(workloads),
-                                        "-".join("x".join(map(str, s)) for s in sizes[:4]))
+    corr = w.get("correction")
+    scheme = "%s-%s-%s" % (w.get("interp", "galerkin"), w.get("solver", "yee"),
+                           "ratio" if corr == "ratio" else ("psi" if corr else "none"))
+    return "%dd_o%d_ppc%d_%s_%s_n%d_%s" % (w["dims"], w["order"], w["ppc"], precision, scheme, len(workloads),
+                                           "-".join("x".join(map(str, s)) for s in sizes[:4]))
+
+
+def lookup(workloads, precision, cache=CACHE):
+    """The cached tuning of these workloads, or None; never runs the tuner."""
+    if isinstance(workloads, dict):
+        workloads = [workloads]
+    return _load_cache(cache).get(key(workloads, precision)) if cache else None
 
 
 def _load_cache(path):
@@ -62,7 +79,12 @@ def tune(workloads, particles, precision="fp32", steps=10, warmup=3, cache=CACHE
     cands = candidates or (CANDIDATES_2D if dims == 2 else CANDIDATES_3D)
     best = None
     for tile, block in cands:
-        sim = Simulation(workloads, particles, precision=precision, tile=tile, block=block)
+        if dims == 3 and any(t > n for t, n in zip(tile, workloads[0]["n"])):
+            continue
+        try:
+            sim = Simulation(workloads, particles, precision=precision, tile=tile, block=block)
+        except L.PicError:
+            continue                # e.g. a tile window that does not fit in LDS
         sim.step(warmup)
         prof = sim.profile(steps)
         sim.close()
@@ -71,6 +93,8 @@ def tune(workloads, particles, precision="fp32", steps=10, warmup=3, cache=CACHE
     best["options"] = {}
     for opts in (options if options is not None else (OPTIONS_2D if dims == 2 else OPTIONS_3D)):
         if not opts:
+            continue
+        if precision != "fp32" and any(k in opts for k in ("particle_prefetch", "particle_waves4")):
             continue
         sim = Simulation(workloads, particles, precision=precision, tile=best["tile"], block=best["block"])
         apply_options(sim, opts)

@@ -50,3 +50,25 @@ def test_stored_counters_follow_the_kernel_source(tmp_path, monkeypatch):
     (tmp_path / "valu_k_particles.json").write_text(json.dumps(doc))
     assert bench.valu_issue("w", 1000, 1e-3) is None
 
+
+
+def test_tune_cache_has_the_timed_workloads():
+    # the shipped cache (written by `bench.py --tune` on the GPU) holds a pick for
+    # the headline batch and the adjoint workload, and keys tell schemes apart
+    import pic_inputs as pi
+    from paper_1401_0838_amd import _lib as L
+    from paper_1401_0838_amd import tune
+    wls = bench.batch_instances(lambda c: L.pic_psi_coeffs(L.PIC_GALERKIN, c["alpha"], 4)[0] == L.PIC_OK)
+    for w, prec in ((wls, "fp32"), ([pi.workload("beam2d_256_adjoint")], "fp32"),
+                    ([pi.workload("beam3d_128x128x256")], "fp32"),
+                    ([pi.workload("beam2d_512", alpha=0.5, precision="fp64")], "fp64")):
+        pick = tune.lookup(w, prec)
+        assert pick is not None, tune.key(w, prec)
+        assert len(pick["tile"]) == 3 and pick["block"] in (256, 512) and pick["schedule"] in ("batched", "plain")
+        assert set(pick["options"]) <= {"seen_tile_z", "yee_tile_z", "particle_defer", "particle_prefetch",
+                                        "particle_waves4", "resort_every"}
+    base = pi.workload("beam2d_512", alpha=0.5)
+    keys = {tune.key([pi.workload("beam2d_512", alpha=0.5, **kw)], "fp32")
+            for kw in ({}, {"interp": "uniform"}, {"solver": "ck"}, {"correction": "ratio"}, {"correction": False})}
+    assert len(keys) == 5 and tune.key([base], "fp32") != tune.key([base], "fp64")
+    assert tune.lookup([base], "fp32", cache=None) is None
