@@ -144,7 +144,7 @@ typedef struct pic_config {
                                  3D 8x4x4 linear, 8x2x4 cubic) */
     int    block;             /* threads per particle workgroup: 0 (default), 256 or 512 */
     int    trace_capacity;    /* steps of per-step field-energy trace kept on the device */
-    int    adjoint_steps;     /* longest gradient run pic_wperp_gradient may do (0: none) */
+    int    adjoint_steps;     /* longest gradient run pic_adjoint_forward may do (0: none) */
     int    adjoint_ckpt;      /* checkpoint interval of gradient runs (steps, >= 1) */
     int    solver;            /* PIC_YEE or PIC_CK; equal for all instances */
 } pic_config;
@@ -255,8 +255,10 @@ int pic_set_schedule(pic_state *st, int sched, int use_graph);
  *   "yee_tile_z"     rows of the 2D Yee tile: 4, 8 or 16 (16 is float only);
  *                    default 8, or 16 for FP32 batches of more than 4 * 512^2 cells
  *   "seen_tile_z"    rows of the 2D seen-field tile: 8, 16, 32 or 64 (32 and 64
- *                    are float only); default 16, or 32 for FP32 batches of more
- *                    than 4 * 512^2 cells
+ *                    are float only), or 128: float segments of 128 rows streamed
+ *                    in 32-row chunks (with the usual stencil widths, else 32);
+ *                    default 16, or 128 (32 where the widths differ) for FP32
+ *                    batches of more than 4 * 512^2 cells
  *   "resort_every"   steps between tile re-sort checks (and per captured graph);
  *                    default 16
  *   "particle_block" threads per particle workgroup: 256 or 512
@@ -320,7 +322,10 @@ int pic_profile(pic_state *st, int nsteps, pic_timing_t *out);
  * recomputed from its checkpoint while its per-step tape is recorded, and its
  * steps are reversed with hand-written adjoint kernels (exact transposes of
  * the Yee update, the correction and filter stencils, the gather, the Boris
- * push, the move and the Esirkepov deposit).  grad[i*9 + j] receives
+ * push, the move and the Esirkepov deposit).  In 2D a segment is recomputed
+ * on the bound stream while the one after it is reversed on a second stream
+ * (default priority, created by the first call and kept until pic_destroy);
+ * the arena holds two segments of tape for that.  grad[i*9 + j] receives
  * dW/dpsi_e[j] of instance i (zero for j > psi_deg).  On return the state is
  * again the forward state after the nsteps steps.  Both calls synchronise. */
 int pic_adjoint_forward(pic_state *st, int nsteps, double *loss);

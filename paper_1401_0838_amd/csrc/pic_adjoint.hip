@@ -515,15 +515,16 @@ __global__ void __launch_bounds__(256) k_adj_particles(const InstDesc *__restric
         // index clamped to the tile's last particle, so every load is valid)
         unsigned nidx = 0;
         R nu[3], nlu[3], noff[3], nloff[3];
+        // (streamed state: non-temporal loads and stores, as in the forward kernel)
         auto fetch = [&](int q) {
-            nidx = pidx[q];
+            nidx = __builtin_nontemporal_load(&pidx[q]);
 #pragma unroll
             for (int a = 0; a < 3; a++) {
-                nu[a] = pu[a][q];
-                nlu[a] = plu[a][q];
+                nu[a] = __builtin_nontemporal_load(&pu[a][q]);
+                nlu[a] = __builtin_nontemporal_load(&plu[a][q]);
                 if (DIM == 2 && a == 1) { noff[a] = R(0); nloff[a] = R(0); continue; }
-                noff[a] = po[a][q];
-                nloff[a] = plo[a][q];
+                noff[a] = __builtin_nontemporal_load(&po[a][q]);
+                nloff[a] = __builtin_nontemporal_load(&plo[a][q]);
             }
         };
         if (p0 + tid < p1) fetch(p0 + tid);
@@ -548,8 +549,8 @@ __global__ void __launch_bounds__(256) k_adj_particles(const InstDesc *__restric
             else adjoint_particle<DIM, L, R, IP>(gw, lc, off, u, loff, lu, dtd, qdt2m, cdr, cyr);
 #pragma unroll
             for (int a = 0; a < 3; a++) {
-                plu[a][p] = lu[a];
-                if (!(DIM == 2 && a == 1)) plo[a][p] = loff[a];
+                __builtin_nontemporal_store(lu[a], &plu[a][p]);
+                if (!(DIM == 2 && a == 1)) __builtin_nontemporal_store(loff[a], &plo[a][p]);
             }
         }
         __syncthreads();
@@ -995,7 +996,9 @@ __global__ void __launch_bounds__(256) k_adj_seen_2d(const InstDesc *__restrict_
 // CK: with the Cole-Karkkainen curl, the transposed Faraday curl averages each
 // backward difference across its direction with (1/8, 3/4, 1/8); the window
 // grows by two cells on the high side: lambda_E' on [-1, T+1], lambda_B'' on [-1, T].
-template <class R, int TZ, bool CK = false>
+// SPLIT blocks share one work item (a tile of SPLIT * TZ rows), TZ rows each:
+// more blocks for the small grids the reverse sweep runs on.
+template <class R, int TZ, bool CK = false, int SPLIT = 1>
 __global__ void __launch_bounds__(256) k_adj_yee_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work)
 {
     constexpr int TX = PIC_YEE_TX;
@@ -1005,11 +1008,12 @@ __global__ void __launch_bounds__(256) k_adj_yee_2d(const InstDesc *__restrict__
     constexpr int EHX = TX + (CK ? 4 : 3), EHZ = TZ + (CK ? 4 : 3);
     constexpr int BHX = TX + (CK ? 3 : 2), BHZ = TZ + (CK ? 3 : 2);
     __shared__ R sE[3][WN], sB[3][WN];
-    const int inst = work[blockIdx.x].x, t = work[blockIdx.x].y;
+    const int item = blockIdx.x / SPLIT, part = blockIdx.x % SPLIT;
+    const int inst = work[item].x, t = work[item].y;
     const InstDesc &D = Dt[inst];
     const int nx = D.n[0], nz = D.n[2];
     const int ntx = (nx + TX - 1) / TX;
-    const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
+    const int x0 = (t % ntx) * TX, z0 = (t / ntx) * (TZ * SPLIT) + part * TZ;
     const int lane = threadIdx.x & 63, wave = wave_id(), nwave = blockDim.x >> 6;
     // inputs: lambda_E, lambda_B as left in T1 by the reverse seen kernels
     const gp<const R> in[6] = {G<R>((const void *)D.T1[0]), G<R>((const void *)D.T1[1]), G<R>((const void *)D.T1[2]),
@@ -1181,8 +1185,9 @@ int launch_adj_step(const LaunchCtx &live, const LaunchCtx &tape, const int2 *fw
                 k_adj_seen_2d<R, PIC_ADJ_TZ, 4, 4, 4, 8><<<g6a, bf, sm, st>>>(tape.desc, awork);
             else
                 k_adj_seen_2d<R, PIC_ADJ_TZ, -1, -1, -1, -1><<<g6a, bf, sm, st>>>(tape.desc, awork);
-            if (live.ck) k_adj_yee_2d<R, PIC_ADJ_TZ, true><<<dim3(nawork), bf, 0, st>>>(live.desc, awork);
-            else k_adj_yee_2d<R, PIC_ADJ_TZ, false><<<dim3(nawork), bf, 0, st>>>(live.desc, awork);
+            // reverse Yee on half tiles (64 x 4 rows): twice the blocks
+            if (live.ck) k_adj_yee_2d<R, PIC_ADJ_TZ / 2, true, 2><<<dim3(2 * nawork), bf, 0, st>>>(live.desc, awork);
+            else k_adj_yee_2d<R, PIC_ADJ_TZ / 2, false, 2><<<dim3(2 * nawork), bf, 0, st>>>(live.desc, awork);
         } else {
             // lambda_E += M_E lambda_Et, lambda_B += M_B lambda_Bt
             k_pass<2, R><<<g6, bf, 0, st>>>(live.desc, fwork, PL_LSEEN, PL_T1, 0, 0);

@@ -144,6 +144,7 @@ struct LaunchCtx {
     // seen-stencil half-widths and Psi degree shared by every instance (-1: they differ)
     int hz = -1, hx = -1, hzf = -1, psi_deg = -1;
     const int *any_resort = nullptr;  // device word: a re-sort is pending
+    const int *defer = nullptr;       // deferred-tile list (count, done count, pairs)
     int record = 0;                   // 2D: descriptors carry tape-recording pointers
     // parity of the current E, B (and of the J they were advanced with): the
     // Yee launch reads set par and writes set par ^ 1; every later launch of the
@@ -172,6 +173,16 @@ int launch_particles(const LaunchCtx &c, const int2 *pwork, int nwork, int grid,
 size_t particle_smem_bytes(int dims, int fp32, const int wmax[3]);
 // clear_any: the last re-sort launch of a step clears the shared pending word
 int launch_resort(const LaunchCtx &c, const int2 *cwork, int ncwork, int n_inst_first, int n_inst, int clear_any);
+// up to PIC_COPY_LIST device-to-device copies (16-byte aligned addresses,
+// sizes a multiple of 4 bytes) in one launch
+#define PIC_COPY_LIST 4
+struct CopyList {
+    const void *src[PIC_COPY_LIST];
+    void *dst[PIC_COPY_LIST];
+    long long bytes[PIC_COPY_LIST];
+    int n = 0;
+};
+int launch_copy_list(hipStream_t st, const CopyList &L);
 int launch_rho(const LaunchCtx &c, const int2 *pwork, int npwork, const int2 *fwork, int nfwork, const int wmax[3],
                int to_rho0);
 int launch_diag(const LaunchCtx &c, const int2 *fwork, int nfwork, const int2 *pwork, int npwork, const int wmax[3]);

@@ -26,9 +26,10 @@ CANDIDATES_3D = [((8, 4, 4), 256), ((8, 2, 4), 256), ((4, 4, 8), 256), ((8, 8, 4
 # re-sort period changes which tile deposits a particle, so FP32 results move
 # within rounding)
 OPTIONS_2D = [{}, {"seen_tile_z": 16, "yee_tile_z": 8}, {"seen_tile_z": 32}, {"seen_tile_z": 32, "yee_tile_z": 16},
-              {"seen_tile_z": 64, "yee_tile_z": 16}, {"particle_defer": 0}, {"particle_defer": 1},
+              {"seen_tile_z": 64, "yee_tile_z": 16}, {"seen_tile_z": 128}, {"particle_defer": 0}, {"particle_defer": 1},
               {"particle_prefetch": 1}, {"particle_waves4": 1}, {"resort_every": 8}, {"resort_every": 32}]
 OPTIONS_3D = [{}, {"resort_every": 8}, {"resort_every": 32}]
+MARGIN = 0.01
 
 
 def key(workloads, precision):
@@ -101,7 +102,9 @@ def tune(workloads, particles, precision="fp32", steps=10, warmup=3, cache=CACHE
         sim.step(warmup)
         prof = sim.profile(steps)
         sim.close()
-        if prof["step_ms"] < best["step_ms"]:
+        # a set replaces the library's defaults only when it is clearly faster
+        # (run-to-run spread of these short timings is about 1 %)
+        if prof["step_ms"] < best["step_ms"] * (1.0 - MARGIN):
             best["options"], best["step_ms"] = dict(opts), prof["step_ms"]
     best["schedule"] = "batched"
     if len(workloads) > 1:

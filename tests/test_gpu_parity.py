@@ -442,6 +442,30 @@ def test_full_size_512_fp32_parity_10_steps():
     sim.close()
 
 
+@pytest.mark.parametrize("n,interp", [((96, 80), "galerkin"), ((64, 160), "momentum"), ((200, 264), "galerkin")])
+def test_streamed_seen_fields_equal_the_tiled_ones(n, interp):
+    """The 128-row streamed seen-field pass (32-row chunks, a ring of x-filtered
+    rows) computes the same sums in the same order as the tiled pass: bitwise
+    equal seen fields, also on grids with a ragged last chunk (nz = 80, 264), a
+    ragged strip (nx = 96, 200), a segment shorter than 128 rows and the wider
+    stencil of the momentum-conserving gather."""
+    wl = pi.workload("beam2d_512", n=n, ppc=2, interp=interp)
+    x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], 1e-3, 5)
+    out = []
+    for tz in (None, 128):
+        sim = _sim(wl, (x, u), precision="fp32")
+        if tz:
+            sim.set_option("seen_tile_z", tz)
+            assert sim.get_option("seen_tile_z") == tz
+        sim.step(3)
+        out.append((sim.fields("Et"), sim.fields("Bt"), sim.fields("E")))
+        sim.close()
+    _say("streamed seen %s %s: max |diff| %g" % (n, interp, max(float(np.max(np.abs(a - b)))
+                                                                  for a, b in zip(*out))))
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
 def test_tuning_knobs_leave_fp32_results_bitwise_unchanged():
     """Workgroup size, field tile heights, the particle-kernel variants and the
     inline or deferred form change only the schedule: every FP32 result is
@@ -454,7 +478,7 @@ def test_tuning_knobs_leave_fp32_results_bitwise_unchanged():
     wl = pi.workload("beam2d_512", n=(128, 96), ppc=4)
     x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], 1e-3, 11)
     runs = [(dict(), True), (dict(block=512), True),
-            (dict(opts={"yee_tile_z": 4, "seen_tile_z": 32}), True),
+            (dict(opts={"yee_tile_z": 4, "seen_tile_z": 32}), True), (dict(opts={"seen_tile_z": 128}), True),
             (dict(opts={"particle_waves4": 1}), True), (dict(opts={"particle_prefetch": 1}), True),
             (dict(opts={"particle_waves4": 1, "particle_prefetch": 1}), True),
             (dict(opts={"particle_defer": 1}), True), (dict(opts={"particle_defer": 0}), True),
