@@ -350,6 +350,11 @@ def variants_block(steps):
                               for k, v in rates.items() if k != "baseline"}}
 
 
+def pi_workload(name, **kw):
+    import pic_inputs as pi
+    return pi.workload(name, **kw)
+
+
 def tune_configs():
     """Run the autotuner (tune.py) on every workload this bench times and store its
     picks in the package's tune cache, which the timed blocks then read."""
@@ -423,9 +428,10 @@ def main():
                     help="only run the autotuner on every timed workload and rewrite its cache")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for scaling HBM counters)")
-    ap.add_argument("--only", choices=("batched", "adjoint", "extra", "cpu", "step"),
+    ap.add_argument("--only", choices=("batched", "adjoint", "extra", "cpu", "step", "cubic3d"),
                     help="run one block alone and print its JSON (for profiling); 'step' runs only "
-                         "the batched graph-replayed steps of the headline workload")
+                         "the batched graph-replayed steps of the headline workload, 'cubic3d' the "
+                         "128x128x256 cubic 3D beam")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -441,7 +447,9 @@ def main():
     if args.only:
         blk = {"batched": lambda: batched_headline(args.steps, args.warmup, args.profile_steps),
                "adjoint": adjoint_block, "extra": extra_blocks, "cpu": cpu_baseline,
-               "step": lambda: batched_steps_only(args.steps, args.warmup)}[args.only]()
+               "step": lambda: batched_steps_only(args.steps, args.warmup),
+               "cubic3d": lambda: single_block(pi_workload("beam3d_128x128x256"), args.steps, args.warmup, 4,
+                                               28)}[args.only]()
         print(json.dumps({args.only: blk}), flush=True)
         return
 
