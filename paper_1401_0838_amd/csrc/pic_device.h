@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <climits>
 
 #include "pic_internal.h"
@@ -33,6 +35,18 @@ __device__ __forceinline__ int wrapu(int i, int n)
 {
     const unsigned a = min((unsigned)i, (unsigned)(i + n));
     return (int)min(a, a - (unsigned)n);
+}
+
+// loads and stores of data read or written once per step: non-temporal when NT
+template <bool NT, class P> __device__ __forceinline__ auto sload(P p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return std::remove_cv_t<std::remove_reference_t<decltype(*p)>>(*p);
+}
+template <bool NT, class T, class P> __device__ __forceinline__ void sstore(T v, P p)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 __device__ __forceinline__ void jadd(long long *p, long long v)
@@ -347,13 +361,14 @@ template <class R, class JT> struct LdsWin {
     __device__ __forceinline__ void add(int comp, int x, int y, int z, JT v) { jadd(&J[comp * wc + at(x, y, z)], v); }
 };
 
-// LDS window with a compile-time row pitch P (2D): every node a particle
-// touches is at a constant offset from one base address
-template <class R, class JT, int P> struct LdsWinP {
+// LDS window with compile-time pitches (PX cells per row, PY rows per plane,
+// PZ planes; 2D: PY = 1): every node a particle touches is at a constant
+// offset from one base address
+template <class R, class JT, int PX, int PY, int PZ> struct LdsWinP {
     const R *F;
     JT *J;
-    static constexpr int wc = P * P;
-    __device__ __forceinline__ int at(int x, int, int z) const { return z * P + x; }
+    static constexpr int wc = PX * PY * PZ;
+    __device__ __forceinline__ int at(int x, int y, int z) const { return (z * PY + y) * PX + x; }
     __device__ __forceinline__ R f(int comp, int x, int y, int z) const { return F[comp * wc + at(x, y, z)]; }
     __device__ __forceinline__ void add(int comp, int x, int y, int z, JT v) { jadd(&J[comp * wc + at(x, y, z)], v); }
 };

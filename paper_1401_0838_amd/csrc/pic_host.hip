@@ -1064,6 +1064,16 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
             s->wmax[a] = std::max(s->wmax[a], w);
         }
     }
+    {
+        // particle state larger than the 256 MB last-level cache (with room for the
+        // fields): stream it past the caches (see the particle kernel)
+        const size_t R = s->fp32 ? 4 : 8;
+        size_t bytes = 0;
+        for (int i = 0; i < n_inst; i++)
+            bytes += (size_t)np[i] * (4 + (s->dims == 2 ? 2 : 3) * R + 3 * R);
+        const int nts = bytes > ((size_t)192 << 20) ? 1 : 0;
+        for (int i = 0; i < n_inst; i++) s->desc[i].nts = nts;
+    }
     if (s->seen_tz == 32) {
         // large FP32 batches: the seen pass streams 128-row segments where the
         // stencil widths allow (measured on a 64-instance batch of 3.9 M cells:
@@ -1078,6 +1088,14 @@ extern "C" int pic_init(const pic_config *cfgs, int n_inst, const pic_particles 
         const int wm2[3] = {pw, 1, pw};
         if (pw != w || s->wmax[0] != s->wmax[2])
             if (particle_smem_bytes(2, s->fp32, wm2) <= (size_t)maxsm) { s->wmax[0] = pw; s->wmax[2] = pw; }
+    }
+    if (s->dims == 3 && s->order == 3 && s->fp32) {
+        // cubic 3D (default tile 8 x 2 x 4): pitches 16 x 9 x 11 let the kernel
+        // address LDS with immediates
+        const int wp[3] = {16, 9, 11};
+        if (s->wmax[0] <= wp[0] && s->wmax[1] <= wp[1] && s->wmax[2] <= wp[2] &&
+            particle_smem_bytes(3, s->fp32, wp) <= (size_t)maxsm)
+            for (int a = 0; a < 3; a++) s->wmax[a] = wp[a];
     }
     while (particle_smem_bytes(s->dims, s->fp32, s->wmax) > (size_t)maxsm) {
         // shrink the slack until the window fits (tiles then re-sort more often)

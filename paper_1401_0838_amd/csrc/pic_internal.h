@@ -49,6 +49,8 @@ struct InstDesc {
     double jq;             // fixed-point quantum of the LDS current sums (float mode): J = int64 * jq
     double jqg;            // quantum of the HBM current planes (float mode): J = int32 * jqg, jqg = jq * 2^jshift
     int jshift;            // float mode: bits the LDS sums are rounded off by when they go to HBM (0 in double)
+    int nts;               // 1: the batch's particle state exceeds the last-level cache, so the
+                           // particle kernels stream it with non-temporal loads and stores
     double cdep[3];        // Esirkepov factors -q w d_a / (dt dV) (times 1/jq in float mode)
     double cy2d;           // q w / dV (times 1/jq in float mode): J_y = cy2d * v_y * W_y in 2D
     double rho_c;          // q w / dV for the charge density
