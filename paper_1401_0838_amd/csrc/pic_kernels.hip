@@ -1947,7 +1947,7 @@ void launch_particles_m(const LaunchCtx &c, const int2 *pwork, int nwork, dim3 g
             else PKS(2, 3, 0, IP_);                                                 \
         } else if constexpr (M == PM_DEFER) {                                       \
             if (c.order == 1) PKS(3, 1, 0, IP_);                                    \
-            else if (wm[0] == 16 && wm[1] == 9 && wm[2] == 11) PKS(3, 3, 160911, IP_); \
+            else if (wm[0] == 15 && wm[1] == 9 && wm[2] == 11) PKS(3, 3, 150911, IP_); \
             else PKS(3, 3, 0, IP_);                                                 \
         }                                                                           \
     } while (0)
@@ -1993,7 +1993,7 @@ void launch_particles_m(const LaunchCtx &c, const int2 *pwork, int nwork, dim3 g
             else PK(2, 3, 0);
         } else if constexpr (M == PM_DEFER) {
             if (c.order == 1) PK(3, 1, 0);
-            else if (wm[0] == 16 && wm[1] == 9 && wm[2] == 11) PK(3, 3, 160911);
+            else if (wm[0] == 15 && wm[1] == 9 && wm[2] == 11) PK(3, 3, 150911);
             else PK(3, 3, 0);
         }
     });
