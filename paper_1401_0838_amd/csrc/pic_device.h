@@ -54,10 +54,13 @@ __device__ __forceinline__ void jadd(long long *p, long long v)
     atomicAdd(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(v));
 }
 __device__ __forceinline__ void jadd(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void jadd(int *p, int v) { atomicAdd(p, v); }
 
 // contribution -> accumulator type (already scaled by 1/quantum in float mode)
 // truncation toward zero (one instruction); the bias is below one quantum
 __device__ __forceinline__ long long jcvt(float v, long long *) { return (long long)(int)v; }
+// 32-bit sums (3D float) use a coarser quantum: rounded to nearest, unbiased
+__device__ __forceinline__ int jcvt(float v, int *) { return __float2int_rn(v); }
 __device__ __forceinline__ double jcvt(double v, double *) { return v; }
 
 __device__ __forceinline__ double jreal(long long v, double q) { return (double)v * q; }
@@ -185,7 +188,8 @@ __device__ __forceinline__ void gatomic_add(gp<float> p, float v)
 // (the add is then skipped or wraps, and the caller flags the instance).
 __device__ __forceinline__ bool jflush(gp<int> p, long long v, int s)
 {
-    const long long r = (v + (s > 0 ? (1LL << (s - 1)) : 0)) >> s;
+    // s < 0: the HBM quantum is the finer one (exact)
+    const long long r = s >= 0 ? (v + (s > 0 ? (1LL << (s - 1)) : 0)) >> s : v * (1LL << -s);
     if (r == 0) return false;
     if (r > INT_MAX || r < INT_MIN) return true;
     const int old = __hip_atomic_fetch_add(p, (int)r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <climits>
+#include <type_traits>
 
 #include "pic_internal.h"
 #include "pic_device.h"
@@ -354,8 +355,12 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
                                                int nwork, int wmx, int wmy, int wmz, int par,
                                                const int *__restrict__ dlist = nullptr)
 {
-    typedef typename JOf<R>::T JT;
+    // LDS current sums: 64-bit fixed point in float mode (2D), 32-bit with a
+    // per-tile quantum in 3D float (half the LDS traffic of the deposit's adds),
+    // double in FP64
+    typedef std::conditional_t<DIM == 3 && std::is_same<R, float>::value, int, typename JOf<R>::T> JT;
     typedef typename JGOf<R>::T JG;
+    constexpr bool J32 = std::is_same<JT, int>::value;
     constexpr int JL = (L + 1) / 2;      // guard cells below the bounding box
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int sbox[6];
@@ -453,8 +458,22 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
         }
         __syncthreads();
 
+        // 32-bit sums count units of jq 2^kq.  A contribution is |cdep| (2^28 jq
+        // at most) times a running sum of shape changes (at most the spline's
+        // peak, the move being under a cell) times a transverse weight (at most
+        // the peak squared): below 2^28 jq for linear, (2/3)^3 2^28 jq for cubic
+        // splines.  kq is the least that keeps the tile's particles, all adding
+        // to one cell, below 2^30 (cubic, 512 particles: kq = 6).  A tile stepped
+        // in global memory adds each contribution to HBM on its own: kq = 0
+        int kq = 0;
+        if constexpr (J32) if (fits) {
+            const double cmax = (L == 3 ? 8.0 / 27.0 : 1.0) * 268435456.0;
+            const double np_t = (double)(p1 - p0);
+            while (kq < 28 && np_t * cmax > ldexp(1.0, 30 + kq)) kq++;
+        }
+        const R cq = J32 ? (R)ldexpf(1.0f, -kq) : R(1);
         const R dtd[3] = {(R)D.dtd[0], (R)D.dtd[1], (R)D.dtd[2]};
-        const R cdep[3] = {(R)D.cdep[0], (R)D.cdep[1], (R)D.cdep[2]};
+        const R cdep[3] = {(R)D.cdep[0] * cq, (R)D.cdep[1] * cq, (R)D.cdep[2] * cq};
         const R qdt2m = (R)D.qdt2m, cy2d = (R)D.cy2d;
         gp<R> poff[3] = {G<R>(D.poff[0]), G<R>(D.poff[1]), G<R>(D.poff[2])};
         gp<R> pu[3] = {G<R>(D.pu[0]), G<R>(D.pu[1]), G<R>(D.pu[2])};
@@ -478,7 +497,7 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
                 gw.o[k] = o[k];
                 gw.n[k] = D.n[k];
             }
-            gw.shift = D.jshift;
+            gw.shift = D.jshift - kq;
         }
 
         // The particle state is streamed: read once and written once per step.
@@ -598,7 +617,8 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
                 // and the Yee update, which reads every current word, flags a word
                 // outside +-2^30.  At most nine windows (27 in 3D) cover a node, so
                 // a word that wrapped past 32 bits lands outside +-2^30.
-                const int js = D.jshift;
+                // LDS quantum jq 2^kq -> HBM quantum jq 2^jshift (exact when kq >= jshift)
+                const int js = D.jshift - kq;
                 const long long half = js > 0 ? (1LL << (js - 1)) : 0;
                 constexpr long long BND = DIM == 2 ? (1LL << 28) : (1LL << 26);
                 bool ovf = false;
@@ -607,7 +627,8 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
                     const int l = lslot(c);
 #pragma unroll
                     for (int k = 0; k < 3; k++) {
-                        const long long r = (sJ[k * wc + l] + half) >> js;
+                        const long long sv = sJ[k * wc + l];
+                        const long long r = js >= 0 ? (sv + half) >> js : sv * (1LL << -js);
                         const bool big = r >= BND || r <= -BND;
                         ovf |= big;
                         if (r != 0 && !big) gatomic_add(gJ[k] + g, (int)r);
@@ -1912,7 +1933,8 @@ size_t particle_smem_bytes(int dims, int fp32, const int wmax[3])
 {
     const size_t wc = (size_t)wmax[0] * (dims == 3 ? wmax[1] : 1) * wmax[2];
     const size_t r = fp32 ? 4 : 8;
-    return wc * (3 * 8 + 6 * r);
+    const size_t jb = (dims == 3 && fp32) ? 4 : 8;   // LDS current sums (see particles_body)
+    return wc * (3 * jb + 6 * r);
 }
 
 // the deferred-tile pass for the gather scheme in use
