@@ -853,7 +853,7 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
         const InstDesc &D = Dt[inst];
         const int nx = D.n[0], nz = D.n[2];
         const int ntx = (nx + TX - 1) / TX;
-        const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
+        const int x0 = (t % ntx) * TX + (nx % TX == 0 ? LO : 0), z0 = (t / ntx) * TZ;
         const gp<const R> E[3] = {G<R>((const void *)D.E[par][0]), G<R>((const void *)D.E[par][1]),
                                   G<R>((const void *)D.E[par][2])};
         const gp<const R> B[3] = {G<R>((const void *)D.B[par][0]), G<R>((const void *)D.B[par][1]),
@@ -880,7 +880,7 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
         const InstDesc &D = Dt[inst];
         const int nx = D.n[0], nz = D.n[2];
         const int ntx = (nx + TX - 1) / TX;
-        const int x0 = (t % ntx) * TX, z0 = (t / ntx) * TZ;
+        const int x0 = (t % ntx) * TX + (nx % TX == 0 ? LO : 0), z0 = (t / ntx) * TZ;
         const gp<const JT> J[3] = {G<JT>((const void *)D.J[par][0]), G<JT>((const void *)D.J[par][1]),
                                    G<JT>((const void *)D.J[par][2])};
         // E, B and J are read with halos that neighbouring tiles own, so the new
@@ -978,8 +978,13 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
         if (jbad) G<int>((void *)D.flags)[FLAG_JRANGE] = 1;
         lds_barrier();
         // B^n on the tile and the stores (rows unrolled: a loop here would make
-        // the compiler wait for every outstanding load before it)
-        const int gx = x0 + lane;
+        // the compiler wait for every outstanding load before it).  On grids
+        // whose width is a multiple of 64 the tiles start LO cells past a 64-cell
+        // boundary, so each staged row begins on a 256-byte boundary (three
+        // 128-byte lines a row rather than four), and the last tile's outputs
+        // wrap onto the first LO columns
+        const int gxs = x0 + lane;
+        const int gx = gxs >= nx && nx % TX == 0 ? gxs - nx : gxs;
         if (gx < nx) {
 #pragma unroll
             for (int r = 0; r < (TZ + 3) / 4; r++) {
@@ -1278,7 +1283,12 @@ __global__ void __launch_bounds__(256) k_seen_2d_stream(const InstDesc *__restri
     const InstDesc &D = Dt[inst];
     const int nx = D.n[0], nz = D.n[2];
     const int ntx = (nx + SEEN_TX - 1) / SEEN_TX;
-    const int x0 = (t % ntx) * SEEN_TX, z0 = (t / ntx) * SEG;
+    // grids whose width is a multiple of 64: strips start HX cells past a
+    // 64-cell boundary, so that every staged row begins on a 256-byte boundary
+    // (three 128-byte lines a row rather than four); the last strip's outputs
+    // wrap onto the first HX columns
+    const int sh = nx % SEEN_TX == 0 ? HX : 0;
+    const int x0 = (t % ntx) * SEEN_TX + sh, z0 = (t / ntx) * SEG;
     const int nch = (min(SEG, nz - z0) + CZ - 1) / CZ;  // chunks of this segment (uniform)
     const double *tzs = ztaps(D, comp), *txs = xtaps(D, comp);
     R rz[NTZ], rx[NTX];
@@ -1361,7 +1371,8 @@ __global__ void __launch_bounds__(256) k_seen_2d_stream(const InstDesc *__restri
             const int s = s0 + k < RING ? s0 + k : s0 + k - RING;
             v[k] = mid[s * SEEN_TX + lane];
         }
-        const int gx = x0 + lane;
+        const int gxs = x0 + lane;
+        const int gx = gxs >= nx && sh ? gxs - nx : gxs;
 #pragma unroll
         for (int j = 0; j < RW; j++) {
             const int gz = z0 + c * CZ + wave * RW + j;
