@@ -458,16 +458,19 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
         }
         __syncthreads();
 
-        // 32-bit sums count units of jq 2^kq.  A contribution is |cdep| (2^28 jq
-        // at most) times a running sum of shape changes (at most the spline's
-        // peak, the move being under a cell) times a transverse weight (at most
-        // the peak squared): below 2^28 jq for linear, (2/3)^3 2^28 jq for cubic
-        // splines.  kq is the least that keeps the tile's particles, all adding
-        // to one cell, below 2^30 (cubic, 512 particles: kq = 6).  A tile stepped
-        // in global memory adds each contribution to HBM on its own: kq = 0
+        // 32-bit sums count units of jq 2^kq.  Along axis a a contribution is
+        // |cdep_a| = |q w| d_a / (c dt dV) times a running sum of shape changes,
+        // which is at most the particle's move in cells (|v| dt / d_a < c dt / d_a)
+        // times the slope bound of the partial sums of the spline (the peak of the
+        // spline one order lower: 1 linear, 3/4 cubic), times a transverse weight
+        // (at most the spline's peak squared: 1, 4/9).  So it is below
+        // |q w| / dV = |rho_c| for linear and |rho_c| / 3 for cubic splines.  kq is
+        // the least that keeps the tile's particles, all adding to one cell, below
+        // 2^30 (cubic, 512 particles, c dt / d = 0.5: kq = 5).  A tile stepped in
+        // global memory adds each contribution to HBM on its own: kq = 0
         int kq = 0;
         if constexpr (J32) if (fits) {
-            const double cmax = (L == 3 ? 8.0 / 27.0 : 1.0) * 268435456.0;
+            const double cmax = (L == 3 ? 1.0 / 3.0 : 1.0) * fabs(D.rho_c) / D.jq;
             const double np_t = (double)(p1 - p0);
             while (kq < 28 && np_t * cmax > ldexp(1.0, 30 + kq)) kq++;
         }

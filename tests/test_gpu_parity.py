@@ -168,6 +168,33 @@ def test_3d_cubic_multipass_tiles_parity():
         sim.close()
 
 
+@pytest.mark.parametrize("order", [1, 3])
+def test_3d_dense_tiles_keep_32bit_lds_sums_in_range(order):
+    """3D float sums a tile's current in 32-bit words whose quantum grows with the
+    tile's particle count (kq, from a bound on one particle's contribution), so
+    that all of a tile's particles adding to one cell stay below 2^30.  A dense
+    clump — 96 particles in each of the 64 cells of one tile, 6144 in the tile,
+    kq = 9 (cubic) and 11 (linear) — must still match the oracle to the FP32
+    bound, with the Gauss residual at rounding level and no range flag."""
+    from paper_1401_0838_amd import _lib as L
+    n = (16, 8, 16)
+    wl = pi.workload("beam3d_128x128x256", n=n, ppc=96, order=order)
+    tile = [i + n[0] * (j + n[1] * k) for i in range(8, 16) for j in range(2, 4) for k in range(4, 8)]
+    x, u = pi.load_beam(3, n, 96, wl["gamma"], 1e-3, 9, cells=np.array(tile))
+    _say("case 3d dense tile order %d np=%d" % (order, x.shape[0]))
+    ref = OracleSim(wl, x, u)
+    ref.step(6)
+    sim = _sim(wl, (x, u), precision="fp32")
+    sim.step(6)
+    errs = _field_errors(sim, ref)
+    d = sim.diag()
+    _say("  %s gauss %.3e rho_max %.3e slow=%d" % (errs, d["gauss_linf"], d["rho_max"], d["slow_tiles"]))
+    assert d["rc"] == L.PIC_OK and d["current_range"] == 0
+    assert max(errs.values()) < 1e-4
+    assert d["gauss_linf"] < 1e-5 * d["rho_max"]
+    sim.close()
+
+
 @pytest.mark.parametrize("dims,order,sigma", [(2, 1, 0.05), (2, 3, 0.05), (3, 1, 0.05), (3, 3, 0.05),
                                                (2, 1, 3.0)])
 def test_charge_density_and_diagnostics_match_oracle(dims, order, sigma):
