@@ -91,13 +91,15 @@ extern "C" {
 
 #define PIC_FP64 0            /* fields, offsets, momenta and J in double */
 #define PIC_FP32 1            /* float fields/offsets/momenta, int32 cell index;
-                                 J summed per tile in 64-bit fixed point (quantum 2^-28
-                                 of the largest single-particle contribution) and
-                                 kept in HBM as 32-bit fixed point (quantum about 2^-21
-                                 of the current of a beam moving at c through the
-                                 densest initial cell; each tile's sum is rounded to it
-                                 once per step).  Integer sums: a run is bitwise
-                                 reproducible for a given particle tiling */
+                                 J summed per tile in fixed point — 64-bit in 2D
+                                 (quantum 2^-28 of the largest single-particle
+                                 contribution), 32-bit in 3D with a per-tile quantum
+                                 that keeps every sum of the tile's particles below
+                                 2^30 — and kept in HBM as 32-bit fixed point (quantum
+                                 about 2^-21 of the current of a beam moving at c
+                                 through the densest initial cell; each tile's sum is
+                                 rounded to it once per step).  Integer sums: a run is
+                                 bitwise reproducible for a given particle tiling */
 
 #define PIC_IONS_CHARGE             0  /* immobile ions carry charge only */
 #define PIC_IONS_CHARGE_AND_CURRENT 1  /* plus a fixed uniform current equal to
