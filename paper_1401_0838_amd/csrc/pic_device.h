@@ -253,6 +253,23 @@ __device__ __forceinline__ int pmod(int g, int n)
     return r;
 }
 
+// periodic index g mod n by a multiply with a reciprocal taken once (a block's
+// row and column wraps: a remainder costs a few tens of instructions, this five):
+// with x = g + 16 n and m = floor((2^32 - 1) / n), the high word of x m is the
+// quotient or one below it, so one conditional subtract finishes the
+// remainder.  Exact for g in [-16 n, 2^31 - 16 n), n >= 1.
+struct PerMod {
+    unsigned n, m, off;
+    __device__ __forceinline__ explicit PerMod(int n_)
+        : n((unsigned)n_), m(0xFFFFFFFFu / (unsigned)n_), off(16u * (unsigned)n_) {}
+    __device__ __forceinline__ int operator()(int g) const
+    {
+        const unsigned x = (unsigned)g + off;
+        const unsigned r = x - __umulhi(x, m) * n;
+        return (int)(r >= n ? r - n : r);
+    }
+};
+
 // periodic index for g in [-n, 2n) (one compare each way), else a modulo
 __device__ __forceinline__ int wrap_near(int g, int n)
 {

@@ -429,11 +429,23 @@ __device__ __forceinline__ void particles_body(const InstDesc *__restrict__ Dt, 
         constexpr int PZc = DIM == 2 ? P : P % 100;
         const int wc = P > 0 ? PXc * PYc * PZc : wn[0] * wn[1] * wn[2];
         const int pitch = P > 0 ? PXc : wn[0];
-        // window cell c (x fastest over wn) -> its LDS slot
+        // window cell c (x fastest over wn) -> its LDS slot.  The quotients are
+        // taken with a float reciprocal, (c + 1/2) / w rounded down, which is
+        // exact for c below 2^22 (windows hold a few thousand cells) and costs a
+        // few instructions where an integer division costs a few tens
+        // (the reciprocals are uniform: kept in scalar registers across the loop)
+        const float rw0 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(1.0f / (float)wn[0])));
+        const float rw1 = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(1.0f / (float)wn[1])));
         auto lslot = [&](int c) {
             if constexpr (P > 0) {
-                const int r = c / wn[0];
-                return ((DIM == 2 ? r : (r / wn[1]) * PYc + r % wn[1]) * PXc) + c % wn[0];
+                const int r = (int)(((float)c + 0.5f) * rw0);
+                const int x = c - r * wn[0];
+                if constexpr (DIM == 2) {
+                    return r * PXc + x;
+                } else {
+                    const int z = (int)(((float)r + 0.5f) * rw1);
+                    return ((z * PYc + (r - z * wn[1])) * PXc) + x;
+                }
             } else {
                 return c;
             }
@@ -855,6 +867,7 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
         tile_of(item, inst, t);
         const InstDesc &D = Dt[inst];
         const int nx = D.n[0], nz = D.n[2];
+        const PerMod wx(nx), wz(nz);
         const int ntx = (nx + TX - 1) / TX;
         const int x0 = (t % ntx) * TX + (nx % TX == 0 ? LO : 0), z0 = (t / ntx) * TZ;
         const gp<const R> E[3] = {G<R>((const void *)D.E[par][0]), G<R>((const void *)D.E[par][1]),
@@ -863,15 +876,15 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
                                   G<R>((const void *)D.B[par][2])};
         // branch-free addresses (a branch between the loads and their use costs
         // exact waits); the row of a wave is uniform, so its wrap is scalar
-        const int gxa = pmod(x0 - LO + lane, nx);
+        const int gxa = wx(x0 - LO + lane);
 #pragma unroll
         for (int u = 0; u < RW; u++) {
-            const int zr = __builtin_amdgcn_readfirstlane(pmod(z0 - LO + min(wave + u * nwave, WZ - 1), nz));
+            const int zr = __builtin_amdgcn_readfirstlane(wz(z0 - LO + min(wave + u * nwave, WZ - 1)));
             const int g = zr * nx + gxa;
 #pragma unroll
             for (int k = 0; k < 3; k++) { ve[u][k] = E[k][g]; vb[u][k] = B[k][g]; }
         }
-        const int gh = pmod(z0 - LO + hrow, nz) * nx + pmod(x0 - LO + hcol, nx);
+        const int gh = wz(z0 - LO + hrow) * nx + wx(x0 - LO + hcol);
 #pragma unroll
         for (int k = 0; k < 3; k++) { he[k] = E[k][gh]; hb[k] = B[k][gh]; }
     };
@@ -882,6 +895,7 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
         tile_of(item, inst, t);
         const InstDesc &D = Dt[inst];
         const int nx = D.n[0], nz = D.n[2];
+        const PerMod wx(nx), wz(nz);
         const int ntx = (nx + TX - 1) / TX;
         const int x0 = (t % ntx) * TX + (nx % TX == 0 ? LO : 0), z0 = (t / ntx) * TZ;
         const gp<const JT> J[3] = {G<JT>((const void *)D.J[par][0]), G<JT>((const void *)D.J[par][1]),
@@ -911,15 +925,15 @@ __global__ void __launch_bounds__(256) k_yee_2d(const InstDesc *__restrict__ Dt,
         JT vj[RW][3], hj[3];
         bool jbad = false;
         {
-            const int gxa = pmod(x0 - LO + lane, nx);
+            const int gxa = wx(x0 - LO + lane);
 #pragma unroll
             for (int u = 0; u < RW; u++) {
-                const int zr = __builtin_amdgcn_readfirstlane(pmod(z0 - LO + min(wave + u * nwave, WZ - 1), nz));
+                const int zr = __builtin_amdgcn_readfirstlane(wz(z0 - LO + min(wave + u * nwave, WZ - 1)));
                 const int g = zr * nx + gxa;
 #pragma unroll
                 for (int k = 0; k < 3; k++) vj[u][k] = J[k][g];
             }
-            const int gh = pmod(z0 - LO + hrow, nz) * nx + pmod(x0 - LO + hcol, nx);
+            const int gh = wz(z0 - LO + hrow) * nx + wx(x0 - LO + hcol);
 #pragma unroll
             for (int k = 0; k < 3; k++) hj[k] = J[k][gh];
         }
@@ -1303,11 +1317,12 @@ __global__ void __launch_bounds__(256) k_seen_2d_stream(const InstDesc *__restri
     gp<R> dst = G<R>(comp < 3 ? D.Et[comp] : D.Bt[comp - 3]);
     const int lane = threadIdx.x & 63, wave = wave_id();
     const bool hasb = lane < 2 * HX;
-    const int gxa = pmod(x0 - HX + lane, nx);
-    const int gxb = hasb ? pmod(x0 - HX + SEEN_TX + lane, nx) : gxa;
+    const PerMod wx(nx), wz(nz);
+    const int gxa = wx(x0 - HX + lane);
+    const int gxb = hasb ? wx(x0 - HX + SEEN_TX + lane) : gxa;
     // window row w is grid row z0 - HZ + w; the first chunk stages rows
     // [0, RING), chunk c >= 1 rows [c CZ + 2 HZ, (c + 1) CZ + 2 HZ)
-    auto grow = [&](int w) { return pmod(z0 - HZ + w, nz) * nx; };
+    auto grow = [&](int w) { return wz(z0 - HZ + w) * nx; };
     {
         R va[R0], vb[R0];
 #pragma unroll
