@@ -1057,6 +1057,38 @@ __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ 
     const InstDesc &D = Dt[inst];
     const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
     const int comp = blockIdx.y;
+    if constexpr (AXIS == 0 && HW >= 0) {
+        // Rows whose length is a multiple of 64, whole chunks: each wave's 64
+        // cells lie in one row, so the wave stages that row's cells
+        // [i0 - HW, i0 + 64 + HW) (wrapped along the row, two loads a lane) in
+        // LDS and every output reads its taps from there at fixed offsets.
+        // Same sums in the same order as the general form below, which takes a
+        // wrapped index and a load per tap (tens of instructions a cell).
+        static_assert(PIC_FIELD_CHUNK == 256, "four waves of 64 cells");
+        constexpr int SW = 64 + 2 * (HW > 0 ? HW : 0);
+        __shared__ R st[4][SW];
+        const int nx = D.n[0];
+        const int c0 = work[blockIdx.x].y * PIC_FIELD_CHUNK;
+        if (nx % 64 == 0 && c0 + PIC_FIELD_CHUNK <= D.ncell) {   // uniform over the block
+            const gp<const R> s = G<R>(src_sel == 0 ? (comp < 3 ? D.E[par][comp] : D.B[par][comp - 3])
+                                                    : (src_sel == 1 ? D.T1[comp] : D.T2[comp]));
+            R *dst = dst_sel == 1 ? (R *)D.T1[comp]
+                                  : (dst_sel == 2 ? (R *)D.T2[comp] : (comp < 3 ? (R *)D.Et[comp] : (R *)D.Bt[comp - 3]));
+            const PerMod wx(nx);
+            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+            const int cw = c0 + 64 * w, i0 = wx(cw), rb = cw - i0;
+            R *sw = st[w];
+            sw[lane] = s[rb + wx(i0 - HW + lane)];
+            if (lane < 2 * HW) sw[64 + lane] = s[rb + wx(i0 - HW + 64 + lane)];
+            __syncthreads();
+            const double *tap = xtaps(D, comp);
+            R acc = R(0);
+#pragma unroll
+            for (int t = 0; t <= 2 * HW; t++) acc += (R)tap[t] * sw[lane + t];
+            G<R>(dst)[cw + lane] = acc;
+            return;
+        }
+    }
     if (cell >= D.ncell) return;
     const R *src;
     if (src_sel == 0) src = comp < 3 ? (const R *)D.E[par][comp] : (const R *)D.B[par][comp - 3];

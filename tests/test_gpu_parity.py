@@ -147,6 +147,28 @@ def test_3d_parity(order, prec, tol):
     sim.close()
 
 
+@pytest.mark.parametrize("order,interp", [(1, "galerkin"), (3, "galerkin"), (1, "momentum")])
+def test_3d_rows_of_64_parity(order, interp):
+    """Grids whose rows are a multiple of 64 cells take the x-direction seen pass
+    that stages each wave's row segment (with its wrapped ends) in LDS; the
+    other 3D tests (rows of 16 and 32) take the per-tap form.  64 x 8 x 16 and
+    128 x 8 x 8 against the oracle after 10 steps: FP64 within 1e-10, FP32
+    within 1e-4, with the wider stencil of the momentum-conserving gather too."""
+    for n in ((64, 8, 16), (128, 8, 8)):
+        wl = pi.workload("beam3d_128x128x256", n=n, ppc=2, order=order, interp=interp)
+        x, u = pi.load_beam(3, wl["n"], wl["ppc"], wl["gamma"], 1e-3, 4)
+        _say("case 3d rows of 64 n=%s order %d %s" % (n, order, interp))
+        ref = OracleSim(wl, x, u)
+        ref.step(10)
+        for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
+            sim = _sim(wl, (x, u), precision=prec)
+            sim.step(10)
+            errs = _field_errors(sim, ref)
+            _say("  %s %s" % (prec, errs))
+            assert max(errs.values()) < tol
+            sim.close()
+
+
 def test_3d_cubic_multipass_tiles_parity():
     """The 3D cubic workload's particle density (8 ppc) on a 32x32x64 grid: a
     cubic tile is 8x2x4 = 64 cells, so every tile holds about 512 particles and
