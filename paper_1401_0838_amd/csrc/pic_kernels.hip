@@ -1048,14 +1048,14 @@ __device__ __forceinline__ const double *ytaps(const InstDesc &D, int comp)
 // axis 2: combined z taps (Psi_E o filter for Ex, Ey; Psi_B o filter for Ez, Bx,
 // By, Bz); axis 0 / 1: filter taps along x / y.  blockIdx.y selects the component.
 template <int AXIS, class R, int HW>
-__global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                                   int src_sel, int dst_sel, int par)
+__device__ __forceinline__ void seen_pass_item(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                               int item, int src_sel, int dst_sel, int par)
 {
     // HW >= 0: the pass's half-width at compile time (taps unrolled, all loads
     // of a cell in flight at once); -1: read it from the descriptor
-    const int inst = work[blockIdx.x].x;
+    const int inst = work[item].x;
     const InstDesc &D = Dt[inst];
-    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
+    const int cell = work[item].y * PIC_FIELD_CHUNK + threadIdx.x;
     const int comp = blockIdx.y;
     if constexpr (AXIS == 0 && HW >= 0) {
         // Rows whose length is a multiple of 64, whole chunks: each wave's 64
@@ -1068,7 +1068,7 @@ __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ 
         constexpr int SW = 64 + 2 * (HW > 0 ? HW : 0);
         __shared__ R st[4][SW];
         const int nx = D.n[0];
-        const int c0 = work[blockIdx.x].y * PIC_FIELD_CHUNK;
+        const int c0 = work[item].y * PIC_FIELD_CHUNK;
         if (nx % 64 == 0 && c0 + PIC_FIELD_CHUNK <= D.ncell) {   // uniform over the block
             const gp<const R> s = G<R>(src_sel == 0 ? (comp < 3 ? D.E[par][comp] : D.B[par][comp - 3])
                                                     : (src_sel == 1 ? D.T1[comp] : D.T2[comp]));
@@ -1117,6 +1117,22 @@ __global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ 
         for (int t = -h; t <= h; t++) acc += (R)tap[t + h] * s[base + wrap_near(q + t, nq) * stride];
     }
     G<R>(dst)[cell] = acc;
+}
+
+// K work items (256-cell chunks) per workgroup, one after the other: a chunk
+// is little work next to a workgroup's start (its chain of dependent loads:
+// work item, descriptor, plane pointers), so the x pass takes several
+template <int AXIS, class R, int HW, int K = 1>
+__global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                                   int nwork, int src_sel, int dst_sel, int par)
+{
+#pragma unroll 1
+    for (int it = 0; it < K; it++) {
+        const int item = (int)blockIdx.x * K + it;
+        if (item >= nwork) break;
+        seen_pass_item<AXIS, R, HW>(Dt, work, item, src_sel, dst_sel, par);
+        if (K > 1) __syncthreads();   // the LDS rows are staged again for the next item
+    }
 }
 
 // One pass of the 3D seen-field stencils along a strided axis (AXIS 2: z,
@@ -1187,6 +1203,7 @@ __global__ void __launch_bounds__(256) k_seen_col(const InstDesc *__restrict__ D
 // HZ, HX >= 0 fix the stencil half-widths at compile time (taps in registers,
 // loops unrolled); -1 reads them from the descriptor.
 #define SEEN_TX PIC_SEEN_TX
+#define SEEN_XK 4   // 256-cell chunks per workgroup of the 3D x-direction pass
 template <class R, int SEEN_TZ, int HZ, int HX>
 __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                  int par)
@@ -1968,18 +1985,19 @@ int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *sw
             // one more with the node average of the momentum-conserving gather
             // z and y: column passes; x (contiguous): one cell per thread
             const dim3 gz(c.col_blocks[0], 6, c.ninst), gy(c.col_blocks[1], 6, c.ninst);
+            const dim3 gx((nwork + SEEN_XK - 1) / SEEN_XK, 6);
             if (c.hz == 8 && c.hx == 4) {
                 k_seen_col<2, R, 8, PIC_COL_RUN><<<gz, b, 0, c.stream>>>(c.desc, c.inst0, 0, 1, c.par);
-                k_seen_pass<0, R, 4><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
+                k_seen_pass<0, R, 4, SEEN_XK><<<gx, b, 0, c.stream>>>(c.desc, fwork, nwork, 1, 2, c.par);
                 k_seen_col<1, R, 4, PIC_COL_RUN><<<gy, b, 0, c.stream>>>(c.desc, c.inst0, 2, 0, c.par);
             } else if (c.hz == 9 && c.hx == 5) {
                 k_seen_col<2, R, 9, PIC_COL_RUN><<<gz, b, 0, c.stream>>>(c.desc, c.inst0, 0, 1, c.par);
-                k_seen_pass<0, R, 5><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
+                k_seen_pass<0, R, 5, SEEN_XK><<<gx, b, 0, c.stream>>>(c.desc, fwork, nwork, 1, 2, c.par);
                 k_seen_col<1, R, 5, PIC_COL_RUN><<<gy, b, 0, c.stream>>>(c.desc, c.inst0, 2, 0, c.par);
             } else {
-                k_seen_pass<2, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1, c.par);
-                k_seen_pass<0, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
-                k_seen_pass<1, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 2, 0, c.par);
+                k_seen_pass<2, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, nwork, 0, 1, c.par);
+                k_seen_pass<0, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, nwork, 1, 2, c.par);
+                k_seen_pass<1, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, nwork, 2, 0, c.par);
             }
         }
         if (c.ratio && c.rtiles > 0) {
