@@ -282,6 +282,7 @@ LaunchCtx ctx(const pic_state *s)
         const long long ty = (long long)d.n[0] * d.n[2] * ((d.n[1] + PIC_COL_RUN - 1) / PIC_COL_RUN);
         c.col_blocks[0] = std::max(c.col_blocks[0], (int)((tz + 255) / 256));
         c.col_blocks[1] = std::max(c.col_blocks[1], (int)((ty + 255) / 256));
+        c.x_blocks = std::max(c.x_blocks, (int)((d.ncell + 256 * PIC_SEEN_XSEG - 1) / (256 * PIC_SEEN_XSEG)));
     }
     if (!s->desc.empty()) {
         const InstDesc &d0 = s->desc[0];

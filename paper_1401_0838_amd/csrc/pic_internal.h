@@ -7,6 +7,7 @@
 #define PIC_MAX_HZ 16           // half-width of the combined z stencil (Psi degree + passes)
 #define PIC_MAX_HX 8            // half-width of the x / y filter stencils
 #define PIC_FIELD_CHUNK 256     // cells per field work item
+#define PIC_SEEN_XSEG 8         // 64-cell row segments per wave of the 3D x-direction seen pass
 #define PIC_GRAD_COPIES 64      // copies of the gradient sums (power of two)
 #define PIC_PART_CHUNK 256      // particles per particle-chunk work item
 #define PIC_SEEN_TX 64          // 2D seen-field tile (x)
@@ -160,6 +161,7 @@ struct LaunchCtx {
     int rtiles = 0;                   // column tiles of the widest instance (ratio solve grid)
     int cus = 256;                    // compute units of the device
     int col_blocks[2] = {0, 0};       // 3D column passes (z, y): 256-thread blocks for the largest instance
+    int x_blocks = 0;                 // 3D x pass: workgroups of 256 * PIC_SEEN_XSEG cells for the largest instance
     int defer_mode = -1;              // particle launch form: -1 by tile count, 0 inline, 1 deferring (2D)
 };
 

@@ -1048,47 +1048,15 @@ __device__ __forceinline__ const double *ytaps(const InstDesc &D, int comp)
 // axis 2: combined z taps (Psi_E o filter for Ex, Ey; Psi_B o filter for Ez, Bx,
 // By, Bz); axis 0 / 1: filter taps along x / y.  blockIdx.y selects the component.
 template <int AXIS, class R, int HW>
-__device__ __forceinline__ void seen_pass_item(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                               int item, int src_sel, int dst_sel, int par)
+__global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+                                                   int src_sel, int dst_sel, int par)
 {
     // HW >= 0: the pass's half-width at compile time (taps unrolled, all loads
     // of a cell in flight at once); -1: read it from the descriptor
-    const int inst = work[item].x;
+    const int inst = work[blockIdx.x].x;
     const InstDesc &D = Dt[inst];
-    const int cell = work[item].y * PIC_FIELD_CHUNK + threadIdx.x;
+    const int cell = work[blockIdx.x].y * PIC_FIELD_CHUNK + threadIdx.x;
     const int comp = blockIdx.y;
-    if constexpr (AXIS == 0 && HW >= 0) {
-        // Rows whose length is a multiple of 64, whole chunks: each wave's 64
-        // cells lie in one row, so the wave stages that row's cells
-        // [i0 - HW, i0 + 64 + HW) (wrapped along the row, two loads a lane) in
-        // LDS and every output reads its taps from there at fixed offsets.
-        // Same sums in the same order as the general form below, which takes a
-        // wrapped index and a load per tap (tens of instructions a cell).
-        static_assert(PIC_FIELD_CHUNK == 256, "four waves of 64 cells");
-        constexpr int SW = 64 + 2 * (HW > 0 ? HW : 0);
-        __shared__ R st[4][SW];
-        const int nx = D.n[0];
-        const int c0 = work[item].y * PIC_FIELD_CHUNK;
-        if (nx % 64 == 0 && c0 + PIC_FIELD_CHUNK <= D.ncell) {   // uniform over the block
-            const gp<const R> s = G<R>(src_sel == 0 ? (comp < 3 ? D.E[par][comp] : D.B[par][comp - 3])
-                                                    : (src_sel == 1 ? D.T1[comp] : D.T2[comp]));
-            R *dst = dst_sel == 1 ? (R *)D.T1[comp]
-                                  : (dst_sel == 2 ? (R *)D.T2[comp] : (comp < 3 ? (R *)D.Et[comp] : (R *)D.Bt[comp - 3]));
-            const PerMod wx(nx);
-            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-            const int cw = c0 + 64 * w, i0 = wx(cw), rb = cw - i0;
-            R *sw = st[w];
-            sw[lane] = s[rb + wx(i0 - HW + lane)];
-            if (lane < 2 * HW) sw[64 + lane] = s[rb + wx(i0 - HW + 64 + lane)];
-            __syncthreads();
-            const double *tap = xtaps(D, comp);
-            R acc = R(0);
-#pragma unroll
-            for (int t = 0; t <= 2 * HW; t++) acc += (R)tap[t] * sw[lane + t];
-            G<R>(dst)[cw + lane] = acc;
-            return;
-        }
-    }
     if (cell >= D.ncell) return;
     const R *src;
     if (src_sel == 0) src = comp < 3 ? (const R *)D.E[par][comp] : (const R *)D.B[par][comp - 3];
@@ -1117,22 +1085,6 @@ __device__ __forceinline__ void seen_pass_item(const InstDesc *__restrict__ Dt, 
         for (int t = -h; t <= h; t++) acc += (R)tap[t + h] * s[base + wrap_near(q + t, nq) * stride];
     }
     G<R>(dst)[cell] = acc;
-}
-
-// K work items (256-cell chunks) per workgroup, one after the other: a chunk
-// is little work next to a workgroup's start (its chain of dependent loads:
-// work item, descriptor, plane pointers), so the x pass takes several
-template <int AXIS, class R, int HW, int K = 1>
-__global__ void __launch_bounds__(256) k_seen_pass(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
-                                                   int nwork, int src_sel, int dst_sel, int par)
-{
-#pragma unroll 1
-    for (int it = 0; it < K; it++) {
-        const int item = (int)blockIdx.x * K + it;
-        if (item >= nwork) break;
-        seen_pass_item<AXIS, R, HW>(Dt, work, item, src_sel, dst_sel, par);
-        if (K > 1) __syncthreads();   // the LDS rows are staged again for the next item
-    }
 }
 
 // One pass of the 3D seen-field stencils along a strided axis (AXIS 2: z,
@@ -1191,6 +1143,77 @@ __global__ void __launch_bounds__(256) k_seen_col(const InstDesc *__restrict__ D
     }
 }
 
+// 3D x-direction pass (compile-time half-width): blockIdx.z = instance,
+// blockIdx.y = component; a workgroup takes PIC_SEEN_XSEG 64-cell row
+// segments per wave.  Rows whose length is a multiple of 64: each wave loads
+// all its segments, with their row-wrapped ends, into LDS before it waits for
+// any (2 PIC_SEEN_XSEG loads in flight a lane), and every output then reads
+// its taps at fixed offsets.  Other rows: one cell per thread, a wrapped index
+// and a load per tap.  Both add the same products in the same order.
+template <class R, int HW>
+__global__ void __launch_bounds__(256) k_seen_x(const InstDesc *__restrict__ Dt, int inst0, int src_sel, int dst_sel,
+                                                int par)
+{
+    constexpr int K = PIC_SEEN_XSEG, SW = 64 + 2 * HW;
+    __shared__ R st[4][K][SW + 1];
+    const InstDesc &D = Dt[inst0 + blockIdx.z];
+    const int comp = blockIdx.y;
+    const int nx = D.n[0], ncell = D.ncell;
+    const int cb = (int)blockIdx.x * (256 * K);
+    if (cb >= ncell) return;   // uniform over the workgroup
+    const gp<const R> s = G<R>(src_sel == 0 ? (comp < 3 ? D.E[par][comp] : D.B[par][comp - 3])
+                                            : (src_sel == 1 ? D.T1[comp] : D.T2[comp]));
+    const gp<R> dst = G<R>(dst_sel == 1 ? D.T1[comp]
+                                        : (dst_sel == 2 ? D.T2[comp] : (comp < 3 ? D.Et[comp] : D.Bt[comp - 3])));
+    const double *tap = xtaps(D, comp);
+    R tp[2 * HW + 1];
+#pragma unroll
+    for (int t = 0; t <= 2 * HW; t++) tp[t] = (R)tap[t];
+    const PerMod wx(nx);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (nx % 64 == 0) {
+        // segment k of wave w: cells [sg, sg + 64), sg = cb + 64 (4 k + w);
+        // ncell is a multiple of 64, so a segment is whole or absent (an absent
+        // one loads the block's first segment again and stores nothing)
+        R va[K], vb[K];
+        const int hl = lane < 2 * HW ? lane : 0;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int sg0 = cb + 64 * (4 * k + w);
+            const int sg = sg0 < ncell ? sg0 : cb;
+            const int i0 = wx(sg), rb = sg - i0;
+            va[k] = s[rb + wx(i0 - HW + lane)];
+            vb[k] = s[rb + wx(i0 - HW + 64 + hl)];
+        }
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            st[w][k][lane] = va[k];
+            // lanes past the halo store into the spare word
+            st[w][k][lane < 2 * HW ? 64 + lane : SW] = vb[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int sg = cb + 64 * (4 * k + w);
+            R acc = R(0);
+#pragma unroll
+            for (int t = 0; t <= 2 * HW; t++) acc += tp[t] * st[w][k][lane + t];
+            if (sg < ncell) dst[sg + lane] = acc;
+        }
+    } else {
+#pragma unroll 1
+        for (int k = 0; k < K; k++) {
+            const int cell = cb + 256 * k + (int)threadIdx.x;
+            if (cell >= ncell) break;
+            const int i = wx(cell), base = cell - i;
+            R acc = R(0);
+#pragma unroll
+            for (int t = -HW; t <= HW; t++) acc += tp[t + HW] * s[base + wrap_near(i + t, nx)];
+            dst[cell] = acc;
+        }
+    }
+}
+
 // 2D fields as seen by the particles in one kernel: one component's (64 x SEEN_TZ)
 // output tile is staged in LDS with its stencil halo (waves own rows, lanes own
 // columns, so addresses are affine in the lane); the x filter stencil then runs
@@ -1203,7 +1226,6 @@ __global__ void __launch_bounds__(256) k_seen_col(const InstDesc *__restrict__ D
 // HZ, HX >= 0 fix the stencil half-widths at compile time (taps in registers,
 // loops unrolled); -1 reads them from the descriptor.
 #define SEEN_TX PIC_SEEN_TX
-#define SEEN_XK 4   // 256-cell chunks per workgroup of the 3D x-direction pass
 template <class R, int SEEN_TZ, int HZ, int HX>
 __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                  int par)
@@ -1985,19 +2007,19 @@ int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *sw
             // one more with the node average of the momentum-conserving gather
             // z and y: column passes; x (contiguous): one cell per thread
             const dim3 gz(c.col_blocks[0], 6, c.ninst), gy(c.col_blocks[1], 6, c.ninst);
-            const dim3 gx((nwork + SEEN_XK - 1) / SEEN_XK, 6);
+            const dim3 gx(c.x_blocks, 6, c.ninst);
             if (c.hz == 8 && c.hx == 4) {
                 k_seen_col<2, R, 8, PIC_COL_RUN><<<gz, b, 0, c.stream>>>(c.desc, c.inst0, 0, 1, c.par);
-                k_seen_pass<0, R, 4, SEEN_XK><<<gx, b, 0, c.stream>>>(c.desc, fwork, nwork, 1, 2, c.par);
+                k_seen_x<R, 4><<<gx, b, 0, c.stream>>>(c.desc, c.inst0, 1, 2, c.par);
                 k_seen_col<1, R, 4, PIC_COL_RUN><<<gy, b, 0, c.stream>>>(c.desc, c.inst0, 2, 0, c.par);
             } else if (c.hz == 9 && c.hx == 5) {
                 k_seen_col<2, R, 9, PIC_COL_RUN><<<gz, b, 0, c.stream>>>(c.desc, c.inst0, 0, 1, c.par);
-                k_seen_pass<0, R, 5, SEEN_XK><<<gx, b, 0, c.stream>>>(c.desc, fwork, nwork, 1, 2, c.par);
+                k_seen_x<R, 5><<<gx, b, 0, c.stream>>>(c.desc, c.inst0, 1, 2, c.par);
                 k_seen_col<1, R, 5, PIC_COL_RUN><<<gy, b, 0, c.stream>>>(c.desc, c.inst0, 2, 0, c.par);
             } else {
-                k_seen_pass<2, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, nwork, 0, 1, c.par);
-                k_seen_pass<0, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, nwork, 1, 2, c.par);
-                k_seen_pass<1, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, nwork, 2, 0, c.par);
+                k_seen_pass<2, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 0, 1, c.par);
+                k_seen_pass<0, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 1, 2, c.par);
+                k_seen_pass<1, R, -1><<<g, b, 0, c.stream>>>(c.desc, fwork, 2, 0, c.par);
             }
         }
         if (c.ratio && c.rtiles > 0) {

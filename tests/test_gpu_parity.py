@@ -169,6 +169,35 @@ def test_3d_rows_of_64_parity(order, interp):
             sim.close()
 
 
+def test_3d_batched_rows_of_64_and_ragged_rows():
+    """Two 3D instances in one batched launch, one with 64-cell rows (staged x
+    pass) and one with 40-cell rows (per-tap x pass) and more cells, so the x
+    pass's grid is sized by the larger: each against its own oracle (FP64 within
+    1e-10), and the plain schedule equal to the batched one bitwise in FP32."""
+    wls = [pi.workload("beam3d_128x128x256", n=(64, 4, 8), ppc=2, order=1, tag="a"),
+           pi.workload("beam3d_128x128x256", n=(40, 8, 12), ppc=2, order=1, tag="b")]
+    parts = [pi.load_beam(3, w["n"], w["ppc"], w["gamma"], 1e-3, 30 + i) for i, w in enumerate(wls)]
+    _say("case 3d batched rows %s" % [w["n"] for w in wls])
+    sim = _sim(wls, parts, precision="fp64")
+    sim.step(8)
+    for i, (w, (x, u)) in enumerate(zip(wls, parts)):
+        ref = OracleSim(w, x, u)
+        ref.step(8)
+        errs = {k: _rel(sim.fields(k, i), getattr(ref, k)) for k in ("E", "B", "J")}
+        _say("  instance %d %s" % (i, errs))
+        assert max(errs.values()) < 1e-10
+    sim.close()
+    res = []
+    for sched in ("batched", "plain"):
+        sim = _sim(wls, parts, precision="fp32")
+        sim.set_schedule(sched, True)
+        sim.step(6)
+        res.append([sim.fields("E", i) for i in range(2)] + [sim.fields("Et", i) for i in range(2)])
+        sim.close()
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+
+
 def test_3d_cubic_multipass_tiles_parity():
     """The 3D cubic workload's particle density (8 ppc) on a 32x32x64 grid: a
     cubic tile is 8x2x4 = 64 cells, so every tile holds about 512 particles and
