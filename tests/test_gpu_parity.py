@@ -171,10 +171,11 @@ def test_3d_rows_of_64_parity(order, interp):
 
 def test_3d_batched_rows_of_64_and_ragged_rows():
     """Two 3D instances in one batched launch, one with 64-cell rows (staged x
-    pass) and one with 40-cell rows (per-tap x pass) and more cells, so the x
-    pass's grid is sized by the larger: each against its own oracle (FP64 within
-    1e-10), and the plain schedule equal to the batched one bitwise in FP32."""
-    wls = [pi.workload("beam3d_128x128x256", n=(64, 4, 8), ppc=2, order=1, tag="a"),
+    pass; 3840 cells, so its second workgroup holds only part of its 2048) and
+    one with 40-cell rows (per-tap x pass) and more cells, so the x pass's grid
+    is sized by the larger: each against its own oracle (FP64 within 1e-10),
+    and the plain schedule equal to the batched one bitwise in FP32."""
+    wls = [pi.workload("beam3d_128x128x256", n=(64, 6, 10), ppc=2, order=1, tag="a"),
            pi.workload("beam3d_128x128x256", n=(40, 8, 12), ppc=2, order=1, tag="b")]
     parts = [pi.load_beam(3, w["n"], w["ppc"], w["gamma"], 1e-3, 30 + i) for i, w in enumerate(wls)]
     _say("case 3d batched rows %s" % [w["n"] for w in wls])
