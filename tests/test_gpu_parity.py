@@ -199,6 +199,21 @@ def test_3d_batched_rows_of_64_and_ragged_rows():
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("n,order", [((16, 12, 24), 1), ((16, 12, 24), 3), ((64, 8, 8), 3)])
+def test_3d_fp64_parity_50_steps(n, order):
+    """The FP64 bar over 50 steps in 3D (relative L2 of E, B, J at most 1e-10),
+    linear and cubic shapes, with rows of 16 cells (per-tap x pass) and of 64
+    (staged x pass); the Gauss residual stays at rounding level."""
+    wl = pi.workload("beam3d_128x128x256", n=n, ppc=2, order=order)
+    sim, ref = _pair(wl, 50, "fp64")
+    errs = _field_errors(sim, ref)
+    d = sim.diag()
+    _say("3d fp64 50 steps n=%s order %d %s gauss %.3e" % (n, order, errs, d["gauss_linf"] / d["rho_max"]))
+    assert max(errs.values()) < 1e-10
+    assert d["gauss_linf"] < 1e-11 * d["rho_max"]
+    sim.close()
+
+
 def test_3d_cubic_multipass_tiles_parity():
     """The 3D cubic workload's particle density (8 ppc) on a 32x32x64 grid: a
     cubic tile is 8x2x4 = 64 cells, so every tile holds about 512 particles and
