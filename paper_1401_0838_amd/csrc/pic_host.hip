@@ -737,7 +737,9 @@ int build_worklists(pic_state *s)
         // each XCD takes a contiguous run of rows of tiles, so the halo rows a
         // tile shares with its neighbour along z are read into one L2
         Range sr{(int)sw.size(), 0};
-        const int nst = ((D.n[0] + PIC_SEEN_TX - 1) / PIC_SEEN_TX) * ((D.n[2] + stz - 1) / stz);
+        // (the streamed pass, seen_tz 128, takes strips PIC_SEEN_SW columns wide)
+        const int stw = stz == 128 ? PIC_SEEN_SW : PIC_SEEN_TX;
+        const int nst = ((D.n[0] + stw - 1) / stw) * ((D.n[2] + stz - 1) / stz);
         tile_order(nst, ord);
         for (int k = 0; k < nst; k++) sw.push_back(make_int2(i, ord[k]));
         sr.n = (int)sw.size() - sr.off;

@@ -11,6 +11,7 @@
 #define PIC_GRAD_COPIES 64      // copies of the gradient sums (power of two)
 #define PIC_PART_CHUNK 256      // particles per particle-chunk work item
 #define PIC_SEEN_TX 64          // 2D seen-field tile (x)
+#define PIC_SEEN_SW 128         // 2D streamed seen pass: strip width (x)
 #define PIC_TILE_SLACK 4        // cells a tile's particle bounding box may grow before a re-sort
 #define PIC_COL_RUN 16          // cells per thread along the axis of a 3D column stencil pass
 

@@ -1346,37 +1346,41 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
 }
 
 // The same operator streamed along z (float, compile-time widths): one block
-// takes one component's 64-column strip over SEG rows and walks down it in
-// chunks of SEEN_CZ rows.  Each chunk's new rows (with the x halo) are staged
-// in LDS and filtered along x into a ring of SEEN_CZ + 2 HZ rows, which keeps
-// the z halo the next chunk needs, so a row enters from HBM once per segment
-// (the 2 HZ halo rows once per SEG rows, not once per 32-row tile).  The next
-// chunk's rows are loaded into registers while the current one is filtered,
-// and the barriers wait for LDS only.  Waves own rows, lanes own columns.
+// takes one component's PIC_SEEN_SW-column strip over SEG rows and walks down
+// it in chunks of SEEN_CZ rows.  Each chunk's new rows (with the x halo) are
+// staged in LDS and filtered along x into a ring of SEEN_CZ + 2 HZ rows, which
+// keeps the z halo the next chunk needs, so a row enters from HBM once per
+// segment (the 2 HZ halo rows once per SEG rows, not once per 32-row tile, and
+// the 2 HX halo columns once per 128 columns).  The next chunk's rows are
+// loaded into registers while the current one is filtered, and the barriers
+// wait for LDS only.  Eight waves: four over the rows of each 64-column half,
+// lanes on columns.
 #define SEEN_CZ 32
 template <class R, int SEG, int HZ, int HX>
-__global__ void __launch_bounds__(256) k_seen_2d_stream(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
+__global__ void __launch_bounds__(512) k_seen_2d_stream(const InstDesc *__restrict__ Dt, const int2 *__restrict__ work,
                                                         int par)
 {
-    static_assert(SEEN_TX == 64 && SEG % SEEN_CZ == 0, "64-column strips, whole chunks");
+    constexpr int TW = PIC_SEEN_SW;
+    static_assert(TW == 128 && SEG % SEEN_CZ == 0, "two 64-column halves, whole chunks");
     constexpr int CZ = SEEN_CZ, NW = 4, RW = CZ / NW, NCH = SEG / CZ;
-    constexpr int RING = CZ + 2 * HZ, WX = SEEN_TX + 2 * HX;
+    constexpr int RING = CZ + 2 * HZ, WX = TW + 2 * HX;
     constexpr int R0 = (RING + NW - 1) / NW;          // rows per wave of the first chunk
-    constexpr int NTZ = 2 * HZ + 1, NTX = 2 * HX + 1, XQ = 4, NQ = SEEN_TX / XQ;
+    constexpr int NTZ = 2 * HZ + 1, NTX = 2 * HX + 1, XQ = 4, NQ = TW / XQ;
     __shared__ R raw[RING * WX];                      // rows staged by this chunk
-    __shared__ R mid[RING * SEEN_TX];                 // x-filtered rows, ring by window row
+    __shared__ R mid[RING * TW];                      // x-filtered rows, ring by window row
     const int inst = work ? work[blockIdx.x].x : 0;
     const int t = work ? work[blockIdx.x].y : xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int comp = blockIdx.y;
     const InstDesc &D = Dt[inst];
     const int nx = D.n[0], nz = D.n[2];
-    const int ntx = (nx + SEEN_TX - 1) / SEEN_TX;
+    const int ntx = (nx + TW - 1) / TW;
     // grids whose width is a multiple of 64: strips start HX cells past a
-    // 64-cell boundary, so that every staged row begins on a 256-byte boundary
-    // (three 128-byte lines a row rather than four); the last strip's outputs
-    // wrap onto the first HX columns
-    const int sh = nx % SEEN_TX == 0 ? HX : 0;
-    const int x0 = (t % ntx) * SEEN_TX + sh, z0 = (t / ntx) * SEG;
+    // 64-cell boundary, so that every staged row begins on a 256-byte boundary;
+    // the last strip's outputs wrap onto the first HX columns (and, where the
+    // width is an odd multiple of 64, its columns past those repeat ones another
+    // strip stores: they are not stored)
+    const int sh = nx % 64 == 0 ? HX : 0;
+    const int x0 = (t % ntx) * TW + sh, z0 = (t / ntx) * SEG;
     const int nch = (min(SEG, nz - z0) + CZ - 1) / CZ;  // chunks of this segment (uniform)
     const double *tzs = ztaps(D, comp), *txs = xtaps(D, comp);
     R rz[NTZ], rx[NTX];
@@ -1387,10 +1391,11 @@ __global__ void __launch_bounds__(256) k_seen_2d_stream(const InstDesc *__restri
     const gp<const R> src = G<R>(comp < 3 ? D.E[par][comp] : D.B[par][comp - 3]);
     gp<R> dst = G<R>(comp < 3 ? D.Et[comp] : D.Bt[comp - 3]);
     const int lane = threadIdx.x & 63, wave = wave_id();
-    const bool hasb = lane < 2 * HX;
+    const int half = wave >> 2, wr = wave & 3, col = 64 * half + lane;
+    const bool hasb = half == 1 && lane < 2 * HX;     // the right halo columns TW + lane
     const PerMod wx(nx), wz(nz);
-    const int gxa = wx(x0 - HX + lane);
-    const int gxb = hasb ? wx(x0 - HX + SEEN_TX + lane) : gxa;
+    const int gxa = wx(x0 - HX + col);
+    const int gxb = hasb ? wx(x0 - HX + TW + lane) : gxa;
     // window row w is grid row z0 - HZ + w; the first chunk stages rows
     // [0, RING), chunk c >= 1 rows [c CZ + 2 HZ, (c + 1) CZ + 2 HZ)
     auto grow = [&](int w) { return wz(z0 - HZ + w) * nx; };
@@ -1398,16 +1403,16 @@ __global__ void __launch_bounds__(256) k_seen_2d_stream(const InstDesc *__restri
         R va[R0], vb[R0];
 #pragma unroll
         for (int u = 0; u < R0; u++) {
-            const int base = grow(min(wave + u * NW, RING - 1));
+            const int base = grow(min(wr + u * NW, RING - 1));
             va[u] = src[base + gxa];
             vb[u] = src[base + gxb];
         }
 #pragma unroll
         for (int u = 0; u < R0; u++) {
-            const int r = wave + u * NW;
+            const int r = wr + u * NW;
             if (r < RING) {
-                raw[r * WX + lane] = va[u];
-                if (hasb) raw[r * WX + SEEN_TX + lane] = vb[u];
+                raw[r * WX + col] = va[u];
+                if (hasb) raw[r * WX + TW + lane] = vb[u];
             }
         }
     }
@@ -1419,15 +1424,15 @@ __global__ void __launch_bounds__(256) k_seen_2d_stream(const InstDesc *__restri
             // this chunk's rows, loaded during the previous one
 #pragma unroll
             for (int u = 0; u < RW; u++) {
-                const int r = wave + u * NW;
-                raw[r * WX + lane] = pa[u];
-                if (hasb) raw[r * WX + SEEN_TX + lane] = pb[u];
+                const int r = wr + u * NW;
+                raw[r * WX + col] = pa[u];
+                if (hasb) raw[r * WX + TW + lane] = pb[u];
             }
         }
         if (c + 1 < nch) {
 #pragma unroll
             for (int u = 0; u < RW; u++) {
-                const int base = grow((c + 1) * CZ + 2 * HZ + wave + u * NW);
+                const int base = grow((c + 1) * CZ + 2 * HZ + wr + u * NW);
                 pa[u] = src[base + gxa];
                 pb[u] = src[base + gxb];
             }
@@ -1435,13 +1440,13 @@ __global__ void __launch_bounds__(256) k_seen_2d_stream(const InstDesc *__restri
         lds_barrier();
         // x stencil on the staged rows: item (row, 4 output columns)
         const int nr = c == 0 ? RING : CZ, w0 = c == 0 ? 0 : c * CZ + 2 * HZ;
-        for (int it = threadIdx.x; it < nr * NQ; it += 256) {
+        for (int it = threadIdx.x; it < nr * NQ; it += 512) {
             const int r = it / NQ, c0 = (it % NQ) * XQ;
             const R *w = raw + r * WX + c0;
             R v[XQ + 2 * HX];
 #pragma unroll
             for (int k = 0; k < XQ + 2 * HX; k++) v[k] = w[k];
-            R *o = mid + ((w0 + r) % RING) * SEEN_TX + c0;
+            R *o = mid + ((w0 + r) % RING) * TW + c0;
 #pragma unroll
             for (int q = 0; q < XQ; q++) {
                 R acc = rx[0] * v[q];
@@ -1451,24 +1456,25 @@ __global__ void __launch_bounds__(256) k_seen_2d_stream(const InstDesc *__restri
             }
         }
         lds_barrier();
-        // z stencil: output rows c CZ + wave RW + [0, RW) take window rows
-        // c CZ + wave RW + [0, RW + 2 HZ)
-        const int s0 = (c * CZ + wave * RW) % RING;
+        // z stencil: output rows c CZ + wr RW + [0, RW) take window rows
+        // c CZ + wr RW + [0, RW + 2 HZ)
+        const int s0 = (c * CZ + wr * RW) % RING;
         R v[RW + 2 * HZ];
 #pragma unroll
         for (int k = 0; k < RW + 2 * HZ; k++) {
             const int s = s0 + k < RING ? s0 + k : s0 + k - RING;
-            v[k] = mid[s * SEEN_TX + lane];
+            v[k] = mid[s * TW + col];
         }
-        const int gxs = x0 + lane;
-        const int gx = gxs >= nx && sh ? gxs - nx : gxs;
+        const int gxs = x0 + col;
+        const bool xok = sh ? gxs < nx + sh : gxs < nx;
+        const int gx = gxs >= nx ? gxs - nx : gxs;
 #pragma unroll
         for (int j = 0; j < RW; j++) {
-            const int gz = z0 + c * CZ + wave * RW + j;
+            const int gz = z0 + c * CZ + wr * RW + j;
             R acc = rz[0] * v[j];
 #pragma unroll
             for (int k = 1; k < NTZ; k++) acc += rz[k] * v[j + k];
-            if (gx < nx && gz < nz) dst[gz * nx + gx] = acc;
+            if (xok && gz < nz) dst[gz * nx + gx] = acc;
         }
     }
 }
@@ -1972,20 +1978,23 @@ void launch_seen_2d_tz(const LaunchCtx &c, const int2 *swork, int nswork)
     else k_seen_2d<R, TZ, -1, -1><<<g, b, sm, c.stream>>>(c.desc, swork, c.par);
 }
 
+// returns nonzero for a tile height the work list cannot serve
 template <class R>
-void launch_seen_2d(const LaunchCtx &c, const int2 *swork, int nswork)
+int launch_seen_2d(const LaunchCtx &c, const int2 *swork, int nswork)
 {
     if constexpr (sizeof(R) == 4) {
         // 128-row segments streamed in 32-row chunks (the usual stencil widths)
         if (c.seen_tz == 128 && ((c.hz == 8 && c.hx == 4) || (c.hz == 9 && c.hx == 5))) {
-            const dim3 g(nswork, 6), b(PIC_FIELD_CHUNK);
+            const dim3 g(nswork, 6), b(512);
             const int2 *w = c.single ? nullptr : swork;
             if (c.hz == 8) k_seen_2d_stream<R, 128, 8, 4><<<g, b, 0, c.stream>>>(c.desc, w, c.par);
             else k_seen_2d_stream<R, 128, 9, 5><<<g, b, 0, c.stream>>>(c.desc, w, c.par);
-            return;
+            return 0;
         }
-        if (c.seen_tz == 128) { launch_seen_2d_tz<R, 32>(c, swork, nswork); return; }
     }
+    // the host sets a tile height of 128 only with the streamed pass's widths
+    // (its work list holds PIC_SEEN_SW-wide strips)
+    if (c.seen_tz == 128) return 1;
     if (c.seen_tz == 8) launch_seen_2d_tz<R, 8>(c, swork, nswork);
     else if (c.seen_tz == 16) launch_seen_2d_tz<R, 16>(c, swork, nswork);
     else if constexpr (sizeof(R) == 4) {
@@ -1993,6 +2002,7 @@ void launch_seen_2d(const LaunchCtx &c, const int2 *swork, int nswork)
         if (c.seen_tz == 64) launch_seen_2d_tz<R, 64>(c, swork, nswork);
         else launch_seen_2d_tz<R, 32>(c, swork, nswork);
     } else launch_seen_2d_tz<R, 32>(c, swork, nswork);
+    return 0;
 }
 
 int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *swork, int nswork)
@@ -2001,7 +2011,7 @@ int launch_seen(const LaunchCtx &c, const int2 *fwork, int nwork, const int2 *sw
     dim3 g(nwork, 6), b(PIC_FIELD_CHUNK);
     DISPATCH_R(c.fp32, {
         if (c.dims == 2) {
-            launch_seen_2d<R>(c, swork, nswork);
+            if (launch_seen_2d<R>(c, swork, nswork)) return 1;
         } else {
             // usual widths: correction of degree 4 with four filter passes (z 8, x and y 4),
             // one more with the node average of the momentum-conserving gather
