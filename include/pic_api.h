@@ -257,8 +257,9 @@ int pic_set_schedule(pic_state *st, int sched, int use_graph);
  *   "yee_tile_z"     rows of the 2D Yee tile: 4, 8 or 16 (16 is float only);
  *                    default 8, or 16 for FP32 batches of more than 4 * 512^2 cells
  *   "seen_tile_z"    rows of the 2D seen-field tile: 8, 16, 32 or 64 (32 and 64
- *                    are float only), or 128: float segments of 128 rows streamed
- *                    in 32-row chunks (with the usual stencil widths, else 32);
+ *                    are float only), or 128: float strips 128 columns wide and
+ *                    128 rows tall streamed in 32-row chunks (with the usual
+ *                    stencil widths, else 32);
  *                    default 16, or 128 (32 where the widths differ) for FP32
  *                    batches of more than 4 * 512^2 cells
  *   "resort_every"   steps between tile re-sort checks (and per captured graph);
