@@ -541,14 +541,13 @@ def test_full_size_512_fp32_parity_10_steps():
 def test_streamed_seen_fields_equal_the_tiled_ones(n, interp):
     """The streamed seen-field pass (128-column strips, 128-row segments, 32-row
     chunks, a ring of x-filtered rows) computes the same sums in the same order
-    as the tiled pass: bitwise
-    equal seen fields, also on segments of one to four chunks (nz = 264, 48,
-    80, 128 rows), with a ragged last chunk (nz = 80, 264), a
-    ragged strip (nx = 96, 200), a segment shorter than 128 rows, the wider
-    stencil of the momentum-conserving gather, and widths that are a multiple
-    of 64 (nx = 64, 128), where the strips start past the 64-cell boundary and
-    the last one wraps (for nx = 64 half of that strip repeats columns another
-    part stores, and stays unstored)."""
+    as the tiled pass: bitwise equal seen fields, also on segments of one to
+    four chunks (nz = 264, 48, 80, 128 rows), with a ragged last chunk (nz = 80,
+    264), a ragged strip (nx = 96, 200), the wider stencil of the
+    momentum-conserving gather, and widths that are a multiple of 64 (nx = 64,
+    128), where the strips start past the 64-cell boundary and the last one
+    wraps (for nx = 64 half of that strip repeats columns stored elsewhere and
+    is not stored)."""
     wl = pi.workload("beam2d_512", n=n, ppc=2, interp=interp)
     x, u = pi.load_beam(2, wl["n"], wl["ppc"], wl["gamma"], 1e-3, 5)
     out = []
