@@ -1270,20 +1270,26 @@ __global__ void __launch_bounds__(256) k_seen_2d(const InstDesc *__restrict__ Dt
     const bool hasb = lane < 2 * hx;
     const int gxa = wrap_near(x0 - hx + lane, nx);
     const int gxb = hasb ? wrap_near(x0 - hx + SEEN_TX + lane, nx) : gxa;
-    constexpr int U = 8;
+    // rows per wave and pass: with compile-time widths, the whole window in one
+    // pass of the four waves (every load of a wave in flight before its first
+    // wait); rows past the window land in the x-filtered area, which is written
+    // only after the barrier below
+    constexpr bool FIXED = HZ >= 0 && SEEN_TZ >= 32;
+    constexpr int U = FIXED ? (SEEN_TZ + 2 * (HZ > 0 ? HZ : 0) + 3) / 4 : 8;
+    const PerMod wzm(nz);
     for (int r0 = wave; r0 < wz; r0 += U * nwave) {
         R va[U], vb[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int row = min(r0 + u * nwave, wz - 1);
-            const int base = wrap_near(z0 - hz + row, nz) * nx;
+            const int base = wzm(z0 - hz + row) * nx;
             va[u] = src[base + gxa];
             vb[u] = src[base + gxb];
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int row = r0 + u * nwave;
-            if (row < wz) {
+            if (FIXED || row < wz) {
                 win[row * wx + lane] = va[u];
                 if (hasb) win[row * wx + SEEN_TX + lane] = vb[u];
             }
